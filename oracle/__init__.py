@@ -1,0 +1,40 @@
+"""FP64 CPU oracle for the particle-in-cell full-order model and the dynamical
+symplectic reduced model of Hesthaven, Pagliantini and Ripamonti,
+"Adaptive symplectic model order reduction of parametric particle-based
+Vlasov-Poisson equation" (arXiv:2201.05555).
+
+TEST INFRASTRUCTURE ONLY.  This package is the plain, slow reference that the
+GPU library is checked against.  Only the test suite, the package smoke check
+and the CPU-baseline leg of the benchmark may import it; the product path
+never does, and shares no code with it.
+
+It follows the paper's real formulation (2N x 2n bases, explicit Poisson
+tensors J), with numpy library primitives (matmul, eigh, QR, SVD, dense
+solves, bincount) as steps.  Every function cites the passage it follows.
+
+Parity status of each piece is listed in ``PINS`` below; a piece whose result
+no closed form, invariant or brute-force check fixes says "parity unpinned".
+"""
+from . import pic, rom, deim  # noqa: F401
+
+PINS = {
+    "pic.cell_index": "brute force on tiny inputs; node ties",
+    "pic.deposit": "total charge = q w N, partition of unity; dense Lambda0 brute force",
+    "pic.poisson": "single cosine mode closed form; residual of the stiffness system",
+    "pic.field / gradient": "central finite difference of the discrete Hamiltonian",
+    "pic.energy": "Phi^T rho = Phi^T L Phi identity",
+    "pic.fom_step": "observed order 2, time reversibility, bounded energy error, Landau rate",
+    "rom.init_csvd": "Eckart-Young: truncation error = tail singular values",
+    "rom.basis_velocity": "real form equals complex form; tangency U^T X = 0",
+    "rom.cayley": "Woodbury form equals the dense Cayley transform; orthosymplecticity",
+    "rom.tangent_velocity": "Y(0,Z) = X(U0,Z); central FD of the retraction",
+    "rom.prk_step": "2n = 2N reduces to implicit midpoint on the full model; order 2; "
+                    "gauge covariance; orthosymplecticity after each step",
+    "rom.reorthonormalise": "R = UZ unchanged; U^T U = I",
+    "rom.rank_grow": "R bitwise unchanged (zero coefficient rows)",
+    "rom.rank_shrink": "removed energy equals dropped singular values",
+    "rom.rank_indicator": "parity unpinned (policy of this build; the paper defers rank adaptation)",
+    "deim.greedy": "brute force on tiny inputs; interpolation property P^T Psi (P^T Psi)^-1 = I",
+    "deim.gradient": "d = N reduces exactly to the Galerkin gradient",
+    "deim.accuracy_with_exact_potential": "parity unpinned (no printed values)",
+}

@@ -1,0 +1,102 @@
+"""Oracle: DEIM hyper-reduction of the particle-to-grid term (paper Sec. 4.3).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+The nonlinear term N_i = Lambda^0(X_r^i) Phi^i (values of the potential at
+the particles) is interpolated on d particle indices.  With the exact
+potential (no DMD, reading for this build) the DEIM gradient of eq. (grHDD) is
+  g_i = U_V^T V_r^i + U_X[I,:]^T ( (q/m) e_i[j(X_r^i[I])] * w ),
+  w = (P^T Psi)^{-T} Psi^T 1,
+since m_p^{-1} M_q = (q/m) 1 and nabla Lambda^0 Phi is the cell field e.
+Snapshots: the last T+1 time levels of N_i for all p parameters, the matrix
+Y = [Y_1 ... Y_p] of eq. (Ydeim); Psi = its first d left singular vectors; the
+indices follow the greedy DEIM selection (Sec. 4.3: at step k, the index of
+the largest interpolation residual of psi_k on the previous vectors).
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import pic
+
+
+@dataclass
+class DeimOp:
+    idx: np.ndarray      # d int64 particle indices, in greedy order
+    w: np.ndarray        # d weights (P^T Psi)^{-T} Psi^T 1
+    Psi: np.ndarray      # N x d
+
+
+def snapshot(Xr, Phi, L):
+    """N_i = Lambda^0(X_r^i) Phi^i: (1 - theta) Phi_j + theta Phi_{j+1} per particle."""
+    Nx = Phi.shape[0]
+    j, th = pic.cell_index(Xr, L, Nx)
+    cols = np.arange(Xr.shape[1])[None, :]
+    return (1.0 - th) * Phi[j, cols] + th * Phi[(j + 1) % Nx, cols]
+
+
+def deim_basis(Y, d):
+    """First d left singular vectors of Y, each signed so that its
+    largest-modulus entry is positive (reading: fixes the SVD sign)."""
+    Q, s, _ = np.linalg.svd(Y, full_matrices=False)
+    Psi = Q[:, :d].copy()
+    for k in range(d):
+        i = int(np.argmax(np.abs(Psi[:, k])))
+        if Psi[i, k] < 0:
+            Psi[:, k] = -Psi[:, k]
+    return Psi, s
+
+
+def greedy_indices(Psi):
+    """DEIM greedy selection: l_1 = argmax |psi_1|; for k >= 2 solve
+    (P^T Psi_{k-1}) c = P^T psi_k, r = psi_k - Psi_{k-1} c, l_k = argmax |r|
+    (ties to the smallest index)."""
+    d = Psi.shape[1]
+    idx = [int(np.argmax(np.abs(Psi[:, 0])))]
+    for k in range(1, d):
+        A = Psi[idx, :k]
+        c = np.linalg.solve(A, Psi[idx, k])
+        r = Psi[:, k] - Psi[:, :k] @ c
+        idx.append(int(np.argmax(np.abs(r))))
+    return np.array(idx, dtype=np.int64)
+
+
+def weights(Psi, idx):
+    """w = (P^T Psi)^{-T} Psi^T 1 (the M_q-dependent factor of eq. grHDD)."""
+    PtPsi = Psi[idx, :]
+    return np.linalg.solve(PtPsi.T, Psi.T @ np.ones(Psi.shape[0]))
+
+
+def build_operator(Y, d):
+    Psi, _ = deim_basis(Y, d)
+    idx = greedy_indices(Psi)
+    return DeimOp(idx=idx, w=weights(Psi, idx), Psi=Psi)
+
+
+def update_window(st, cfg, U0, gr0):
+    """Append the snapshot at the start of the step; once T+1 snapshots are
+    held, return the DEIM operator for this step, else None (the first T
+    steps use the Galerkin gradient, Alg. 2)."""
+    st.window.append(snapshot(gr0.Xr, gr0.Phi, st.L))
+    T = cfg.deim_window
+    if len(st.window) > T + 1:
+        st.window.pop(0)
+    if len(st.window) < T + 1:
+        st.deim_indices = None
+        return None
+    Y = np.concatenate(st.window, axis=1)
+    op = build_operator(Y, cfg.two_n)
+    st.deim_indices = op.idx
+    return op
+
+
+def restrict(op, cols):
+    """The operator is shared by every parameter."""
+    return op
+
+
+def deim_gradient(U, Z, gr, op, cfg):
+    """g = U_V^T V_r + U_X[I,:]^T ((q/m) e_{j(X_r[I])} * w)  (eq. grHDD)."""
+    N = U.shape[0] // 2
+    F_I = gr.G[:N][op.idx, :]
+    return U[N:].T @ gr.G[N:] + U[:N][op.idx, :].T @ (F_I * op.w[:, None])

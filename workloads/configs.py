@@ -1,0 +1,47 @@
+"""Named synthetic workloads.
+
+Each entry fixes the ensemble family, the particle / parameter / grid sizes,
+the time step and the reduced rank.  The parameter ranges follow the
+perturbed-Maxwellian initial conditions of the paper's numerical experiments
+(weak Landau damping, Sec. 6.2; two-stream instability, Sec. 6.4), widened to
+the ranges used here.  Seeds: parameter draws use ``1000*c + 1`` and the
+shared particle uniforms ``1000*c + 2`` where ``c`` is the workload number.
+"""
+
+WORKLOADS = {
+    # tiny plain-FP64 Landau ensemble: every parameter has its own domain
+    "landau_tiny": dict(
+        number=1, family="landau", N=10_000, p=4, Nx=64, steps=100, dt=0.1,
+        two_n=10, two_n_max=10, projection="galerkin",
+        ranges=dict(alpha=(0.01, 0.1), k=(0.3, 0.6)), sigma=1.0,
+    ),
+    # two-stream ensemble, FP64, DEIM with d = 2n, adaptive rank 10 -> 60
+    "twostream_deim": dict(
+        number=2, family="twostream", N=100_000, p=64, Nx=128, steps=500,
+        dt=0.05, two_n=10, two_n_max=60, projection="deim", deim_window=3,
+        ranges=dict(alpha=(1e-3, 1e-2), v0=(2.0, 3.0), sigma=(0.1, 0.5)),
+        k=0.2,
+    ),
+    # large two-stream ensemble (mixed-precision target sizes)
+    "twostream_mixed": dict(
+        number=3, family="twostream", N=1_000_000, p=256, Nx=256, steps=1000,
+        dt=0.05, two_n=16, two_n_max=64, projection="galerkin",
+        ranges=dict(alpha=(1e-3, 1e-2), v0=(2.0, 3.0), sigma=(0.1, 0.5)),
+        k=0.2,
+    ),
+    # very large two-stream ensemble
+    "twostream_large": dict(
+        number=5, family="twostream", N=4_000_000, p=1024, Nx=512, steps=2000,
+        dt=0.05, two_n=16, two_n_max=128, projection="galerkin",
+        ranges=dict(alpha=(1e-3, 1e-2), v0=(2.0, 3.0), sigma=(0.1, 0.5)),
+        k=0.2,
+    ),
+}
+
+
+def workload(name, **overrides):
+    """Return a copy of a named workload with some fields replaced."""
+    w = dict(WORKLOADS[name])
+    w["name"] = name
+    w.update(overrides)
+    return w
