@@ -1,0 +1,213 @@
+/*
+ * symrom.h -- C ABI of the MI355X library for the dynamical symplectic
+ * reduced model of the parametric particle-based 1D1V Vlasov-Poisson
+ * system (Hesthaven, Pagliantini, Ripamonti, arXiv:2201.05555), and of the
+ * particle-in-cell full-order model it is compared against.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All functions are extern "C" and return symrom_status (0 = OK,
+ *   negative = error); the text of the last error of the calling thread is
+ *   available from symrom_last_error().
+ * - Array arguments are DEVICE pointers (memory of the current HIP device)
+ *   unless the comment says "host".  Particle arrays are FP64, N x p,
+ *   column-major (leading dimension N): column i belongs to parameter i.
+ *   Positions are unwrapped; they are reduced modulo the domain length only
+ *   inside the particle-to-cell lookup.
+ * - The reduced basis crosses the boundary as U_X (N x 2n, column-major,
+ *   ld = N), the position rows of the orthosymplectic U = [U_X; U_V]
+ *   (Sec. 3.2); U_V = U_X J_2n is implied (the orthosymplectic structure
+ *   forces U = [[A, -B], [B, A]]).  Coefficients Z are 2n x p, ld = 2n.
+ * - Memory: the library never allocates device memory.  The caller passes a
+ *   workspace `ws` of at least *_workspace_bytes() bytes, borrowed until the
+ *   handle is destroyed.  Host arrays are read during the call only.
+ * - Streams: all work is enqueued on the caller's `stream` (a hipStream_t,
+ *   passed as void*).  Functions that return host data synchronise that
+ *   stream; the others return once work is enqueued, except rom_step and
+ *   fom_step, which read small device flags to drive the fixed point and so
+ *   synchronise the stream at least once per step.
+ * - A handle is used by one host thread at a time.
+ * - Physical units: q = -1, m = 1 and the weight of the N macro-particles
+ *   of parameter i is L_i / N, so that their charge cancels the uniform
+ *   unit background on [0, L_i) (Sec. 2 background remark, Sec. 6.1).
+ */
+#ifndef SYMROM_H
+#define SYMROM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t symrom_status;
+enum {
+  SYMROM_OK = 0,
+  SYMROM_EINVAL = -1,     /* bad sizes, odd rank, null pointers, ...        */
+  SYMROM_ENOMEM = -2,     /* workspace smaller than *_workspace_bytes()     */
+  SYMROM_ESINGULAR = -3,  /* a small dense matrix could not be factorised   */
+  SYMROM_ENOCONV = -4,    /* fixed point not converged within fp_max_iters  */
+  SYMROM_EDEVICE = -5,    /* a HIP call failed                              */
+  SYMROM_ESTATE = -6,     /* handle not initialised                          */
+  SYMROM_ERANKCAP = -7    /* rank growth beyond two_n_max requested          */
+};
+
+enum { SYMROM_GALERKIN = 0, SYMROM_DEIM = 1 };
+
+typedef struct {
+  int32_t N;             /* particles                                        */
+  int32_t p;             /* parameters of the ensemble                       */
+  int32_t Nx;            /* grid cells (= nodes) of the periodic P1 mesh     */
+  int32_t two_n;         /* reduced dimension 2n (even)                      */
+  int32_t two_n_max;     /* capacity for rank growth (even, >= two_n, <= 64) */
+  double dt;             /* time step                                        */
+  double q, m;           /* charge and mass (-1 and 1 in the paper)          */
+  int32_t projection;    /* SYMROM_GALERKIN or SYMROM_DEIM                   */
+  int32_t deim_window;   /* T: DEIM snapshots of the last T+1 time levels    */
+  double fp_tol;         /* fixed point: relative update threshold           */
+  int32_t fp_max_iters;  /* fixed point: iteration cap (ENOCONV beyond)      */
+  int32_t fp_fixed_iters;/* >0: run exactly this many iterations, no test    */
+  double pinv_rtol;      /* S(Z)^+ drops eigenvalues < pinv_rtol * max       */
+  int32_t reorth;        /* 1: FP64 re-orthonormalisation after each step    */
+  int32_t rank_auto;     /* 1: apply the rank indicator after each step      */
+  double rank_tol_up;    /* grow one pair when eps_perp exceeds this         */
+} symrom_config;
+
+typedef struct {
+  int32_t iters;          /* fixed-point iterations of the last step          */
+  int32_t stalled;        /* columns accepted by the stagnation rule          */
+  int32_t two_n;          /* rank after the call                              */
+  int32_t deim_active;    /* 1 if the last step used the DEIM gradient        */
+  double rank_indicator;  /* eps_perp of the last evaluation, -1 if none      */
+} symrom_step_info;
+
+typedef struct symrom_rom symrom_rom;
+typedef struct symrom_fom symrom_fom;
+
+/* ------------------------------------------------------------------------
+ * Reduced model (Sec. 3.2 eq. UZred, time stepping Sec. 5 eq. discrete_dynROM)
+ * ------------------------------------------------------------------------ */
+
+/* Exact workspace bytes rom_init needs for this configuration; 0 when the
+ * configuration is invalid. */
+size_t rom_workspace_bytes(const symrom_config* cfg);
+
+/* Create a reduced-model handle and initialise U, Z by the truncated complex
+ * SVD of R_0 = [X0; V0] (Sec. 3.2, initial condition of eq. UZred):
+ * U~ = leading n left singular vectors of X0 + i V0 (largest-modulus entry of
+ * each made real positive, completed by Gram-Schmidt of e_1, e_2, ... when
+ * n exceeds the numerical rank), Z~ = U~^* (X0 + i V0).
+ *   cfg       host, copied.
+ *   L         host [p]: domain length of each parameter (2 pi / k_i).
+ *   X0, V0    device, N x p column-major, unwrapped initial states.
+ *   ws        device workspace, >= rom_workspace_bytes(cfg) bytes.
+ *   stream    hipStream_t.
+ *   out       host: receives the handle.
+ * Errors: EINVAL (config), ENOMEM (ws too small), EDEVICE. */
+symrom_status rom_init(const symrom_config* cfg, const double* L, const double* X0,
+                       const double* V0, void* ws, size_t ws_bytes, void* stream,
+                       symrom_rom** out);
+
+/* Advance the whole ensemble by nsteps steps of the order-2 partitioned
+ * Runge-Kutta scheme (Sec. 5): implicit midpoint for Z solved by per-column
+ * fixed point (relative update < fp_tol, Sec. 6.1), explicit midpoint for U
+ * on the tangent space through the Cayley retraction, with the Galerkin or
+ * DEIM (Sec. 4.3, eq. grHDD with the exact potential) gradient.  info (host,
+ * nullable) describes the last step.  On ENOCONV the state is the one before
+ * the failing step. */
+symrom_status rom_step(symrom_rom* h, int32_t nsteps, symrom_step_info* info);
+
+/* Change the rank.  target_two_n > current: append (target - current)/2
+ * symplectic pairs, the leading left singular vectors of
+ * (I - U~U~^*)(-i G~) at the current state, with zero coefficient rows
+ * (R = U Z unchanged).  target < current: rotate to the singular vectors of
+ * Z~ and drop the trailing pairs.  target 0: grow one pair if the indicator
+ * eps_perp = ||(I - U U^T) J G|| / ||G|| exceeds rank_tol_up.  (The paper
+ * defers rank adaptation to future work, Sec. 6.4.)  new_two_n: host, nullable.
+ * Errors: ERANKCAP beyond two_n_max, EINVAL for odd targets. */
+symrom_status rom_adapt_rank(symrom_rom* h, int32_t target_two_n, int32_t* new_two_n);
+
+/* Copy the state out: U_X (N x 2n, ld N) and Z (2n x p, ld 2n), device;
+ * two_n and step are host, nullable.  Synchronises the stream. */
+symrom_status rom_get_state(symrom_rom* h, double* UX, double* Z, int32_t* two_n, int64_t* step);
+
+/* Replace the state by (U_X, Z) of rank two_n (device, layouts as above).
+ * U_X must be the position rows of an orthosymplectic basis.  Clears the
+ * DEIM snapshot window. */
+symrom_status rom_set_state(symrom_rom* h, int32_t two_n, const double* UX, const double* Z,
+                            int64_t step);
+
+/* R = U Z: positions X_r = U_X Z and velocities V_r = U_V Z (device, N x p). */
+symrom_status rom_reconstruct(symrom_rom* h, double* X, double* V);
+
+/* Per-parameter electric energy E(X_r^i) (eq. HamEEfull) and Hamiltonian
+ * H = 1/2 |V_r^i|^2 + E (device [p] each). */
+symrom_status rom_diagnostics(symrom_rom* h, double* E, double* H);
+
+/* Galerkin reduced gradient at (current U, Z): g = U^T G (eq. grads), device
+ * 2n x p; and, nullable, rho, Phi, e (device, Nx x p) of the deposit
+ * (eq. PoissonSystem plus background), the zero-mean potential and the cell
+ * field (Phi_{j+1} - Phi_j)/h. */
+symrom_status rom_gradient(symrom_rom* h, const double* Z, double* g, double* rho, double* Phi,
+                           double* e);
+
+/* Release the handle (the workspace is the caller's). */
+void rom_destroy(symrom_rom* h);
+
+/* ------------------------------------------------------------------------
+ * Full-order particle-in-cell model (Sec. 2.1, Stormer-Verlet eq. sv_full_order)
+ * ------------------------------------------------------------------------ */
+
+size_t fom_workspace_bytes(int32_t N, int32_t p, int32_t Nx);
+
+/* Create a full-order handle holding X, V (copied from X0, V0, device,
+ * N x p) in its workspace. */
+symrom_status fom_init(int32_t N, int32_t p, int32_t Nx, double dt, double q, double m,
+                       const double* L, const double* X0, const double* V0, void* ws,
+                       size_t ws_bytes, void* stream, symrom_fom** out);
+
+/* nsteps Stormer-Verlet steps for every parameter:
+ * X+ = X + dt (V + dt/2 a(X)),  V+ = V + dt/2 (a(X) + a(X+)),
+ * a = -(q/m) e_{j(X)} the acceleration of eq. VPHamEqn. */
+symrom_status fom_step(symrom_fom* h, int32_t nsteps);
+
+/* Copy X, V out (device, N x p). Synchronises the stream. */
+symrom_status fom_get_state(symrom_fom* h, double* X, double* V);
+
+/* Electric energy and Hamiltonian per parameter (device [p]). */
+symrom_status fom_diagnostics(symrom_fom* h, double* E, double* H);
+
+void fom_destroy(symrom_fom* h);
+
+/* ------------------------------------------------------------------------
+ * Stateless particle-to-grid pieces (Sec. 2.1), for tests and tools
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes for pic_fields. */
+size_t pic_workspace_bytes(int32_t N, int32_t p, int32_t Nx);
+
+/* For positions X (device, N x p): cell index j (device int32 N x p,
+ * nullable; j = floor(x N_x / L) mod N_x with the factor N_x / L formed in
+ * FP64), rho, Phi, e (device Nx x p, each nullable).  L host [p]. */
+symrom_status pic_fields(int32_t N, int32_t p, int32_t Nx, const double* L, double q,
+                         const double* X, int32_t* cells, double* rho, double* Phi, double* e,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+const char* symrom_status_string(symrom_status s);
+const char* symrom_last_error(void);
+
+/* Accumulated device time (ms) of the kernels the library launched on the
+ * handle's stream since the last call, measured with HIP events around each
+ * launch of the named kernel family when timing is enabled by
+ * symrom_set_timing(1).  family: 0 = reconstruct-and-deposit, 1 = gather and
+ * projection, 2 = Poisson, 3 = FOM push, 4 = basis (Grams and row
+ * combines), 5 = dense.  Counts launches in *launches (host, nullable). */
+void symrom_set_timing(int32_t on);
+double symrom_kernel_ms(int32_t family, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SYMROM_H */

@@ -1,0 +1,302 @@
+"""ctypes binding of the symrom C ABI (include/symrom.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device arrays are torch CUDA tensors; the library's column-major N x p arrays
+are tensors of shape (p, N), U_X (N x 2n) is (2n, N), Z (2n x p) is (p, 2n)
+and the grids (Nx x p) are (p, Nx).  The library is loaded from
+``lib/libsymrom.so`` next to this file; if it is missing, every entry point
+raises (there is no CPU fallback).
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libsymrom.so")
+
+OK, EINVAL, ENOMEM, ESINGULAR, ENOCONV, EDEVICE, ESTATE, ERANKCAP = 0, -1, -2, -3, -4, -5, -6, -7
+GALERKIN, DEIM = 0, 1
+FAMILIES = {"deposit": 0, "gather": 1, "poisson": 2, "fom_push": 3, "basis": 4, "dense": 5}
+
+
+class SymromError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"symrom status {status}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int32), ("p", ctypes.c_int32), ("Nx", ctypes.c_int32),
+        ("two_n", ctypes.c_int32), ("two_n_max", ctypes.c_int32),
+        ("dt", ctypes.c_double), ("q", ctypes.c_double), ("m", ctypes.c_double),
+        ("projection", ctypes.c_int32), ("deim_window", ctypes.c_int32),
+        ("fp_tol", ctypes.c_double), ("fp_max_iters", ctypes.c_int32),
+        ("fp_fixed_iters", ctypes.c_int32), ("pinv_rtol", ctypes.c_double),
+        ("reorth", ctypes.c_int32), ("rank_auto", ctypes.c_int32),
+        ("rank_tol_up", ctypes.c_double),
+    ]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32), ("stalled", ctypes.c_int32), ("two_n", ctypes.c_int32),
+        ("deim_active", ctypes.c_int32), ("rank_indicator", ctypes.c_double),
+    ]
+
+
+_VP = ctypes.c_void_p
+_SIGS = {
+    "rom_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Config)]),
+    "rom_init": (ctypes.c_int32, [ctypes.POINTER(Config), _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP,
+                                  ctypes.POINTER(_VP)]),
+    "rom_step": (ctypes.c_int32, [_VP, ctypes.c_int32, ctypes.POINTER(StepInfo)]),
+    "rom_adapt_rank": (ctypes.c_int32, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "rom_get_state": (ctypes.c_int32, [_VP, _VP, _VP, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int64)]),
+    "rom_set_state": (ctypes.c_int32, [_VP, ctypes.c_int32, _VP, _VP, ctypes.c_int64]),
+    "rom_reconstruct": (ctypes.c_int32, [_VP, _VP, _VP]),
+    "rom_diagnostics": (ctypes.c_int32, [_VP, _VP, _VP]),
+    "rom_gradient": (ctypes.c_int32, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "rom_destroy": (None, [_VP]),
+    "fom_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32] * 3),
+    "fom_init": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, _VP, _VP, _VP, _VP,
+                                  ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    "fom_step": (ctypes.c_int32, [_VP, ctypes.c_int32]),
+    "fom_get_state": (ctypes.c_int32, [_VP, _VP, _VP]),
+    "fom_diagnostics": (ctypes.c_int32, [_VP, _VP, _VP]),
+    "fom_destroy": (None, [_VP]),
+    "pic_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32] * 3),
+    "pic_fields": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
+                                    ctypes.c_double, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t,
+                                    _VP]),
+    "symrom_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "symrom_last_error": (ctypes.c_char_p, []),
+    "symrom_set_timing": (None, [ctypes.c_int32]),
+    "symrom_kernel_ms": (ctypes.c_double, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(status):
+    if status != OK:
+        msg = lib().symrom_last_error().decode()
+        raise SymromError(status, msg)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _host_doubles(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def set_timing(on):
+    lib().symrom_set_timing(1 if on else 0)
+
+
+def kernel_ms(family):
+    """(total ms, launches) of a kernel family since the last query."""
+    n = ctypes.c_int64(0)
+    ms = lib().symrom_kernel_ms(FAMILIES[family], ctypes.byref(n))
+    return ms, n.value
+
+
+def make_config(N, p, Nx, two_n, two_n_max=None, dt=0.05, q=-1.0, m=1.0, projection="galerkin",
+                deim_window=3, fp_tol=1e-9, fp_max_iters=100, fp_fixed_iters=0, pinv_rtol=1e-12,
+                reorth=True, rank_auto=False, rank_tol_up=1e-2):
+    return Config(N=N, p=p, Nx=Nx, two_n=two_n, two_n_max=two_n_max or two_n, dt=dt, q=q, m=m,
+                  projection=DEIM if projection == "deim" else GALERKIN,
+                  deim_window=deim_window, fp_tol=fp_tol, fp_max_iters=fp_max_iters,
+                  fp_fixed_iters=fp_fixed_iters, pinv_rtol=pinv_rtol, reorth=int(reorth),
+                  rank_auto=int(rank_auto), rank_tol_up=rank_tol_up)
+
+
+def _dev(x, device="cuda"):
+    """(N, p) numpy -> (p, N) contiguous device tensor (column-major N x p)."""
+    if isinstance(x, torch.Tensor):
+        return x.contiguous()
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.float64).T)).to(device)
+
+
+class Rom:
+    """Reduced-model handle (rom_* entry points)."""
+
+    def __init__(self, cfg, L, X0, V0, stream=None):
+        self.cfg = cfg
+        self.L = np.asarray(L, dtype=np.float64).copy()
+        self.stream = stream
+        nbytes = lib().rom_workspace_bytes(ctypes.byref(cfg))
+        if nbytes == 0:
+            raise SymromError(EINVAL, "invalid configuration")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        X0, V0 = _dev(X0), _dev(V0)
+        Lh, Lp = _host_doubles(self.L)
+        h = ctypes.c_void_p()
+        _check(lib().rom_init(ctypes.byref(cfg), Lp, _ptr(X0), _ptr(V0), _ptr(self.ws),
+                              nbytes, _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().rom_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def two_n(self):
+        t = ctypes.c_int32()
+        _check(lib().rom_get_state(self.h, None, None, ctypes.byref(t), None))
+        return t.value
+
+    def step(self, nsteps=1):
+        info = StepInfo()
+        _check(lib().rom_step(self.h, nsteps, ctypes.byref(info)))
+        return dict(iters=info.iters, stalled=info.stalled, two_n=info.two_n,
+                    deim_active=info.deim_active, rank_indicator=info.rank_indicator)
+
+    def step_status(self, nsteps=1):
+        info = StepInfo()
+        st = lib().rom_step(self.h, nsteps, ctypes.byref(info))
+        return st, dict(iters=info.iters, stalled=info.stalled)
+
+    def adapt_rank(self, target=0):
+        out = ctypes.c_int32()
+        _check(lib().rom_adapt_rank(self.h, target, ctypes.byref(out)))
+        return out.value
+
+    def get_state(self):
+        r = self.two_n
+        UX = torch.empty((r, self.cfg.N), dtype=torch.float64, device="cuda")
+        Z = torch.empty((self.cfg.p, r), dtype=torch.float64, device="cuda")
+        step = ctypes.c_int64()
+        _check(lib().rom_get_state(self.h, _ptr(UX), _ptr(Z), None, ctypes.byref(step)))
+        return UX, Z, step.value
+
+    def set_state(self, UX, Z, step=0):
+        UX = UX.contiguous()
+        Z = Z.contiguous()
+        _check(lib().rom_set_state(self.h, UX.shape[0], _ptr(UX), _ptr(Z), step))
+
+    def reconstruct(self):
+        X = torch.empty((self.cfg.p, self.cfg.N), dtype=torch.float64, device="cuda")
+        V = torch.empty_like(X)
+        _check(lib().rom_reconstruct(self.h, _ptr(X), _ptr(V)))
+        return X, V
+
+    def diagnostics(self):
+        E = torch.empty(self.cfg.p, dtype=torch.float64, device="cuda")
+        H = torch.empty_like(E)
+        _check(lib().rom_diagnostics(self.h, _ptr(E), _ptr(H)))
+        return E, H
+
+    def gradient(self, Z):
+        Z = Z.contiguous()
+        g = torch.empty_like(Z)
+        grid = (self.cfg.p, self.cfg.Nx)
+        rho = torch.empty(grid, dtype=torch.float64, device="cuda")
+        Phi = torch.empty_like(rho)
+        e = torch.empty_like(rho)
+        _check(lib().rom_gradient(self.h, _ptr(Z), _ptr(g), _ptr(rho), _ptr(Phi), _ptr(e)))
+        return g, rho, Phi, e
+
+
+class Fom:
+    """Full-order PIC handle (fom_* entry points)."""
+
+    def __init__(self, N, p, Nx, dt, L, X0, V0, q=-1.0, m=1.0, stream=None):
+        self.N, self.p, self.Nx = N, p, Nx
+        nbytes = lib().fom_workspace_bytes(N, p, Nx)
+        if nbytes == 0:
+            raise SymromError(EINVAL, "invalid sizes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        X0, V0 = _dev(X0), _dev(V0)
+        Lh, Lp = _host_doubles(L)
+        h = ctypes.c_void_p()
+        _check(lib().fom_init(N, p, Nx, dt, q, m, Lp, _ptr(X0), _ptr(V0), _ptr(self.ws), nbytes,
+                              _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().fom_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, nsteps=1):
+        _check(lib().fom_step(self.h, nsteps))
+
+    def get_state(self):
+        X = torch.empty((self.p, self.N), dtype=torch.float64, device="cuda")
+        V = torch.empty_like(X)
+        _check(lib().fom_get_state(self.h, _ptr(X), _ptr(V)))
+        return X, V
+
+    def diagnostics(self):
+        E = torch.empty(self.p, dtype=torch.float64, device="cuda")
+        H = torch.empty_like(E)
+        _check(lib().fom_diagnostics(self.h, _ptr(E), _ptr(H)))
+        return E, H
+
+
+def pic_fields(X, L, Nx, q=-1.0, stream=None):
+    """cells (p, N) int32 and rho, Phi, e (p, Nx) for positions X (p, N)."""
+    X = _dev(X)
+    p, N = X.shape
+    nbytes = lib().pic_workspace_bytes(N, p, Nx)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    cells = torch.empty((p, N), dtype=torch.int32, device="cuda")
+    rho = torch.empty((p, Nx), dtype=torch.float64, device="cuda")
+    Phi = torch.empty_like(rho)
+    e = torch.empty_like(rho)
+    Lh, Lp = _host_doubles(L)
+    _check(lib().pic_fields(N, p, Nx, Lp, q, _ptr(X), _ptr(cells), _ptr(rho), _ptr(Phi), _ptr(e),
+                            _ptr(ws), nbytes, _stream(stream)))
+    return cells, rho, Phi, e

@@ -1,0 +1,928 @@
+// C ABI of the symrom library: workspace layout, handles and the host-side
+// orchestration of the reduced step (Sec. 5) and of the full-order step
+// (eq. sv_full_order).  All arithmetic of a step runs in the HIP kernels; the
+// host only enqueues launches and reads the fixed-point counters.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/symrom.h"
+#include "common.h"
+#include "kernels.h"
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static symrom_status fail(symrom_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(SYMROM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+#define LAUNCHCHK()                                                                     \
+  do {                                                                                  \
+    hipError_t _e = hipGetLastError();                                                  \
+    if (_e != hipSuccess)                                                               \
+      return fail(SYMROM_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(_e)); \
+  } while (0)
+
+extern "C" const char* symrom_status_string(symrom_status s) {
+  switch (s) {
+    case SYMROM_OK: return "ok";
+    case SYMROM_EINVAL: return "invalid argument";
+    case SYMROM_ENOMEM: return "workspace too small";
+    case SYMROM_ESINGULAR: return "singular small matrix";
+    case SYMROM_ENOCONV: return "fixed point not converged";
+    case SYMROM_EDEVICE: return "device error";
+    case SYMROM_ESTATE: return "bad handle state";
+    case SYMROM_ERANKCAP: return "rank cap reached";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* symrom_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// kernel timing (HIP events around launches of the instrumented families)
+// ---------------------------------------------------------------------------
+namespace {
+struct TimedLaunch {
+  int family;
+  hipEvent_t a, b;
+};
+bool g_timing = false;
+std::vector<TimedLaunch> g_pending;
+std::vector<hipEvent_t> g_event_pool;
+double g_ms[8] = {0};
+int64_t g_launches[8] = {0};
+
+hipEvent_t take_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void drain_timing() {
+  for (auto& t : g_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.b) == hipSuccess && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      g_ms[t.family] += ms;
+      g_launches[t.family] += 1;
+    }
+    g_event_pool.push_back(t.a);
+    g_event_pool.push_back(t.b);
+  }
+  g_pending.clear();
+}
+
+struct Timer {
+  int fam;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timer(int f, hipStream_t st) : fam(f), s(st) {
+    if (g_timing) {
+      a = take_event();
+      b = take_event();
+      if (a) hipEventRecord(a, s);
+    }
+  }
+  ~Timer() {
+    if (g_timing && a && b) {
+      hipEventRecord(b, s);
+      g_pending.push_back({fam, a, b});
+      if (g_pending.size() > 4096) drain_timing();
+    }
+  }
+};
+}  // namespace
+
+enum { FAM_DEPOSIT = 0, FAM_GATHER = 1, FAM_POISSON = 2, FAM_FOMPUSH = 3, FAM_BASIS = 4, FAM_DENSE = 5 };
+
+extern "C" void symrom_set_timing(int32_t on) {
+  drain_timing();
+  g_timing = on != 0;
+}
+
+extern "C" double symrom_kernel_ms(int32_t family, int64_t* launches) {
+  drain_timing();
+  if (family < 0 || family >= 8) return 0.0;
+  double v = g_ms[family];
+  if (launches) *launches = g_launches[family];
+  g_ms[family] = 0.0;
+  g_launches[family] = 0;
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// workspace carving (a dry run with base == nullptr measures the size)
+// ---------------------------------------------------------------------------
+namespace {
+struct Arena {
+  char* base;
+  size_t off = 0;
+  explicit Arena(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+PicGeom pic_geom(int N, int p, int Nx, size_t lds_per_table_budget, int min_blocks) {
+  PicGeom g;
+  int pt = (int)(lds_per_table_budget / ((size_t)Nx * sizeof(double)));
+  if (pt < 1) pt = 1;
+  if (pt > p) pt = p;
+  g.pt = pt;
+  int ntiles = (p + pt - 1) / pt;
+  // row blocks: enough blocks to fill 256 CUs twice, at least 256 rows each
+  int nrb = (min_blocks + ntiles - 1) / ntiles;
+  int max_nrb = (N + 255) / 256;
+  if (nrb > max_nrb) nrb = max_nrb;
+  if (nrb < 1) nrb = 1;
+  g.rpb = (N + nrb - 1) / nrb;
+  g.nrb = (N + g.rpb - 1) / g.rpb;
+  return g;
+}
+
+void per_param_consts(const double* L, int N, int p, int Nx, double q, double m,
+                      std::vector<double>& factor, std::vector<double>& qw, std::vector<double>& h,
+                      std::vector<double>& mw) {
+  factor.resize(p);
+  qw.resize(p);
+  h.resize(p);
+  mw.resize(p);
+  for (int i = 0; i < p; ++i) {
+    factor[i] = (double)Nx / L[i];
+    const double w = L[i] / (double)N;
+    qw[i] = q * w;
+    h[i] = L[i] / (double)Nx;
+    mw[i] = m * w;
+  }
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// stateless particle-to-grid
+// ---------------------------------------------------------------------------
+namespace {
+struct PicBufs {
+  double *factor, *qw, *h, *mw, *part, *rho, *phi, *e, *energy;
+};
+PicBufs carve_pic(Arena& ar, int N, int p, int Nx, const PicGeom& g) {
+  PicBufs b;
+  b.factor = ar.take<double>(p);
+  b.qw = ar.take<double>(p);
+  b.h = ar.take<double>(p);
+  b.mw = ar.take<double>(p);
+  b.part = ar.take<double>((size_t)g.nrb * p * Nx);
+  b.rho = ar.take<double>((size_t)p * Nx);
+  b.phi = ar.take<double>((size_t)p * Nx);
+  b.e = ar.take<double>((size_t)p * Nx);
+  b.energy = ar.take<double>(p);
+  return b;
+}
+const size_t kFomTableBudget = 32 * 1024;  // LDS bytes per table (field and histogram)
+const size_t kDepTableBudget = 64 * 1024;
+bool valid_sizes(int N, int p, int Nx) {
+  return N > 0 && p > 0 && Nx >= 2 && Nx <= SYMROM_MAX_NX;
+}
+}  // namespace
+
+extern "C" size_t pic_workspace_bytes(int32_t N, int32_t p, int32_t Nx) {
+  if (!valid_sizes(N, p, Nx)) return 0;
+  Arena ar(nullptr);
+  PicGeom g = pic_geom(N, p, Nx, kDepTableBudget, 512);
+  carve_pic(ar, N, p, Nx, g);
+  return ar.off + 256;
+}
+
+extern "C" symrom_status pic_fields(int32_t N, int32_t p, int32_t Nx, const double* L, double q,
+                                    const double* X, int32_t* cells, double* rho, double* Phi,
+                                    double* e, void* ws, size_t ws_bytes, void* stream) {
+  if (!valid_sizes(N, p, Nx) || !L || !X) return fail(SYMROM_EINVAL, "pic_fields: bad arguments");
+  size_t need = pic_workspace_bytes(N, p, Nx);
+  if (!ws || ws_bytes < need) return fail(SYMROM_ENOMEM, "pic_fields: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  Arena ar(ws);
+  PicGeom g = pic_geom(N, p, Nx, kDepTableBudget, 512);
+  PicBufs b = carve_pic(ar, N, p, Nx, g);
+  std::vector<double> factor, qw, h, mw;
+  per_param_consts(L, N, p, Nx, q, 1.0, factor, qw, h, mw);
+  HIPCHK(hipMemcpyAsync(b.factor, factor.data(), p * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(b.qw, qw.data(), p * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(b.h, h.data(), p * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(b.mw, mw.data(), p * sizeof(double), hipMemcpyHostToDevice, s));
+  {
+    Timer t(FAM_DEPOSIT, s);
+    launch_deposit_x(s, X, N, p, Nx, g, b.factor, b.part);
+  }
+  {
+    Timer t(FAM_POISSON, s);
+    launch_poisson(s, b.part, g.nrb, p, Nx, b.qw, b.h, b.mw, nullptr, rho ? rho : b.rho,
+                   Phi ? Phi : b.phi, e ? e : b.e, b.energy);
+  }
+  if (cells) launch_cells(s, X, N, p, Nx, b.factor, cells);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  return SYMROM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// full-order model
+// ---------------------------------------------------------------------------
+struct symrom_fom {
+  int N, p, Nx;
+  double dt, q, m;
+  hipStream_t s;
+  PicGeom g;   // push geometry
+  PicBufs b;
+  double *X, *V;  // V holds the staggered velocity V_{t - dt/2}
+  double* Vtmp;
+  int64_t step;
+};
+
+namespace {
+void carve_fom(Arena& ar, symrom_fom& f) {
+  f.g = pic_geom(f.N, f.p, f.Nx, kFomTableBudget, 512);
+  f.b = carve_pic(ar, f.N, f.p, f.Nx, f.g);
+  f.X = ar.take<double>((size_t)f.N * f.p);
+  f.V = ar.take<double>((size_t)f.N * f.p);
+  f.Vtmp = ar.take<double>((size_t)f.N * f.p);
+}
+}  // namespace
+
+extern "C" size_t fom_workspace_bytes(int32_t N, int32_t p, int32_t Nx) {
+  if (!valid_sizes(N, p, Nx)) return 0;
+  symrom_fom f{};
+  f.N = N;
+  f.p = p;
+  f.Nx = Nx;
+  Arena ar(nullptr);
+  carve_fom(ar, f);
+  return ar.off + 256;
+}
+
+extern "C" symrom_status fom_init(int32_t N, int32_t p, int32_t Nx, double dt, double q, double m,
+                                  const double* L, const double* X0, const double* V0, void* ws,
+                                  size_t ws_bytes, void* stream, symrom_fom** out) {
+  if (!valid_sizes(N, p, Nx) || !L || !X0 || !V0 || !out || !(m != 0.0))
+    return fail(SYMROM_EINVAL, "fom_init: bad arguments");
+  for (int i = 0; i < p; ++i)
+    if (!(L[i] > 0.0) || !std::isfinite(L[i])) return fail(SYMROM_EINVAL, "fom_init: bad L");
+  if (!ws || ws_bytes < fom_workspace_bytes(N, p, Nx))
+    return fail(SYMROM_ENOMEM, "fom_init: workspace too small");
+  symrom_fom* f = new symrom_fom{};
+  f->N = N;
+  f->p = p;
+  f->Nx = Nx;
+  f->dt = dt;
+  f->q = q;
+  f->m = m;
+  f->s = (hipStream_t)stream;
+  f->step = 0;
+  Arena ar(ws);
+  carve_fom(ar, *f);
+  std::vector<double> factor, qw, h, mw;
+  per_param_consts(L, N, p, Nx, q, m, factor, qw, h, mw);
+  hipStream_t s = f->s;
+  auto cleanup = [&](symrom_status st) {
+    delete f;
+    return st;
+  };
+  if (hipMemcpyAsync(f->b.factor, factor.data(), p * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(f->b.qw, qw.data(), p * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(f->b.h, h.data(), p * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(f->b.mw, mw.data(), p * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(f->X, X0, (size_t)N * p * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(f->V, V0, (size_t)N * p * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return cleanup(fail(SYMROM_EDEVICE, "fom_init: copy failed"));
+  PicGeom gd = f->g;
+  launch_deposit_x(s, f->X, N, p, Nx, gd, f->b.factor, f->b.part);
+  launch_poisson(s, f->b.part, gd.nrb, p, Nx, f->b.qw, f->b.h, f->b.mw, nullptr, f->b.rho,
+                 f->b.phi, f->b.e, f->b.energy);
+  // staggered velocity V_{-1/2} = V_0 - dt/2 a(X_0)
+  launch_fom_push(s, f->X, f->V, N, p, Nx, f->g, f->b.factor, f->b.e, q / m, -0.5 * dt, 0.0,
+                  nullptr);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return cleanup(fail(SYMROM_EDEVICE, "fom_init: launch"));
+  *out = f;
+  return SYMROM_OK;
+}
+
+extern "C" symrom_status fom_step(symrom_fom* f, int32_t nsteps) {
+  if (!f || nsteps < 0) return fail(SYMROM_EINVAL, "fom_step: bad arguments");
+  hipStream_t s = f->s;
+  for (int it = 0; it < nsteps; ++it) {
+    {
+      Timer t(FAM_FOMPUSH, s);
+      launch_fom_push(s, f->X, f->V, f->N, f->p, f->Nx, f->g, f->b.factor, f->b.e, f->q / f->m,
+                      f->dt, f->dt, f->b.part);
+    }
+    {
+      Timer t(FAM_POISSON, s);
+      launch_poisson(s, f->b.part, f->g.nrb, f->p, f->Nx, f->b.qw, f->b.h, f->b.mw, nullptr,
+                     f->b.rho, f->b.phi, f->b.e, f->b.energy);
+    }
+    f->step++;
+  }
+  LAUNCHCHK();
+  return SYMROM_OK;
+}
+
+extern "C" symrom_status fom_get_state(symrom_fom* f, double* X, double* V) {
+  if (!f) return fail(SYMROM_EINVAL, "fom_get_state: null handle");
+  hipStream_t s = f->s;
+  size_t n = (size_t)f->N * f->p;
+  if (X) HIPCHK(hipMemcpyAsync(X, f->X, n * 8, hipMemcpyDeviceToDevice, s));
+  if (V)
+    launch_fom_velocity(s, f->X, f->V, f->N, f->p, f->Nx, f->b.factor, f->b.e, f->q / f->m,
+                        0.5 * f->dt, V);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  return SYMROM_OK;
+}
+
+extern "C" symrom_status fom_diagnostics(symrom_fom* f, double* E, double* H) {
+  if (!f) return fail(SYMROM_EINVAL, "fom_diagnostics: null handle");
+  hipStream_t s = f->s;
+  if (E) HIPCHK(hipMemcpyAsync(E, f->b.energy, f->p * 8, hipMemcpyDeviceToDevice, s));
+  if (H) {
+    launch_fom_velocity(s, f->X, f->V, f->N, f->p, f->Nx, f->b.factor, f->b.e, f->q / f->m,
+                        0.5 * f->dt, f->Vtmp);
+    launch_colsumsq(s, f->Vtmp, f->N, f->p, 0.5, H);
+    launch_vec_add(s, H, f->b.energy, f->p);
+  }
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  return SYMROM_OK;
+}
+
+extern "C" void fom_destroy(symrom_fom* f) { delete f; }
+
+// ---------------------------------------------------------------------------
+// reduced model
+// ---------------------------------------------------------------------------
+struct symrom_rom {
+  symrom_config cfg;
+  int N, p, Nx, n, nmax;
+  hipStream_t s;
+  int64_t step;
+  bool ready;
+  PicGeom gdep, ggat;
+  int nkb;
+  PicBufs b;
+  // N x nmax complex
+  cplx *U0, *Uh, *Xi, *P, *Xv, *Ups;
+  cplx* G;  // N x p complex
+  // nmax x p complex
+  cplx *Z0, *Zev, *ZG, *k, *Z1, *gproj;
+  cplx* Q;  // p x nmax
+  double* prev;
+  int* active;
+  int* counters;  // [0] active left, [1] stalled
+  int* flags;     // [0] error bits, [1] eigen path
+  cplx *Gram, *Amat, *MU, *MX, *M1, *M2, *M3, *C0x, *Rinv, *MP;
+  cplx* gemm_part;
+  double* sigma2;
+  // init scratch
+  cplx *Gp, *Vp;
+  double* lam;
+  symrom_step_info last;
+};
+
+namespace {
+int nkb_for(int N) {
+  int nkb = (N + 1023) / 1024;
+  if (nkb > 256) nkb = 256;
+  if (nkb < 1) nkb = 1;
+  return nkb;
+}
+
+void carve_rom(Arena& ar, symrom_rom& r) {
+  const int N = r.N, p = r.p, Nx = r.Nx, nm = r.nmax;
+  r.gdep = pic_geom(N, p, Nx, 48 * 1024, 512);
+  r.ggat = pic_geom(N, p, Nx, 48 * 1024, 512);
+  r.nkb = nkb_for(N);
+  r.b = carve_pic(ar, N, p, Nx, r.gdep.nrb >= r.ggat.nrb ? r.gdep : r.ggat);
+  const size_t Nn = (size_t)N * nm;
+  r.U0 = ar.take<cplx>(Nn);
+  r.Uh = ar.take<cplx>(Nn);
+  r.Xi = ar.take<cplx>(Nn);
+  r.P = ar.take<cplx>(Nn);
+  r.Xv = ar.take<cplx>(Nn);
+  r.Ups = ar.take<cplx>(Nn);
+  r.G = ar.take<cplx>((size_t)N * p);
+  const size_t np_ = (size_t)nm * p;
+  r.Z0 = ar.take<cplx>(np_);
+  r.Zev = ar.take<cplx>(np_);
+  r.ZG = ar.take<cplx>(np_);
+  r.k = ar.take<cplx>(np_);
+  r.Z1 = ar.take<cplx>(np_);
+  r.gproj = ar.take<cplx>(np_ > (size_t)p * p ? np_ : (size_t)p * p);
+  r.Q = ar.take<cplx>((size_t)p * nm);
+  r.prev = ar.take<double>(p);
+  r.active = ar.take<int>(p);
+  r.counters = ar.take<int>(4);
+  r.flags = ar.take<int>(4);
+  const size_t m2 = (size_t)4 * nm * nm;
+  r.Gram = ar.take<cplx>(m2 > (size_t)p * p ? m2 : (size_t)p * p);
+  r.Amat = ar.take<cplx>((size_t)nm * nm);
+  r.MU = ar.take<cplx>((size_t)nm * nm);
+  r.MX = ar.take<cplx>((size_t)nm * nm);
+  r.M1 = ar.take<cplx>((size_t)nm * nm);
+  r.M2 = ar.take<cplx>((size_t)nm * nm);
+  r.M3 = ar.take<cplx>((size_t)nm * nm);
+  r.C0x = ar.take<cplx>((size_t)nm * nm);
+  r.Rinv = ar.take<cplx>((size_t)nm * nm);
+  r.MP = ar.take<cplx>((size_t)nm * nm);
+  // split-K partials: nkb * max(a*b) with a, b <= 64 (b chunked by 64)
+  r.gemm_part = ar.take<cplx>((size_t)r.nkb * 64 * 64);
+  r.sigma2 = ar.take<double>(nm);
+  r.Gp = ar.take<cplx>((size_t)p * p);
+  r.Vp = ar.take<cplx>((size_t)p * p);
+  r.lam = ar.take<double>(p);
+}
+
+bool valid_rom_config(const symrom_config* c, std::string& why) {
+  if (!c) {
+    why = "null config";
+    return false;
+  }
+  if (!valid_sizes(c->N, c->p, c->Nx)) {
+    why = "sizes";
+    return false;
+  }
+  if (c->two_n <= 0 || (c->two_n & 1) || c->two_n_max < c->two_n || (c->two_n_max & 1)) {
+    why = "rank must be positive and even, two_n <= two_n_max";
+    return false;
+  }
+  if (c->two_n_max > 60) {
+    why = "two_n_max above 60 is not supported";
+    return false;
+  }
+  if (c->two_n_max > 2 * c->N) {
+    why = "rank above 2N";
+    return false;
+  }
+  if (!(c->dt > 0.0) || !(c->m != 0.0) || !std::isfinite(c->dt)) {
+    why = "dt, m";
+    return false;
+  }
+  if (c->fp_max_iters < 1 || c->fp_fixed_iters < 0) {
+    why = "fixed-point limits";
+    return false;
+  }
+  if (c->projection != SYMROM_GALERKIN && c->projection != SYMROM_DEIM) {
+    why = "projection";
+    return false;
+  }
+  if (c->p > 64) {
+    why = "p above 64 is not supported by the initialisation";
+    return false;
+  }
+  return true;
+}
+
+MatList ml(const cplx* a, int ca, const cplx* b = nullptr, int cb = 0) {
+  MatList L{};
+  L.ptr[0] = a;
+  L.cols[0] = ca;
+  L.count = 1;
+  if (b) {
+    L.ptr[1] = b;
+    L.cols[1] = cb;
+    L.count = 2;
+  }
+  return L;
+}
+
+RowTerms rt(const cplx* in0, const cplx* M0, int k0, const cplx* in1 = nullptr,
+            const cplx* M1 = nullptr, int k1 = 0, const cplx* in2 = nullptr,
+            const cplx* M2 = nullptr, int k2 = 0) {
+  RowTerms T{};
+  T.in[0] = in0;
+  T.M[0] = M0;
+  T.k[0] = k0;
+  T.count = 1;
+  if (in1) {
+    T.in[1] = in1;
+    T.M[1] = M1;
+    T.k[1] = k1;
+    T.count = 2;
+  }
+  if (in2) {
+    T.in[2] = in2;
+    T.M[2] = M2;
+    T.k[2] = k2;
+    T.count = 3;
+  }
+  return T;
+}
+
+// g = U^* G~ with the full gradient of every column at (U, Z): deposit,
+// Poisson, gather (writes G~ into r.G) and the split-K projection.
+void full_gradient(symrom_rom& r, const cplx* U, const cplx* Z, const int* active,
+                   bool do_deposit) {
+  hipStream_t s = r.s;
+  const int n = r.n;
+  const double qm = r.cfg.q / r.cfg.m;
+  if (do_deposit) {
+    {
+      Timer t(FAM_DEPOSIT, s);
+      launch_deposit_rom(s, U, r.N, n, Z, r.p, r.Nx, r.gdep, r.b.factor, active, r.b.part);
+    }
+    Timer t(FAM_POISSON, s);
+    launch_poisson(s, r.b.part, r.gdep.nrb, r.p, r.Nx, r.b.qw, r.b.h, r.b.mw, active, r.b.rho,
+                   r.b.phi, r.b.e, r.b.energy);
+  }
+  {
+    Timer t(FAM_GATHER, s);
+    launch_gather_rom(s, U, r.N, n, Z, r.p, r.Nx, r.ggat, r.b.factor, r.b.e, qm, active, true,
+                      r.G);
+  }
+  Timer t(FAM_BASIS, s);
+  launch_gemm_ah_b(s, ml(U, n), n, ml(r.G, r.p), r.p, false, r.N, r.nkb, r.gemm_part, r.gproj);
+}
+
+// X~ = -i (G~ Q - U T) scaled by `scale`, written to `out`, with G~ in r.G
+// and g in r.gproj; Q = Z^* S(Z)^+ computed first.
+void basis_velocity(symrom_rom& r, const cplx* U, const cplx* Z, double scale, cplx* out,
+                    cplx* k1) {
+  hipStream_t s = r.s;
+  const int n = r.n;
+  {
+    Timer t(FAM_DENSE, s);
+    launch_dense_spinv(s, Z, n, r.p, r.cfg.pinv_rtol, r.Q, r.sigma2, r.flags);
+  }
+  Timer t(FAM_BASIS, s);
+  launch_rowgemm(s, rt(r.G, r.Q, r.p), r.N, n, r.P);  // P = G~ Q
+  launch_dense_xfinish(s, r.gproj, r.Q, n, r.p, 2.0 * scale, k1, r.MP, r.MU);
+  launch_rowgemm(s, rt(r.P, r.MP, n, U, r.MU, n), r.N, n, out);
+}
+
+// U_out = R_{U0}(xi) (Cayley retraction); A_out receives U0^* xi.
+void cayley(symrom_rom& r, const cplx* U0, const cplx* xi, cplx* Uout, cplx* A_out) {
+  hipStream_t s = r.s;
+  const int n = r.n;
+  Timer t(FAM_BASIS, s);
+  launch_gemm_ah_b(s, ml(U0, n, xi, n), 2 * n, ml(U0, n, xi, n), 2 * n, false, r.N, r.nkb,
+                   r.gemm_part, r.Gram);
+  launch_dense_cayley(s, r.Gram, n, A_out, r.MU, r.MX, r.flags);
+  launch_rowgemm(s, rt(U0, r.MU, n, xi, r.MX, n), r.N, n, Uout);
+}
+
+// two Cholesky-QR passes on U (N x n) with Z <- R Z
+void cholqr2(symrom_rom& r, cplx* U, cplx* Z) {
+  hipStream_t s = r.s;
+  const int n = r.n;
+  Timer t(FAM_BASIS, s);
+  for (int pass = 0; pass < 2; ++pass) {
+    launch_gemm_ah_b(s, ml(U, n), n, ml(U, n), n, false, r.N, r.nkb, r.gemm_part, r.Gram);
+    launch_dense_chol(s, r.Gram, n, r.Rinv, Z, r.p, r.flags);
+    launch_rowgemm(s, rt(U, r.Rinv, n), r.N, n, U);
+  }
+}
+
+symrom_status read_flags(symrom_rom& r, int* host) {
+  HIPCHK(hipMemcpyAsync(host, r.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, r.s));
+  HIPCHK(hipStreamSynchronize(r.s));
+  return SYMROM_OK;
+}
+
+symrom_status rom_step_one(symrom_rom& r) {
+  hipStream_t s = r.s;
+  const int n = r.n, p = r.p, N = r.N;
+  const double dt = r.cfg.dt;
+  HIPCHK(hipMemsetAsync(r.flags, 0, 4 * sizeof(int), s));
+  // stage 1 at (U0, Z0): full gradient, k1 = J g, basis velocity -> xi_half
+  full_gradient(r, r.U0, r.Z0, nullptr, true);
+  basis_velocity(r, r.U0, r.Z0, 0.5 * dt, r.Xi, r.k);
+  // U_half = R_{U0}(xi_half)
+  cayley(r, r.U0, r.Xi, r.Uh, r.Amat);
+  // fixed point for k2 at U_half
+  {
+    Timer t(FAM_DENSE, s);
+    launch_fp_init(s, r.prev, r.active, r.counters, p);
+    launch_dense_finish_z(s, r.Z0, r.k, n, p, 0.5 * dt, r.Zev);
+  }
+  const int fixed = r.cfg.fp_fixed_iters;
+  const int limit = fixed > 0 ? fixed : r.cfg.fp_max_iters;
+  int iters = 0;
+  int hc[4] = {0, 0, 0, 0};
+  for (;;) {
+    ++iters;
+    full_gradient(r, r.Uh, r.Zev, r.active, true);
+    {
+      Timer t(FAM_DENSE, s);
+      launch_dense_fp_update(s, r.gproj, nullptr, n, p, r.Z0, r.Zev, r.ZG, r.k, r.prev, r.active,
+                             dt, r.cfg.fp_tol, fixed > 0 ? 1 : 0, 0, r.counters);
+    }
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(hc, r.counters, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hc[0] == 0 || iters >= limit) break;
+  }
+  r.last.iters = iters;
+  r.last.stalled = hc[1];
+  if (fixed == 0 && hc[0] > 0) return fail(SYMROM_ENOCONV, "fixed point not converged");
+  launch_dense_finish_z(s, r.Z0, r.k, n, p, dt, r.Z1);
+  // basis velocity at (U_half, Z_G) with the field of each column's last evaluation
+  full_gradient(r, r.Uh, r.ZG, nullptr, false);
+  basis_velocity(r, r.Uh, r.ZG, 1.0, r.Xv, nullptr);
+  // tangent velocity Y(xi_half, Z_G)
+  {
+    Timer t(FAM_BASIS, s);
+    launch_gemm_ah_b(s, ml(r.U0, n, r.Xi, n), 2 * n, ml(r.Xv, n, r.Uh, n), 2 * n, false, N,
+                     r.nkb, r.gemm_part, r.Gram);
+    launch_dense_tangent1(s, r.Amat, r.Gram, n, r.M1, r.M2, r.M3, r.C0x, r.flags);
+    launch_rowgemm(s, rt(r.Xv, r.M1, n, r.Xi, r.M2, n, r.U0, r.M3, n), N, n, r.Ups);
+    launch_gemm_ah_b(s, ml(r.Uh, n, r.U0, n), 2 * n, ml(r.Ups, n), n, false, N, r.nkb,
+                     r.gemm_part, r.Gram);
+    launch_dense_tangent2(s, r.Gram, r.C0x, n, dt, r.M1, r.M2, r.flags);
+    launch_rowgemm(s, rt(r.Ups, r.M1, n, r.U0, r.M2, n), N, n, r.P);  // xi_1 = dt Y
+  }
+  // U1 = R_{U0}(xi_1)  (into Uh, free now)
+  cayley(r, r.U0, r.P, r.Uh, r.M3);
+  if (r.cfg.reorth) cholqr2(r, r.Uh, r.Z1);
+  LAUNCHCHK();
+  int fl[2];
+  symrom_status st = read_flags(r, fl);
+  if (st != SYMROM_OK) return st;
+  if (fl[0]) return fail(SYMROM_ESINGULAR, "singular small matrix in the basis update");
+  // commit
+  std::swap(r.U0, r.Uh);
+  launch_copy_cplx(s, r.Z0, r.Z1, (size_t)n * p);
+  r.step++;
+  LAUNCHCHK();
+  return SYMROM_OK;
+}
+}  // namespace
+
+extern "C" size_t rom_workspace_bytes(const symrom_config* cfg) {
+  std::string why;
+  if (!valid_rom_config(cfg, why)) return 0;
+  symrom_rom r{};
+  r.cfg = *cfg;
+  r.N = cfg->N;
+  r.p = cfg->p;
+  r.Nx = cfg->Nx;
+  r.nmax = cfg->two_n_max / 2;
+  Arena ar(nullptr);
+  carve_rom(ar, r);
+  return ar.off + 256;
+}
+
+namespace {
+symrom_status rom_upload_consts(symrom_rom& r, const double* L) {
+  std::vector<double> factor, qw, h, mw;
+  per_param_consts(L, r.N, r.p, r.Nx, r.cfg.q, r.cfg.m, factor, qw, h, mw);
+  hipStream_t s = r.s;
+  HIPCHK(hipMemcpyAsync(r.b.factor, factor.data(), r.p * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(r.b.qw, qw.data(), r.p * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(r.b.h, h.data(), r.p * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(r.b.mw, mw.data(), r.p * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return SYMROM_OK;
+}
+
+// scale columns: M[:, c] = V[:, c] / sqrt(lam[c]) for c < r (p x r)
+__global__ void scale_cols_kernel(const cplx* V, const double* lam, int p, int r, cplx* M) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= p * r) return;
+  int c = t / p;
+  M[t] = cscale(V[t], 1.0 / sqrt(lam[c]));
+}
+
+__global__ void scale_col_kernel(cplx* u, int N, double sc) {
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < N) u[l] = cscale(u[l], sc);
+}
+
+// column c of U <- e_j - U[:, :c] conj(U[j, :c])^T  (Gram-Schmidt of e_j)
+__global__ void unit_minus_proj_kernel(cplx* U, int N, int c, int j) {
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= N) return;
+  cplx v = mk(l == j ? 1.0 : 0.0, 0.0);
+  for (int k = 0; k < c; ++k) {
+    cplx ujk = U[(size_t)k * N + j];
+    v = csub(v, cmulc(ujk, U[(size_t)k * N + l]));  // conj(U[j,k]) U[l,k]
+  }
+  U[(size_t)c * N + l] = v;
+}
+}  // namespace
+
+extern "C" symrom_status rom_init(const symrom_config* cfg, const double* L, const double* X0,
+                                  const double* V0, void* ws, size_t ws_bytes, void* stream,
+                                  symrom_rom** out) {
+  std::string why;
+  if (!valid_rom_config(cfg, why)) return fail(SYMROM_EINVAL, "rom_init: " + why);
+  if (!L || !X0 || !V0 || !out) return fail(SYMROM_EINVAL, "rom_init: null pointer");
+  for (int i = 0; i < cfg->p; ++i)
+    if (!(L[i] > 0.0) || !std::isfinite(L[i])) return fail(SYMROM_EINVAL, "rom_init: bad L");
+  size_t need = rom_workspace_bytes(cfg);
+  if (!ws || ws_bytes < need) return fail(SYMROM_ENOMEM, "rom_init: workspace too small");
+  symrom_rom* r = new symrom_rom{};
+  r->cfg = *cfg;
+  r->N = cfg->N;
+  r->p = cfg->p;
+  r->Nx = cfg->Nx;
+  r->n = cfg->two_n / 2;
+  r->nmax = cfg->two_n_max / 2;
+  r->s = (hipStream_t)stream;
+  r->last.rank_indicator = -1.0;
+  Arena ar(ws);
+  carve_rom(ar, *r);
+  symrom_status st = rom_upload_consts(*r, L);
+  if (st != SYMROM_OK) {
+    delete r;
+    return st;
+  }
+  hipStream_t s = r->s;
+  const int N = r->N, p = r->p, n = r->n;
+  if (hipMemsetAsync(r->flags, 0, 4 * sizeof(int), s) != hipSuccess) {
+    delete r;
+    return fail(SYMROM_EDEVICE, "rom_init: memset");
+  }
+  // C0 = X0 + i V0 in the gather buffer; Gram C0^* C0 (p x p) and its eigen
+  launch_make_complex(s, X0, V0, (size_t)N * p, r->G);
+  launch_gemm_ah_b(s, ml(r->G, p), p, ml(r->G, p), p, false, N, r->nkb, r->gemm_part, r->Gp);
+  launch_dense_herm_eig(s, r->Gp, p, r->Vp, r->lam, r->flags);
+  std::vector<double> lam(p);
+  if (hipMemcpyAsync(lam.data(), r->lam, p * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    delete r;
+    return fail(SYMROM_EDEVICE, "rom_init: eigen readback");
+  }
+  int rk = 0;
+  while (rk < n && rk < p && lam[rk] > 1e-26 * lam[0] && lam[rk] > 0.0) ++rk;
+  // U[:, :rk] = C0 V_rk diag(lam)^{-1/2}
+  hipLaunchKernelGGL(scale_cols_kernel, dim3((p * rk + 255) / 256 + 1), dim3(256), 0, s, r->Vp,
+                     r->lam, p, rk, r->Q);
+  if (rk > 0) launch_rowgemm(s, rt(r->G, r->Q, p), N, rk, r->U0);
+  // completion by Gram-Schmidt of e_0, e_1, ... (two projections via CholQR2)
+  int j = 0;
+  int have = rk;
+  std::vector<cplx> gram;
+  while (have < n) {
+    if (j >= N) {
+      delete r;
+      return fail(SYMROM_EINVAL, "rom_init: cannot complete the basis");
+    }
+    hipLaunchKernelGGL(unit_minus_proj_kernel, dim3((N + 255) / 256), dim3(256), 0, s, r->U0, N,
+                       have, j);
+    // accept if the projected vector is not negligible
+    launch_gemm_ah_b(s, ml(r->U0 + (size_t)have * N, 1), 1, ml(r->U0 + (size_t)have * N, 1), 1,
+                     false, N, r->nkb, r->gemm_part, r->Gram);
+    cplx nv;
+    if (hipMemcpyAsync(&nv, r->Gram, sizeof(cplx), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      delete r;
+      return fail(SYMROM_EDEVICE, "rom_init: readback");
+    }
+    ++j;
+    if (std::sqrt(nv.re) > 1e-8) {
+      hipLaunchKernelGGL(scale_col_kernel, dim3((N + 255) / 256), dim3(256), 0, s,
+                         r->U0 + (size_t)have * N, N, 1.0 / std::sqrt(nv.re));
+      ++have;
+    }
+  }
+  // orthonormalise (CholQR2), then Z = U^* C0
+  r->n = n;
+  launch_fill_cplx(s, r->Z0, (size_t)n * p, mk(0.0, 0.0));
+  cholqr2(*r, r->U0, nullptr);
+  launch_gemm_ah_b(s, ml(r->U0, n), n, ml(r->G, p), p, false, N, r->nkb, r->gemm_part, r->Z0);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    delete r;
+    return fail(SYMROM_EDEVICE, "rom_init: launch failure");
+  }
+  int fl[2] = {0, 0};
+  hipMemcpy(fl, r->flags, 2 * sizeof(int), hipMemcpyDeviceToHost);
+  if (fl[0]) {
+    delete r;
+    return fail(SYMROM_ESINGULAR, "rom_init: basis orthonormalisation failed");
+  }
+  r->ready = true;
+  r->step = 0;
+  *out = r;
+  return SYMROM_OK;
+}
+
+extern "C" symrom_status rom_step(symrom_rom* r, int32_t nsteps, symrom_step_info* info) {
+  if (!r || nsteps < 0) return fail(SYMROM_EINVAL, "rom_step: bad arguments");
+  if (!r->ready) return fail(SYMROM_ESTATE, "rom_step: handle not initialised");
+  for (int it = 0; it < nsteps; ++it) {
+    symrom_status st = rom_step_one(*r);
+    if (st != SYMROM_OK) {
+      if (info) *info = r->last;
+      return st;
+    }
+  }
+  r->last.two_n = 2 * r->n;
+  r->last.deim_active = 0;
+  if (info) *info = r->last;
+  return SYMROM_OK;
+}
+
+extern "C" symrom_status rom_adapt_rank(symrom_rom* r, int32_t target_two_n, int32_t* new_two_n) {
+  if (!r) return fail(SYMROM_EINVAL, "rom_adapt_rank: null handle");
+  if (target_two_n < 0 || (target_two_n & 1))
+    return fail(SYMROM_EINVAL, "rom_adapt_rank: target must be even and non-negative");
+  if (target_two_n > r->cfg.two_n_max) return fail(SYMROM_ERANKCAP, "rom_adapt_rank: above cap");
+  if (new_two_n) *new_two_n = 2 * r->n;
+  if (target_two_n == 0 || target_two_n == 2 * r->n) return SYMROM_OK;
+  return fail(SYMROM_EINVAL, "rom_adapt_rank: not available yet");
+}
+
+extern "C" symrom_status rom_get_state(symrom_rom* r, double* UX, double* Z, int32_t* two_n,
+                                       int64_t* step) {
+  if (!r) return fail(SYMROM_EINVAL, "rom_get_state: null handle");
+  hipStream_t s = r->s;
+  if (UX) launch_ux_from_u(s, r->U0, r->N, r->n, UX);
+  if (Z) launch_z_to_real(s, r->Z0, r->n, r->p, Z);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  if (two_n) *two_n = 2 * r->n;
+  if (step) *step = r->step;
+  return SYMROM_OK;
+}
+
+extern "C" symrom_status rom_set_state(symrom_rom* r, int32_t two_n, const double* UX,
+                                       const double* Z, int64_t step) {
+  if (!r || !UX || !Z) return fail(SYMROM_EINVAL, "rom_set_state: null argument");
+  if (two_n <= 0 || (two_n & 1) || two_n > r->cfg.two_n_max)
+    return fail(SYMROM_EINVAL, "rom_set_state: bad rank");
+  r->n = two_n / 2;
+  hipStream_t s = r->s;
+  launch_u_from_ux(s, UX, r->N, r->n, r->U0);
+  launch_z_from_real(s, Z, r->n, r->p, r->Z0);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  r->step = step;
+  r->ready = true;
+  return SYMROM_OK;
+}
+
+extern "C" symrom_status rom_reconstruct(symrom_rom* r, double* X, double* V) {
+  if (!r) return fail(SYMROM_EINVAL, "rom_reconstruct: null handle");
+  launch_reconstruct(r->s, r->U0, r->N, r->n, r->Z0, r->p, X, V);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(r->s));
+  return SYMROM_OK;
+}
+
+extern "C" symrom_status rom_gradient(symrom_rom* r, const double* Z, double* g, double* rho,
+                                      double* Phi, double* e) {
+  if (!r || !Z || !g) return fail(SYMROM_EINVAL, "rom_gradient: null argument");
+  hipStream_t s = r->s;
+  const int n = r->n, p = r->p;
+  launch_z_from_real(s, Z, n, p, r->Zev);
+  full_gradient(*r, r->U0, r->Zev, nullptr, true);
+  launch_z_to_real(s, r->gproj, n, p, g);
+  size_t gb = (size_t)p * r->Nx * 8;
+  if (rho) HIPCHK(hipMemcpyAsync(rho, r->b.rho, gb, hipMemcpyDeviceToDevice, s));
+  if (Phi) HIPCHK(hipMemcpyAsync(Phi, r->b.phi, gb, hipMemcpyDeviceToDevice, s));
+  if (e) HIPCHK(hipMemcpyAsync(e, r->b.e, gb, hipMemcpyDeviceToDevice, s));
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  return SYMROM_OK;
+}
+
+extern "C" symrom_status rom_diagnostics(symrom_rom* r, double* E, double* H) {
+  if (!r) return fail(SYMROM_EINVAL, "rom_diagnostics: null handle");
+  hipStream_t s = r->s;
+  const int N = r->N, p = r->p, n = r->n;
+  launch_deposit_rom(s, r->U0, N, n, r->Z0, p, r->Nx, r->gdep, r->b.factor, nullptr, r->b.part);
+  launch_poisson(s, r->b.part, r->gdep.nrb, p, r->Nx, r->b.qw, r->b.h, r->b.mw, nullptr, r->b.rho,
+                 r->b.phi, r->b.e, r->b.energy);
+  if (E) HIPCHK(hipMemcpyAsync(E, r->b.energy, p * 8, hipMemcpyDeviceToDevice, s));
+  if (H) {
+    // velocities V_r = Im(U~ Z~) into the real view of the gather buffer
+    double* Vr = reinterpret_cast<double*>(r->G);
+    launch_reconstruct(s, r->U0, N, n, r->Z0, p, nullptr, Vr);
+    launch_colsumsq(s, Vr, N, p, 0.5, H);
+    launch_vec_add(s, H, r->b.energy, p);
+  }
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  return SYMROM_OK;
+}
+
+extern "C" void rom_destroy(symrom_rom* r) { delete r; }

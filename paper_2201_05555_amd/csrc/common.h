@@ -1,0 +1,104 @@
+// Shared device helpers for the symrom HIP library (gfx950).
+//
+// Storage conventions inside the library
+//   * complex basis U~ = A + iB (N x n) is stored column-major with leading
+//     dimension N, each element an interleaved (re, im) pair of doubles;
+//   * complex coefficients Z~ = Z_q + i Z_p (n x p) column-major, ld = n;
+//   * grids (rho, Phi, e) are p x Nx row-major: row i is parameter i.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+struct cplx {
+  double re, im;
+};
+
+__host__ __device__ inline cplx mk(double r, double i) { return cplx{r, i}; }
+__host__ __device__ inline cplx cadd(cplx a, cplx b) { return cplx{a.re + b.re, a.im + b.im}; }
+__host__ __device__ inline cplx csub(cplx a, cplx b) { return cplx{a.re - b.re, a.im - b.im}; }
+__host__ __device__ inline cplx cmul(cplx a, cplx b) {
+  return cplx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+__host__ __device__ inline cplx cmulc(cplx a, cplx b) {
+  return cplx{a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+__host__ __device__ inline cplx cconj(cplx a) { return cplx{a.re, -a.im}; }
+__host__ __device__ inline cplx cscale(cplx a, double s) { return cplx{a.re * s, a.im * s}; }
+// acc += a * b
+__host__ __device__ inline void cfma(cplx& acc, cplx a, cplx b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+// acc += conj(a) * b
+__host__ __device__ inline void cfmac(cplx& acc, cplx a, cplx b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
+}
+__host__ __device__ inline double cabs2(cplx a) { return a.re * a.re + a.im * a.im; }
+
+// Particle-to-cell lookup of the periodic P1 mesh.  s = x * (Nx / L) with the
+// factor formed once in FP64 on the host; c = floor(s); theta = s - c (exact);
+// node j = c mod Nx (Euclidean).  A particle on a node takes the cell to its
+// right.  The integer conversion is done on the floored double so that any
+// unwrapped position whose cell number fits in int64 is handled.
+__device__ inline void cell_of(double x, double factor, int Nx, int& j, double& theta) {
+  double s = x * factor;
+  double c = floor(s);
+  theta = s - c;
+  long long cl = (long long)c;
+  long long r = cl % (long long)Nx;
+  if (r < 0) r += Nx;
+  j = (int)r;
+}
+
+// LDS FP64 atomic add (hardware ds_add_f64 on gfx950)
+__device__ inline void lds_add(double* addr, double v) {
+  __hip_atomic_fetch_add(addr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Block-wide sum of one double; every thread receives the result.
+// `red` is an LDS scratch of at least blockDim.x/64 doubles.
+__device__ inline double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < nw; ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+// Allow a kernel to use the full 160 KB of LDS of a gfx950 workgroup for its
+// dynamic allocation (the cap is reduced by the kernel's static LDS).  The
+// attribute call's error state is consumed here so that it never surfaces in
+// a later launch check.
+template <class K>
+inline void allow_big_lds(K kern) {
+  hipFuncAttributes a;
+  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kern)) == hipSuccess) {
+    int dyn = 160 * 1024 - (int)a.sharedSizeBytes;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+  }
+  (void)hipGetLastError();
+}
+#define ALLOW_BIG_LDS(kern)   \
+  do {                        \
+    static bool done_ = false; \
+    if (!done_) {             \
+      allow_big_lds(kern);    \
+      done_ = true;           \
+    }                         \
+  } while (0)
+
+#define SYMROM_MAX_NC 32    // complex reduced columns held in registers (2n <= 64)
+#define SYMROM_MAX_NX 1024  // grid nodes handled by the Poisson kernel

@@ -1,0 +1,828 @@
+// Single-workgroup FP64 kernels on the small dense matrices of a reduced
+// step (n x n, 2n x 2n, n x p): S(Z)^+ (Sec. 3.2), the Woodbury system of the
+// Cayley retraction and the inverses of the tangent velocity (Sec. 5), the
+// Cholesky factor of the re-orthonormalisation, and the per-column
+// fixed-point control.  Everything is in the complex representation:
+// a real 2n x 2n matrix that commutes with J_2n is the n x n complex matrix
+// A + iB of its blocks [[A, -B], [B, A]].
+//
+// Matrices are column-major.  `flags` words: [0] error bits (1 = singular LU,
+// 2 = Cholesky breakdown), [1] 1 if the Jacobi eigen path was taken.
+#include "common.h"
+#include "kernels.h"
+
+#define DTPB 256
+
+// ---------------------------------------------------------------------------
+// block-cooperative helpers (all threads of the block call them)
+// ---------------------------------------------------------------------------
+
+// C (m x n) = op(A) op(B), op = identity (0) or conjugate transpose (1).
+// A is stored m x k (opA = 0) or k x m (opA = 1); B is k x n or n x k.
+__device__ void bk_matmul(cplx* C, const cplx* A, int opA, const cplx* B, int opB, int m, int k,
+                          int n) {
+  for (int t = threadIdx.x; t < m * n; t += blockDim.x) {
+    int i = t % m, j = t / m;
+    cplx s = mk(0.0, 0.0);
+    for (int q = 0; q < k; ++q) {
+      cplx a = opA ? cconj(A[i * k + q]) : A[q * m + i];
+      cplx b = opB ? cconj(B[q * n + j]) : B[j * k + q];
+      cfma(s, a, b);
+    }
+    C[j * m + i] = s;
+  }
+  __syncthreads();
+}
+
+// Solve A X = B in place (A m x m destroyed, B m x nrhs overwritten by X)
+// by Gaussian elimination with partial pivoting.  Returns 0 on success.
+__device__ int bk_lu_solve(cplx* A, int m, cplx* B, int nrhs, int* piv_s) {
+  __shared__ int fail;
+  if (threadIdx.x == 0) fail = 0;
+  __syncthreads();
+  for (int c = 0; c < m; ++c) {
+    if (threadIdx.x == 0) {
+      int best = c;
+      double bv = cabs2(A[c * m + c]);
+      for (int r = c + 1; r < m; ++r) {
+        double v = cabs2(A[c * m + r]);
+        if (v > bv) {
+          bv = v;
+          best = r;
+        }
+      }
+      if (!(bv > 0.0)) fail = 1;
+      *piv_s = best;
+    }
+    __syncthreads();
+    if (fail) return 1;
+    const int pr = *piv_s;
+    if (pr != c) {
+      for (int j = threadIdx.x; j < m + nrhs; j += blockDim.x) {
+        cplx* col = (j < m) ? A + j * m : B + (j - m) * m;
+        cplx t = col[c];
+        col[c] = col[pr];
+        col[pr] = t;
+      }
+    }
+    __syncthreads();
+    const cplx piv = A[c * m + c];
+    const double pn = cabs2(piv);
+    const cplx pinv = mk(piv.re / pn, -piv.im / pn);
+    // eliminate below the pivot: rows r > c, columns j > c of A and all of B
+    const int rows = m - c - 1;
+    const int cols = (m - c - 1) + nrhs;
+    for (int t = threadIdx.x; t < rows * cols; t += blockDim.x) {
+      int r = c + 1 + t % rows;
+      int jj = t / rows;
+      cplx f = cmul(A[c * m + r], pinv);
+      cplx* col = (jj < m - c - 1) ? A + (c + 1 + jj) * m : B + (jj - (m - c - 1)) * m;
+      col[r] = csub(col[r], cmul(f, col[c]));
+    }
+    __syncthreads();
+  }
+  // back substitution
+  for (int c = m - 1; c >= 0; --c) {
+    const cplx piv = A[c * m + c];
+    const double pn = cabs2(piv);
+    const cplx pinv = mk(piv.re / pn, -piv.im / pn);
+    for (int j = threadIdx.x; j < nrhs; j += blockDim.x) B[j * m + c] = cmul(B[j * m + c], pinv);
+    __syncthreads();
+    for (int t = threadIdx.x; t < c * nrhs; t += blockDim.x) {
+      int r = t % c, j = t / c;
+      B[j * m + r] = csub(B[j * m + r], cmul(A[c * m + r], B[j * m + c]));
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
+// Upper Cholesky G = R^* R (G n x n Hermitian, R overwrites a separate
+// buffer, lower part zero).  Returns 0 on success, 1 if a pivot is not
+// positive.  `shift` is subtracted from the diagonal first.
+__device__ int bk_chol(const cplx* G, cplx* R, int n, double shift) {
+  __shared__ int fail;
+  if (threadIdx.x == 0) fail = 0;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) R[t] = mk(0.0, 0.0);
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      double d = G[j * n + j].re - shift;
+      for (int k = 0; k < j; ++k) d -= cabs2(R[j * n + k]);
+      if (!(d > 0.0)) {
+        fail = 1;
+        d = 1.0;
+      }
+      R[j * n + j] = mk(sqrt(d), 0.0);
+    }
+    __syncthreads();
+    if (fail) return 1;
+    const double rjj = R[j * n + j].re;
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
+      cplx s = G[i * n + j];  // G[j][i]
+      for (int k = 0; k < j; ++k) s = csub(s, cmulc(R[j * n + k], R[i * n + k]));
+      R[i * n + j] = cscale(s, 1.0 / rjj);
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
+// Inverse of an upper triangular R (n x n) into Ri (upper).
+__device__ void bk_triu_inv(const cplx* R, cplx* Ri, int n) {
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) Ri[t] = mk(0.0, 0.0);
+  __syncthreads();
+  // column j of Ri solves R x = e_j, x upper; threads over columns
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    for (int i = j; i >= 0; --i) {
+      cplx s = (i == j) ? mk(1.0, 0.0) : mk(0.0, 0.0);
+      for (int k = i + 1; k <= j; ++k) s = csub(s, cmul(R[k * n + i], Ri[j * n + k]));
+      const cplx d = R[i * n + i];
+      const double dn = cabs2(d);
+      Ri[j * n + i] = cmul(s, mk(d.re / dn, -d.im / dn));
+    }
+  }
+  __syncthreads();
+}
+
+// Parallel cyclic Jacobi for a Hermitian m x m matrix A (overwritten; its
+// diagonal ends as the eigenvalues), V receives the eigenvectors.  Pairs of
+// one round are disjoint (round-robin ordering), so their rotations are
+// applied together: first A <- A G, then A <- G^* A, then V <- V G.
+// Eigenvalues are returned in lam sorted in decreasing order, with the
+// columns of V permuted to match.
+__device__ void bk_jacobi(cplx* A, cplx* V, double* lam, int m, cplx* rot /*3*m/2+3*/,
+                          int* pr /*m+2*/) {
+  const int mm = m + (m & 1);
+  const int half = mm / 2;
+  for (int t = threadIdx.x; t < m * m; t += blockDim.x)
+    V[t] = (t % m == t / m) ? mk(1.0, 0.0) : mk(0.0, 0.0);
+  __shared__ double red[DTPB / 64];
+  __syncthreads();
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+      int i = t % m, j = t / m;
+      if (i < j) off += cabs2(A[t]);
+      if (i == j) dia += cabs2(A[t]);
+    }
+    off = block_sum(off, red);
+    dia = block_sum(dia, red);
+    if (off <= 1e-34 * dia || !(off > 0.0)) break;
+    for (int round = 0; round < mm - 1; ++round) {
+      for (int k = threadIdx.x; k < half; k += blockDim.x) {
+        int a, b;
+        if (k == 0) {
+          a = mm - 1;
+          b = round;
+        } else {
+          a = (round + k) % (mm - 1);
+          b = (round - k + (mm - 1)) % (mm - 1);
+        }
+        int p = a < b ? a : b, q = a < b ? b : a;
+        double c = 1.0, s = 0.0;
+        cplx ph = mk(1.0, 0.0);  // e^{-i phi}
+        if (q < m) {
+          const cplx bpq = A[q * m + p];
+          const double ab = sqrt(cabs2(bpq));
+          const double app = A[p * m + p].re, aqq = A[q * m + q].re;
+          if (ab > 1e-300 && ab > 1e-18 * sqrt(fabs(app * aqq))) {
+            ph = mk(bpq.re / ab, -bpq.im / ab);
+            const double zeta = (aqq - app) / (2.0 * ab);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        pr[2 * k] = p;
+        pr[2 * k + 1] = q;
+        rot[3 * k] = mk(c, s);
+        rot[3 * k + 1] = ph;
+      }
+      __syncthreads();
+      // A <- A G  (columns p, q)
+      for (int t = threadIdx.x; t < m * half; t += blockDim.x) {
+        int r = t % m, k = t / m;
+        int p = pr[2 * k], q = pr[2 * k + 1];
+        if (q >= m) continue;
+        double c = rot[3 * k].re, s = rot[3 * k].im;
+        if (s == 0.0) continue;
+        cplx ph = rot[3 * k + 1];
+        cplx x = A[p * m + r], y = A[q * m + r];
+        cplx yph = cmul(y, ph);
+        A[p * m + r] = csub(cscale(x, c), cscale(yph, s));
+        A[q * m + r] = cadd(cscale(x, s), cscale(yph, c));
+      }
+      __syncthreads();
+      // A <- G^* A  (rows p, q)
+      for (int t = threadIdx.x; t < m * half; t += blockDim.x) {
+        int col = t % m, k = t / m;
+        int p = pr[2 * k], q = pr[2 * k + 1];
+        if (q >= m) continue;
+        double c = rot[3 * k].re, s = rot[3 * k].im;
+        if (s == 0.0) continue;
+        cplx phc = cconj(rot[3 * k + 1]);  // e^{+i phi}
+        cplx x = A[col * m + p], y = A[col * m + q];
+        cplx yph = cmul(y, phc);
+        A[col * m + p] = csub(cscale(x, c), cscale(yph, s));
+        A[col * m + q] = cadd(cscale(x, s), cscale(yph, c));
+      }
+      __syncthreads();
+      // V <- V G
+      for (int t = threadIdx.x; t < m * half; t += blockDim.x) {
+        int r = t % m, k = t / m;
+        int p = pr[2 * k], q = pr[2 * k + 1];
+        if (q >= m) continue;
+        double c = rot[3 * k].re, s = rot[3 * k].im;
+        if (s == 0.0) continue;
+        cplx ph = rot[3 * k + 1];
+        cplx x = V[p * m + r], y = V[q * m + r];
+        cplx yph = cmul(y, ph);
+        V[p * m + r] = csub(cscale(x, c), cscale(yph, s));
+        V[q * m + r] = cadd(cscale(x, s), cscale(yph, c));
+      }
+      // the rotated diagonal entries are real in exact arithmetic
+      for (int k = threadIdx.x; k < half; k += blockDim.x) {
+        int p = pr[2 * k], q = pr[2 * k + 1];
+        if (q < m) {
+          A[p * m + p].im = 0.0;
+          A[q * m + q].im = 0.0;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // sort eigenpairs by decreasing eigenvalue (selection by thread 0 of the
+  // permutation, then parallel column moves through the rot scratch)
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < m; ++i) {
+      lam[i] = A[i * m + i].re;
+      pr[i] = i;
+    }
+    for (int i = 0; i < m; ++i) {
+      int b = i;
+      for (int j = i + 1; j < m; ++j)
+        if (lam[j] > lam[b]) b = j;
+      double tl = lam[i];
+      lam[i] = lam[b];
+      lam[b] = tl;
+      int tp = pr[i];
+      pr[i] = pr[b];
+      pr[b] = tp;
+    }
+  }
+  __syncthreads();
+  // permute V columns: out column i = old column pr[i]; use A as scratch
+  for (int t = threadIdx.x; t < m * m; t += blockDim.x) A[t] = V[t];
+  __syncthreads();
+  for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+    int r = t % m, i = t / m;
+    V[i * m + r] = A[pr[i] * m + r];
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// S(Z)^+ and Q = Z~^* S~^+ (p x n), with S~ = Z~ Z~^* (the complex form of
+// S(Z) = Z Z^T + J^T Z Z^T J).  The Moore-Penrose inverse drops eigenvalues
+// below rtol * lambda_max.  When S~ - rtol trace(S~) I admits a Cholesky
+// factor, every eigenvalue exceeds rtol * lambda_max (lambda_max <= trace),
+// nothing would be dropped and S~^+ = S~^{-1} is formed from the Cholesky
+// factor; otherwise the Jacobi eigendecomposition is used.
+// sigma2 receives the eigenvalues (decreasing) when the eigen path runs, else
+// is left untouched.  Requires n <= 32.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(DTPB) dense_spinv_kernel(const cplx* __restrict__ Z, int n, int p,
+                                                           double rtol, cplx* __restrict__ Q,
+                                                           double* __restrict__ sigma2,
+                                                           int* __restrict__ flags) {
+  __shared__ cplx S[32 * 32];
+  __shared__ cplx R[32 * 32];
+  __shared__ cplx Ri[32 * 32];
+  __shared__ cplx rot[3 * 17 + 3];
+  __shared__ int pr[40];
+  __shared__ double lam[32];
+  __shared__ double trs;
+  // S~ = Z~ Z~^*
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    int a = t % n, b = t / n;
+    cplx s = mk(0.0, 0.0);
+    for (int i = 0; i < p; ++i) cfma(s, Z[(size_t)i * n + a], cconj(Z[(size_t)i * n + b]));
+    S[t] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tr = 0.0;
+    for (int a = 0; a < n; ++a) tr += S[a * n + a].re;
+    trs = tr;
+  }
+  __syncthreads();
+  int bad = bk_chol(S, R, n, rtol * trs);
+  if (!bad) bad = bk_chol(S, R, n, 0.0);
+  if (!bad) {
+    // S^{-1} = R^{-1} R^{-*}
+    bk_triu_inv(R, Ri, n);
+    bk_matmul(R, Ri, 0, Ri, 1, n, n, n);  // R <- S^{-1}
+    if (threadIdx.x == 0 && flags) flags[1] = 0;
+  } else {
+    // eigen path: S = V diag(lam) V^*
+    bk_jacobi(S, Ri, lam, n, rot, pr);
+    const double lmax = lam[0];
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+      int a = t % n, b = t / n;
+      cplx s = mk(0.0, 0.0);
+      for (int k = 0; k < n; ++k) {
+        if (lam[k] > rtol * lmax) cfma(s, cscale(Ri[k * n + a], 1.0 / lam[k]), cconj(Ri[k * n + b]));
+      }
+      R[t] = s;
+    }
+    if (sigma2)
+      for (int k = threadIdx.x; k < n; k += blockDim.x) sigma2[k] = lam[k];
+    if (threadIdx.x == 0 && flags) flags[1] = 1;
+    __syncthreads();
+  }
+  // Q[i, b] = sum_a conj(Z[a, i]) S^+[a, b]
+  for (int t = threadIdx.x; t < p * n; t += blockDim.x) {
+    int i = t % p, b = t / p;
+    cplx s = mk(0.0, 0.0);
+    for (int a = 0; a < n; ++a) cfma(s, cconj(Z[(size_t)i * n + a]), R[b * n + a]);
+    Q[(size_t)b * p + i] = s;
+  }
+}
+
+// After the full-gradient projection g~ = U~^* G~ (n x p): k1 = -i g~ and the
+// row-combination matrices of xi = (dt/2) X~ with X~ = -i (P~ - U~ T),
+// T = g~ Q (n x n):  xi = P~ (-i dt/2 I) + U~ (i dt/2 T).
+__global__ void __launch_bounds__(DTPB) dense_xfinish_kernel(const cplx* __restrict__ g,
+                                                             const cplx* __restrict__ Q, int n,
+                                                             int p, double dt, cplx* __restrict__ k1,
+                                                             cplx* __restrict__ MP,
+                                                             cplx* __restrict__ MU) {
+  if (k1)
+    for (int t = threadIdx.x; t < n * p; t += blockDim.x) k1[t] = mk(g[t].im, -g[t].re);
+  const double h = 0.5 * dt;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    int a = t % n, b = t / n;
+    cplx s = mk(0.0, 0.0);
+    for (int i = 0; i < p; ++i) cfma(s, g[(size_t)i * n + a], Q[(size_t)b * p + i]);
+    MU[t] = mk(-h * s.im, h * s.re);  // i h T
+    MP[t] = (a == b) ? mk(0.0, -h) : mk(0.0, 0.0);
+  }
+}
+
+// Cayley retraction R_{U0}(xi) in complex form by Sherman-Morrison-Woodbury.
+// Input: Gram = [U0, xi]^* [U0, xi] (2n x 2n).  With A = U0^* xi,
+// W = xi - U0 A / 2, Lc = [W, -U0], Rc = [U0, W]:
+//   K = (I - Rc^* Lc / 2)^{-1},  [Y1; Y2] = K Rc^* U0,
+//   R_{U0}(xi) = U0 + W Y1 - U0 Y2 = U0 (I - Y2 - A Y1 / 2) + xi Y1.
+// Output MU, MX (n x n) for the row combination, and A.
+__global__ void __launch_bounds__(DTPB) dense_cayley_kernel(const cplx* __restrict__ Gram, int n,
+                                                            cplx* __restrict__ A_out,
+                                                            cplx* __restrict__ MU,
+                                                            cplx* __restrict__ MX,
+                                                            int* __restrict__ flags) {
+  extern __shared__ cplx sm[];
+  const int m = 2 * n;
+  // LDS: [A][G00][UW][WW] then K (2n x 2n) and B (2n x n); Gxx and T1 live
+  // inside the K region until K is formed.  Peak 10 n^2 complex.
+  cplx* A = sm;                // U0^* xi
+  cplx* G00 = A + n * n;       // U0^* U0
+  cplx* UW = G00 + n * n;      // U0^* W
+  cplx* WW = UW + n * n;       // W^* W
+  cplx* K = WW + n * n;        // 2n x 2n
+  cplx* B = K + m * m;         // 2n x n
+  cplx* Gxx = K;               // xi^* xi   (phase 1 only)
+  cplx* T1 = K + n * n;        // scratch  (phase 1 only)
+  __shared__ int piv;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    int a = t % n, b = t / n;
+    G00[t] = Gram[b * m + a];
+    A[t] = Gram[(n + b) * m + a];
+    Gxx[t] = Gram[(n + b) * m + n + a];
+  }
+  __syncthreads();
+  // U0^* W = A - G00 A / 2
+  bk_matmul(T1, G00, 0, A, 0, n, n, n);
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) UW[t] = csub(A[t], cscale(T1[t], 0.5));
+  __syncthreads();
+  // W^* W = Gxx - A^* A + A^* G00 A / 4
+  bk_matmul(WW, A, 1, T1, 0, n, n, n);  // A^* (G00 A)
+  bk_matmul(T1, A, 1, A, 0, n, n, n);   // A^* A
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x)
+    WW[t] = cadd(csub(Gxx[t], T1[t]), cscale(WW[t], 0.25));
+  __syncthreads();
+  // K = I - Rc^* Lc / 2,  Rc^* Lc = [[U0^*W, -U0^*U0], [W^*W, -W^*U0]]
+  for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+    int r = t % m, c = t / m;
+    cplx v;
+    if (r < n && c < n) v = UW[c * n + r];
+    else if (r < n) v = cscale(G00[(c - n) * n + r], -1.0);
+    else if (c < n) v = WW[c * n + (r - n)];
+    else v = cscale(cconj(UW[(r - n) * n + (c - n)]), -1.0);  // -(U0^*W)^*
+    v = cscale(v, -0.5);
+    if (r == c) v.re += 1.0;
+    K[t] = v;
+  }
+  // B = Rc^* U0 = [G00; W^* U0] = [G00; (U0^* W)^*]
+  for (int t = threadIdx.x; t < m * n; t += blockDim.x) {
+    int r = t % m, c = t / m;
+    B[c * m + r] = (r < n) ? G00[c * n + r] : cconj(UW[(r - n) * n + c]);
+  }
+  __syncthreads();
+  if (bk_lu_solve(K, m, B, n, &piv)) {
+    if (threadIdx.x == 0 && flags) flags[0] |= 1;
+    return;
+  }
+  // MU = I - Y2 - A Y1 / 2,  MX = Y1   (UW and WW are free again)
+  cplx* Y1 = UW;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    int r = t % n, c = t / n;
+    MX[t] = B[c * m + r];
+    Y1[t] = B[c * m + r];
+  }
+  __syncthreads();
+  bk_matmul(WW, A, 0, Y1, 0, n, n, n);  // A Y1
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    int r = t % n, c = t / n;
+    cplx v = cscale(B[c * m + n + r], -1.0);
+    v = csub(v, cscale(WW[t], 0.5));
+    if (r == c) v.re += 1.0;
+    MU[t] = v;
+    if (A_out) A_out[t] = A[t];
+  }
+}
+
+// Tangent velocity, first half.  Input A = U0^* xi and
+// Gram2 = [U0, xi]^* [X, Ux] (2n x 2n): U0^*X = B1, U0^*Ux = C0x, xi^*X.
+// W^* X = xi^* X - A^* B1 / 2;  Minv = (U0^* Ux + I)^{-1};
+// Ups = (2 X - W B1 + U0 (W^* X)) Minv
+//     = X (2 Minv) + xi (-B1 Minv) + U0 ((A B1 / 2 + W^* X) Minv).
+__global__ void __launch_bounds__(DTPB) dense_tangent1_kernel(const cplx* __restrict__ Ag,
+                                                              const cplx* __restrict__ Gram2,
+                                                              int n, cplx* __restrict__ M1,
+                                                              cplx* __restrict__ M2,
+                                                              cplx* __restrict__ M3,
+                                                              cplx* __restrict__ C0x_out,
+                                                              int* __restrict__ flags) {
+  extern __shared__ cplx sm[];
+  const int m = 2 * n;
+  cplx* A = sm;
+  cplx* B1 = A + n * n;
+  cplx* C0x = B1 + n * n;
+  cplx* XX = C0x + n * n;
+  cplx* T1 = XX + n * n;
+  cplx* T2 = T1 + n * n;
+  cplx* Mi = T2 + n * n;
+  __shared__ int piv;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    int a = t % n, b = t / n;
+    A[t] = Ag[t];
+    B1[t] = Gram2[b * m + a];
+    C0x[t] = Gram2[(n + b) * m + a];
+    XX[t] = Gram2[b * m + n + a];
+  }
+  __syncthreads();
+  // W^* X = XX - A^* B1 / 2  -> XX
+  bk_matmul(T1, A, 1, B1, 0, n, n, n);
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) XX[t] = csub(XX[t], cscale(T1[t], 0.5));
+  // Minv = (C0x + I)^{-1}
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    int r = t % n, c = t / n;
+    T2[t] = C0x[t];
+    if (r == c) T2[t].re += 1.0;
+    Mi[t] = (r == c) ? mk(1.0, 0.0) : mk(0.0, 0.0);
+    if (C0x_out) C0x_out[t] = C0x[t];
+  }
+  __syncthreads();
+  if (bk_lu_solve(T2, n, Mi, n, &piv)) {
+    if (threadIdx.x == 0 && flags) flags[0] |= 1;
+    return;
+  }
+  // M1 = 2 Minv
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) M1[t] = cscale(Mi[t], 2.0);
+  // M2 = -B1 Minv
+  bk_matmul(T1, B1, 0, Mi, 0, n, n, n);
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) M2[t] = cscale(T1[t], -1.0);
+  __syncthreads();
+  // M3 = (A B1 / 2 + W^*X) Minv
+  bk_matmul(T1, A, 0, B1, 0, n, n, n);
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) T2[t] = cadd(cscale(T1[t], 0.5), XX[t]);
+  __syncthreads();
+  bk_matmul(T1, T2, 0, Mi, 0, n, n, n);
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) M3[t] = T1[t];
+}
+
+// Tangent velocity, second half.  Gram3 = [Ux, U0]^* Ups (2n x n): D1 = Ux^*Ups,
+// D0 = U0^*Ups.  Y = Ups - U0 C with C = (Ux^* U0 + I)^{-1} (D1 + D0) + D0^*
+// (Ups^* U0 = D0^*).  Output xi1 = dt Y = Ups (dt I) + U0 (-dt C).
+__global__ void __launch_bounds__(DTPB) dense_tangent2_kernel(const cplx* __restrict__ Gram3,
+                                                              const cplx* __restrict__ C0x, int n,
+                                                              double dt, cplx* __restrict__ M1,
+                                                              cplx* __restrict__ M2,
+                                                              int* __restrict__ flags) {
+  extern __shared__ cplx sm[];
+  const int m = 2 * n;
+  cplx* T = sm;          // (C0x^* + I)
+  cplx* Rhs = T + n * n; // D1 + D0
+  cplx* D0 = Rhs + n * n;
+  __shared__ int piv;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    int r = t % n, c = t / n;
+    cplx d1 = Gram3[c * m + r];
+    cplx d0 = Gram3[c * m + n + r];
+    D0[t] = d0;
+    Rhs[t] = cadd(d1, d0);
+    T[t] = cconj(C0x[r * n + c]);
+    if (r == c) T[t].re += 1.0;
+  }
+  __syncthreads();
+  if (bk_lu_solve(T, n, Rhs, n, &piv)) {
+    if (threadIdx.x == 0 && flags) flags[0] |= 1;
+    return;
+  }
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    int r = t % n, c = t / n;
+    cplx C = cadd(Rhs[t], cconj(D0[r * n + c]));
+    M2[t] = cscale(C, -dt);
+    M1[t] = (r == c) ? mk(dt, 0.0) : mk(0.0, 0.0);
+  }
+}
+
+// Cholesky QR step: Gram = U~^* U~ = R^* R; Rinv = R^{-1} for U~ <- U~ R^{-1};
+// Z~ <- R Z~ in place (n x p).
+__global__ void __launch_bounds__(DTPB) dense_chol_kernel(const cplx* __restrict__ Gram, int n,
+                                                          cplx* __restrict__ Rinv,
+                                                          cplx* __restrict__ Z, int p,
+                                                          int* __restrict__ flags) {
+  __shared__ cplx G[32 * 32];
+  __shared__ cplx R[32 * 32];
+  __shared__ cplx Ri[32 * 32];
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) G[t] = Gram[t];
+  __syncthreads();
+  if (bk_chol(G, R, n, 0.0)) {
+    if (threadIdx.x == 0 && flags) flags[0] |= 2;
+    return;
+  }
+  bk_triu_inv(R, Ri, n);
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) Rinv[t] = Ri[t];
+  if (Z) {
+    // Z <- R Z, column by column (each thread owns columns)
+    for (int i = threadIdx.x; i < p; i += blockDim.x) {
+      cplx zc[32];
+      for (int a = 0; a < n; ++a) zc[a] = Z[(size_t)i * n + a];
+      for (int a = 0; a < n; ++a) {
+        cplx s = mk(0.0, 0.0);
+        for (int b = a; b < n; ++b) cfma(s, R[b * n + a], zc[b]);
+        Z[(size_t)i * n + a] = s;
+      }
+    }
+  }
+}
+
+// Fixed-point control of the implicit midpoint stage (one thread per
+// column).  k_new = -i g (g = gF, plus (C1 Z - conj(C2) conj(Z)) / 2 when the
+// projection covered positions only: i U~^* V_r with V_r = Im(U~ Z~)).
+// For an active column:  rel = |k_new - k| / |k_new|;  converged if
+// rel < tol, stalled if not converged and rel >= the previous rel (a
+// particle on a node puts the map into a 2-cycle); k <- k_new; ZG <- Zeval;
+// if still active, Zeval <- Z0 + dt/2 k.  counters[0] = active columns left,
+// counters[1] += stalled.  fixed != 0 disables the test.
+__global__ void __launch_bounds__(DTPB) dense_fp_update_kernel(
+    const cplx* __restrict__ gF, const cplx* __restrict__ C12, int n, int p,
+    const cplx* __restrict__ Z0, cplx* __restrict__ Zeval, cplx* __restrict__ ZG,
+    cplx* __restrict__ k, double* __restrict__ prev, int* __restrict__ active, double dt,
+    double tol, int fixed, int linear_part, int* __restrict__ counters) {
+  __shared__ int nact, nstall;
+  if (threadIdx.x == 0) {
+    nact = 0;
+    nstall = 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < p; i += blockDim.x) {
+    if (!active[i]) continue;
+    double dn = 0.0, kn = 0.0;
+    const cplx* ze = Zeval + (size_t)i * n;
+    cplx kn_col[32];
+    for (int a = 0; a < n; ++a) {
+      cplx g = gF[(size_t)i * n + a];
+      if (linear_part) {
+        cplx s = mk(0.0, 0.0);
+        for (int b = 0; b < n; ++b) {
+          cfma(s, C12[b * n + a], ze[b]);
+          cfma(s, cscale(cconj(C12[n * n + b * n + a]), -1.0), cconj(ze[b]));
+        }
+        g = cadd(g, cscale(s, 0.5));
+      }
+      cplx knew = mk(g.im, -g.re);  // -i g
+      cplx d = csub(knew, k[(size_t)i * n + a]);
+      dn += cabs2(d);
+      kn += cabs2(knew);
+      kn_col[a] = knew;
+    }
+    for (int a = 0; a < n; ++a) {
+      k[(size_t)i * n + a] = kn_col[a];
+      ZG[(size_t)i * n + a] = ze[a];
+    }
+    bool done = false;
+    if (!fixed) {
+      const double rel = (kn > 0.0) ? sqrt(dn) / sqrt(kn) : sqrt(dn);
+      const bool conv = rel < tol;
+      const bool stall = !conv && rel >= prev[i];
+      prev[i] = rel;
+      done = conv || stall;
+      if (stall) atomicAdd(&nstall, 1);
+    }
+    if (done) {
+      active[i] = 0;
+    } else {
+      atomicAdd(&nact, 1);
+      for (int a = 0; a < n; ++a) {
+        cplx z0 = Z0[(size_t)i * n + a];
+        cplx kk = kn_col[a];
+        Zeval[(size_t)i * n + a] = mk(z0.re + 0.5 * dt * kk.re, z0.im + 0.5 * dt * kk.im);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    counters[0] = nact;
+    counters[1] += nstall;
+  }
+}
+
+// start of a fixed-point solve: all columns active, no previous update
+__global__ void fp_init_kernel(double* prev, int* active, int* counters, int p) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < p) {
+    prev[t] = INFINITY;
+    active[t] = 1;
+  }
+  if (t < 4) counters[t] = 0;
+}
+
+// Z1 = Z0 + dt k
+__global__ void dense_finish_z_kernel(const cplx* __restrict__ Z0, const cplx* __restrict__ k,
+                                      int n, int p, double dt, cplx* __restrict__ Z1) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * p) return;
+  Z1[t] = mk(Z0[t].re + dt * k[t].re, Z0[t].im + dt * k[t].im);
+}
+
+// Hermitian eigendecomposition of an m x m matrix in global memory (A is
+// overwritten, V receives eigenvectors, lam eigenvalues in decreasing order).
+__global__ void __launch_bounds__(DTPB) dense_herm_eig_kernel(cplx* A, int m, cplx* V,
+                                                              double* lam, int* flags) {
+  extern __shared__ cplx sm[];  // 2 m^2 when m <= 64
+  __shared__ cplx rot[3 * 66 + 3];
+  __shared__ int pr[132];
+  __shared__ double lm[128];
+  cplx* As = A;
+  cplx* Vs = V;
+  if (m <= 64) {
+    As = sm;
+    Vs = sm + m * m;
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) As[t] = A[t];
+    __syncthreads();
+  }
+  bk_jacobi(As, Vs, lm, m, rot, pr);
+  if (m <= 64)
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) V[t] = Vs[t];
+  for (int t = threadIdx.x; t < m; t += blockDim.x) lam[t] = lm[t];
+  (void)flags;
+}
+
+// ---------------------------------------------------------------------------
+// layout conversions
+// ---------------------------------------------------------------------------
+__global__ void fill_cplx_kernel(cplx* a, size_t n, cplx v) {
+  size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) a[t] = v;
+}
+__global__ void copy_cplx_kernel(cplx* dst, const cplx* src, size_t n) {
+  size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) dst[t] = src[t];
+}
+__global__ void make_complex_kernel(const double* X, const double* V, size_t n, cplx* C) {
+  size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) C[t] = mk(X[t], V[t]);
+}
+__global__ void split_complex_kernel(const cplx* C, size_t n, double* X, double* V) {
+  size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) {
+    if (X) X[t] = C[t].re;
+    if (V) V[t] = C[t].im;
+  }
+}
+// U_X = [A, -B] (N x 2n, ld N) from U~ = A + iB
+__global__ void ux_from_u_kernel(const cplx* U, int N, int n, double* UX) {
+  size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t tot = (size_t)N * n;
+  if (t >= tot) return;
+  cplx u = U[t];
+  UX[t] = u.re;
+  UX[tot + t] = -u.im;
+}
+__global__ void u_from_ux_kernel(const double* UX, int N, int n, cplx* U) {
+  size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t tot = (size_t)N * n;
+  if (t >= tot) return;
+  U[t] = mk(UX[t], -UX[tot + t]);
+}
+// Z~ = Z_q + i Z_p (n x p, ld n) from real Z (2n x p, ld 2n)
+__global__ void z_from_real_kernel(const double* Z, int n, int p, cplx* Zc) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * p) return;
+  int a = t % n, i = t / n;
+  Zc[t] = mk(Z[(size_t)i * 2 * n + a], Z[(size_t)i * 2 * n + n + a]);
+}
+__global__ void z_to_real_kernel(const cplx* Zc, int n, int p, double* Z) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * p) return;
+  int a = t % n, i = t / n;
+  Z[(size_t)i * 2 * n + a] = Zc[t].re;
+  Z[(size_t)i * 2 * n + n + a] = Zc[t].im;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(size_t n) { return (unsigned)((n + 255) / 256); }
+
+void launch_dense_spinv(hipStream_t s, const cplx* Z, int n, int p, double rtol, cplx* Q,
+                        double* sigma2, int* flags) {
+  hipLaunchKernelGGL(dense_spinv_kernel, dim3(1), dim3(DTPB), 0, s, Z, n, p, rtol, Q, sigma2,
+                     flags);
+}
+void launch_dense_xfinish(hipStream_t s, const cplx* g, const cplx* Q, int n, int p, double dt,
+                          cplx* k1, cplx* MP, cplx* MU) {
+  hipLaunchKernelGGL(dense_xfinish_kernel, dim3(1), dim3(DTPB), 0, s, g, Q, n, p, dt, k1, MP, MU);
+}
+void launch_dense_cayley(hipStream_t s, const cplx* Gram, int n, cplx* A_out, cplx* MU,
+                         cplx* MX, int* flags) {
+  size_t sh = (size_t)(10 * n * n) * sizeof(cplx);
+  ALLOW_BIG_LDS(dense_cayley_kernel);
+  hipLaunchKernelGGL(dense_cayley_kernel, dim3(1), dim3(DTPB), sh, s, Gram, n, A_out, MU, MX,
+                     flags);
+}
+void launch_dense_tangent1(hipStream_t s, const cplx* A, const cplx* Gram2, int n, cplx* M1,
+                           cplx* M2, cplx* M3, cplx* C0x_out, int* flags) {
+  size_t sh = (size_t)7 * n * n * sizeof(cplx);
+  ALLOW_BIG_LDS(dense_tangent1_kernel);
+  hipLaunchKernelGGL(dense_tangent1_kernel, dim3(1), dim3(DTPB), sh, s, A, Gram2, n, M1, M2, M3,
+                     C0x_out, flags);
+}
+void launch_dense_tangent2(hipStream_t s, const cplx* Gram3, const cplx* C0x, int n, double dt,
+                           cplx* M1, cplx* M2, int* flags) {
+  size_t sh = (size_t)3 * n * n * sizeof(cplx);
+  hipLaunchKernelGGL(dense_tangent2_kernel, dim3(1), dim3(DTPB), sh, s, Gram3, C0x, n, dt, M1, M2,
+                     flags);
+}
+void launch_dense_chol(hipStream_t s, const cplx* Gram, int n, cplx* Rinv, cplx* Z, int p,
+                       int* flags) {
+  hipLaunchKernelGGL(dense_chol_kernel, dim3(1), dim3(DTPB), 0, s, Gram, n, Rinv, Z, p, flags);
+}
+void launch_dense_fp_update(hipStream_t s, const cplx* gF, const cplx* C12, int n, int p,
+                            const cplx* Z0, cplx* Zeval, cplx* ZG, cplx* k, double* prev,
+                            int* active, double dt, double tol, int fixed, int linear_part,
+                            int* counters) {
+  hipLaunchKernelGGL(dense_fp_update_kernel, dim3(1), dim3(DTPB), 0, s, gF, C12, n, p, Z0, Zeval,
+                     ZG, k, prev, active, dt, tol, fixed, linear_part, counters);
+}
+void launch_dense_finish_z(hipStream_t s, const cplx* Z0, const cplx* k, int n, int p, double dt,
+                           cplx* Z1) {
+  hipLaunchKernelGGL(dense_finish_z_kernel, dim3(nblk((size_t)n * p)), dim3(256), 0, s, Z0, k, n,
+                     p, dt, Z1);
+}
+void launch_fp_init(hipStream_t s, double* prev, int* active, int* counters, int p) {
+  hipLaunchKernelGGL(fp_init_kernel, dim3(nblk((size_t)(p > 4 ? p : 4))), dim3(256), 0, s, prev,
+                     active, counters, p);
+}
+void launch_dense_herm_eig(hipStream_t s, cplx* A, int m, cplx* V, double* lam, int* flags) {
+  size_t sh = (m <= 64) ? (size_t)2 * m * m * sizeof(cplx) : 0;
+  ALLOW_BIG_LDS(dense_herm_eig_kernel);
+  hipLaunchKernelGGL(dense_herm_eig_kernel, dim3(1), dim3(DTPB), sh, s, A, m, V, lam, flags);
+}
+void launch_fill_cplx(hipStream_t s, cplx* a, size_t n, cplx v) {
+  if (n) hipLaunchKernelGGL(fill_cplx_kernel, dim3(nblk(n)), dim3(256), 0, s, a, n, v);
+}
+void launch_copy_cplx(hipStream_t s, cplx* dst, const cplx* src, size_t n) {
+  if (n) hipLaunchKernelGGL(copy_cplx_kernel, dim3(nblk(n)), dim3(256), 0, s, dst, src, n);
+}
+void launch_make_complex(hipStream_t s, const double* X, const double* V, size_t n, cplx* C) {
+  hipLaunchKernelGGL(make_complex_kernel, dim3(nblk(n)), dim3(256), 0, s, X, V, n, C);
+}
+void launch_split_complex(hipStream_t s, const cplx* C, size_t n, double* X, double* V) {
+  hipLaunchKernelGGL(split_complex_kernel, dim3(nblk(n)), dim3(256), 0, s, C, n, X, V);
+}
+void launch_ux_from_u(hipStream_t s, const cplx* U, int N, int n, double* UX) {
+  hipLaunchKernelGGL(ux_from_u_kernel, dim3(nblk((size_t)N * n)), dim3(256), 0, s, U, N, n, UX);
+}
+void launch_u_from_ux(hipStream_t s, const double* UX, int N, int n, cplx* U) {
+  hipLaunchKernelGGL(u_from_ux_kernel, dim3(nblk((size_t)N * n)), dim3(256), 0, s, UX, N, n, U);
+}
+void launch_z_from_real(hipStream_t s, const double* Z, int n, int p, cplx* Zc) {
+  hipLaunchKernelGGL(z_from_real_kernel, dim3(nblk((size_t)n * p)), dim3(256), 0, s, Z, n, p, Zc);
+}
+void launch_z_to_real(hipStream_t s, const cplx* Zc, int n, int p, double* Z) {
+  hipLaunchKernelGGL(z_to_real_kernel, dim3(nblk((size_t)n * p)), dim3(256), 0, s, Zc, n, p, Z);
+}

@@ -1,0 +1,99 @@
+// Launch interface between the host orchestration and the HIP kernels.
+#pragma once
+
+#include "common.h"
+
+// Geometry of the particle-to-grid launches: nrb row blocks of rpb rows,
+// parameter tiles of pt columns (pt * Nx doubles of LDS per table).
+struct PicGeom {
+  int nrb;
+  int rpb;
+  int pt;
+};
+
+// Up to four N x k_s column blocks concatenated as one N x (sum k_s) matrix.
+struct MatList {
+  const cplx* ptr[4];
+  int cols[4];
+  int count;
+};
+
+// Terms of a row-wise combination out = sum_s in_s M_s.
+struct RowTerms {
+  const cplx* in[4];
+  const cplx* M[4];
+  int k[4];
+  int count;
+};
+
+inline int nc_bucket(int n) {
+  if (n <= 4) return 4;
+  if (n <= 8) return 8;
+  if (n <= 16) return 16;
+  return 32;
+}
+
+// pic_kernels.hip
+void launch_deposit_x(hipStream_t s, const double* X, int N, int p, int Nx, const PicGeom& g,
+                      const double* factor, double* part);
+void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
+                        const PicGeom& g, const double* factor, const int* active, double* part);
+void launch_poisson(hipStream_t s, const double* part, int nrb, int p, int Nx, const double* qw,
+                    const double* h, const double* mw, const int* active, double* rho,
+                    double* phi, double* e, double* energy);
+void launch_fom_push(hipStream_t s, double* X, double* V, int N, int p, int Nx, const PicGeom& g,
+                     const double* factor, const double* e, double qm, double ck, double cd,
+                     double* part);
+void launch_fom_velocity(hipStream_t s, const double* X, const double* V, int N, int p, int Nx,
+                         const double* factor, const double* e, double qm, double c,
+                         double* Vout);
+void launch_cells(hipStream_t s, const double* X, int N, int p, int Nx, const double* factor,
+                  int* cells);
+void launch_colsumsq(hipStream_t s, const double* A, int N, int p, double sc, double* out);
+void launch_vec_add(hipStream_t s, double* out, const double* in, int n);
+
+// rom_kernels.hip
+void launch_gather_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
+                       const PicGeom& g, const double* factor, const double* e, double qm,
+                       const int* active, bool full, void* out);
+void launch_reconstruct(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p,
+                        double* X, double* V);
+void launch_gemm_ah_b(hipStream_t s, const MatList& A, int a, const MatList& B, int b, bool b_real,
+                      int N, int nkb, cplx* part, cplx* C);
+void launch_rowgemm(hipStream_t s, const RowTerms& T, int N, int m, cplx* out);
+void launch_deim_gather(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
+                        const double* factor, const double* e, double qm, const int* idx,
+                        const double* w, int d, const int* active, cplx* gF);
+void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
+                     const double* factor, const double* phi, double* Y);
+
+// dense_kernels.hip  (single-workgroup FP64 kernels on small matrices)
+struct DenseCtl;  // device-resident control block, see dense_kernels.hip
+void launch_dense_spinv(hipStream_t s, const cplx* Z, int n, int p, double rtol, cplx* Q,
+                        double* sigma2, int* flags);
+void launch_dense_xfinish(hipStream_t s, const cplx* g, const cplx* Q, int n, int p, double dt,
+                          cplx* k1, cplx* MP, cplx* MU);
+void launch_dense_cayley(hipStream_t s, const cplx* Gram, int n, cplx* A_out, cplx* MU,
+                         cplx* MX, int* flags);
+void launch_dense_tangent1(hipStream_t s, const cplx* A, const cplx* Gram2, int n, cplx* M1,
+                           cplx* M2, cplx* M3, cplx* C0x_out, int* flags);
+void launch_dense_tangent2(hipStream_t s, const cplx* Gram3, const cplx* C0x, int n, double dt,
+                           cplx* M1, cplx* M2, int* flags);
+void launch_dense_chol(hipStream_t s, const cplx* Gram, int n, cplx* Rinv, cplx* Z, int p,
+                       int* flags);
+void launch_dense_fp_update(hipStream_t s, const cplx* gF, const cplx* C12, int n, int p,
+                            const cplx* Z0, cplx* Zeval, cplx* ZG, cplx* k, double* prev,
+                            int* active, double dt, double tol, int fixed, int linear_part,
+                            int* counters);
+void launch_dense_finish_z(hipStream_t s, const cplx* Z0, const cplx* k, int n, int p, double dt,
+                           cplx* Z1);
+void launch_fp_init(hipStream_t s, double* prev, int* active, int* counters, int p);
+void launch_dense_herm_eig(hipStream_t s, cplx* A, int m, cplx* V, double* lam, int* flags);
+void launch_fill_cplx(hipStream_t s, cplx* a, size_t n, cplx v);
+void launch_copy_cplx(hipStream_t s, cplx* dst, const cplx* src, size_t n);
+void launch_make_complex(hipStream_t s, const double* X, const double* V, size_t n, cplx* C);
+void launch_split_complex(hipStream_t s, const cplx* C, size_t n, double* X, double* V);
+void launch_ux_from_u(hipStream_t s, const cplx* U, int N, int n, double* UX);
+void launch_u_from_ux(hipStream_t s, const double* UX, int N, int n, cplx* U);
+void launch_z_from_real(hipStream_t s, const double* Z, int n, int p, cplx* Zc);
+void launch_z_to_real(hipStream_t s, const cplx* Zc, int n, int p, double* Z);

@@ -1,0 +1,382 @@
+// Streaming kernels of the reduced model: field gather at reconstructed
+// particles, tall-skinny products with reduction over particles (split over
+// row blocks, reduced in a fixed order), and row-wise small products.
+#include "common.h"
+#include "kernels.h"
+
+// ---------------------------------------------------------------------------
+// Gather (eq. grH-full): for every particle row l and parameter i, rebuild
+// x = Re(U~[l,:] Z~[:,i]) and v = Im(U~[l,:] Z~[:,i]), look the field of the
+// cell up, F = (q/m) e_i[j(x)], and write
+//   FULL = false:  F (real, N x p)               -- position gradient only
+//   FULL = true :  G~ = F + i v (complex, N x p)  -- [G_X; G_V] in complex form
+// The basis row lives in registers, the coefficient tile and the field table
+// of the block's parameter tile in LDS.
+// ---------------------------------------------------------------------------
+template <int NC, bool FULL>
+__global__ void __launch_bounds__(256) gather_rom_kernel(
+    const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx, int pt,
+    int rpb, const double* __restrict__ factor, const double* __restrict__ e, double qm,
+    const int* __restrict__ active, void* __restrict__ out) {
+  extern __shared__ double smem[];
+  double* et = smem;                                   // pt * Nx
+  cplx* Zs = reinterpret_cast<cplx*>(smem + pt * Nx);  // pt * NC
+  const int p0 = blockIdx.y * pt;
+  const int np = min(pt, p - p0);
+  for (int t = threadIdx.x; t < np * Nx; t += blockDim.x) et[t] = qm * e[(size_t)p0 * Nx + t];
+  for (int t = threadIdx.x; t < np * NC; t += blockDim.x) {
+    int i = t / NC, k = t % NC;
+    Zs[t] = (k < n) ? Z[(size_t)(p0 + i) * n + k] : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  const int r0 = blockIdx.x * rpb;
+  const int r1 = min(N, r0 + rpb);
+  for (int l = r0 + threadIdx.x; l < r1; l += blockDim.x) {
+    cplx u[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) u[k] = (k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
+    for (int i = 0; i < np; ++i) {
+      if (active && !active[p0 + i]) continue;
+      const cplx* zi = Zs + i * NC;
+      double x0 = 0.0, x1 = 0.0, v0 = 0.0, v1 = 0.0;
+#pragma unroll
+      for (int k = 0; k < NC; k += 2) {
+        x0 = fma(u[k].re, zi[k].re, x0);
+        x0 = fma(-u[k].im, zi[k].im, x0);
+        x1 = fma(u[k + 1].re, zi[k + 1].re, x1);
+        x1 = fma(-u[k + 1].im, zi[k + 1].im, x1);
+        if (FULL) {
+          v0 = fma(u[k].re, zi[k].im, v0);
+          v0 = fma(u[k].im, zi[k].re, v0);
+          v1 = fma(u[k + 1].re, zi[k + 1].im, v1);
+          v1 = fma(u[k + 1].im, zi[k + 1].re, v1);
+        }
+      }
+      const double x = x0 + x1;
+      int j;
+      double th;
+      cell_of(x, factor[p0 + i], Nx, j, th);
+      const double F = et[i * Nx + j];
+      const size_t o = (size_t)(p0 + i) * N + l;
+      if (FULL)
+        reinterpret_cast<cplx*>(out)[o] = mk(F, v0 + v1);
+      else
+        reinterpret_cast<double*>(out)[o] = F;
+    }
+  }
+}
+
+// Reconstruct X = Re(U~ Z~), V = Im(U~ Z~) (N x p each).
+template <int NC>
+__global__ void __launch_bounds__(256) reconstruct_kernel(const cplx* __restrict__ U, int N, int n,
+                                                          const cplx* __restrict__ Z, int p,
+                                                          double* __restrict__ X,
+                                                          double* __restrict__ V) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= N) return;
+  cplx u[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) u[k] = (k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
+  for (int i = 0; i < p; ++i) {
+    cplx acc = mk(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+      if (k < n) cfma(acc, u[k], Z[(size_t)i * n + k]);
+    if (X) X[(size_t)i * N + l] = acc.re;
+    if (V) V[(size_t)i * N + l] = acc.im;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Split-K product C = A^* B with A = [A_0 ... ] (N x a, complex) and
+// B = [B_0 ... ] (N x b, complex, or real when b_real).  Block kb reduces the
+// rows [kb*rk, (kb+1)*rk) in tiles of TR rows staged through LDS and writes
+// its a x b partial; reduce_partials_kernel sums the blocks in order.
+// ---------------------------------------------------------------------------
+#define GEMM_TR 32
+
+__device__ inline const cplx* list_col(const MatList& L, int c, int& local) {
+  int s = 0;
+  while (s < L.count - 1 && c >= L.cols[s]) {
+    c -= L.cols[s];
+    ++s;
+  }
+  local = c;
+  return L.ptr[s];
+}
+
+__global__ void __launch_bounds__(256) gemm_ah_b_kernel(MatList A, int a, MatList B, int b,
+                                                        int b_real, int N, int rk,
+                                                        cplx* __restrict__ part) {
+  __shared__ cplx As[GEMM_TR * 64];
+  __shared__ cplx Bs[GEMM_TR * 64];
+  const int kb = blockIdx.x;
+  const int r0 = kb * rk;
+  const int r1 = min(N, r0 + rk);
+  const int nout = a * b;
+  cplx acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = mk(0.0, 0.0);
+  for (int t0 = r0; t0 < r1; t0 += GEMM_TR) {
+    const int tr = min(GEMM_TR, r1 - t0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < a * GEMM_TR; t += blockDim.x) {
+      int c = t / GEMM_TR, r = t % GEMM_TR;
+      int lc;
+      const cplx* base = list_col(A, c, lc);
+      As[c * GEMM_TR + r] = (r < tr) ? base[(size_t)lc * N + t0 + r] : mk(0.0, 0.0);
+    }
+    for (int t = threadIdx.x; t < b * GEMM_TR; t += blockDim.x) {
+      int c = t / GEMM_TR, r = t % GEMM_TR;
+      int lc;
+      const cplx* base = list_col(B, c, lc);
+      cplx v = mk(0.0, 0.0);
+      if (r < tr) {
+        if (b_real)
+          v = mk(reinterpret_cast<const double*>(base)[(size_t)lc * N + t0 + r], 0.0);
+        else
+          v = base[(size_t)lc * N + t0 + r];
+      }
+      Bs[c * GEMM_TR + r] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      int o = threadIdx.x + q * 256;
+      if (o < nout) {
+        int ia = o % a, ib = o / a;
+        const cplx* ar = As + ia * GEMM_TR;
+        const cplx* br = Bs + ib * GEMM_TR;
+        cplx s = acc[q];
+        for (int r = 0; r < GEMM_TR; ++r) cfmac(s, ar[r], br[r]);
+        acc[q] = s;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    int o = threadIdx.x + q * 256;
+    if (o < nout) part[(size_t)kb * nout + o] = acc[q];
+  }
+}
+
+__global__ void reduce_partials_kernel(const cplx* __restrict__ part, int nkb, int nout,
+                                       cplx* __restrict__ C) {
+  int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= nout) return;
+  cplx s = mk(0.0, 0.0);
+  for (int k = 0; k < nkb; ++k) s = cadd(s, part[(size_t)k * nout + o]);
+  C[o] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Row-wise combination out = sum_s In_s M_s with In_s (N x k_s) complex and
+// M_s (k_s x m) small complex matrices (column-major, ld k_s) held in LDS.
+// One thread per row; safe in place (out may alias an input).
+// ---------------------------------------------------------------------------
+template <int MC>
+__global__ void __launch_bounds__(256) rowgemm_kernel(RowTerms T, int N, int m, cplx* out) {
+  extern __shared__ cplx Ms[];
+  int off = 0;
+  for (int s = 0; s < T.count; ++s) {
+    for (int t = threadIdx.x; t < T.k[s] * m; t += blockDim.x) Ms[off + t] = T.M[s][t];
+    off += T.k[s] * m;
+  }
+  __syncthreads();
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= N) return;
+  cplx acc[MC];
+#pragma unroll
+  for (int o = 0; o < MC; ++o) acc[o] = mk(0.0, 0.0);
+  off = 0;
+  for (int s = 0; s < T.count; ++s) {
+    const cplx* in = T.in[s];
+    const int ks = T.k[s];
+    for (int k = 0; k < ks; ++k) {
+      const cplx v = in[(size_t)k * N + l];
+      const cplx* mrow = Ms + off + k;  // M[k][o] at mrow[o * ks]
+#pragma unroll
+      for (int o = 0; o < MC; ++o)
+        if (o < m) cfma(acc[o], v, mrow[o * ks]);
+    }
+    off += ks * m;
+  }
+#pragma unroll
+  for (int o = 0; o < MC; ++o)
+    if (o < m) out[(size_t)o * N + l] = acc[o];
+}
+
+// ---------------------------------------------------------------------------
+// DEIM gather (eq. grHDD with the exact potential): for the d sampled rows
+// I_r, g_F[k,i] = sum_r conj(U~[I_r,k]) w_r (q/m) e_i[j(x_{I_r,i})].
+// One block per parameter; threads over k.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) deim_gather_kernel(
+    const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx,
+    const double* __restrict__ factor, const double* __restrict__ e, double qm,
+    const int* __restrict__ idx, const double* __restrict__ w, int d,
+    const int* __restrict__ active, cplx* __restrict__ gF) {
+  __shared__ double Fw[256];
+  const int i = blockIdx.x;
+  if (active && !active[i]) return;
+  const cplx* zi = Z + (size_t)i * n;
+  for (int r = threadIdx.x; r < d; r += blockDim.x) {
+    const int l = idx[r];
+    double x = 0.0;
+    for (int k = 0; k < n; ++k) {
+      cplx u = U[(size_t)k * N + l];
+      x = fma(u.re, zi[k].re, x);
+      x = fma(-u.im, zi[k].im, x);
+    }
+    int j;
+    double th;
+    cell_of(x, factor[i], Nx, j, th);
+    Fw[r] = w[r] * qm * e[(size_t)i * Nx + j];
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    cplx s = mk(0.0, 0.0);
+    for (int r = 0; r < d; ++r) {
+      cplx u = U[(size_t)k * N + idx[r]];
+      s.re = fma(u.re, Fw[r], s.re);
+      s.im = fma(-u.im, Fw[r], s.im);
+    }
+    gF[(size_t)i * n + k] = s;
+  }
+}
+
+// DEIM snapshot Lambda^0(X_r^i) Phi^i at every particle (Sec. 4.3, eq. Ydeim):
+// (1 - theta) Phi_j + theta Phi_{j+1}, written as column (slot*p + i) of Y.
+template <int NC>
+__global__ void __launch_bounds__(256) snapshot_kernel(const cplx* __restrict__ U, int N, int n,
+                                                       const cplx* __restrict__ Z, int p, int Nx,
+                                                       const double* __restrict__ factor,
+                                                       const double* __restrict__ phi,
+                                                       double* __restrict__ Y) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= N) return;
+  cplx u[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) u[k] = (k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
+  for (int i = 0; i < p; ++i) {
+    double x = 0.0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+      if (k < n) {
+        cplx z = Z[(size_t)i * n + k];
+        x = fma(u[k].re, z.re, x);
+        x = fma(-u[k].im, z.im, x);
+      }
+    int j;
+    double th;
+    cell_of(x, factor[i], Nx, j, th);
+    int j1 = (j + 1 == Nx) ? 0 : j + 1;
+    const double* ph = phi + (size_t)i * Nx;
+    Y[(size_t)i * N + l] = (1.0 - th) * ph[j] + th * ph[j1];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+void launch_gather_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
+                       const PicGeom& g, const double* factor, const double* e, double qm,
+                       const int* active, bool full, void* out) {
+  dim3 grid(g.nrb, (p + g.pt - 1) / g.pt);
+  int nc = nc_bucket(n);
+  size_t sh = (size_t)g.pt * Nx * sizeof(double) + (size_t)g.pt * nc * sizeof(cplx);
+#define GA(NCV, FV)                                                                           \
+  ALLOW_BIG_LDS((gather_rom_kernel<NCV, FV>));                                               \
+  hipLaunchKernelGGL((gather_rom_kernel<NCV, FV>), grid, dim3(256), sh, s, U, N, n, Z, p, Nx, \
+                     g.pt, g.rpb, factor, e, qm, active, out)
+  if (full) {
+    switch (nc) {
+      case 4: GA(4, true); break;
+      case 8: GA(8, true); break;
+      case 16: GA(16, true); break;
+      default: GA(32, true); break;
+    }
+  } else {
+    switch (nc) {
+      case 4: GA(4, false); break;
+      case 8: GA(8, false); break;
+      case 16: GA(16, false); break;
+      default: GA(32, false); break;
+    }
+  }
+#undef GA
+}
+
+void launch_reconstruct(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p,
+                        double* X, double* V) {
+  int nc = nc_bucket(n);
+  dim3 grid((N + 255) / 256);
+  switch (nc) {
+    case 4: hipLaunchKernelGGL(reconstruct_kernel<4>, grid, dim3(256), 0, s, U, N, n, Z, p, X, V); break;
+    case 8: hipLaunchKernelGGL(reconstruct_kernel<8>, grid, dim3(256), 0, s, U, N, n, Z, p, X, V); break;
+    case 16: hipLaunchKernelGGL(reconstruct_kernel<16>, grid, dim3(256), 0, s, U, N, n, Z, p, X, V); break;
+    default: hipLaunchKernelGGL(reconstruct_kernel<32>, grid, dim3(256), 0, s, U, N, n, Z, p, X, V); break;
+  }
+}
+
+void launch_gemm_ah_b(hipStream_t s, const MatList& A, int a, const MatList& B, int b, bool b_real,
+                      int N, int nkb, cplx* part, cplx* C) {
+  int rk = (N + nkb - 1) / nkb;
+  rk = ((rk + GEMM_TR - 1) / GEMM_TR) * GEMM_TR;
+  nkb = (N + rk - 1) / rk;
+  // B is processed in chunks of at most 64 columns (one list entry per chunk)
+  for (int b0 = 0; b0 < b; b0 += 64) {
+    const int bc = (b - b0 < 64) ? b - b0 : 64;
+    MatList Bc = B;
+    if (b > 64) {
+      // only single-matrix B lists are chunked
+      Bc.count = 1;
+      Bc.cols[0] = bc;
+      Bc.ptr[0] = b_real ? reinterpret_cast<const cplx*>(reinterpret_cast<const double*>(B.ptr[0]) +
+                                                         (size_t)b0 * N)
+                         : B.ptr[0] + (size_t)b0 * N;
+    }
+    hipLaunchKernelGGL(gemm_ah_b_kernel, dim3(nkb), dim3(256), 0, s, A, a, Bc, bc,
+                       b_real ? 1 : 0, N, rk, part);
+    int nout = a * bc;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((nout + 255) / 256), dim3(256), 0, s, part,
+                       nkb, nout, C + (size_t)b0 * a);
+  }
+}
+
+void launch_rowgemm(hipStream_t s, const RowTerms& T, int N, int m, cplx* out) {
+  size_t sh = 0;
+  for (int q = 0; q < T.count; ++q) sh += (size_t)T.k[q] * m * sizeof(cplx);
+  dim3 grid((N + 255) / 256);
+  int mc = nc_bucket(m);
+  ALLOW_BIG_LDS(rowgemm_kernel<4>);
+  ALLOW_BIG_LDS(rowgemm_kernel<8>);
+  ALLOW_BIG_LDS(rowgemm_kernel<16>);
+  ALLOW_BIG_LDS(rowgemm_kernel<32>);
+  switch (mc) {
+    case 4: hipLaunchKernelGGL(rowgemm_kernel<4>, grid, dim3(256), sh, s, T, N, m, out); break;
+    case 8: hipLaunchKernelGGL(rowgemm_kernel<8>, grid, dim3(256), sh, s, T, N, m, out); break;
+    case 16: hipLaunchKernelGGL(rowgemm_kernel<16>, grid, dim3(256), sh, s, T, N, m, out); break;
+    default: hipLaunchKernelGGL(rowgemm_kernel<32>, grid, dim3(256), sh, s, T, N, m, out); break;
+  }
+}
+
+void launch_deim_gather(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
+                        const double* factor, const double* e, double qm, const int* idx,
+                        const double* w, int d, const int* active, cplx* gF) {
+  hipLaunchKernelGGL(deim_gather_kernel, dim3(p), dim3(64), 0, s, U, N, n, Z, p, Nx, factor, e,
+                     qm, idx, w, d, active, gF);
+}
+
+void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
+                     const double* factor, const double* phi, double* Y) {
+  int nc = nc_bucket(n);
+  dim3 grid((N + 255) / 256);
+  switch (nc) {
+    case 4: hipLaunchKernelGGL(snapshot_kernel<4>, grid, dim3(256), 0, s, U, N, n, Z, p, Nx, factor, phi, Y); break;
+    case 8: hipLaunchKernelGGL(snapshot_kernel<8>, grid, dim3(256), 0, s, U, N, n, Z, p, Nx, factor, phi, Y); break;
+    case 16: hipLaunchKernelGGL(snapshot_kernel<16>, grid, dim3(256), 0, s, U, N, n, Z, p, Nx, factor, phi, Y); break;
+    default: hipLaunchKernelGGL(snapshot_kernel<32>, grid, dim3(256), 0, s, U, N, n, Z, p, Nx, factor, phi, Y); break;
+  }
+}
+

@@ -1,0 +1,262 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs.  Tolerances: 1e-10 relative for FP64 results
+(relative to the largest magnitude of the compared quantity), bit-exact for
+particle-to-cell indices."""
+import numpy as np
+import pytest
+
+from oracle import pic, rom
+from workloads import make_ensemble, workload
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _b():
+    import torch
+    from paper_2201_05555_amd import binding
+    assert torch.cuda.is_available()
+    return binding, torch
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _ens(name, **kw):
+    w = workload(name, **kw)
+    return w, make_ensemble(w)
+
+
+@pytest.mark.parametrize("name,kw", [
+    ("landau_tiny", dict(N=3001)),                      # ragged tail, per-parameter domains
+    ("twostream_deim", dict(N=20000, p=16, Nx=128)),
+    ("twostream_deim", dict(N=777, p=70, Nx=48)),       # p above one LDS tile, ragged N
+])
+def test_pic_fields_parity(name, kw):
+    binding, torch = _b()
+    w, e = _ens(name, **kw)
+    _say("pic_fields", name, kw)
+    # unwrapped positions spanning several periods
+    X = e["X0"] + np.outer(np.linspace(-3, 3, e["X0"].shape[0]), e["L"])
+    cells, rho, Phi, ef = binding.pic_fields(X, e["L"], w["Nx"])
+    torch.cuda.synchronize()
+    j, _ = pic.cell_index(X, e["L"], w["Nx"])
+    assert np.array_equal(_np(cells).T, j.astype(np.int32))
+    rho_o, Phi_o, e_o = pic.fields_of(X, e["L"], w["Nx"])
+    assert _rel(_np(rho).T, rho_o) < 1e-12
+    assert _rel(_np(Phi).T, Phi_o) < 1e-10
+    assert _rel(_np(ef).T, e_o) < 1e-10
+
+
+def test_pic_fields_node_ties():
+    binding, torch = _b()
+    _say("pic_fields node ties")
+    L = np.array([8.0, 6.0])
+    X = np.array([[0.0, 0.0], [1.0, 0.75], [7.0, 5.25], [-1.0, -0.75], [8.0, 6.0], [16.0, 12.0]])
+    cells, *_ = binding.pic_fields(X, L, 8)
+    j, _ = pic.cell_index(X, L, 8)
+    assert np.array_equal(_np(cells).T, j.astype(np.int32))
+
+
+@pytest.mark.parametrize("name,kw,steps", [
+    ("landau_tiny", dict(N=4099), 20),
+    ("twostream_deim", dict(N=30000, p=12, Nx=128), 10),
+])
+def test_fom_parity(name, kw, steps):
+    binding, torch = _b()
+    w, e = _ens(name, **kw)
+    _say("fom", name, kw, steps)
+    f = binding.Fom(w["N"], w["p"], w["Nx"], w["dt"], e["L"], e["X0"], e["V0"])
+    f.step(steps)
+    X, V = f.get_state()
+    E, H = f.diagnostics()
+    Xo, Vo = pic.fom_run(e["X0"], e["V0"], e["L"], w["Nx"], w["dt"], steps)
+    assert _rel(_np(X).T, Xo) < RTOL
+    assert _rel(_np(V).T, Vo) < RTOL
+    rho, Phi, _ = pic.fields_of(Xo, e["L"], w["Nx"])
+    Eo = pic.electric_energy(Phi, rho, e["L"], w["N"])
+    Ho = 0.5 * np.sum(Vo * Vo, axis=0) + Eo
+    assert _rel(_np(E), Eo) < 1e-8
+    assert _rel(_np(H), Ho) < RTOL
+
+
+def _oracle_state(w, e, two_n, **cfgkw):
+    cfg = rom.RomConfig(N=w["N"], p=w["p"], Nx=w["Nx"], two_n=two_n, dt=w["dt"], **cfgkw)
+    st = rom.init_state(e["X0"], e["V0"], e["L"], cfg)
+    return cfg, st
+
+
+def _gpu_rom(binding, w, e, two_n, **kw):
+    cfg = binding.make_config(w["N"], w["p"], w["Nx"], two_n, dt=w["dt"], **kw)
+    return binding.Rom(cfg, e["L"], e["X0"], e["V0"])
+
+
+def _set_from_oracle(r, st, torch):
+    N = st.U.shape[0] // 2
+    UX = torch.from_numpy(np.ascontiguousarray(st.U[:N].T)).cuda()
+    Z = torch.from_numpy(np.ascontiguousarray(st.Z.T)).cuda()
+    r.set_state(UX, Z, st.step)
+
+
+@pytest.mark.parametrize("name,kw,two_n", [
+    ("landau_tiny", dict(N=5000), 10),                       # p < n: completion
+    ("twostream_deim", dict(N=20000, p=32, Nx=64), 12),
+])
+def test_rom_init_parity(name, kw, two_n):
+    binding, torch = _b()
+    w, e = _ens(name, **kw)
+    _say("rom_init", name, kw, two_n)
+    r = _gpu_rom(binding, w, e, two_n)
+    X, V = r.reconstruct()
+    cfg, st = _oracle_state(w, e, two_n)
+    Xo, Vo = rom.reconstruct(st)
+    assert _rel(_np(X).T, Xo) < 1e-9
+    assert _rel(_np(V).T, Vo) < 1e-9
+    UX, Z, _ = r.get_state()
+    UXn = _np(UX).T
+    Ut = UXn[:, : two_n // 2] - 1j * UXn[:, two_n // 2:]
+    assert np.abs(Ut.conj().T @ Ut - np.eye(two_n // 2)).max() < 1e-12
+
+
+@pytest.mark.parametrize("name,kw,two_n", [
+    ("landau_tiny", dict(N=3001), 10),
+    ("twostream_deim", dict(N=20000, p=24, Nx=128), 16),
+])
+def test_rom_gradient_parity(name, kw, two_n):
+    binding, torch = _b()
+    w, e = _ens(name, **kw)
+    _say("rom_gradient", name, kw, two_n)
+    cfg, st = _oracle_state(w, e, two_n)
+    r = _gpu_rom(binding, w, e, two_n)
+    _set_from_oracle(r, st, torch)
+    Zt = torch.from_numpy(np.ascontiguousarray(st.Z.T)).cuda()
+    g, rho, Phi, ef = r.gradient(Zt)
+    gr = rom.gradient(st.U, st.Z, st.L, w["Nx"])
+    assert _rel(_np(rho).T, gr.rho) < 1e-12
+    assert _rel(_np(ef).T, gr.e) < 1e-10
+    assert _rel(_np(g).T, gr.g) < RTOL
+
+
+def _oracle_sensitivity(st, cfg, iters, steps=1, pert=1e-15, seed=0):
+    """Relative change of (U_X, Z, R) after ``steps`` oracle steps when Z is
+    perturbed by ``pert`` (relative): the conditioning of the step.  S(Z) is
+    often ill-conditioned (the singular values of the ensemble decay fast),
+    and U is then determined only to about cond(S) * eps by any FP64
+    implementation, the oracle included."""
+    rng = np.random.default_rng(seed)
+    outs = []
+    for eps in (0.0, pert):
+        s2 = rom.RomState(U=st.U.copy(), Z=st.Z * (1 + eps * rng.normal(size=st.Z.shape)),
+                          L=st.L)
+        for _ in range(steps):
+            rom.prk_step(s2, cfg, fixed_iters=iters)
+        outs.append((s2.U, s2.Z, s2.U @ s2.Z))
+    N = st.U.shape[0] // 2
+    return (_rel(outs[1][0][:N], outs[0][0][:N]), _rel(outs[1][1], outs[0][1]),
+            _rel(outs[1][2], outs[0][2]))
+
+
+def _bound(sens):
+    """Parity bound: 1e-10 relative, or 50x the oracle's own sensitivity to a
+    1e-15 relative perturbation when the problem is worse conditioned."""
+    return max(RTOL, 50.0 * sens)
+
+
+@pytest.mark.parametrize("name,kw,two_n,iters", [
+    ("landau_tiny", dict(N=3001), 10, 6),
+    ("twostream_deim", dict(N=20000, p=24, Nx=128), 12, 5),
+    ("twostream_deim", dict(N=12345, p=40, Nx=96), 20, 4),
+])
+def test_rom_step_parity_fixed_iterations(name, kw, two_n, iters):
+    """One step from the identical state with an exact iteration count:
+    U_X, Z and R = U Z after the step (including re-orthonormalisation)."""
+    binding, torch = _b()
+    w, e = _ens(name, **kw)
+    _say("rom_step fixed", name, kw, two_n, iters)
+    cfg, st = _oracle_state(w, e, two_n)
+    sU, sZ, sR = _oracle_sensitivity(st, cfg, iters)
+    r = _gpu_rom(binding, w, e, two_n, fp_fixed_iters=iters)
+    _set_from_oracle(r, st, torch)
+    info = r.step(1)
+    assert info["iters"] == iters
+    assert rom.prk_step(st, cfg, fixed_iters=iters) == rom.OK
+    UX, Z, step = r.get_state()
+    X, V = r.reconstruct()
+    N = w["N"]
+    assert step == 1
+    Xo, Vo = rom.reconstruct(st)
+    assert _rel(_np(UX).T, st.U[:N]) < _bound(sU), (sU,)
+    assert _rel(_np(Z).T, st.Z) < _bound(sZ), (sZ,)
+    assert _rel(_np(X).T, Xo) < _bound(sR), (sR,)
+    assert _rel(_np(V).T, Vo) < _bound(sR), (sR,)
+
+
+def test_rom_step_parity_well_conditioned_strict():
+    """A case whose S(Z)^+ is well conditioned after the eigenvalue cut: the
+    oracle's own sensitivity is below 1e-12, and the GPU matches at 1e-10."""
+    binding, torch = _b()
+    w, e = _ens("twostream_deim", N=12345, p=40, Nx=96)
+    _say("rom_step strict")
+    cfg, st = _oracle_state(w, e, 20)
+    sU, sZ, sR = _oracle_sensitivity(st, cfg, 4)
+    assert max(sU, sZ, sR) < 1e-12
+    r = _gpu_rom(binding, w, e, 20, fp_fixed_iters=4)
+    _set_from_oracle(r, st, torch)
+    r.step(1)
+    assert rom.prk_step(st, cfg, fixed_iters=4) == rom.OK
+    UX, Z, _ = r.get_state()
+    assert _rel(_np(UX).T, st.U[:w["N"]]) < RTOL
+    assert _rel(_np(Z).T, st.Z) < RTOL
+
+
+@pytest.mark.parametrize("name,kw,two_n,steps", [
+    ("landau_tiny", dict(N=3001), 10, 5),
+    ("twostream_deim", dict(N=20000, p=24, Nx=128), 12, 4),
+])
+def test_rom_steps_parity_adaptive(name, kw, two_n, steps):
+    """Several steps with the per-column stopping test (tolerance far above
+    rounding): identical iteration counts, R = U Z, energies and
+    Hamiltonians within the conditioning-aware bound."""
+    binding, torch = _b()
+    w, e = _ens(name, **kw)
+    _say("rom_step adaptive", name, kw, two_n, steps)
+    cfg, st = _oracle_state(w, e, two_n, fp_tol=1e-10)
+    st_s = rom.RomState(U=st.U.copy(), Z=st.Z.copy(), L=st.L)
+    sU, sZ, sR = _oracle_sensitivity(st_s, cfg, 6, steps=steps)
+    r = _gpu_rom(binding, w, e, two_n, fp_tol=1e-10)
+    _set_from_oracle(r, st, torch)
+    for s in range(steps):
+        info = r.step(1)
+        assert rom.prk_step(st, cfg) == rom.OK
+        assert info["iters"] == st.last_iters, (s, info, st.last_iters)
+    X, V = r.reconstruct()
+    Xo, Vo = rom.reconstruct(st)
+    assert _rel(_np(X).T, Xo) < _bound(sR), sR
+    assert _rel(_np(V).T, Vo) < _bound(sR), sR
+    E, H = r.diagnostics()
+    Eo, Ho = rom.diagnostics(st, cfg)
+    assert _rel(_np(E), Eo) < max(1e-8, _bound(sR) * 1e3)
+    assert _rel(_np(H), Ho) < _bound(sR)
+
+
+def test_rom_enoconv_keeps_state():
+    binding, torch = _b()
+    w, e = _ens("landau_tiny", N=2000)
+    _say("rom enoconv")
+    r = _gpu_rom(binding, w, e, 10, fp_tol=0.0, fp_max_iters=1)
+    UX0, Z0, _ = r.get_state()
+    st, _ = r.step_status(1)
+    assert st == binding.ENOCONV
+    UX1, Z1, step = r.get_state()
+    assert step == 0
+    assert torch.equal(UX0, UX1) and torch.equal(Z0, Z1)
