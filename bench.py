@@ -1,0 +1,197 @@
+"""Benchmark: particle-parameter steps per second of the reduced model (ROM)
+and of the full-order PIC model (FOM) on one MI355X, on the synthetic
+two-stream ensemble N = 100,000 particles, p = 64 parameters, Nx = 128 cells,
+dt = 0.05, reduced rank 2n starting at 10 (cap 60).
+
+Prints ONE JSON line.  `value` is the ROM throughput N * p * steps / time of
+the timed steps (inputs resident in HBM).  `roofline` describes the
+dominant kernel family of the ROM step, timed with HIP events on the
+library's stream over the timed region; `cpu_baseline` times the FP64
+oracle on a bounded sample of the same workload on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12        # B/s, MI355X HBM3E
+PEAK_FP64 = 78.6e12      # flop/s, MI355X FP64 vector (= FP64 matrix) peak
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="twostream_deim")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this size first (counter calibration)")
+    return ap.parse_args()
+
+
+def roofline_of(ms, flops, nbytes, launches):
+    """Binding roofline of a kernel family from its algorithmic work and its
+    measured time: the resource with the larger lower bound on time."""
+    t = ms * 1e-3
+    if t <= 0:
+        return None
+    t_alu = flops / PEAK_FP64
+    t_hbm = nbytes / PEAK_HBM
+    if t_hbm >= t_alu:
+        ach = nbytes / t / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": ach / (PEAK_HBM / 1e9), "traffic": None,
+                "avg_launch_us": 1e3 * ms / max(launches, 1), "launches": launches}
+    ach = flops / t / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+            "frac": ach / (PEAK_FP64 / 1e12), "traffic": None,
+            "avg_launch_us": 1e3 * ms / max(launches, 1), "launches": launches}
+
+
+def cpu_baseline(w, ens, seconds):
+    """The oracle's reduced step on a sample of the workload: the first
+    p_sub parameters, the same N, rank and time step."""
+    import numpy as np
+    from oracle import rom
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    p_sub = min(8, w["p"])
+    X0 = np.asfortranarray(ens["X0"][:, :p_sub])
+    V0 = np.asfortranarray(ens["V0"][:, :p_sub])
+    cfg = rom.RomConfig(N=w["N"], p=p_sub, Nx=w["Nx"], two_n=w["two_n"], dt=w["dt"],
+                        fp_tol=1e-9)
+    st = rom.init_state(X0, V0, ens["L"][:p_sub], cfg)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        rom.prk_step(st, cfg)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > seconds or steps >= 50:
+            break
+    val = w["N"] * p_sub * steps / el
+    return {"value": val, "unit": "particle-param-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle prk_step, first {p_sub} of {w['p']} parameters, N={w['N']}, "
+                      f"2n={w['two_n']}, Galerkin, {steps} steps in {el:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {a.gpus}); the "
+              "multi-GPU design is described but not built.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2201_05555_amd import binding
+    from workloads import make_ensemble, workload
+
+    torch.cuda.set_device(0)
+    if a.calib_copy_mib:
+        src = torch.empty(a.calib_copy_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    w = workload(a.workload)
+    N, p, Nx = w["N"], w["p"], w["Nx"]
+    ens = make_ensemble(w)
+    X0 = binding._dev(ens["X0"])
+    V0 = binding._dev(ens["V0"])
+    torch.cuda.synchronize()
+
+    # ---------------- reduced model ----------------
+    cfg = binding.make_config(N, p, Nx, w["two_n"], two_n_max=w["two_n_max"], dt=w["dt"],
+                              projection="galerkin", fp_tol=1e-9)
+    rom_h = binding.Rom(cfg, ens["L"], X0, V0)
+    iters = []
+    for _ in range(a.warmup):
+        iters.append(rom_h.step(1)["iters"])
+    torch.cuda.synchronize()
+    binding.set_timing(True)
+    for fam in binding.FAMILIES:
+        binding.kernel_ms(fam)
+        binding.kernel_work(fam)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        iters.append(rom_h.step(1)["iters"])
+    torch.cuda.synchronize()
+    t_rom = time.perf_counter() - t0
+    fams = {}
+    for fam in binding.FAMILIES:
+        ms, n = binding.kernel_ms(fam)
+        fl, by = binding.kernel_work(fam)
+        fams[fam] = dict(ms=ms, launches=n, flops=fl, bytes=by)
+    binding.set_timing(False)
+    two_n_end = rom_h.two_n
+    rom_h.close()
+
+    # ---------------- full-order model ----------------
+    fom_h = binding.Fom(N, p, Nx, w["dt"], ens["L"], X0, V0)
+    fom_h.step(a.warmup)
+    torch.cuda.synchronize()
+    binding.set_timing(True)
+    binding.kernel_ms("fom_push")
+    binding.kernel_work("fom_push")
+    t0 = time.perf_counter()
+    fom_h.step(a.steps)
+    torch.cuda.synchronize()
+    t_fom = time.perf_counter() - t0
+    ms_push, n_push = binding.kernel_ms("fom_push")
+    fl_push, by_push = binding.kernel_work("fom_push")
+    binding.set_timing(False)
+    fom_h.close()
+
+    pp = N * p
+    rom_rate = pp * a.steps / t_rom
+    fom_rate = pp * a.steps / t_fom
+    # dominant kernel family of the ROM step (largest share of device time)
+    dom = max(("deposit", "gather", "basis", "dense", "poisson"), key=lambda f: fams[f]["ms"])
+    d = fams[dom]
+    roof = roofline_of(d["ms"], d["flops"], d["bytes"], d["launches"])
+    if roof is not None:
+        roof["kernel_family"] = dom
+    fom_roof = roofline_of(ms_push, fl_push, by_push, n_push)
+
+    out = {
+        "metric": "particle-param steps/s, reduced model (ROM) on 1 GPU; FOM and ratio beside",
+        "value": rom_rate,
+        "unit": "particle-param-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * t_rom / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded two-stream ensemble, inverse-CDF loading)",
+        "config": {"workload": a.workload, "N": N, "p": p, "Nx": Nx, "dt": w["dt"],
+                   "two_n_start": w["two_n"], "two_n_end": two_n_end,
+                   "two_n_max": w["two_n_max"], "projection": "galerkin",
+                   "fp_tol": 1e-9, "mean_fp_iters": float(np.mean(iters[a.warmup:]))},
+        "fom": {"value": fom_rate, "unit": "particle-param-steps/s",
+                "ms_per_step": 1e3 * t_fom / a.steps, "roofline": fom_roof},
+        "rom_over_fom": rom_rate / fom_rate,
+        "roofline": roof,
+        "kernel_families_ms_per_step": {f: fams[f]["ms"] / a.steps for f in fams},
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, ens, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

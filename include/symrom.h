@@ -207,6 +207,15 @@ const char* symrom_last_error(void);
 void symrom_set_timing(int32_t on);
 double symrom_kernel_ms(int32_t family, int64_t* launches);
 
+/* Algorithmic work of the timed launches of a family since the last call:
+ * flops and HBM bytes as counted by the operation definitions (not by
+ * hardware counters).  Reconstruct-and-deposit: 4n flops per
+ * particle-parameter (x = Re(U~ Z~), n complex products), bytes = U~ read
+ * once per parameter tile plus the partial histograms.  FOM push: 32 bytes
+ * per particle-parameter (read and write X and V) plus the histograms.
+ * flops, bytes: host, nullable. */
+void symrom_kernel_work(int32_t family, double* flops, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,8 @@ _SIGS = {
     "symrom_last_error": (ctypes.c_char_p, []),
     "symrom_set_timing": (None, [ctypes.c_int32]),
     "symrom_kernel_ms": (ctypes.c_double, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "symrom_kernel_work": (None, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
@@ -137,6 +139,14 @@ def kernel_ms(family):
     n = ctypes.c_int64(0)
     ms = lib().symrom_kernel_ms(FAMILIES[family], ctypes.byref(n))
     return ms, n.value
+
+
+def kernel_work(family):
+    """(algorithmic flops, algorithmic HBM bytes) of the timed launches."""
+    f = ctypes.c_double(0.0)
+    b = ctypes.c_double(0.0)
+    lib().symrom_kernel_work(FAMILIES[family], ctypes.byref(f), ctypes.byref(b))
+    return f.value, b.value
 
 
 def make_config(N, p, Nx, two_n, two_n_max=None, dt=0.05, q=-1.0, m=1.0, projection="galerkin",

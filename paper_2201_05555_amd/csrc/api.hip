@@ -65,6 +65,8 @@ std::vector<TimedLaunch> g_pending;
 std::vector<hipEvent_t> g_event_pool;
 double g_ms[8] = {0};
 int64_t g_launches[8] = {0};
+double g_flops[8] = {0};
+double g_bytes[8] = {0};
 
 hipEvent_t take_event() {
   if (!g_event_pool.empty()) {
@@ -94,8 +96,11 @@ struct Timer {
   int fam;
   hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
-  Timer(int f, hipStream_t st) : fam(f), s(st) {
+  // flops / bytes: algorithmic work of the launches inside the scope
+  Timer(int f, hipStream_t st, double flops = 0.0, double bytes = 0.0) : fam(f), s(st) {
     if (g_timing) {
+      g_flops[f] += flops;
+      g_bytes[f] += bytes;
       a = take_event();
       b = take_event();
       if (a) hipEventRecord(a, s);
@@ -126,6 +131,14 @@ extern "C" double symrom_kernel_ms(int32_t family, int64_t* launches) {
   g_ms[family] = 0.0;
   g_launches[family] = 0;
   return v;
+}
+
+extern "C" void symrom_kernel_work(int32_t family, double* flops, double* bytes) {
+  if (family < 0 || family >= 8) return;
+  if (flops) *flops = g_flops[family];
+  if (bytes) *bytes = g_bytes[family];
+  g_flops[family] = 0.0;
+  g_bytes[family] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -192,7 +205,7 @@ PicBufs carve_pic(Arena& ar, int N, int p, int Nx, const PicGeom& g) {
   b.qw = ar.take<double>(p);
   b.h = ar.take<double>(p);
   b.mw = ar.take<double>(p);
-  b.part = ar.take<double>((size_t)g.nrb * p * Nx);
+  b.part = ar.take<double>((size_t)(g.nrb + 1) * p * Nx);
   b.rho = ar.take<double>((size_t)p * Nx);
   b.phi = ar.take<double>((size_t)p * Nx);
   b.e = ar.take<double>((size_t)p * Nx);
@@ -332,7 +345,9 @@ extern "C" symrom_status fom_step(symrom_fom* f, int32_t nsteps) {
   hipStream_t s = f->s;
   for (int it = 0; it < nsteps; ++it) {
     {
-      Timer t(FAM_FOMPUSH, s);
+      const double pp = (double)f->N * f->p;
+      Timer t(FAM_FOMPUSH, s, 12.0 * pp,
+              32.0 * pp + 8.0 * (double)f->g.nrb * f->p * f->Nx);
       launch_fom_push(s, f->X, f->V, f->N, f->p, f->Nx, f->g, f->b.factor, f->b.e, f->q / f->m,
                       f->dt, f->dt, f->b.part);
     }
@@ -405,12 +420,14 @@ struct symrom_rom {
   // init scratch
   cplx *Gp, *Vp;
   double* lam;
+  int n_active;  // active fixed-point columns (host copy, for work accounting)
   symrom_step_info last;
 };
 
 namespace {
 int nkb_for(int N) {
-  int nkb = (N + 1023) / 1024;
+  // split-K blocks: about one per CU, at least 64 rows each
+  int nkb = (N + 63) / 64;
   if (nkb > 256) nkb = 256;
   if (nkb < 1) nkb = 1;
   return nkb;
@@ -418,8 +435,9 @@ int nkb_for(int N) {
 
 void carve_rom(Arena& ar, symrom_rom& r) {
   const int N = r.N, p = r.p, Nx = r.Nx, nm = r.nmax;
-  r.gdep = pic_geom(N, p, Nx, 48 * 1024, 512);
-  r.ggat = pic_geom(N, p, Nx, 48 * 1024, 512);
+  // one parameter tile of up to 64 KB of LDS per table, ~one block per CU
+  r.gdep = pic_geom(N, p, Nx, 64 * 1024, 256);
+  r.ggat = pic_geom(N, p, Nx, 64 * 1024, 256);
   r.nkb = nkb_for(N);
   r.b = carve_pic(ar, N, p, Nx, r.gdep.nrb >= r.ggat.nrb ? r.gdep : r.ggat);
   const size_t Nn = (size_t)N * nm;
@@ -546,7 +564,10 @@ void full_gradient(symrom_rom& r, const cplx* U, const cplx* Z, const int* activ
   const double qm = r.cfg.q / r.cfg.m;
   if (do_deposit) {
     {
-      Timer t(FAM_DEPOSIT, s);
+      const double pact = (active ? (double)r.n_active : (double)r.p);
+      const int ntiles = (r.p + r.gdep.pt - 1) / r.gdep.pt;
+      Timer t(FAM_DEPOSIT, s, 4.0 * n * (double)r.N * pact,
+              16.0 * n * (double)r.N * ntiles + 8.0 * (double)r.gdep.nrb * pact * r.Nx);
       launch_deposit_rom(s, U, r.N, n, Z, r.p, r.Nx, r.gdep, r.b.factor, active, r.b.part);
     }
     Timer t(FAM_POISSON, s);
@@ -554,7 +575,10 @@ void full_gradient(symrom_rom& r, const cplx* U, const cplx* Z, const int* activ
                    r.b.phi, r.b.e, r.b.energy);
   }
   {
-    Timer t(FAM_GATHER, s);
+    const double pact = (active ? (double)r.n_active : (double)r.p);
+    const int ntiles = (r.p + r.ggat.pt - 1) / r.ggat.pt;
+    Timer t(FAM_GATHER, s, 8.0 * n * (double)r.N * pact,
+            16.0 * n * (double)r.N * ntiles + 16.0 * (double)r.N * pact);
     launch_gather_rom(s, U, r.N, n, Z, r.p, r.Nx, r.ggat, r.b.factor, r.b.e, qm, active, true,
                       r.G);
   }
@@ -627,6 +651,7 @@ symrom_status rom_step_one(symrom_rom& r) {
   const int limit = fixed > 0 ? fixed : r.cfg.fp_max_iters;
   int iters = 0;
   int hc[4] = {0, 0, 0, 0};
+  r.n_active = p;
   for (;;) {
     ++iters;
     full_gradient(r, r.Uh, r.Zev, r.active, true);
@@ -638,6 +663,7 @@ symrom_status rom_step_one(symrom_rom& r) {
     LAUNCHCHK();
     HIPCHK(hipMemcpyAsync(hc, r.counters, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    r.n_active = hc[0];
     if (hc[0] == 0 || iters >= limit) break;
   }
   r.last.iters = iters;

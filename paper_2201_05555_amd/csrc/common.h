@@ -45,15 +45,18 @@ __host__ __device__ inline double cabs2(cplx a) { return a.re * a.re + a.im * a.
 // Particle-to-cell lookup of the periodic P1 mesh.  s = x * (Nx / L) with the
 // factor formed once in FP64 on the host; c = floor(s); theta = s - c (exact);
 // node j = c mod Nx (Euclidean).  A particle on a node takes the cell to its
-// right.  The integer conversion is done on the floored double so that any
-// unwrapped position whose cell number fits in int64 is handled.
+// right.  Valid for unwrapped positions with |s| < 2^52.
 __device__ inline void cell_of(double x, double factor, int Nx, int& j, double& theta) {
-  double s = x * factor;
-  double c = floor(s);
+  const double s = x * factor;
+  const double c = floor(s);
   theta = s - c;
-  long long cl = (long long)c;
-  long long r = cl % (long long)Nx;
-  if (r < 0) r += Nx;
+  // Euclidean c mod Nx in exact double arithmetic (c and q*Nx are integers
+  // below 2^53); the quotient estimate is corrected by at most one.
+  const double fNx = (double)Nx;
+  const double q = floor(c * (1.0 / fNx));
+  double r = fma(-q, fNx, c);
+  r = (r < 0.0) ? r + fNx : r;
+  r = (r >= fNx) ? r - fNx : r;
   j = (int)r;
 }
 

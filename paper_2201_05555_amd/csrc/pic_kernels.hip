@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(512) deposit_x_kernel(const double* __restrict
 // `active` flag is 0 are skipped (frozen fixed-point columns).
 // ---------------------------------------------------------------------------
 template <int NC>
-__global__ void __launch_bounds__(256) deposit_rom_kernel(
+__global__ void __launch_bounds__(512) deposit_rom_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx, int pt,
     int rpb, const double* __restrict__ factor, const int* __restrict__ active,
     double* __restrict__ part) {
@@ -143,12 +143,8 @@ __global__ void __launch_bounds__(256) poisson_kernel(
   const int j0 = threadIdx.x * per;
   const double hi = h[i];
   const double qwi = qw[i];
-  // 1. reduce partials in a fixed order
-  for (int j = threadIdx.x; j < Nx; j += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nrb; ++b) s += part[((size_t)b * p + i) * Nx + j];
-    rho_s[j] = qwi * s + hi;
-  }
+  // 1. sums of the unit weights (already reduced over row blocks)
+  for (int j = threadIdx.x; j < Nx; j += blockDim.x) rho_s[j] = qwi * part[(size_t)i * Nx + j] + hi;
   __syncthreads();
   // 2. zero-mean charge and its prefix sums
   double loc = 0.0;
@@ -203,6 +199,27 @@ __global__ void __launch_bounds__(256) poisson_kernel(
   }
   const double E = block_sum(en, red);
   if (threadIdx.x == 0 && energy_out) energy_out[i] = E / (2.0 * mw[i]);
+}
+
+// Sum of the row-block partial histograms: out[o] = sum_b part[b][o] for the
+// p * Nx entries, in a fixed order (32 entries x 8 lanes of b per block).
+__global__ void __launch_bounds__(256) reduce_hist_kernel(const double* __restrict__ part, int nrb,
+                                                          int nout, const int* __restrict__ active,
+                                                          int Nx, double* __restrict__ out) {
+  __shared__ double sm[256];
+  const int ol = threadIdx.x % 32, kl = threadIdx.x / 32;
+  const int o = blockIdx.x * 32 + ol;
+  const bool on = o < nout && !(active && !active[o / Nx]);
+  double s = 0.0;
+  if (on)
+    for (int k = kl; k < nrb; k += 8) s += part[(size_t)k * nout + o];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  if (kl == 0 && on) {
+    double t = sm[ol];
+    for (int q = 1; q < 8; ++q) t += sm[q * 32 + ol];
+    out[o] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -327,7 +344,7 @@ void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* 
   size_t sh = (size_t)g.pt * Nx * sizeof(double) + (size_t)g.pt * nc * sizeof(cplx);
 #define DEP(NCV)                                                                              \
   ALLOW_BIG_LDS(deposit_rom_kernel<NCV>);                                                    \
-  hipLaunchKernelGGL(deposit_rom_kernel<NCV>, grid, dim3(256), sh, s, U, N, n, Z, p, Nx, g.pt, \
+  hipLaunchKernelGGL(deposit_rom_kernel<NCV>, grid, dim3(512), sh, s, U, N, n, Z, p, Nx, g.pt, \
                      g.rpb, factor, active, part)
   switch (nc) {
     case 4: DEP(4); break;
@@ -341,7 +358,12 @@ void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* 
 void launch_poisson(hipStream_t s, const double* part, int nrb, int p, int Nx, const double* qw,
                     const double* h, const double* mw, const int* active, double* rho,
                     double* phi, double* e, double* energy) {
-  hipLaunchKernelGGL(poisson_kernel, dim3(p), dim3(256), 0, s, part, nrb, p, Nx, qw, h, mw,
+  // the row-block sums go to the first p*Nx doubles after the partials
+  double* sums = const_cast<double*>(part) + (size_t)nrb * p * Nx;
+  const int nout = p * Nx;
+  hipLaunchKernelGGL(reduce_hist_kernel, dim3((nout + 31) / 32), dim3(256), 0, s, part, nrb, nout,
+                     active, Nx, sums);
+  hipLaunchKernelGGL(poisson_kernel, dim3(p), dim3(256), 0, s, sums, nrb, p, Nx, qw, h, mw,
                      active, rho, phi, e, energy);
 }
 

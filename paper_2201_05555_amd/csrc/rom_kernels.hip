@@ -14,7 +14,7 @@
 // of the block's parameter tile in LDS.
 // ---------------------------------------------------------------------------
 template <int NC, bool FULL>
-__global__ void __launch_bounds__(256) gather_rom_kernel(
+__global__ void __launch_bounds__(512) gather_rom_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx, int pt,
     int rpb, const double* __restrict__ factor, const double* __restrict__ e, double qm,
     const int* __restrict__ active, void* __restrict__ out) {
@@ -105,68 +105,109 @@ __device__ inline const cplx* list_col(const MatList& L, int c, int& local) {
   return L.ptr[s];
 }
 
+// Each thread owns a 4 x 4 tile of C (4 columns of A, 4 columns of B) and a
+// row group: the R = 256 / tiles threads of a tile stream the block's rows
+// with stride R straight from global memory (consecutive threads read
+// consecutive rows of the same columns, so loads are coalesced), and the R
+// partial tiles are summed in LDS in a fixed order.  Requires a, b <= 64.
 __global__ void __launch_bounds__(256) gemm_ah_b_kernel(MatList A, int a, MatList B, int b,
                                                         int b_real, int N, int rk,
                                                         cplx* __restrict__ part) {
-  __shared__ cplx As[GEMM_TR * 64];
-  __shared__ cplx Bs[GEMM_TR * 64];
+  __shared__ cplx red[256 * 16];
   const int kb = blockIdx.x;
   const int r0 = kb * rk;
   const int r1 = min(N, r0 + rk);
-  const int nout = a * b;
-  cplx acc[16];
+  const int nta = (a + 3) / 4;
+  const int ntb = (b + 3) / 4;
+  const int nt = nta * ntb;
+  const int R = max(1, 256 / nt);
+  const int tid = threadIdx.x;
+  const int tile = tid / R;
+  const int rg = tid % R;
+  const bool owner = tile < nt;
+  cplx acc[4][4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = mk(0.0, 0.0);
-  for (int t0 = r0; t0 < r1; t0 += GEMM_TR) {
-    const int tr = min(GEMM_TR, r1 - t0);
-    __syncthreads();
-    for (int t = threadIdx.x; t < a * GEMM_TR; t += blockDim.x) {
-      int c = t / GEMM_TR, r = t % GEMM_TR;
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = mk(0.0, 0.0);
+  if (owner) {
+    const int ta0 = (tile % nta) * 4;
+    const int tb0 = (tile / nta) * 4;
+    const cplx* ap[4];
+    const cplx* bp[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
       int lc;
-      const cplx* base = list_col(A, c, lc);
-      As[c * GEMM_TR + r] = (r < tr) ? base[(size_t)lc * N + t0 + r] : mk(0.0, 0.0);
-    }
-    for (int t = threadIdx.x; t < b * GEMM_TR; t += blockDim.x) {
-      int c = t / GEMM_TR, r = t % GEMM_TR;
-      int lc;
-      const cplx* base = list_col(B, c, lc);
-      cplx v = mk(0.0, 0.0);
-      if (r < tr) {
+      ap[i] = (ta0 + i < a) ? list_col(A, ta0 + i, lc) : nullptr;
+      if (ap[i]) ap[i] += (size_t)lc * N;
+      bp[i] = (tb0 + i < b) ? list_col(B, tb0 + i, lc) : nullptr;
+      if (bp[i]) {
         if (b_real)
-          v = mk(reinterpret_cast<const double*>(base)[(size_t)lc * N + t0 + r], 0.0);
+          bp[i] = reinterpret_cast<const cplx*>(reinterpret_cast<const double*>(bp[i]) +
+                                                (size_t)lc * N);
         else
-          v = base[(size_t)lc * N + t0 + r];
+          bp[i] += (size_t)lc * N;
       }
-      Bs[c * GEMM_TR + r] = v;
     }
-    __syncthreads();
+    for (int l = r0 + rg; l < r1; l += R) {
+      cplx av[4], bv[4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      int o = threadIdx.x + q * 256;
-      if (o < nout) {
-        int ia = o % a, ib = o / a;
-        const cplx* ar = As + ia * GEMM_TR;
-        const cplx* br = Bs + ib * GEMM_TR;
-        cplx s = acc[q];
-        for (int r = 0; r < GEMM_TR; ++r) cfmac(s, ar[r], br[r]);
-        acc[q] = s;
+      for (int i = 0; i < 4; ++i) av[i] = ap[i] ? ap[i][l] : mk(0.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (!bp[j])
+          bv[j] = mk(0.0, 0.0);
+        else if (b_real)
+          bv[j] = mk(reinterpret_cast<const double*>(bp[j])[l], 0.0);
+        else
+          bv[j] = bp[j][l];
       }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cfmac(acc[i][j], av[i], bv[j]);
     }
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    int o = threadIdx.x + q * 256;
-    if (o < nout) part[(size_t)kb * nout + o] = acc[q];
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[tid * 16 + i * 4 + j] = acc[i][j];
+  __syncthreads();
+  // tile leader sums its R row groups in order and writes the partial tile
+  if (owner && rg == 0) {
+    const int ta0 = (tile % nta) * 4;
+    const int tb0 = (tile / nta) * 4;
+    const int nout = a * b;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        cplx s = mk(0.0, 0.0);
+        for (int g = 0; g < R; ++g) s = cadd(s, red[(tile * R + g) * 16 + i * 4 + j]);
+        const int ia = ta0 + i, ib = tb0 + j;
+        if (ia < a && ib < b) part[(size_t)kb * nout + (size_t)ib * a + ia] = s;
+      }
   }
 }
 
-__global__ void reduce_partials_kernel(const cplx* __restrict__ part, int nkb, int nout,
-                                       cplx* __restrict__ C) {
-  int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= nout) return;
+// C[o] = sum_k part[k][o], k in a fixed order.  Block: 32 outputs x 8 lanes
+// of k; lane sums are combined in a fixed order in LDS.
+__global__ void __launch_bounds__(256) reduce_partials_kernel(const cplx* __restrict__ part,
+                                                              int nkb, int nout,
+                                                              cplx* __restrict__ C) {
+  __shared__ cplx sm[256];
+  const int ol = threadIdx.x % 32, kl = threadIdx.x / 32;
+  const int o = blockIdx.x * 32 + ol;
   cplx s = mk(0.0, 0.0);
-  for (int k = 0; k < nkb; ++k) s = cadd(s, part[(size_t)k * nout + o]);
-  C[o] = s;
+  if (o < nout)
+    for (int k = kl; k < nkb; k += 8) s = cadd(s, part[(size_t)k * nout + o]);
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  if (kl == 0 && o < nout) {
+    cplx t = sm[ol];
+    for (int q = 1; q < 8; ++q) t = cadd(t, sm[q * 32 + ol]);
+    C[o] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -287,7 +328,7 @@ void launch_gather_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z
   size_t sh = (size_t)g.pt * Nx * sizeof(double) + (size_t)g.pt * nc * sizeof(cplx);
 #define GA(NCV, FV)                                                                           \
   ALLOW_BIG_LDS((gather_rom_kernel<NCV, FV>));                                               \
-  hipLaunchKernelGGL((gather_rom_kernel<NCV, FV>), grid, dim3(256), sh, s, U, N, n, Z, p, Nx, \
+  hipLaunchKernelGGL((gather_rom_kernel<NCV, FV>), grid, dim3(512), sh, s, U, N, n, Z, p, Nx, \
                      g.pt, g.rpb, factor, e, qm, active, out)
   if (full) {
     switch (nc) {
@@ -322,14 +363,12 @@ void launch_reconstruct(hipStream_t s, const cplx* U, int N, int n, const cplx* 
 void launch_gemm_ah_b(hipStream_t s, const MatList& A, int a, const MatList& B, int b, bool b_real,
                       int N, int nkb, cplx* part, cplx* C) {
   int rk = (N + nkb - 1) / nkb;
-  rk = ((rk + GEMM_TR - 1) / GEMM_TR) * GEMM_TR;
   nkb = (N + rk - 1) / rk;
   // B is processed in chunks of at most 64 columns (one list entry per chunk)
   for (int b0 = 0; b0 < b; b0 += 64) {
     const int bc = (b - b0 < 64) ? b - b0 : 64;
     MatList Bc = B;
     if (b > 64) {
-      // only single-matrix B lists are chunked
       Bc.count = 1;
       Bc.cols[0] = bc;
       Bc.ptr[0] = b_real ? reinterpret_cast<const cplx*>(reinterpret_cast<const double*>(B.ptr[0]) +
@@ -339,8 +378,8 @@ void launch_gemm_ah_b(hipStream_t s, const MatList& A, int a, const MatList& B, 
     hipLaunchKernelGGL(gemm_ah_b_kernel, dim3(nkb), dim3(256), 0, s, A, a, Bc, bc,
                        b_real ? 1 : 0, N, rk, part);
     int nout = a * bc;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((nout + 255) / 256), dim3(256), 0, s, part,
-                       nkb, nout, C + (size_t)b0 * a);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((nout + 31) / 32), dim3(256), 0, s, part, nkb,
+                       nout, C + (size_t)b0 * a);
   }
 }
 
