@@ -441,31 +441,25 @@ def rank_shrink(st, new_two_n):
 def adapt_rank(st, cfg, target_two_n=0):
     """Force the rank to ``target_two_n`` (even), or apply the indicator
     policy when target is 0: grow one pair if eps_perp > rank_tol_up and the
-    cap allows, else shrink the pairs whose singular value of Z~ falls below
-    rank_tol_down * sigma_max.  Returns (status, new 2n)."""
+    cap allows (shrinking is only done on request).  Returns (status, new 2n,
+    eps_perp or None)."""
     r = st.U.shape[1]
     if target_two_n:
         if target_two_n % 2 or target_two_n <= 0:
             raise ValueError("rank must be a positive even number")
         if target_two_n > cfg.two_n_max:
-            return ERANKCAP, r
+            return ERANKCAP, r, None
         if target_two_n > r:
             rank_grow(st, cfg, (target_two_n - r) // 2)
         elif target_two_n < r:
             rank_shrink(st, target_two_n)
         cfg.two_n = st.U.shape[1]
-        return OK, cfg.two_n
+        return OK, cfg.two_n, None
     eps, gr = rank_indicator(st, cfg)
     if eps > cfg.rank_tol_up and r < cfg.two_n_max:
         rank_grow(st, cfg, 1, gr)
-    else:
-        s = np.linalg.svd(to_complex_coeff(st.Z), compute_uv=False)
-        keep = int(np.sum(s > cfg.rank_tol_down * s[0])) if s.size else 0
-        keep = max(1, keep)
-        if keep < r // 2:
-            rank_shrink(st, 2 * keep)
     cfg.two_n = st.U.shape[1]
-    return OK, cfg.two_n
+    return OK, cfg.two_n, eps
 
 
 # ----------------------------------------------------------------------------

@@ -417,6 +417,7 @@ struct symrom_rom {
   cplx *Gram, *Amat, *MU, *MX, *M1, *M2, *M3, *C0x, *Rinv, *MP;
   cplx* gemm_part;
   double* sigma2;
+  double* eps_dev;
   // init scratch
   cplx *Gp, *Vp;
   double* lam;
@@ -474,6 +475,7 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   // split-K partials: nkb * max(a*b) with a, b <= 64 (b chunked by 64)
   r.gemm_part = ar.take<cplx>((size_t)r.nkb * 64 * 64);
   r.sigma2 = ar.take<double>(nm);
+  r.eps_dev = ar.take<double>(4);
   r.Gp = ar.take<cplx>((size_t)p * p);
   r.Vp = ar.take<cplx>((size_t)p * p);
   r.lam = ar.take<double>(p);
@@ -851,11 +853,16 @@ extern "C" symrom_status rom_init(const symrom_config* cfg, const double* L, con
   return SYMROM_OK;
 }
 
+namespace {
+symrom_status rom_grow(symrom_rom& r, int k, bool decide);
+}
+
 extern "C" symrom_status rom_step(symrom_rom* r, int32_t nsteps, symrom_step_info* info) {
   if (!r || nsteps < 0) return fail(SYMROM_EINVAL, "rom_step: bad arguments");
   if (!r->ready) return fail(SYMROM_ESTATE, "rom_step: handle not initialised");
   for (int it = 0; it < nsteps; ++it) {
     symrom_status st = rom_step_one(*r);
+    if (st == SYMROM_OK && r->cfg.rank_auto) st = rom_grow(*r, 0, true);
     if (st != SYMROM_OK) {
       if (info) *info = r->last;
       return st;
@@ -867,14 +874,71 @@ extern "C" symrom_status rom_step(symrom_rom* r, int32_t nsteps, symrom_step_inf
   return SYMROM_OK;
 }
 
+namespace {
+// Grow by k pairs (k > 0), or only evaluate the indicator when k == 0 and
+// decide = true (then grow one pair if eps > rank_tol_up and the cap allows).
+symrom_status rom_grow(symrom_rom& r, int k, bool decide) {
+  hipStream_t s = r.s;
+  const int n = r.n, p = r.p, N = r.N;
+  HIPCHK(hipMemsetAsync(r.flags, 0, 4 * sizeof(int), s));
+  full_gradient(r, r.U0, r.Z0, nullptr, true);
+  launch_gemm_ah_b(s, ml(r.G, p), p, ml(r.G, p), p, false, N, r.nkb, r.gemm_part, r.Gp);
+  launch_dense_hh(s, r.Gp, r.gproj, n, p, r.eps_dev);
+  LAUNCHCHK();
+  if (decide) {
+    double eps = 0.0;
+    HIPCHK(hipMemcpyAsync(&eps, r.eps_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    r.last.rank_indicator = eps;
+    if (!(eps > r.cfg.rank_tol_up) || 2 * (n + 1) > r.cfg.two_n_max) return SYMROM_OK;
+    k = 1;
+  }
+  if (n + k > r.nmax) return fail(SYMROM_ERANKCAP, "rank growth beyond two_n_max");
+  if (k > p) return fail(SYMROM_EINVAL, "cannot grow by more pairs than parameters");
+  launch_dense_herm_eig(s, r.Gp, p, r.Vp, r.lam, r.flags);
+  launch_dense_grow_prep(s, r.Vp, r.lam, r.gproj, n, p, k, r.Q, r.MP, r.flags);
+  launch_rowgemm(s, rt(r.G, r.Q, p, r.U0, r.MP, n), N, k, r.U0 + (size_t)n * N);
+  launch_colphase(s, r.U0, N, n, k);
+  launch_z_resize(s, r.Z0, n, r.Z1, n + k, p);
+  launch_copy_cplx(s, r.Z0, r.Z1, (size_t)(n + k) * p);
+  LAUNCHCHK();
+  int fl[2];
+  symrom_status st = read_flags(r, fl);
+  if (st != SYMROM_OK) return st;
+  if (fl[0]) return fail(SYMROM_ESINGULAR, "rank growth: indicator matrix has too small rank");
+  r.n = n + k;
+  return SYMROM_OK;
+}
+
+symrom_status rom_shrink(symrom_rom& r, int n_new) {
+  hipStream_t s = r.s;
+  const int n = r.n, p = r.p, N = r.N;
+  launch_dense_shrink(s, r.Z0, n, p, r.M1, r.Z1, r.sigma2);
+  launch_rowgemm(s, rt(r.U0, r.M1, n), N, n_new, r.Uh);
+  std::swap(r.U0, r.Uh);
+  launch_z_resize(s, r.Z1, n, r.Z0, n_new, p);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  r.n = n_new;
+  return SYMROM_OK;
+}
+}  // namespace
+
 extern "C" symrom_status rom_adapt_rank(symrom_rom* r, int32_t target_two_n, int32_t* new_two_n) {
   if (!r) return fail(SYMROM_EINVAL, "rom_adapt_rank: null handle");
+  if (!r->ready) return fail(SYMROM_ESTATE, "rom_adapt_rank: handle not initialised");
   if (target_two_n < 0 || (target_two_n & 1))
     return fail(SYMROM_EINVAL, "rom_adapt_rank: target must be even and non-negative");
   if (target_two_n > r->cfg.two_n_max) return fail(SYMROM_ERANKCAP, "rom_adapt_rank: above cap");
+  symrom_status st = SYMROM_OK;
+  if (target_two_n == 0)
+    st = rom_grow(*r, 0, true);
+  else if (target_two_n > 2 * r->n)
+    st = rom_grow(*r, (target_two_n - 2 * r->n) / 2, false);
+  else if (target_two_n < 2 * r->n)
+    st = rom_shrink(*r, target_two_n / 2);
   if (new_two_n) *new_two_n = 2 * r->n;
-  if (target_two_n == 0 || target_two_n == 2 * r->n) return SYMROM_OK;
-  return fail(SYMROM_EINVAL, "rom_adapt_rank: not available yet");
+  return st;
 }
 
 extern "C" symrom_status rom_get_state(symrom_rom* r, double* UX, double* Z, int32_t* two_n,

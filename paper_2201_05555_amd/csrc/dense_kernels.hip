@@ -158,17 +158,22 @@ __device__ void bk_jacobi(cplx* A, cplx* V, double* lam, int m, cplx* rot /*3*m/
   for (int t = threadIdx.x; t < m * m; t += blockDim.x)
     V[t] = (t % m == t / m) ? mk(1.0, 0.0) : mk(0.0, 0.0);
   __shared__ double red[DTPB / 64];
+  __shared__ int nrot;
   __syncthreads();
   for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
-      int i = t % m, j = t / m;
-      if (i < j) off += cabs2(A[t]);
-      if (i == j) dia += cabs2(A[t]);
-    }
-    off = block_sum(off, red);
-    dia = block_sum(dia, red);
-    if (off <= 1e-34 * dia || !(off > 0.0)) break;
+    // threshold Jacobi: an off-diagonal entry is rotated away only when it is
+    // above 1e-15 sqrt(|a_pp a_qq|) and above 1e-18 of the largest diagonal
+    // entry; the sweep loop ends when a sweep applies no rotation
+    double dmax = 0.0;
+    for (int t = threadIdx.x; t < m; t += blockDim.x) dmax = fmax(dmax, fabs(A[t * m + t].re));
+    for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dmax;
+    if (threadIdx.x == 0) nrot = 0;
+    __syncthreads();
+    dmax = 0.0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) dmax = fmax(dmax, red[w]);
+    const double floor_abs = 1e-18 * dmax;
+    __syncthreads();
     for (int round = 0; round < mm - 1; ++round) {
       for (int k = threadIdx.x; k < half; k += blockDim.x) {
         int a, b;
@@ -186,7 +191,8 @@ __device__ void bk_jacobi(cplx* A, cplx* V, double* lam, int m, cplx* rot /*3*m/
           const cplx bpq = A[q * m + p];
           const double ab = sqrt(cabs2(bpq));
           const double app = A[p * m + p].re, aqq = A[q * m + q].re;
-          if (ab > 1e-300 && ab > 1e-18 * sqrt(fabs(app * aqq))) {
+          if (ab > 1e-300 && ab > floor_abs && ab > 1e-15 * sqrt(fabs(app * aqq))) {
+            atomicAdd(&nrot, 1);
             ph = mk(bpq.re / ab, -bpq.im / ab);
             const double zeta = (aqq - app) / (2.0 * ab);
             const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -251,6 +257,8 @@ __device__ void bk_jacobi(cplx* A, cplx* V, double* lam, int m, cplx* rot /*3*m/
       }
       __syncthreads();
     }
+    if (nrot == 0) break;
+    __syncthreads();
   }
   // sort eigenpairs by decreasing eigenvalue (selection by thread 0 of the
   // permutation, then parallel column moves through the rot scratch)
@@ -825,4 +833,166 @@ void launch_z_from_real(hipStream_t s, const double* Z, int n, int p, cplx* Zc) 
 }
 void launch_z_to_real(hipStream_t s, const cplx* Zc, int n, int p, double* Z) {
   hipLaunchKernelGGL(z_to_real_kernel, dim3(nblk((size_t)n * p)), dim3(256), 0, s, Zc, n, p, Z);
+}
+
+// ---------------------------------------------------------------------------
+// rank adaptation
+// ---------------------------------------------------------------------------
+
+// Gp <- Gp - g^* g  (Gp = G~^* G~, p x p; g = U~^* G~, n x p), i.e. H^* H for
+// H = (I - U~ U~^*) G~; eps = sqrt(1 - ||g||^2 / ||G||^2) (the rank indicator,
+// ||(I - U U^T) J G|| / ||G|| with U^T J = J U^T).
+__global__ void __launch_bounds__(DTPB) dense_hh_kernel(cplx* __restrict__ Gp,
+                                                        const cplx* __restrict__ g, int n, int p,
+                                                        double* __restrict__ eps_out) {
+  __shared__ double red[DTPB / 64];
+  double tr = 0.0, gn = 0.0;
+  for (int i = threadIdx.x; i < p; i += blockDim.x) tr += Gp[i * p + i].re;
+  for (int t = threadIdx.x; t < n * p; t += blockDim.x) gn += cabs2(g[t]);
+  tr = block_sum(tr, red);
+  gn = block_sum(gn, red);
+  for (int t = threadIdx.x; t < p * p; t += blockDim.x) {
+    int i = t % p, j = t / p;
+    cplx s = Gp[t];
+    for (int k = 0; k < n; ++k) s = csub(s, cmulc(g[(size_t)i * n + k], g[(size_t)j * n + k]));
+    Gp[t] = s;
+  }
+  if (threadIdx.x == 0 && eps_out) *eps_out = (tr > 0.0) ? sqrt(fmax(0.0, 1.0 - gn / tr)) : 0.0;
+}
+
+// W[:, j] = V[:, j] / sqrt(lam_j) (p x k) and T = -g W (n x k): the new basis
+// vectors are y_j = H w_j / sigma_j = G~ W[:, j] + U~ T[:, j].
+__global__ void __launch_bounds__(DTPB) dense_grow_prep_kernel(
+    const cplx* __restrict__ V, const double* __restrict__ lam, const cplx* __restrict__ g, int n,
+    int p, int k, cplx* __restrict__ W, cplx* __restrict__ T, int* __restrict__ flags) {
+  for (int t = threadIdx.x; t < p * k; t += blockDim.x) {
+    int j = t / p;
+    double l = lam[j];
+    if (!(l > 0.0)) {
+      if (flags) flags[0] |= 4;
+      W[t] = mk(0.0, 0.0);
+    } else {
+      W[t] = cscale(V[t], 1.0 / sqrt(l));
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n * k; t += blockDim.x) {
+    int a = t % n, j = t / n;
+    cplx s = mk(0.0, 0.0);
+    for (int i = 0; i < p; ++i) cfma(s, g[(size_t)i * n + a], W[(size_t)j * p + i]);
+    T[t] = cscale(s, -1.0);
+  }
+}
+
+// Canonical phase of columns col0 .. col0+k-1 of U (N rows): the entry of
+// largest modulus (smallest row index on ties) is made real positive.
+// One block per column.
+__global__ void __launch_bounds__(1024) colphase_kernel(cplx* __restrict__ U, int N, int col0) {
+  __shared__ double sv[1024];
+  __shared__ int si[1024];
+  cplx* u = U + (size_t)(col0 + blockIdx.x) * N;
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int l = threadIdx.x; l < N; l += blockDim.x) {
+    double a = cabs2(u[l]);
+    if (a > best) {
+      best = a;
+      bi = l;
+    }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      double a = sv[threadIdx.x + o];
+      int ai = si[threadIdx.x + o];
+      if (a > sv[threadIdx.x] || (a == sv[threadIdx.x] && ai < si[threadIdx.x])) {
+        sv[threadIdx.x] = a;
+        si[threadIdx.x] = ai;
+      }
+    }
+    __syncthreads();
+  }
+  const cplx a = u[si[0]];
+  const double m = sqrt(cabs2(a));
+  const cplx ph = (m > 0.0) ? mk(a.re / m, -a.im / m) : mk(1.0, 0.0);
+  __syncthreads();
+  for (int l = threadIdx.x; l < N; l += blockDim.x) u[l] = cmul(u[l], ph);
+}
+
+// Zout (nout x p) from Zin (nin x p): copy the common rows, zero the rest.
+__global__ void z_resize_kernel(const cplx* __restrict__ Zin, int nin, cplx* __restrict__ Zout,
+                                int nout, int p) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nout * p) return;
+  int a = t % nout, i = t / nout;
+  Zout[t] = (a < nin) ? Zin[(size_t)i * nin + a] : mk(0.0, 0.0);
+}
+
+// Shrink: eigendecomposition Z~ Z~^* = V diag(sigma^2) V^* (decreasing, each
+// column of V with canonical phase), V (n x n) and Znew = V^* Z~ (n x p).
+__global__ void __launch_bounds__(DTPB) dense_shrink_kernel(const cplx* __restrict__ Z, int n,
+                                                            int p, cplx* __restrict__ Vout,
+                                                            cplx* __restrict__ Znew,
+                                                            double* __restrict__ sig2) {
+  __shared__ cplx S[32 * 32];
+  __shared__ cplx V[32 * 32];
+  __shared__ cplx rot[3 * 17 + 3];
+  __shared__ int pr[40];
+  __shared__ double lam[32];
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    int a = t % n, b = t / n;
+    cplx s = mk(0.0, 0.0);
+    for (int i = 0; i < p; ++i) cfma(s, Z[(size_t)i * n + a], cconj(Z[(size_t)i * n + b]));
+    S[t] = s;
+  }
+  __syncthreads();
+  bk_jacobi(S, V, lam, n, rot, pr);
+  // canonical phase of each eigenvector
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    int bi = 0;
+    double bv = -1.0;
+    for (int r = 0; r < n; ++r) {
+      double a = cabs2(V[c * n + r]);
+      if (a > bv) {
+        bv = a;
+        bi = r;
+      }
+    }
+    cplx a = V[c * n + bi];
+    double m = sqrt(cabs2(a));
+    cplx ph = (m > 0.0) ? mk(a.re / m, -a.im / m) : mk(1.0, 0.0);
+    for (int r = 0; r < n; ++r) V[c * n + r] = cmul(V[c * n + r], ph);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) Vout[t] = V[t];
+  for (int t = threadIdx.x; t < n * p; t += blockDim.x) {
+    int a = t % n, i = t / n;
+    cplx s = mk(0.0, 0.0);
+    for (int b = 0; b < n; ++b) cfmac(s, V[a * n + b], Z[(size_t)i * n + b]);
+    Znew[t] = s;
+  }
+  if (sig2)
+    for (int t = threadIdx.x; t < n; t += blockDim.x) sig2[t] = lam[t];
+}
+
+void launch_dense_hh(hipStream_t s, cplx* Gp, const cplx* g, int n, int p, double* eps) {
+  hipLaunchKernelGGL(dense_hh_kernel, dim3(1), dim3(DTPB), 0, s, Gp, g, n, p, eps);
+}
+void launch_dense_grow_prep(hipStream_t s, const cplx* V, const double* lam, const cplx* g, int n,
+                            int p, int k, cplx* W, cplx* T, int* flags) {
+  hipLaunchKernelGGL(dense_grow_prep_kernel, dim3(1), dim3(DTPB), 0, s, V, lam, g, n, p, k, W, T,
+                     flags);
+}
+void launch_colphase(hipStream_t s, cplx* U, int N, int col0, int k) {
+  hipLaunchKernelGGL(colphase_kernel, dim3(k), dim3(1024), 0, s, U, N, col0);
+}
+void launch_z_resize(hipStream_t s, const cplx* Zin, int nin, cplx* Zout, int nout, int p) {
+  hipLaunchKernelGGL(z_resize_kernel, dim3(nblk((size_t)nout * p)), dim3(256), 0, s, Zin, nin,
+                     Zout, nout, p);
+}
+void launch_dense_shrink(hipStream_t s, const cplx* Z, int n, int p, cplx* V, cplx* Znew,
+                         double* sig2) {
+  hipLaunchKernelGGL(dense_shrink_kernel, dim3(1), dim3(DTPB), 0, s, Z, n, p, V, Znew, sig2);
 }

@@ -97,3 +97,10 @@ void launch_ux_from_u(hipStream_t s, const cplx* U, int N, int n, double* UX);
 void launch_u_from_ux(hipStream_t s, const double* UX, int N, int n, cplx* U);
 void launch_z_from_real(hipStream_t s, const double* Z, int n, int p, cplx* Zc);
 void launch_z_to_real(hipStream_t s, const cplx* Zc, int n, int p, double* Z);
+void launch_dense_hh(hipStream_t s, cplx* Gp, const cplx* g, int n, int p, double* eps);
+void launch_dense_grow_prep(hipStream_t s, const cplx* V, const double* lam, const cplx* g, int n,
+                            int p, int k, cplx* W, cplx* T, int* flags);
+void launch_colphase(hipStream_t s, cplx* U, int N, int col0, int k);
+void launch_z_resize(hipStream_t s, const cplx* Zin, int nin, cplx* Zout, int nout, int p);
+void launch_dense_shrink(hipStream_t s, const cplx* Z, int n, int p, cplx* V, cplx* Znew,
+                         double* sig2);

@@ -260,3 +260,74 @@ def test_rom_enoconv_keeps_state():
     UX1, Z1, step = r.get_state()
     assert step == 0
     assert torch.equal(UX0, UX1) and torch.equal(Z0, Z1)
+
+
+def test_rom_rank_grow_parity():
+    """Growth appends the leading left singular vectors of
+    (I - U~U~^*)(-i G~) with zero coefficient rows: R is bitwise unchanged on
+    the device, and the new directions match the oracle's SVD (canonical
+    phase) to the accuracy of the Gram route, eps (sigma_1 / sigma_k)^2."""
+    binding, torch = _b()
+    w, e = _ens("twostream_deim", N=20000, p=24, Nx=128)
+    _say("rom rank grow")
+    cfg, st = _oracle_state(w, e, 8)
+    cfg.two_n_max = 16
+    r = _gpu_rom(binding, w, e, 8, two_n_max=16)
+    _set_from_oracle(r, st, torch)
+    X0, V0 = r.reconstruct()
+    # singular values of H for the accuracy bound
+    gr = rom.gradient(st.U, st.Z, st.L, w["Nx"])
+    N = w["N"]
+    Ut = rom.to_complex_basis(st.U)
+    Gt = gr.G[:N] + 1j * gr.G[N:]
+    H = Gt - Ut @ (Ut.conj().T @ Gt)
+    sv = np.linalg.svd(H, compute_uv=False)
+    assert r.adapt_rank(12) == 12
+    rom.adapt_rank(st, cfg, 12)
+    X1, V1 = r.reconstruct()
+    assert torch.equal(X0, X1) and torch.equal(V0, V1)
+    UX, Z, _ = r.get_state()
+    UXn = _np(UX).T
+    tol = max(1e-9, 1e-14 * (sv[0] / sv[1]) ** 2)
+    assert _rel(UXn, st.U[:N]) < tol, (tol, sv[:2])
+    assert _rel(_np(Z).T, st.Z) < 1e-12
+    # still orthonormal to the accuracy of the Gram route
+    Utg = UXn[:, :6] - 1j * UXn[:, 6:]
+    assert np.abs(Utg.conj().T @ Utg - np.eye(6)).max() < 1e-9
+
+
+def test_rom_rank_shrink_parity():
+    binding, torch = _b()
+    w, e = _ens("twostream_deim", N=20000, p=24, Nx=128)
+    _say("rom rank shrink")
+    cfg, st = _oracle_state(w, e, 12)
+    r = _gpu_rom(binding, w, e, 12)
+    _set_from_oracle(r, st, torch)
+    assert r.adapt_rank(8) == 8
+    rom.adapt_rank(st, cfg, 8)
+    X, V = r.reconstruct()
+    Xo, Vo = rom.reconstruct(st)
+    assert _rel(_np(X).T, Xo) < 1e-10
+    assert _rel(_np(V).T, Vo) < 1e-10
+    UX, Z, _ = r.get_state()
+    assert UX.shape[0] == 8
+    assert _rel(_np(Z).T, st.Z) < 1e-9
+
+
+def test_rom_rank_auto_indicator():
+    """With rank_auto, after each step the indicator eps_perp is evaluated at
+    the new state; it matches the oracle, and a threshold of 0 grows one
+    pair per step."""
+    binding, torch = _b()
+    w, e = _ens("twostream_deim", N=20000, p=24, Nx=128)
+    _say("rom rank auto")
+    cfg, st = _oracle_state(w, e, 8, fp_tol=1e-10)
+    cfg.two_n_max, cfg.rank_tol_up = 12, 0.0
+    r = _gpu_rom(binding, w, e, 8, two_n_max=12, fp_tol=1e-10, rank_auto=True, rank_tol_up=0.0)
+    _set_from_oracle(r, st, torch)
+    for s in range(3):
+        info = r.step(1)
+        assert rom.prk_step(st, cfg) == rom.OK
+        status, two_n, eps = rom.adapt_rank(st, cfg, 0)
+        assert abs(info["rank_indicator"] - eps) < 1e-9 * max(eps, 1e-3), (info, eps)
+        assert info["two_n"] == two_n == min(8 + 2 * (s + 1), 12)

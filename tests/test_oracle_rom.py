@@ -261,6 +261,12 @@ def test_rank_growth_keeps_R_bitwise_and_shrink_error():
     np.testing.assert_allclose(dropped, s[3:], rtol=1e-10)
     assert _orth_err(st.U) < 1e-12
     assert rom.adapt_rank(st, cfg, 14)[0] == rom.ERANKCAP
+    # the automatic policy grows one pair when the indicator exceeds its threshold
+    cfg.rank_tol_up = 0.0
+    st2, cfg2, _ = _tiny_landau(two_n=4, N=800)
+    cfg2.two_n_max, cfg2.rank_tol_up = 8, 0.0
+    status, r2, eps = rom.adapt_rank(st2, cfg2, 0)
+    assert status == rom.OK and r2 == 6 and eps > 0
 
 
 def test_rank_indicator_identity():
