@@ -8,10 +8,13 @@ potential (no DMD, reading for this build) the DEIM gradient of eq. (grHDD) is
   g_i = U_V^T V_r^i + U_X[I,:]^T ( (q/m) e_i[j(X_r^i[I])] * w ),
   w = (P^T Psi)^{-T} Psi^T 1,
 since m_p^{-1} M_q = (q/m) 1 and nabla Lambda^0 Phi is the cell field e.
-Snapshots: the last T+1 time levels of N_i for all p parameters, the matrix
-Y = [Y_1 ... Y_p] of eq. (Ydeim); Psi = its first d left singular vectors; the
-indices follow the greedy DEIM selection (Sec. 4.3: at step k, the index of
-the largest interpolation residual of psi_k on the previous vectors).
+Snapshots: the last T+1 time levels of N_i for a parameter subset of size
+p*, the matrix Y = [Y_1 ... Y_p*] of eq. (Ydeim) (N x p*(T+1)); Psi = its
+first d left singular vectors; the indices follow the greedy DEIM selection
+(Sec. 4.3: at step k, the index of the largest interpolation residual of
+psi_k on the previous vectors).  reading: the subset is evenly spaced in the
+parameter index, i_k = floor(k p / p*), with p* = min(p, max(8,
+ceil(two_n_max / (T+1)))) so that p*(T+1) >= d for every rank reached.
 """
 from dataclasses import dataclass
 
@@ -25,6 +28,12 @@ class DeimOp:
     idx: np.ndarray      # d int64 particle indices, in greedy order
     w: np.ndarray        # d weights (P^T Psi)^{-T} Psi^T 1
     Psi: np.ndarray      # N x d
+
+
+def snapshot_params(p, two_n_max, T):
+    """Indices of the DEIM snapshot parameters (see the module docstring)."""
+    pstar = min(p, max(8, -(-two_n_max // (T + 1))))
+    return np.array([(k * p) // pstar for k in range(pstar)], dtype=np.int64)
 
 
 def snapshot(Xr, Phi, L):
@@ -77,7 +86,8 @@ def update_window(st, cfg, U0, gr0):
     """Append the snapshot at the start of the step; once T+1 snapshots are
     held, return the DEIM operator for this step, else None (the first T
     steps use the Galerkin gradient, Alg. 2)."""
-    st.window.append(snapshot(gr0.Xr, gr0.Phi, st.L))
+    sub = snapshot_params(st.Z.shape[1], cfg.two_n_max, cfg.deim_window)
+    st.window.append(snapshot(gr0.Xr[:, sub], gr0.Phi[:, sub], st.L[sub]))
     T = cfg.deim_window
     if len(st.window) > T + 1:
         st.window.pop(0)

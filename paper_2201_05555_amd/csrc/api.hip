@@ -422,10 +422,32 @@ struct symrom_rom {
   cplx *Gp, *Vp;
   double* lam;
   int n_active;  // active fixed-point columns (host copy, for work accounting)
+  // DEIM (Sec. 4.3): snapshot ring of T+1 slots (N x psub each) and operator
+  int psub, nslots, win_count, d_cur;
+  bool deim_on;
+  int* sub;
+  double* Ywin;
+  double* Psi;
+  int* didx;
+  double *dw, *dc, *bval, *colpart, *Mdeim, *ylam;
+  int* bidx;
+  int nbg, nbc;
+  cplx *YG, *YV, *C12, *gF;
   symrom_step_info last;
 };
 
 namespace {
+// Size p* of the DEIM snapshot parameter subset: evenly spaced indices
+// i_k = floor(k p / p*), p* = min(p, max(8, ceil(two_n_max / (T+1)))) so that
+// the snapshot matrix (N x p*(T+1)) has at least d = 2n <= two_n_max columns.
+int deim_psub(const symrom_config& c) {
+  const int T1 = c.deim_window + 1;
+  int ps = (c.two_n_max + T1 - 1) / T1;
+  if (ps < 8) ps = 8;
+  if (ps > c.p) ps = c.p;
+  return ps;
+}
+
 int nkb_for(int N) {
   // split-K blocks: about one per CU, at least 64 rows each
   int nkb = (N + 63) / 64;
@@ -479,6 +501,28 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.Gp = ar.take<cplx>((size_t)p * p);
   r.Vp = ar.take<cplx>((size_t)p * p);
   r.lam = ar.take<double>(p);
+  // DEIM
+  r.nslots = r.cfg.deim_window + 1;
+  r.psub = deim_psub(r.cfg);
+  const int P = r.psub * r.nslots;
+  const int dmax = 2 * nm;
+  r.nbg = 256;
+  r.nbc = 64;
+  r.sub = ar.take<int>(r.psub);
+  r.Ywin = ar.take<double>(r.cfg.projection == SYMROM_DEIM ? (size_t)P * N : 0);
+  r.Psi = ar.take<double>(r.cfg.projection == SYMROM_DEIM ? (size_t)dmax * N : 0);
+  r.didx = ar.take<int>(dmax);
+  r.dw = ar.take<double>(dmax);
+  r.dc = ar.take<double>(dmax);
+  r.bval = ar.take<double>(r.nbg);
+  r.bidx = ar.take<int>(r.nbg);
+  r.colpart = ar.take<double>((size_t)r.nbc * dmax);
+  r.Mdeim = ar.take<double>((size_t)P * dmax);
+  r.ylam = ar.take<double>(P);
+  r.YG = ar.take<cplx>((size_t)P * P);
+  r.YV = ar.take<cplx>((size_t)P * P);
+  r.C12 = ar.take<cplx>((size_t)2 * nm * nm);
+  r.gF = ar.take<cplx>((size_t)nm * p);
 }
 
 bool valid_rom_config(const symrom_config* c, std::string& why) {
@@ -517,6 +561,16 @@ bool valid_rom_config(const symrom_config* c, std::string& why) {
   if (c->p > 64) {
     why = "p above 64 is not supported by the initialisation";
     return false;
+  }
+  if (c->projection == SYMROM_DEIM) {
+    if (c->deim_window < 0 || c->deim_window > 7) {
+      why = "deim_window must be in 0..7";
+      return false;
+    }
+    if (deim_psub(*c) * (c->deim_window + 1) > 64) {
+      why = "DEIM snapshot matrix wider than 64 columns";
+      return false;
+    }
   }
   return true;
 }
@@ -627,6 +681,65 @@ void cholqr2(symrom_rom& r, cplx* U, cplx* Z) {
   }
 }
 
+// C12 = [U~^* U~, U~^T U~] (n x n each) for the linear part of the gradient
+void linear_grams(symrom_rom& r, const cplx* U) {
+  hipStream_t s = r.s;
+  const int n = r.n;
+  Timer t(FAM_BASIS, s);
+  launch_gemm_flags(s, ml(U, n), n, ml(U, n), n, 0, r.N, r.nkb, r.gemm_part, r.C12);
+  launch_gemm_flags(s, ml(U, n), n, ml(U, n), n, GEMM_NO_CONJ_A, r.N, r.nkb, r.gemm_part,
+                    r.C12 + (size_t)n * n);
+}
+
+// Snapshot at the start of a step into the ring, and when T+1 snapshots are
+// held, the DEIM operator of this step: Psi = first d left singular vectors
+// of Y (from the eigenpairs of Y^T Y), greedy indices, weights.
+void deim_update(symrom_rom& r, const cplx* U, const cplx* Z) {
+  hipStream_t s = r.s;
+  const int N = r.N, n = r.n;
+  const int slot = r.win_count % r.nslots;
+  launch_snapshot(s, U, N, n, Z, r.sub, r.psub, r.Nx, r.b.factor, r.b.phi,
+                  r.Ywin + (size_t)slot * r.psub * N);
+  r.win_count++;
+  r.deim_on = r.win_count >= r.nslots;
+  if (!r.deim_on) return;
+  Timer t(FAM_DENSE, s);
+  const int P = r.psub * r.nslots;
+  const int d = (2 * n < P) ? 2 * n : P;
+  r.d_cur = d;
+  MatList Yl{};
+  std::vector<const double*> slots(r.nslots);
+  for (int q = 0; q < r.nslots; ++q) {
+    slots[q] = r.Ywin + (size_t)q * r.psub * N;
+    Yl.ptr[q] = reinterpret_cast<const cplx*>(slots[q]);
+    Yl.cols[q] = r.psub;
+  }
+  Yl.count = r.nslots;
+  launch_gemm_flags(s, Yl, P, Yl, P, GEMM_A_REAL | GEMM_B_REAL, N, r.nkb, r.gemm_part, r.YG);
+  launch_dense_herm_eig(s, r.YG, P, r.YV, r.ylam, r.flags);
+  launch_deim_basis_coeffs(s, r.YV, r.ylam, P, d, r.Mdeim, r.flags);
+  launch_rowgemm_real(s, slots.data(), r.nslots, r.psub, N, r.Mdeim, P, d, r.Psi);
+  launch_colsign(s, r.Psi, N, d);
+  launch_deim_residual(s, r.Psi, N, 0, r.dc, r.nbg, r.bval, r.bidx);
+  for (int k = 1; k < d; ++k) {
+    launch_deim_solve(s, r.Psi, N, k, r.didx, r.bval, r.bidx, r.nbg, r.dc, r.flags);
+    launch_deim_residual(s, r.Psi, N, k, r.dc, r.nbg, r.bval, r.bidx);
+  }
+  launch_colsum_partial(s, r.Psi, N, d, r.nbc, r.colpart);
+  launch_deim_weights(s, r.Psi, N, d, r.didx, r.bval, r.bidx, r.nbg, r.colpart, r.nbc, r.dw,
+                      r.flags);
+}
+
+// DEIM gradient at (U, Z) with the field of the last Poisson solve:
+// gF = U~[I]^* ((q/m) e_{j(x_I)} w), then k = -i (gF + linear part).
+void deim_k(symrom_rom& r, const cplx* U, const cplx* Z, const int* active, cplx* kout) {
+  hipStream_t s = r.s;
+  Timer t(FAM_GATHER, s);
+  launch_deim_gather(s, U, r.N, r.n, Z, r.p, r.Nx, r.b.factor, r.b.e, r.cfg.q / r.cfg.m, r.didx,
+                     r.dw, r.d_cur, active, r.gF);
+  if (kout) launch_deim_k(s, r.gF, r.C12, Z, r.n, r.p, kout);
+}
+
 symrom_status read_flags(symrom_rom& r, int* host) {
   HIPCHK(hipMemcpyAsync(host, r.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, r.s));
   HIPCHK(hipStreamSynchronize(r.s));
@@ -638,11 +751,19 @@ symrom_status rom_step_one(symrom_rom& r) {
   const int n = r.n, p = r.p, N = r.N;
   const double dt = r.cfg.dt;
   HIPCHK(hipMemsetAsync(r.flags, 0, 4 * sizeof(int), s));
+  const bool use_deim = r.cfg.projection == SYMROM_DEIM;
   // stage 1 at (U0, Z0): full gradient, k1 = J g, basis velocity -> xi_half
   full_gradient(r, r.U0, r.Z0, nullptr, true);
-  basis_velocity(r, r.U0, r.Z0, 0.5 * dt, r.Xi, r.k);
+  if (use_deim) deim_update(r, r.U0, r.Z0);
+  const bool deim = use_deim && r.deim_on;
+  basis_velocity(r, r.U0, r.Z0, 0.5 * dt, r.Xi, deim ? nullptr : r.k);
+  if (deim) {
+    linear_grams(r, r.U0);
+    deim_k(r, r.U0, r.Z0, nullptr, r.k);
+  }
   // U_half = R_{U0}(xi_half)
   cayley(r, r.U0, r.Xi, r.Uh, r.Amat);
+  if (deim) linear_grams(r, r.Uh);
   // fixed point for k2 at U_half
   {
     Timer t(FAM_DENSE, s);
@@ -656,11 +777,28 @@ symrom_status rom_step_one(symrom_rom& r) {
   r.n_active = p;
   for (;;) {
     ++iters;
-    full_gradient(r, r.Uh, r.Zev, r.active, true);
+    if (deim) {
+      const double pact = (double)r.n_active;
+      {
+        const int ntiles = (r.p + r.gdep.pt - 1) / r.gdep.pt;
+        Timer t(FAM_DEPOSIT, s, 4.0 * n * (double)N * pact,
+                16.0 * n * (double)N * ntiles + 8.0 * (double)r.gdep.nrb * pact * r.Nx);
+        launch_deposit_rom(s, r.Uh, N, n, r.Zev, p, r.Nx, r.gdep, r.b.factor, r.active, r.b.part);
+      }
+      {
+        Timer t(FAM_POISSON, s);
+        launch_poisson(s, r.b.part, r.gdep.nrb, p, r.Nx, r.b.qw, r.b.h, r.b.mw, r.active, r.b.rho,
+                       r.b.phi, r.b.e, r.b.energy);
+      }
+      deim_k(r, r.Uh, r.Zev, r.active, nullptr);
+    } else {
+      full_gradient(r, r.Uh, r.Zev, r.active, true);
+    }
     {
       Timer t(FAM_DENSE, s);
-      launch_dense_fp_update(s, r.gproj, nullptr, n, p, r.Z0, r.Zev, r.ZG, r.k, r.prev, r.active,
-                             dt, r.cfg.fp_tol, fixed > 0 ? 1 : 0, 0, r.counters);
+      launch_dense_fp_update(s, deim ? r.gF : r.gproj, r.C12, n, p, r.Z0, r.Zev, r.ZG, r.k,
+                             r.prev, r.active, dt, r.cfg.fp_tol, fixed > 0 ? 1 : 0,
+                             deim ? 1 : 0, r.counters);
     }
     LAUNCHCHK();
     HIPCHK(hipMemcpyAsync(hc, r.counters, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -670,6 +808,7 @@ symrom_status rom_step_one(symrom_rom& r) {
   }
   r.last.iters = iters;
   r.last.stalled = hc[1];
+  r.last.deim_active = deim ? 1 : 0;
   if (fixed == 0 && hc[0] > 0) return fail(SYMROM_ENOCONV, "fixed point not converged");
   launch_dense_finish_z(s, r.Z0, r.k, n, p, dt, r.Z1);
   // basis velocity at (U_half, Z_G) with the field of each column's last evaluation
@@ -720,6 +859,11 @@ extern "C" size_t rom_workspace_bytes(const symrom_config* cfg) {
 
 namespace {
 symrom_status rom_upload_consts(symrom_rom& r, const double* L) {
+  std::vector<int> sub(r.psub);
+  for (int k = 0; k < r.psub; ++k) sub[k] = (int)(((long long)k * r.p) / r.psub);
+  HIPCHK(hipMemcpyAsync(r.sub, sub.data(), r.psub * sizeof(int), hipMemcpyHostToDevice, r.s));
+  r.win_count = 0;
+  r.deim_on = false;
   std::vector<double> factor, qw, h, mw;
   per_param_consts(L, r.N, r.p, r.Nx, r.cfg.q, r.cfg.m, factor, qw, h, mw);
   hipStream_t s = r.s;
@@ -869,7 +1013,6 @@ extern "C" symrom_status rom_step(symrom_rom* r, int32_t nsteps, symrom_step_inf
     }
   }
   r->last.two_n = 2 * r->n;
-  r->last.deim_active = 0;
   if (info) *info = r->last;
   return SYMROM_OK;
 }
@@ -967,6 +1110,8 @@ extern "C" symrom_status rom_set_state(symrom_rom* r, int32_t two_n, const doubl
   HIPCHK(hipStreamSynchronize(s));
   r->step = step;
   r->ready = true;
+  r->win_count = 0;
+  r->deim_on = false;
   return SYMROM_OK;
 }
 

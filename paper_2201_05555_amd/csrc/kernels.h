@@ -11,12 +11,21 @@ struct PicGeom {
   int pt;
 };
 
-// Up to four N x k_s column blocks concatenated as one N x (sum k_s) matrix.
+// Up to eight N x k_s column blocks concatenated as one N x (sum k_s) matrix.
 struct MatList {
-  const cplx* ptr[4];
-  int cols[4];
+  const cplx* ptr[8];
+  int cols[8];
   int count;
 };
+
+// Up to eight real N x k column blocks.
+struct RealList {
+  const double* ptr[8];
+  int count;
+};
+
+// gemm flags
+enum { GEMM_B_REAL = 1, GEMM_A_REAL = 2, GEMM_NO_CONJ_A = 4 };
 
 // Terms of a row-wise combination out = sum_s in_s M_s.
 struct RowTerms {
@@ -60,12 +69,22 @@ void launch_reconstruct(hipStream_t s, const cplx* U, int N, int n, const cplx* 
                         double* X, double* V);
 void launch_gemm_ah_b(hipStream_t s, const MatList& A, int a, const MatList& B, int b, bool b_real,
                       int N, int nkb, cplx* part, cplx* C);
+// C = op(A) B with flags (GEMM_*): real A / B inputs, A^T instead of A^*
+void launch_gemm_flags(hipStream_t s, const MatList& A, int a, const MatList& B, int b, int flags,
+                       int N, int nkb, cplx* part, cplx* C);
 void launch_rowgemm(hipStream_t s, const RowTerms& T, int N, int m, cplx* out);
 void launch_deim_gather(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                         const double* factor, const double* e, double qm, const int* idx,
                         const double* w, int d, const int* active, cplx* gF);
-void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
-                     const double* factor, const double* phi, double* Y);
+void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, const int* sub,
+                     int psub, int Nx, const double* factor, const double* phi, double* Y);
+void launch_rowgemm_real(hipStream_t s, const double* const* in, int nin, int kin, int N,
+                         const double* M, int ldM, int d, double* out);
+void launch_colsign(hipStream_t s, double* A, int N, int d);
+void launch_deim_residual(hipStream_t s, const double* Psi, int N, int k, const double* c,
+                          int nblk, double* bval, int* bidx);
+void launch_colsum_partial(hipStream_t s, const double* Psi, int N, int d, int nblk,
+                           double* part);
 
 // dense_kernels.hip  (single-workgroup FP64 kernels on small matrices)
 struct DenseCtl;  // device-resident control block, see dense_kernels.hip
@@ -104,3 +123,12 @@ void launch_colphase(hipStream_t s, cplx* U, int N, int col0, int k);
 void launch_z_resize(hipStream_t s, const cplx* Zin, int nin, cplx* Zout, int nout, int p);
 void launch_dense_shrink(hipStream_t s, const cplx* Z, int n, int p, cplx* V, cplx* Znew,
                          double* sig2);
+void launch_deim_solve(hipStream_t s, const double* Psi, int N, int k, int* idx,
+                       const double* bval, const int* bidx, int nblk, double* c, int* flags);
+void launch_deim_weights(hipStream_t s, const double* Psi, int N, int d, int* idx,
+                         const double* bval, const int* bidx, int nblk, const double* colpart,
+                         int nbc, double* w, int* flags);
+void launch_deim_basis_coeffs(hipStream_t s, const cplx* V, const double* lam, int P, int d,
+                              double* M, int* flags);
+void launch_deim_k(hipStream_t s, const cplx* gF, const cplx* C12, const cplx* Z, int n, int p,
+                   cplx* k);

@@ -111,8 +111,11 @@ __device__ inline const cplx* list_col(const MatList& L, int c, int& local) {
 // consecutive rows of the same columns, so loads are coalesced), and the R
 // partial tiles are summed in LDS in a fixed order.  Requires a, b <= 64.
 __global__ void __launch_bounds__(256) gemm_ah_b_kernel(MatList A, int a, MatList B, int b,
-                                                        int b_real, int N, int rk,
+                                                        int flags, int N, int rk,
                                                         cplx* __restrict__ part) {
+  const bool b_real = flags & GEMM_B_REAL;
+  const bool a_real = flags & GEMM_A_REAL;
+  const bool conj_a = !(flags & GEMM_NO_CONJ_A);
   __shared__ cplx red[256 * 16];
   const int kb = blockIdx.x;
   const int r0 = kb * rk;
@@ -139,7 +142,13 @@ __global__ void __launch_bounds__(256) gemm_ah_b_kernel(MatList A, int a, MatLis
     for (int i = 0; i < 4; ++i) {
       int lc;
       ap[i] = (ta0 + i < a) ? list_col(A, ta0 + i, lc) : nullptr;
-      if (ap[i]) ap[i] += (size_t)lc * N;
+      if (ap[i]) {
+        if (a_real)
+          ap[i] = reinterpret_cast<const cplx*>(reinterpret_cast<const double*>(ap[i]) +
+                                                (size_t)lc * N);
+        else
+          ap[i] += (size_t)lc * N;
+      }
       bp[i] = (tb0 + i < b) ? list_col(B, tb0 + i, lc) : nullptr;
       if (bp[i]) {
         if (b_real)
@@ -152,7 +161,14 @@ __global__ void __launch_bounds__(256) gemm_ah_b_kernel(MatList A, int a, MatLis
     for (int l = r0 + rg; l < r1; l += R) {
       cplx av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = ap[i] ? ap[i][l] : mk(0.0, 0.0);
+      for (int i = 0; i < 4; ++i) {
+        if (!ap[i])
+          av[i] = mk(0.0, 0.0);
+        else if (a_real)
+          av[i] = mk(reinterpret_cast<const double*>(ap[i])[l], 0.0);
+        else
+          av[i] = conj_a ? ap[i][l] : cconj(ap[i][l]);
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (!bp[j])
@@ -286,12 +302,14 @@ __global__ void __launch_bounds__(64) deim_gather_kernel(
   }
 }
 
-// DEIM snapshot Lambda^0(X_r^i) Phi^i at every particle (Sec. 4.3, eq. Ydeim):
-// (1 - theta) Phi_j + theta Phi_{j+1}, written as column (slot*p + i) of Y.
+// DEIM snapshot Lambda^0(X_r^i) Phi^i at every particle (Sec. 4.3, eq. Ydeim)
+// for the parameters sub[0..psub): (1 - theta) Phi_j + theta Phi_{j+1},
+// written as column c of Y (N x psub).
 template <int NC>
 __global__ void __launch_bounds__(256) snapshot_kernel(const cplx* __restrict__ U, int N, int n,
-                                                       const cplx* __restrict__ Z, int p, int Nx,
-                                                       const double* __restrict__ factor,
+                                                       const cplx* __restrict__ Z,
+                                                       const int* __restrict__ sub, int psub,
+                                                       int Nx, const double* __restrict__ factor,
                                                        const double* __restrict__ phi,
                                                        double* __restrict__ Y) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
@@ -299,21 +317,149 @@ __global__ void __launch_bounds__(256) snapshot_kernel(const cplx* __restrict__ 
   cplx u[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) u[k] = (k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
-  for (int i = 0; i < p; ++i) {
-    double x = 0.0;
+  for (int c = 0; c < psub; ++c) {
+    const int i = sub[c];
+    double x0 = 0.0, x1 = 0.0;
 #pragma unroll
-    for (int k = 0; k < NC; ++k)
+    for (int k = 0; k < NC; k += 2) {
       if (k < n) {
         cplx z = Z[(size_t)i * n + k];
-        x = fma(u[k].re, z.re, x);
-        x = fma(-u[k].im, z.im, x);
+        x0 = fma(u[k].re, z.re, x0);
+        x0 = fma(-u[k].im, z.im, x0);
       }
+      if (k + 1 < n) {
+        cplx z = Z[(size_t)i * n + k + 1];
+        x1 = fma(u[k + 1].re, z.re, x1);
+        x1 = fma(-u[k + 1].im, z.im, x1);
+      }
+    }
     int j;
     double th;
-    cell_of(x, factor[i], Nx, j, th);
+    cell_of(x0 + x1, factor[i], Nx, j, th);
     int j1 = (j + 1 == Nx) ? 0 : j + 1;
     const double* ph = phi + (size_t)i * Nx;
-    Y[(size_t)i * N + l] = (1.0 - th) * ph[j] + th * ph[j1];
+    Y[(size_t)c * N + l] = (1.0 - th) * ph[j] + th * ph[j1];
+  }
+}
+
+// out (N x d) = sum_s in_s (N x kin) * M[s*kin : (s+1)*kin, :] with M (P x d,
+// column-major, ld ldM): the DEIM basis Psi = Y V diag(lam)^{-1/2}.
+template <int MC>
+__global__ void __launch_bounds__(256) rowgemm_real_kernel(RealList L, int kin, int N,
+                                                           const double* __restrict__ M, int ldM,
+                                                           int d, double* __restrict__ out) {
+  extern __shared__ double Mr[];
+  const int P = L.count * kin;
+  for (int t = threadIdx.x; t < P * d; t += blockDim.x) {
+    int r = t % P, c = t / P;
+    Mr[t] = M[(size_t)c * ldM + r];
+  }
+  __syncthreads();
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= N) return;
+  double acc[MC];
+#pragma unroll
+  for (int o = 0; o < MC; ++o) acc[o] = 0.0;
+  for (int s = 0; s < L.count; ++s)
+    for (int k = 0; k < kin; ++k) {
+      const double y = L.ptr[s][(size_t)k * N + l];
+      const double* mrow = Mr + s * kin + k;
+#pragma unroll
+      for (int o = 0; o < MC; ++o)
+        if (o < d) acc[o] = fma(y, mrow[o * P], acc[o]);
+    }
+#pragma unroll
+  for (int o = 0; o < MC; ++o)
+    if (o < d) out[(size_t)o * N + l] = acc[o];
+}
+
+// Sign convention of the DEIM basis: the entry of largest modulus of each
+// column (smallest row on ties) is made positive.  One block per column.
+__global__ void __launch_bounds__(1024) colsign_kernel(double* __restrict__ A, int N) {
+  __shared__ double sv[1024];
+  __shared__ int si[1024];
+  double* a = A + (size_t)blockIdx.x * N;
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int l = threadIdx.x; l < N; l += blockDim.x) {
+    double v = fabs(a[l]);
+    if (v > best) {
+      best = v;
+      bi = l;
+    }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      double v = sv[threadIdx.x + o];
+      int vi = si[threadIdx.x + o];
+      if (v > sv[threadIdx.x] || (v == sv[threadIdx.x] && vi < si[threadIdx.x])) {
+        sv[threadIdx.x] = v;
+        si[threadIdx.x] = vi;
+      }
+    }
+    __syncthreads();
+  }
+  const bool neg = a[si[0]] < 0.0;
+  __syncthreads();
+  if (neg)
+    for (int l = threadIdx.x; l < N; l += blockDim.x) a[l] = -a[l];
+}
+
+// Greedy DEIM residual r = psi_k - Psi[:, :k] c and its per-block argmax
+// of |r| (smallest index on ties).
+__global__ void __launch_bounds__(256) deim_residual_kernel(const double* __restrict__ Psi, int N,
+                                                            int k, const double* __restrict__ c,
+                                                            double* __restrict__ bval,
+                                                            int* __restrict__ bidx) {
+  __shared__ double cs[64];
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  for (int t = threadIdx.x; t < k; t += blockDim.x) cs[t] = c[t];
+  __syncthreads();
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < N; l += gridDim.x * blockDim.x) {
+    double r = Psi[(size_t)k * N + l];
+    for (int q = 0; q < k; ++q) r = fma(-Psi[(size_t)q * N + l], cs[q], r);
+    const double v = fabs(r);
+    if (v > best) {
+      best = v;
+      bi = l;
+    }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      double v = sv[threadIdx.x + o];
+      int vi = si[threadIdx.x + o];
+      if (v > sv[threadIdx.x] || (v == sv[threadIdx.x] && vi < si[threadIdx.x])) {
+        sv[threadIdx.x] = v;
+        si[threadIdx.x] = vi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    bval[blockIdx.x] = sv[0];
+    bidx[blockIdx.x] = si[0];
+  }
+}
+
+// Column sums of Psi (N x d), partial per block: part[b][j].
+__global__ void __launch_bounds__(256) colsum_partial_kernel(const double* __restrict__ Psi, int N,
+                                                             int d, double* __restrict__ part) {
+  __shared__ double red[8];
+  for (int j = 0; j < d; ++j) {
+    double s = 0.0;
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < N; l += gridDim.x * blockDim.x)
+      s += Psi[(size_t)j * N + l];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * d + j] = s;
   }
 }
 
@@ -360,10 +506,11 @@ void launch_reconstruct(hipStream_t s, const cplx* U, int N, int n, const cplx* 
   }
 }
 
-void launch_gemm_ah_b(hipStream_t s, const MatList& A, int a, const MatList& B, int b, bool b_real,
-                      int N, int nkb, cplx* part, cplx* C) {
+void launch_gemm_flags(hipStream_t s, const MatList& A, int a, const MatList& B, int b, int flags,
+                       int N, int nkb, cplx* part, cplx* C) {
   int rk = (N + nkb - 1) / nkb;
   nkb = (N + rk - 1) / rk;
+  const bool b_real = flags & GEMM_B_REAL;
   // B is processed in chunks of at most 64 columns (one list entry per chunk)
   for (int b0 = 0; b0 < b; b0 += 64) {
     const int bc = (b - b0 < 64) ? b - b0 : 64;
@@ -375,12 +522,17 @@ void launch_gemm_ah_b(hipStream_t s, const MatList& A, int a, const MatList& B, 
                                                          (size_t)b0 * N)
                          : B.ptr[0] + (size_t)b0 * N;
     }
-    hipLaunchKernelGGL(gemm_ah_b_kernel, dim3(nkb), dim3(256), 0, s, A, a, Bc, bc,
-                       b_real ? 1 : 0, N, rk, part);
+    hipLaunchKernelGGL(gemm_ah_b_kernel, dim3(nkb), dim3(256), 0, s, A, a, Bc, bc, flags, N, rk,
+                       part);
     int nout = a * bc;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((nout + 31) / 32), dim3(256), 0, s, part, nkb,
-                       nout, C + (size_t)b0 * a);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((nout + 31) / 32), dim3(256), 0, s, part,
+                       nkb, nout, C + (size_t)b0 * a);
   }
+}
+
+void launch_gemm_ah_b(hipStream_t s, const MatList& A, int a, const MatList& B, int b, bool b_real,
+                      int N, int nkb, cplx* part, cplx* C) {
+  launch_gemm_flags(s, A, a, B, b, b_real ? GEMM_B_REAL : 0, N, nkb, part, C);
 }
 
 void launch_rowgemm(hipStream_t s, const RowTerms& T, int N, int m, cplx* out) {
@@ -407,15 +559,51 @@ void launch_deim_gather(hipStream_t s, const cplx* U, int N, int n, const cplx* 
                      qm, idx, w, d, active, gF);
 }
 
-void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
-                     const double* factor, const double* phi, double* Y) {
+void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, const int* sub,
+                     int psub, int Nx, const double* factor, const double* phi, double* Y) {
   int nc = nc_bucket(n);
   dim3 grid((N + 255) / 256);
+#define SN(NCV)                                                                               \
+  hipLaunchKernelGGL(snapshot_kernel<NCV>, grid, dim3(256), 0, s, U, N, n, Z, sub, psub, Nx, \
+                     factor, phi, Y)
   switch (nc) {
-    case 4: hipLaunchKernelGGL(snapshot_kernel<4>, grid, dim3(256), 0, s, U, N, n, Z, p, Nx, factor, phi, Y); break;
-    case 8: hipLaunchKernelGGL(snapshot_kernel<8>, grid, dim3(256), 0, s, U, N, n, Z, p, Nx, factor, phi, Y); break;
-    case 16: hipLaunchKernelGGL(snapshot_kernel<16>, grid, dim3(256), 0, s, U, N, n, Z, p, Nx, factor, phi, Y); break;
-    default: hipLaunchKernelGGL(snapshot_kernel<32>, grid, dim3(256), 0, s, U, N, n, Z, p, Nx, factor, phi, Y); break;
+    case 4: SN(4); break;
+    case 8: SN(8); break;
+    case 16: SN(16); break;
+    default: SN(32); break;
+  }
+#undef SN
+}
+
+void launch_rowgemm_real(hipStream_t s, const double* const* in, int nin, int kin, int N,
+                         const double* M, int ldM, int d, double* out) {
+  RealList L{};
+  for (int q = 0; q < nin; ++q) L.ptr[q] = in[q];
+  L.count = nin;
+  size_t sh = (size_t)nin * kin * d * sizeof(double);
+  dim3 grid((N + 255) / 256);
+  if (d <= 16) {
+    ALLOW_BIG_LDS(rowgemm_real_kernel<16>);
+    hipLaunchKernelGGL(rowgemm_real_kernel<16>, grid, dim3(256), sh, s, L, kin, N, M, ldM, d, out);
+  } else if (d <= 32) {
+    ALLOW_BIG_LDS(rowgemm_real_kernel<32>);
+    hipLaunchKernelGGL(rowgemm_real_kernel<32>, grid, dim3(256), sh, s, L, kin, N, M, ldM, d, out);
+  } else {
+    ALLOW_BIG_LDS(rowgemm_real_kernel<64>);
+    hipLaunchKernelGGL(rowgemm_real_kernel<64>, grid, dim3(256), sh, s, L, kin, N, M, ldM, d, out);
   }
 }
 
+void launch_colsign(hipStream_t s, double* A, int N, int d) {
+  hipLaunchKernelGGL(colsign_kernel, dim3(d), dim3(1024), 0, s, A, N);
+}
+
+void launch_deim_residual(hipStream_t s, const double* Psi, int N, int k, const double* c,
+                          int nblk, double* bval, int* bidx) {
+  hipLaunchKernelGGL(deim_residual_kernel, dim3(nblk), dim3(256), 0, s, Psi, N, k, c, bval, bidx);
+}
+
+void launch_colsum_partial(hipStream_t s, const double* Psi, int N, int d, int nblk,
+                           double* part) {
+  hipLaunchKernelGGL(colsum_partial_kernel, dim3(nblk), dim3(256), 0, s, Psi, N, d, part);
+}

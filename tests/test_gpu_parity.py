@@ -331,3 +331,37 @@ def test_rom_rank_auto_indicator():
         status, two_n, eps = rom.adapt_rank(st, cfg, 0)
         assert abs(info["rank_indicator"] - eps) < 1e-9 * max(eps, 1e-3), (info, eps)
         assert info["two_n"] == two_n == min(8 + 2 * (s + 1), 12)
+
+
+@pytest.mark.parametrize("kw,two_n,two_n_max,steps", [
+    (dict(N=20000, p=24, Nx=128), 8, 8, 6),
+    (dict(N=30000, p=64, Nx=128), 10, 60, 6),     # the two-stream workload's DEIM shape
+])
+def test_rom_deim_steps_parity(kw, two_n, two_n_max, steps):
+    """DEIM with the exact potential: Galerkin for the first T steps while
+    the snapshot window fills, then the DEIM gradient in the fixed point.
+    Same iteration counts and DEIM switch-over as the oracle; R within the
+    conditioning-aware bound."""
+    binding, torch = _b()
+    w, e = _ens("twostream_deim", **kw)
+    _say("rom deim", kw, two_n, two_n_max, steps)
+    cfg, st = _oracle_state(w, e, two_n, fp_tol=1e-10, projection="deim", deim_window=3)
+    cfg.two_n_max = two_n_max
+    st_s = rom.RomState(U=st.U.copy(), Z=st.Z.copy(), L=st.L)
+    # sensitivity of the same DEIM run (the DEIM basis is the SVD of an
+    # ill-conditioned snapshot matrix, so this bound is wider than Galerkin's)
+    sU, sZ, sR = _oracle_sensitivity(st_s, rom.RomConfig(**cfg.__dict__), 6, steps=steps)
+    r = _gpu_rom(binding, w, e, two_n, two_n_max=two_n_max, fp_tol=1e-10, projection="deim",
+                 deim_window=3)
+    _set_from_oracle(r, st, torch)
+    for s in range(steps):
+        info = r.step(1)
+        assert rom.prk_step(st, cfg) == rom.OK
+        assert info["deim_active"] == (1 if s >= 3 else 0), (s, info)
+        assert (st.deim_indices is not None) == (s >= 3)
+        assert info["iters"] == st.last_iters, (s, info, st.last_iters)
+    X, V = r.reconstruct()
+    Xo, Vo = rom.reconstruct(st)
+    bound = max(1e-9, _bound(sR))
+    assert _rel(_np(X).T, Xo) < bound, (sR,)
+    assert _rel(_np(V).T, Vo) < bound, (sR,)

@@ -80,3 +80,13 @@ def test_deim_rom_runs_and_switches_after_window():
             assert st.deim_indices is None
         else:
             assert st.deim_indices is not None and len(st.deim_indices) == 6
+
+
+def test_snapshot_parameter_subset():
+    """p* (T+1) covers the largest DEIM dimension d = two_n_max; the subset is
+    evenly spaced and starts at the first parameter."""
+    for p, cap, T in ((64, 60, 3), (16, 10, 3), (4, 10, 3), (300, 8, 5)):
+        sub = deim.snapshot_params(p, cap, T)
+        assert sub[0] == 0 and len(set(sub.tolist())) == len(sub)
+        assert len(sub) == min(p, max(8, -(-cap // (T + 1))))
+        assert np.all(np.diff(sub) > 0) and sub[-1] < p
