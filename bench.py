@@ -69,20 +69,26 @@ def cpu_baseline(w, ens, seconds):
     X0 = np.asfortranarray(ens["X0"][:, :p_sub])
     V0 = np.asfortranarray(ens["V0"][:, :p_sub])
     cfg = rom.RomConfig(N=w["N"], p=p_sub, Nx=w["Nx"], two_n=w["two_n"], dt=w["dt"],
-                        fp_tol=1e-9)
+                        fp_tol=1e-9, two_n_max=w["two_n_max"],
+                        projection=w.get("projection", "galerkin"),
+                        deim_window=w.get("deim_window", 3),
+                        rank_auto=w["two_n_max"] > w["two_n"], rank_tol_up=1e-2)
     st = rom.init_state(X0, V0, ens["L"][:p_sub], cfg)
     steps = 0
     t0 = time.perf_counter()
     while True:
         rom.prk_step(st, cfg)
+        if cfg.rank_auto:
+            rom.adapt_rank(st, cfg, 0)
         steps += 1
         el = time.perf_counter() - t0
         if el > seconds or steps >= 50:
             break
     val = w["N"] * p_sub * steps / el
     return {"value": val, "unit": "particle-param-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"oracle prk_step, first {p_sub} of {w['p']} parameters, N={w['N']}, "
-                      f"2n={w['two_n']}, Galerkin, {steps} steps in {el:.1f} s"}
+            "sample": f"oracle prk_step (+ rank policy), first {p_sub} of {w['p']} parameters, "
+                      f"N={w['N']}, 2n={w['two_n']}->{st.U.shape[1]}, {cfg.projection}, "
+                      f"{steps} steps in {el:.1f} s"}
 
 
 def main():
@@ -113,10 +119,12 @@ def main():
     torch.cuda.synchronize()
 
     # ---------------- reduced model ----------------
+    proj = w.get("projection", "galerkin")
     cfg = binding.make_config(N, p, Nx, w["two_n"], two_n_max=w["two_n_max"], dt=w["dt"],
-                              projection="galerkin", fp_tol=1e-9)
+                              projection=proj, deim_window=w.get("deim_window", 3), fp_tol=1e-9,
+                              rank_auto=w["two_n_max"] > w["two_n"], rank_tol_up=1e-2)
     rom_h = binding.Rom(cfg, ens["L"], X0, V0)
-    iters = []
+    iters, ranks, deim_steps = [], [], 0
     for _ in range(a.warmup):
         iters.append(rom_h.step(1)["iters"])
     torch.cuda.synchronize()
@@ -126,7 +134,10 @@ def main():
         binding.kernel_work(fam)
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        iters.append(rom_h.step(1)["iters"])
+        info = rom_h.step(1)
+        iters.append(info["iters"])
+        ranks.append(info["two_n"])
+        deim_steps += info["deim_active"]
     torch.cuda.synchronize()
     t_rom = time.perf_counter() - t0
     fams = {}
@@ -180,7 +191,9 @@ def main():
         "data": "synthetic (seeded two-stream ensemble, inverse-CDF loading)",
         "config": {"workload": a.workload, "N": N, "p": p, "Nx": Nx, "dt": w["dt"],
                    "two_n_start": w["two_n"], "two_n_end": two_n_end,
-                   "two_n_max": w["two_n_max"], "projection": "galerkin",
+                   "two_n_max": w["two_n_max"], "projection": proj,
+                   "rank_auto": bool(cfg.rank_auto), "rank_tol_up": 1e-2,
+                   "two_n_timed_steps": ranks, "deim_steps": deim_steps,
                    "fp_tol": 1e-9, "mean_fp_iters": float(np.mean(iters[a.warmup:]))},
         "fom": {"value": fom_rate, "unit": "particle-param-steps/s",
                 "ms_per_step": 1e3 * t_fom / a.steps, "roofline": fom_roof},

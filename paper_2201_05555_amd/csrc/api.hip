@@ -205,7 +205,10 @@ PicBufs carve_pic(Arena& ar, int N, int p, int Nx, const PicGeom& g) {
   b.qw = ar.take<double>(p);
   b.h = ar.take<double>(p);
   b.mw = ar.take<double>(p);
-  b.part = ar.take<double>((size_t)(g.nrb + 1) * p * Nx);
+  // deposit partials + their row-block sums; also scratch for column sums
+  size_t np_ = (size_t)(g.nrb + 1) * p * Nx;
+  if (np_ < (size_t)32 * p) np_ = (size_t)32 * p;
+  b.part = ar.take<double>(np_);
   b.rho = ar.take<double>((size_t)p * Nx);
   b.phi = ar.take<double>((size_t)p * Nx);
   b.e = ar.take<double>((size_t)p * Nx);
@@ -382,7 +385,7 @@ extern "C" symrom_status fom_diagnostics(symrom_fom* f, double* E, double* H) {
   if (H) {
     launch_fom_velocity(s, f->X, f->V, f->N, f->p, f->Nx, f->b.factor, f->b.e, f->q / f->m,
                         0.5 * f->dt, f->Vtmp);
-    launch_colsumsq(s, f->Vtmp, f->N, f->p, 0.5, H);
+    launch_colsumsq(s, f->Vtmp, f->N, f->p, 0.5, H, f->b.part);
     launch_vec_add(s, H, f->b.energy, f->p);
   }
   LAUNCHCHK();
@@ -422,6 +425,8 @@ struct symrom_rom {
   cplx *Gp, *Vp;
   double* lam;
   int n_active;  // active fixed-point columns (host copy, for work accounting)
+  bool stage1_cached;  // G, g and the fields in the buffers belong to (U0, Z0)
+  double* colsq;       // per-parameter |G~|^2
   // DEIM (Sec. 4.3): snapshot ring of T+1 slots (N x psub each) and operator
   int psub, nslots, win_count, d_cur;
   bool deim_on;
@@ -498,6 +503,7 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.gemm_part = ar.take<cplx>((size_t)r.nkb * 64 * 64);
   r.sigma2 = ar.take<double>(nm);
   r.eps_dev = ar.take<double>(4);
+  r.colsq = ar.take<double>(p);
   r.Gp = ar.take<cplx>((size_t)p * p);
   r.Vp = ar.take<cplx>((size_t)p * p);
   r.lam = ar.take<double>(p);
@@ -716,8 +722,9 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z) {
   }
   Yl.count = r.nslots;
   launch_gemm_flags(s, Yl, P, Yl, P, GEMM_A_REAL | GEMM_B_REAL, N, r.nkb, r.gemm_part, r.YG);
-  launch_dense_herm_eig(s, r.YG, P, r.YV, r.ylam, r.flags);
-  launch_deim_basis_coeffs(s, r.YV, r.ylam, P, d, r.Mdeim, r.flags);
+  launch_dense_topeig(s, r.YG, P, d, reinterpret_cast<double*>(r.YV), r.ylam, r.flags);
+  launch_deim_basis_coeffs(s, reinterpret_cast<const double*>(r.YV), r.ylam, P, d, r.Mdeim,
+                           r.flags);
   launch_rowgemm_real(s, slots.data(), r.nslots, r.psub, N, r.Mdeim, P, d, r.Psi);
   launch_colsign(s, r.Psi, N, d);
   launch_deim_residual(s, r.Psi, N, 0, r.dc, r.nbg, r.bval, r.bidx);
@@ -753,7 +760,8 @@ symrom_status rom_step_one(symrom_rom& r) {
   HIPCHK(hipMemsetAsync(r.flags, 0, 4 * sizeof(int), s));
   const bool use_deim = r.cfg.projection == SYMROM_DEIM;
   // stage 1 at (U0, Z0): full gradient, k1 = J g, basis velocity -> xi_half
-  full_gradient(r, r.U0, r.Z0, nullptr, true);
+  if (!r.stage1_cached) full_gradient(r, r.U0, r.Z0, nullptr, true);
+  r.stage1_cached = false;
   if (use_deim) deim_update(r, r.U0, r.Z0);
   const bool deim = use_deim && r.deim_on;
   basis_velocity(r, r.U0, r.Z0, 0.5 * dt, r.Xi, deim ? nullptr : r.k);
@@ -992,6 +1000,7 @@ extern "C" symrom_status rom_init(const symrom_config* cfg, const double* L, con
     return fail(SYMROM_ESINGULAR, "rom_init: basis orthonormalisation failed");
   }
   r->ready = true;
+  r->stage1_cached = false;
   r->step = 0;
   *out = r;
   return SYMROM_OK;
@@ -1025,17 +1034,26 @@ symrom_status rom_grow(symrom_rom& r, int k, bool decide) {
   const int n = r.n, p = r.p, N = r.N;
   HIPCHK(hipMemsetAsync(r.flags, 0, 4 * sizeof(int), s));
   full_gradient(r, r.U0, r.Z0, nullptr, true);
-  launch_gemm_ah_b(s, ml(r.G, p), p, ml(r.G, p), p, false, N, r.nkb, r.gemm_part, r.Gp);
-  launch_dense_hh(s, r.Gp, r.gproj, n, p, r.eps_dev);
-  LAUNCHCHK();
   if (decide) {
+    // eps needs only |G|^2 and |g|^2
+    launch_colsumsq(s, reinterpret_cast<const double*>(r.G), 2 * N, p, 1.0, r.colsq, r.b.part);
+    launch_dense_indicator(s, r.colsq, r.gproj, n, p, r.eps_dev);
+    LAUNCHCHK();
     double eps = 0.0;
     HIPCHK(hipMemcpyAsync(&eps, r.eps_dev, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     r.last.rank_indicator = eps;
-    if (!(eps > r.cfg.rank_tol_up) || 2 * (n + 1) > r.cfg.two_n_max) return SYMROM_OK;
+    if (!(eps > r.cfg.rank_tol_up) || 2 * (n + 1) > r.cfg.two_n_max) {
+      // the gradient just computed is the next step's first-stage gradient
+      r.stage1_cached = true;
+      return SYMROM_OK;
+    }
     k = 1;
   }
+  r.stage1_cached = false;
+  launch_gemm_ah_b(s, ml(r.G, p), p, ml(r.G, p), p, false, N, r.nkb, r.gemm_part, r.Gp);
+  launch_dense_hh(s, r.Gp, r.gproj, n, p, nullptr);
+  LAUNCHCHK();
   if (n + k > r.nmax) return fail(SYMROM_ERANKCAP, "rank growth beyond two_n_max");
   if (k > p) return fail(SYMROM_EINVAL, "cannot grow by more pairs than parameters");
   launch_dense_herm_eig(s, r.Gp, p, r.Vp, r.lam, r.flags);
@@ -1069,6 +1087,7 @@ symrom_status rom_shrink(symrom_rom& r, int n_new) {
 
 extern "C" symrom_status rom_adapt_rank(symrom_rom* r, int32_t target_two_n, int32_t* new_two_n) {
   if (!r) return fail(SYMROM_EINVAL, "rom_adapt_rank: null handle");
+  r->stage1_cached = false;
   if (!r->ready) return fail(SYMROM_ESTATE, "rom_adapt_rank: handle not initialised");
   if (target_two_n < 0 || (target_two_n & 1))
     return fail(SYMROM_EINVAL, "rom_adapt_rank: target must be even and non-negative");
@@ -1103,6 +1122,7 @@ extern "C" symrom_status rom_set_state(symrom_rom* r, int32_t two_n, const doubl
   if (two_n <= 0 || (two_n & 1) || two_n > r->cfg.two_n_max)
     return fail(SYMROM_EINVAL, "rom_set_state: bad rank");
   r->n = two_n / 2;
+  r->stage1_cached = false;
   hipStream_t s = r->s;
   launch_u_from_ux(s, UX, r->N, r->n, r->U0);
   launch_z_from_real(s, Z, r->n, r->p, r->Z0);
@@ -1128,6 +1148,7 @@ extern "C" symrom_status rom_gradient(symrom_rom* r, const double* Z, double* g,
   if (!r || !Z || !g) return fail(SYMROM_EINVAL, "rom_gradient: null argument");
   hipStream_t s = r->s;
   const int n = r->n, p = r->p;
+  r->stage1_cached = false;
   launch_z_from_real(s, Z, n, p, r->Zev);
   full_gradient(*r, r->U0, r->Zev, nullptr, true);
   launch_z_to_real(s, r->gproj, n, p, g);
@@ -1142,6 +1163,7 @@ extern "C" symrom_status rom_gradient(symrom_rom* r, const double* Z, double* g,
 
 extern "C" symrom_status rom_diagnostics(symrom_rom* r, double* E, double* H) {
   if (!r) return fail(SYMROM_EINVAL, "rom_diagnostics: null handle");
+  r->stage1_cached = false;
   hipStream_t s = r->s;
   const int N = r->N, p = r->p, n = r->n;
   launch_deposit_rom(s, r->U0, N, n, r->Z0, p, r->Nx, r->gdep, r->b.factor, nullptr, r->b.part);
@@ -1152,7 +1174,7 @@ extern "C" symrom_status rom_diagnostics(symrom_rom* r, double* E, double* H) {
     // velocities V_r = Im(U~ Z~) into the real view of the gather buffer
     double* Vr = reinterpret_cast<double*>(r->G);
     launch_reconstruct(s, r->U0, N, n, r->Z0, p, nullptr, Vr);
-    launch_colsumsq(s, Vr, N, p, 0.5, H);
+    launch_colsumsq(s, Vr, N, p, 0.5, H, r->b.part);
     launch_vec_add(s, H, r->b.energy, p);
   }
   LAUNCHCHK();

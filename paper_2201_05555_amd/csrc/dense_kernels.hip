@@ -1004,7 +1004,7 @@ void launch_dense_shrink(hipStream_t s, const cplx* Z, int n, int p, cplx* V, cp
 // M[:, c] = Re V[:, c] / sqrt(lam_c), c < d: Psi = Y M is the first d left
 // singular vectors of Y from the eigenpairs of Y^T Y (real symmetric, so V
 // is real).
-__global__ void deim_basis_coeffs_kernel(const cplx* __restrict__ V, const double* __restrict__ lam,
+__global__ void deim_basis_coeffs_kernel(const double* __restrict__ V, const double* __restrict__ lam,
                                          int P, int d, double* __restrict__ M,
                                          int* __restrict__ flags) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1016,7 +1016,7 @@ __global__ void deim_basis_coeffs_kernel(const cplx* __restrict__ V, const doubl
     M[t] = 0.0;
     return;
   }
-  M[t] = V[t].re / sqrt(l);
+  M[t] = V[t] / sqrt(l);
 }
 
 // winner of the per-block argmax results (largest value, smallest index)
@@ -1143,7 +1143,7 @@ void launch_deim_weights(hipStream_t s, const double* Psi, int N, int d, int* id
   hipLaunchKernelGGL(deim_weights_kernel, dim3(1), dim3(DTPB), 0, s, Psi, N, d, idx, bval, bidx,
                      nblk, colpart, nbc, w, flags);
 }
-void launch_deim_basis_coeffs(hipStream_t s, const cplx* V, const double* lam, int P, int d,
+void launch_deim_basis_coeffs(hipStream_t s, const double* V, const double* lam, int P, int d,
                               double* M, int* flags) {
   hipLaunchKernelGGL(deim_basis_coeffs_kernel, dim3(nblk((size_t)P * d)), dim3(256), 0, s, V, lam,
                      P, d, M, flags);
@@ -1152,4 +1152,478 @@ void launch_deim_k(hipStream_t s, const cplx* gF, const cplx* C12, const cplx* Z
                    cplx* k) {
   hipLaunchKernelGGL(deim_k_kernel, dim3(nblk((size_t)n * p)), dim3(256), 0, s, gF, C12, Z, n, p,
                      k);
+}
+
+// ---------------------------------------------------------------------------
+// Real symmetric eigendecomposition (n <= 64) in one wavefront: Householder
+// reduction to tridiagonal form, accumulation of the reflectors, then the
+// implicit QL iteration with Wilkinson-type shifts on the tridiagonal matrix.
+// Lane r owns row r of the matrices, so every Givens rotation of the QL
+// sweep is applied by each lane to its own row without barriers; the scalar
+// recurrence runs redundantly on all lanes with d, e shared in LDS.
+// Input: the real part of G (n x n, column-major).  Output: eigenvalues lam
+// in decreasing order and eigenvectors V (n x n, column-major, real).
+// ---------------------------------------------------------------------------
+#define SE_LD 65
+__global__ void __launch_bounds__(64) dense_symeig_kernel(const cplx* __restrict__ G, int n,
+                                                          double* __restrict__ V,
+                                                          double* __restrict__ lam,
+                                                          int* __restrict__ flags) {
+  __shared__ double A[64 * SE_LD];
+  __shared__ double Z[64 * SE_LD];
+  __shared__ double H[64 * SE_LD];  // Householder vectors, row k holds v_k
+  __shared__ double tau[64];
+  __shared__ double wv[64];
+  __shared__ double dd[64];
+  __shared__ double ee[64];
+  __shared__ int perm[64];
+  const int r = threadIdx.x;
+  auto wsum = [](double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+  };
+  if (r < n)
+    for (int c = 0; c < n; ++c) A[r * SE_LD + c] = G[(size_t)c * n + r].re;
+  __syncthreads();
+  // 1. Householder tridiagonalisation: H_k = I - tau_k v_k v_k^T zeroes column k
+  //    below the subdiagonal; B <- H B H via p = tau B v, w = p - (tau/2 v.p) v
+  for (int k = 0; k + 2 < n; ++k) {
+    const double xr = (r > k && r < n) ? A[r * SE_LD + k] : 0.0;
+    const double sig = wsum(xr * xr);
+    const double x0 = A[(k + 1) * SE_LD + k];
+    double t = 0.0, alpha = 0.0;
+    if (sig > 0.0) {
+      alpha = (x0 >= 0.0) ? -sqrt(sig) : sqrt(sig);
+      const double vn2 = 2.0 * sig - 2.0 * alpha * x0;
+      t = (vn2 > 0.0) ? 2.0 / vn2 : 0.0;
+    }
+    const double vr = (r > k && r < n) ? (r == k + 1 ? xr - alpha : xr) : 0.0;
+    if (r < 64) H[k * SE_LD + r] = vr;
+    if (r == 0) tau[k] = t;
+    __syncthreads();
+    if (t != 0.0) {
+      double pa[4] = {0.0, 0.0, 0.0, 0.0};
+      if (r > k && r < n) {
+        const double* ar = A + r * SE_LD;
+        const double* hv = H + k * SE_LD;
+#pragma unroll 4
+        for (int j = k + 1; j < n; ++j) pa[j & 3] = fma(ar[j], hv[j], pa[j & 3]);
+      }
+      double pr_ = t * ((pa[0] + pa[1]) + (pa[2] + pa[3]));
+      const double K = 0.5 * t * wsum(vr * pr_);
+      const double wr = pr_ - K * vr;
+      wv[r] = wr;
+      __syncthreads();
+      if (r > k && r < n) {
+        double* ar = A + r * SE_LD;
+        const double* hv = H + k * SE_LD;
+#pragma unroll 8
+        for (int j = k + 1; j < n; ++j) ar[j] -= vr * wv[j] + wr * hv[j];
+      }
+      __syncthreads();
+      if (r > k + 1 && r < n) {
+        A[r * SE_LD + k] = 0.0;
+        A[k * SE_LD + r] = 0.0;
+      }
+      if (r == 0) {
+        A[(k + 1) * SE_LD + k] = alpha;
+        A[k * SE_LD + k + 1] = alpha;
+      }
+    }
+    __syncthreads();
+  }
+  // 2. Z = H_0 H_1 ... H_{n-3}, applied right to left to the identity
+  if (r < n)
+    for (int c = 0; c < n; ++c) Z[r * SE_LD + c] = (r == c) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int k = n - 3; k >= 0; --k) {
+    const double t = tau[k];
+    if (t == 0.0) continue;
+    // s_c = v^T Z[:, c] (lane c), then Z[i, c] -= t v_i s_c (lane i)
+    double sa[4] = {0.0, 0.0, 0.0, 0.0};
+    if (r < n) {
+      const double* hv = H + k * SE_LD;
+#pragma unroll 4
+      for (int i = k + 1; i < n; ++i) sa[i & 3] = fma(hv[i], Z[i * SE_LD + r], sa[i & 3]);
+    }
+    wv[r] = (sa[0] + sa[1]) + (sa[2] + sa[3]);
+    __syncthreads();
+    if (r > k && r < n) {
+      const double tv = t * H[k * SE_LD + r];
+      double* zr = Z + r * SE_LD;
+#pragma unroll 8
+      for (int c = 0; c < n; ++c) zr[c] -= tv * wv[c];
+    }
+    __syncthreads();
+  }
+  // 3. implicit QL on the tridiagonal (d, e).  Lane 0 runs the scalar
+  //    recurrence of one QL iteration and records its Givens rotations
+  //    (applied to columns i, i+1 for i = m-1 .. l); then every lane applies
+  //    them, in order, to its own row of Z.
+  double* rc = H;                 // rotation cosines (H is free now)
+  double* rs = H + 64;            // rotation sines
+  __shared__ int qctl[4];         // [0] l, [1] m, [2] rotations recorded, [3] state
+  if (r < n) {
+    dd[r] = A[r * SE_LD + r];
+    ee[r] = (r + 1 < n) ? A[(r + 1) * SE_LD + r] : 0.0;
+  }
+  if (r == 0) {
+    qctl[0] = 0;
+    qctl[3] = 0;  // 0 running, 1 done, 2 iteration cap exceeded
+  }
+  __syncthreads();
+  const double eps = 2.220446049250313e-16;
+  int iter_l = 0;  // lane 0: QL iterations spent on the current l
+  for (;;) {
+    if (r == 0) {
+      int l = qctl[0];
+      int nrec = 0, mfound = l;
+      for (;;) {
+        if (l >= n) {
+          qctl[3] = 1;
+          break;
+        }
+        int m = l;
+        while (m < n - 1 && !(fabs(ee[m]) <= eps * (fabs(dd[m]) + fabs(dd[m + 1])))) ++m;
+        if (m == l) {
+          ++l;
+          iter_l = 0;
+          continue;
+        }
+        if (++iter_l > 60) {
+          qctl[3] = 2;
+          break;
+        }
+        mfound = m;
+        double g = (dd[l + 1] - dd[l]) / (2.0 * ee[l]);
+        double rr = hypot(g, 1.0);
+        g = dd[m] - dd[l] + ee[l] / (g + (g >= 0.0 ? rr : -rr));
+        double s = 1.0, c = 1.0, pp = 0.0;
+        bool early = false;
+        // d_{i+1} is carried in a register; e_i and d_i of the next index are
+        // loaded one iteration ahead (the iteration writes index i+1 only)
+        double d_up = dd[m];
+        double e_i = ee[m - 1], d_i = dd[m - 1];
+        for (int i = m - 1; i >= l; --i) {
+          const double e_nx = (i > l) ? ee[i - 1] : 0.0;
+          const double d_nx = (i > l) ? dd[i - 1] : 0.0;
+          const double f = s * e_i;
+          const double b = c * e_i;
+          rr = hypot(f, g);
+          ee[i + 1] = rr;
+          if (rr == 0.0) {
+            dd[i + 1] = d_up - pp;
+            ee[m] = 0.0;
+            early = true;
+            break;
+          }
+          const double inv = 1.0 / rr;
+          s = f * inv;
+          c = g * inv;
+          g = d_up - pp;
+          rr = (d_i - g) * s + 2.0 * c * b;
+          pp = s * rr;
+          dd[i + 1] = g + pp;
+          g = c * rr - b;
+          rc[nrec] = c;
+          rs[nrec] = s;
+          ++nrec;
+          d_up = d_i;
+          e_i = e_nx;
+          d_i = d_nx;
+        }
+        if (!early) {
+          dd[l] -= pp;
+          ee[l] = g;
+          ee[m] = 0.0;
+        }
+        break;
+      }
+      qctl[0] = l;
+      qctl[1] = mfound;
+      qctl[2] = nrec;
+    }
+    __syncthreads();
+    if (qctl[3] != 0) break;
+    const int nrec = qctl[2];
+    const int m = qctl[1];
+    if (r < n && nrec > 0) {
+      // rotation t acts on columns (i, i+1), i = m-1-t; the updated column i
+      // is the upper operand of the next rotation, so it stays in a register
+      double* zr = Z + r * SE_LD;
+      double hi = zr[m];
+      for (int t = 0; t < nrec; ++t) {
+        const int i = m - 1 - t;
+        const double lo = zr[i];
+        const double c = rc[t], s = rs[t];
+        zr[i + 1] = s * lo + c * hi;
+        hi = c * lo - s * hi;
+      }
+      zr[m - nrec] = hi;
+    }
+    __syncthreads();
+  }
+  const int bad = (qctl[3] == 2);
+  // 4. decreasing order
+  if (r == 0) {
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    for (int i = 0; i < n; ++i) {
+      int b = i;
+      for (int j = i + 1; j < n; ++j)
+        if (dd[perm[j]] > dd[perm[b]]) b = j;
+      int tp = perm[i];
+      perm[i] = perm[b];
+      perm[b] = tp;
+    }
+  }
+  __syncthreads();
+  if (r < n) {
+    lam[r] = dd[perm[r]];
+    for (int c = 0; c < n; ++c) V[(size_t)c * n + r] = Z[r * SE_LD + perm[c]];
+  }
+  if (r == 0 && bad && flags) flags[0] |= 32;
+}
+
+void launch_dense_symeig(hipStream_t s, const cplx* G, int n, double* V, double* lam, int* flags) {
+  hipLaunchKernelGGL(dense_symeig_kernel, dim3(1), dim3(64), 0, s, G, n, V, lam, flags);
+}
+
+// Rank indicator from column sums of squares of G~ (p) and g (n x p):
+// eps = sqrt(1 - ||g||^2 / ||G||^2).
+__global__ void __launch_bounds__(DTPB) dense_indicator_kernel(const double* __restrict__ colsq,
+                                                               const cplx* __restrict__ g, int n,
+                                                               int p, double* __restrict__ eps_out) {
+  __shared__ double red[DTPB / 64];
+  double tr = 0.0, gn = 0.0;
+  for (int i = threadIdx.x; i < p; i += blockDim.x) tr += colsq[i];
+  for (int t = threadIdx.x; t < n * p; t += blockDim.x) gn += cabs2(g[t]);
+  tr = block_sum(tr, red);
+  gn = block_sum(gn, red);
+  if (threadIdx.x == 0) *eps_out = (tr > 0.0) ? sqrt(fmax(0.0, 1.0 - gn / tr)) : 0.0;
+}
+void launch_dense_indicator(hipStream_t s, const double* colsq, const cplx* g, int n, int p,
+                            double* eps) {
+  hipLaunchKernelGGL(dense_indicator_kernel, dim3(1), dim3(DTPB), 0, s, colsq, g, n, p, eps);
+}
+
+// ---------------------------------------------------------------------------
+// Leading eigenpairs of a real symmetric matrix (n <= 64, d <= n) in one
+// wavefront: Householder tridiagonalisation (as dense_symeig_kernel), then
+// lane j finds the j-th largest eigenvalue of the tridiagonal T by bisection
+// on Sturm counts, its eigenvector by inverse iteration (banded Gaussian
+// elimination with partial pivoting on T - lambda I), and back-transforms it
+// through the stored reflectors; a Cholesky QR pass orthonormalises the d
+// vectors.  Output: lam (d, decreasing) and V (n x d, column-major).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) dense_topeig_kernel(const cplx* __restrict__ G, int n, int d,
+                                                          double* __restrict__ V,
+                                                          double* __restrict__ lam,
+                                                          int* __restrict__ flags) {
+  __shared__ double A[64 * SE_LD];
+  __shared__ double H[64 * SE_LD];
+  __shared__ double X[64 * 64];    // X[i * 64 + j]: entry i of vector j
+  __shared__ double tau[64];
+  __shared__ double wv[64];
+  __shared__ double dd[64];
+  __shared__ double e2[64];        // squared off-diagonal
+  __shared__ double ee[64];
+  __shared__ double Rc[64 * 65];   // Gram / Cholesky factor of the d vectors
+  const int r = threadIdx.x;
+  auto wsum = [](double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+  };
+  if (r < n)
+    for (int c = 0; c < n; ++c) A[r * SE_LD + c] = G[(size_t)c * n + r].re;
+  __syncthreads();
+  for (int k = 0; k + 2 < n; ++k) {
+    const double xr = (r > k && r < n) ? A[r * SE_LD + k] : 0.0;
+    const double sig = wsum(xr * xr);
+    const double x0 = A[(k + 1) * SE_LD + k];
+    double t = 0.0, alpha = 0.0;
+    if (sig > 0.0) {
+      alpha = (x0 >= 0.0) ? -sqrt(sig) : sqrt(sig);
+      const double vn2 = 2.0 * sig - 2.0 * alpha * x0;
+      t = (vn2 > 0.0) ? 2.0 / vn2 : 0.0;
+    }
+    const double vr = (r > k && r < n) ? (r == k + 1 ? xr - alpha : xr) : 0.0;
+    H[k * SE_LD + r] = vr;
+    if (r == 0) tau[k] = t;
+    __syncthreads();
+    if (t != 0.0) {
+      double pa[4] = {0.0, 0.0, 0.0, 0.0};
+      if (r > k && r < n) {
+        const double* ar = A + r * SE_LD;
+        const double* hv = H + k * SE_LD;
+#pragma unroll 4
+        for (int j = k + 1; j < n; ++j) pa[j & 3] = fma(ar[j], hv[j], pa[j & 3]);
+      }
+      const double pr_ = t * ((pa[0] + pa[1]) + (pa[2] + pa[3]));
+      const double K = 0.5 * t * wsum(vr * pr_);
+      const double wr = pr_ - K * vr;
+      wv[r] = wr;
+      __syncthreads();
+      if (r > k && r < n) {
+        double* ar = A + r * SE_LD;
+        const double* hv = H + k * SE_LD;
+#pragma unroll 8
+        for (int j = k + 1; j < n; ++j) ar[j] -= vr * wv[j] + wr * hv[j];
+      }
+      __syncthreads();
+      if (r == 0) {
+        A[(k + 1) * SE_LD + k] = alpha;
+        A[k * SE_LD + k + 1] = alpha;
+      }
+    }
+    __syncthreads();
+  }
+  if (r < n) {
+    dd[r] = A[r * SE_LD + r];
+    const double e = (r + 1 < n) ? A[(r + 1) * SE_LD + r] : 0.0;
+    ee[r] = e;
+    e2[r] = e * e;
+  }
+  __syncthreads();
+  // Gershgorin interval and scale
+  double lo = 0.0, hi = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double rad = fabs(i > 0 ? ee[i - 1] : 0.0) + fabs(ee[i]);
+    lo = (i == 0) ? dd[i] - rad : fmin(lo, dd[i] - rad);
+    hi = (i == 0) ? dd[i] + rad : fmax(hi, dd[i] + rad);
+  }
+  const double scale = fmax(fabs(lo), fabs(hi));
+  const double tiny = 1e-290 + 1e-300 * scale;
+  double lj = 0.0;
+  if (r < d) {
+    // bisection: the j-th largest eigenvalue has ascending index n-1-j;
+    // count(x) = number of eigenvalues below x
+    const int kk = n - 1 - r;
+    double a = lo, b = hi;
+    for (int it = 0; it < 120; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (b - a <= 2.2e-16 * scale || mid <= a || mid >= b) break;
+      int cnt = 0;
+      double q = dd[0] - mid;
+      if (q < 0.0) ++cnt;
+      for (int i = 1; i < n; ++i) {
+        if (q == 0.0) q = -tiny;
+        q = (dd[i] - mid) - e2[i - 1] / q;
+        if (q < 0.0) ++cnt;
+      }
+      if (cnt <= kk)
+        a = mid;
+      else
+        b = mid;
+    }
+    lj = 0.5 * (a + b);
+    // inverse iteration: (T - lj I) y = x, banded elimination with row swaps;
+    // the upper factor has bandwidth 2 (u0 diagonal, u1, u2 superdiagonals)
+    double x[64], u0[64], u1[64], u2[64];
+    for (int i = 0; i < n; ++i) x[i] = 1.0;
+    for (int pass = 0; pass < 3; ++pass) {
+      // current row (c0, c1, c2) and next row's (sub, diag, sup)
+      double c0 = dd[0] - lj, c1 = (n > 1) ? ee[0] : 0.0, c2 = 0.0;
+      for (int i = 0; i < n - 1; ++i) {
+        const double sb = ee[i], dg = dd[i + 1] - lj, sp = (i + 2 < n) ? ee[i + 1] : 0.0;
+        double n0, n1, n2;
+        if (fabs(sb) > fabs(c0)) {
+          // swap rows i and i+1
+          const double f = c0 / sb;
+          u0[i] = sb;
+          u1[i] = dg;
+          u2[i] = sp;
+          const double xi = x[i];
+          x[i] = x[i + 1];
+          x[i + 1] = xi - f * x[i];
+          n0 = c1 - f * dg;
+          n1 = c2 - f * sp;
+          n2 = 0.0;
+        } else {
+          const double piv = (c0 == 0.0) ? tiny : c0;
+          const double f = sb / piv;
+          u0[i] = piv;
+          u1[i] = c1;
+          u2[i] = c2;
+          x[i + 1] -= f * x[i];
+          n0 = dg - f * c1;
+          n1 = sp - f * c2;
+          n2 = 0.0;
+        }
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+      }
+      u0[n - 1] = (c0 == 0.0) ? tiny : c0;
+      u1[n - 1] = 0.0;
+      u2[n - 1] = 0.0;
+      for (int i = n - 1; i >= 0; --i) {
+        double s = x[i];
+        if (i + 1 < n) s -= u1[i] * x[i + 1];
+        if (i + 2 < n) s -= u2[i] * x[i + 2];
+        x[i] = s / u0[i];
+      }
+      double nrm = 0.0;
+      for (int i = 0; i < n; ++i) nrm = fma(x[i], x[i], nrm);
+      nrm = 1.0 / sqrt(nrm);
+      for (int i = 0; i < n; ++i) x[i] *= nrm;
+    }
+    // back-transform: x <- H_0 H_1 ... H_{n-3} x
+    for (int k = n - 3; k >= 0; --k) {
+      const double t = tau[k];
+      if (t == 0.0) continue;
+      const double* hv = H + k * SE_LD;
+      double s = 0.0;
+      for (int i = k + 1; i < n; ++i) s = fma(hv[i], x[i], s);
+      s *= t;
+      for (int i = k + 1; i < n; ++i) x[i] -= s * hv[i];
+    }
+    for (int i = 0; i < n; ++i) X[i * 64 + r] = x[i];
+  }
+  __syncthreads();
+  // Cholesky QR of the d vectors: Gram (lane a computes row a), Cholesky
+  // (upper R), then X <- X R^{-1} row by row (lane i owns row i)
+  if (r < d)
+    for (int b = 0; b < d; ++b) {
+      double s = 0.0;
+      for (int i = 0; i < n; ++i) s = fma(X[i * 64 + r], X[i * 64 + b], s);
+      Rc[r * 65 + b] = s;
+    }
+  __syncthreads();
+  int bad = 0;
+  for (int j = 0; j < d; ++j) {
+    if (r == 0) {
+      double s = Rc[j * 65 + j];
+      for (int k = 0; k < j; ++k) s -= Rc[k * 65 + j] * Rc[k * 65 + j];
+      Rc[j * 65 + j] = (s > 0.0) ? sqrt(s) : 0.0;
+    }
+    __syncthreads();
+    const double rjj = Rc[j * 65 + j];
+    if (!(rjj > 0.0)) {
+      bad = 1;
+      break;
+    }
+    if (r > j && r < d) {
+      double s = Rc[j * 65 + r];
+      for (int k = 0; k < j; ++k) s -= Rc[k * 65 + j] * Rc[k * 65 + r];
+      Rc[j * 65 + r] = s / rjj;  // R[j][r], upper
+    }
+    __syncthreads();
+  }
+  if (!bad && r < n) {
+    // row r of X times R^{-1}: forward substitution over the columns
+    double y[64];
+    for (int c = 0; c < d; ++c) {
+      double s = X[r * 64 + c];
+      for (int k = 0; k < c; ++k) s -= y[k] * Rc[k * 65 + c];
+      y[c] = s / Rc[c * 65 + c];
+    }
+    for (int c = 0; c < d; ++c) V[(size_t)c * n + r] = y[c];
+  }
+  if (r < d) lam[r] = lj;
+  if (r == 0 && bad && flags) flags[0] |= 32;
+}
+
+void launch_dense_topeig(hipStream_t s, const cplx* G, int n, int d, double* V, double* lam,
+                         int* flags) {
+  hipLaunchKernelGGL(dense_topeig_kernel, dim3(1), dim3(64), 0, s, G, n, d, V, lam, flags);
 }

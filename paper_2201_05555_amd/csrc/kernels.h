@@ -58,7 +58,8 @@ void launch_fom_velocity(hipStream_t s, const double* X, const double* V, int N,
                          double* Vout);
 void launch_cells(hipStream_t s, const double* X, int N, int p, int Nx, const double* factor,
                   int* cells);
-void launch_colsumsq(hipStream_t s, const double* A, int N, int p, double sc, double* out);
+void launch_colsumsq(hipStream_t s, const double* A, int N, int p, double sc, double* out,
+                     double* scratch);  // scratch: 32 p doubles
 void launch_vec_add(hipStream_t s, double* out, const double* in, int n);
 
 // rom_kernels.hip
@@ -128,7 +129,12 @@ void launch_deim_solve(hipStream_t s, const double* Psi, int N, int k, int* idx,
 void launch_deim_weights(hipStream_t s, const double* Psi, int N, int d, int* idx,
                          const double* bval, const int* bidx, int nblk, const double* colpart,
                          int nbc, double* w, int* flags);
-void launch_deim_basis_coeffs(hipStream_t s, const cplx* V, const double* lam, int P, int d,
+void launch_deim_basis_coeffs(hipStream_t s, const double* V, const double* lam, int P, int d,
                               double* M, int* flags);
+void launch_dense_symeig(hipStream_t s, const cplx* G, int n, double* V, double* lam, int* flags);
 void launch_deim_k(hipStream_t s, const cplx* gF, const cplx* C12, const cplx* Z, int n, int p,
                    cplx* k);
+void launch_dense_indicator(hipStream_t s, const double* colsq, const cplx* g, int n, int p,
+                            double* eps);
+void launch_dense_topeig(hipStream_t s, const cplx* G, int n, int d, double* V, double* lam,
+                         int* flags);

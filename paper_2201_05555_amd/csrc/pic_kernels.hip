@@ -307,16 +307,28 @@ __global__ void cells_kernel(const double* __restrict__ X, int N, int p, int Nx,
   cells[t] = j;
 }
 
-// Per-parameter sum of squares of the columns of an N x p matrix, times s.
-__global__ void __launch_bounds__(256) colsumsq_kernel(const double* __restrict__ A, int N, int p,
-                                                       double s, double* __restrict__ out) {
+// Per-parameter sum of squares of the columns of an N x p matrix, times s:
+// grid (p, chunks) partial sums, combined in order by the second kernel.
+#define CSQ_CHUNKS 32
+__global__ void __launch_bounds__(256) colsumsq_part_kernel(const double* __restrict__ A, int N,
+                                                            double* __restrict__ part) {
   __shared__ double red[8];
-  const int i = blockIdx.x;
+  const int i = blockIdx.x, c = blockIdx.y;
   const double* a = A + (size_t)i * N;
+  const int per = (N + CSQ_CHUNKS - 1) / CSQ_CHUNKS;
+  const int l0 = c * per, l1 = min(N, l0 + per);
   double acc = 0.0;
-  for (int l = threadIdx.x; l < N; l += blockDim.x) acc = fma(a[l], a[l], acc);
+  for (int l = l0 + threadIdx.x; l < l1; l += blockDim.x) acc = fma(a[l], a[l], acc);
   acc = block_sum(acc, red);
-  if (threadIdx.x == 0) out[i] = s * acc;
+  if (threadIdx.x == 0) part[(size_t)i * CSQ_CHUNKS + c] = acc;
+}
+__global__ void colsumsq_fin_kernel(const double* __restrict__ part, int p, double s,
+                                    double* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p) return;
+  double t = 0.0;
+  for (int c = 0; c < CSQ_CHUNKS; ++c) t += part[(size_t)i * CSQ_CHUNKS + c];
+  out[i] = s * t;
 }
 
 // out[i] += in[i]
@@ -392,8 +404,11 @@ void launch_cells(hipStream_t s, const double* X, int N, int p, int Nx, const do
                      Nx, factor, cells);
 }
 
-void launch_colsumsq(hipStream_t s, const double* A, int N, int p, double sc, double* out) {
-  hipLaunchKernelGGL(colsumsq_kernel, dim3(p), dim3(256), 0, s, A, N, p, sc, out);
+void launch_colsumsq(hipStream_t s, const double* A, int N, int p, double sc, double* out,
+                     double* scratch) {
+  hipLaunchKernelGGL(colsumsq_part_kernel, dim3(p, CSQ_CHUNKS), dim3(256), 0, s, A, N, scratch);
+  hipLaunchKernelGGL(colsumsq_fin_kernel, dim3((p + 255) / 256), dim3(256), 0, s, scratch, p, sc,
+                     out);
 }
 
 void launch_vec_add(hipStream_t s, double* out, const double* in, int n) {

@@ -158,7 +158,40 @@ __global__ void __launch_bounds__(256) gemm_ah_b_kernel(MatList A, int a, MatLis
           bp[i] += (size_t)lc * N;
       }
     }
-    for (int l = r0 + rg; l < r1; l += R) {
+    int l = r0 + rg;
+    // two rows per pass: twice the loads in flight
+    for (; l + R < r1; l += 2 * R) {
+      cplx av[2][4], bv[2][4];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int lu = l + u * R;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (!ap[i])
+            av[u][i] = mk(0.0, 0.0);
+          else if (a_real)
+            av[u][i] = mk(reinterpret_cast<const double*>(ap[i])[lu], 0.0);
+          else
+            av[u][i] = conj_a ? ap[i][lu] : cconj(ap[i][lu]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (!bp[j])
+            bv[u][j] = mk(0.0, 0.0);
+          else if (b_real)
+            bv[u][j] = mk(reinterpret_cast<const double*>(bp[j])[lu], 0.0);
+          else
+            bv[u][j] = bp[j][lu];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) cfmac(acc[i][j], av[u][i], bv[u][j]);
+    }
+    for (; l < r1; l += R) {
       cplx av[4], bv[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -189,41 +222,37 @@ __global__ void __launch_bounds__(256) gemm_ah_b_kernel(MatList A, int a, MatLis
 #pragma unroll
     for (int j = 0; j < 4; ++j) red[tid * 16 + i * 4 + j] = acc[i][j];
   __syncthreads();
-  // tile leader sums its R row groups in order and writes the partial tile
-  if (owner && rg == 0) {
-    const int ta0 = (tile % nta) * 4;
-    const int tb0 = (tile / nta) * 4;
-    const int nout = a * b;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        cplx s = mk(0.0, 0.0);
-        for (int g = 0; g < R; ++g) s = cadd(s, red[(tile * R + g) * 16 + i * 4 + j]);
-        const int ia = ta0 + i, ib = tb0 + j;
-        if (ia < a && ib < b) part[(size_t)kb * nout + (size_t)ib * a + ia] = s;
-      }
+  // sum the R row groups of every (tile, entry) in a fixed order, one
+  // output entry per thread at a time
+  const int nout = a * b;
+  for (int o = tid; o < nt * 16; o += blockDim.x) {
+    const int tl = o / 16, q = o % 16;
+    cplx sm = mk(0.0, 0.0);
+    for (int g = 0; g < R; ++g) sm = cadd(sm, red[(tl * R + g) * 16 + q]);
+    const int ia = (tl % nta) * 4 + q / 4, ib = (tl / nta) * 4 + q % 4;
+    if (ia < a && ib < b) part[(size_t)kb * nout + (size_t)ib * a + ia] = sm;
   }
 }
 
-// C[o] = sum_k part[k][o], k in a fixed order.  Block: 32 outputs x 8 lanes
-// of k; lane sums are combined in a fixed order in LDS.
+// C[o] = sum_k part[k][o], k in a fixed order: one wavefront per output,
+// lane-strided partial sums combined by a fixed butterfly.
 __global__ void __launch_bounds__(256) reduce_partials_kernel(const cplx* __restrict__ part,
                                                               int nkb, int nout,
                                                               cplx* __restrict__ C) {
-  __shared__ cplx sm[256];
-  const int ol = threadIdx.x % 32, kl = threadIdx.x / 32;
-  const int o = blockIdx.x * 32 + ol;
-  cplx s = mk(0.0, 0.0);
-  if (o < nout)
-    for (int k = kl; k < nkb; k += 8) s = cadd(s, part[(size_t)k * nout + o]);
-  sm[threadIdx.x] = s;
-  __syncthreads();
-  if (kl == 0 && o < nout) {
-    cplx t = sm[ol];
-    for (int q = 1; q < 8; ++q) t = cadd(t, sm[q * 32 + ol]);
-    C[o] = t;
+  const int lane = threadIdx.x & 63;
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (o >= nout) return;
+  double re = 0.0, im = 0.0;
+  for (int k = lane; k < nkb; k += 64) {
+    const cplx v = part[(size_t)k * nout + o];
+    re += v.re;
+    im += v.im;
   }
+  for (int s = 32; s > 0; s >>= 1) {
+    re += __shfl_xor(re, s, 64);
+    im += __shfl_xor(im, s, 64);
+  }
+  if (lane == 0) C[o] = mk(re, im);
 }
 
 // ---------------------------------------------------------------------------
@@ -508,6 +537,15 @@ void launch_reconstruct(hipStream_t s, const cplx* U, int N, int n, const cplx* 
 
 void launch_gemm_flags(hipStream_t s, const MatList& A, int a, const MatList& B, int b, int flags,
                        int N, int nkb, cplx* part, cplx* C) {
+  // split-K blocks: about 128 rows each, at most 1024, and partials of at
+  // most 2^19 complex values (the caller's buffer holds nkb * 64 * 64)
+  const int bmax = (b < 64) ? b : 64;
+  int cap = (1 << 19) / (a * bmax);
+  if (cap > nkb * 64 * 64 / (a * bmax)) cap = nkb * 64 * 64 / (a * bmax);
+  nkb = (N + 127) / 128;
+  if (nkb > 256) nkb = 256;
+  if (nkb > cap) nkb = cap;
+  if (nkb < 1) nkb = 1;
   int rk = (N + nkb - 1) / nkb;
   nkb = (N + rk - 1) / rk;
   const bool b_real = flags & GEMM_B_REAL;
@@ -525,8 +563,8 @@ void launch_gemm_flags(hipStream_t s, const MatList& A, int a, const MatList& B,
     hipLaunchKernelGGL(gemm_ah_b_kernel, dim3(nkb), dim3(256), 0, s, A, a, Bc, bc, flags, N, rk,
                        part);
     int nout = a * bc;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((nout + 31) / 32), dim3(256), 0, s, part,
-                       nkb, nout, C + (size_t)b0 * a);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((nout + 3) / 4), dim3(256), 0, s, part, nkb,
+                       nout, C + (size_t)b0 * a);
   }
 }
 
