@@ -704,25 +704,24 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z) {
   hipStream_t s = r.s;
   const int N = r.N, n = r.n;
   const int slot = r.win_count % r.nslots;
-  launch_snapshot(s, U, N, n, Z, r.sub, r.psub, r.Nx, r.b.factor, r.b.phi,
-                  r.Ywin + (size_t)slot * r.psub * N);
+  double* Ys = r.Ywin + (size_t)slot * r.psub * N;
+  launch_snapshot(s, U, N, n, Z, r.sub, r.psub, r.Nx, r.b.factor, r.b.phi, Ys);
   r.win_count++;
-  r.deim_on = r.win_count >= r.nslots;
-  if (!r.deim_on) return;
   Timer t(FAM_DENSE, s);
   const int P = r.psub * r.nslots;
+  std::vector<const double*> slots(r.nslots);
+  for (int q = 0; q < r.nslots; ++q) slots[q] = r.Ywin + (size_t)q * r.psub * N;
+  // the Gram Y^T Y (real, P x P) is kept across steps: only the row and
+  // column block of the overwritten slot changes
+  launch_gram_block_real(s, Ys, slots.data(), r.nslots, r.psub, N, slot * r.psub,
+                         r.nkb * 64 * 64 * 2, reinterpret_cast<double*>(r.gemm_part),
+                         reinterpret_cast<double*>(r.YG));
+  r.deim_on = r.win_count >= r.nslots;
+  if (!r.deim_on) return;
   const int d = (2 * n < P) ? 2 * n : P;
   r.d_cur = d;
-  MatList Yl{};
-  std::vector<const double*> slots(r.nslots);
-  for (int q = 0; q < r.nslots; ++q) {
-    slots[q] = r.Ywin + (size_t)q * r.psub * N;
-    Yl.ptr[q] = reinterpret_cast<const cplx*>(slots[q]);
-    Yl.cols[q] = r.psub;
-  }
-  Yl.count = r.nslots;
-  launch_gemm_flags(s, Yl, P, Yl, P, GEMM_A_REAL | GEMM_B_REAL, N, r.nkb, r.gemm_part, r.YG);
-  launch_dense_topeig(s, r.YG, P, d, reinterpret_cast<double*>(r.YV), r.ylam, r.flags);
+  launch_dense_topeig(s, reinterpret_cast<const double*>(r.YG), P, d,
+                      reinterpret_cast<double*>(r.YV), r.ylam, r.flags);
   launch_deim_basis_coeffs(s, reinterpret_cast<const double*>(r.YV), r.ylam, P, d, r.Mdeim,
                            r.flags);
   launch_rowgemm_real(s, slots.data(), r.nslots, r.psub, N, r.Mdeim, P, d, r.Psi);

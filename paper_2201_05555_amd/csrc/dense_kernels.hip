@@ -1415,7 +1415,7 @@ void launch_dense_indicator(hipStream_t s, const double* colsq, const cplx* g, i
 // through the stored reflectors; a Cholesky QR pass orthonormalises the d
 // vectors.  Output: lam (d, decreasing) and V (n x d, column-major).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) dense_topeig_kernel(const cplx* __restrict__ G, int n, int d,
+__global__ void __launch_bounds__(64) dense_topeig_kernel(const double* __restrict__ G, int n, int d,
                                                           double* __restrict__ V,
                                                           double* __restrict__ lam,
                                                           int* __restrict__ flags) {
@@ -1429,12 +1429,19 @@ __global__ void __launch_bounds__(64) dense_topeig_kernel(const cplx* __restrict
   __shared__ double ee[64];
   __shared__ double Rc[64 * 65];   // Gram / Cholesky factor of the d vectors
   const int r = threadIdx.x;
+#ifdef SYMROM_TOPEIG_TIMING
+  unsigned long long tsv[6];
+  tsv[0] = wall_clock64();
+#define TS(k) tsv[k] = wall_clock64()
+#else
+#define TS(k)
+#endif
   auto wsum = [](double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
   };
   if (r < n)
-    for (int c = 0; c < n; ++c) A[r * SE_LD + c] = G[(size_t)c * n + r].re;
+    for (int c = 0; c < n; ++c) A[r * SE_LD + c] = G[(size_t)c * n + r];
   __syncthreads();
   for (int k = 0; k + 2 < n; ++k) {
     const double xr = (r > k && r < n) ? A[r * SE_LD + k] : 0.0;
@@ -1484,6 +1491,7 @@ __global__ void __launch_bounds__(64) dense_topeig_kernel(const cplx* __restrict
     e2[r] = e * e;
   }
   __syncthreads();
+  TS(1);
   // Gershgorin interval and scale
   double lo = 0.0, hi = 0.0;
   for (int i = 0; i < n; ++i) {
@@ -1493,93 +1501,129 @@ __global__ void __launch_bounds__(64) dense_topeig_kernel(const cplx* __restrict
   }
   const double scale = fmax(fabs(lo), fabs(hi));
   const double tiny = 1e-290 + 1e-300 * scale;
-  double lj = 0.0;
-  if (r < d) {
-    // bisection: the j-th largest eigenvalue has ascending index n-1-j;
-    // count(x) = number of eigenvalues below x
-    const int kk = n - 1 - r;
-    double a = lo, b = hi;
-    for (int it = 0; it < 120; ++it) {
-      const double mid = 0.5 * (a + b);
-      if (b - a <= 2.2e-16 * scale || mid <= a || mid >= b) break;
-      int cnt = 0;
-      double q = dd[0] - mid;
+  // multisection: ms lanes per eigenvalue; lane (g, s) evaluates the Sturm
+  // count at the s-th of ms interior points of eigenvalue g's bracket, and
+  // the group narrows the bracket to the two neighbouring points
+  __shared__ double msx[64];
+  __shared__ int msc[64];
+  const int ms = (d > 0) ? max(1, 64 / d) : 1;
+  const int grp = r / ms, sub = r % ms;
+  const bool gact = grp < d;
+  const int kk = n - 1 - (gact ? grp : 0);
+  double a = lo, b = hi;
+  for (int it = 0; it < 120; ++it) {
+    const bool more = gact && (b - a > 2.2e-16 * scale);
+    // every group runs the same number of rounds; finished groups idle
+    const int any = __any(more);
+    if (!any) break;
+    double x = a + (b - a) * (double)(sub + 1) / (double)(ms + 1);
+    int cnt = 0;
+    if (more) {
+      double q = dd[0] - x;
       if (q < 0.0) ++cnt;
       for (int i = 1; i < n; ++i) {
         if (q == 0.0) q = -tiny;
-        q = (dd[i] - mid) - e2[i - 1] / q;
+        q = (dd[i] - x) - e2[i - 1] / q;
         if (q < 0.0) ++cnt;
       }
-      if (cnt <= kk)
-        a = mid;
-      else
-        b = mid;
     }
-    lj = 0.5 * (a + b);
-    // inverse iteration: (T - lj I) y = x, banded elimination with row swaps;
-    // the upper factor has bandwidth 2 (u0 diagonal, u1, u2 superdiagonals)
-    double x[64], u0[64], u1[64], u2[64];
-    for (int i = 0; i < n; ++i) x[i] = 1.0;
+    msx[r] = x;
+    msc[r] = cnt;
+    __syncthreads();
+    if (more) {
+      double na = a, nb = b;
+      for (int s2 = 0; s2 < ms; ++s2) {
+        const double xs = msx[grp * ms + s2];
+        if (!(xs > a && xs < b)) continue;
+        if (msc[grp * ms + s2] <= kk)
+          na = fmax(na, xs);
+        else
+          nb = fmin(nb, xs);
+      }
+      if (na == a && nb == b) {
+        // no interior point was representable: the bracket is converged
+        b = a;
+      } else {
+        a = na;
+        b = nb;
+      }
+    }
+    __syncthreads();
+  }
+  const double lj = 0.5 * (a + b);
+  // group leaders hold the eigenvalue of their group
+  __shared__ double lamg[64];
+  if (gact && sub == 0) lamg[grp] = lj;
+  __syncthreads();
+  TS(2);
+  if (r < d) {
+    const double lv = lamg[r];
+    // inverse iteration: (T - lv I) y = x, banded elimination with row swaps;
+    // the upper factor has bandwidth 2 (u0 diagonal, u1, u2 superdiagonals);
+    // the vector lives in X[:, r] (LDS)
+    double u0[64], u1[64], u2[64];
+    for (int i = 0; i < n; ++i) X[i * 64 + r] = 1.0;
     for (int pass = 0; pass < 3; ++pass) {
-      // current row (c0, c1, c2) and next row's (sub, diag, sup)
-      double c0 = dd[0] - lj, c1 = (n > 1) ? ee[0] : 0.0, c2 = 0.0;
+      double c0 = dd[0] - lv, c1 = (n > 1) ? ee[0] : 0.0, c2 = 0.0;
       for (int i = 0; i < n - 1; ++i) {
-        const double sb = ee[i], dg = dd[i + 1] - lj, sp = (i + 2 < n) ? ee[i + 1] : 0.0;
-        double n0, n1, n2;
+        const double sb = ee[i], dg = dd[i + 1] - lv, sp = (i + 2 < n) ? ee[i + 1] : 0.0;
+        double n0, n1;
         if (fabs(sb) > fabs(c0)) {
-          // swap rows i and i+1
           const double f = c0 / sb;
           u0[i] = sb;
           u1[i] = dg;
           u2[i] = sp;
-          const double xi = x[i];
-          x[i] = x[i + 1];
-          x[i + 1] = xi - f * x[i];
+          const double xi = X[i * 64 + r];
+          const double xn = X[(i + 1) * 64 + r];
+          X[i * 64 + r] = xn;
+          X[(i + 1) * 64 + r] = xi - f * xn;
           n0 = c1 - f * dg;
           n1 = c2 - f * sp;
-          n2 = 0.0;
         } else {
           const double piv = (c0 == 0.0) ? tiny : c0;
           const double f = sb / piv;
           u0[i] = piv;
           u1[i] = c1;
           u2[i] = c2;
-          x[i + 1] -= f * x[i];
+          X[(i + 1) * 64 + r] -= f * X[i * 64 + r];
           n0 = dg - f * c1;
           n1 = sp - f * c2;
-          n2 = 0.0;
         }
         c0 = n0;
         c1 = n1;
-        c2 = n2;
+        c2 = 0.0;
       }
       u0[n - 1] = (c0 == 0.0) ? tiny : c0;
-      u1[n - 1] = 0.0;
-      u2[n - 1] = 0.0;
+      double x1 = 0.0, x2 = 0.0, nrm = 0.0;  // x_{i+1}, x_{i+2}
       for (int i = n - 1; i >= 0; --i) {
-        double s = x[i];
-        if (i + 1 < n) s -= u1[i] * x[i + 1];
-        if (i + 2 < n) s -= u2[i] * x[i + 2];
-        x[i] = s / u0[i];
+        double s = X[i * 64 + r];
+        if (i + 1 < n) s -= u1[i] * x1;
+        if (i + 2 < n) s -= u2[i] * x2;
+        const double xi = s / u0[i];
+        X[i * 64 + r] = xi;
+        nrm = fma(xi, xi, nrm);
+        x2 = x1;
+        x1 = xi;
       }
-      double nrm = 0.0;
-      for (int i = 0; i < n; ++i) nrm = fma(x[i], x[i], nrm);
       nrm = 1.0 / sqrt(nrm);
-      for (int i = 0; i < n; ++i) x[i] *= nrm;
+      for (int i = 0; i < n; ++i) X[i * 64 + r] *= nrm;
     }
+    TS(3);
     // back-transform: x <- H_0 H_1 ... H_{n-3} x
     for (int k = n - 3; k >= 0; --k) {
       const double t = tau[k];
       if (t == 0.0) continue;
       const double* hv = H + k * SE_LD;
-      double s = 0.0;
-      for (int i = k + 1; i < n; ++i) s = fma(hv[i], x[i], s);
-      s *= t;
-      for (int i = k + 1; i < n; ++i) x[i] -= s * hv[i];
+      double sa[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int i = k + 1; i < n; ++i) sa[i & 3] = fma(hv[i], X[i * 64 + r], sa[i & 3]);
+      const double s = t * ((sa[0] + sa[1]) + (sa[2] + sa[3]));
+#pragma unroll 4
+      for (int i = k + 1; i < n; ++i) X[i * 64 + r] -= s * hv[i];
     }
-    for (int i = 0; i < n; ++i) X[i * 64 + r] = x[i];
   }
   __syncthreads();
+  TS(4);
   // Cholesky QR of the d vectors: Gram (lane a computes row a), Cholesky
   // (upper R), then X <- X R^{-1} row by row (lane i owns row i)
   if (r < d)
@@ -1619,11 +1663,17 @@ __global__ void __launch_bounds__(64) dense_topeig_kernel(const cplx* __restrict
     }
     for (int c = 0; c < d; ++c) V[(size_t)c * n + r] = y[c];
   }
-  if (r < d) lam[r] = lj;
+  if (r < d) lam[r] = lamg[r];
   if (r == 0 && bad && flags) flags[0] |= 32;
+#ifdef SYMROM_TOPEIG_TIMING
+  TS(5);
+  if (r == 0 && flags)
+    for (int k = 0; k < 6; ++k) flags[8 + k] = (int)(tsv[k] - tsv[0]);
+#endif
+#undef TS
 }
 
-void launch_dense_topeig(hipStream_t s, const cplx* G, int n, int d, double* V, double* lam,
+void launch_dense_topeig(hipStream_t s, const double* G, int n, int d, double* V, double* lam,
                          int* flags) {
   hipLaunchKernelGGL(dense_topeig_kernel, dim3(1), dim3(64), 0, s, G, n, d, V, lam, flags);
 }

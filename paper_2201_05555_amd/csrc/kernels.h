@@ -136,5 +136,8 @@ void launch_deim_k(hipStream_t s, const cplx* gF, const cplx* C12, const cplx* Z
                    cplx* k);
 void launch_dense_indicator(hipStream_t s, const double* colsq, const cplx* g, int n, int p,
                             double* eps);
-void launch_dense_topeig(hipStream_t s, const cplx* G, int n, int d, double* V, double* lam,
+void launch_dense_topeig(hipStream_t s, const double* G, int n, int d, double* V, double* lam,
                          int* flags);
+void launch_gram_block_real(hipStream_t s, const double* Ynew, const double* const* slots,
+                            int nslots, int psub, int N, int r0, int nkb_cap, double* part,
+                            double* S);

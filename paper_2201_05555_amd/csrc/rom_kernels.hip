@@ -645,3 +645,120 @@ void launch_colsum_partial(hipStream_t s, const double* Psi, int N, int d, int n
                            double* part) {
   hipLaunchKernelGGL(colsum_partial_kernel, dim3(nblk), dim3(256), 0, s, Psi, N, d, part);
 }
+
+// ---------------------------------------------------------------------------
+// Real product C = A^T B (A: N x a, B: N x b, both real column-major lists,
+// a, b <= 64), split over row blocks like gemm_ah_b_kernel.  Output partials
+// part[kb][ib * a + ia].
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) gemm_real_tn_kernel(RealList A, int ka, int a, RealList B,
+                                                           int kbcols, int b, int N, int rk,
+                                                           double* __restrict__ part) {
+  __shared__ double red[256 * 16];
+  const int kb = blockIdx.x;
+  const int r0 = kb * rk;
+  const int r1 = min(N, r0 + rk);
+  const int nta = (a + 3) / 4, ntb = (b + 3) / 4, nt = nta * ntb;
+  const int R = max(1, 256 / nt);
+  const int tid = threadIdx.x;
+  const int tile = tid / R, rg = tid % R;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  if (tile < nt) {
+    const int ta0 = (tile % nta) * 4, tb0 = (tile / nta) * 4;
+    const double* ap[4];
+    const double* bp[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int ca = ta0 + i, cb = tb0 + i;
+      ap[i] = (ca < a) ? A.ptr[ca / ka] + (size_t)(ca % ka) * N : nullptr;
+      bp[i] = (cb < b) ? B.ptr[cb / kbcols] + (size_t)(cb % kbcols) * N : nullptr;
+    }
+    int l = r0 + rg;
+    for (; l + R < r1; l += 2 * R) {
+      double av[2][4], bv[2][4];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          av[u][i] = ap[i] ? ap[i][l + u * R] : 0.0;
+          bv[u][i] = bp[i] ? bp[i][l + u * R] : 0.0;
+        }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[u][i], bv[u][j], acc[i][j]);
+    }
+    for (; l < r1; l += R) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        av[i] = ap[i] ? ap[i][l] : 0.0;
+        bv[i] = bp[i] ? bp[i][l] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[tid * 16 + i * 4 + j] = acc[i][j];
+  __syncthreads();
+  const int nout = a * b;
+  for (int o = tid; o < nt * 16; o += blockDim.x) {
+    const int tl = o / 16, q = o % 16;
+    double sm = 0.0;
+    for (int g = 0; g < R; ++g) sm += red[(tl * R + g) * 16 + q];
+    const int ia = (tl % nta) * 4 + q / 4, ib = (tl / nta) * 4 + q % 4;
+    if (ia < a && ib < b) part[(size_t)kb * nout + (size_t)ib * a + ia] = sm;
+  }
+}
+
+// Sum the partials of a real product and scatter the a x b result into the
+// symmetric P x P matrix S at rows r0.. (and the transpose at columns r0..).
+__global__ void __launch_bounds__(256) reduce_gram_block_kernel(const double* __restrict__ part,
+                                                                int nkb, int a, int b, int P,
+                                                                int r0, double* __restrict__ S) {
+  const int lane = threadIdx.x & 63;
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int nout = a * b;
+  if (o >= nout) return;
+  double s = 0.0;
+  for (int k = lane; k < nkb; k += 64) s += part[(size_t)k * nout + o];
+  for (int w = 32; w > 0; w >>= 1) s += __shfl_xor(s, w, 64);
+  if (lane == 0) {
+    const int ia = o % a, ib = o / a;
+    S[(size_t)ib * P + r0 + ia] = s;   // row r0+ia, column ib
+    S[(size_t)(r0 + ia) * P + ib] = s; // transpose
+  }
+}
+
+void launch_gram_block_real(hipStream_t s, const double* Ynew, const double* const* slots,
+                            int nslots, int psub, int N, int r0, int nkb_cap, double* part,
+                            double* S) {
+  RealList A{}, B{};
+  A.ptr[0] = Ynew;
+  A.count = 1;
+  for (int q = 0; q < nslots; ++q) B.ptr[q] = slots[q];
+  B.count = nslots;
+  const int a = psub, b = psub * nslots;
+  int nkb = (N + 127) / 128;
+  if (nkb > 256) nkb = 256;
+  const int cap = nkb_cap / (a * b);
+  if (nkb > cap) nkb = cap;
+  if (nkb < 1) nkb = 1;
+  const int rk = (N + nkb - 1) / nkb;
+  nkb = (N + rk - 1) / rk;
+  hipLaunchKernelGGL(gemm_real_tn_kernel, dim3(nkb), dim3(256), 0, s, A, psub, a, B, psub, b, N, rk,
+                     part);
+  hipLaunchKernelGGL(reduce_gram_block_kernel, dim3((a * b + 3) / 4), dim3(256), 0, s, part, nkb, a,
+                     b, b, r0, S);
+}
