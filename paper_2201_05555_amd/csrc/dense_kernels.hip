@@ -1408,26 +1408,73 @@ void launch_dense_indicator(hipStream_t s, const double* colsq, const cplx* g, i
 
 // ---------------------------------------------------------------------------
 // Leading eigenpairs of a real symmetric matrix (n <= 64, d <= n) in one
-// wavefront: Householder tridiagonalisation (as dense_symeig_kernel), then
-// lane j finds the j-th largest eigenvalue of the tridiagonal T by bisection
-// on Sturm counts, its eigenvector by inverse iteration (banded Gaussian
-// elimination with partial pivoting on T - lambda I), and back-transforms it
-// through the stored reflectors; a Cholesky QR pass orthonormalises the d
-// vectors.  Output: lam (d, decreasing) and V (n x d, column-major).
+// wavefront.  Lane r keeps row r of the matrix in registers through a
+// Householder tridiagonalisation (the reflectors go to LDS); the d largest
+// eigenvalues of the tridiagonal T are found by multisection on Sturm counts
+// (a group of lanes per eigenvalue, several points per lane); lane j then
+// computes eigenvector j by inverse iteration (banded Gaussian elimination
+// with partial pivoting on T - lambda_j I, vector in registers, factors in
+// LDS), back-transforms it through the reflectors, and a Cholesky QR pass
+// orthonormalises the d vectors.  Output: lam (d, decreasing) and V (n x d,
+// column-major); bit 32 of flags[0] is set if the vectors are rank deficient.
 // ---------------------------------------------------------------------------
+namespace {
+constexpr int TE_M = 64;   // largest order
+constexpr int TE_NP = 1;   // Sturm-count points per lane per multisection round
+
+// 1/x to full double precision for finite x with |x| >= 1e-290: the hardware
+// estimate refined by two Newton steps
+__device__ __forceinline__ double te_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// value of v in lane `lane` (uniform), as a scalar
+__device__ __forceinline__ double te_lane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// one 32-bit DPP move (zero where the source lane is out of range or the
+// row is masked off)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double te_dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over the 64 lanes of a wavefront, returned in every lane: row shifts
+// accumulate each row of 16 into its last lane, the row broadcasts carry
+// rows 0..2 into lane 63
+__device__ __forceinline__ double te_wave_sum(double v) {
+  v += te_dpp<0x111, 0xf>(v);   // row_shr:1
+  v += te_dpp<0x112, 0xf>(v);   // row_shr:2
+  v += te_dpp<0x114, 0xf>(v);   // row_shr:4
+  v += te_dpp<0x118, 0xf>(v);   // row_shr:8
+  v += te_dpp<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += te_dpp<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return te_lane(v, 63);
+}
+}  // namespace
+
 __global__ void __launch_bounds__(64) dense_topeig_kernel(const double* __restrict__ G, int n, int d,
                                                           double* __restrict__ V,
                                                           double* __restrict__ lam,
                                                           int* __restrict__ flags) {
-  __shared__ double A[64 * SE_LD];
-  __shared__ double H[64 * SE_LD];
-  __shared__ double X[64 * 64];    // X[i * 64 + j]: entry i of vector j
-  __shared__ double tau[64];
-  __shared__ double wv[64];
-  __shared__ double dd[64];
-  __shared__ double e2[64];        // squared off-diagonal
-  __shared__ double ee[64];
-  __shared__ double Rc[64 * 65];   // Gram / Cholesky factor of the d vectors
+  constexpr int M = TE_M;
+  __shared__ double H[M * M];          // H[k * M + i]: reflector k (zero for i <= k)
+  __shared__ double W[3 * M * M];      // elimination factors; later vectors and Gram
+  __shared__ double bc[M];             // broadcast of w in the two-sided update
+  __shared__ double tau[M], dd[M], ee[M], e2[M], lamg[M];
+  __shared__ double msx[M * TE_NP];
+  __shared__ int msc[M * TE_NP];
   const int r = threadIdx.x;
 #ifdef SYMROM_TOPEIG_TIMING
   unsigned long long tsv[6];
@@ -1436,232 +1483,302 @@ __global__ void __launch_bounds__(64) dense_topeig_kernel(const double* __restri
 #else
 #define TS(k)
 #endif
-  auto wsum = [](double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-  };
-  if (r < n)
-    for (int c = 0; c < n; ++c) A[r * SE_LD + c] = G[(size_t)c * n + r];
-  __syncthreads();
+  // ---- tridiagonalisation, row r of A in registers ----
+  double a[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) a[j] = (r < n && j < n) ? G[(size_t)j * n + r] : 0.0;
   for (int k = 0; k + 2 < n; ++k) {
-    const double xr = (r > k && r < n) ? A[r * SE_LD + k] : 0.0;
-    const double sig = wsum(xr * xr);
-    const double x0 = A[(k + 1) * SE_LD + k];
-    double t = 0.0, alpha = 0.0;
+    // xr = A[r][k], the column below the diagonal for r > k
+    double xr = 0.0;
+#pragma unroll
+    for (int jc = 0; jc < M; jc += 16) {
+      if ((k >> 4) == (jc >> 4)) {
+#pragma unroll
+        for (int j = jc; j < jc + 16; ++j) xr = (j == k) ? a[j] : xr;
+      }
+    }
+    if (!(r > k)) xr = 0.0;
+    const double sig = te_wave_sum(xr * xr);
+    const double x0 = te_lane(xr, k + 1);
+    double t = 0.0, alpha = x0;
     if (sig > 0.0) {
-      alpha = (x0 >= 0.0) ? -sqrt(sig) : sqrt(sig);
-      const double vn2 = 2.0 * sig - 2.0 * alpha * x0;
-      t = (vn2 > 0.0) ? 2.0 / vn2 : 0.0;
+      const double al = (x0 >= 0.0) ? -sqrt(sig) : sqrt(sig);
+      const double vn2 = 2.0 * sig - 2.0 * al * x0;
+      if (vn2 > 0.0) {
+        t = 2.0 / vn2;
+        alpha = al;
+      }
     }
     const double vr = (r > k && r < n) ? (r == k + 1 ? xr - alpha : xr) : 0.0;
-    H[k * SE_LD + r] = vr;
-    if (r == 0) tau[k] = t;
+    H[k * M + r] = vr;
+    if (r == 0) {
+      tau[k] = t;
+      ee[k] = alpha;
+    }
     __syncthreads();
     if (t != 0.0) {
-      double pa[4] = {0.0, 0.0, 0.0, 0.0};
-      if (r > k && r < n) {
-        const double* ar = A + r * SE_LD;
-        const double* hv = H + k * SE_LD;
-#pragma unroll 4
-        for (int j = k + 1; j < n; ++j) pa[j & 3] = fma(ar[j], hv[j], pa[j & 3]);
+      const double* hk = H + k * M;
+      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+#pragma unroll
+      for (int jc = 0; jc < M; jc += 16) {
+        if (k < jc + 15) {
+#pragma unroll
+          for (int j = jc; j < jc + 16; j += 4) {
+            p0 = fma(a[j], hk[j], p0);
+            p1 = fma(a[j + 1], hk[j + 1], p1);
+            p2 = fma(a[j + 2], hk[j + 2], p2);
+            p3 = fma(a[j + 3], hk[j + 3], p3);
+          }
+        }
       }
-      const double pr_ = t * ((pa[0] + pa[1]) + (pa[2] + pa[3]));
-      const double K = 0.5 * t * wsum(vr * pr_);
-      const double wr = pr_ - K * vr;
-      wv[r] = wr;
+      const double pr = (r > k && r < n) ? t * ((p0 + p1) + (p2 + p3)) : 0.0;
+      const double kv = te_wave_sum(vr * pr);
+      const double wr = pr - 0.5 * t * kv * vr;   // zero for r <= k
+      bc[r] = wr;
       __syncthreads();
-      if (r > k && r < n) {
-        double* ar = A + r * SE_LD;
-        const double* hv = H + k * SE_LD;
-#pragma unroll 8
-        for (int j = k + 1; j < n; ++j) ar[j] -= vr * wv[j] + wr * hv[j];
-      }
-      __syncthreads();
-      if (r == 0) {
-        A[(k + 1) * SE_LD + k] = alpha;
-        A[k * SE_LD + k + 1] = alpha;
+#pragma unroll
+      for (int jc = 0; jc < M; jc += 16) {
+        if (k < jc + 15) {
+#pragma unroll
+          for (int j = jc; j < jc + 16; ++j) a[j] -= vr * bc[j] + wr * hk[j];
+        }
       }
     }
     __syncthreads();
   }
-  if (r < n) {
-    dd[r] = A[r * SE_LD + r];
-    const double e = (r + 1 < n) ? A[(r + 1) * SE_LD + r] : 0.0;
-    ee[r] = e;
-    e2[r] = e * e;
+  {
+    // diagonal and last subdiagonal entry
+    double dv = 0.0, sv = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      dv = (j == r) ? a[j] : dv;
+      sv = (j + 1 == r) ? a[j] : sv;
+    }
+    if (r < n) dd[r] = dv;
+    if (n >= 2 && r == n - 1) ee[n - 2] = sv;
+    if (r == n - 1 || r >= n) ee[r] = 0.0;
+    __syncthreads();
+    if (r < n) e2[r] = ee[r] * ee[r];
+    __syncthreads();
   }
-  __syncthreads();
   TS(1);
-  // Gershgorin interval and scale
-  double lo = 0.0, hi = 0.0;
+  // ---- d largest eigenvalues by multisection ----
+  double lo = 0.0, hi = 0.0, e2max = 0.0;
   for (int i = 0; i < n; ++i) {
     const double rad = fabs(i > 0 ? ee[i - 1] : 0.0) + fabs(ee[i]);
     lo = (i == 0) ? dd[i] - rad : fmin(lo, dd[i] - rad);
     hi = (i == 0) ? dd[i] + rad : fmax(hi, dd[i] + rad);
+    e2max = fmax(e2max, e2[i]);
   }
   const double scale = fmax(fabs(lo), fabs(hi));
-  const double tiny = 1e-290 + 1e-300 * scale;
-  // multisection: ms lanes per eigenvalue; lane (g, s) evaluates the Sturm
-  // count at the s-th of ms interior points of eigenvalue g's bracket, and
-  // the group narrows the bracket to the two neighbouring points
-  __shared__ double msx[64];
-  __shared__ int msc[64];
-  const int ms = (d > 0) ? max(1, 64 / d) : 1;
+  // lane i holds d_i, e_i and e_i^2 (read back by readlane in the recurrences)
+  const double ddl = (r < n) ? dd[r] : 0.0, eel = ee[r], e2l = (r < n) ? e2[r] : 0.0;
+  // pivots below pivmin are replaced by -pivmin: e2 / pivmin stays finite
+  const double pivmin = 1e-290 * fmax(1.0, e2max);
+  const int ms = (d > 0) ? max(1, M / d) : 1;     // lanes per eigenvalue
+  const int nps = ms * TE_NP;                    // points per eigenvalue per round
   const int grp = r / ms, sub = r % ms;
   const bool gact = grp < d;
-  const int kk = n - 1 - (gact ? grp : 0);
-  double a = lo, b = hi;
-  for (int it = 0; it < 120; ++it) {
-    const bool more = gact && (b - a > 2.2e-16 * scale);
-    // every group runs the same number of rounds; finished groups idle
-    const int any = __any(more);
-    if (!any) break;
-    double x = a + (b - a) * (double)(sub + 1) / (double)(ms + 1);
-    int cnt = 0;
-    if (more) {
-      double q = dd[0] - x;
-      if (q < 0.0) ++cnt;
-      for (int i = 1; i < n; ++i) {
-        if (q == 0.0) q = -tiny;
-        q = (dd[i] - x) - e2[i - 1] / q;
-        if (q < 0.0) ++cnt;
+  const int kk = n - 1 - (gact ? grp : 0);       // eigenvalue kk in increasing order
+  double a0 = lo, b0 = hi;
+  for (int it = 0; it < 200; ++it) {
+    const bool more = gact && (b0 - a0 > 2.2e-16 * scale);
+    if (!__any(more)) break;
+    double x[TE_NP], q[TE_NP];
+    int cnt[TE_NP];
+#pragma unroll
+    for (int s = 0; s < TE_NP; ++s) {
+      x[s] = a0 + (b0 - a0) * (double)(sub * TE_NP + s + 1) / (double)(nps + 1);
+      q[s] = dd[0] - x[s];
+      cnt[s] = 0;
+    }
+    // every lane runs the recurrence (uniform control flow around readlane)
+#pragma unroll
+    for (int s = 0; s < TE_NP; ++s) {
+      if (fabs(q[s]) < pivmin) q[s] = -pivmin;
+      cnt[s] += (q[s] < 0.0);
+    }
+#pragma unroll
+    for (int i = 1; i < M; ++i) {
+      if (i < n) {
+        const double di = te_lane(ddl, i), ei = te_lane(e2l, i - 1);
+#pragma unroll
+        for (int s = 0; s < TE_NP; ++s) {
+          q[s] = (di - x[s]) - ei * te_rcp(q[s]);
+          if (fabs(q[s]) < pivmin) q[s] = -pivmin;
+          cnt[s] += (q[s] < 0.0);
+        }
       }
     }
-    msx[r] = x;
-    msc[r] = cnt;
+#pragma unroll
+    for (int s = 0; s < TE_NP; ++s) {
+      msx[r * TE_NP + s] = x[s];
+      msc[r * TE_NP + s] = cnt[s];
+    }
     __syncthreads();
     if (more) {
-      double na = a, nb = b;
-      for (int s2 = 0; s2 < ms; ++s2) {
-        const double xs = msx[grp * ms + s2];
-        if (!(xs > a && xs < b)) continue;
-        if (msc[grp * ms + s2] <= kk)
+      double na = a0, nb = b0;
+      const int base = grp * nps;
+      for (int m = 0; m < nps; ++m) {
+        const double xs = msx[base + m];
+        if (!(xs > a0 && xs < b0)) continue;
+        if (msc[base + m] <= kk)
           na = fmax(na, xs);
         else
           nb = fmin(nb, xs);
       }
-      if (na == a && nb == b) {
-        // no interior point was representable: the bracket is converged
-        b = a;
+      if (na == a0 && nb == b0) {
+        b0 = a0;   // no interior point is representable: converged
       } else {
-        a = na;
-        b = nb;
+        a0 = na;
+        b0 = nb;
       }
     }
     __syncthreads();
   }
-  const double lj = 0.5 * (a + b);
-  // group leaders hold the eigenvalue of their group
-  __shared__ double lamg[64];
-  if (gact && sub == 0) lamg[grp] = lj;
+  if (gact && sub == 0) lamg[grp] = 0.5 * (a0 + b0);
   __syncthreads();
   TS(2);
-  if (r < d) {
-    const double lv = lamg[r];
-    // inverse iteration: (T - lv I) y = x, banded elimination with row swaps;
-    // the upper factor has bandwidth 2 (u0 diagonal, u1, u2 superdiagonals);
-    // the vector lives in X[:, r] (LDS)
-    double u0[64], u1[64], u2[64];
-    for (int i = 0; i < n; ++i) X[i * 64 + r] = 1.0;
-    for (int pass = 0; pass < 3; ++pass) {
-      double c0 = dd[0] - lv, c1 = (n > 1) ? ee[0] : 0.0, c2 = 0.0;
-      for (int i = 0; i < n - 1; ++i) {
-        const double sb = ee[i], dg = dd[i + 1] - lv, sp = (i + 2 < n) ? ee[i + 1] : 0.0;
-        double n0, n1;
-        if (fabs(sb) > fabs(c0)) {
-          const double f = c0 / sb;
-          u0[i] = sb;
-          u1[i] = dg;
-          u2[i] = sp;
-          const double xi = X[i * 64 + r];
-          const double xn = X[(i + 1) * 64 + r];
-          X[i * 64 + r] = xn;
-          X[(i + 1) * 64 + r] = xi - f * xn;
-          n0 = c1 - f * dg;
-          n1 = c2 - f * sp;
-        } else {
-          const double piv = (c0 == 0.0) ? tiny : c0;
-          const double f = sb / piv;
-          u0[i] = piv;
-          u1[i] = c1;
-          u2[i] = c2;
-          X[(i + 1) * 64 + r] -= f * X[i * 64 + r];
-          n0 = dg - f * c1;
-          n1 = sp - f * c2;
-        }
-        c0 = n0;
-        c1 = n1;
-        c2 = 0.0;
-      }
-      u0[n - 1] = (c0 == 0.0) ? tiny : c0;
-      double x1 = 0.0, x2 = 0.0, nrm = 0.0;  // x_{i+1}, x_{i+2}
-      for (int i = n - 1; i >= 0; --i) {
-        double s = X[i * 64 + r];
-        if (i + 1 < n) s -= u1[i] * x1;
-        if (i + 2 < n) s -= u2[i] * x2;
-        const double xi = s / u0[i];
-        X[i * 64 + r] = xi;
-        nrm = fma(xi, xi, nrm);
-        x2 = x1;
-        x1 = xi;
-      }
-      nrm = 1.0 / sqrt(nrm);
-      for (int i = 0; i < n; ++i) X[i * 64 + r] *= nrm;
+  // ---- inverse iteration, lane c < d owns eigenvector c (the other lanes
+  // repeat eigenvector d - 1 so that control flow stays uniform) ----
+  // T is scaled by 1/scale so that pivots are O(1) or O(eps)
+  const double isc = (scale > 0.0) ? 1.0 / scale : 1.0;
+  const double ptiny = 2.2e-16;
+  const double dls = ddl * isc, els = eel * isc;   // every lane: read by readlane
+  double x[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) x[i] = 0.0;
+  double* U0 = W;
+  double* U1 = W + M * M;
+  double* U2 = W + 2 * M * M;
+  if (d > 0) {
+    const double lv = lamg[min(r, d - 1)] * isc;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      // a fixed start vector with no symmetry: 1 + frac(0.618 i) / 2
+      const double h = 0.6180339887498949 * (double)i;
+      x[i] = (i < n) ? 1.0 + 0.5 * (h - floor(h)) : 0.0;
     }
-    TS(3);
-    // back-transform: x <- H_0 H_1 ... H_{n-3} x
-    for (int k = n - 3; k >= 0; --k) {
-      const double t = tau[k];
-      if (t == 0.0) continue;
-      const double* hv = H + k * SE_LD;
-      double sa[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-      for (int i = k + 1; i < n; ++i) sa[i & 3] = fma(hv[i], X[i * 64 + r], sa[i & 3]);
-      const double s = t * ((sa[0] + sa[1]) + (sa[2] + sa[3]));
-#pragma unroll 4
-      for (int i = k + 1; i < n; ++i) X[i * 64 + r] -= s * hv[i];
+    for (int pass = 0; pass < 3; ++pass) {
+      double c0 = te_lane(dls, 0) - lv, c1 = (n > 1) ? te_lane(els, 0) : 0.0;
+#pragma unroll
+      for (int i = 0; i < M - 1; ++i) {
+        if (i < n - 1) {
+          const double sb = te_lane(els, i), dg = te_lane(dls, i + 1) - lv;
+          const double sp = (i + 2 < n) ? te_lane(els, i + 1) : 0.0;
+          const bool swap = fabs(sb) > fabs(c0);
+          const double piv = swap ? sb : ((c0 == 0.0) ? ptiny : c0);
+          const double f = (swap ? c0 : sb) * te_rcp(piv);
+          U0[i * M + r] = piv;
+          U1[i * M + r] = swap ? dg : c1;
+          U2[i * M + r] = swap ? sp : 0.0;
+          const double xi = x[i], xn = x[i + 1];
+          x[i] = swap ? xn : xi;
+          x[i + 1] = swap ? (xi - f * xn) : (xn - f * xi);
+          const double n0 = swap ? (c1 - f * dg) : (dg - f * c1);
+          const double n1 = swap ? (-f * sp) : sp;
+          c0 = n0;
+          c1 = n1;
+        }
+      }
+      const double plast = (c0 == 0.0) ? ptiny : c0;
+      double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+#pragma unroll
+      for (int i = M - 1; i >= 0; --i) {
+        if (i < n) {
+          const double u0 = (i == n - 1) ? plast : U0[i * M + r];
+          const double u1 = (i + 1 < n) ? U1[i * M + r] : 0.0;
+          const double u2 = (i + 2 < n) ? U2[i * M + r] : 0.0;
+          const double xi = (x[i] - u1 * x1 - u2 * x2) * te_rcp(u0);
+          x[i] = xi;
+          nrm = fma(xi, xi, nrm);
+          x2 = x1;
+          x1 = xi;
+        }
+      }
+      const double inv = 1.0 / sqrt(nrm);
+#pragma unroll
+      for (int i = 0; i < M; ++i) x[i] *= inv;
+    }
+  }
+  TS(3);
+  // ---- back-transform x <- H_0 H_1 ... H_{n-3} x ----
+  for (int k = n - 3; k >= 0; --k) {
+    const double t = tau[k];
+    if (t == 0.0) continue;
+    const double* hk = H + k * M;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+    for (int ic = 0; ic < M; ic += 16) {
+      if (k < ic + 15) {
+#pragma unroll
+        for (int i = ic; i < ic + 16; i += 4) {
+          s0 = fma(hk[i], x[i], s0);
+          s1 = fma(hk[i + 1], x[i + 1], s1);
+          s2 = fma(hk[i + 2], x[i + 2], s2);
+          s3 = fma(hk[i + 3], x[i + 3], s3);
+        }
+      }
+    }
+    const double s = t * ((s0 + s1) + (s2 + s3));
+#pragma unroll
+    for (int ic = 0; ic < M; ic += 16) {
+      if (k < ic + 15) {
+#pragma unroll
+        for (int i = ic; i < ic + 16; ++i) x[i] -= s * hk[i];
+      }
     }
   }
   __syncthreads();
   TS(4);
-  // Cholesky QR of the d vectors: Gram (lane a computes row a), Cholesky
-  // (upper R), then X <- X R^{-1} row by row (lane i owns row i)
-  if (r < d)
+  // ---- Cholesky QR of the d vectors ----
+  double* XL = W;                 // XL[i * M + c]: entry i of vector c
+  double* Rc = W + M * M;         // Rc[a * (M + 1) + b]
+  if (r < d) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) XL[i * M + r] = x[i];
+  }
+  __syncthreads();
+  if (r < d) {
     for (int b = 0; b < d; ++b) {
-      double s = 0.0;
-      for (int i = 0; i < n; ++i) s = fma(X[i * 64 + r], X[i * 64 + b], s);
-      Rc[r * 65 + b] = s;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < M; i += 2) {
+        s0 = fma(x[i], XL[i * M + b], s0);
+        s1 = fma(x[i + 1], XL[(i + 1) * M + b], s1);
+      }
+      Rc[r * (M + 1) + b] = s0 + s1;
     }
+  }
   __syncthreads();
   int bad = 0;
   for (int j = 0; j < d; ++j) {
     if (r == 0) {
-      double s = Rc[j * 65 + j];
-      for (int k = 0; k < j; ++k) s -= Rc[k * 65 + j] * Rc[k * 65 + j];
-      Rc[j * 65 + j] = (s > 0.0) ? sqrt(s) : 0.0;
+      double s = Rc[j * (M + 1) + j];
+      for (int k = 0; k < j; ++k) s -= Rc[k * (M + 1) + j] * Rc[k * (M + 1) + j];
+      Rc[j * (M + 1) + j] = (s > 0.0) ? sqrt(s) : 0.0;
     }
     __syncthreads();
-    const double rjj = Rc[j * 65 + j];
+    const double rjj = Rc[j * (M + 1) + j];
     if (!(rjj > 0.0)) {
       bad = 1;
       break;
     }
     if (r > j && r < d) {
-      double s = Rc[j * 65 + r];
-      for (int k = 0; k < j; ++k) s -= Rc[k * 65 + j] * Rc[k * 65 + r];
-      Rc[j * 65 + r] = s / rjj;  // R[j][r], upper
+      double s = Rc[j * (M + 1) + r];
+      for (int k = 0; k < j; ++k) s -= Rc[k * (M + 1) + j] * Rc[k * (M + 1) + r];
+      Rc[j * (M + 1) + r] = s / rjj;   // R[j][r], upper triangle
     }
     __syncthreads();
   }
   if (!bad && r < n) {
-    // row r of X times R^{-1}: forward substitution over the columns
-    double y[64];
+    // row r of X R^{-1} by forward substitution, in place
     for (int c = 0; c < d; ++c) {
-      double s = X[r * 64 + c];
-      for (int k = 0; k < c; ++k) s -= y[k] * Rc[k * 65 + c];
-      y[c] = s / Rc[c * 65 + c];
+      double s = XL[r * M + c];
+      for (int k = 0; k < c; ++k) s -= XL[r * M + k] * Rc[k * (M + 1) + c];
+      XL[r * M + c] = s / Rc[c * (M + 1) + c];
     }
-    for (int c = 0; c < d; ++c) V[(size_t)c * n + r] = y[c];
+    for (int c = 0; c < d; ++c) V[(size_t)c * n + r] = XL[r * M + c];
   }
   if (r < d) lam[r] = lamg[r];
   if (r == 0 && bad && flags) flags[0] |= 32;
