@@ -618,9 +618,11 @@ RowTerms rt(const cplx* in0, const cplx* M0, int k0, const cplx* in1 = nullptr,
 }
 
 // g = U^* G~ with the full gradient of every column at (U, Z): deposit,
-// Poisson, gather (writes G~ into r.G) and the split-K projection.
+// Poisson, then either the fused gather-projection (G~ never stored) or, for
+// ranks beyond the fused kernels, the gather into r.G and a split-K product.
+// With want_colsq, |G~[:, c]|^2 goes to r.colsq.
 void full_gradient(symrom_rom& r, const cplx* U, const cplx* Z, const int* active,
-                   bool do_deposit) {
+                   bool do_deposit, bool want_colsq = false) {
   hipStream_t s = r.s;
   const int n = r.n;
   const double qm = r.cfg.q / r.cfg.m;
@@ -636,8 +638,18 @@ void full_gradient(symrom_rom& r, const cplx* U, const cplx* Z, const int* activ
     launch_poisson(s, r.b.part, r.gdep.nrb, r.p, r.Nx, r.b.qw, r.b.h, r.b.mw, active, r.b.rho,
                    r.b.phi, r.b.e, r.b.energy);
   }
+  const double pact = (active ? (double)r.n_active : (double)r.p);
+  if (fused_gradient_ok(n)) {
+    // per (particle, parameter): 4n flops for x and v, 4n for the projection,
+    // 4 for |G~|^2; bytes: the basis once per parameter tile, the partials
+    const int ntiles = (r.p + 31) / 32;
+    Timer t(FAM_GATHER, s, (8.0 * n + 4.0) * (double)r.N * pact,
+            16.0 * n * (double)r.N * ntiles);
+    launch_gather_project(s, U, r.N, n, Z, r.p, r.Nx, r.b.factor, r.b.e, qm, active, want_colsq,
+                          r.gemm_part, (size_t)r.nkb * 64 * 64, r.gproj, r.colsq);
+    return;
+  }
   {
-    const double pact = (active ? (double)r.n_active : (double)r.p);
     const int ntiles = (r.p + r.ggat.pt - 1) / r.ggat.pt;
     Timer t(FAM_GATHER, s, 8.0 * n * (double)r.N * pact,
             16.0 * n * (double)r.N * ntiles + 16.0 * (double)r.N * pact);
@@ -646,6 +658,16 @@ void full_gradient(symrom_rom& r, const cplx* U, const cplx* Z, const int* activ
   }
   Timer t(FAM_BASIS, s);
   launch_gemm_ah_b(s, ml(U, n), n, ml(r.G, r.p), r.p, false, r.N, r.nkb, r.gemm_part, r.gproj);
+  if (want_colsq)
+    launch_colsumsq(s, reinterpret_cast<const double*>(r.G), 2 * r.N, r.p, 1.0, r.colsq, r.b.part);
+}
+
+// G~ at (U, Z) into r.G with the field already in r.b.e (for the rank
+// growth, which needs G~^* G~ and G~ Q)
+void materialise_gradient(symrom_rom& r, const cplx* U, const cplx* Z) {
+  Timer t(FAM_GATHER, r.s);
+  launch_gather_rom(r.s, U, r.N, r.n, Z, r.p, r.Nx, r.ggat, r.b.factor, r.b.e, r.cfg.q / r.cfg.m,
+                    nullptr, true, r.G);
 }
 
 // X~ = -i (G~ Q - U T) scaled by `scale`, written to `out`, with G~ in r.G
@@ -657,6 +679,19 @@ void basis_velocity(symrom_rom& r, const cplx* U, const cplx* Z, double scale, c
   {
     Timer t(FAM_DENSE, s);
     launch_dense_spinv(s, Z, n, r.p, r.cfg.pinv_rtol, r.Q, r.sigma2, r.flags);
+  }
+  if (fused_gradient_ok(n)) {
+    {
+      Timer t(FAM_DENSE, s);
+      launch_dense_xfinish(s, r.gproj, r.Q, n, r.p, 2.0 * scale, k1, r.MP, r.MU);
+    }
+    // per (particle, parameter): 4n flops for x and v, 4n for G~ Q; plus 4n^2
+    // per particle for U MU; bytes: U read, out written
+    Timer t(FAM_GATHER, s, 8.0 * n * (double)r.N * r.p + 4.0 * n * n * (double)r.N,
+            32.0 * n * (double)r.N);
+    launch_gather_xi(s, U, r.N, n, Z, r.p, r.Nx, r.b.factor, r.b.e, r.cfg.q / r.cfg.m, r.Q, r.MU,
+                     scale, out);
+    return;
   }
   Timer t(FAM_BASIS, s);
   launch_rowgemm(s, rt(r.G, r.Q, r.p), r.N, n, r.P);  // P = G~ Q
@@ -1032,10 +1067,9 @@ symrom_status rom_grow(symrom_rom& r, int k, bool decide) {
   hipStream_t s = r.s;
   const int n = r.n, p = r.p, N = r.N;
   HIPCHK(hipMemsetAsync(r.flags, 0, 4 * sizeof(int), s));
-  full_gradient(r, r.U0, r.Z0, nullptr, true);
+  full_gradient(r, r.U0, r.Z0, nullptr, true, decide);
   if (decide) {
     // eps needs only |G|^2 and |g|^2
-    launch_colsumsq(s, reinterpret_cast<const double*>(r.G), 2 * N, p, 1.0, r.colsq, r.b.part);
     launch_dense_indicator(s, r.colsq, r.gproj, n, p, r.eps_dev);
     LAUNCHCHK();
     double eps = 0.0;
@@ -1050,6 +1084,7 @@ symrom_status rom_grow(symrom_rom& r, int k, bool decide) {
     k = 1;
   }
   r.stage1_cached = false;
+  if (fused_gradient_ok(n)) materialise_gradient(r, r.U0, r.Z0);
   launch_gemm_ah_b(s, ml(r.G, p), p, ml(r.G, p), p, false, N, r.nkb, r.gemm_part, r.Gp);
   launch_dense_hh(s, r.Gp, r.gproj, n, p, nullptr);
   LAUNCHCHK();

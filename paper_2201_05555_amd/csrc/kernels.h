@@ -25,7 +25,7 @@ struct RealList {
 };
 
 // gemm flags
-enum { GEMM_B_REAL = 1, GEMM_A_REAL = 2, GEMM_NO_CONJ_A = 4 };
+enum { GEMM_B_REAL = 1, GEMM_A_REAL = 2, GEMM_NO_CONJ_A = 4, GEMM_SAME = 8 };  // SAME: internal
 
 // Terms of a row-wise combination out = sum_s in_s M_s.
 struct RowTerms {
@@ -74,6 +74,17 @@ void launch_gemm_ah_b(hipStream_t s, const MatList& A, int a, const MatList& B, 
 void launch_gemm_flags(hipStream_t s, const MatList& A, int a, const MatList& B, int b, int flags,
                        int N, int nkb, cplx* part, cplx* C);
 void launch_rowgemm(hipStream_t s, const RowTerms& T, int N, int m, cplx* out);
+// Fused gather + projection / basis velocity (G~ never stored); only for
+// n with fused_gradient_ok(n).  launch_gather_project writes g (n x p) and,
+// when want_colsq, |G~[:, c]|^2 into colsq; part holds part_cap complex.
+bool fused_gradient_ok(int n);
+void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p,
+                           int Nx, const double* factor, const double* e, double qm,
+                           const int* active, bool want_colsq, cplx* part, size_t part_cap,
+                           cplx* g, double* colsq);
+void launch_gather_xi(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
+                      const double* factor, const double* e, double qm, const cplx* Q,
+                      const cplx* MU, double h, cplx* out);
 void launch_deim_gather(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                         const double* factor, const double* e, double qm, const int* idx,
                         const double* w, int d, const int* active, cplx* gF);

@@ -106,17 +106,32 @@ __device__ inline const cplx* list_col(const MatList& L, int c, int& local) {
 }
 
 // Each thread owns a 4 x 4 tile of C (4 columns of A, 4 columns of B) and a
-// row group: the R = 256 / tiles threads of a tile stream the block's rows
-// with stride R straight from global memory (consecutive threads read
-// consecutive rows of the same columns, so loads are coalesced), and the R
-// partial tiles are summed in LDS in a fixed order.  Requires a, b <= 64.
+// row group: the R = 256 / tiles threads of a tile take every R-th row of
+// the block's range.  Rows arrive in chunks of TR staged through LDS with
+// coalesced loads (each element read from memory once per block; one copy
+// when A and B are the same list), and the R partial tiles are summed in
+// LDS in a fixed order.  Requires a, b <= 64.
+// ---------------------------------------------------------------------------
+#define GEMM_RED_LD 257
 __global__ void __launch_bounds__(256) gemm_ah_b_kernel(MatList A, int a, MatList B, int b,
-                                                        int flags, int N, int rk,
+                                                        int flags, int N, int rk, int TR,
                                                         cplx* __restrict__ part) {
+  extern __shared__ cplx sm[];   // staging [a (+ b)][TR], later the tile sums [16][GEMM_RED_LD]
+  __shared__ const void* colp[128];
   const bool b_real = flags & GEMM_B_REAL;
   const bool a_real = flags & GEMM_A_REAL;
   const bool conj_a = !(flags & GEMM_NO_CONJ_A);
-  __shared__ cplx red[256 * 16];
+  const bool same = flags & GEMM_SAME;
+  const int tid = threadIdx.x;
+  const int nst = same ? a : a + b;   // staged columns
+  if (tid < nst) {
+    const bool isA = tid < a;
+    int lc;
+    const cplx* base = isA ? list_col(A, tid, lc) : list_col(B, tid - a, lc);
+    const bool re = isA ? a_real : b_real;
+    colp[tid] = re ? static_cast<const void*>(reinterpret_cast<const double*>(base) + (size_t)lc * N)
+                   : static_cast<const void*>(base + (size_t)lc * N);
+  }
   const int kb = blockIdx.x;
   const int r0 = kb * rk;
   const int r1 = min(N, r0 + rk);
@@ -124,113 +139,83 @@ __global__ void __launch_bounds__(256) gemm_ah_b_kernel(MatList A, int a, MatLis
   const int ntb = (b + 3) / 4;
   const int nt = nta * ntb;
   const int R = max(1, 256 / nt);
-  const int tid = threadIdx.x;
   const int tile = tid / R;
   const int rg = tid % R;
   const bool owner = tile < nt;
+  const int ta0 = (tile % nta) * 4;
+  const int tb0 = (tile / nta) * 4;
+  cplx* sA = sm;
+  cplx* sB = same ? sm : sm + (size_t)a * TR;
   cplx acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = mk(0.0, 0.0);
-  if (owner) {
-    const int ta0 = (tile % nta) * 4;
-    const int tb0 = (tile / nta) * 4;
-    const cplx* ap[4];
-    const cplx* bp[4];
+  for (int c0 = r0; c0 < r1; c0 += TR) {
+    const int tn = min(TR, r1 - c0);
+    __syncthreads();
+    // stage the chunk: element t = col * TR + row; up to 16 loads in flight
+    const int tot = nst * TR;
+    for (int t0 = 0; t0 < tot; t0 += 16 * 256) {
+      cplx v[16];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int lc;
-      ap[i] = (ta0 + i < a) ? list_col(A, ta0 + i, lc) : nullptr;
-      if (ap[i]) {
-        if (a_real)
-          ap[i] = reinterpret_cast<const cplx*>(reinterpret_cast<const double*>(ap[i]) +
-                                                (size_t)lc * N);
-        else
-          ap[i] += (size_t)lc * N;
+      for (int u = 0; u < 16; ++u) {
+        const int t = t0 + u * 256 + tid;
+        v[u] = mk(0.0, 0.0);
+        if (t < tot) {
+          const int col = t / TR, row = t % TR;
+          if (row < tn) {
+            const bool re = (col < a) ? a_real : b_real;
+            v[u] = re ? mk(reinterpret_cast<const double*>(colp[col])[c0 + row], 0.0)
+                      : reinterpret_cast<const cplx*>(colp[col])[c0 + row];
+          }
+        }
       }
-      bp[i] = (tb0 + i < b) ? list_col(B, tb0 + i, lc) : nullptr;
-      if (bp[i]) {
-        if (b_real)
-          bp[i] = reinterpret_cast<const cplx*>(reinterpret_cast<const double*>(bp[i]) +
-                                                (size_t)lc * N);
-        else
-          bp[i] += (size_t)lc * N;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int t = t0 + u * 256 + tid;
+        if (t < tot) sm[t] = v[u];
       }
     }
-    int l = r0 + rg;
-    // two rows per pass: twice the loads in flight
-    for (; l + R < r1; l += 2 * R) {
-      cplx av[2][4], bv[2][4];
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int lu = l + u * R;
+    __syncthreads();
+    if (owner) {
+      for (int row = rg; row < tn; row += R) {
+        cplx av[4], bv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          if (!ap[i])
-            av[u][i] = mk(0.0, 0.0);
-          else if (a_real)
-            av[u][i] = mk(reinterpret_cast<const double*>(ap[i])[lu], 0.0);
-          else
-            av[u][i] = conj_a ? ap[i][lu] : cconj(ap[i][lu]);
+          const cplx x = (ta0 + i < a) ? sA[(ta0 + i) * TR + row] : mk(0.0, 0.0);
+          av[i] = conj_a ? x : cconj(x);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (!bp[j])
-            bv[u][j] = mk(0.0, 0.0);
-          else if (b_real)
-            bv[u][j] = mk(reinterpret_cast<const double*>(bp[j])[lu], 0.0);
-          else
-            bv[u][j] = bp[j][lu];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
+        for (int j = 0; j < 4; ++j) bv[j] = (tb0 + j < b) ? sB[(tb0 + j) * TR + row] : mk(0.0, 0.0);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) cfmac(acc[i][j], av[u][i], bv[u][j]);
-    }
-    for (; l < r1; l += R) {
-      cplx av[4], bv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        if (!ap[i])
-          av[i] = mk(0.0, 0.0);
-        else if (a_real)
-          av[i] = mk(reinterpret_cast<const double*>(ap[i])[l], 0.0);
-        else
-          av[i] = conj_a ? ap[i][l] : cconj(ap[i][l]);
+          for (int j = 0; j < 4; ++j) cfmac(acc[i][j], av[i], bv[j]);
       }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (!bp[j])
-          bv[j] = mk(0.0, 0.0);
-        else if (b_real)
-          bv[j] = mk(reinterpret_cast<const double*>(bp[j])[l], 0.0);
-        else
-          bv[j] = bp[j][l];
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) cfmac(acc[i][j], av[i], bv[j]);
     }
   }
+  __syncthreads();
+  // tile sums, entry-major with a padded stride (GEMM_RED_LD = 257 complex):
+  // the writes of a wavefront are consecutive and the reads of different
+  // entries fall in different banks
+  cplx* red = sm;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) red[tid * 16 + i * 4 + j] = acc[i][j];
+    for (int j = 0; j < 4; ++j) red[(i * 4 + j) * GEMM_RED_LD + tid] = acc[i][j];
   __syncthreads();
   // sum the R row groups of every (tile, entry) in a fixed order, one
   // output entry per thread at a time
   const int nout = a * b;
   for (int o = tid; o < nt * 16; o += blockDim.x) {
     const int tl = o / 16, q = o % 16;
-    cplx sm = mk(0.0, 0.0);
-    for (int g = 0; g < R; ++g) sm = cadd(sm, red[(tl * R + g) * 16 + q]);
+    cplx sm2 = mk(0.0, 0.0);
+    // in order; unrolled so that the independent LDS loads are batched
+#pragma unroll 8
+    for (int g = 0; g < R; ++g) sm2 = cadd(sm2, red[q * GEMM_RED_LD + tl * R + g]);
     const int ia = (tl % nta) * 4 + q / 4, ib = (tl / nta) * 4 + q % 4;
-    if (ia < a && ib < b) part[(size_t)kb * nout + (size_t)ib * a + ia] = sm;
+    if (ia < a && ib < b) part[(size_t)kb * nout + (size_t)ib * a + ia] = sm2;
   }
 }
 
@@ -493,8 +478,323 @@ __global__ void __launch_bounds__(256) colsum_partial_kernel(const double* __res
 }
 
 // ---------------------------------------------------------------------------
+// Fused gather + projection (eq. grads): g = U~^* G~ (n x p) with
+// G~ = F + i v evaluated on the fly and never stored; F = (q/m) e_c at the
+// particle's cell, v = Im(U~ Z~).  Lanes are the 64 parameters of a tile
+// (blockIdx.y); each wavefront takes one particle row at a time, so the row
+// of U~ is wavefront-uniform (scalar loads, no LDS traffic) and the
+// projection needs no cross-lane reduction while rows stream.  The field
+// rows of the tile sit in LDS.  The eight wavefronts are summed in a fixed
+// order; block b writes part[b * rec + c * n + k] and, with want_colsq,
+// |G~[:, c]|^2 at part[b * rec + n * p + c].re.  Positions use the operation
+// order of the deposit, so both see the same cells.
+// ---------------------------------------------------------------------------
+template <int NC, bool ET_LDS>
+__global__ void __launch_bounds__(512) gather_project_kernel(
+    const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx, int rpb,
+    const double* __restrict__ factor, const double* __restrict__ e, double qm,
+    const int* __restrict__ active, int rec, int want_colsq, cplx* __restrict__ part) {
+  extern __shared__ double smem[];
+  double* et = smem;  // [64][Nx] (ET_LDS); after the rows, the wavefront sums
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c0 = blockIdx.y * 64;
+  const int c = c0 + lane;
+  const int ntc = min(64, p - c0);
+  const bool on = (lane < ntc) && (!active || active[c]);
+  if (ET_LDS) {
+    // the tile's field rows are contiguous: a linear copy, four loads in flight
+    const double* es = e + (size_t)c0 * Nx;
+    const int tot = ntc * Nx;
+    for (int t0 = 0; t0 < tot; t0 += 4 * 512) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = t0 + u * 512 + tid;
+        v[u] = (t < tot) ? es[t] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = t0 + u * 512 + tid;
+        if (t < tot) et[t] = qm * v[u];
+      }
+    }
+  }
+  cplx z[NC], acc[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    z[k] = (on && k < n) ? Z[(size_t)c * n + k] : mk(0.0, 0.0);
+    acc[k] = mk(0.0, 0.0);
+  }
+  const double fac = on ? factor[c] : 1.0;
+  double csq = 0.0;
+  __syncthreads();
+  const int r0 = blockIdx.x * rpb;
+  const int r1 = min(N, r0 + rpb);
+  if (on) {
+    for (int l = r0 + w; l < r1; l += 8) {
+      // the padding (k >= n) is zero in u and z: those terms add exact
+      // zeros, so the loops run branch-free over NC
+      cplx u[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) u[k] = (k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
+      double x0 = 0.0, x1 = 0.0, v0 = 0.0, v1 = 0.0;
+#pragma unroll
+      for (int k = 0; k < NC; k += 2) {
+        x0 = fma(u[k].re, z[k].re, x0);
+        x0 = fma(-u[k].im, z[k].im, x0);
+        v0 = fma(u[k].re, z[k].im, v0);
+        v0 = fma(u[k].im, z[k].re, v0);
+        x1 = fma(u[k + 1].re, z[k + 1].re, x1);
+        x1 = fma(-u[k + 1].im, z[k + 1].im, x1);
+        v1 = fma(u[k + 1].re, z[k + 1].im, v1);
+        v1 = fma(u[k + 1].im, z[k + 1].re, v1);
+      }
+      const double v = v0 + v1;
+      int j;
+      double th;
+      cell_of(x0 + x1, fac, Nx, j, th);
+      const double F = ET_LDS ? et[lane * Nx + j] : qm * e[(size_t)c * Nx + j];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) cfmac(acc[k], u[k], mk(F, v));
+      csq = fma(F, F, csq);
+      csq = fma(v, v, csq);
+    }
+  }
+  // the eight wavefronts in order, through LDS (the field rows are free now)
+  __syncthreads();
+  cplx* red = reinterpret_cast<cplx*>(smem);                  // [NC][64]
+  double* rcs = smem + 2 * NC * 64;                            // [64]
+  for (int ww = 0; ww < 8; ++ww) {
+    if (w == ww) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) red[k * 64 + lane] = (ww == 0) ? acc[k] : cadd(red[k * 64 + lane], acc[k]);
+      rcs[lane] = (ww == 0) ? csq : rcs[lane] + csq;
+    }
+    __syncthreads();
+  }
+  cplx* pb = part + (size_t)blockIdx.x * rec;
+  for (int t = tid; t < ntc * n; t += 512) {
+    const int q = t / n, k = t % n;
+    pb[(size_t)(c0 + q) * n + k] = red[k * 64 + q];
+  }
+  if (want_colsq)
+    for (int t = tid; t < ntc; t += 512) pb[(size_t)n * p + c0 + t] = mk(rcs[t], 0.0);
+}
+
+// C1[o] = sum_b part[b][o] for o < n1, C2[o - n1] = the real part of that sum
+// for n1 <= o < nout; blocks summed in a fixed order (one wavefront per output).
+__global__ void __launch_bounds__(256) reduce_partials2_kernel(const cplx* __restrict__ part,
+                                                               int nkb, int rec, int n1, int nout,
+                                                               cplx* __restrict__ C1,
+                                                               double* __restrict__ C2) {
+  const int lane = threadIdx.x & 63;
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (o >= nout) return;
+  double re = 0.0, im = 0.0;
+  for (int k = lane; k < nkb; k += 64) {
+    const cplx v = part[(size_t)k * rec + o];
+    re += v.re;
+    im += v.im;
+  }
+  for (int s = 32; s > 0; s >>= 1) {
+    re += __shfl_xor(re, s, 64);
+    im += __shfl_xor(im, s, 64);
+  }
+  if (lane == 0) {
+    if (o < n1)
+      C1[o] = mk(re, im);
+    else
+      C2[o - n1] = re;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused gather + basis velocity: out = G~ (-i h Q) + U~ MU (N x n), the
+// tangent step xi = h X~ of eq. Xdot in complex form (X~ = -i (G~ Q - U~ g~ Q)),
+// with G~ evaluated on the fly (not stored).  One thread per particle row;
+// the block walks the parameters in order with the field row of the next
+// parameter prefetched into the other half of a two-row LDS buffer.  Q
+// (p x n, ld p) and MU (n x n, ld n) as written by the dense kernels.
+// ---------------------------------------------------------------------------
+template <int NC>
+__global__ void __launch_bounds__(256) gather_xi_kernel(
+    const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx,
+    const double* __restrict__ factor, const double* __restrict__ e, double qm,
+    const cplx* __restrict__ Q, const cplx* __restrict__ MU, double h, cplx* __restrict__ out) {
+  extern __shared__ double smem[];
+  cplx* Zs = reinterpret_cast<cplx*>(smem);  // [p][NC], zero beyond n
+  cplx* Qs = Zs + (size_t)p * NC;            // [p][NC]: -i h Q[c][k], zero beyond n
+  cplx* Ms = Qs + (size_t)p * NC;            // [NC][NC]: MU[j][k] at Ms[j * NC + k]
+  double* fs = reinterpret_cast<double*>(Ms + NC * NC);  // [p]
+  double* tb = fs + p;                       // [2][Nx]: field rows (q/m) e_c
+  const int tid = threadIdx.x;
+  for (int t = tid; t < p * NC; t += 256) {
+    const int c = t / NC, k = t % NC;
+    Zs[t] = (k < n) ? Z[(size_t)c * n + k] : mk(0.0, 0.0);
+    const cplx qv = (k < n) ? Q[(size_t)k * p + c] : mk(0.0, 0.0);
+    Qs[t] = mk(h * qv.im, -h * qv.re);
+  }
+  for (int t = tid; t < NC * NC; t += 256) {
+    const int j = t / NC, k = t % NC;
+    Ms[t] = (j < n && k < n) ? MU[(size_t)k * n + j] : mk(0.0, 0.0);
+  }
+  for (int t = tid; t < p; t += 256) fs[t] = factor[t];
+  for (int t = tid; t < Nx; t += 256) tb[t] = qm * e[t];
+  const int l = blockIdx.x * 256 + tid;
+  const bool valid = l < N;
+  cplx u[NC], acc[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    u[k] = (valid && k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
+    acc[k] = mk(0.0, 0.0);
+  }
+  __syncthreads();
+  // the padding (k >= n) is zero in u, Zs, Qs and Ms: those terms add exact
+  // zeros, so the loops run branch-free over NC.  First U~ MU, one row of MU
+  // at a time (keeps the register footprint to one row)
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const cplx* mj = Ms + j * NC;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) cfma(acc[k], u[j], mj[k]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll 1
+  for (int c = 0; c < p; ++c) {
+    // prefetch the next field row (Nx <= 1024: at most 4 per thread)
+    double pf[4];
+    const bool more = c + 1 < p;
+#pragma unroll
+    for (int u4 = 0; u4 < 4; ++u4) {
+      const int t = tid + u4 * 256;
+      pf[u4] = (more && t < Nx) ? e[(size_t)(c + 1) * Nx + t] : 0.0;
+    }
+    const double* te = tb + (c & 1) * Nx;
+    const cplx* zc = Zs + c * NC;
+    double x0 = 0.0, x1 = 0.0, v0 = 0.0, v1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NC; k += 2) {
+      const cplx za = zc[k], zb = zc[k + 1];
+      x0 = fma(u[k].re, za.re, x0);
+      x0 = fma(-u[k].im, za.im, x0);
+      v0 = fma(u[k].re, za.im, v0);
+      v0 = fma(u[k].im, za.re, v0);
+      x1 = fma(u[k + 1].re, zb.re, x1);
+      x1 = fma(-u[k + 1].im, zb.im, x1);
+      v1 = fma(u[k + 1].re, zb.im, v1);
+      v1 = fma(u[k + 1].im, zb.re, v1);
+    }
+    int j;
+    double th;
+    cell_of(x0 + x1, fs[c], Nx, j, th);
+    const cplx gv = mk(te[j], v0 + v1);
+    const cplx* qc = Qs + c * NC;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) cfma(acc[k], gv, qc[k]);
+    if (more) {
+      double* tn = tb + ((c + 1) & 1) * Nx;
+#pragma unroll
+      for (int u4 = 0; u4 < 4; ++u4) {
+        const int t = tid + u4 * 256;
+        if (t < Nx) tn[t] = qm * pf[u4];
+      }
+    }
+    __syncthreads();
+  }
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+      if (k < n) out[(size_t)k * N + l] = acc[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+bool fused_gradient_ok(int n) { return n <= 16; }
+
+// register width of the fused kernels: an even count >= n (the position sums
+// split into even and odd k, so every even width gives the deposit's cells)
+static int fused_nc(int n) {
+  if (n <= 4) return 4;
+  if (n <= 6) return 6;
+  if (n <= 8) return 8;
+  if (n <= 12) return 12;
+  return 16;
+}
+
+void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p,
+                           int Nx, const double* factor, const double* e, double qm,
+                           const int* active, bool want_colsq, cplx* part, size_t part_cap,
+                           cplx* g, double* colsq) {
+  const int nc = fused_nc(n);
+  const int ntile = (p + 63) / 64;
+  const int rec = n * p + p;
+  // about 256 rows per block (32 per wavefront), at most 1024 blocks,
+  // partials within part_cap
+  int nb = (N + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  const int cap = (int)(part_cap / (size_t)rec);
+  if (nb > cap) nb = cap;
+  if (nb < 1) nb = 1;
+  const int rpb = (N + nb - 1) / nb;
+  nb = (N + rpb - 1) / rpb;
+  const int tw = (p < 64) ? p : 64;
+  const size_t et_bytes = (size_t)tw * Nx * sizeof(double);
+  const bool et_lds = et_bytes <= 72 * 1024;
+  // the wavefront sums reuse the table's space: NC x 64 complex + 64 doubles
+  const size_t red_bytes = (size_t)nc * 64 * sizeof(cplx) + 64 * sizeof(double);
+  const size_t sh = (et_lds && et_bytes > red_bytes) ? et_bytes : red_bytes;
+  dim3 grid(nb, ntile);
+#define GPK(NCV, ETV)                                                                          \
+  ALLOW_BIG_LDS((gather_project_kernel<NCV, ETV>));                                          \
+  hipLaunchKernelGGL((gather_project_kernel<NCV, ETV>), grid, dim3(512), sh, s, U, N, n, Z, p, \
+                     Nx, rpb, factor, e, qm, active, rec, want_colsq ? 1 : 0, part)
+  if (et_lds) {
+    switch (nc) {
+      case 4: GPK(4, true); break;
+      case 6: GPK(6, true); break;
+      case 8: GPK(8, true); break;
+      case 12: GPK(12, true); break;
+      default: GPK(16, true); break;
+    }
+  } else {
+    switch (nc) {
+      case 4: GPK(4, false); break;
+      case 6: GPK(6, false); break;
+      case 8: GPK(8, false); break;
+      case 12: GPK(12, false); break;
+      default: GPK(16, false); break;
+    }
+  }
+#undef GPK
+  const int nout = want_colsq ? rec : n * p;
+  hipLaunchKernelGGL(reduce_partials2_kernel, dim3((nout + 3) / 4), dim3(256), 0, s, part, nb, rec,
+                     n * p, nout, g, colsq);
+}
+
+
+void launch_gather_xi(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
+                      const double* factor, const double* e, double qm, const cplx* Q,
+                      const cplx* MU, double h, cplx* out) {
+  const int nc = fused_nc(n);
+  const size_t sh = (size_t)(2 * p * nc + nc * nc) * sizeof(cplx) + (size_t)(p + 2 * Nx) * sizeof(double);
+  dim3 grid((N + 255) / 256);
+#define GXK(NCV)                                                                              \
+  ALLOW_BIG_LDS(gather_xi_kernel<NCV>);                                                     \
+  hipLaunchKernelGGL(gather_xi_kernel<NCV>, grid, dim3(256), sh, s, U, N, n, Z, p, Nx, factor, e, \
+                     qm, Q, MU, h, out)
+  switch (nc) {
+    case 4: GXK(4); break;
+    case 6: GXK(6); break;
+    case 8: GXK(8); break;
+    case 12: GXK(12); break;
+    default: GXK(16); break;
+  }
+#undef GXK
+}
+
 void launch_gather_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                        const PicGeom& g, const double* factor, const double* e, double qm,
                        const int* active, bool full, void* out) {
@@ -543,12 +843,16 @@ void launch_gemm_flags(hipStream_t s, const MatList& A, int a, const MatList& B,
   int cap = (1 << 19) / (a * bmax);
   if (cap > nkb * 64 * 64 / (a * bmax)) cap = nkb * 64 * 64 / (a * bmax);
   nkb = (N + 127) / 128;
-  if (nkb > 256) nkb = 256;
+  if (nkb > 512) nkb = 512;
   if (nkb > cap) nkb = cap;
   if (nkb < 1) nkb = 1;
   int rk = (N + nkb - 1) / nkb;
   nkb = (N + rk - 1) / rk;
   const bool b_real = flags & GEMM_B_REAL;
+  // one staged copy when A and B are the same list of the same kind
+  bool same = (a == b) && (((flags & GEMM_A_REAL) != 0) == b_real) && A.count == B.count;
+  for (int q = 0; same && q < A.count; ++q)
+    same = A.ptr[q] == B.ptr[q] && A.cols[q] == B.cols[q];
   // B is processed in chunks of at most 64 columns (one list entry per chunk)
   for (int b0 = 0; b0 < b; b0 += 64) {
     const int bc = (b - b0 < 64) ? b - b0 : 64;
@@ -560,8 +864,16 @@ void launch_gemm_flags(hipStream_t s, const MatList& A, int a, const MatList& B,
                                                          (size_t)b0 * N)
                          : B.ptr[0] + (size_t)b0 * N;
     }
-    hipLaunchKernelGGL(gemm_ah_b_kernel, dim3(nkb), dim3(256), 0, s, A, a, Bc, bc, flags, N, rk,
-                       part);
+    const bool sm_same = same && b <= 64;
+    const int nst = sm_same ? a : a + bc;
+    // rows per staged chunk: up to 256, within 64 KB of LDS
+    int TR = 256;
+    while (TR > 32 && nst * TR > 4096) TR >>= 1;
+    size_t sh = (size_t)nst * TR * sizeof(cplx);
+    if (sh < (size_t)16 * GEMM_RED_LD * sizeof(cplx)) sh = (size_t)16 * GEMM_RED_LD * sizeof(cplx);
+    ALLOW_BIG_LDS(gemm_ah_b_kernel);
+    hipLaunchKernelGGL(gemm_ah_b_kernel, dim3(nkb), dim3(256), sh, s, A, a, Bc, bc,
+                       flags | (sm_same ? GEMM_SAME : 0), N, rk, TR, part);
     int nout = a * bc;
     hipLaunchKernelGGL(reduce_partials_kernel, dim3((nout + 3) / 4), dim3(256), 0, s, part, nkb,
                        nout, C + (size_t)b0 * a);
@@ -654,7 +966,8 @@ void launch_colsum_partial(hipStream_t s, const double* Psi, int N, int d, int n
 __global__ void __launch_bounds__(256) gemm_real_tn_kernel(RealList A, int ka, int a, RealList B,
                                                            int kbcols, int b, int N, int rk,
                                                            double* __restrict__ part) {
-  __shared__ double red[256 * 16];
+  // tile sums, entry-major with a padded stride (conflict-free writes)
+  __shared__ double red[16 * GEMM_RED_LD];
   const int kb = blockIdx.x;
   const int r0 = kb * rk;
   const int r1 = min(N, r0 + rk);
@@ -710,13 +1023,14 @@ __global__ void __launch_bounds__(256) gemm_real_tn_kernel(RealList A, int ka, i
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) red[tid * 16 + i * 4 + j] = acc[i][j];
+    for (int j = 0; j < 4; ++j) red[(i * 4 + j) * GEMM_RED_LD + tid] = acc[i][j];
   __syncthreads();
   const int nout = a * b;
   for (int o = tid; o < nt * 16; o += blockDim.x) {
     const int tl = o / 16, q = o % 16;
     double sm = 0.0;
-    for (int g = 0; g < R; ++g) sm += red[(tl * R + g) * 16 + q];
+#pragma unroll 8
+    for (int g = 0; g < R; ++g) sm += red[q * GEMM_RED_LD + tl * R + g];
     const int ia = (tl % nta) * 4 + q / 4, ib = (tl / nta) * 4 + q % 4;
     if (ia < a && ib < b) part[(size_t)kb * nout + (size_t)ib * a + ia] = sm;
   }
