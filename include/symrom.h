@@ -57,10 +57,10 @@ enum { SYMROM_GALERKIN = 0, SYMROM_DEIM = 1 };
 
 typedef struct {
   int32_t N;             /* particles                                        */
-  int32_t p;             /* parameters of the ensemble                       */
+  int32_t p;             /* parameters of the ensemble (reduced model: <= 64) */
   int32_t Nx;            /* grid cells (= nodes) of the periodic P1 mesh     */
   int32_t two_n;         /* reduced dimension 2n (even)                      */
-  int32_t two_n_max;     /* capacity for rank growth (even, >= two_n, <= 64) */
+  int32_t two_n_max;     /* capacity for rank growth (even, >= two_n, <= 60) */
   double dt;             /* time step                                        */
   double q, m;           /* charge and mass (-1 and 1 in the paper)          */
   int32_t projection;    /* SYMROM_GALERKIN or SYMROM_DEIM                   */
@@ -201,9 +201,12 @@ const char* symrom_last_error(void);
 /* Accumulated device time (ms) of the kernels the library launched on the
  * handle's stream since the last call, measured with HIP events around each
  * launch of the named kernel family when timing is enabled by
- * symrom_set_timing(1).  family: 0 = reconstruct-and-deposit, 1 = gather and
- * projection, 2 = Poisson, 3 = FOM push, 4 = basis (Grams and row
- * combines), 5 = dense.  Counts launches in *launches (host, nullable). */
+ * symrom_set_timing(1).  family: 0 = reconstruct-and-deposit, 1 = fused
+ * gather-projection (g = U~^* G~), 2 = Poisson (histogram sum and solve),
+ * 3 = FOM push, 4 = basis (tall-skinny Grams and row combines), 5 = dense
+ * (small matrices, DEIM greedy), 6 = DEIM eigenpairs (top d of the snapshot
+ * Gram), 7 = fused gather-basis-velocity (xi = -i h G~ Q + U~ M).  Counts
+ * launches in *launches (host, nullable). */
 void symrom_set_timing(int32_t on);
 double symrom_kernel_ms(int32_t family, int64_t* launches);
 
@@ -211,9 +214,14 @@ double symrom_kernel_ms(int32_t family, int64_t* launches);
  * flops and HBM bytes as counted by the operation definitions (not by
  * hardware counters).  Reconstruct-and-deposit: 4n flops per
  * particle-parameter (x = Re(U~ Z~), n complex products), bytes = U~ read
- * once per parameter tile plus the partial histograms.  FOM push: 32 bytes
- * per particle-parameter (read and write X and V) plus the histograms.
- * flops, bytes: host, nullable. */
+ * once per parameter tile plus the partial histograms.  Gather-projection:
+ * (8n + 4) flops per particle-parameter, bytes = U~ read once per tile of 64
+ * parameters.  Gather-basis-velocity: 8n flops per particle-parameter plus
+ * 8n^2 per particle, bytes = U~ read and xi written.  DEIM eigenpairs:
+ * 4P^3/3 + 2P^2 d + 2P d^2 flops for the tridiagonal reduction,
+ * back-transform and orthonormalisation of a P x P Gram, no HBM bytes
+ * beyond the matrix.  FOM push: 32 bytes per particle-parameter (read and
+ * write X and V) plus the histograms.  flops, bytes: host, nullable. */
 void symrom_kernel_work(int32_t family, double* flops, double* bytes);
 
 #ifdef __cplusplus

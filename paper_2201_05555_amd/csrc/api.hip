@@ -116,7 +116,16 @@ struct Timer {
 };
 }  // namespace
 
-enum { FAM_DEPOSIT = 0, FAM_GATHER = 1, FAM_POISSON = 2, FAM_FOMPUSH = 3, FAM_BASIS = 4, FAM_DENSE = 5 };
+enum {
+  FAM_DEPOSIT = 0,
+  FAM_GATHER = 1,
+  FAM_POISSON = 2,
+  FAM_FOMPUSH = 3,
+  FAM_BASIS = 4,
+  FAM_DENSE = 5,
+  FAM_EIG = 6,
+  FAM_XI = 7
+};
 
 extern "C" void symrom_set_timing(int32_t on) {
   drain_timing();
@@ -665,7 +674,7 @@ void full_gradient(symrom_rom& r, const cplx* U, const cplx* Z, const int* activ
 // G~ at (U, Z) into r.G with the field already in r.b.e (for the rank
 // growth, which needs G~^* G~ and G~ Q)
 void materialise_gradient(symrom_rom& r, const cplx* U, const cplx* Z) {
-  Timer t(FAM_GATHER, r.s);
+  Timer t(FAM_BASIS, r.s);
   launch_gather_rom(r.s, U, r.N, r.n, Z, r.p, r.Nx, r.ggat, r.b.factor, r.b.e, r.cfg.q / r.cfg.m,
                     nullptr, true, r.G);
 }
@@ -687,7 +696,7 @@ void basis_velocity(symrom_rom& r, const cplx* U, const cplx* Z, double scale, c
     }
     // per (particle, parameter): 4n flops for x and v, 4n for G~ Q; plus 4n^2
     // per particle for U MU; bytes: U read, out written
-    Timer t(FAM_GATHER, s, 8.0 * n * (double)r.N * r.p + 4.0 * n * n * (double)r.N,
+    Timer t(FAM_XI, s, 8.0 * n * (double)r.N * r.p + 8.0 * n * n * (double)r.N,
             32.0 * n * (double)r.N);
     launch_gather_xi(s, U, r.N, n, Z, r.p, r.Nx, r.b.factor, r.b.e, r.cfg.q / r.cfg.m, r.Q, r.MU,
                      scale, out);
@@ -742,21 +751,29 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z) {
   double* Ys = r.Ywin + (size_t)slot * r.psub * N;
   launch_snapshot(s, U, N, n, Z, r.sub, r.psub, r.Nx, r.b.factor, r.b.phi, Ys);
   r.win_count++;
-  Timer t(FAM_DENSE, s);
   const int P = r.psub * r.nslots;
   std::vector<const double*> slots(r.nslots);
   for (int q = 0; q < r.nslots; ++q) slots[q] = r.Ywin + (size_t)q * r.psub * N;
-  // the Gram Y^T Y (real, P x P) is kept across steps: only the row and
-  // column block of the overwritten slot changes
-  launch_gram_block_real(s, Ys, slots.data(), r.nslots, r.psub, N, slot * r.psub,
-                         r.nkb * 64 * 64 * 2, reinterpret_cast<double*>(r.gemm_part),
-                         reinterpret_cast<double*>(r.YG));
+  {
+    // the Gram Y^T Y (real, P x P) is kept across steps: only the row and
+    // column block of the overwritten slot changes
+    Timer t(FAM_DENSE, s);
+    launch_gram_block_real(s, Ys, slots.data(), r.nslots, r.psub, N, slot * r.psub,
+                           r.nkb * 64 * 64 * 2, reinterpret_cast<double*>(r.gemm_part),
+                           reinterpret_cast<double*>(r.YG));
+  }
   r.deim_on = r.win_count >= r.nslots;
   if (!r.deim_on) return;
   const int d = (2 * n < P) ? 2 * n : P;
   r.d_cur = d;
-  launch_dense_topeig(s, reinterpret_cast<const double*>(r.YG), P, d,
-                      reinterpret_cast<double*>(r.YV), r.ylam, r.flags);
+  {
+    const double fP = P, fd = d;
+    Timer te(FAM_EIG, s, 4.0 * fP * fP * fP / 3.0 + 2.0 * fP * fP * fd + 2.0 * fP * fd * fd,
+             8.0 * fP * fP + 8.0 * fP * fd);
+    launch_dense_topeig(s, reinterpret_cast<const double*>(r.YG), P, d,
+                        reinterpret_cast<double*>(r.YV), r.ylam, r.flags);
+  }
+  Timer t(FAM_DENSE, s);
   launch_deim_basis_coeffs(s, reinterpret_cast<const double*>(r.YV), r.ylam, P, d, r.Mdeim,
                            r.flags);
   launch_rowgemm_real(s, slots.data(), r.nslots, r.psub, N, r.Mdeim, P, d, r.Psi);
@@ -775,7 +792,7 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z) {
 // gF = U~[I]^* ((q/m) e_{j(x_I)} w), then k = -i (gF + linear part).
 void deim_k(symrom_rom& r, const cplx* U, const cplx* Z, const int* active, cplx* kout) {
   hipStream_t s = r.s;
-  Timer t(FAM_GATHER, s);
+  Timer t(FAM_DENSE, s);
   launch_deim_gather(s, U, r.N, r.n, Z, r.p, r.Nx, r.b.factor, r.b.e, r.cfg.q / r.cfg.m, r.didx,
                      r.dw, r.d_cur, active, r.gF);
   if (kout) launch_deim_k(s, r.gF, r.C12, Z, r.n, r.p, kout);

@@ -90,6 +90,34 @@ def test_fom_parity(name, kw, steps):
     assert _rel(_np(H), Ho) < RTOL
 
 
+def test_fom_nonlinear_landau_growth_rate_golden():
+    """The GPU full-order model reproduces the trapping-phase growth rate the
+    paper prints for nonlinear Landau damping at eta = (0.5, 1) (Sec. 6.3,
+    fixture tests/golden/nld_rates.txt), within 10 %: a physics check of the
+    whole deposit / Poisson / push path over 800 steps."""
+    from rates import read_golden, trapping_growth_rate
+    from workloads import hammersley_uniforms, load_particles
+    binding, torch = _b()
+    g = read_golden("nld_rates.txt")
+    N, Nx, dt = 100_000, int(g["Nx"]), 0.05
+    _say("fom nonlinear Landau growth rate", N, Nx, dt)
+    L = np.array([2 * np.pi / g["k"]])
+    ux, uv = hammersley_uniforms(N)
+    params = dict(alpha=np.array([g["alpha"]]), k=np.array([g["k"]]), v0=np.zeros(1),
+                  sigma=np.array([g["sigma"]]))
+    X, V = load_particles(params, ux, uv, "landau")
+    f = binding.Fom(N, 1, Nx, dt, L, np.asfortranarray(X), np.asfortranarray(V))
+    ts, Es = [], []
+    for s in range(1, int(round(g["t_end"] / dt)) + 1):
+        f.step(1)
+        E, _ = f.diagnostics()
+        ts.append(s * dt)
+        Es.append(float(_np(E)[0]))
+    f.close()
+    rate = trapping_growth_rate(ts, Es)
+    assert abs(rate - g["growth_rate"]) < 0.1 * g["growth_rate"], rate
+
+
 def _oracle_state(w, e, two_n, **cfgkw):
     cfg = rom.RomConfig(N=w["N"], p=w["p"], Nx=w["Nx"], two_n=two_n, dt=w["dt"], **cfgkw)
     st = rom.init_state(e["X0"], e["V0"], e["L"], cfg)

@@ -239,3 +239,27 @@ def test_linear_landau_damping_rate():
     slope = np.polyfit(ts[peaks], np.log(Es[peaks]), 1)[0]
     gamma2 = 2 * _landau_rate(k).imag
     assert abs(slope - gamma2) < 0.05 * abs(gamma2), (slope, gamma2)
+
+
+def test_nonlinear_landau_growth_rate_golden():
+    """Trapping-phase growth rate of the field amplitude for the nonlinear
+    Landau case eta = (0.5, 1) against the value the paper prints (Sec. 6.3,
+    fixture tests/golden/nld_rates.txt), within 10 %."""
+    from rates import read_golden, trapping_growth_rate
+    g = read_golden("nld_rates.txt")
+    N, Nx, dt = 100_000, int(g["Nx"]), 0.05
+    L = np.array([2 * np.pi / g["k"]])
+    ux, uv = hammersley_uniforms(N)
+    params = dict(alpha=np.array([g["alpha"]]), k=np.array([g["k"]]), v0=np.zeros(1),
+                  sigma=np.array([g["sigma"]]))
+    X, V = load_particles(params, ux, uv, "landau")
+    X, V = np.array(X), np.array(V)
+    ts, Es = [], []
+    a = None
+    for s in range(1, int(round(g["t_end"] / dt)) + 1):
+        X, V, a = pic.fom_step(X, V, L, Nx, dt, a0=a)
+        rho, Phi, _ = pic.fields_of(X, L, Nx)
+        ts.append(s * dt)
+        Es.append(pic.electric_energy(Phi, rho, L, N)[0])
+    rate = trapping_growth_rate(ts, Es)
+    assert abs(rate - g["growth_rate"]) < 0.1 * g["growth_rate"], rate
