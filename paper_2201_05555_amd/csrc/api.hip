@@ -529,9 +529,9 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.didx = ar.take<int>(dmax);
   r.dw = ar.take<double>(dmax);
   r.dc = ar.take<double>(dmax);
-  r.bval = ar.take<double>(r.nbg);
-  r.bidx = ar.take<int>(r.nbg);
-  r.colpart = ar.take<double>((size_t)r.nbc * dmax);
+  r.bval = ar.take<double>(2 * (size_t)r.nbg);
+  r.bidx = ar.take<int>(2 * (size_t)r.nbg);
+  r.colpart = ar.take<double>((size_t)psi_blocks(r.N) * dmax);
   r.Mdeim = ar.take<double>((size_t)P * dmax);
   r.ylam = ar.take<double>(P);
   r.YG = ar.take<cplx>((size_t)P * P);
@@ -776,16 +776,20 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z) {
   Timer t(FAM_DENSE, s);
   launch_deim_basis_coeffs(s, reinterpret_cast<const double*>(r.YV), r.ylam, P, d, r.Mdeim,
                            r.flags);
-  launch_rowgemm_real(s, slots.data(), r.nslots, r.psub, N, r.Mdeim, P, d, r.Psi);
-  launch_colsign(s, r.Psi, N, d);
-  launch_deim_residual(s, r.Psi, N, 0, r.dc, r.nbg, r.bval, r.bidx);
-  for (int k = 1; k < d; ++k) {
-    launch_deim_solve(s, r.Psi, N, k, r.didx, r.bval, r.bidx, r.nbg, r.dc, r.flags);
-    launch_deim_residual(s, r.Psi, N, k, r.dc, r.nbg, r.bval, r.bidx);
+  // Psi and its column sums.  No sign convention is applied to the columns:
+  // flipping the sign of column k negates c_k and the residual exactly, so
+  // the greedy indices and the weights are the same bit for bit.
+  launch_psi_colsum(s, slots.data(), r.nslots, r.psub, N, r.Mdeim, P, d, r.Psi, r.colpart);
+  // greedy selection, one launch per index; block results ping-pong between
+  // the two halves of bval / bidx
+  for (int k = 0; k < d; ++k) {
+    const int cur = k & 1, prev = cur ^ 1;
+    launch_deim_greedy(s, r.Psi, N, k, r.didx, r.bval + prev * r.nbg, r.bidx + prev * r.nbg,
+                       r.nbg, r.nbg, r.bval + cur * r.nbg, r.bidx + cur * r.nbg, r.flags);
   }
-  launch_colsum_partial(s, r.Psi, N, d, r.nbc, r.colpart);
-  launch_deim_weights(s, r.Psi, N, d, r.didx, r.bval, r.bidx, r.nbg, r.colpart, r.nbc, r.dw,
-                      r.flags);
+  const int last = (d - 1) & 1;
+  launch_deim_weights2(s, r.Psi, N, d, r.didx, r.bval + last * r.nbg, r.bidx + last * r.nbg,
+                       r.nbg, r.colpart, psi_blocks(N), r.dw, r.flags);
 }
 
 // DEIM gradient at (U, Z) with the field of the last Poisson solve:

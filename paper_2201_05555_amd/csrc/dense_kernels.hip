@@ -1019,102 +1019,6 @@ __global__ void deim_basis_coeffs_kernel(const double* __restrict__ V, const dou
   M[t] = V[t] / sqrt(l);
 }
 
-// winner of the per-block argmax results (largest value, smallest index)
-__device__ int bk_argmax(const double* bval, const int* bidx, int nblk, double* sv, int* si) {
-  double best = -1.0;
-  int bi = 0x7fffffff;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-    double v = bval[b];
-    int vi = bidx[b];
-    if (v > best || (v == best && vi < bi)) {
-      best = v;
-      bi = vi;
-    }
-  }
-  sv[threadIdx.x] = best;
-  si[threadIdx.x] = bi;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      double v = sv[threadIdx.x + o];
-      int vi = si[threadIdx.x + o];
-      if (v > sv[threadIdx.x] || (v == sv[threadIdx.x] && vi < si[threadIdx.x])) {
-        sv[threadIdx.x] = v;
-        si[threadIdx.x] = vi;
-      }
-    }
-    __syncthreads();
-  }
-  int r = si[0];
-  __syncthreads();
-  return r;
-}
-
-// Greedy step k >= 1: record l_{k-1} (winner of the previous residual pass),
-// then solve (P^T Psi_k) c = P^T psi_k, the k x k system on the selected rows.
-__global__ void __launch_bounds__(DTPB) deim_solve_kernel(const double* __restrict__ Psi, int N,
-                                                          int k, int* __restrict__ idx,
-                                                          const double* __restrict__ bval,
-                                                          const int* __restrict__ bidx, int nblk,
-                                                          double* __restrict__ c,
-                                                          int* __restrict__ flags) {
-  __shared__ double sv[DTPB];
-  __shared__ int si[DTPB];
-  __shared__ cplx A[64 * 64];
-  __shared__ cplx B[64];
-  __shared__ int piv;
-  __shared__ int rows[64];
-  const int w = bk_argmax(bval, bidx, nblk, sv, si);
-  if (threadIdx.x == 0) idx[k - 1] = w;
-  for (int t = threadIdx.x; t < k; t += blockDim.x) rows[t] = (t == k - 1) ? w : idx[t];
-  __syncthreads();
-  for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
-    int j = t % k, q = t / k;  // A[j][q] = Psi[row_j, q]
-    A[q * k + j] = mk(Psi[(size_t)q * N + rows[j]], 0.0);
-  }
-  for (int t = threadIdx.x; t < k; t += blockDim.x) B[t] = mk(Psi[(size_t)k * N + rows[t]], 0.0);
-  __syncthreads();
-  if (bk_lu_solve(A, k, B, 1, &piv)) {
-    if (threadIdx.x == 0 && flags) flags[0] |= 16;
-    return;
-  }
-  for (int t = threadIdx.x; t < k; t += blockDim.x) c[t] = B[t].re;
-}
-
-// Last greedy index and the weights w = (P^T Psi)^{-T} Psi^T 1 (d x d solve);
-// colpart holds per-block column sums of Psi.
-__global__ void __launch_bounds__(DTPB) deim_weights_kernel(
-    const double* __restrict__ Psi, int N, int d, int* __restrict__ idx,
-    const double* __restrict__ bval, const int* __restrict__ bidx, int nblk,
-    const double* __restrict__ colpart, int nbc, double* __restrict__ w, int* __restrict__ flags) {
-  __shared__ double sv[DTPB];
-  __shared__ int si[DTPB];
-  __shared__ cplx A[64 * 64];
-  __shared__ cplx B[64];
-  __shared__ int piv;
-  __shared__ int rows[64];
-  const int last = bk_argmax(bval, bidx, nblk, sv, si);
-  if (threadIdx.x == 0) idx[d - 1] = last;
-  for (int t = threadIdx.x; t < d; t += blockDim.x) rows[t] = (t == d - 1) ? last : idx[t];
-  __syncthreads();
-  // A = (P^T Psi)^T: A[q][j] = Psi[row_j, q]
-  for (int t = threadIdx.x; t < d * d; t += blockDim.x) {
-    int q = t % d, j = t / d;
-    A[j * d + q] = mk(Psi[(size_t)q * N + rows[j]], 0.0);
-  }
-  for (int q = threadIdx.x; q < d; q += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nbc; ++b) s += colpart[(size_t)b * d + q];
-    B[q] = mk(s, 0.0);
-  }
-  __syncthreads();
-  if (bk_lu_solve(A, d, B, 1, &piv)) {
-    if (threadIdx.x == 0 && flags) flags[0] |= 16;
-    return;
-  }
-  for (int t = threadIdx.x; t < d; t += blockDim.x) w[t] = B[t].re;
-}
-
 // k = -i (gF + (C1 Z - conj(C2) conj(Z)) / 2): the DEIM reduced gradient
 // (eq. grHDD) with its linear part i U~^* V_r, C1 = U~^* U~, C2 = U~^T U~.
 __global__ void deim_k_kernel(const cplx* __restrict__ gF, const cplx* __restrict__ C12,
@@ -1132,17 +1036,6 @@ __global__ void deim_k_kernel(const cplx* __restrict__ gF, const cplx* __restric
   k[t] = mk(g.im, -g.re);
 }
 
-void launch_deim_solve(hipStream_t s, const double* Psi, int N, int k, int* idx,
-                       const double* bval, const int* bidx, int nblk, double* c, int* flags) {
-  hipLaunchKernelGGL(deim_solve_kernel, dim3(1), dim3(DTPB), 0, s, Psi, N, k, idx, bval, bidx,
-                     nblk, c, flags);
-}
-void launch_deim_weights(hipStream_t s, const double* Psi, int N, int d, int* idx,
-                         const double* bval, const int* bidx, int nblk, const double* colpart,
-                         int nbc, double* w, int* flags) {
-  hipLaunchKernelGGL(deim_weights_kernel, dim3(1), dim3(DTPB), 0, s, Psi, N, d, idx, bval, bidx,
-                     nblk, colpart, nbc, w, flags);
-}
 void launch_deim_basis_coeffs(hipStream_t s, const double* V, const double* lam, int P, int d,
                               double* M, int* flags) {
   hipLaunchKernelGGL(deim_basis_coeffs_kernel, dim3(nblk((size_t)P * d)), dim3(256), 0, s, V, lam,

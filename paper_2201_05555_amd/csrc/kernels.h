@@ -35,6 +35,15 @@ struct RowTerms {
   int count;
 };
 
+// register width of the fused kernels: an even count >= n (the position sums
+// split into even and odd k, so every even width gives the same cells)
+inline int nc_even(int n) {
+  if (n <= 4) return 4;
+  if (n <= 6) return 6;
+  if (n <= 8) return 8;
+  if (n <= 12) return 12;
+  return 16;
+}
 inline int nc_bucket(int n) {
   if (n <= 4) return 4;
   if (n <= 8) return 8;
@@ -90,13 +99,18 @@ void launch_deim_gather(hipStream_t s, const cplx* U, int N, int n, const cplx* 
                         const double* w, int d, const int* active, cplx* gF);
 void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, const int* sub,
                      int psub, int Nx, const double* factor, const double* phi, double* Y);
-void launch_rowgemm_real(hipStream_t s, const double* const* in, int nin, int kin, int N,
-                         const double* M, int ldM, int d, double* out);
-void launch_colsign(hipStream_t s, double* A, int N, int d);
-void launch_deim_residual(hipStream_t s, const double* Psi, int N, int k, const double* c,
-                          int nblk, double* bval, int* bidx);
-void launch_colsum_partial(hipStream_t s, const double* Psi, int N, int d, int nblk,
-                           double* part);
+// DEIM basis Psi = sum_s Y_s M_s with per-block column sums (psi_blocks(N)
+// blocks, colpart[block][c]); fused greedy step k (per-block winners into
+// bval, bidx from the previous pass pval, pidx); last index and weights.
+int psi_blocks(int N);
+void launch_psi_colsum(hipStream_t s, const double* const* in, int nin, int kin, int N,
+                       const double* M, int ldM, int d, double* out, double* colpart);
+void launch_deim_greedy(hipStream_t s, const double* Psi, int N, int k, int* idx,
+                        const double* pval, const int* pidx, int nprev, int nblk, double* bval,
+                        int* bidx, int* flags);
+void launch_deim_weights2(hipStream_t s, const double* Psi, int N, int d, int* idx,
+                          const double* pval, const int* pidx, int nprev, const double* colpart,
+                          int ncp, double* w, int* flags);
 
 // dense_kernels.hip  (single-workgroup FP64 kernels on small matrices)
 struct DenseCtl;  // device-resident control block, see dense_kernels.hip
@@ -135,11 +149,7 @@ void launch_colphase(hipStream_t s, cplx* U, int N, int col0, int k);
 void launch_z_resize(hipStream_t s, const cplx* Zin, int nin, cplx* Zout, int nout, int p);
 void launch_dense_shrink(hipStream_t s, const cplx* Z, int n, int p, cplx* V, cplx* Znew,
                          double* sig2);
-void launch_deim_solve(hipStream_t s, const double* Psi, int N, int k, int* idx,
-                       const double* bval, const int* bidx, int nblk, double* c, int* flags);
-void launch_deim_weights(hipStream_t s, const double* Psi, int N, int d, int* idx,
-                         const double* bval, const int* bidx, int nblk, const double* colpart,
-                         int nbc, double* w, int* flags);
+
 void launch_deim_basis_coeffs(hipStream_t s, const double* V, const double* lam, int P, int d,
                               double* M, int* flags);
 void launch_dense_symeig(hipStream_t s, const cplx* G, int n, double* V, double* lam, int* flags);

@@ -55,9 +55,13 @@ __global__ void __launch_bounds__(512) deposit_rom_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx, int pt,
     int rpb, const double* __restrict__ factor, const int* __restrict__ active,
     double* __restrict__ part) {
+  // parameters in flight per thread (independent chains), within registers
+  constexpr int ILP = (NC <= 8) ? 4 : (NC <= 16) ? 2 : 1;
   extern __shared__ double smem[];
   double* hist = smem;                                  // pt * Nx
   cplx* Zs = reinterpret_cast<cplx*>(smem + pt * Nx);   // pt * NC
+  double* fs = reinterpret_cast<double*>(Zs + pt * NC);  // pt factors
+  int* act = reinterpret_cast<int*>(fs + pt);            // pt flags
   const int rb = blockIdx.x;
   const int p0 = blockIdx.y * pt;
   const int np = min(pt, p - p0);
@@ -66,6 +70,10 @@ __global__ void __launch_bounds__(512) deposit_rom_kernel(
     int i = t / NC, k = t % NC;
     Zs[t] = (k < n) ? Z[(size_t)(p0 + i) * n + k] : mk(0.0, 0.0);
   }
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    fs[i] = factor[p0 + i];
+    act[i] = active ? active[p0 + i] : 1;
+  }
   __syncthreads();
   const int r0 = rb * rpb;
   const int r1 = min(N, r0 + rpb);
@@ -73,30 +81,44 @@ __global__ void __launch_bounds__(512) deposit_rom_kernel(
     cplx u[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) u[k] = (k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
-    for (int i = 0; i < np; ++i) {
-      if (active && !active[p0 + i]) continue;
-      const cplx* zi = Zs + i * NC;
-      double x0 = 0.0, x1 = 0.0;
+    // ILP parameters at a time: their position sums, cell lookups and
+    // histogram updates are independent and interleave
+    for (int i0 = 0; i0 < np; i0 += ILP) {
+      double x0[ILP], x1[ILP];
 #pragma unroll
-      for (int k = 0; k < NC; k += 2) {
-        x0 = fma(u[k].re, zi[k].re, x0);
-        x0 = fma(-u[k].im, zi[k].im, x0);
-        x1 = fma(u[k + 1].re, zi[k + 1].re, x1);
-        x1 = fma(-u[k + 1].im, zi[k + 1].im, x1);
+      for (int q = 0; q < ILP; ++q) {
+        x0[q] = 0.0;
+        x1[q] = 0.0;
       }
-      const double x = x0 + x1;
-      int j;
-      double th;
-      cell_of(x, factor[p0 + i], Nx, j, th);
-      int j1 = (j + 1 == Nx) ? 0 : j + 1;
-      lds_add(hist + i * Nx + j, 1.0 - th);
-      lds_add(hist + i * Nx + j1, th);
+#pragma unroll
+      for (int q = 0; q < ILP; ++q) {
+        const cplx* zi = Zs + min(i0 + q, np - 1) * NC;
+#pragma unroll
+        for (int k = 0; k < NC; k += 2) {
+          x0[q] = fma(u[k].re, zi[k].re, x0[q]);
+          x0[q] = fma(-u[k].im, zi[k].im, x0[q]);
+          x1[q] = fma(u[k + 1].re, zi[k + 1].re, x1[q]);
+          x1[q] = fma(-u[k + 1].im, zi[k + 1].im, x1[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < ILP; ++q) {
+        const int i = i0 + q;
+        int j;
+        double th;
+        cell_of(x0[q] + x1[q], fs[min(i, np - 1)], Nx, j, th);
+        if (i < np && act[i]) {
+          const int j1 = (j + 1 == Nx) ? 0 : j + 1;
+          lds_add(hist + i * Nx + j, 1.0 - th);
+          lds_add(hist + i * Nx + j1, th);
+        }
+      }
     }
   }
   __syncthreads();
   for (int t = threadIdx.x; t < np * Nx; t += blockDim.x) {
     int i = t / Nx;
-    if (active && !active[p0 + i]) continue;
+    if (!act[i]) continue;
     part[((size_t)rb * p + p0) * Nx + t] = hist[t];
   }
 }
@@ -352,15 +374,18 @@ void launch_deposit_x(hipStream_t s, const double* X, int N, int p, int Nx, cons
 void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                         const PicGeom& g, const double* factor, const int* active, double* part) {
   dim3 grid(g.nrb, (p + g.pt - 1) / g.pt);
-  int nc = nc_bucket(n);
-  size_t sh = (size_t)g.pt * Nx * sizeof(double) + (size_t)g.pt * nc * sizeof(cplx);
+  int nc = (n <= 16) ? nc_even(n) : 32;
+  size_t sh = (size_t)g.pt * Nx * sizeof(double) + (size_t)g.pt * nc * sizeof(cplx) +
+              (size_t)g.pt * (sizeof(double) + sizeof(int));
 #define DEP(NCV)                                                                              \
   ALLOW_BIG_LDS(deposit_rom_kernel<NCV>);                                                    \
   hipLaunchKernelGGL(deposit_rom_kernel<NCV>, grid, dim3(512), sh, s, U, N, n, Z, p, Nx, g.pt, \
                      g.rpb, factor, active, part)
   switch (nc) {
     case 4: DEP(4); break;
+    case 6: DEP(6); break;
     case 8: DEP(8); break;
+    case 12: DEP(12); break;
     case 16: DEP(16); break;
     default: DEP(32); break;
   }

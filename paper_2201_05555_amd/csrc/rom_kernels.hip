@@ -316,166 +316,6 @@ __global__ void __launch_bounds__(64) deim_gather_kernel(
   }
 }
 
-// DEIM snapshot Lambda^0(X_r^i) Phi^i at every particle (Sec. 4.3, eq. Ydeim)
-// for the parameters sub[0..psub): (1 - theta) Phi_j + theta Phi_{j+1},
-// written as column c of Y (N x psub).
-template <int NC>
-__global__ void __launch_bounds__(256) snapshot_kernel(const cplx* __restrict__ U, int N, int n,
-                                                       const cplx* __restrict__ Z,
-                                                       const int* __restrict__ sub, int psub,
-                                                       int Nx, const double* __restrict__ factor,
-                                                       const double* __restrict__ phi,
-                                                       double* __restrict__ Y) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= N) return;
-  cplx u[NC];
-#pragma unroll
-  for (int k = 0; k < NC; ++k) u[k] = (k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
-  for (int c = 0; c < psub; ++c) {
-    const int i = sub[c];
-    double x0 = 0.0, x1 = 0.0;
-#pragma unroll
-    for (int k = 0; k < NC; k += 2) {
-      if (k < n) {
-        cplx z = Z[(size_t)i * n + k];
-        x0 = fma(u[k].re, z.re, x0);
-        x0 = fma(-u[k].im, z.im, x0);
-      }
-      if (k + 1 < n) {
-        cplx z = Z[(size_t)i * n + k + 1];
-        x1 = fma(u[k + 1].re, z.re, x1);
-        x1 = fma(-u[k + 1].im, z.im, x1);
-      }
-    }
-    int j;
-    double th;
-    cell_of(x0 + x1, factor[i], Nx, j, th);
-    int j1 = (j + 1 == Nx) ? 0 : j + 1;
-    const double* ph = phi + (size_t)i * Nx;
-    Y[(size_t)c * N + l] = (1.0 - th) * ph[j] + th * ph[j1];
-  }
-}
-
-// out (N x d) = sum_s in_s (N x kin) * M[s*kin : (s+1)*kin, :] with M (P x d,
-// column-major, ld ldM): the DEIM basis Psi = Y V diag(lam)^{-1/2}.
-template <int MC>
-__global__ void __launch_bounds__(256) rowgemm_real_kernel(RealList L, int kin, int N,
-                                                           const double* __restrict__ M, int ldM,
-                                                           int d, double* __restrict__ out) {
-  extern __shared__ double Mr[];
-  const int P = L.count * kin;
-  for (int t = threadIdx.x; t < P * d; t += blockDim.x) {
-    int r = t % P, c = t / P;
-    Mr[t] = M[(size_t)c * ldM + r];
-  }
-  __syncthreads();
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= N) return;
-  double acc[MC];
-#pragma unroll
-  for (int o = 0; o < MC; ++o) acc[o] = 0.0;
-  for (int s = 0; s < L.count; ++s)
-    for (int k = 0; k < kin; ++k) {
-      const double y = L.ptr[s][(size_t)k * N + l];
-      const double* mrow = Mr + s * kin + k;
-#pragma unroll
-      for (int o = 0; o < MC; ++o)
-        if (o < d) acc[o] = fma(y, mrow[o * P], acc[o]);
-    }
-#pragma unroll
-  for (int o = 0; o < MC; ++o)
-    if (o < d) out[(size_t)o * N + l] = acc[o];
-}
-
-// Sign convention of the DEIM basis: the entry of largest modulus of each
-// column (smallest row on ties) is made positive.  One block per column.
-__global__ void __launch_bounds__(1024) colsign_kernel(double* __restrict__ A, int N) {
-  __shared__ double sv[1024];
-  __shared__ int si[1024];
-  double* a = A + (size_t)blockIdx.x * N;
-  double best = -1.0;
-  int bi = 0x7fffffff;
-  for (int l = threadIdx.x; l < N; l += blockDim.x) {
-    double v = fabs(a[l]);
-    if (v > best) {
-      best = v;
-      bi = l;
-    }
-  }
-  sv[threadIdx.x] = best;
-  si[threadIdx.x] = bi;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      double v = sv[threadIdx.x + o];
-      int vi = si[threadIdx.x + o];
-      if (v > sv[threadIdx.x] || (v == sv[threadIdx.x] && vi < si[threadIdx.x])) {
-        sv[threadIdx.x] = v;
-        si[threadIdx.x] = vi;
-      }
-    }
-    __syncthreads();
-  }
-  const bool neg = a[si[0]] < 0.0;
-  __syncthreads();
-  if (neg)
-    for (int l = threadIdx.x; l < N; l += blockDim.x) a[l] = -a[l];
-}
-
-// Greedy DEIM residual r = psi_k - Psi[:, :k] c and its per-block argmax
-// of |r| (smallest index on ties).
-__global__ void __launch_bounds__(256) deim_residual_kernel(const double* __restrict__ Psi, int N,
-                                                            int k, const double* __restrict__ c,
-                                                            double* __restrict__ bval,
-                                                            int* __restrict__ bidx) {
-  __shared__ double cs[64];
-  __shared__ double sv[256];
-  __shared__ int si[256];
-  for (int t = threadIdx.x; t < k; t += blockDim.x) cs[t] = c[t];
-  __syncthreads();
-  double best = -1.0;
-  int bi = 0x7fffffff;
-  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < N; l += gridDim.x * blockDim.x) {
-    double r = Psi[(size_t)k * N + l];
-    for (int q = 0; q < k; ++q) r = fma(-Psi[(size_t)q * N + l], cs[q], r);
-    const double v = fabs(r);
-    if (v > best) {
-      best = v;
-      bi = l;
-    }
-  }
-  sv[threadIdx.x] = best;
-  si[threadIdx.x] = bi;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      double v = sv[threadIdx.x + o];
-      int vi = si[threadIdx.x + o];
-      if (v > sv[threadIdx.x] || (v == sv[threadIdx.x] && vi < si[threadIdx.x])) {
-        sv[threadIdx.x] = v;
-        si[threadIdx.x] = vi;
-      }
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    bval[blockIdx.x] = sv[0];
-    bidx[blockIdx.x] = si[0];
-  }
-}
-
-// Column sums of Psi (N x d), partial per block: part[b][j].
-__global__ void __launch_bounds__(256) colsum_partial_kernel(const double* __restrict__ Psi, int N,
-                                                             int d, double* __restrict__ part) {
-  __shared__ double red[8];
-  for (int j = 0; j < d; ++j) {
-    double s = 0.0;
-    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < N; l += gridDim.x * blockDim.x)
-      s += Psi[(size_t)j * N + l];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) part[(size_t)blockIdx.x * d + j] = s;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Fused gather + projection (eq. grads): g = U~^* G~ (n x p) with
@@ -613,21 +453,23 @@ __global__ void __launch_bounds__(256) reduce_partials2_kernel(const cplx* __res
 // Fused gather + basis velocity: out = G~ (-i h Q) + U~ MU (N x n), the
 // tangent step xi = h X~ of eq. Xdot in complex form (X~ = -i (G~ Q - U~ g~ Q)),
 // with G~ evaluated on the fly (not stored).  One thread per particle row;
-// the block walks the parameters in order with the field row of the next
-// parameter prefetched into the other half of a two-row LDS buffer.  Q
-// (p x n, ld p) and MU (n x n, ld n) as written by the dense kernels.
+// the coefficients, -i h Q and (when they fit) the field rows of all
+// parameters sit in LDS; ILP parameters are processed at a time so their
+// independent position / cell / lookup chains interleave.  Q (p x n, ld p)
+// and MU (n x n, ld n) as written by the dense kernels.
 // ---------------------------------------------------------------------------
-template <int NC>
+template <int NC, bool ET_LDS>
 __global__ void __launch_bounds__(256) gather_xi_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx,
     const double* __restrict__ factor, const double* __restrict__ e, double qm,
     const cplx* __restrict__ Q, const cplx* __restrict__ MU, double h, cplx* __restrict__ out) {
+  constexpr int ILP = (NC <= 8) ? 4 : 2;
   extern __shared__ double smem[];
   cplx* Zs = reinterpret_cast<cplx*>(smem);  // [p][NC], zero beyond n
   cplx* Qs = Zs + (size_t)p * NC;            // [p][NC]: -i h Q[c][k], zero beyond n
   cplx* Ms = Qs + (size_t)p * NC;            // [NC][NC]: MU[j][k] at Ms[j * NC + k]
   double* fs = reinterpret_cast<double*>(Ms + NC * NC);  // [p]
-  double* tb = fs + p;                       // [2][Nx]: field rows (q/m) e_c
+  double* et = fs + p;                       // [p][Nx] (ET_LDS)
   const int tid = threadIdx.x;
   for (int t = tid; t < p * NC; t += 256) {
     const int c = t / NC, k = t % NC;
@@ -640,7 +482,22 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
     Ms[t] = (j < n && k < n) ? MU[(size_t)k * n + j] : mk(0.0, 0.0);
   }
   for (int t = tid; t < p; t += 256) fs[t] = factor[t];
-  for (int t = tid; t < Nx; t += 256) tb[t] = qm * e[t];
+  if (ET_LDS) {
+    const int tot = p * Nx;
+    for (int t0 = 0; t0 < tot; t0 += 8 * 256) {
+      double v[8];
+#pragma unroll
+      for (int u8 = 0; u8 < 8; ++u8) {
+        const int t = t0 + u8 * 256 + tid;
+        v[u8] = (t < tot) ? e[t] : 0.0;
+      }
+#pragma unroll
+      for (int u8 = 0; u8 < 8; ++u8) {
+        const int t = t0 + u8 * 256 + tid;
+        if (t < tot) et[t] = qm * v[u8];
+      }
+    }
+  }
   const int l = blockIdx.x * 256 + tid;
   const bool valid = l < N;
   cplx u[NC], acc[NC];
@@ -651,8 +508,7 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
   }
   __syncthreads();
   // the padding (k >= n) is zero in u, Zs, Qs and Ms: those terms add exact
-  // zeros, so the loops run branch-free over NC.  First U~ MU, one row of MU
-  // at a time (keeps the register footprint to one row)
+  // zeros, so the loops run branch-free over NC.  First U~ MU.
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
     const cplx* mj = Ms + j * NC;
@@ -660,47 +516,47 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
     for (int k = 0; k < NC; ++k) cfma(acc[k], u[j], mj[k]);
     __builtin_amdgcn_sched_barrier(0);
   }
-#pragma unroll 1
-  for (int c = 0; c < p; ++c) {
-    // prefetch the next field row (Nx <= 1024: at most 4 per thread)
-    double pf[4];
-    const bool more = c + 1 < p;
+  // then G~ (-i h Q), ILP parameters at a time, accumulated in parameter order
+  for (int c0 = 0; c0 < p; c0 += ILP) {
+    double x0[ILP], x1[ILP], v0[ILP], v1[ILP];
 #pragma unroll
-    for (int u4 = 0; u4 < 4; ++u4) {
-      const int t = tid + u4 * 256;
-      pf[u4] = (more && t < Nx) ? e[(size_t)(c + 1) * Nx + t] : 0.0;
-    }
-    const double* te = tb + (c & 1) * Nx;
-    const cplx* zc = Zs + c * NC;
-    double x0 = 0.0, x1 = 0.0, v0 = 0.0, v1 = 0.0;
+    for (int q = 0; q < ILP; ++q) {
+      const cplx* zc = Zs + min(c0 + q, p - 1) * NC;
+      x0[q] = 0.0;
+      x1[q] = 0.0;
+      v0[q] = 0.0;
+      v1[q] = 0.0;
 #pragma unroll
-    for (int k = 0; k < NC; k += 2) {
-      const cplx za = zc[k], zb = zc[k + 1];
-      x0 = fma(u[k].re, za.re, x0);
-      x0 = fma(-u[k].im, za.im, x0);
-      v0 = fma(u[k].re, za.im, v0);
-      v0 = fma(u[k].im, za.re, v0);
-      x1 = fma(u[k + 1].re, zb.re, x1);
-      x1 = fma(-u[k + 1].im, zb.im, x1);
-      v1 = fma(u[k + 1].re, zb.im, v1);
-      v1 = fma(u[k + 1].im, zb.re, v1);
-    }
-    int j;
-    double th;
-    cell_of(x0 + x1, fs[c], Nx, j, th);
-    const cplx gv = mk(te[j], v0 + v1);
-    const cplx* qc = Qs + c * NC;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) cfma(acc[k], gv, qc[k]);
-    if (more) {
-      double* tn = tb + ((c + 1) & 1) * Nx;
-#pragma unroll
-      for (int u4 = 0; u4 < 4; ++u4) {
-        const int t = tid + u4 * 256;
-        if (t < Nx) tn[t] = qm * pf[u4];
+      for (int k = 0; k < NC; k += 2) {
+        const cplx za = zc[k], zb = zc[k + 1];
+        x0[q] = fma(u[k].re, za.re, x0[q]);
+        x0[q] = fma(-u[k].im, za.im, x0[q]);
+        v0[q] = fma(u[k].re, za.im, v0[q]);
+        v0[q] = fma(u[k].im, za.re, v0[q]);
+        x1[q] = fma(u[k + 1].re, zb.re, x1[q]);
+        x1[q] = fma(-u[k + 1].im, zb.im, x1[q]);
+        v1[q] = fma(u[k + 1].re, zb.im, v1[q]);
+        v1[q] = fma(u[k + 1].im, zb.re, v1[q]);
       }
     }
-    __syncthreads();
+    double F[ILP];
+#pragma unroll
+    for (int q = 0; q < ILP; ++q) {
+      const int c = min(c0 + q, p - 1);
+      int j;
+      double th;
+      cell_of(x0[q] + x1[q], fs[c], Nx, j, th);
+      F[q] = ET_LDS ? et[c * Nx + j] : qm * e[(size_t)c * Nx + j];
+    }
+#pragma unroll
+    for (int q = 0; q < ILP; ++q) {
+      if (c0 + q < p) {
+        const cplx gv = mk(F[q], v0[q] + v1[q]);
+        const cplx* qc = Qs + (c0 + q) * NC;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) cfma(acc[k], gv, qc[k]);
+      }
+    }
   }
   if (valid) {
 #pragma unroll
@@ -710,19 +566,418 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// DEIM basis, indices and weights (Sec. 4.3), N-wide passes.
+// ---------------------------------------------------------------------------
+
+// Dense solve of the k x k system in the augmented array A (row j at
+// A[j * DG_LD], right-hand side in column k) by Gaussian elimination with
+// partial pivoting (largest modulus, smallest row on ties); x receives the
+// solution.  Called by every thread of a 256-thread block (barriers inside);
+// rows are owned by the lanes of the first wavefront.  Returns nonzero (in
+// every thread) when a pivot is zero.
+#define DG_LD 65
+__device__ int dg_solve(double* A, int k, double* x, int* flag) {
+  const int tid = threadIdx.x;
+  if (tid == 0) *flag = 0;
+  __syncthreads();
+  for (int s = 0; s < k; ++s) {
+    if (tid < 64) {
+      double v = (tid >= s && tid < k) ? fabs(A[tid * DG_LD + s]) : -1.0;
+      int vi = tid;
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(v, o, 64);
+        const int oi = __shfl_xor(vi, o, 64);
+        if (ov > v || (ov == v && oi < vi)) {
+          v = ov;
+          vi = oi;
+        }
+      }
+      // every lane holds the pivot row vi; swap rows s and vi column-wise
+      if (vi != s)
+        for (int q = tid; q <= k; q += 64) {
+          const double t = A[s * DG_LD + q];
+          A[s * DG_LD + q] = A[vi * DG_LD + q];
+          A[vi * DG_LD + q] = t;
+        }
+      if (tid == 0 && !(v > 0.0)) *flag = 1;
+    }
+    __syncthreads();
+    if (*flag) return 1;
+    if (tid > s && tid < k) {
+      const double f = A[tid * DG_LD + s] / A[s * DG_LD + s];
+      for (int q = s + 1; q <= k; ++q) A[tid * DG_LD + q] = fma(-f, A[s * DG_LD + q], A[tid * DG_LD + q]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0)
+    for (int s = k - 1; s >= 0; --s) {
+      double v = A[s * DG_LD + k];
+      for (int q = s + 1; q < k; ++q) v = fma(-A[s * DG_LD + q], x[q], v);
+      x[s] = v / A[s * DG_LD + s];
+    }
+  __syncthreads();
+  return 0;
+}
+
+// winner of per-block (value, index) results: largest value, smallest index
+// on ties; computed by the first wavefront, returned in its lanes
+__device__ int dg_winner(const double* __restrict__ val, const int* __restrict__ idx, int nb) {
+  const int lane = threadIdx.x & 63;
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int b = lane; b < nb; b += 64) {
+    const double v = val[b];
+    const int vi = idx[b];
+    if (v > best || (v == best && vi < bi)) {
+      best = v;
+      bi = vi;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ov > best || (ov == best && oi < bi)) {
+      best = ov;
+      bi = oi;
+    }
+  }
+  return bi;
+}
+
+// Greedy DEIM step k (the selection rule of Sec. 4.3): l_k = argmax |r_k|,
+// r_k = psi_k - Psi_{k-1} c, (P^T Psi_{k-1}) c = P^T psi_k.  Each block first
+// takes the winner of the previous pass (pval, pidx: nprev block results),
+// which block 0 records as idx[k-1], solves the k x k system redundantly,
+// then writes the (value, index) of the largest residual over its rows
+// (smallest index on ties) to bval, bidx.  k = 0 takes r_0 = psi_0.
+__global__ void __launch_bounds__(256) deim_greedy_kernel(const double* __restrict__ Psi, int N,
+                                                          int k, int* __restrict__ idx,
+                                                          const double* __restrict__ pval,
+                                                          const int* __restrict__ pidx, int nprev,
+                                                          double* __restrict__ bval,
+                                                          int* __restrict__ bidx,
+                                                          int* __restrict__ flags) {
+  __shared__ double A[64 * DG_LD];
+  __shared__ double cs[64];
+  __shared__ int rows[64];
+  __shared__ int flag;
+  __shared__ double sv[4];
+  __shared__ int si[4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (k > 0) {
+    if (w == 0) {
+      int win = dg_winner(pval, pidx, nprev);
+      if (win < 0 || win >= N) {
+        // no finite residual anywhere: report, and keep the row in range
+        if (lane == 0 && blockIdx.x == 0 && flags) flags[0] |= 16;
+        win = 0;
+      }
+      if (lane == 0) {
+        rows[k - 1] = win;
+        if (blockIdx.x == 0) idx[k - 1] = win;
+      }
+      for (int t = lane; t < k - 1; t += 64) rows[t] = idx[t];
+    }
+    __syncthreads();
+    for (int t = tid; t < k * (k + 1); t += 256) {
+      const int j = t / (k + 1), q = t % (k + 1);
+      A[j * DG_LD + q] = Psi[(size_t)q * N + rows[j]];
+    }
+    __syncthreads();
+    if (dg_solve(A, k, cs, &flag)) {
+      if (tid == 0 && blockIdx.x == 0 && flags) flags[0] |= 16;
+      return;
+    }
+  }
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int l = blockIdx.x * 256 + tid; l < N; l += gridDim.x * 256) {
+    double r = Psi[(size_t)k * N + l];
+#pragma unroll 4
+    for (int q = 0; q < k; ++q) r = fma(-Psi[(size_t)q * N + l], cs[q], r);
+    const double v = fabs(r);
+    if (v > best) {
+      best = v;
+      bi = l;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ov > best || (ov == best && oi < bi)) {
+      best = ov;
+      bi = oi;
+    }
+  }
+  if (lane == 0) {
+    sv[w] = best;
+    si[w] = bi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int q = 1; q < 4; ++q)
+      if (sv[q] > best || (sv[q] == best && si[q] < bi)) {
+        best = sv[q];
+        bi = si[q];
+      }
+    bval[blockIdx.x] = best;
+    bidx[blockIdx.x] = bi;
+  }
+}
+
+// Last index l_{d-1} (winner of the last greedy pass) and the weights
+// w = (P^T Psi)^{-T} Psi^T 1 of eq. grHDD (the factor m_p^{-1} M_q is applied
+// in the gather); colpart holds per-block column sums of Psi (ncp blocks).
+__global__ void __launch_bounds__(256) deim_weights2_kernel(
+    const double* __restrict__ Psi, int N, int d, int* __restrict__ idx,
+    const double* __restrict__ pval, const int* __restrict__ pidx, int nprev,
+    const double* __restrict__ colpart, int ncp, double* __restrict__ wout,
+    int* __restrict__ flags) {
+  __shared__ double A[64 * DG_LD];
+  __shared__ double xs[64];
+  __shared__ int rows[64];
+  __shared__ int flag;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (w == 0) {
+    int win = dg_winner(pval, pidx, nprev);
+    if (win < 0 || win >= N) {
+      if (lane == 0 && flags) flags[0] |= 16;
+      win = 0;
+    }
+    if (lane == 0) {
+      rows[d - 1] = win;
+      idx[d - 1] = win;
+    }
+    for (int t = lane; t < d - 1; t += 64) rows[t] = idx[t];
+  }
+  __syncthreads();
+  // (P^T Psi)^T: row q holds Psi[rows[j], q] over j; right-hand side Psi^T 1
+  for (int t = tid; t < d * d; t += 256) {
+    const int q = t / d, j = t % d;
+    A[q * DG_LD + j] = Psi[(size_t)q * N + rows[j]];
+  }
+  // column sums of Psi: one wavefront per column, lane-strided partial sums
+  // combined by a fixed butterfly
+  for (int q = w; q < d; q += 4) {
+    double s = 0.0;
+    for (int b = lane; b < ncp; b += 64) s += colpart[(size_t)b * d + q];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) A[q * DG_LD + d] = s;
+  }
+  __syncthreads();
+  if (dg_solve(A, d, xs, &flag)) {
+    if (tid == 0 && flags) flags[0] |= 16;
+    return;
+  }
+  for (int t = tid; t < d; t += 256) wout[t] = xs[t];
+}
+
+// Psi (N x d) = sum_s Y_s M[s*kin:(s+1)*kin, :] (the DEIM basis Y V diag(lam)^{-1/2},
+// M = P x d column-major, ld ldM), plus per-block column sums of Psi into
+// colpart[blockIdx][c] (fixed order: wavefront butterflies, then the four
+// wavefronts in order).  Grid-stride over rows; loads in batches of four.
+template <int MC>
+__global__ void __launch_bounds__(256) psi_colsum_kernel(RealList L, int kin, int N,
+                                                         const double* __restrict__ M, int ldM,
+                                                         int d, double* __restrict__ out,
+                                                         double* __restrict__ colpart) {
+  extern __shared__ double Mr[];   // [P][MC], zero beyond d; then [4][MC] wavefront sums
+  const int P = L.count * kin;
+  for (int t = threadIdx.x; t < P * MC; t += blockDim.x) {
+    const int r = t / MC, c = t % MC;
+    Mr[t] = (c < d) ? M[(size_t)c * ldM + r] : 0.0;
+  }
+  __syncthreads();
+  double csum[MC];
+#pragma unroll
+  for (int o = 0; o < MC; ++o) csum[o] = 0.0;
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < N; l += gridDim.x * blockDim.x) {
+    double acc[MC];
+#pragma unroll
+    for (int o = 0; o < MC; ++o) acc[o] = 0.0;
+    for (int s = 0; s < L.count; ++s) {
+      const double* ys = L.ptr[s] + l;
+      int k = 0;
+      for (; k + 4 <= kin; k += 4) {
+        double y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] = ys[(size_t)(k + u) * N];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double* mrow = Mr + (s * kin + k + u) * MC;
+#pragma unroll
+          for (int o = 0; o < MC; ++o) acc[o] = fma(y[u], mrow[o], acc[o]);
+        }
+      }
+      for (; k < kin; ++k) {
+        const double y = ys[(size_t)k * N];
+        const double* mrow = Mr + (s * kin + k) * MC;
+#pragma unroll
+        for (int o = 0; o < MC; ++o) acc[o] = fma(y, mrow[o], acc[o]);
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < MC; ++o) {
+      if (o < d) out[(size_t)o * N + l] = acc[o];
+      csum[o] += acc[o];
+    }
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 0; o < MC; ++o)
+    for (int q = 32; q > 0; q >>= 1) csum[o] += __shfl_xor(csum[o], q, 64);
+  __syncthreads();
+  double* ws = Mr;
+  if (lane == 0)
+#pragma unroll
+    for (int o = 0; o < MC; ++o) ws[w * MC + o] = csum[o];
+  __syncthreads();
+  for (int o = threadIdx.x; o < d; o += blockDim.x)
+    colpart[(size_t)blockIdx.x * d + o] = ((ws[o] + ws[MC + o]) + ws[2 * MC + o]) + ws[3 * MC + o];
+}
+
+// DEIM snapshot Lambda^0(X_r^i) Phi^i at every particle (Sec. 4.3, eq. Ydeim)
+// for the parameters sub[0..psub): (1 - theta) Phi_j + theta Phi_{j+1}, written
+// as column c of Y (N x psub).  The subset's coefficients (zero-padded to NC),
+// factors and, when they fit (PH_LDS), potentials sit in LDS; positions use the
+// deposit's operation order.
+template <int NC, bool PH_LDS>
+__global__ void __launch_bounds__(256) snapshot_kernel(const cplx* __restrict__ U, int N, int n,
+                                                       const cplx* __restrict__ Z,
+                                                       const int* __restrict__ sub, int psub,
+                                                       int Nx, const double* __restrict__ factor,
+                                                       const double* __restrict__ phi,
+                                                       double* __restrict__ Y) {
+  extern __shared__ double smem[];
+  cplx* Zs = reinterpret_cast<cplx*>(smem);                 // [psub][NC]
+  double* fs = reinterpret_cast<double*>(Zs + psub * NC);    // [psub]
+  double* ph = fs + psub;                                    // [psub][Nx] (PH_LDS)
+  const int tid = threadIdx.x;
+  for (int t = tid; t < psub * NC; t += 256) {
+    const int c = t / NC, k = t % NC;
+    Zs[t] = (k < n) ? Z[(size_t)sub[c] * n + k] : mk(0.0, 0.0);
+  }
+  for (int c = tid; c < psub; c += 256) fs[c] = factor[sub[c]];
+  if (PH_LDS)
+    for (int t = tid; t < psub * Nx; t += 256) {
+      const int c = t / Nx, j = t % Nx;
+      ph[t] = phi[(size_t)sub[c] * Nx + j];
+    }
+  __syncthreads();
+  const int l = blockIdx.x * 256 + tid;
+  if (l >= N) return;
+  cplx u[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) u[k] = (k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
+  for (int c = 0; c < psub; ++c) {
+    const cplx* zc = Zs + c * NC;
+    double x0 = 0.0, x1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NC; k += 2) {
+      x0 = fma(u[k].re, zc[k].re, x0);
+      x0 = fma(-u[k].im, zc[k].im, x0);
+      x1 = fma(u[k + 1].re, zc[k + 1].re, x1);
+      x1 = fma(-u[k + 1].im, zc[k + 1].im, x1);
+    }
+    int j;
+    double th;
+    cell_of(x0 + x1, fs[c], Nx, j, th);
+    const int j1 = (j + 1 == Nx) ? 0 : j + 1;
+    const double* pc = PH_LDS ? ph + c * Nx : phi + (size_t)sub[c] * Nx;
+    Y[(size_t)c * N + l] = (1.0 - th) * pc[j] + th * pc[j1];
+  }
+}
+
+// Real product C = A^T B (A: N x a, B = [B_0 ...] N x b, column-major,
+// a, b <= 64), split over row blocks: row chunks staged through LDS with
+// coalesced loads, 4 x 4 register tiles, tile sums in a padded entry-major
+// LDS layout, block partials part[kb][ib * a + ia] summed by
+// reduce_gram_block_kernel.
+__global__ void __launch_bounds__(256) gemm_real_tn_kernel(RealList A, int ka, int a, RealList B,
+                                                           int kbcols, int b, int N, int rk, int TR,
+                                                           double* __restrict__ part) {
+  extern __shared__ double smr[];   // staging [a + b][TR], later tile sums [16][GEMM_RED_LD]
+  __shared__ const double* colp[128];
+  const int tid = threadIdx.x;
+  if (tid < a + b)
+    colp[tid] = (tid < a) ? A.ptr[tid / ka] + (size_t)(tid % ka) * N
+                          : B.ptr[(tid - a) / kbcols] + (size_t)((tid - a) % kbcols) * N;
+  const int kb = blockIdx.x;
+  const int r0 = kb * rk;
+  const int r1 = min(N, r0 + rk);
+  const int nta = (a + 3) / 4, ntb = (b + 3) / 4, nt = nta * ntb;
+  const int R = max(1, 256 / nt);
+  const int tile = tid / R, rg = tid % R;
+  const bool owner = tile < nt;
+  const int ta0 = (tile % nta) * 4, tb0 = (tile / nta) * 4;
+  const int nst = a + b;
+  double* sA = smr;
+  double* sB = smr + (size_t)a * TR;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int c0 = r0; c0 < r1; c0 += TR) {
+    const int tn = min(TR, r1 - c0);
+    __syncthreads();
+    const int tot = nst * TR;
+    for (int t0 = 0; t0 < tot; t0 += 16 * 256) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int t = t0 + u * 256 + tid;
+        v[u] = 0.0;
+        if (t < tot) {
+          const int col = t / TR, row = t % TR;
+          if (row < tn) v[u] = colp[col][c0 + row];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int t = t0 + u * 256 + tid;
+        if (t < tot) smr[t] = v[u];
+      }
+    }
+    __syncthreads();
+    if (owner) {
+      for (int row = rg; row < tn; row += R) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = (ta0 + i < a) ? sA[(ta0 + i) * TR + row] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = (tb0 + j < b) ? sB[(tb0 + j) * TR + row] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+      }
+    }
+  }
+  __syncthreads();
+  double* red = smr;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[(i * 4 + j) * GEMM_RED_LD + tid] = acc[i][j];
+  __syncthreads();
+  const int nout = a * b;
+  for (int o = tid; o < nt * 16; o += blockDim.x) {
+    const int tl = o / 16, q = o % 16;
+    double s2 = 0.0;
+#pragma unroll 8
+    for (int g = 0; g < R; ++g) s2 += red[q * GEMM_RED_LD + tl * R + g];
+    const int ia = (tl % nta) * 4 + q / 4, ib = (tl / nta) * 4 + q % 4;
+    if (ia < a && ib < b) part[(size_t)kb * nout + (size_t)ib * a + ia] = s2;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 bool fused_gradient_ok(int n) { return n <= 16; }
 
-// register width of the fused kernels: an even count >= n (the position sums
-// split into even and odd k, so every even width gives the deposit's cells)
-static int fused_nc(int n) {
-  if (n <= 4) return 4;
-  if (n <= 6) return 6;
-  if (n <= 8) return 8;
-  if (n <= 12) return 12;
-  return 16;
-}
+static int fused_nc(int n) { return nc_even(n); }
 
 void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p,
                            int Nx, const double* factor, const double* e, double qm,
@@ -779,18 +1034,31 @@ void launch_gather_xi(hipStream_t s, const cplx* U, int N, int n, const cplx* Z,
                       const double* factor, const double* e, double qm, const cplx* Q,
                       const cplx* MU, double h, cplx* out) {
   const int nc = fused_nc(n);
-  const size_t sh = (size_t)(2 * p * nc + nc * nc) * sizeof(cplx) + (size_t)(p + 2 * Nx) * sizeof(double);
+  const size_t base = (size_t)(2 * p * nc + nc * nc) * sizeof(cplx) + (size_t)p * sizeof(double);
+  const size_t et_bytes = (size_t)p * Nx * sizeof(double);
+  const bool et_lds = base + et_bytes <= 76 * 1024;
+  const size_t sh = base + (et_lds ? et_bytes : 0);
   dim3 grid((N + 255) / 256);
-#define GXK(NCV)                                                                              \
-  ALLOW_BIG_LDS(gather_xi_kernel<NCV>);                                                     \
-  hipLaunchKernelGGL(gather_xi_kernel<NCV>, grid, dim3(256), sh, s, U, N, n, Z, p, Nx, factor, e, \
-                     qm, Q, MU, h, out)
-  switch (nc) {
-    case 4: GXK(4); break;
-    case 6: GXK(6); break;
-    case 8: GXK(8); break;
-    case 12: GXK(12); break;
-    default: GXK(16); break;
+#define GXK(NCV, ETV)                                                                          \
+  ALLOW_BIG_LDS((gather_xi_kernel<NCV, ETV>));                                               \
+  hipLaunchKernelGGL((gather_xi_kernel<NCV, ETV>), grid, dim3(256), sh, s, U, N, n, Z, p, Nx,  \
+                     factor, e, qm, Q, MU, h, out)
+  if (et_lds) {
+    switch (nc) {
+      case 4: GXK(4, true); break;
+      case 6: GXK(6, true); break;
+      case 8: GXK(8, true); break;
+      case 12: GXK(12, true); break;
+      default: GXK(16, true); break;
+    }
+  } else {
+    switch (nc) {
+      case 4: GXK(4, false); break;
+      case 6: GXK(6, false); break;
+      case 8: GXK(8, false); break;
+      case 12: GXK(12, false); break;
+      default: GXK(16, false); break;
+    }
   }
 #undef GXK
 }
@@ -909,132 +1177,7 @@ void launch_deim_gather(hipStream_t s, const cplx* U, int N, int n, const cplx* 
                      qm, idx, w, d, active, gF);
 }
 
-void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, const int* sub,
-                     int psub, int Nx, const double* factor, const double* phi, double* Y) {
-  int nc = nc_bucket(n);
-  dim3 grid((N + 255) / 256);
-#define SN(NCV)                                                                               \
-  hipLaunchKernelGGL(snapshot_kernel<NCV>, grid, dim3(256), 0, s, U, N, n, Z, sub, psub, Nx, \
-                     factor, phi, Y)
-  switch (nc) {
-    case 4: SN(4); break;
-    case 8: SN(8); break;
-    case 16: SN(16); break;
-    default: SN(32); break;
-  }
-#undef SN
-}
 
-void launch_rowgemm_real(hipStream_t s, const double* const* in, int nin, int kin, int N,
-                         const double* M, int ldM, int d, double* out) {
-  RealList L{};
-  for (int q = 0; q < nin; ++q) L.ptr[q] = in[q];
-  L.count = nin;
-  size_t sh = (size_t)nin * kin * d * sizeof(double);
-  dim3 grid((N + 255) / 256);
-  if (d <= 16) {
-    ALLOW_BIG_LDS(rowgemm_real_kernel<16>);
-    hipLaunchKernelGGL(rowgemm_real_kernel<16>, grid, dim3(256), sh, s, L, kin, N, M, ldM, d, out);
-  } else if (d <= 32) {
-    ALLOW_BIG_LDS(rowgemm_real_kernel<32>);
-    hipLaunchKernelGGL(rowgemm_real_kernel<32>, grid, dim3(256), sh, s, L, kin, N, M, ldM, d, out);
-  } else {
-    ALLOW_BIG_LDS(rowgemm_real_kernel<64>);
-    hipLaunchKernelGGL(rowgemm_real_kernel<64>, grid, dim3(256), sh, s, L, kin, N, M, ldM, d, out);
-  }
-}
-
-void launch_colsign(hipStream_t s, double* A, int N, int d) {
-  hipLaunchKernelGGL(colsign_kernel, dim3(d), dim3(1024), 0, s, A, N);
-}
-
-void launch_deim_residual(hipStream_t s, const double* Psi, int N, int k, const double* c,
-                          int nblk, double* bval, int* bidx) {
-  hipLaunchKernelGGL(deim_residual_kernel, dim3(nblk), dim3(256), 0, s, Psi, N, k, c, bval, bidx);
-}
-
-void launch_colsum_partial(hipStream_t s, const double* Psi, int N, int d, int nblk,
-                           double* part) {
-  hipLaunchKernelGGL(colsum_partial_kernel, dim3(nblk), dim3(256), 0, s, Psi, N, d, part);
-}
-
-// ---------------------------------------------------------------------------
-// Real product C = A^T B (A: N x a, B: N x b, both real column-major lists,
-// a, b <= 64), split over row blocks like gemm_ah_b_kernel.  Output partials
-// part[kb][ib * a + ia].
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) gemm_real_tn_kernel(RealList A, int ka, int a, RealList B,
-                                                           int kbcols, int b, int N, int rk,
-                                                           double* __restrict__ part) {
-  // tile sums, entry-major with a padded stride (conflict-free writes)
-  __shared__ double red[16 * GEMM_RED_LD];
-  const int kb = blockIdx.x;
-  const int r0 = kb * rk;
-  const int r1 = min(N, r0 + rk);
-  const int nta = (a + 3) / 4, ntb = (b + 3) / 4, nt = nta * ntb;
-  const int R = max(1, 256 / nt);
-  const int tid = threadIdx.x;
-  const int tile = tid / R, rg = tid % R;
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  if (tile < nt) {
-    const int ta0 = (tile % nta) * 4, tb0 = (tile / nta) * 4;
-    const double* ap[4];
-    const double* bp[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int ca = ta0 + i, cb = tb0 + i;
-      ap[i] = (ca < a) ? A.ptr[ca / ka] + (size_t)(ca % ka) * N : nullptr;
-      bp[i] = (cb < b) ? B.ptr[cb / kbcols] + (size_t)(cb % kbcols) * N : nullptr;
-    }
-    int l = r0 + rg;
-    for (; l + R < r1; l += 2 * R) {
-      double av[2][4], bv[2][4];
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          av[u][i] = ap[i] ? ap[i][l + u * R] : 0.0;
-          bv[u][i] = bp[i] ? bp[i][l + u * R] : 0.0;
-        }
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[u][i], bv[u][j], acc[i][j]);
-    }
-    for (; l < r1; l += R) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        av[i] = ap[i] ? ap[i][l] : 0.0;
-        bv[i] = bp[i] ? bp[i][l] : 0.0;
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) red[(i * 4 + j) * GEMM_RED_LD + tid] = acc[i][j];
-  __syncthreads();
-  const int nout = a * b;
-  for (int o = tid; o < nt * 16; o += blockDim.x) {
-    const int tl = o / 16, q = o % 16;
-    double sm = 0.0;
-#pragma unroll 8
-    for (int g = 0; g < R; ++g) sm += red[q * GEMM_RED_LD + tl * R + g];
-    const int ia = (tl % nta) * 4 + q / 4, ib = (tl / nta) * 4 + q % 4;
-    if (ia < a && ib < b) part[(size_t)kb * nout + (size_t)ib * a + ia] = sm;
-  }
-}
 
 // Sum the partials of a real product and scatter the a x b result into the
 // symmetric P x P matrix S at rows r0.. (and the transpose at columns r0..).
@@ -1065,14 +1208,95 @@ void launch_gram_block_real(hipStream_t s, const double* Ynew, const double* con
   B.count = nslots;
   const int a = psub, b = psub * nslots;
   int nkb = (N + 127) / 128;
-  if (nkb > 256) nkb = 256;
+  if (nkb > 512) nkb = 512;
   const int cap = nkb_cap / (a * b);
   if (nkb > cap) nkb = cap;
   if (nkb < 1) nkb = 1;
   const int rk = (N + nkb - 1) / nkb;
   nkb = (N + rk - 1) / rk;
-  hipLaunchKernelGGL(gemm_real_tn_kernel, dim3(nkb), dim3(256), 0, s, A, psub, a, B, psub, b, N, rk,
-                     part);
+  int TR = 256;
+  while (TR > 32 && (a + b) * TR > 8192) TR >>= 1;
+  size_t sh = (size_t)(a + b) * TR * sizeof(double);
+  if (sh < (size_t)16 * GEMM_RED_LD * sizeof(double)) sh = (size_t)16 * GEMM_RED_LD * sizeof(double);
+  ALLOW_BIG_LDS(gemm_real_tn_kernel);
+  hipLaunchKernelGGL(gemm_real_tn_kernel, dim3(nkb), dim3(256), sh, s, A, psub, a, B, psub, b, N, rk,
+                     TR, part);
   hipLaunchKernelGGL(reduce_gram_block_kernel, dim3((a * b + 3) / 4), dim3(256), 0, s, part, nkb, a,
                      b, b, r0, S);
+}
+
+void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, const int* sub,
+                     int psub, int Nx, const double* factor, const double* phi, double* Y) {
+  const int nc = (n <= 16) ? fused_nc(n) : 32;
+  const size_t base = (size_t)psub * nc * sizeof(cplx) + (size_t)psub * sizeof(double);
+  const size_t phb = (size_t)psub * Nx * sizeof(double);
+  const bool ph_lds = base + phb <= 96 * 1024;
+  const size_t sh = base + (ph_lds ? phb : 0);
+  dim3 grid((N + 255) / 256);
+#define SN(NCV, PV)                                                                          \
+  ALLOW_BIG_LDS((snapshot_kernel<NCV, PV>));                                               \
+  hipLaunchKernelGGL((snapshot_kernel<NCV, PV>), grid, dim3(256), sh, s, U, N, n, Z, sub, psub, \
+                     Nx, factor, phi, Y)
+  if (ph_lds) {
+    switch (nc) {
+      case 4: SN(4, true); break;
+      case 6: SN(6, true); break;
+      case 8: SN(8, true); break;
+      case 12: SN(12, true); break;
+      case 16: SN(16, true); break;
+      default: SN(32, true); break;
+    }
+  } else {
+    switch (nc) {
+      case 4: SN(4, false); break;
+      case 6: SN(6, false); break;
+      case 8: SN(8, false); break;
+      case 12: SN(12, false); break;
+      case 16: SN(16, false); break;
+      default: SN(32, false); break;
+    }
+  }
+#undef SN
+}
+
+int psi_blocks(int N) {
+  int nb = (N + 255) / 256;
+  return nb > 512 ? 512 : nb;
+}
+
+void launch_psi_colsum(hipStream_t s, const double* const* in, int nin, int kin, int N,
+                       const double* M, int ldM, int d, double* out, double* colpart) {
+  RealList L{};
+  for (int q = 0; q < nin; ++q) L.ptr[q] = in[q];
+  L.count = nin;
+  const int P = nin * kin;
+  const int mc = (d <= 8) ? 8 : (d <= 16) ? 16 : (d <= 32) ? 32 : 64;
+  size_t sh = (size_t)P * mc * sizeof(double);
+  if (sh < (size_t)4 * mc * sizeof(double)) sh = (size_t)4 * mc * sizeof(double);
+  dim3 grid(psi_blocks(N));
+#define PC(MCV)                                                                                  \
+  ALLOW_BIG_LDS(psi_colsum_kernel<MCV>);                                                       \
+  hipLaunchKernelGGL(psi_colsum_kernel<MCV>, grid, dim3(256), sh, s, L, kin, N, M, ldM, d, out, \
+                     colpart)
+  switch (mc) {
+    case 8: PC(8); break;
+    case 16: PC(16); break;
+    case 32: PC(32); break;
+    default: PC(64); break;
+  }
+#undef PC
+}
+
+void launch_deim_greedy(hipStream_t s, const double* Psi, int N, int k, int* idx,
+                        const double* pval, const int* pidx, int nprev, int nblk, double* bval,
+                        int* bidx, int* flags) {
+  hipLaunchKernelGGL(deim_greedy_kernel, dim3(nblk), dim3(256), 0, s, Psi, N, k, idx, pval, pidx,
+                     nprev, bval, bidx, flags);
+}
+
+void launch_deim_weights2(hipStream_t s, const double* Psi, int N, int d, int* idx,
+                          const double* pval, const int* pidx, int nprev, const double* colpart,
+                          int ncp, double* w, int* flags) {
+  hipLaunchKernelGGL(deim_weights2_kernel, dim3(1), dim3(256), 0, s, Psi, N, d, idx, pval, pidx,
+                     nprev, colpart, ncp, w, flags);
 }

@@ -277,6 +277,29 @@ def test_rom_steps_parity_adaptive(name, kw, two_n, steps):
     assert _rel(_np(H), Ho) < _bound(sR)
 
 
+def test_rom_full_size_workload_parity():
+    """The benchmark's own shapes (N = 100000, p = 64, Nx = 128, 2n = 10, the
+    launch configuration bench.py times): two steps from the oracle's
+    initial state with identical iteration counts, and R = U Z on every row
+    within the conditioning-aware bound."""
+    binding, torch = _b()
+    w, e = _ens("twostream_deim")
+    _say("rom full size", w["N"], w["p"], w["Nx"])
+    cfg, st = _oracle_state(w, e, 10, fp_tol=1e-10)
+    st_s = rom.RomState(U=st.U.copy(), Z=st.Z.copy(), L=st.L)
+    sU, sZ, sR = _oracle_sensitivity(st_s, cfg, 6, steps=2)
+    r = _gpu_rom(binding, w, e, 10, fp_tol=1e-10)
+    _set_from_oracle(r, st, torch)
+    for s in range(2):
+        info = r.step(1)
+        assert rom.prk_step(st, cfg) == rom.OK
+        assert info["iters"] == st.last_iters, (s, info, st.last_iters)
+    X, V = r.reconstruct()
+    Xo, Vo = rom.reconstruct(st)
+    assert _rel(_np(X).T, Xo) < _bound(sR), sR
+    assert _rel(_np(V).T, Vo) < _bound(sR), sR
+
+
 def test_rom_enoconv_keeps_state():
     binding, torch = _b()
     w, e = _ens("landau_tiny", N=2000)
