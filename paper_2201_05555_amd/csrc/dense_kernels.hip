@@ -1301,19 +1301,24 @@ void launch_dense_indicator(hipStream_t s, const double* colsq, const cplx* g, i
 
 // ---------------------------------------------------------------------------
 // Leading eigenpairs of a real symmetric matrix (n <= 64, d <= n) in one
-// wavefront.  Lane r keeps row r of the matrix in registers through a
-// Householder tridiagonalisation (the reflectors go to LDS); the d largest
-// eigenvalues of the tridiagonal T are found by multisection on Sturm counts
-// (a group of lanes per eigenvalue, several points per lane); lane j then
-// computes eigenvector j by inverse iteration (banded Gaussian elimination
-// with partial pivoting on T - lambda_j I, vector in registers, factors in
-// LDS), back-transforms it through the reflectors, and a Cholesky QR pass
-// orthonormalises the d vectors.  Output: lam (d, decreasing) and V (n x d,
-// column-major); bit 32 of flags[0] is set if the vectors are rank deficient.
+// workgroup of four wavefronts (one per SIMD of the CU).
+//  * Householder tridiagonalisation: lane r of wavefront w keeps entries
+//    16w .. 16w+15 of row r in registers; the column being reduced is
+//    published through LDS by the wavefront that owns it; each wavefront
+//    forms its part of p = t A v, the four parts are added in LDS in a fixed
+//    order, and every wavefront applies the rank-2 update to its columns
+//    (v and w are read from the lanes that own them with readlane).
+//  * The d largest eigenvalues of the tridiagonal T by multisection on
+//    Sturm counts: 256 / d lanes per eigenvalue.
+//  * Eigenvector j by inverse iteration (banded Gaussian elimination with
+//    partial pivoting on T - lambda_j I; vector in registers, factors in LDS)
+//    in lane j of the first wavefront; back-transform through the stored
+//    reflectors with the rows split over the four wavefronts; Cholesky QR.
+// Output: lam (d, decreasing), V (n x d, column-major); bit 32 of flags[0]
+// is set if the vectors are rank deficient.
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int TE_M = 64;   // largest order
-constexpr int TE_NP = 1;   // Sturm-count points per lane per multisection round
 
 // 1/x to full double precision for finite x with |x| >= 1e-290: the hardware
 // estimate refined by two Newton steps
@@ -1357,18 +1362,20 @@ __device__ __forceinline__ double te_wave_sum(double v) {
 }
 }  // namespace
 
-__global__ void __launch_bounds__(64) dense_topeig_kernel(const double* __restrict__ G, int n, int d,
-                                                          double* __restrict__ V,
-                                                          double* __restrict__ lam,
-                                                          int* __restrict__ flags) {
+__global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restrict__ G, int n, int d,
+                                                           double* __restrict__ V,
+                                                           double* __restrict__ lam,
+                                                           int* __restrict__ flags) {
   constexpr int M = TE_M;
+  constexpr int CW = 16;                // columns per wavefront
   __shared__ double H[M * M];          // H[k * M + i]: reflector k (zero for i <= k)
   __shared__ double W[3 * M * M];      // elimination factors; later vectors and Gram
-  __shared__ double bc[M];             // broadcast of w in the two-sided update
+  __shared__ double colk[M];           // column being reduced
+  __shared__ double ps[4 * M];         // per-wavefront parts of p (and of the back-transform dots)
+  __shared__ double vw[4 * 2 * M];     // per-wavefront copies of v and w
   __shared__ double tau[M], dd[M], ee[M], e2[M], lamg[M];
-  __shared__ double msx[M * TE_NP];
-  __shared__ int msc[M * TE_NP];
-  const int r = threadIdx.x;
+  const int tid = threadIdx.x, r = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
 #ifdef SYMROM_TOPEIG_TIMING
   unsigned long long tsv[6];
   tsv[0] = wall_clock64();
@@ -1376,21 +1383,22 @@ __global__ void __launch_bounds__(64) dense_topeig_kernel(const double* __restri
 #else
 #define TS(k)
 #endif
-  // ---- tridiagonalisation, row r of A in registers ----
-  double a[M];
+  // ---- tridiagonalisation ----
+  double a[CW];
 #pragma unroll
-  for (int j = 0; j < M; ++j) a[j] = (r < n && j < n) ? G[(size_t)j * n + r] : 0.0;
+  for (int jj = 0; jj < CW; ++jj) {
+    const int j = CW * w + jj;
+    a[jj] = (r < n && j < n) ? G[(size_t)j * n + r] : 0.0;
+  }
   for (int k = 0; k + 2 < n; ++k) {
-    // xr = A[r][k], the column below the diagonal for r > k
-    double xr = 0.0;
+    if (w == (k >> 4)) {
+      double xk = 0.0;
 #pragma unroll
-    for (int jc = 0; jc < M; jc += 16) {
-      if ((k >> 4) == (jc >> 4)) {
-#pragma unroll
-        for (int j = jc; j < jc + 16; ++j) xr = (j == k) ? a[j] : xr;
-      }
+      for (int jj = 0; jj < CW; ++jj) xk = (jj == (k & 15)) ? a[jj] : xk;
+      colk[r] = xk;
     }
-    if (!(r > k)) xr = 0.0;
+    __syncthreads();
+    const double xr = (r > k) ? colk[r] : 0.0;
     const double sig = te_wave_sum(xr * xr);
     const double x0 = te_lane(xr, k + 1);
     double t = 0.0, alpha = x0;
@@ -1403,55 +1411,57 @@ __global__ void __launch_bounds__(64) dense_topeig_kernel(const double* __restri
       }
     }
     const double vr = (r > k && r < n) ? (r == k + 1 ? xr - alpha : xr) : 0.0;
-    H[k * M + r] = vr;
-    if (r == 0) {
-      tau[k] = t;
-      ee[k] = alpha;
-    }
-    __syncthreads();
-    if (t != 0.0) {
-      const double* hk = H + k * M;
-      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-#pragma unroll
-      for (int jc = 0; jc < M; jc += 16) {
-        if (k < jc + 15) {
-#pragma unroll
-          for (int j = jc; j < jc + 16; j += 4) {
-            p0 = fma(a[j], hk[j], p0);
-            p1 = fma(a[j + 1], hk[j + 1], p1);
-            p2 = fma(a[j + 2], hk[j + 2], p2);
-            p3 = fma(a[j + 3], hk[j + 3], p3);
-          }
-        }
+    if (w == 0) {
+      H[k * M + r] = vr;
+      if (r == 0) {
+        tau[k] = t;
+        ee[k] = alpha;
       }
-      const double pr = (r > k && r < n) ? t * ((p0 + p1) + (p2 + p3)) : 0.0;
+    }
+    if (t != 0.0) {
+      // v and w of this wavefront's columns: each wavefront publishes its own
+      // (identical) copy in LDS and reads it back (same wavefront: ordered)
+      double* vb = vw + w * 2 * M;
+      double* wb = vb + M;
+      vb[r] = vr;
+      __builtin_amdgcn_wave_barrier();
+      double vj[CW];
+#pragma unroll
+      for (int jj = 0; jj < CW; ++jj) vj[jj] = vb[CW * w + jj];
+      double pw = 0.0, pw2 = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < CW; jj += 2) {
+        pw = fma(a[jj], vj[jj], pw);
+        pw2 = fma(a[jj + 1], vj[jj + 1], pw2);
+      }
+      ps[w * M + r] = pw + pw2;
+      __syncthreads();
+      const double pr = (r > k && r < n)
+                            ? t * (((ps[r] + ps[M + r]) + ps[2 * M + r]) + ps[3 * M + r])
+                            : 0.0;
       const double kv = te_wave_sum(vr * pr);
       const double wr = pr - 0.5 * t * kv * vr;   // zero for r <= k
-      bc[r] = wr;
+      wb[r] = wr;
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int jj = 0; jj < CW; ++jj) a[jj] -= vr * wb[CW * w + jj] + wr * vj[jj];
+    } else {
+      // keep colk stable until every wavefront has read it
       __syncthreads();
-#pragma unroll
-      for (int jc = 0; jc < M; jc += 16) {
-        if (k < jc + 15) {
-#pragma unroll
-          for (int j = jc; j < jc + 16; ++j) a[j] -= vr * bc[j] + wr * hk[j];
-        }
-      }
     }
-    __syncthreads();
   }
+  __syncthreads();
   {
-    // diagonal and last subdiagonal entry
-    double dv = 0.0, sv = 0.0;
+    // diagonal and last subdiagonal entry from the wavefront owning the column
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      dv = (j == r) ? a[j] : dv;
-      sv = (j + 1 == r) ? a[j] : sv;
+    for (int jj = 0; jj < CW; ++jj) {
+      const int j = CW * w + jj;
+      if (j == r && r < n) dd[r] = a[jj];
+      if (n >= 2 && j == n - 2 && r == n - 1) ee[n - 2] = a[jj];
     }
-    if (r < n) dd[r] = dv;
-    if (n >= 2 && r == n - 1) ee[n - 2] = sv;
-    if (r == n - 1 || r >= n) ee[r] = 0.0;
+    if (w == 0 && (r == n - 1 || r >= n)) ee[r] = 0.0;
     __syncthreads();
-    if (r < n) e2[r] = ee[r] * ee[r];
+    if (w == 0 && r < n) e2[r] = ee[r] * ee[r];
     __syncthreads();
   }
   TS(1);
@@ -1464,101 +1474,90 @@ __global__ void __launch_bounds__(64) dense_topeig_kernel(const double* __restri
     e2max = fmax(e2max, e2[i]);
   }
   const double scale = fmax(fabs(lo), fabs(hi));
-  // lane i holds d_i, e_i and e_i^2 (read back by readlane in the recurrences)
-  const double ddl = (r < n) ? dd[r] : 0.0, eel = ee[r], e2l = (r < n) ? e2[r] : 0.0;
+  // lane i of every wavefront holds d_i, e_i (read back by readlane later)
+  const double ddl = (r < n) ? dd[r] : 0.0, eel = ee[r];
+  // (d_i, e_{i-1}^2) pairs for the Sturm recurrence, one LDS read per step
+  double2* de = reinterpret_cast<double2*>(W);
+  if (tid < n) de[tid] = make_double2(dd[tid], tid > 0 ? e2[tid - 1] : 0.0);
   // pivots below pivmin are replaced by -pivmin: e2 / pivmin stays finite
   const double pivmin = 1e-290 * fmax(1.0, e2max);
-  const int ms = (d > 0) ? max(1, M / d) : 1;     // lanes per eigenvalue
-  const int nps = ms * TE_NP;                    // points per eigenvalue per round
-  const int grp = r / ms, sub = r % ms;
+  // ms lanes per eigenvalue (a power of two, so a group never straddles a
+  // wavefront and its bracket update is a butterfly over ms lanes)
+  int ms = 1;
+  while (ms * 2 <= 64 && ms * 2 * d <= 256) ms *= 2;
+  const int grp = tid / ms, sub = tid % ms;
   const bool gact = grp < d;
   const int kk = n - 1 - (gact ? grp : 0);       // eigenvalue kk in increasing order
+  __syncthreads();
   double a0 = lo, b0 = hi;
   for (int it = 0; it < 200; ++it) {
     const bool more = gact && (b0 - a0 > 2.2e-16 * scale);
-    if (!__any(more)) break;
-    double x[TE_NP], q[TE_NP];
-    int cnt[TE_NP];
-#pragma unroll
-    for (int s = 0; s < TE_NP; ++s) {
-      x[s] = a0 + (b0 - a0) * (double)(sub * TE_NP + s + 1) / (double)(nps + 1);
-      q[s] = dd[0] - x[s];
-      cnt[s] = 0;
+    if (!__syncthreads_or(more)) break;
+    const double x = a0 + (b0 - a0) * (double)(sub + 1) / (double)(ms + 1);
+    // Sturm count: negative pivots of the LDL^T of T - x I; the reciprocal
+    // is the hardware estimate refined by one Newton step (a backward
+    // perturbation of e^2 by a few tens of ulps)
+    double2 pr = de[0];
+    double q = pr.x - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int cnt = (q < 0.0);
+#pragma unroll 4
+    for (int i = 1; i < n; ++i) {
+      pr = de[i];
+      double rq = __builtin_amdgcn_rcp(q);
+      rq = fma(rq, fma(-q, rq, 1.0), rq);
+      q = (pr.x - x) - pr.y * rq;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += (q < 0.0);
     }
-    // every lane runs the recurrence (uniform control flow around readlane)
-#pragma unroll
-    for (int s = 0; s < TE_NP; ++s) {
-      if (fabs(q[s]) < pivmin) q[s] = -pivmin;
-      cnt[s] += (q[s] < 0.0);
+    // new bracket: the largest point with count <= kk and the smallest with
+    // count > kk, by a butterfly over the group (max / min: order-free)
+    double na = (cnt <= kk) ? x : a0;
+    double nb = (cnt > kk) ? x : b0;
+    for (int o = 1; o < ms; o <<= 1) {
+      na = fmax(na, __shfl_xor(na, o, 64));
+      nb = fmin(nb, __shfl_xor(nb, o, 64));
     }
-#pragma unroll
-    for (int i = 1; i < M; ++i) {
-      if (i < n) {
-        const double di = te_lane(ddl, i), ei = te_lane(e2l, i - 1);
-#pragma unroll
-        for (int s = 0; s < TE_NP; ++s) {
-          q[s] = (di - x[s]) - ei * te_rcp(q[s]);
-          if (fabs(q[s]) < pivmin) q[s] = -pivmin;
-          cnt[s] += (q[s] < 0.0);
-        }
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < TE_NP; ++s) {
-      msx[r * TE_NP + s] = x[s];
-      msc[r * TE_NP + s] = cnt[s];
-    }
-    __syncthreads();
     if (more) {
-      double na = a0, nb = b0;
-      const int base = grp * nps;
-      for (int m = 0; m < nps; ++m) {
-        const double xs = msx[base + m];
-        if (!(xs > a0 && xs < b0)) continue;
-        if (msc[base + m] <= kk)
-          na = fmax(na, xs);
-        else
-          nb = fmin(nb, xs);
-      }
-      if (na == a0 && nb == b0) {
+      if (!(na > a0) && !(nb < b0)) {
         b0 = a0;   // no interior point is representable: converged
       } else {
         a0 = na;
         b0 = nb;
       }
     }
-    __syncthreads();
   }
   if (gact && sub == 0) lamg[grp] = 0.5 * (a0 + b0);
   __syncthreads();
   TS(2);
-  // ---- inverse iteration, lane c < d owns eigenvector c (the other lanes
-  // repeat eigenvector d - 1 so that control flow stays uniform) ----
-  // T is scaled by 1/scale so that pivots are O(1) or O(eps)
+  // ---- inverse iteration: lane c < d of wavefront 0 owns eigenvector c ----
   const double isc = (scale > 0.0) ? 1.0 / scale : 1.0;
   const double ptiny = 2.2e-16;
-  const double dls = ddl * isc, els = eel * isc;   // every lane: read by readlane
-  double x[M];
-#pragma unroll
-  for (int i = 0; i < M; ++i) x[i] = 0.0;
   double* U0 = W;
   double* U1 = W + M * M;
   double* U2 = W + 2 * M * M;
-  if (d > 0) {
+  // (d_i, e_i) of T / scale, one LDS read per elimination step
+  __shared__ double2 dsc[M + 1];
+  if (tid <= M) dsc[tid] = (tid < n) ? make_double2(ddl * isc, eel * isc) : make_double2(0.0, 0.0);
+  __syncthreads();
+  if (w == 0 && d > 0) {
+    double x[M];
     const double lv = lamg[min(r, d - 1)] * isc;
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       // a fixed start vector with no symmetry: 1 + frac(0.618 i) / 2
-      const double h = 0.6180339887498949 * (double)i;
-      x[i] = (i < n) ? 1.0 + 0.5 * (h - floor(h)) : 0.0;
+      const double hh = 0.6180339887498949 * (double)i;
+      x[i] = (i < n) ? 1.0 + 0.5 * (hh - floor(hh)) : 0.0;
     }
-    for (int pass = 0; pass < 3; ++pass) {
-      double c0 = te_lane(dls, 0) - lv, c1 = (n > 1) ? te_lane(els, 0) : 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      const double2 d0 = dsc[0];
+      double c0 = d0.x - lv, c1 = (n > 1) ? d0.y : 0.0;
 #pragma unroll
       for (int i = 0; i < M - 1; ++i) {
         if (i < n - 1) {
-          const double sb = te_lane(els, i), dg = te_lane(dls, i + 1) - lv;
-          const double sp = (i + 2 < n) ? te_lane(els, i + 1) : 0.0;
+          const double2 di = dsc[i], dn = dsc[i + 1];
+          const double sb = di.y, dg = dn.x - lv;
+          const double sp = (i + 2 < n) ? dn.y : 0.0;
           const bool swap = fabs(sb) > fabs(c0);
           const double piv = swap ? sb : ((c0 == 0.0) ? ptiny : c0);
           const double f = (swap ? c0 : sb) * te_rcp(piv);
@@ -1593,60 +1592,57 @@ __global__ void __launch_bounds__(64) dense_topeig_kernel(const double* __restri
 #pragma unroll
       for (int i = 0; i < M; ++i) x[i] *= inv;
     }
+    // publish: XV[i * M + c] (the factors are no longer needed)
+#pragma unroll
+    for (int i = 0; i < M; ++i) W[i * M + r] = x[i];
   }
+  __syncthreads();
   TS(3);
-  // ---- back-transform x <- H_0 H_1 ... H_{n-3} x ----
-  for (int k = n - 3; k >= 0; --k) {
-    const double t = tau[k];
-    if (t == 0.0) continue;
-    const double* hk = H + k * M;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  // ---- back-transform x <- H_0 H_1 ... H_{n-3} x, rows split over the
+  //      four wavefronts: wavefront w holds rows 16w .. 16w+15 of vector r ----
+  {
+    double xb[CW];
 #pragma unroll
-    for (int ic = 0; ic < M; ic += 16) {
-      if (k < ic + 15) {
+    for (int ii = 0; ii < CW; ++ii) xb[ii] = W[(CW * w + ii) * M + r];
+    for (int k = n - 3; k >= 0; --k) {
+      const double t = tau[k];
+      if (t == 0.0) continue;
+      const double* hk = H + k * M + CW * w;
+      double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int i = ic; i < ic + 16; i += 4) {
-          s0 = fma(hk[i], x[i], s0);
-          s1 = fma(hk[i + 1], x[i + 1], s1);
-          s2 = fma(hk[i + 2], x[i + 2], s2);
-          s3 = fma(hk[i + 3], x[i + 3], s3);
-        }
+      for (int ii = 0; ii < CW; ii += 2) {
+        s0 = fma(hk[ii], xb[ii], s0);
+        s1 = fma(hk[ii + 1], xb[ii + 1], s1);
       }
-    }
-    const double s = t * ((s0 + s1) + (s2 + s3));
+      ps[w * M + r] = s0 + s1;
+      __syncthreads();
+      const double s = t * (((ps[r] + ps[M + r]) + ps[2 * M + r]) + ps[3 * M + r]);
 #pragma unroll
-    for (int ic = 0; ic < M; ic += 16) {
-      if (k < ic + 15) {
-#pragma unroll
-        for (int i = ic; i < ic + 16; ++i) x[i] -= s * hk[i];
-      }
+      for (int ii = 0; ii < CW; ++ii) xb[ii] -= s * hk[ii];
+      __syncthreads();
     }
+#pragma unroll
+    for (int ii = 0; ii < CW; ++ii) W[(CW * w + ii) * M + r] = xb[ii];
   }
   __syncthreads();
   TS(4);
   // ---- Cholesky QR of the d vectors ----
   double* XL = W;                 // XL[i * M + c]: entry i of vector c
   double* Rc = W + M * M;         // Rc[a * (M + 1) + b]
-  if (r < d) {
-#pragma unroll
-    for (int i = 0; i < M; ++i) XL[i * M + r] = x[i];
-  }
-  __syncthreads();
-  if (r < d) {
-    for (int b = 0; b < d; ++b) {
+  // Gram: row a in lane a, columns b = w, w + 4, ... in wavefront w
+  if (r < d)
+    for (int b = w; b < d; b += 4) {
       double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int i = 0; i < M; i += 2) {
-        s0 = fma(x[i], XL[i * M + b], s0);
-        s1 = fma(x[i + 1], XL[(i + 1) * M + b], s1);
+      for (int i = 0; i < n; i += 2) {
+        s0 = fma(XL[i * M + r], XL[i * M + b], s0);
+        if (i + 1 < n) s1 = fma(XL[(i + 1) * M + r], XL[(i + 1) * M + b], s1);
       }
       Rc[r * (M + 1) + b] = s0 + s1;
     }
-  }
   __syncthreads();
   int bad = 0;
   for (int j = 0; j < d; ++j) {
-    if (r == 0) {
+    if (tid == 0) {
       double s = Rc[j * (M + 1) + j];
       for (int k = 0; k < j; ++k) s -= Rc[k * (M + 1) + j] * Rc[k * (M + 1) + j];
       Rc[j * (M + 1) + j] = (s > 0.0) ? sqrt(s) : 0.0;
@@ -1657,27 +1653,27 @@ __global__ void __launch_bounds__(64) dense_topeig_kernel(const double* __restri
       bad = 1;
       break;
     }
-    if (r > j && r < d) {
-      double s = Rc[j * (M + 1) + r];
-      for (int k = 0; k < j; ++k) s -= Rc[k * (M + 1) + j] * Rc[k * (M + 1) + r];
-      Rc[j * (M + 1) + r] = s / rjj;   // R[j][r], upper triangle
+    if (tid > j && tid < d) {
+      double s = Rc[j * (M + 1) + tid];
+      for (int k = 0; k < j; ++k) s -= Rc[k * (M + 1) + j] * Rc[k * (M + 1) + tid];
+      Rc[j * (M + 1) + tid] = s / rjj;   // R[j][tid], upper triangle
     }
     __syncthreads();
   }
-  if (!bad && r < n) {
-    // row r of X R^{-1} by forward substitution, in place
+  if (!bad && tid < n) {
+    // row tid of X R^{-1} by forward substitution, in place
     for (int c = 0; c < d; ++c) {
-      double s = XL[r * M + c];
-      for (int k = 0; k < c; ++k) s -= XL[r * M + k] * Rc[k * (M + 1) + c];
-      XL[r * M + c] = s / Rc[c * (M + 1) + c];
+      double s = XL[tid * M + c];
+      for (int k = 0; k < c; ++k) s -= XL[tid * M + k] * Rc[k * (M + 1) + c];
+      XL[tid * M + c] = s / Rc[c * (M + 1) + c];
     }
-    for (int c = 0; c < d; ++c) V[(size_t)c * n + r] = XL[r * M + c];
+    for (int c = 0; c < d; ++c) V[(size_t)c * n + tid] = XL[tid * M + c];
   }
-  if (r < d) lam[r] = lamg[r];
-  if (r == 0 && bad && flags) flags[0] |= 32;
+  if (tid < d) lam[tid] = lamg[tid];
+  if (tid == 0 && bad && flags) flags[0] |= 32;
 #ifdef SYMROM_TOPEIG_TIMING
   TS(5);
-  if (r == 0 && flags)
+  if (tid == 0 && flags)
     for (int k = 0; k < 6; ++k) flags[8 + k] = (int)(tsv[k] - tsv[0]);
 #endif
 #undef TS
@@ -1685,5 +1681,5 @@ __global__ void __launch_bounds__(64) dense_topeig_kernel(const double* __restri
 
 void launch_dense_topeig(hipStream_t s, const double* G, int n, int d, double* V, double* lam,
                          int* flags) {
-  hipLaunchKernelGGL(dense_topeig_kernel, dim3(1), dim3(64), 0, s, G, n, d, V, lam, flags);
+  hipLaunchKernelGGL(dense_topeig_kernel, dim3(1), dim3(256), 0, s, G, n, d, V, lam, flags);
 }
