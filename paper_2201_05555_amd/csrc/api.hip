@@ -473,7 +473,7 @@ int nkb_for(int N) {
 void carve_rom(Arena& ar, symrom_rom& r) {
   const int N = r.N, p = r.p, Nx = r.Nx, nm = r.nmax;
   // one parameter tile of up to 64 KB of LDS per table, ~one block per CU
-  r.gdep = pic_geom(N, p, Nx, 64 * 1024, 256);
+  r.gdep = pic_geom(N, p, Nx, 16 * 1024, 256);
   r.ggat = pic_geom(N, p, Nx, 64 * 1024, 256);
   r.nkb = nkb_for(N);
   r.b = carve_pic(ar, N, p, Nx, r.gdep.nrb >= r.ggat.nrb ? r.gdep : r.ggat);

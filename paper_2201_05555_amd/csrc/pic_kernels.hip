@@ -165,9 +165,35 @@ __global__ void __launch_bounds__(256) poisson_kernel(
   const int j0 = threadIdx.x * per;
   const double hi = h[i];
   const double qwi = qw[i];
-  // 1. sums of the unit weights (already reduced over row blocks)
-  for (int j = threadIdx.x; j < Nx; j += blockDim.x) rho_s[j] = qwi * part[(size_t)i * Nx + j] + hi;
-  __syncthreads();
+  // 1. sums of the unit weights over the nrb row-block partials
+  //    part[(k * p + i) * Nx + j]: G threads per node take every G-th block,
+  //    two chains each, combined in a fixed order
+  {
+    const int G = (Nx <= 64) ? 4 : (Nx <= 128) ? 2 : 1;
+    for (int t = threadIdx.x; t < G * Nx; t += blockDim.x) {
+      const int j = t % Nx, g = t / Nx;
+      double s0 = 0.0, s1 = 0.0;
+      int k = g;
+      for (; k + G < nrb; k += 2 * G) {
+        s0 += part[((size_t)k * p + i) * Nx + j];
+        s1 += part[((size_t)(k + G) * p + i) * Nx + j];
+      }
+      if (k < nrb) s0 += part[((size_t)k * p + i) * Nx + j];
+      if (G == 1)
+        rho_s[j] = qwi * (s0 + s1) + hi;
+      else
+        buf[g * Nx + j] = s0 + s1;
+    }
+    __syncthreads();
+    if (G > 1) {
+      for (int j = threadIdx.x; j < Nx; j += blockDim.x) {
+        double t2 = buf[j];
+        for (int g = 1; g < G; ++g) t2 += buf[g * Nx + j];
+        rho_s[j] = qwi * t2 + hi;
+      }
+      __syncthreads();
+    }
+  }
   // 2. zero-mean charge and its prefix sums
   double loc = 0.0;
   for (int q = 0; q < per; ++q)
@@ -223,26 +249,6 @@ __global__ void __launch_bounds__(256) poisson_kernel(
   if (threadIdx.x == 0 && energy_out) energy_out[i] = E / (2.0 * mw[i]);
 }
 
-// Sum of the row-block partial histograms: out[o] = sum_b part[b][o] for the
-// p * Nx entries, in a fixed order (32 entries x 8 lanes of b per block).
-__global__ void __launch_bounds__(256) reduce_hist_kernel(const double* __restrict__ part, int nrb,
-                                                          int nout, const int* __restrict__ active,
-                                                          int Nx, double* __restrict__ out) {
-  __shared__ double sm[256];
-  const int ol = threadIdx.x % 32, kl = threadIdx.x / 32;
-  const int o = blockIdx.x * 32 + ol;
-  const bool on = o < nout && !(active && !active[o / Nx]);
-  double s = 0.0;
-  if (on)
-    for (int k = kl; k < nrb; k += 8) s += part[(size_t)k * nout + o];
-  sm[threadIdx.x] = s;
-  __syncthreads();
-  if (kl == 0 && on) {
-    double t = sm[ol];
-    for (int q = 1; q < 8; ++q) t += sm[q * 32 + ol];
-    out[o] = t;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Full-order Stormer-Verlet in leapfrog form.  State (X_t, V_{t-1/2}).
@@ -395,13 +401,9 @@ void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* 
 void launch_poisson(hipStream_t s, const double* part, int nrb, int p, int Nx, const double* qw,
                     const double* h, const double* mw, const int* active, double* rho,
                     double* phi, double* e, double* energy) {
-  // the row-block sums go to the first p*Nx doubles after the partials
-  double* sums = const_cast<double*>(part) + (size_t)nrb * p * Nx;
-  const int nout = p * Nx;
-  hipLaunchKernelGGL(reduce_hist_kernel, dim3((nout + 31) / 32), dim3(256), 0, s, part, nrb, nout,
-                     active, Nx, sums);
-  hipLaunchKernelGGL(poisson_kernel, dim3(p), dim3(256), 0, s, sums, nrb, p, Nx, qw, h, mw,
-                     active, rho, phi, e, energy);
+  // one block per parameter sums its row-block partials and solves
+  hipLaunchKernelGGL(poisson_kernel, dim3(p), dim3(256), 0, s, part, nrb, p, Nx, qw, h, mw, active,
+                     rho, phi, e, energy);
 }
 
 void launch_fom_push(hipStream_t s, double* X, double* V, int N, int p, int Nx, const PicGeom& g,
