@@ -224,7 +224,7 @@ PicBufs carve_pic(Arena& ar, int N, int p, int Nx, const PicGeom& g) {
   b.energy = ar.take<double>(p);
   return b;
 }
-const size_t kFomTableBudget = 32 * 1024;  // LDS bytes per table (field and histogram)
+const size_t kFomTableBudget = 16 * 1024;  // LDS bytes per table (field and histogram)
 const size_t kDepTableBudget = 64 * 1024;
 bool valid_sizes(int N, int p, int Nx) {
   return N > 0 && p > 0 && Nx >= 2 && Nx <= SYMROM_MAX_NX;

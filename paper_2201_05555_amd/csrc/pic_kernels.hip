@@ -172,17 +172,26 @@ __global__ void __launch_bounds__(256) poisson_kernel(
     const int G = (Nx <= 64) ? 4 : (Nx <= 128) ? 2 : 1;
     for (int t = threadIdx.x; t < G * Nx; t += blockDim.x) {
       const int j = t % Nx, g = t / Nx;
-      double s0 = 0.0, s1 = 0.0;
+      // eight partials in flight per thread, summed in block order
+      double acc8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc8[u] = 0.0;
       int k = g;
-      for (; k + G < nrb; k += 2 * G) {
-        s0 += part[((size_t)k * p + i) * Nx + j];
-        s1 += part[((size_t)(k + G) * p + i) * Nx + j];
+      for (; k + 7 * G < nrb; k += 8 * G) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc8[u] += part[((size_t)(k + u * G) * p + i) * Nx + j];
       }
-      if (k < nrb) s0 += part[((size_t)k * p + i) * Nx + j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int kq = k + u * G;
+        if (kq < nrb) acc8[u] += part[((size_t)kq * p + i) * Nx + j];
+      }
+      const double s01 = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) +
+                         ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
       if (G == 1)
-        rho_s[j] = qwi * (s0 + s1) + hi;
+        rho_s[j] = qwi * s01 + hi;
       else
-        buf[g * Nx + j] = s0 + s1;
+        buf[g * Nx + j] = s01;
     }
     __syncthreads();
     if (G > 1) {
