@@ -2,6 +2,7 @@
 // orchestration of the reduced step (Sec. 5) and of the full-order step
 // (eq. sv_full_order).  All arithmetic of a step runs in the HIP kernels; the
 // host only enqueues launches and reads the fixed-point counters.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -424,7 +425,7 @@ struct symrom_rom {
   cplx* Q;  // p x nmax
   double* prev;
   int* active;
-  int* counters;  // [0] active left, [1] stalled
+  int* counters;  // [0] active left, [1] stalled, [2] iterations run
   int* flags;     // [0] error bits, [1] eigen path
   cplx *Gram, *Amat, *MU, *MX, *M1, *M2, *M3, *C0x, *Rinv, *MP;
   cplx* gemm_part;
@@ -434,6 +435,7 @@ struct symrom_rom {
   cplx *Gp, *Vp;
   double* lam;
   int n_active;  // active fixed-point columns (host copy, for work accounting)
+  int fp_hint;   // iterations the last fixed point took (speculative batch size)
   bool stage1_cached;  // G, g and the fields in the buffers belong to (U0, Z0)
   double* colsq;       // per-parameter |G~|^2
   // DEIM (Sec. 4.3): snapshot ring of T+1 slots (N x psub each) and operator
@@ -631,7 +633,7 @@ RowTerms rt(const cplx* in0, const cplx* M0, int k0, const cplx* in1 = nullptr,
 // ranks beyond the fused kernels, the gather into r.G and a split-K product.
 // With want_colsq, |G~[:, c]|^2 goes to r.colsq.
 void full_gradient(symrom_rom& r, const cplx* U, const cplx* Z, const int* active,
-                   bool do_deposit, bool want_colsq = false) {
+                   bool do_deposit, bool want_colsq = false, const int* gate = nullptr) {
   hipStream_t s = r.s;
   const int n = r.n;
   const double qm = r.cfg.q / r.cfg.m;
@@ -641,11 +643,12 @@ void full_gradient(symrom_rom& r, const cplx* U, const cplx* Z, const int* activ
       const int ntiles = (r.p + r.gdep.pt - 1) / r.gdep.pt;
       Timer t(FAM_DEPOSIT, s, 4.0 * n * (double)r.N * pact,
               16.0 * n * (double)r.N * ntiles + 8.0 * (double)r.gdep.nrb * pact * r.Nx);
-      launch_deposit_rom(s, U, r.N, n, Z, r.p, r.Nx, r.gdep, r.b.factor, active, r.b.part);
+      launch_deposit_rom(s, U, r.N, n, Z, r.p, r.Nx, r.gdep, r.b.factor, active, r.b.part,
+                         gate);
     }
     Timer t(FAM_POISSON, s);
     launch_poisson(s, r.b.part, r.gdep.nrb, r.p, r.Nx, r.b.qw, r.b.h, r.b.mw, active, r.b.rho,
-                   r.b.phi, r.b.e, r.b.energy);
+                   r.b.phi, r.b.e, r.b.energy, gate);
   }
   const double pact = (active ? (double)r.n_active : (double)r.p);
   if (fused_gradient_ok(n)) {
@@ -655,7 +658,7 @@ void full_gradient(symrom_rom& r, const cplx* U, const cplx* Z, const int* activ
     Timer t(FAM_GATHER, s, (8.0 * n + 4.0) * (double)r.N * pact,
             16.0 * n * (double)r.N * ntiles);
     launch_gather_project(s, U, r.N, n, Z, r.p, r.Nx, r.b.factor, r.b.e, qm, active, want_colsq,
-                          r.gemm_part, (size_t)r.nkb * 64 * 64, r.gproj, r.colsq);
+                          r.gemm_part, (size_t)r.nkb * 64 * 64, r.gproj, r.colsq, gate);
     return;
   }
   {
@@ -794,11 +797,12 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z) {
 
 // DEIM gradient at (U, Z) with the field of the last Poisson solve:
 // gF = U~[I]^* ((q/m) e_{j(x_I)} w), then k = -i (gF + linear part).
-void deim_k(symrom_rom& r, const cplx* U, const cplx* Z, const int* active, cplx* kout) {
+void deim_k(symrom_rom& r, const cplx* U, const cplx* Z, const int* active, cplx* kout,
+            const int* gate = nullptr) {
   hipStream_t s = r.s;
   Timer t(FAM_DENSE, s);
   launch_deim_gather(s, U, r.N, r.n, Z, r.p, r.Nx, r.b.factor, r.b.e, r.cfg.q / r.cfg.m, r.didx,
-                     r.dw, r.d_cur, active, r.gF);
+                     r.dw, r.d_cur, active, r.gF, gate);
   if (kout) launch_deim_k(s, r.gF, r.C12, Z, r.n, r.p, kout);
 }
 
@@ -808,7 +812,11 @@ symrom_status read_flags(symrom_rom& r, int* host) {
   return SYMROM_OK;
 }
 
-symrom_status rom_step_one(symrom_rom& r) {
+symrom_status rom_grow_apply(symrom_rom& r, int k);
+
+// One step of the reduced model; with decide_rank, the rank indicator at the
+// new state and a growth by one pair when it exceeds the threshold.
+symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   hipStream_t s = r.s;
   const int n = r.n, p = r.p, N = r.N;
   const double dt = r.cfg.dt;
@@ -833,42 +841,56 @@ symrom_status rom_step_one(symrom_rom& r) {
     launch_fp_init(s, r.prev, r.active, r.counters, p);
     launch_dense_finish_z(s, r.Z0, r.k, n, p, 0.5 * dt, r.Zev);
   }
+  // The iterations are enqueued in batches with one counter readback per
+  // batch: the first batch as long as the previous step's fixed point, then
+  // one at a time.  Every launch in the loop is gated on the device counter
+  // of active columns, so iterations enqueued past convergence do nothing
+  // (and are not counted).  With kernel timing on, batches are single
+  // iterations so that the work accounted to each launch is exact.
   const int fixed = r.cfg.fp_fixed_iters;
   const int limit = fixed > 0 ? fixed : r.cfg.fp_max_iters;
-  int iters = 0;
-  int hc[4] = {0, 0, 0, 0};
+  const int* gate = r.counters;
+  int hc[4] = {p, 0, 0, 0};
   r.n_active = p;
-  for (;;) {
-    ++iters;
-    if (deim) {
-      const double pact = (double)r.n_active;
-      {
-        const int ntiles = (r.p + r.gdep.pt - 1) / r.gdep.pt;
-        Timer t(FAM_DEPOSIT, s, 4.0 * n * (double)N * pact,
-                16.0 * n * (double)N * ntiles + 8.0 * (double)r.gdep.nrb * pact * r.Nx);
-        launch_deposit_rom(s, r.Uh, N, n, r.Zev, p, r.Nx, r.gdep, r.b.factor, r.active, r.b.part);
+  int batch = fixed > 0 ? fixed : std::max(1, std::min(r.fp_hint, limit));
+  if (g_timing) batch = 1;
+  int launched = 0;
+  while (launched < limit) {
+    for (int b = 0; b < batch && launched < limit; ++b, ++launched) {
+      if (deim) {
+        const double pact = (double)r.n_active;
+        {
+          const int ntiles = (r.p + r.gdep.pt - 1) / r.gdep.pt;
+          Timer t(FAM_DEPOSIT, s, 4.0 * n * (double)N * pact,
+                  16.0 * n * (double)N * ntiles + 8.0 * (double)r.gdep.nrb * pact * r.Nx);
+          launch_deposit_rom(s, r.Uh, N, n, r.Zev, p, r.Nx, r.gdep, r.b.factor, r.active,
+                             r.b.part, gate);
+        }
+        {
+          Timer t(FAM_POISSON, s);
+          launch_poisson(s, r.b.part, r.gdep.nrb, p, r.Nx, r.b.qw, r.b.h, r.b.mw, r.active,
+                         r.b.rho, r.b.phi, r.b.e, r.b.energy, gate);
+        }
+        deim_k(r, r.Uh, r.Zev, r.active, nullptr, gate);
+      } else {
+        full_gradient(r, r.Uh, r.Zev, r.active, true, false, gate);
       }
       {
-        Timer t(FAM_POISSON, s);
-        launch_poisson(s, r.b.part, r.gdep.nrb, p, r.Nx, r.b.qw, r.b.h, r.b.mw, r.active, r.b.rho,
-                       r.b.phi, r.b.e, r.b.energy);
+        Timer t(FAM_DENSE, s);
+        launch_dense_fp_update(s, deim ? r.gF : r.gproj, r.C12, n, p, r.Z0, r.Zev, r.ZG, r.k,
+                               r.prev, r.active, dt, r.cfg.fp_tol, fixed > 0 ? 1 : 0,
+                               deim ? 1 : 0, r.counters);
       }
-      deim_k(r, r.Uh, r.Zev, r.active, nullptr);
-    } else {
-      full_gradient(r, r.Uh, r.Zev, r.active, true);
-    }
-    {
-      Timer t(FAM_DENSE, s);
-      launch_dense_fp_update(s, deim ? r.gF : r.gproj, r.C12, n, p, r.Z0, r.Zev, r.ZG, r.k,
-                             r.prev, r.active, dt, r.cfg.fp_tol, fixed > 0 ? 1 : 0,
-                             deim ? 1 : 0, r.counters);
     }
     LAUNCHCHK();
-    HIPCHK(hipMemcpyAsync(hc, r.counters, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hc, r.counters, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     r.n_active = hc[0];
-    if (hc[0] == 0 || iters >= limit) break;
+    if (hc[0] == 0) break;
+    batch = 1;
   }
+  const int iters = hc[2];
+  if (fixed == 0) r.fp_hint = iters;
   r.last.iters = iters;
   r.last.stalled = hc[1];
   r.last.deim_active = deim ? 1 : 0;
@@ -892,17 +914,37 @@ symrom_status rom_step_one(symrom_rom& r) {
   // U1 = R_{U0}(xi_1)  (into Uh, free now)
   cayley(r, r.U0, r.P, r.Uh, r.M3);
   if (r.cfg.reorth) cholqr2(r, r.Uh, r.Z1);
+  // Commit by exchanging buffers before the flags are known, and with rank
+  // adaptation enqueue the indicator's gradient at the new state behind it,
+  // so that one readback serves both; a failed step exchanges them back.
+  std::swap(r.U0, r.Uh);
+  std::swap(r.Z0, r.Z1);
+  if (decide_rank) {
+    full_gradient(r, r.U0, r.Z0, nullptr, true, true);
+    launch_dense_indicator(s, r.colsq, r.gproj, n, p, r.eps_dev);
+  }
   LAUNCHCHK();
   int fl[2];
-  symrom_status st = read_flags(r, fl);
-  if (st != SYMROM_OK) return st;
-  if (fl[0]) return fail(SYMROM_ESINGULAR, "singular small matrix in the basis update");
-  // commit
-  std::swap(r.U0, r.Uh);
-  launch_copy_cplx(s, r.Z0, r.Z1, (size_t)n * p);
+  double eps = 0.0;
+  HIPCHK(hipMemcpyAsync(fl, r.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  if (decide_rank)
+    HIPCHK(hipMemcpyAsync(&eps, r.eps_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (fl[0]) {
+    std::swap(r.U0, r.Uh);
+    std::swap(r.Z0, r.Z1);
+    return fail(SYMROM_ESINGULAR, "singular small matrix in the basis update");
+  }
   r.step++;
-  LAUNCHCHK();
-  return SYMROM_OK;
+  if (!decide_rank) return SYMROM_OK;
+  r.last.rank_indicator = eps;
+  if (!(eps > r.cfg.rank_tol_up) || 2 * (n + 1) > r.cfg.two_n_max) {
+    // the gradient just computed is the next step's first-stage gradient
+    r.stage1_cached = true;
+    return SYMROM_OK;
+  }
+  HIPCHK(hipMemsetAsync(r.flags, 0, 4 * sizeof(int), s));
+  return rom_grow_apply(r, 1);
 }
 }  // namespace
 
@@ -1069,8 +1111,7 @@ extern "C" symrom_status rom_step(symrom_rom* r, int32_t nsteps, symrom_step_inf
   if (!r || nsteps < 0) return fail(SYMROM_EINVAL, "rom_step: bad arguments");
   if (!r->ready) return fail(SYMROM_ESTATE, "rom_step: handle not initialised");
   for (int it = 0; it < nsteps; ++it) {
-    symrom_status st = rom_step_one(*r);
-    if (st == SYMROM_OK && r->cfg.rank_auto) st = rom_grow(*r, 0, true);
+    symrom_status st = rom_step_one(*r, r->cfg.rank_auto != 0);
     if (st != SYMROM_OK) {
       if (info) *info = r->last;
       return st;
@@ -1086,7 +1127,7 @@ namespace {
 // decide = true (then grow one pair if eps > rank_tol_up and the cap allows).
 symrom_status rom_grow(symrom_rom& r, int k, bool decide) {
   hipStream_t s = r.s;
-  const int n = r.n, p = r.p, N = r.N;
+  const int n = r.n, p = r.p;
   HIPCHK(hipMemsetAsync(r.flags, 0, 4 * sizeof(int), s));
   full_gradient(r, r.U0, r.Z0, nullptr, true, decide);
   if (decide) {
@@ -1104,6 +1145,14 @@ symrom_status rom_grow(symrom_rom& r, int k, bool decide) {
     }
     k = 1;
   }
+  return rom_grow_apply(r, k);
+}
+
+// Growth by k pairs with the full gradient at (U0, Z0) (field and g) in the
+// buffers; flags cleared by the caller.
+symrom_status rom_grow_apply(symrom_rom& r, int k) {
+  hipStream_t s = r.s;
+  const int n = r.n, p = r.p, N = r.N;
   r.stage1_cached = false;
   if (fused_gradient_ok(n)) materialise_gradient(r, r.U0, r.Z0);
   launch_gemm_ah_b(s, ml(r.G, p), p, ml(r.G, p), p, false, N, r.nkb, r.gemm_part, r.Gp);

@@ -600,6 +600,8 @@ __global__ void __launch_bounds__(DTPB) dense_fp_update_kernel(
     const cplx* __restrict__ Z0, cplx* __restrict__ Zeval, cplx* __restrict__ ZG,
     cplx* __restrict__ k, double* __restrict__ prev, int* __restrict__ active, double dt,
     double tol, int fixed, int linear_part, int* __restrict__ counters) {
+  // nothing left to iterate: a speculative launch after convergence
+  if (counters[0] == 0) return;
   __shared__ int nact, nstall;
   if (threadIdx.x == 0) {
     nact = 0;
@@ -655,6 +657,7 @@ __global__ void __launch_bounds__(DTPB) dense_fp_update_kernel(
   if (threadIdx.x == 0) {
     counters[0] = nact;
     counters[1] += nstall;
+    counters[2] += 1;
   }
 }
 
@@ -665,7 +668,9 @@ __global__ void fp_init_kernel(double* prev, int* active, int* counters, int p) 
     prev[t] = INFINITY;
     active[t] = 1;
   }
-  if (t < 4) counters[t] = 0;
+  // [0] columns still active (all, before the first iteration), [1] stalled
+  // columns, [2] iterations that updated at least one column
+  if (t < 4) counters[t] = (t == 0) ? p : 0;
 }
 
 // Z1 = Z0 + dt k

@@ -54,11 +54,14 @@ inline int nc_bucket(int n) {
 // pic_kernels.hip
 void launch_deposit_x(hipStream_t s, const double* X, int N, int p, int Nx, const PicGeom& g,
                       const double* factor, double* part);
+// gate (nullable, device): when *gate == 0 the launch does nothing (the
+// fixed point has converged: speculative iterations exit at once)
 void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
-                        const PicGeom& g, const double* factor, const int* active, double* part);
+                        const PicGeom& g, const double* factor, const int* active, double* part,
+                        const int* gate = nullptr);
 void launch_poisson(hipStream_t s, const double* part, int nrb, int p, int Nx, const double* qw,
                     const double* h, const double* mw, const int* active, double* rho,
-                    double* phi, double* e, double* energy);
+                    double* phi, double* e, double* energy, const int* gate = nullptr);
 void launch_fom_push(hipStream_t s, double* X, double* V, int N, int p, int Nx, const PicGeom& g,
                      const double* factor, const double* e, double qm, double ck, double cd,
                      double* part);
@@ -90,13 +93,14 @@ bool fused_gradient_ok(int n);
 void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p,
                            int Nx, const double* factor, const double* e, double qm,
                            const int* active, bool want_colsq, cplx* part, size_t part_cap,
-                           cplx* g, double* colsq);
+                           cplx* g, double* colsq, const int* gate = nullptr);
 void launch_gather_xi(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                       const double* factor, const double* e, double qm, const cplx* Q,
                       const cplx* MU, double h, cplx* out);
 void launch_deim_gather(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                         const double* factor, const double* e, double qm, const int* idx,
-                        const double* w, int d, const int* active, cplx* gF);
+                        const double* w, int d, const int* active, cplx* gF,
+                        const int* gate = nullptr);
 void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, const int* sub,
                      int psub, int Nx, const double* factor, const double* phi, double* Y);
 // DEIM basis Psi = sum_s Y_s M_s with per-block column sums (psi_blocks(N)

@@ -54,7 +54,8 @@ template <int NC>
 __global__ void __launch_bounds__(512) deposit_rom_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx, int pt,
     int rpb, const double* __restrict__ factor, const int* __restrict__ active,
-    double* __restrict__ part) {
+    double* __restrict__ part, const int* __restrict__ gate) {
+  if (gate && gate[0] == 0) return;
   // parameters in flight per thread (independent chains), within registers
   constexpr int ILP = (NC <= 8) ? 4 : (NC <= 16) ? 2 : 1;
   extern __shared__ double smem[];
@@ -154,7 +155,8 @@ __global__ void __launch_bounds__(256) poisson_kernel(
     const double* __restrict__ part, int nrb, int p, int Nx, const double* __restrict__ qw,
     const double* __restrict__ h, const double* __restrict__ mw, const int* __restrict__ active,
     double* __restrict__ rho_out, double* __restrict__ phi_out, double* __restrict__ e_out,
-    double* __restrict__ energy_out) {
+    double* __restrict__ energy_out, const int* __restrict__ gate) {
+  if (gate && gate[0] == 0) return;
   __shared__ double buf[256];
   __shared__ double red[8];
   __shared__ double rho_s[SYMROM_MAX_NX];
@@ -387,7 +389,8 @@ void launch_deposit_x(hipStream_t s, const double* X, int N, int p, int Nx, cons
 }
 
 void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
-                        const PicGeom& g, const double* factor, const int* active, double* part) {
+                        const PicGeom& g, const double* factor, const int* active, double* part,
+                        const int* gate) {
   dim3 grid(g.nrb, (p + g.pt - 1) / g.pt);
   int nc = (n <= 16) ? nc_even(n) : 32;
   size_t sh = (size_t)g.pt * Nx * sizeof(double) + (size_t)g.pt * nc * sizeof(cplx) +
@@ -395,7 +398,7 @@ void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* 
 #define DEP(NCV)                                                                              \
   ALLOW_BIG_LDS(deposit_rom_kernel<NCV>);                                                    \
   hipLaunchKernelGGL(deposit_rom_kernel<NCV>, grid, dim3(512), sh, s, U, N, n, Z, p, Nx, g.pt, \
-                     g.rpb, factor, active, part)
+                     g.rpb, factor, active, part, gate)
   switch (nc) {
     case 4: DEP(4); break;
     case 6: DEP(6); break;
@@ -409,10 +412,10 @@ void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* 
 
 void launch_poisson(hipStream_t s, const double* part, int nrb, int p, int Nx, const double* qw,
                     const double* h, const double* mw, const int* active, double* rho,
-                    double* phi, double* e, double* energy) {
+                    double* phi, double* e, double* energy, const int* gate) {
   // one block per parameter sums its row-block partials and solves
   hipLaunchKernelGGL(poisson_kernel, dim3(p), dim3(256), 0, s, part, nrb, p, Nx, qw, h, mw, active,
-                     rho, phi, e, energy);
+                     rho, phi, e, energy, gate);
 }
 
 void launch_fom_push(hipStream_t s, double* X, double* V, int N, int p, int Nx, const PicGeom& g,

@@ -286,7 +286,8 @@ __global__ void __launch_bounds__(64) deim_gather_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx,
     const double* __restrict__ factor, const double* __restrict__ e, double qm,
     const int* __restrict__ idx, const double* __restrict__ w, int d,
-    const int* __restrict__ active, cplx* __restrict__ gF) {
+    const int* __restrict__ active, cplx* __restrict__ gF, const int* __restrict__ gate) {
+  if (gate && gate[0] == 0) return;
   __shared__ double Fw[256];
   const int i = blockIdx.x;
   if (active && !active[i]) return;
@@ -333,7 +334,9 @@ template <int NC, bool ET_LDS>
 __global__ void __launch_bounds__(512) gather_project_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx, int rpb,
     const double* __restrict__ factor, const double* __restrict__ e, double qm,
-    const int* __restrict__ active, int rec, int want_colsq, cplx* __restrict__ part) {
+    const int* __restrict__ active, int rec, int want_colsq, cplx* __restrict__ part,
+    const int* __restrict__ gate) {
+  if (gate && gate[0] == 0) return;
   extern __shared__ double smem[];
   double* et = smem;  // [64][Nx] (ET_LDS); after the rows, the wavefront sums
   const int tid = threadIdx.x, lane = tid & 63;
@@ -427,7 +430,9 @@ __global__ void __launch_bounds__(512) gather_project_kernel(
 __global__ void __launch_bounds__(256) reduce_partials2_kernel(const cplx* __restrict__ part,
                                                                int nkb, int rec, int n1, int nout,
                                                                cplx* __restrict__ C1,
-                                                               double* __restrict__ C2) {
+                                                               double* __restrict__ C2,
+                                                               const int* __restrict__ gate) {
+  if (gate && gate[0] == 0) return;
   const int lane = threadIdx.x & 63;
   const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (o >= nout) return;
@@ -982,7 +987,7 @@ static int fused_nc(int n) { return nc_even(n); }
 void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p,
                            int Nx, const double* factor, const double* e, double qm,
                            const int* active, bool want_colsq, cplx* part, size_t part_cap,
-                           cplx* g, double* colsq) {
+                           cplx* g, double* colsq, const int* gate) {
   const int nc = fused_nc(n);
   const int ntile = (p + 63) / 64;
   const int rec = n * p + p;
@@ -1005,7 +1010,7 @@ void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cpl
 #define GPK(NCV, ETV)                                                                          \
   ALLOW_BIG_LDS((gather_project_kernel<NCV, ETV>));                                          \
   hipLaunchKernelGGL((gather_project_kernel<NCV, ETV>), grid, dim3(512), sh, s, U, N, n, Z, p, \
-                     Nx, rpb, factor, e, qm, active, rec, want_colsq ? 1 : 0, part)
+                     Nx, rpb, factor, e, qm, active, rec, want_colsq ? 1 : 0, part, gate)
   if (et_lds) {
     switch (nc) {
       case 4: GPK(4, true); break;
@@ -1026,7 +1031,7 @@ void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cpl
 #undef GPK
   const int nout = want_colsq ? rec : n * p;
   hipLaunchKernelGGL(reduce_partials2_kernel, dim3((nout + 3) / 4), dim3(256), 0, s, part, nb, rec,
-                     n * p, nout, g, colsq);
+                     n * p, nout, g, colsq, gate);
 }
 
 
@@ -1172,9 +1177,9 @@ void launch_rowgemm(hipStream_t s, const RowTerms& T, int N, int m, cplx* out) {
 
 void launch_deim_gather(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                         const double* factor, const double* e, double qm, const int* idx,
-                        const double* w, int d, const int* active, cplx* gF) {
+                        const double* w, int d, const int* active, cplx* gF, const int* gate) {
   hipLaunchKernelGGL(deim_gather_kernel, dim3(p), dim3(64), 0, s, U, N, n, Z, p, Nx, factor, e,
-                     qm, idx, w, d, active, gF);
+                     qm, idx, w, d, active, gF, gate);
 }
 
 
