@@ -448,7 +448,13 @@ struct symrom_rom {
   double *dw, *dc, *bval, *colpart, *Mdeim, *ylam;
   int* bidx;
   int nbg, nbc;
-  cplx *YG, *YV, *C12, *gF;
+  cplx *YG, *YV, *C12, *C12a, *gF;
+  double* dpart;  // split-K partials of the DEIM Gram (its own: the chain runs beside the main work)
+  // The DEIM operator is built on a second stream (default priority) beside
+  // the basis velocity and Cayley map of the same step, which do not need it;
+  // ev_fork / ev_join order it after the first-stage field and before its use.
+  hipStream_t s2;
+  hipEvent_t ev_fork, ev_join;
   symrom_step_info last;
 };
 
@@ -539,7 +545,9 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.YG = ar.take<cplx>((size_t)P * P);
   r.YV = ar.take<cplx>((size_t)P * P);
   r.C12 = ar.take<cplx>((size_t)2 * nm * nm);
+  r.C12a = ar.take<cplx>((size_t)2 * nm * nm);
   r.gF = ar.take<cplx>((size_t)nm * p);
+  r.dpart = ar.take<double>(r.cfg.projection == SYMROM_DEIM ? (size_t)r.nkb * 64 * 64 * 2 : 0);
 }
 
 bool valid_rom_config(const symrom_config* c, std::string& why) {
@@ -735,20 +743,22 @@ void cholqr2(symrom_rom& r, cplx* U, cplx* Z) {
 }
 
 // C12 = [U~^* U~, U~^T U~] (n x n each) for the linear part of the gradient
-void linear_grams(symrom_rom& r, const cplx* U) {
+void linear_grams(symrom_rom& r, const cplx* U, cplx* C12) {
   hipStream_t s = r.s;
   const int n = r.n;
   Timer t(FAM_BASIS, s);
-  launch_gemm_flags(s, ml(U, n), n, ml(U, n), n, 0, r.N, r.nkb, r.gemm_part, r.C12);
+  launch_gemm_flags(s, ml(U, n), n, ml(U, n), n, 0, r.N, r.nkb, r.gemm_part, C12);
   launch_gemm_flags(s, ml(U, n), n, ml(U, n), n, GEMM_NO_CONJ_A, r.N, r.nkb, r.gemm_part,
-                    r.C12 + (size_t)n * n);
+                    C12 + (size_t)n * n);
 }
 
 // Snapshot at the start of a step into the ring, and when T+1 snapshots are
 // held, the DEIM operator of this step: Psi = first d left singular vectors
-// of Y (from the eigenpairs of Y^T Y), greedy indices, weights.
+// of Y (from the eigenpairs of Y^T Y), greedy indices, weights.  Enqueued on
+// the second stream, with its own partials and its own error word flags[2].
 void deim_update(symrom_rom& r, const cplx* U, const cplx* Z) {
-  hipStream_t s = r.s;
+  hipStream_t s = r.s2;
+  int* dflags = r.flags + 2;
   const int N = r.N, n = r.n;
   const int slot = r.win_count % r.nslots;
   double* Ys = r.Ywin + (size_t)slot * r.psub * N;
@@ -762,8 +772,7 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z) {
     // column block of the overwritten slot changes
     Timer t(FAM_DENSE, s);
     launch_gram_block_real(s, Ys, slots.data(), r.nslots, r.psub, N, slot * r.psub,
-                           r.nkb * 64 * 64 * 2, reinterpret_cast<double*>(r.gemm_part),
-                           reinterpret_cast<double*>(r.YG));
+                           r.nkb * 64 * 64 * 2, r.dpart, reinterpret_cast<double*>(r.YG));
   }
   r.deim_on = r.win_count >= r.nslots;
   if (!r.deim_on) return;
@@ -774,11 +783,11 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z) {
     Timer te(FAM_EIG, s, 4.0 * fP * fP * fP / 3.0 + 2.0 * fP * fP * fd + 2.0 * fP * fd * fd,
              8.0 * fP * fP + 8.0 * fP * fd);
     launch_dense_topeig(s, reinterpret_cast<const double*>(r.YG), P, d,
-                        reinterpret_cast<double*>(r.YV), r.ylam, r.flags);
+                        reinterpret_cast<double*>(r.YV), r.ylam, dflags);
   }
   Timer t(FAM_DENSE, s);
   launch_deim_basis_coeffs(s, reinterpret_cast<const double*>(r.YV), r.ylam, P, d, r.Mdeim,
-                           r.flags);
+                           dflags);
   // Psi and its column sums.  No sign convention is applied to the columns:
   // flipping the sign of column k negates c_k and the residual exactly, so
   // the greedy indices and the weights are the same bit for bit.
@@ -788,22 +797,22 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z) {
   for (int k = 0; k < d; ++k) {
     const int cur = k & 1, prev = cur ^ 1;
     launch_deim_greedy(s, r.Psi, N, k, r.didx, r.bval + prev * r.nbg, r.bidx + prev * r.nbg,
-                       r.nbg, r.nbg, r.bval + cur * r.nbg, r.bidx + cur * r.nbg, r.flags);
+                       r.nbg, r.nbg, r.bval + cur * r.nbg, r.bidx + cur * r.nbg, dflags);
   }
   const int last = (d - 1) & 1;
   launch_deim_weights2(s, r.Psi, N, d, r.didx, r.bval + last * r.nbg, r.bidx + last * r.nbg,
-                       r.nbg, r.colpart, psi_blocks(N), r.dw, r.flags);
+                       r.nbg, r.colpart, psi_blocks(N), r.dw, dflags);
 }
 
 // DEIM gradient at (U, Z) with the field of the last Poisson solve:
 // gF = U~[I]^* ((q/m) e_{j(x_I)} w), then k = -i (gF + linear part).
 void deim_k(symrom_rom& r, const cplx* U, const cplx* Z, const int* active, cplx* kout,
-            const int* gate = nullptr) {
+            const cplx* c12 = nullptr, const int* gate = nullptr) {
   hipStream_t s = r.s;
   Timer t(FAM_DENSE, s);
   launch_deim_gather(s, U, r.N, r.n, Z, r.p, r.Nx, r.b.factor, r.b.e, r.cfg.q / r.cfg.m, r.didx,
                      r.dw, r.d_cur, active, r.gF, gate);
-  if (kout) launch_deim_k(s, r.gF, r.C12, Z, r.n, r.p, kout);
+  if (kout) launch_deim_k(s, r.gF, c12, Z, r.n, r.p, kout);
 }
 
 symrom_status read_flags(symrom_rom& r, int* host) {
@@ -825,16 +834,22 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   // stage 1 at (U0, Z0): full gradient, k1 = J g, basis velocity -> xi_half
   if (!r.stage1_cached) full_gradient(r, r.U0, r.Z0, nullptr, true);
   r.stage1_cached = false;
-  if (use_deim) deim_update(r, r.U0, r.Z0);
+  if (use_deim) {
+    // the DEIM chain needs the first-stage field; it runs beside the basis
+    // velocity, the Gram matrices of the linear part and the Cayley map
+    HIPCHK(hipEventRecord(r.ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(r.s2, r.ev_fork, 0));
+    deim_update(r, r.U0, r.Z0);
+    HIPCHK(hipEventRecord(r.ev_join, r.s2));
+  }
   const bool deim = use_deim && r.deim_on;
   basis_velocity(r, r.U0, r.Z0, 0.5 * dt, r.Xi, deim ? nullptr : r.k);
-  if (deim) {
-    linear_grams(r, r.U0);
-    deim_k(r, r.U0, r.Z0, nullptr, r.k);
-  }
+  if (deim) linear_grams(r, r.U0, r.C12a);
   // U_half = R_{U0}(xi_half)
   cayley(r, r.U0, r.Xi, r.Uh, r.Amat);
-  if (deim) linear_grams(r, r.Uh);
+  if (deim) linear_grams(r, r.Uh, r.C12);
+  if (use_deim) HIPCHK(hipStreamWaitEvent(s, r.ev_join, 0));
+  if (deim) deim_k(r, r.U0, r.Z0, nullptr, r.k, r.C12a);
   // fixed point for k2 at U_half
   {
     Timer t(FAM_DENSE, s);
@@ -871,7 +886,7 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
           launch_poisson(s, r.b.part, r.gdep.nrb, p, r.Nx, r.b.qw, r.b.h, r.b.mw, r.active,
                          r.b.rho, r.b.phi, r.b.e, r.b.energy, gate);
         }
-        deim_k(r, r.Uh, r.Zev, r.active, nullptr, gate);
+        deim_k(r, r.Uh, r.Zev, r.active, nullptr, nullptr, gate);
       } else {
         full_gradient(r, r.Uh, r.Zev, r.active, true, false, gate);
       }
@@ -924,13 +939,13 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
     launch_dense_indicator(s, r.colsq, r.gproj, n, p, r.eps_dev);
   }
   LAUNCHCHK();
-  int fl[2];
+  int fl[4];
   double eps = 0.0;
-  HIPCHK(hipMemcpyAsync(fl, r.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(fl, r.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
   if (decide_rank)
     HIPCHK(hipMemcpyAsync(&eps, r.eps_dev, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (fl[0]) {
+  if (fl[0] | fl[2]) {
     std::swap(r.U0, r.Uh);
     std::swap(r.Z0, r.Z1);
     return fail(SYMROM_ESINGULAR, "singular small matrix in the basis update");
@@ -1095,6 +1110,13 @@ extern "C" symrom_status rom_init(const symrom_config* cfg, const double* L, con
   if (fl[0]) {
     delete r;
     return fail(SYMROM_ESINGULAR, "rom_init: basis orthonormalisation failed");
+  }
+  if (cfg->projection == SYMROM_DEIM &&
+      (hipStreamCreateWithFlags(&r->s2, hipStreamNonBlocking) != hipSuccess ||
+       hipEventCreateWithFlags(&r->ev_fork, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&r->ev_join, hipEventDisableTiming) != hipSuccess)) {
+    rom_destroy(r);
+    return fail(SYMROM_EDEVICE, "rom_init: stream or event creation");
   }
   r->ready = true;
   r->stage1_cached = false;
@@ -1286,4 +1308,10 @@ extern "C" symrom_status rom_diagnostics(symrom_rom* r, double* E, double* H) {
   return SYMROM_OK;
 }
 
-extern "C" void rom_destroy(symrom_rom* r) { delete r; }
+extern "C" void rom_destroy(symrom_rom* r) {
+  if (!r) return;
+  if (r->ev_fork) (void)hipEventDestroy(r->ev_fork);
+  if (r->ev_join) (void)hipEventDestroy(r->ev_join);
+  if (r->s2) (void)hipStreamDestroy(r->s2);
+  delete r;
+}

@@ -1308,22 +1308,25 @@ void launch_dense_indicator(hipStream_t s, const double* colsq, const cplx* g, i
 // Leading eigenpairs of a real symmetric matrix (n <= 64, d <= n) in one
 // workgroup of four wavefronts (one per SIMD of the CU).
 //  * Householder tridiagonalisation: lane r of wavefront w keeps entries
-//    16w .. 16w+15 of row r in registers; the column being reduced is
-//    published through LDS by the wavefront that owns it; each wavefront
-//    forms its part of p = t A v, the four parts are added in LDS in a fixed
-//    order, and every wavefront applies the rank-2 update to its columns
-//    (v and w are read from the lanes that own them with readlane).
-//  * The d largest eigenvalues of the tridiagonal T by multisection on
-//    Sturm counts: 256 / d lanes per eigenvalue.
+//    16w .. 16w+15 of row r in registers.  Columns k and k+1 are published
+//    through LDS; each wavefront forms its part of A x (x = column k below
+//    the diagonal) while the reflector's scalars are computed, so that
+//    p = t A v = t (A x - alpha A e_{k+1}) needs one exchange per column.
+//  * The d largest eigenvalues of T by multisection on Sturm counts, with
+//    the three-term recurrence of the leading principal minors of T - x I
+//    (no division; power-of-two rescaling every two terms): 256 / d lanes
+//    per eigenvalue.
 //  * Eigenvector j by inverse iteration (banded Gaussian elimination with
-//    partial pivoting on T - lambda_j I; vector in registers, factors in LDS)
-//    in lane j of the first wavefront; back-transform through the stored
-//    reflectors with the rows split over the four wavefronts; Cholesky QR.
+//    partial pivoting on T - lambda_j I, two passes) in lane j of the first
+//    wavefront; back-transform through the stored reflectors and the Gram
+//    matrix of the vectors by groups of lanes, one group per vector; Cholesky
+//    QR to orthonormalise in order.
 // Output: lam (d, decreasing), V (n x d, column-major); bit 32 of flags[0]
 // is set if the vectors are rank deficient.
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int TE_M = 64;   // largest order
+constexpr int TE_LX = TE_M + 1;   // padded stride of the vector array
 
 // 1/x to full double precision for finite x with |x| >= 1e-290: the hardware
 // estimate refined by two Newton steps
@@ -1353,6 +1356,15 @@ __device__ __forceinline__ double te_dpp(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// orders LDS accesses of one wavefront around an exchange between its lanes
+// (the wavefront executes them in program order; the fences keep the
+// compiler from moving them across)
+__device__ __forceinline__ void te_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // sum over the 64 lanes of a wavefront, returned in every lane: row shifts
 // accumulate each row of 16 into its last lane, the row broadcasts carry
 // rows 0..2 into lane 63
@@ -1365,6 +1377,93 @@ __device__ __forceinline__ double te_wave_sum(double v) {
   v += te_dpp<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
   return te_lane(v, 63);
 }
+
+// sum over aligned groups of L lanes (L a power of two, 4 <= L <= 64),
+// returned in every lane of the group: an inclusive scan inside the group
+// leaves the total in its last lane, which is then read by the group
+template <int L>
+__device__ __forceinline__ double te_grp_sum(double v) {
+  const int sub = threadIdx.x & (L - 1);
+  double t;
+  t = te_dpp<0x111, 0xf>(v);
+  v += (sub >= 1) ? t : 0.0;
+  t = te_dpp<0x112, 0xf>(v);
+  v += (sub >= 2) ? t : 0.0;
+  if (L >= 8) {
+    t = te_dpp<0x114, 0xf>(v);
+    v += (sub >= 4) ? t : 0.0;
+  }
+  if (L >= 16) {
+    t = te_dpp<0x118, 0xf>(v);
+    v += (sub >= 8) ? t : 0.0;
+  }
+  if (L >= 32) v += te_dpp<0x142, 0xa>(v);
+  if (L >= 64) {
+    v += te_dpp<0x143, 0xc>(v);
+    return te_lane(v, 63);
+  }
+  return __shfl(v, (int)(threadIdx.x & 63) | (L - 1), 64);
+}
+
+// Back-transform x <- H_0 H_1 ... H_{n-3} x of the d vectors in Xv
+// (Xv[c * TE_LX + i]: entry i of vector c), then the upper triangle of their
+// Gram matrix into Rc (Rc[a * TE_LX + b], a <= b).  Group c of L lanes owns
+// vector c, lane s of the group its entries s, s + L, ...
+template <int L>
+__device__ void te_back_gram(const double* __restrict__ H, const double* __restrict__ tau,
+                             double* __restrict__ Xv, double* __restrict__ Rc, int n, int d) {
+  constexpr int R = TE_M / L;
+  const int c = threadIdx.x / L, sub = threadIdx.x & (L - 1);
+  const bool act = c < d;
+  double x[R];
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int i = sub + L * t;
+    const double v = Xv[(act ? c : 0) * TE_LX + i];
+    x[t] = (act && i < n) ? v : 0.0;
+  }
+  for (int k = n - 3; k >= 0; --k) {
+    const double tk = tau[k];
+    if (tk == 0.0) continue;
+    const double* hk = H + k * TE_M + sub;
+    double h[R];
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      h[t] = hk[L * t];
+      if (t & 1)
+        s1 = fma(h[t], x[t], s1);
+      else
+        s0 = fma(h[t], x[t], s0);
+    }
+    const double s = tk * te_grp_sum<L>(s0 + s1);
+#pragma unroll
+    for (int t = 0; t < R; ++t) x[t] = fma(-s, h[t], x[t]);
+  }
+  __syncthreads();   // every group has read its input
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int i = sub + L * t;
+    if (act && i < n) Xv[c * TE_LX + i] = x[t];
+  }
+  __syncthreads();
+  // row c of the Gram matrix: all groups read vector j at the same time
+  for (int j = 0; j < d; ++j) {
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int i = sub + L * t;
+      const double xv = Xv[j * TE_LX + i];
+      const double xj = (i < n) ? xv : 0.0;
+      if (t & 1)
+        s1 = fma(x[t], xj, s1);
+      else
+        s0 = fma(x[t], xj, s0);
+    }
+    const double g = te_grp_sum<L>(s0 + s1);
+    if (act && sub == 0 && j >= c) Rc[c * TE_LX + j] = g;
+  }
+}
 }  // namespace
 
 __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restrict__ G, int n, int d,
@@ -1374,11 +1473,13 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
   constexpr int M = TE_M;
   constexpr int CW = 16;                // columns per wavefront
   __shared__ double H[M * M];          // H[k * M + i]: reflector k (zero for i <= k)
-  __shared__ double W[3 * M * M];      // elimination factors; later vectors and Gram
-  __shared__ double colk[M];           // column being reduced
-  __shared__ double ps[4 * M];         // per-wavefront parts of p (and of the back-transform dots)
-  __shared__ double vw[4 * 2 * M];     // per-wavefront copies of v and w
-  __shared__ double tau[M], dd[M], ee[M], e2[M], lamg[M];
+  __shared__ double W[3 * M * M];      // Sturm data; elimination factors; vectors and Gram
+  __shared__ double colk[M], colk1[M]; // columns k and k + 1
+  __shared__ double ps[4 * M];         // per-wavefront parts of A x
+  __shared__ double wbuf[4 * M];       // per-wavefront copies of w
+  __shared__ double tau[M], dd[M], ee[M], lamg[M];
+  __shared__ double red[8];
+  __shared__ int badf;
   const int tid = threadIdx.x, r = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
 #ifdef SYMROM_TOPEIG_TIMING
@@ -1395,15 +1496,37 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
     const int j = CW * w + jj;
     a[jj] = (r < n && j < n) ? G[(size_t)j * n + r] : 0.0;
   }
+  double* wb = wbuf + w * M;
   for (int k = 0; k + 2 < n; ++k) {
-    if (w == (k >> 4)) {
-      double xk = 0.0;
+    if (w == (k >> 4) || w == ((k + 1) >> 4)) {
+      double xk = 0.0, xk1 = 0.0;
 #pragma unroll
-      for (int jj = 0; jj < CW; ++jj) xk = (jj == (k & 15)) ? a[jj] : xk;
-      colk[r] = xk;
+      for (int jj = 0; jj < CW; ++jj) {
+        xk = (CW * w + jj == k) ? a[jj] : xk;
+        xk1 = (CW * w + jj == k + 1) ? a[jj] : xk1;
+      }
+      if (w == (k >> 4)) colk[r] = xk;
+      if (w == ((k + 1) >> 4)) colk1[r] = xk1;
     }
     __syncthreads();
-    const double xr = (r > k) ? colk[r] : 0.0;
+    // x (column k below the diagonal), this wavefront's part of A x, and
+    // the reflector I - t v v^T with v = x - alpha e_{k+1}
+    // (loads first, masks after: a conditional load would become a branch)
+    const double cr = colk[r];
+    const double a1 = colk1[r];
+    double xj[CW];
+#pragma unroll
+    for (int jj = 0; jj < CW; ++jj) xj[jj] = colk[CW * w + jj];
+    const double xr = (r > k) ? cr : 0.0;
+#pragma unroll
+    for (int jj = 0; jj < CW; ++jj) xj[jj] = (CW * w + jj > k) ? xj[jj] : 0.0;
+    double pw = 0.0, pw2 = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < CW; jj += 2) {
+      pw = fma(a[jj], xj[jj], pw);
+      pw2 = fma(a[jj + 1], xj[jj + 1], pw2);
+    }
+    ps[w * M + r] = pw + pw2;
     const double sig = te_wave_sum(xr * xr);
     const double x0 = te_lane(xr, k + 1);
     double t = 0.0, alpha = x0;
@@ -1423,36 +1546,19 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
         ee[k] = alpha;
       }
     }
+    __syncthreads();
     if (t != 0.0) {
-      // v and w of this wavefront's columns: each wavefront publishes its own
-      // (identical) copy in LDS and reads it back (same wavefront: ordered)
-      double* vb = vw + w * 2 * M;
-      double* wb = vb + M;
-      vb[r] = vr;
-      __builtin_amdgcn_wave_barrier();
-      double vj[CW];
-#pragma unroll
-      for (int jj = 0; jj < CW; ++jj) vj[jj] = vb[CW * w + jj];
-      double pw = 0.0, pw2 = 0.0;
-#pragma unroll
-      for (int jj = 0; jj < CW; jj += 2) {
-        pw = fma(a[jj], vj[jj], pw);
-        pw2 = fma(a[jj + 1], vj[jj + 1], pw2);
-      }
-      ps[w * M + r] = pw + pw2;
-      __syncthreads();
-      const double pr = (r > k && r < n)
-                            ? t * (((ps[r] + ps[M + r]) + ps[2 * M + r]) + ps[3 * M + r])
-                            : 0.0;
+      const double ax = ((ps[r] + ps[M + r]) + ps[2 * M + r]) + ps[3 * M + r];
+      const double pr = (r > k && r < n) ? t * (ax - alpha * a1) : 0.0;
       const double kv = te_wave_sum(vr * pr);
       const double wr = pr - 0.5 * t * kv * vr;   // zero for r <= k
       wb[r] = wr;
-      __builtin_amdgcn_wave_barrier();
+      te_wave_sync();
 #pragma unroll
-      for (int jj = 0; jj < CW; ++jj) a[jj] -= vr * wb[CW * w + jj] + wr * vj[jj];
-    } else {
-      // keep colk stable until every wavefront has read it
-      __syncthreads();
+      for (int jj = 0; jj < CW; ++jj) {
+        const double vj = (CW * w + jj == k + 1) ? xj[jj] - alpha : xj[jj];
+        a[jj] -= vr * wb[CW * w + jj] + wr * vj;
+      }
     }
   }
   __syncthreads();
@@ -1466,26 +1572,40 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
     }
     if (w == 0 && (r == n - 1 || r >= n)) ee[r] = 0.0;
     __syncthreads();
-    if (w == 0 && r < n) e2[r] = ee[r] * ee[r];
-    __syncthreads();
   }
   TS(1);
   // ---- d largest eigenvalues by multisection ----
-  double lo = 0.0, hi = 0.0, e2max = 0.0;
-  for (int i = 0; i < n; ++i) {
-    const double rad = fabs(i > 0 ? ee[i - 1] : 0.0) + fabs(ee[i]);
-    lo = (i == 0) ? dd[i] - rad : fmin(lo, dd[i] - rad);
-    hi = (i == 0) ? dd[i] + rad : fmax(hi, dd[i] + rad);
-    e2max = fmax(e2max, e2[i]);
+  // Gershgorin interval, in wavefront 0 (lane i: row i)
+  if (w == 0) {
+    const double ddr = dd[r], eer = ee[r], eem = ee[r > 0 ? r - 1 : 0];
+    const double di = (r < n) ? ddr : 0.0;
+    const double rad = (r < n) ? fabs(r > 0 ? eem : 0.0) + fabs(eer) : 0.0;
+    double lo = (r < n) ? di - rad : INFINITY, hi = (r < n) ? di + rad : -INFINITY;
+    for (int o = 32; o > 0; o >>= 1) {
+      lo = fmin(lo, __shfl_xor(lo, o, 64));
+      hi = fmax(hi, __shfl_xor(hi, o, 64));
+    }
+    if (r == 0) {
+      red[0] = lo;
+      red[1] = hi;
+    }
   }
-  const double scale = fmax(fabs(lo), fabs(hi));
-  // lane i of every wavefront holds d_i, e_i (read back by readlane later)
-  const double ddl = (r < n) ? dd[r] : 0.0, eel = ee[r];
-  // (d_i, e_{i-1}^2) pairs for the Sturm recurrence, one LDS read per step
+  __syncthreads();
+  const double lo = red[0], hi = red[1];
+  // power-of-two scale: T / sc exactly, entries of modulus <= 1
+  const double amax = fmax(fabs(lo), fabs(hi));
+  const double sc = (amax > 0.0) ? __builtin_amdgcn_ldexp(1.0, __builtin_amdgcn_frexp_exp(amax)) : 1.0;
+  const double isc = 1.0 / sc;
+  // (d_i, e_{i-1}^2) of T / sc, one LDS read per term; four padding terms
+  // with d = 4 (above every shift) leave the count unchanged
   double2* de = reinterpret_cast<double2*>(W);
-  if (tid < n) de[tid] = make_double2(dd[tid], tid > 0 ? e2[tid - 1] : 0.0);
-  // pivots below pivmin are replaced by -pivmin: e2 / pivmin stays finite
-  const double pivmin = 1e-290 * fmax(1.0, e2max);
+  if (tid < n + 4) {
+    const double ep = (tid > 0 && tid < n) ? ee[tid - 1] * isc : 0.0;
+    de[tid] = (tid < n) ? make_double2(dd[tid] * isc, ep * ep) : make_double2(4.0, 0.0);
+  }
+  // a pivot (ratio of consecutive minors) of modulus below pivmin is replaced
+  // by -pivmin: a perturbation of T / sc far below rounding
+  const double pivmin = 1e-60;
   // ms lanes per eigenvalue (a power of two, so a group never straddles a
   // wavefront and its bracket update is a butterfly over ms lanes)
   int ms = 1;
@@ -1494,26 +1614,33 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
   const bool gact = grp < d;
   const int kk = n - 1 - (gact ? grp : 0);       // eigenvalue kk in increasing order
   __syncthreads();
-  double a0 = lo, b0 = hi;
+  double a0 = lo * isc, b0 = hi * isc;
   for (int it = 0; it < 200; ++it) {
-    const bool more = gact && (b0 - a0 > 2.2e-16 * scale);
+    const bool more = gact && (b0 - a0 > 2.2e-16);
     if (!__syncthreads_or(more)) break;
     const double x = a0 + (b0 - a0) * (double)(sub + 1) / (double)(ms + 1);
-    // Sturm count: negative pivots of the LDL^T of T - x I; the reciprocal
-    // is the hardware estimate refined by one Newton step (a backward
-    // perturbation of e^2 by a few tens of ulps)
-    double2 pr = de[0];
-    double q = pr.x - x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    int cnt = (q < 0.0);
-#pragma unroll 4
-    for (int i = 1; i < n; ++i) {
-      pr = de[i];
-      double rq = __builtin_amdgcn_rcp(q);
-      rq = fma(rq, fma(-q, rq, 1.0), rq);
-      q = (pr.x - x) - pr.y * rq;
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += (q < 0.0);
+    // count of negative ratios P_{i+1} / P_i of the leading minors of
+    // T / sc - x I (the negative pivots of its LDL^T factorisation)
+    double pa = 1.0, pb = 0.0;   // P_i, P_{i-1}
+    int cnt = 0;
+    double2 c0 = de[0], c1 = de[1];
+    for (int i = 0; i < n; i += 2) {
+      const double2 n0 = de[i + 2], n1 = de[i + 3];
+      double pn = fma(c0.x - x, pa, -c0.y * pb);
+      pn = (fabs(pn) < pivmin * fabs(pa)) ? -pivmin * pa : pn;
+      cnt += (pn < 0.0) != (pa < 0.0);
+      pb = pa;
+      pa = pn;
+      pn = fma(c1.x - x, pa, -c1.y * pb);
+      pn = (fabs(pn) < pivmin * fabs(pa)) ? -pivmin * pa : pn;
+      cnt += (pn < 0.0) != (pa < 0.0);
+      pb = pa;
+      pa = pn;
+      const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(pa), fabs(pb)));
+      pa = __builtin_amdgcn_ldexp(pa, -ex);
+      pb = __builtin_amdgcn_ldexp(pb, -ex);
+      c0 = n0;
+      c1 = n1;
     }
     // new bracket: the largest point with count <= kk and the smallest with
     // count > kk, by a butterfly over the group (max / min: order-free)
@@ -1532,147 +1659,131 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
       }
     }
   }
-  if (gact && sub == 0) lamg[grp] = 0.5 * (a0 + b0);
+  if (gact && sub == 0) lamg[grp] = 0.5 * (a0 + b0) * sc;
   __syncthreads();
   TS(2);
   // ---- inverse iteration: lane c < d of wavefront 0 owns eigenvector c ----
-  const double isc = (scale > 0.0) ? 1.0 / scale : 1.0;
   const double ptiny = 2.2e-16;
-  double* U0 = W;
-  double* U1 = W + M * M;
-  double* U2 = W + 2 * M * M;
-  // (d_i, e_i) of T / scale, one LDS read per elimination step
+  double* U0 = W;                // reciprocal pivots
+  double* U1 = W + M * M;        // first superdiagonal of U
+  double* Xw = W + 2 * M * M;    // right-hand side, then solution: Xw[i * M + c]
+  double* Xv = W;                // vectors, Xv[c * TE_LX + i] (after the solves)
+  double* Rc = W + M * TE_LX;    // Gram matrix, then Cholesky factor
+  // (d_i, e_i) of T / sc
   __shared__ double2 dsc[M + 1];
-  if (tid <= M) dsc[tid] = (tid < n) ? make_double2(ddl * isc, eel * isc) : make_double2(0.0, 0.0);
-  __syncthreads();
-  if (w == 0 && d > 0) {
-    double x[M];
-    const double lv = lamg[min(r, d - 1)] * isc;
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
+  if (tid <= M)
+    dsc[tid] = (tid < n) ? make_double2(dd[tid] * isc, ee[tid] * isc) : make_double2(0.0, 0.0);
+  if (w == 0) {
+    for (int i = 0; i < n; ++i) {
       // a fixed start vector with no symmetry: 1 + frac(0.618 i) / 2
       const double hh = 0.6180339887498949 * (double)i;
-      x[i] = (i < n) ? 1.0 + 0.5 * (hh - floor(hh)) : 0.0;
+      Xw[i * M + r] = 1.0 + 0.5 * (hh - floor(hh));
     }
+  }
+  __syncthreads();
+  if (w == 0 && d > 0) {
+    const double lv = lamg[min(r, d - 1)] * isc;
     for (int pass = 0; pass < 2; ++pass) {
+      // forward elimination; bit i of swm: rows i and i + 1 exchanged
+      unsigned long long swm = 0ull;
       const double2 d0 = dsc[0];
       double c0 = d0.x - lv, c1 = (n > 1) ? d0.y : 0.0;
-#pragma unroll
-      for (int i = 0; i < M - 1; ++i) {
-        if (i < n - 1) {
-          const double2 di = dsc[i], dn = dsc[i + 1];
-          const double sb = di.y, dg = dn.x - lv;
-          const double sp = (i + 2 < n) ? dn.y : 0.0;
-          const bool swap = fabs(sb) > fabs(c0);
-          const double piv = swap ? sb : ((c0 == 0.0) ? ptiny : c0);
-          const double f = (swap ? c0 : sb) * te_rcp(piv);
-          U0[i * M + r] = piv;
-          U1[i * M + r] = swap ? dg : c1;
-          U2[i * M + r] = swap ? sp : 0.0;
-          const double xi = x[i], xn = x[i + 1];
-          x[i] = swap ? xn : xi;
-          x[i + 1] = swap ? (xi - f * xn) : (xn - f * xi);
-          const double n0 = swap ? (c1 - f * dg) : (dg - f * c1);
-          const double n1 = swap ? (-f * sp) : sp;
-          c0 = n0;
-          c1 = n1;
-        }
+      double carry = Xw[r];
+      for (int i = 0; i < n - 1; ++i) {
+        const double2 di = dsc[i], dn = dsc[i + 1];
+        const double sb = di.y, dg = dn.x - lv;
+        const double sp = (i + 2 < n) ? dn.y : 0.0;
+        const bool swap = fabs(sb) > fabs(c0);
+        const double piv = swap ? sb : ((c0 == 0.0) ? ptiny : c0);
+        const double rp = te_rcp(piv);
+        const double f = (swap ? c0 : sb) * rp;
+        U0[i * M + r] = rp;
+        U1[i * M + r] = swap ? dg : c1;
+        swm |= (unsigned long long)swap << i;
+        const double xi = carry, xn = Xw[(i + 1) * M + r];
+        Xw[i * M + r] = swap ? xn : xi;
+        carry = swap ? (xi - f * xn) : (xn - f * xi);
+        const double n0 = swap ? (c1 - f * dg) : (dg - f * c1);
+        const double n1 = swap ? (-f * sp) : sp;
+        c0 = n0;
+        c1 = n1;
       }
-      const double plast = (c0 == 0.0) ? ptiny : c0;
+      Xw[(n - 1) * M + r] = carry;
+      const double rpl = te_rcp((c0 == 0.0) ? ptiny : c0);
+      // back substitution
       double x1 = 0.0, x2 = 0.0, nrm = 0.0;
-#pragma unroll
-      for (int i = M - 1; i >= 0; --i) {
-        if (i < n) {
-          const double u0 = (i == n - 1) ? plast : U0[i * M + r];
-          const double u1 = (i + 1 < n) ? U1[i * M + r] : 0.0;
-          const double u2 = (i + 2 < n) ? U2[i * M + r] : 0.0;
-          const double xi = (x[i] - u1 * x1 - u2 * x2) * te_rcp(u0);
-          x[i] = xi;
-          nrm = fma(xi, xi, nrm);
-          x2 = x1;
-          x1 = xi;
-        }
+      for (int i = n - 1; i >= 0; --i) {
+        const double u0l = U0[i * M + r], u1l = U1[i * M + r], el = dsc[i + 1].y;
+        const double u0 = (i == n - 1) ? rpl : u0l;
+        const double u1 = (i + 1 < n) ? u1l : 0.0;
+        const double u2 = (i + 2 < n && ((swm >> i) & 1ull)) ? el : 0.0;
+        const double xi = (Xw[i * M + r] - u1 * x1 - u2 * x2) * u0;
+        Xw[i * M + r] = xi;
+        nrm = fma(xi, xi, nrm);
+        x2 = x1;
+        x1 = xi;
       }
       const double inv = 1.0 / sqrt(nrm);
-#pragma unroll
-      for (int i = 0; i < M; ++i) x[i] *= inv;
+      if (pass == 0) {
+        for (int i = 0; i < n; ++i) Xw[i * M + r] *= inv;
+      } else {
+        // publish vector r (the factors are no longer needed)
+        for (int i = 0; i < n; ++i) Xv[r * TE_LX + i] = Xw[i * M + r] * inv;
+      }
     }
-    // publish: XV[i * M + c] (the factors are no longer needed)
-#pragma unroll
-    for (int i = 0; i < M; ++i) W[i * M + r] = x[i];
   }
   __syncthreads();
   TS(3);
-  // ---- back-transform x <- H_0 H_1 ... H_{n-3} x, rows split over the
-  //      four wavefronts: wavefront w holds rows 16w .. 16w+15 of vector r ----
+  // ---- back-transform and Gram matrix, one group of lanes per vector ----
   {
-    double xb[CW];
-#pragma unroll
-    for (int ii = 0; ii < CW; ++ii) xb[ii] = W[(CW * w + ii) * M + r];
-    for (int k = n - 3; k >= 0; --k) {
-      const double t = tau[k];
-      if (t == 0.0) continue;
-      const double* hk = H + k * M + CW * w;
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int ii = 0; ii < CW; ii += 2) {
-        s0 = fma(hk[ii], xb[ii], s0);
-        s1 = fma(hk[ii + 1], xb[ii + 1], s1);
-      }
-      ps[w * M + r] = s0 + s1;
-      __syncthreads();
-      const double s = t * (((ps[r] + ps[M + r]) + ps[2 * M + r]) + ps[3 * M + r]);
-#pragma unroll
-      for (int ii = 0; ii < CW; ++ii) xb[ii] -= s * hk[ii];
-      __syncthreads();
+    int L = 64;
+    while (L > 4 && L * d > 256) L >>= 1;
+    switch (L) {
+      case 64: te_back_gram<64>(H, tau, Xv, Rc, n, d); break;
+      case 32: te_back_gram<32>(H, tau, Xv, Rc, n, d); break;
+      case 16: te_back_gram<16>(H, tau, Xv, Rc, n, d); break;
+      case 8: te_back_gram<8>(H, tau, Xv, Rc, n, d); break;
+      default: te_back_gram<4>(H, tau, Xv, Rc, n, d); break;
     }
-#pragma unroll
-    for (int ii = 0; ii < CW; ++ii) W[(CW * w + ii) * M + r] = xb[ii];
   }
   __syncthreads();
   TS(4);
-  // ---- Cholesky QR of the d vectors ----
-  double* XL = W;                 // XL[i * M + c]: entry i of vector c
-  double* Rc = W + M * M;         // Rc[a * (M + 1) + b]
-  // Gram: row a in lane a, columns b = w, w + 4, ... in wavefront w
-  if (r < d)
-    for (int b = w; b < d; b += 4) {
-      double s0 = 0.0, s1 = 0.0;
-      for (int i = 0; i < n; i += 2) {
-        s0 = fma(XL[i * M + r], XL[i * M + b], s0);
-        if (i + 1 < n) s1 = fma(XL[(i + 1) * M + r], XL[(i + 1) * M + b], s1);
+  // ---- Cholesky factor R of the Gram matrix (right-looking, wavefront 0;
+  //      lane b owns column b), then V = X R^{-1} ----
+  if (w == 0) {
+    int bad = 0;
+    for (int j = 0; j < d; ++j) {
+      const double gjj = Rc[j * TE_LX + j];
+      if (!(gjj > 0.0)) {
+        bad = 1;
+        break;
       }
-      Rc[r * (M + 1) + b] = s0 + s1;
+      const double rjj = sqrt(gjj);
+      const double ri = 1.0 / rjj;
+      double rjb = 0.0;
+      if (r > j && r < d) {
+        rjb = Rc[j * TE_LX + r] * ri;
+        Rc[j * TE_LX + r] = rjb;
+      }
+      if (r == j) Rc[j * TE_LX + j] = rjj;
+      te_wave_sync();
+      if (r > j && r < d)
+        for (int q = j + 1; q <= r; ++q) Rc[q * TE_LX + r] -= Rc[j * TE_LX + q] * rjb;
+      te_wave_sync();
     }
-  __syncthreads();
-  int bad = 0;
-  for (int j = 0; j < d; ++j) {
-    if (tid == 0) {
-      double s = Rc[j * (M + 1) + j];
-      for (int k = 0; k < j; ++k) s -= Rc[k * (M + 1) + j] * Rc[k * (M + 1) + j];
-      Rc[j * (M + 1) + j] = (s > 0.0) ? sqrt(s) : 0.0;
-    }
-    __syncthreads();
-    const double rjj = Rc[j * (M + 1) + j];
-    if (!(rjj > 0.0)) {
-      bad = 1;
-      break;
-    }
-    if (tid > j && tid < d) {
-      double s = Rc[j * (M + 1) + tid];
-      for (int k = 0; k < j; ++k) s -= Rc[k * (M + 1) + j] * Rc[k * (M + 1) + tid];
-      Rc[j * (M + 1) + tid] = s / rjj;   // R[j][tid], upper triangle
-    }
-    __syncthreads();
+    if (r == 0) badf = bad;
   }
+  __syncthreads();
+  const int bad = badf;
   if (!bad && tid < n) {
     // row tid of X R^{-1} by forward substitution, in place
     for (int c = 0; c < d; ++c) {
-      double s = XL[tid * M + c];
-      for (int k = 0; k < c; ++k) s -= XL[tid * M + k] * Rc[k * (M + 1) + c];
-      XL[tid * M + c] = s / Rc[c * (M + 1) + c];
+      double s = Xv[c * TE_LX + tid];
+      for (int q = 0; q < c; ++q) s = fma(-Xv[q * TE_LX + tid], Rc[q * TE_LX + c], s);
+      s /= Rc[c * TE_LX + c];
+      Xv[c * TE_LX + tid] = s;
+      V[(size_t)c * n + tid] = s;
     }
-    for (int c = 0; c < d; ++c) V[(size_t)c * n + tid] = XL[tid * M + c];
   }
   if (tid < d) lam[tid] = lamg[tid];
   if (tid == 0 && bad && flags) flags[0] |= 32;
