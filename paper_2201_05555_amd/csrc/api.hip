@@ -425,8 +425,13 @@ struct symrom_rom {
   cplx* Q;  // p x nmax
   double* prev;
   int* active;
-  int* counters;  // [0] active left, [1] stalled, [2] iterations run
-  int* flags;     // [0] error bits, [1] eigen path
+  // status block (device, 48 bytes, one readback): flags [0] error bits,
+  // [1] eigen path, [2] error bits of the DEIM chain; counters [0] active
+  // left, [1] stalled, [2] iterations run; eps_dev the rank indicator
+  int* status;
+  int* counters;
+  int* flags;
+  int* hstat;  // pinned host mirror of the status block
   cplx *Gram, *Amat, *MU, *MX, *M1, *M2, *M3, *C0x, *Rinv, *MP;
   cplx* gemm_part;
   double* sigma2;
@@ -503,8 +508,10 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.Q = ar.take<cplx>((size_t)p * nm);
   r.prev = ar.take<double>(p);
   r.active = ar.take<int>(p);
-  r.counters = ar.take<int>(4);
-  r.flags = ar.take<int>(4);
+  r.status = ar.take<int>(16);
+  r.flags = r.status;
+  r.counters = r.status + 4;
+  r.eps_dev = reinterpret_cast<double*>(r.status + 8);
   const size_t m2 = (size_t)4 * nm * nm;
   r.Gram = ar.take<cplx>(m2 > (size_t)p * p ? m2 : (size_t)p * p);
   r.Amat = ar.take<cplx>((size_t)nm * nm);
@@ -519,7 +526,6 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   // split-K partials: nkb * max(a*b) with a, b <= 64 (b chunked by 64)
   r.gemm_part = ar.take<cplx>((size_t)r.nkb * 64 * 64);
   r.sigma2 = ar.take<double>(nm);
-  r.eps_dev = ar.take<double>(4);
   r.colsq = ar.take<double>(p);
   r.Gp = ar.take<cplx>((size_t)p * p);
   r.Vp = ar.take<cplx>((size_t)p * p);
@@ -788,6 +794,18 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z) {
   Timer t(FAM_DENSE, s);
   launch_deim_basis_coeffs(s, reinterpret_cast<const double*>(r.YV), r.ylam, P, d, r.Mdeim,
                            dflags);
+}
+
+// Second half of the DEIM operator (after deim_update, same stream).
+void deim_update_tail(symrom_rom& r) {
+  if (!r.deim_on) return;
+  hipStream_t s = r.s2;
+  int* dflags = r.flags + 2;
+  const int N = r.N, d = r.d_cur;
+  std::vector<const double*> slots(r.nslots);
+  for (int q = 0; q < r.nslots; ++q) slots[q] = r.Ywin + (size_t)q * r.psub * N;
+  const int P = r.psub * r.nslots;
+  Timer t(FAM_DENSE, s);
   // Psi and its column sums.  No sign convention is applied to the columns:
   // flipping the sign of column k negates c_k and the residual exactly, so
   // the greedy indices and the weights are the same bit for bit.
@@ -815,10 +833,18 @@ void deim_k(symrom_rom& r, const cplx* U, const cplx* Z, const int* active, cplx
   if (kout) launch_deim_k(s, r.gF, c12, Z, r.n, r.p, kout);
 }
 
-symrom_status read_flags(symrom_rom& r, int* host) {
-  HIPCHK(hipMemcpyAsync(host, r.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, r.s));
+// the whole status block into the pinned mirror (one copy, one wait)
+symrom_status read_status(symrom_rom& r) {
+  HIPCHK(hipMemcpyAsync(r.hstat, r.status, 12 * sizeof(int), hipMemcpyDeviceToHost, r.s));
   HIPCHK(hipStreamSynchronize(r.s));
   return SYMROM_OK;
+}
+
+symrom_status read_flags(symrom_rom& r, int* host) {
+  symrom_status st = read_status(r);
+  host[0] = r.hstat[0] | r.hstat[2];
+  host[1] = r.hstat[1];
+  return st;
 }
 
 symrom_status rom_grow_apply(symrom_rom& r, int k);
@@ -840,10 +866,15 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
     HIPCHK(hipEventRecord(r.ev_fork, s));
     HIPCHK(hipStreamWaitEvent(r.s2, r.ev_fork, 0));
     deim_update(r, r.U0, r.Z0);
-    HIPCHK(hipEventRecord(r.ev_join, r.s2));
   }
   const bool deim = use_deim && r.deim_on;
+  // (the eigensolver keeps one CU busy for a while: enqueue part of the main
+  // work before the rest of the chain, so that both streams have work)
   basis_velocity(r, r.U0, r.Z0, 0.5 * dt, r.Xi, deim ? nullptr : r.k);
+  if (use_deim) {
+    deim_update_tail(r);
+    HIPCHK(hipEventRecord(r.ev_join, r.s2));
+  }
   if (deim) linear_grams(r, r.U0, r.C12a);
   // U_half = R_{U0}(xi_half)
   cayley(r, r.U0, r.Xi, r.Uh, r.Amat);
@@ -898,8 +929,9 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
       }
     }
     LAUNCHCHK();
-    HIPCHK(hipMemcpyAsync(hc, r.counters, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(r.hstat + 4, r.counters, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    for (int q = 0; q < 3; ++q) hc[q] = r.hstat[4 + q];
     r.n_active = hc[0];
     if (hc[0] == 0) break;
     batch = 1;
@@ -939,13 +971,14 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
     launch_dense_indicator(s, r.colsq, r.gproj, n, p, r.eps_dev);
   }
   LAUNCHCHK();
-  int fl[4];
+  {
+    symrom_status st = read_status(r);
+    if (st != SYMROM_OK) return st;
+  }
+  const int fl0 = r.hstat[0] | r.hstat[2];
   double eps = 0.0;
-  HIPCHK(hipMemcpyAsync(fl, r.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-  if (decide_rank)
-    HIPCHK(hipMemcpyAsync(&eps, r.eps_dev, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  if (fl[0] | fl[2]) {
+  std::memcpy(&eps, r.hstat + 8, sizeof(double));
+  if (fl0) {
     std::swap(r.U0, r.Uh);
     std::swap(r.Z0, r.Z1);
     return fail(SYMROM_ESINGULAR, "singular small matrix in the basis update");
@@ -1106,10 +1139,18 @@ extern "C" symrom_status rom_init(const symrom_config* cfg, const double* L, con
     return fail(SYMROM_EDEVICE, "rom_init: launch failure");
   }
   int fl[2] = {0, 0};
-  hipMemcpy(fl, r->flags, 2 * sizeof(int), hipMemcpyDeviceToHost);
+  if (hipMemcpy(fl, r->flags, 2 * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+    delete r;
+    return fail(SYMROM_EDEVICE, "rom_init: flags readback");
+  }
   if (fl[0]) {
     delete r;
     return fail(SYMROM_ESINGULAR, "rom_init: basis orthonormalisation failed");
+  }
+  if (hipHostMalloc((void**)&r->hstat, 64, hipHostMallocDefault) != hipSuccess) {
+    r->hstat = nullptr;
+    rom_destroy(r);
+    return fail(SYMROM_EDEVICE, "rom_init: pinned status buffer");
   }
   if (cfg->projection == SYMROM_DEIM &&
       (hipStreamCreateWithFlags(&r->s2, hipStreamNonBlocking) != hipSuccess ||
@@ -1156,9 +1197,12 @@ symrom_status rom_grow(symrom_rom& r, int k, bool decide) {
     // eps needs only |G|^2 and |g|^2
     launch_dense_indicator(s, r.colsq, r.gproj, n, p, r.eps_dev);
     LAUNCHCHK();
+    {
+      symrom_status st = read_status(r);
+      if (st != SYMROM_OK) return st;
+    }
     double eps = 0.0;
-    HIPCHK(hipMemcpyAsync(&eps, r.eps_dev, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    std::memcpy(&eps, r.hstat + 8, sizeof(double));
     r.last.rank_indicator = eps;
     if (!(eps > r.cfg.rank_tol_up) || 2 * (n + 1) > r.cfg.two_n_max) {
       // the gradient just computed is the next step's first-stage gradient
@@ -1313,5 +1357,6 @@ extern "C" void rom_destroy(symrom_rom* r) {
   if (r->ev_fork) (void)hipEventDestroy(r->ev_fork);
   if (r->ev_join) (void)hipEventDestroy(r->ev_join);
   if (r->s2) (void)hipStreamDestroy(r->s2);
+  if (r->hstat) (void)hipHostFree(r->hstat);
   delete r;
 }

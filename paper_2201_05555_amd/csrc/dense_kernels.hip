@@ -1486,8 +1486,17 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
   unsigned long long tsv[6];
   tsv[0] = wall_clock64();
 #define TS(k) tsv[k] = wall_clock64()
+  long long seg[5] = {0, 0, 0, 0, 0};
+  long long tprev = clock64();
+#define SEG(i)                  \
+  {                             \
+    long long tn = clock64();   \
+    seg[i] += tn - tprev;       \
+    tprev = tn;                 \
+  }
 #else
 #define TS(k)
+#define SEG(i)
 #endif
   // ---- tridiagonalisation ----
   double a[CW];
@@ -1508,7 +1517,9 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
       if (w == (k >> 4)) colk[r] = xk;
       if (w == ((k + 1) >> 4)) colk1[r] = xk1;
     }
+    SEG(0);
     __syncthreads();
+    SEG(1);
     // x (column k below the diagonal), this wavefront's part of A x, and
     // the reflector I - t v v^T with v = x - alpha e_{k+1}
     // (loads first, masks after: a conditional load would become a branch)
@@ -1546,7 +1557,9 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
         ee[k] = alpha;
       }
     }
+    SEG(2);
     __syncthreads();
+    SEG(3);
     if (t != 0.0) {
       const double ax = ((ps[r] + ps[M + r]) + ps[2 * M + r]) + ps[3 * M + r];
       const double pr = (r > k && r < n) ? t * (ax - alpha * a1) : 0.0;
@@ -1560,6 +1573,7 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
         a[jj] -= vr * wb[CW * w + jj] + wr * vj;
       }
     }
+    SEG(4);
   }
   __syncthreads();
   {
@@ -1791,8 +1805,11 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
   TS(5);
   if (tid == 0 && flags)
     for (int k = 0; k < 6; ++k) flags[8 + k] = (int)(tsv[k] - tsv[0]);
+  if ((tid & 63) == 0 && flags)
+    for (int k = 0; k < 5; ++k) flags[16 + 8 * w + k] = (int)seg[k];
 #endif
 #undef TS
+#undef SEG
 }
 
 void launch_dense_topeig(hipStream_t s, const double* G, int n, int d, double* V, double* lam,
