@@ -451,6 +451,7 @@ struct symrom_rom {
   double* Psi;
   int* didx;
   double *dw, *dc, *bval, *colpart, *Mdeim, *ylam;
+  double *dB, *dcv;  // ping-pong (P^T Psi)^{-1} (64 x 64) and coefficient vectors of the greedy passes
   int* bidx;
   int nbg, nbc;
   cplx *YG, *YV, *C12, *C12a, *gF;
@@ -544,6 +545,8 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.dw = ar.take<double>(dmax);
   r.dc = ar.take<double>(dmax);
   r.bval = ar.take<double>(2 * (size_t)r.nbg);
+  r.dB = ar.take<double>(r.cfg.projection == SYMROM_DEIM ? 2 * 64 * 64 : 0);
+  r.dcv = ar.take<double>(r.cfg.projection == SYMROM_DEIM ? 2 * 64 : 0);
   r.bidx = ar.take<int>(2 * (size_t)r.nbg);
   r.colpart = ar.take<double>((size_t)psi_blocks(r.N) * dmax);
   r.Mdeim = ar.take<double>((size_t)P * dmax);
@@ -812,14 +815,19 @@ void deim_update_tail(symrom_rom& r) {
   launch_psi_colsum(s, slots.data(), r.nslots, r.psub, N, r.Mdeim, P, d, r.Psi, r.colpart);
   // greedy selection, one launch per index; block results ping-pong between
   // the two halves of bval / bidx
+  // the inverse of P^T Psi and the coefficients ping-pong as well (pass k
+  // reads those of pass k-1)
   for (int k = 0; k < d; ++k) {
     const int cur = k & 1, prev = cur ^ 1;
     launch_deim_greedy(s, r.Psi, N, k, r.didx, r.bval + prev * r.nbg, r.bidx + prev * r.nbg,
-                       r.nbg, r.nbg, r.bval + cur * r.nbg, r.bidx + cur * r.nbg, dflags);
+                       r.nbg, r.nbg, r.bval + cur * r.nbg, r.bidx + cur * r.nbg,
+                       r.dB + prev * 4096, r.dcv + prev * 64, r.dB + cur * 4096,
+                       r.dcv + cur * 64, dflags);
   }
   const int last = (d - 1) & 1;
-  launch_deim_weights2(s, r.Psi, N, d, r.didx, r.bval + last * r.nbg, r.bidx + last * r.nbg,
-                       r.nbg, r.colpart, psi_blocks(N), r.dw, dflags);
+  launch_deim_weights(s, r.Psi, N, d, r.didx, r.bval + last * r.nbg, r.bidx + last * r.nbg,
+                      r.nbg, r.dB + last * 4096, r.dcv + last * 64, r.colpart, psi_blocks(N),
+                      r.dw, dflags);
 }
 
 // DEIM gradient at (U, Z) with the field of the last Poisson solve:

@@ -1338,6 +1338,20 @@ __device__ __forceinline__ double te_rcp(double x) {
   return fma(r, e, r);
 }
 
+// square root of a positive normal x to about full precision: the hardware
+// reciprocal square root estimate refined by Goldschmidt steps
+__device__ __forceinline__ double te_sqrt(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double e = fma(-g, h, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
 // value of v in lane `lane` (uniform), as a scalar
 __device__ __forceinline__ double te_lane(double v, int lane) {
   const long long b = __double_as_longlong(v);
@@ -1376,6 +1390,24 @@ __device__ __forceinline__ double te_wave_sum(double v) {
   v += te_dpp<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
   v += te_dpp<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
   return te_lane(v, 63);
+}
+
+// two wavefront sums at once (independent chains, interleaved)
+__device__ __forceinline__ void te_wave_sum2(double& u, double& v) {
+  u += te_dpp<0x111, 0xf>(u);
+  v += te_dpp<0x111, 0xf>(v);
+  u += te_dpp<0x112, 0xf>(u);
+  v += te_dpp<0x112, 0xf>(v);
+  u += te_dpp<0x114, 0xf>(u);
+  v += te_dpp<0x114, 0xf>(v);
+  u += te_dpp<0x118, 0xf>(u);
+  v += te_dpp<0x118, 0xf>(v);
+  u += te_dpp<0x142, 0xa>(u);
+  v += te_dpp<0x142, 0xa>(v);
+  u += te_dpp<0x143, 0xc>(u);
+  v += te_dpp<0x143, 0xc>(v);
+  u = te_lane(u, 63);
+  v = te_lane(v, 63);
 }
 
 // sum over aligned groups of L lanes (L a power of two, 4 <= L <= 64),
@@ -1476,7 +1508,9 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
   __shared__ double W[3 * M * M];      // Sturm data; elimination factors; vectors and Gram
   __shared__ double colk[M], colk1[M]; // columns k and k + 1
   __shared__ double ps[4 * M];         // per-wavefront parts of A x
+  __shared__ double dcor[M];           // corrections of the diagonal
   __shared__ double wbuf[4 * M];       // per-wavefront copies of w
+  __shared__ double qsw[8];            // per-wavefront parts of x^T A x and |x|^2
   __shared__ double tau[M], dd[M], ee[M], lamg[M];
   __shared__ double red[8];
   __shared__ int badf;
@@ -1499,53 +1533,72 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
 #define SEG(i)
 #endif
   // ---- tridiagonalisation ----
+  // The matrix is first scaled by a power of two (exact) so that its largest
+  // entry lies in [1/2, 1): the reflector scalars then stay far from under-
+  // and overflow.  The eigenvalues are scaled back at the end.
   double a[CW];
+  double gmx = 0.0;
 #pragma unroll
   for (int jj = 0; jj < CW; ++jj) {
     const int j = CW * w + jj;
     a[jj] = (r < n && j < n) ? G[(size_t)j * n + r] : 0.0;
+    gmx = fmax(gmx, fabs(a[jj]));
   }
+  for (int o = 32; o > 0; o >>= 1) gmx = fmax(gmx, __shfl_xor(gmx, o, 64));
+  if (r == 0) red[w] = gmx;
+  __syncthreads();
+  gmx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  const int gex = (gmx > 0.0) ? __builtin_amdgcn_frexp_exp(gmx) : 0;
+#pragma unroll
+  for (int jj = 0; jj < CW; ++jj) a[jj] = __builtin_amdgcn_ldexp(a[jj], -gex);
   double* wb = wbuf + w * M;
   for (int k = 0; k + 2 < n; ++k) {
-    if (w == (k >> 4) || w == ((k + 1) >> 4)) {
-      double xk = 0.0, xk1 = 0.0;
+    // Rows k and k+1 (the trailing matrix is symmetric: they are columns k
+    // and k+1) are published by lanes k and k+1 of every wavefront, each for
+    // its own 16 columns; then the processed part of row k (columns <= k) is
+    // cleared by the lanes of the same wavefront (stores of one wavefront to
+    // LDS take effect in program order).
+    if (r == k || r == k + 1) {
+      double* dst = (r == k ? colk : colk1) + CW * w;
 #pragma unroll
-      for (int jj = 0; jj < CW; ++jj) {
-        xk = (CW * w + jj == k) ? a[jj] : xk;
-        xk1 = (CW * w + jj == k + 1) ? a[jj] : xk1;
-      }
-      if (w == (k >> 4)) colk[r] = xk;
-      if (w == ((k + 1) >> 4)) colk1[r] = xk1;
+      for (int jj = 0; jj < CW; jj += 2)
+        *reinterpret_cast<double2*>(dst + jj) = make_double2(a[jj], a[jj + 1]);
     }
+    if (r >= CW * w && r < CW * w + CW && r <= k) colk[r] = 0.0;
     SEG(0);
     __syncthreads();
     SEG(1);
-    // x (column k below the diagonal), this wavefront's part of A x, and
-    // the reflector I - t v v^T with v = x - alpha e_{k+1}
-    // (loads first, masks after: a conditional load would become a branch)
-    const double cr = colk[r];
-    const double a1 = colk1[r];
+    // x (row k right of the diagonal), this wavefront's part of A x and of
+    // x^T A x, |x|^2, and the reflector I - t v v^T with v = x - alpha e_{k+1}
+    const double xr = colk[r];          // zero for r <= k
+    const double a1 = colk1[r];         // A[r][k+1]
+    const double x0 = colk[k + 1];
+    const double a11 = colk1[k + 1];
     double xj[CW];
 #pragma unroll
-    for (int jj = 0; jj < CW; ++jj) xj[jj] = colk[CW * w + jj];
-    const double xr = (r > k) ? cr : 0.0;
-#pragma unroll
-    for (int jj = 0; jj < CW; ++jj) xj[jj] = (CW * w + jj > k) ? xj[jj] : 0.0;
+    for (int jj = 0; jj < CW; jj += 2) {
+      const double2 q = *reinterpret_cast<const double2*>(colk + CW * w + jj);
+      xj[jj] = q.x;
+      xj[jj + 1] = q.y;
+    }
     double pw = 0.0, pw2 = 0.0;
 #pragma unroll
     for (int jj = 0; jj < CW; jj += 2) {
       pw = fma(a[jj], xj[jj], pw);
       pw2 = fma(a[jj + 1], xj[jj + 1], pw2);
     }
-    ps[w * M + r] = pw + pw2;
-    const double sig = te_wave_sum(xr * xr);
-    const double x0 = te_lane(xr, k + 1);
+    pw += pw2;
+    ps[w * M + r] = pw;
+    double qw = xr * pw, sig = xr * xr;
+    te_wave_sum2(qw, sig);
+    if (r == 0) qsw[w] = qw;
     double t = 0.0, alpha = x0;
-    if (sig > 0.0) {
-      const double al = (x0 >= 0.0) ? -sqrt(sig) : sqrt(sig);
+    if (sig > 1e-280) {
+      const double sq = te_sqrt(sig);
+      const double al = (x0 >= 0.0) ? -sq : sq;
       const double vn2 = 2.0 * sig - 2.0 * al * x0;
-      if (vn2 > 0.0) {
-        t = 2.0 / vn2;
+      if (vn2 > 1e-280) {
+        t = 2.0 * te_rcp(vn2);
         alpha = al;
       }
     }
@@ -1561,28 +1614,45 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
     __syncthreads();
     SEG(3);
     if (t != 0.0) {
+      // p = t A v = t (A x - alpha A e_{k+1});  v^T p = t (x^T A x -
+      // 2 alpha (A x)_{k+1} + alpha^2 A_{k+1,k+1});  w = p - (t/2)(v^T p) v
       const double ax = ((ps[r] + ps[M + r]) + ps[2 * M + r]) + ps[3 * M + r];
+      const double ax1 =
+          ((ps[k + 1] + ps[M + k + 1]) + ps[2 * M + k + 1]) + ps[3 * M + k + 1];
+      const double xax = ((qsw[0] + qsw[1]) + qsw[2]) + qsw[3];
       const double pr = (r > k && r < n) ? t * (ax - alpha * a1) : 0.0;
-      const double kv = te_wave_sum(vr * pr);
+      const double kv = t * ((xax - 2.0 * alpha * ax1) + alpha * alpha * a11);
       const double wr = pr - 0.5 * t * kv * vr;   // zero for r <= k
+      // A <- A - v w^T - w v^T, with x in place of v for the column factor:
+      // the difference, alpha w in column k+1, is never read again except
+      // on the diagonal, which is corrected at the end
+      if (w == 0 && r == k + 1) dcor[r] = alpha * wr;
       wb[r] = wr;
-      te_wave_sync();
+      double wj[CW];
 #pragma unroll
-      for (int jj = 0; jj < CW; ++jj) {
-        const double vj = (CW * w + jj == k + 1) ? xj[jj] - alpha : xj[jj];
-        a[jj] -= vr * wb[CW * w + jj] + wr * vj;
+      for (int jj = 0; jj < CW; jj += 2) {
+        const double2 q = *reinterpret_cast<const double2*>(wb + CW * w + jj);
+        wj[jj] = q.x;
+        wj[jj + 1] = q.y;
       }
+#pragma unroll
+      for (int jj = 0; jj < CW; ++jj) a[jj] = fma(-vr, wj[jj], fma(-wr, xj[jj], a[jj]));
+    } else if (w == 0 && r == k + 1) {
+      dcor[r] = 0.0;
     }
     SEG(4);
   }
   __syncthreads();
   {
     // diagonal and last subdiagonal entry from the wavefront owning the column
+    // (column k+1 of step k holds A - v w^T - w x^T: its diagonal entry
+    // misses alpha w_{k+1}, and the last subdiagonal entry is read from row
+    // n-2, whose column n-1 was never such a column)
 #pragma unroll
     for (int jj = 0; jj < CW; ++jj) {
       const int j = CW * w + jj;
-      if (j == r && r < n) dd[r] = a[jj];
-      if (n >= 2 && j == n - 2 && r == n - 1) ee[n - 2] = a[jj];
+      if (j == r && r < n) dd[r] = a[jj] + ((r >= 1 && r + 1 < n) ? dcor[r] : 0.0);
+      if (n >= 2 && j == n - 1 && r == n - 2) ee[n - 2] = a[jj];
     }
     if (w == 0 && (r == n - 1 || r >= n)) ee[r] = 0.0;
     __syncthreads();
@@ -1799,7 +1869,7 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
       V[(size_t)c * n + tid] = s;
     }
   }
-  if (tid < d) lam[tid] = lamg[tid];
+  if (tid < d) lam[tid] = __builtin_amdgcn_ldexp(lamg[tid], gex);
   if (tid == 0 && bad && flags) flags[0] |= 32;
 #ifdef SYMROM_TOPEIG_TIMING
   TS(5);

@@ -111,10 +111,12 @@ void launch_psi_colsum(hipStream_t s, const double* const* in, int nin, int kin,
                        const double* M, int ldM, int d, double* out, double* colpart);
 void launch_deim_greedy(hipStream_t s, const double* Psi, int N, int k, int* idx,
                         const double* pval, const int* pidx, int nprev, int nblk, double* bval,
-                        int* bidx, int* flags);
-void launch_deim_weights2(hipStream_t s, const double* Psi, int N, int d, int* idx,
-                          const double* pval, const int* pidx, int nprev, const double* colpart,
-                          int ncp, double* w, int* flags);
+                        int* bidx, const double* Bprev, const double* uprev, double* Bnext,
+                        double* cnext, int* flags);
+void launch_deim_weights(hipStream_t s, const double* Psi, int N, int d, int* idx,
+                         const double* pval, const int* pidx, int nprev, const double* Bprev,
+                         const double* uprev, const double* colpart, int ncp, double* w,
+                         int* flags);
 
 // dense_kernels.hip  (single-workgroup FP64 kernels on small matrices)
 struct DenseCtl;  // device-resident control block, see dense_kernels.hip

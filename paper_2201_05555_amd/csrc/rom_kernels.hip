@@ -574,56 +574,6 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
 // DEIM basis, indices and weights (Sec. 4.3), N-wide passes.
 // ---------------------------------------------------------------------------
 
-// Dense solve of the k x k system in the augmented array A (row j at
-// A[j * DG_LD], right-hand side in column k) by Gaussian elimination with
-// partial pivoting (largest modulus, smallest row on ties); x receives the
-// solution.  Called by every thread of a 256-thread block (barriers inside);
-// rows are owned by the lanes of the first wavefront.  Returns nonzero (in
-// every thread) when a pivot is zero.
-#define DG_LD 65
-__device__ int dg_solve(double* A, int k, double* x, int* flag) {
-  const int tid = threadIdx.x;
-  if (tid == 0) *flag = 0;
-  __syncthreads();
-  for (int s = 0; s < k; ++s) {
-    if (tid < 64) {
-      double v = (tid >= s && tid < k) ? fabs(A[tid * DG_LD + s]) : -1.0;
-      int vi = tid;
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(v, o, 64);
-        const int oi = __shfl_xor(vi, o, 64);
-        if (ov > v || (ov == v && oi < vi)) {
-          v = ov;
-          vi = oi;
-        }
-      }
-      // every lane holds the pivot row vi; swap rows s and vi column-wise
-      if (vi != s)
-        for (int q = tid; q <= k; q += 64) {
-          const double t = A[s * DG_LD + q];
-          A[s * DG_LD + q] = A[vi * DG_LD + q];
-          A[vi * DG_LD + q] = t;
-        }
-      if (tid == 0 && !(v > 0.0)) *flag = 1;
-    }
-    __syncthreads();
-    if (*flag) return 1;
-    if (tid > s && tid < k) {
-      const double f = A[tid * DG_LD + s] / A[s * DG_LD + s];
-      for (int q = s + 1; q <= k; ++q) A[tid * DG_LD + q] = fma(-f, A[s * DG_LD + q], A[tid * DG_LD + q]);
-    }
-    __syncthreads();
-  }
-  if (tid == 0)
-    for (int s = k - 1; s >= 0; --s) {
-      double v = A[s * DG_LD + k];
-      for (int q = s + 1; q < k; ++q) v = fma(-A[s * DG_LD + q], x[q], v);
-      x[s] = v / A[s * DG_LD + s];
-    }
-  __syncthreads();
-  return 0;
-}
-
 // winner of per-block (value, index) results: largest value, smallest index
 // on ties; computed by the first wavefront, returned in its lanes
 __device__ int dg_winner(const double* __restrict__ val, const int* __restrict__ idx, int nb) {
@@ -650,26 +600,93 @@ __device__ int dg_winner(const double* __restrict__ val, const int* __restrict__
 }
 
 // Greedy DEIM step k (the selection rule of Sec. 4.3): l_k = argmax |r_k|,
-// r_k = psi_k - Psi_{k-1} c, (P^T Psi_{k-1}) c = P^T psi_k.  Each block first
-// takes the winner of the previous pass (pval, pidx: nprev block results),
-// which block 0 records as idx[k-1], solves the k x k system redundantly,
-// then writes the (value, index) of the largest residual over its rows
-// (smallest index on ties) to bval, bidx.  k = 0 takes r_0 = psi_0.
-__global__ void __launch_bounds__(256) deim_greedy_kernel(const double* __restrict__ Psi, int N,
-                                                          int k, int* __restrict__ idx,
-                                                          const double* __restrict__ pval,
-                                                          const int* __restrict__ pidx, int nprev,
-                                                          double* __restrict__ bval,
-                                                          int* __restrict__ bidx,
-                                                          int* __restrict__ flags) {
-  __shared__ double A[64 * DG_LD];
-  __shared__ double cs[64];
-  __shared__ int rows[64];
-  __shared__ int flag;
+// r_k = psi_k - Psi_{k-1} c_k, M_k c_k = P^T psi_k with M_k = P^T Psi_{k-1}
+// (k x k; rows l_0 .. l_{k-1}).  Instead of a fresh solve per step, the
+// inverse of M_k is carried from pass to pass by bordering: with
+// B = M_{k-1}^{-1} and u = c_{k-1} from the previous pass, the new row
+// b = Psi[l_{k-1}, 0..k-2], delta = Psi[l_{k-1}, k-1] and the Schur complement
+// s = delta - b.u (the winning residual itself),
+//   M_k^{-1} = [[B + u v^T / s, -u / s], [-v^T / s, 1 / s]],  v = B^T b,
+//   c_k = [B y' - tau u ; tau],  tau = (y_last - v.y') / s,
+// where y' = Psi[l_0..l_{k-2}, k] and y_last = Psi[l_{k-1}, k].  Every block
+// forms c_k redundantly (wavefront 0); block 0 also writes M_k^{-1} and c_k
+// for the next pass and records l_{k-1} = the winner of the previous pass
+// (pval, pidx: nprev block results).  Each block then writes the (value,
+// index) of the largest |r_k| over its rows (smallest index on ties) to bval,
+// bidx.  k = 0 takes r_0 = psi_0.  Inverses are kept as 64 x 64 row-major.
+#define DG_KR 16   // leading columns of Psi prefetched for a thread's first two rows
+__device__ __forceinline__ double dg_wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Bordering step shared by the greedy passes and the weights: reads
+// Bprev (m x m, m = k - 1), uprev (m), the rows idx[0..m-1] and l = lwin;
+// leaves c_k in cs[0..k-1], v in vs, u in us, B in Bs and s in sh_s.
+__device__ void dg_border(const double* __restrict__ Psi, int N, int k, int ycol,
+                          const int* __restrict__ idx, int l, double* Bs, double* us,
+                          double* ys, double* bs, double* cs, double* vs, double* sh_s) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int m = k - 1;
+  if (tid < m) bs[tid] = Psi[(size_t)tid * N + l];
+  __syncthreads();
+  if (tid < 64) {
+    const double delta = Psi[(size_t)m * N + l];
+    const double ylast = (ycol >= 0) ? Psi[(size_t)ycol * N + l] : 0.0;
+    double vj = 0.0, zj = 0.0;
+    for (int i = 0; i < m; ++i) {
+      vj = fma(Bs[i * 65 + lane], bs[i], vj);   // (B^T b)_lane
+      zj = fma(Bs[lane * 65 + i], ys[i], zj);   // (B y')_lane
+    }
+    const double ul = us[lane], bl = bs[lane], yl = ys[lane];
+    vj = (lane < m) ? vj : 0.0;
+    zj = (lane < m) ? zj : 0.0;
+    const double s = delta - dg_wave_sum((lane < m) ? bl * ul : 0.0);
+    const double vy = dg_wave_sum((lane < m) ? vj * yl : 0.0);
+    const double tau = (ylast - vy) / s;
+    cs[lane] = (lane < m) ? zj - tau * ul : ((lane == m) ? tau : 0.0);
+    vs[lane] = vj;
+    if (lane == 0) *sh_s = s;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) deim_greedy_kernel(
+    const double* __restrict__ Psi, int N, int k, int* __restrict__ idx,
+    const double* __restrict__ pval, const int* __restrict__ pidx, int nprev,
+    double* __restrict__ bval, int* __restrict__ bidx, const double* __restrict__ Bprev,
+    const double* __restrict__ uprev, double* __restrict__ Bnext, double* __restrict__ cnext,
+    int* __restrict__ flags) {
+  __shared__ double Bs[64 * 65];
+  __shared__ double us[64], ys[64], bs[64], cs[64], vs[64], cf[64];
+  __shared__ double sh_s;
   __shared__ double sv[4];
   __shared__ int si[4];
+  __shared__ int lwin;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int stride = gridDim.x * 256;
+  // the leading entries of this thread's first two rows, loaded before the
+  // winner is known (addresses clamped in range; unused entries ignored)
+  const int l0 = blockIdx.x * 256 + tid, l1 = l0 + stride;
+  const int l0c = min(l0, N - 1), l1c = min(l1, N - 1);
+  double p0[DG_KR], p1[DG_KR];
+#pragma unroll
+  for (int q = 0; q < DG_KR; ++q) {
+    const int qc = min(q, k);
+    p0[q] = Psi[(size_t)qc * N + l0c];
+    p1[q] = Psi[(size_t)qc * N + l1c];
+  }
   if (k > 0) {
+    const int m = k - 1;
+    for (int t = tid; t < m * m; t += 256) {
+      const int i = t / m, j = t - i * m;
+      Bs[i * 65 + j] = Bprev[i * 64 + j];
+    }
+    if (tid < 64) {
+      us[tid] = (tid < m) ? uprev[tid] : 0.0;
+      ys[tid] = (tid < m) ? Psi[(size_t)k * N + idx[tid]] : 0.0;
+      bs[tid] = 0.0;
+    }
     if (w == 0) {
       int win = dg_winner(pval, pidx, nprev);
       if (win < 0 || win >= N) {
@@ -678,33 +695,75 @@ __global__ void __launch_bounds__(256) deim_greedy_kernel(const double* __restri
         win = 0;
       }
       if (lane == 0) {
-        rows[k - 1] = win;
+        lwin = win;
         if (blockIdx.x == 0) idx[k - 1] = win;
       }
-      for (int t = lane; t < k - 1; t += 64) rows[t] = idx[t];
     }
     __syncthreads();
-    for (int t = tid; t < k * (k + 1); t += 256) {
-      const int j = t / (k + 1), q = t % (k + 1);
-      A[j * DG_LD + q] = Psi[(size_t)q * N + rows[j]];
-    }
-    __syncthreads();
-    if (dg_solve(A, k, cs, &flag)) {
+    dg_border(Psi, N, k, k, idx, lwin, Bs, us, ys, bs, cs, vs, &sh_s);
+    const double s = sh_s;
+    if (!(fabs(s) > 0.0) || !isfinite(cs[m])) {
       if (tid == 0 && blockIdx.x == 0 && flags) flags[0] |= 16;
-      return;
+    }
+    if (blockIdx.x == 0) {
+      const double is = 1.0 / s;
+      for (int t = tid; t < k * k; t += 256) {
+        const int i = t / k, j = t - i * k;
+        double val;
+        if (i < m && j < m)
+          val = fma(us[i] * vs[j], is, Bs[i * 65 + j]);
+        else if (i < m)
+          val = -us[i] * is;
+        else if (j < m)
+          val = -vs[j] * is;
+        else
+          val = is;
+        Bnext[i * 64 + j] = val;
+      }
+      if (tid < k) cnext[tid] = cs[tid];
     }
   }
+  // residual coefficients: r_k = psi_k - sum_q c_q psi_q
+  if (tid < 64) cf[tid] = (tid < k) ? -cs[tid] : ((tid == k) ? 1.0 : 0.0);
+  __syncthreads();
   double best = -1.0;
   int bi = 0x7fffffff;
-  for (int l = blockIdx.x * 256 + tid; l < N; l += gridDim.x * 256) {
-    double r = Psi[(size_t)k * N + l];
-#pragma unroll 4
-    for (int q = 0; q < k; ++q) r = fma(-Psi[(size_t)q * N + l], cs[q], r);
-    const double v = fabs(r);
+  auto take = [&](double v, int l) {
     if (v > best) {
       best = v;
       bi = l;
     }
+  };
+  // the two prefetched rows, then any further rows of the grid-stride loop
+  if (l0 < N) {
+    double r0 = 0.0, r1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < DG_KR; q += 2) {
+      r0 = fma(p0[q], cf[q], r0);
+      r1 = fma(p0[q + 1], cf[q + 1], r1);
+    }
+    for (int q = DG_KR; q <= k; ++q) r0 = fma(Psi[(size_t)q * N + l0], cf[q], r0);
+    take(fabs(r0 + r1), l0);
+  }
+  if (l1 < N) {
+    double r0 = 0.0, r1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < DG_KR; q += 2) {
+      r0 = fma(p1[q], cf[q], r0);
+      r1 = fma(p1[q + 1], cf[q + 1], r1);
+    }
+    for (int q = DG_KR; q <= k; ++q) r0 = fma(Psi[(size_t)q * N + l1], cf[q], r0);
+    take(fabs(r0 + r1), l1);
+  }
+  for (int l = l1 + stride; l < N; l += stride) {
+    double r0 = 0.0, r1 = 0.0;
+    int q = 0;
+    for (; q + 1 <= k; q += 2) {
+      r0 = fma(Psi[(size_t)q * N + l], cf[q], r0);
+      r1 = fma(Psi[(size_t)(q + 1) * N + l], cf[q + 1], r1);
+    }
+    if (q <= k) r0 = fma(Psi[(size_t)q * N + l], cf[q], r0);
+    take(fabs(r0 + r1), l);
   }
   for (int o = 32; o > 0; o >>= 1) {
     const double ov = __shfl_xor(best, o, 64);
@@ -732,17 +791,32 @@ __global__ void __launch_bounds__(256) deim_greedy_kernel(const double* __restri
 
 // Last index l_{d-1} (winner of the last greedy pass) and the weights
 // w = (P^T Psi)^{-T} Psi^T 1 of eq. grHDD (the factor m_p^{-1} M_q is applied
-// in the gather); colpart holds per-block column sums of Psi (ncp blocks).
-__global__ void __launch_bounds__(256) deim_weights2_kernel(
+// in the gather).  With M_d^{-1} in the bordered form of the greedy passes
+// (B = M_{d-1}^{-1}, u = c_{d-1}, v, s), and sigma = Psi^T 1 = (sigma', sigma_m):
+//   g = (u.sigma' - sigma_m) / s,  w_i = (B^T sigma')_i + v_i g,  w_m = -g.
+// colpart holds per-block column sums of Psi (ncp blocks).
+__global__ void __launch_bounds__(256) deim_weights_kernel(
     const double* __restrict__ Psi, int N, int d, int* __restrict__ idx,
     const double* __restrict__ pval, const int* __restrict__ pidx, int nprev,
+    const double* __restrict__ Bprev, const double* __restrict__ uprev,
     const double* __restrict__ colpart, int ncp, double* __restrict__ wout,
     int* __restrict__ flags) {
-  __shared__ double A[64 * DG_LD];
-  __shared__ double xs[64];
-  __shared__ int rows[64];
-  __shared__ int flag;
+  __shared__ double Bs[64 * 65];
+  __shared__ double us[64], ys[64], bs[64], cs[64], vs[64], sg[64];
+  __shared__ double sh_s;
+  __shared__ int lwin;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int m = d - 1;
+  for (int t = tid; t < m * m; t += 256) {
+    const int i = t / m, j = t - i * m;
+    Bs[i * 65 + j] = Bprev[i * 64 + j];
+  }
+  if (tid < 64) {
+    us[tid] = (tid < m) ? uprev[tid] : 0.0;
+    ys[tid] = 0.0;
+    bs[tid] = 0.0;
+    sg[tid] = 0.0;
+  }
   if (w == 0) {
     int win = dg_winner(pval, pidx, nprev);
     if (win < 0 || win >= N) {
@@ -750,31 +824,30 @@ __global__ void __launch_bounds__(256) deim_weights2_kernel(
       win = 0;
     }
     if (lane == 0) {
-      rows[d - 1] = win;
+      lwin = win;
       idx[d - 1] = win;
     }
-    for (int t = lane; t < d - 1; t += 64) rows[t] = idx[t];
   }
   __syncthreads();
-  // (P^T Psi)^T: row q holds Psi[rows[j], q] over j; right-hand side Psi^T 1
-  for (int t = tid; t < d * d; t += 256) {
-    const int q = t / d, j = t % d;
-    A[q * DG_LD + j] = Psi[(size_t)q * N + rows[j]];
-  }
   // column sums of Psi: one wavefront per column, lane-strided partial sums
   // combined by a fixed butterfly
   for (int q = w; q < d; q += 4) {
     double s = 0.0;
     for (int b = lane; b < ncp; b += 64) s += colpart[(size_t)b * d + q];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) A[q * DG_LD + d] = s;
+    s = dg_wave_sum(s);
+    if (lane == 0) sg[q] = s;
   }
-  __syncthreads();
-  if (dg_solve(A, d, xs, &flag)) {
-    if (tid == 0 && flags) flags[0] |= 16;
-    return;
+  dg_border(Psi, N, d, -1, idx, lwin, Bs, us, ys, bs, cs, vs, &sh_s);
+  if (tid < 64) {
+    const double s = sh_s;
+    double bt = 0.0;
+    for (int i = 0; i < m; ++i) bt = fma(Bs[i * 65 + lane], sg[i], bt);   // (B^T sigma')_lane
+    const double usg = dg_wave_sum((lane < m) ? us[lane] * sg[lane] : 0.0);
+    const double g = (usg - sg[m]) / s;
+    if (lane < m) wout[lane] = fma(vs[lane], g, bt);
+    if (lane == m) wout[m] = -g;
+    if (lane == 0 && (!(fabs(s) > 0.0) || !isfinite(g)) && flags) flags[0] |= 16;
   }
-  for (int t = tid; t < d; t += 256) wout[t] = xs[t];
 }
 
 // Psi (N x d) = sum_s Y_s M[s*kin:(s+1)*kin, :] (the DEIM basis Y V diag(lam)^{-1/2},
@@ -1294,14 +1367,16 @@ void launch_psi_colsum(hipStream_t s, const double* const* in, int nin, int kin,
 
 void launch_deim_greedy(hipStream_t s, const double* Psi, int N, int k, int* idx,
                         const double* pval, const int* pidx, int nprev, int nblk, double* bval,
-                        int* bidx, int* flags) {
+                        int* bidx, const double* Bprev, const double* uprev, double* Bnext,
+                        double* cnext, int* flags) {
   hipLaunchKernelGGL(deim_greedy_kernel, dim3(nblk), dim3(256), 0, s, Psi, N, k, idx, pval, pidx,
-                     nprev, bval, bidx, flags);
+                     nprev, bval, bidx, Bprev, uprev, Bnext, cnext, flags);
 }
 
-void launch_deim_weights2(hipStream_t s, const double* Psi, int N, int d, int* idx,
-                          const double* pval, const int* pidx, int nprev, const double* colpart,
-                          int ncp, double* w, int* flags) {
-  hipLaunchKernelGGL(deim_weights2_kernel, dim3(1), dim3(256), 0, s, Psi, N, d, idx, pval, pidx,
-                     nprev, colpart, ncp, w, flags);
+void launch_deim_weights(hipStream_t s, const double* Psi, int N, int d, int* idx,
+                         const double* pval, const int* pidx, int nprev, const double* Bprev,
+                         const double* uprev, const double* colpart, int ncp, double* w,
+                         int* flags) {
+  hipLaunchKernelGGL(deim_weights_kernel, dim3(1), dim3(256), 0, s, Psi, N, d, idx, pval, pidx,
+                     nprev, Bprev, uprev, colpart, ncp, w, flags);
 }
