@@ -80,6 +80,8 @@ typedef struct {
   int32_t two_n;          /* rank after the call                              */
   int32_t deim_active;    /* 1 if the last step used the DEIM gradient        */
   double rank_indicator;  /* eps_perp of the last evaluation, -1 if none      */
+  int32_t iters_total;    /* fixed-point iterations summed over the call      */
+  int32_t deim_steps;     /* steps of the call that used the DEIM gradient    */
 } symrom_step_info;
 
 typedef struct symrom_rom symrom_rom;

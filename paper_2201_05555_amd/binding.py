@@ -45,6 +45,7 @@ class StepInfo(ctypes.Structure):
     _fields_ = [
         ("iters", ctypes.c_int32), ("stalled", ctypes.c_int32), ("two_n", ctypes.c_int32),
         ("deim_active", ctypes.c_int32), ("rank_indicator", ctypes.c_double),
+        ("iters_total", ctypes.c_int32), ("deim_steps", ctypes.c_int32),
     ]
 
 
@@ -206,7 +207,8 @@ class Rom:
         info = StepInfo()
         _check(lib().rom_step(self.h, nsteps, ctypes.byref(info)))
         return dict(iters=info.iters, stalled=info.stalled, two_n=info.two_n,
-                    deim_active=info.deim_active, rank_indicator=info.rank_indicator)
+                    deim_active=info.deim_active, rank_indicator=info.rank_indicator,
+                    iters_total=info.iters_total, deim_steps=info.deim_steps)
 
     def step_status(self, nsteps=1):
         info = StepInfo()

@@ -425,9 +425,13 @@ struct symrom_rom {
   cplx* Q;  // p x nmax
   double* prev;
   int* active;
-  // status block (device, 48 bytes, one readback): flags [0] error bits,
-  // [1] eigen path, [2] error bits of the DEIM chain; counters [0] active
-  // left, [1] stalled, [2] iterations run; eps_dev the rank indicator
+  // status block (device, 16 ints; [0..11] read back in one copy): flags
+  // [0] error bits, [1] eigen path, [2] error bits of the DEIM chain of the
+  // step, [3] those of the DEIM chain in flight (folded into [2] at the end of
+  // its step, so that a chain enqueued ahead never mixes with the step
+  // before it); counters [0] active
+  // left, [1] stalled, [2] iterations run; eps_dev the rank indicator;
+  // [12] the stop word of a head enqueued ahead (nonzero: the step failed)
   int* status;
   int* counters;
   int* flags;
@@ -461,6 +465,15 @@ struct symrom_rom {
   // ev_fork / ev_join order it after the first-stage field and before its use.
   hipStream_t s2;
   hipEvent_t ev_fork, ev_join;
+  hipEvent_t ev_read;  // end-of-step status copy done
+  // With rank adaptation the first-stage field of the next step is known at
+  // the end of a step: the head of the next DEIM update (snapshot, Gram
+  // block, eigenpairs, coefficients) is then enqueued on the second stream
+  // before the end-of-step readback, gated on the device by the stop word.
+  // head_n: the rank it was built for (a rank change before the next step
+  // means it is built again for the same slot).
+  bool head_pending;
+  int head_n;
   symrom_step_info last;
 };
 
@@ -765,14 +778,17 @@ void linear_grams(symrom_rom& r, const cplx* U, cplx* C12) {
 // held, the DEIM operator of this step: Psi = first d left singular vectors
 // of Y (from the eigenpairs of Y^T Y), greedy indices, weights.  Enqueued on
 // the second stream, with its own partials and its own error word flags[2].
-void deim_update(symrom_rom& r, const cplx* U, const cplx* Z) {
+void deim_update(symrom_rom& r, const cplx* U, const cplx* Z, bool redo = false,
+                 const int* stop = nullptr) {
   hipStream_t s = r.s2;
-  int* dflags = r.flags + 2;
+  int* dflags = r.flags + 3;
   const int N = r.N, n = r.n;
-  const int slot = r.win_count % r.nslots;
+  // redo: the snapshot of the newest slot again (the state changed after a
+  // head built ahead of its step)
+  const int slot = (redo ? r.win_count - 1 : r.win_count) % r.nslots;
   double* Ys = r.Ywin + (size_t)slot * r.psub * N;
-  launch_snapshot(s, U, N, n, Z, r.sub, r.psub, r.Nx, r.b.factor, r.b.phi, Ys);
-  r.win_count++;
+  launch_snapshot(s, U, N, n, Z, r.sub, r.psub, r.Nx, r.b.factor, r.b.phi, Ys, stop);
+  if (!redo) r.win_count++;
   const int P = r.psub * r.nslots;
   std::vector<const double*> slots(r.nslots);
   for (int q = 0; q < r.nslots; ++q) slots[q] = r.Ywin + (size_t)q * r.psub * N;
@@ -781,7 +797,7 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z) {
     // column block of the overwritten slot changes
     Timer t(FAM_DENSE, s);
     launch_gram_block_real(s, Ys, slots.data(), r.nslots, r.psub, N, slot * r.psub,
-                           r.nkb * 64 * 64 * 2, r.dpart, reinterpret_cast<double*>(r.YG));
+                           r.nkb * 64 * 64 * 2, r.dpart, reinterpret_cast<double*>(r.YG), stop);
   }
   r.deim_on = r.win_count >= r.nslots;
   if (!r.deim_on) return;
@@ -792,18 +808,18 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z) {
     Timer te(FAM_EIG, s, 4.0 * fP * fP * fP / 3.0 + 2.0 * fP * fP * fd + 2.0 * fP * fd * fd,
              8.0 * fP * fP + 8.0 * fP * fd);
     launch_dense_topeig(s, reinterpret_cast<const double*>(r.YG), P, d,
-                        reinterpret_cast<double*>(r.YV), r.ylam, dflags);
+                        reinterpret_cast<double*>(r.YV), r.ylam, dflags, stop);
   }
   Timer t(FAM_DENSE, s);
   launch_deim_basis_coeffs(s, reinterpret_cast<const double*>(r.YV), r.ylam, P, d, r.Mdeim,
-                           dflags);
+                           dflags, stop);
 }
 
 // Second half of the DEIM operator (after deim_update, same stream).
 void deim_update_tail(symrom_rom& r) {
   if (!r.deim_on) return;
   hipStream_t s = r.s2;
-  int* dflags = r.flags + 2;
+  int* dflags = r.flags + 3;
   const int N = r.N, d = r.d_cur;
   std::vector<const double*> slots(r.nslots);
   for (int q = 0; q < r.nslots; ++q) slots[q] = r.Ywin + (size_t)q * r.psub * N;
@@ -863,23 +879,27 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   hipStream_t s = r.s;
   const int n = r.n, p = r.p, N = r.N;
   const double dt = r.cfg.dt;
-  HIPCHK(hipMemsetAsync(r.flags, 0, 4 * sizeof(int), s));
+  // (word 3 belongs to a head that may be running on the second stream)
+  HIPCHK(hipMemsetAsync(r.flags, 0, 3 * sizeof(int), s));
   const bool use_deim = r.cfg.projection == SYMROM_DEIM;
   // stage 1 at (U0, Z0): full gradient, k1 = J g, basis velocity -> xi_half
   if (!r.stage1_cached) full_gradient(r, r.U0, r.Z0, nullptr, true);
   r.stage1_cached = false;
-  if (use_deim) {
+  // the DEIM chain is already enqueued when it was built ahead for this rank
+  const bool chain_ready = use_deim && r.head_pending && r.head_n == n;
+  if (use_deim && !chain_ready) {
     // the DEIM chain needs the first-stage field; it runs beside the basis
     // velocity, the Gram matrices of the linear part and the Cayley map
     HIPCHK(hipEventRecord(r.ev_fork, s));
     HIPCHK(hipStreamWaitEvent(r.s2, r.ev_fork, 0));
-    deim_update(r, r.U0, r.Z0);
+    deim_update(r, r.U0, r.Z0, r.head_pending);
   }
+  r.head_pending = false;
   const bool deim = use_deim && r.deim_on;
   // (the eigensolver keeps one CU busy for a while: enqueue part of the main
   // work before the rest of the chain, so that both streams have work)
   basis_velocity(r, r.U0, r.Z0, 0.5 * dt, r.Xi, deim ? nullptr : r.k);
-  if (use_deim) {
+  if (use_deim && !chain_ready) {
     deim_update_tail(r);
     HIPCHK(hipEventRecord(r.ev_join, r.s2));
   }
@@ -978,17 +998,39 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
     full_gradient(r, r.U0, r.Z0, nullptr, true, true);
     launch_dense_indicator(s, r.colsq, r.gproj, n, p, r.eps_dev);
   }
-  LAUNCHCHK();
-  {
-    symrom_status st = read_status(r);
-    if (st != SYMROM_OK) return st;
+  if (use_deim) launch_fold_status(s, r.status);
+  const bool ahead = use_deim && decide_rank;
+  if (ahead) HIPCHK(hipEventRecord(r.ev_fork, s));
+  // the status copy is started before the chain ahead is enqueued, and
+  // waited for after
+  HIPCHK(hipMemcpyAsync(r.hstat, r.status, 12 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(r.ev_read, s));
+  if (ahead) {
+    // the next step's DEIM chain, beside the readback; its head does
+    // nothing if this step failed (stop word)
+    HIPCHK(hipStreamWaitEvent(r.s2, r.ev_fork, 0));
+    deim_update(r, r.U0, r.Z0, false, r.status + 12);
+    deim_update_tail(r);
+    HIPCHK(hipEventRecord(r.ev_join, r.s2));
+    r.head_pending = true;
+    r.head_n = n;
   }
+  LAUNCHCHK();
+  HIPCHK(hipEventSynchronize(r.ev_read));
   const int fl0 = r.hstat[0] | r.hstat[2];
   double eps = 0.0;
   std::memcpy(&eps, r.hstat + 8, sizeof(double));
   if (fl0) {
     std::swap(r.U0, r.Uh);
     std::swap(r.Z0, r.Z1);
+    if (ahead) {
+      // the head was gated off (the rest of the chain only rewrote the
+      // operator, which the next step builds afresh)
+      HIPCHK(hipStreamSynchronize(r.s2));
+      r.head_pending = false;
+      r.win_count--;
+      r.deim_on = r.win_count >= r.nslots;
+    }
     return fail(SYMROM_ESINGULAR, "singular small matrix in the basis update");
   }
   r.step++;
@@ -999,7 +1041,9 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
     r.stage1_cached = true;
     return SYMROM_OK;
   }
-  HIPCHK(hipMemsetAsync(r.flags, 0, 4 * sizeof(int), s));
+  // the growth rewrites Z0 in its new layout: the head must be done with it
+  if (r.head_pending) HIPCHK(hipStreamSynchronize(r.s2));
+  HIPCHK(hipMemsetAsync(r.flags, 0, 2 * sizeof(int), s));
   return rom_grow_apply(r, 1);
 }
 }  // namespace
@@ -1090,7 +1134,7 @@ extern "C" symrom_status rom_init(const symrom_config* cfg, const double* L, con
   }
   hipStream_t s = r->s;
   const int N = r->N, p = r->p, n = r->n;
-  if (hipMemsetAsync(r->flags, 0, 4 * sizeof(int), s) != hipSuccess) {
+  if (hipMemsetAsync(r->status, 0, 16 * sizeof(int), s) != hipSuccess) {
     delete r;
     return fail(SYMROM_EDEVICE, "rom_init: memset");
   }
@@ -1160,6 +1204,11 @@ extern "C" symrom_status rom_init(const symrom_config* cfg, const double* L, con
     rom_destroy(r);
     return fail(SYMROM_EDEVICE, "rom_init: pinned status buffer");
   }
+  if (hipEventCreateWithFlags(&r->ev_read, hipEventDisableTiming) != hipSuccess) {
+    r->ev_read = nullptr;
+    rom_destroy(r);
+    return fail(SYMROM_EDEVICE, "rom_init: event creation");
+  }
   if (cfg->projection == SYMROM_DEIM &&
       (hipStreamCreateWithFlags(&r->s2, hipStreamNonBlocking) != hipSuccess ||
        hipEventCreateWithFlags(&r->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -1176,13 +1225,26 @@ extern "C" symrom_status rom_init(const symrom_config* cfg, const double* L, con
 
 namespace {
 symrom_status rom_grow(symrom_rom& r, int k, bool decide);
+
+// Entry points other than rom_step first wait for a DEIM head enqueued
+// ahead (it reads the state and the field buffers they may rewrite).
+void side_wait(symrom_rom* r) {
+  if (r && r->s2 && r->head_pending) (void)hipStreamSynchronize(r->s2);
+}
 }
 
 extern "C" symrom_status rom_step(symrom_rom* r, int32_t nsteps, symrom_step_info* info) {
   if (!r || nsteps < 0) return fail(SYMROM_EINVAL, "rom_step: bad arguments");
   if (!r->ready) return fail(SYMROM_ESTATE, "rom_step: handle not initialised");
+  int64_t iters_total = 0, deim_steps = 0;
+  r->last.iters_total = 0;
+  r->last.deim_steps = 0;
   for (int it = 0; it < nsteps; ++it) {
     symrom_status st = rom_step_one(*r, r->cfg.rank_auto != 0);
+    iters_total += r->last.iters;
+    deim_steps += r->last.deim_active;
+    r->last.iters_total = (int32_t)iters_total;
+    r->last.deim_steps = (int32_t)deim_steps;
     if (st != SYMROM_OK) {
       if (info) *info = r->last;
       return st;
@@ -1199,7 +1261,7 @@ namespace {
 symrom_status rom_grow(symrom_rom& r, int k, bool decide) {
   hipStream_t s = r.s;
   const int n = r.n, p = r.p;
-  HIPCHK(hipMemsetAsync(r.flags, 0, 4 * sizeof(int), s));
+  HIPCHK(hipMemsetAsync(r.flags, 0, 2 * sizeof(int), s));
   full_gradient(r, r.U0, r.Z0, nullptr, true, decide);
   if (decide) {
     // eps needs only |G|^2 and |g|^2
@@ -1264,6 +1326,7 @@ symrom_status rom_shrink(symrom_rom& r, int n_new) {
 }  // namespace
 
 extern "C" symrom_status rom_adapt_rank(symrom_rom* r, int32_t target_two_n, int32_t* new_two_n) {
+  side_wait(r);
   if (!r) return fail(SYMROM_EINVAL, "rom_adapt_rank: null handle");
   r->stage1_cached = false;
   if (!r->ready) return fail(SYMROM_ESTATE, "rom_adapt_rank: handle not initialised");
@@ -1283,6 +1346,7 @@ extern "C" symrom_status rom_adapt_rank(symrom_rom* r, int32_t target_two_n, int
 
 extern "C" symrom_status rom_get_state(symrom_rom* r, double* UX, double* Z, int32_t* two_n,
                                        int64_t* step) {
+  side_wait(r);
   if (!r) return fail(SYMROM_EINVAL, "rom_get_state: null handle");
   hipStream_t s = r->s;
   if (UX) launch_ux_from_u(s, r->U0, r->N, r->n, UX);
@@ -1296,6 +1360,7 @@ extern "C" symrom_status rom_get_state(symrom_rom* r, double* UX, double* Z, int
 
 extern "C" symrom_status rom_set_state(symrom_rom* r, int32_t two_n, const double* UX,
                                        const double* Z, int64_t step) {
+  side_wait(r);
   if (!r || !UX || !Z) return fail(SYMROM_EINVAL, "rom_set_state: null argument");
   if (two_n <= 0 || (two_n & 1) || two_n > r->cfg.two_n_max)
     return fail(SYMROM_EINVAL, "rom_set_state: bad rank");
@@ -1310,10 +1375,12 @@ extern "C" symrom_status rom_set_state(symrom_rom* r, int32_t two_n, const doubl
   r->ready = true;
   r->win_count = 0;
   r->deim_on = false;
+  r->head_pending = false;
   return SYMROM_OK;
 }
 
 extern "C" symrom_status rom_reconstruct(symrom_rom* r, double* X, double* V) {
+  side_wait(r);
   if (!r) return fail(SYMROM_EINVAL, "rom_reconstruct: null handle");
   launch_reconstruct(r->s, r->U0, r->N, r->n, r->Z0, r->p, X, V);
   LAUNCHCHK();
@@ -1323,6 +1390,7 @@ extern "C" symrom_status rom_reconstruct(symrom_rom* r, double* X, double* V) {
 
 extern "C" symrom_status rom_gradient(symrom_rom* r, const double* Z, double* g, double* rho,
                                       double* Phi, double* e) {
+  side_wait(r);
   if (!r || !Z || !g) return fail(SYMROM_EINVAL, "rom_gradient: null argument");
   hipStream_t s = r->s;
   const int n = r->n, p = r->p;
@@ -1340,6 +1408,7 @@ extern "C" symrom_status rom_gradient(symrom_rom* r, const double* Z, double* g,
 }
 
 extern "C" symrom_status rom_diagnostics(symrom_rom* r, double* E, double* H) {
+  side_wait(r);
   if (!r) return fail(SYMROM_EINVAL, "rom_diagnostics: null handle");
   r->stage1_cached = false;
   hipStream_t s = r->s;
@@ -1362,8 +1431,10 @@ extern "C" symrom_status rom_diagnostics(symrom_rom* r, double* E, double* H) {
 
 extern "C" void rom_destroy(symrom_rom* r) {
   if (!r) return;
+  side_wait(r);
   if (r->ev_fork) (void)hipEventDestroy(r->ev_fork);
   if (r->ev_join) (void)hipEventDestroy(r->ev_join);
+  if (r->ev_read) (void)hipEventDestroy(r->ev_read);
   if (r->s2) (void)hipStreamDestroy(r->s2);
   if (r->hstat) (void)hipHostFree(r->hstat);
   delete r;

@@ -673,6 +673,21 @@ __global__ void fp_init_kernel(double* prev, int* active, int* counters, int p) 
   if (t < 4) counters[t] = (t == 0) ? p : 0;
 }
 
+// End of a step with the DEIM chain: the error word of the chain in flight
+// (3) is folded into the step's word (2) and cleared for the next chain; the
+// stop word (12) of a chain enqueued next is set when this step failed.
+__global__ void fold_status_kernel(int* status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int tail = status[2] | status[3];
+    status[2] = tail;
+    status[3] = 0;
+    status[12] = status[0] | tail;
+  }
+}
+void launch_fold_status(hipStream_t s, int* status) {
+  hipLaunchKernelGGL(fold_status_kernel, dim3(1), dim3(64), 0, s, status);
+}
+
 // Z1 = Z0 + dt k
 __global__ void dense_finish_z_kernel(const cplx* __restrict__ Z0, const cplx* __restrict__ k,
                                       int n, int p, double dt, cplx* __restrict__ Z1) {
@@ -1011,7 +1026,8 @@ void launch_dense_shrink(hipStream_t s, const cplx* Z, int n, int p, cplx* V, cp
 // is real).
 __global__ void deim_basis_coeffs_kernel(const double* __restrict__ V, const double* __restrict__ lam,
                                          int P, int d, double* __restrict__ M,
-                                         int* __restrict__ flags) {
+                                         int* __restrict__ flags, const int* __restrict__ stop) {
+  if (stop && *stop) return;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= P * d) return;
   int c = t / P;
@@ -1042,9 +1058,9 @@ __global__ void deim_k_kernel(const cplx* __restrict__ gF, const cplx* __restric
 }
 
 void launch_deim_basis_coeffs(hipStream_t s, const double* V, const double* lam, int P, int d,
-                              double* M, int* flags) {
+                              double* M, int* flags, const int* stop) {
   hipLaunchKernelGGL(deim_basis_coeffs_kernel, dim3(nblk((size_t)P * d)), dim3(256), 0, s, V, lam,
-                     P, d, M, flags);
+                     P, d, M, flags, stop);
 }
 void launch_deim_k(hipStream_t s, const cplx* gF, const cplx* C12, const cplx* Z, int n, int p,
                    cplx* k) {
@@ -1501,7 +1517,9 @@ __device__ void te_back_gram(const double* __restrict__ H, const double* __restr
 __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restrict__ G, int n, int d,
                                                            double* __restrict__ V,
                                                            double* __restrict__ lam,
-                                                           int* __restrict__ flags) {
+                                                           int* __restrict__ flags,
+                                                           const int* __restrict__ stop) {
+  if (stop && *stop) return;
   constexpr int M = TE_M;
   constexpr int CW = 16;                // columns per wavefront
   __shared__ double H[M * M];          // H[k * M + i]: reflector k (zero for i <= k)
@@ -1680,15 +1698,16 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
   const double amax = fmax(fabs(lo), fabs(hi));
   const double sc = (amax > 0.0) ? __builtin_amdgcn_ldexp(1.0, __builtin_amdgcn_frexp_exp(amax)) : 1.0;
   const double isc = 1.0 / sc;
-  // (d_i, e_{i-1}^2) of T / sc, one LDS read per term; four padding terms
+  // (d_i, e_{i-1}^2) of T / sc, one LDS read per term; eight padding terms
   // with d = 4 (above every shift) leave the count unchanged
   double2* de = reinterpret_cast<double2*>(W);
-  if (tid < n + 4) {
+  if (tid < n + 8) {
     const double ep = (tid > 0 && tid < n) ? ee[tid - 1] * isc : 0.0;
     de[tid] = (tid < n) ? make_double2(dd[tid] * isc, ep * ep) : make_double2(4.0, 0.0);
   }
-  // a pivot (ratio of consecutive minors) of modulus below pivmin is replaced
-  // by -pivmin: a perturbation of T / sc far below rounding
+  // every pivot (ratio of consecutive minors) is moved away from zero by
+  // pivmin in its own direction: no effect above 1e-44 of the pivot, and no
+  // zero minor (a perturbation of T / sc far below rounding)
   const double pivmin = 1e-60;
   // ms lanes per eigenvalue (a power of two, so a group never straddles a
   // wavefront and its bracket update is a butterfly over ms lanes)
@@ -1706,30 +1725,37 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
     // count of negative ratios P_{i+1} / P_i of the leading minors of
     // T / sc - x I (the negative pivots of its LDL^T factorisation)
     double pa = 1.0, pb = 0.0;   // P_i, P_{i-1}
-    int cnt = 0;
-    double2 c0 = de[0], c1 = de[1];
-    for (int i = 0; i < n; i += 2) {
-      const double2 n0 = de[i + 2], n1 = de[i + 3];
-      double pn = fma(c0.x - x, pa, -c0.y * pb);
-      pn = (fabs(pn) < pivmin * fabs(pa)) ? -pivmin * pa : pn;
-      cnt += (pn < 0.0) != (pa < 0.0);
-      pb = pa;
-      pa = pn;
-      pn = fma(c1.x - x, pa, -c1.y * pb);
-      pn = (fabs(pn) < pivmin * fabs(pa)) ? -pivmin * pa : pn;
-      cnt += (pn < 0.0) != (pa < 0.0);
-      pb = pa;
-      pa = pn;
+    unsigned cnt = 0;
+    double2 c0 = de[0], c1 = de[1], c2 = de[2], c3 = de[3];
+    for (int i = 0; i < n; i += 4) {
+      const double2 n0 = de[i + 4], n1 = de[i + 5], n2 = de[i + 6], n3 = de[i + 7];
+#define TE_STURM(C)                                                            \
+  {                                                                            \
+    double pn = fma((C).x - x, pa, -(C).y * pb);                               \
+    pn += copysign(pivmin * fabs(pa), pn);                                     \
+    cnt += (unsigned)(__double2hiint(pn) ^ __double2hiint(pa)) >> 31;          \
+    pb = pa;                                                                   \
+    pa = pn;                                                                   \
+  }
+      TE_STURM(c0)
+      TE_STURM(c1)
+      TE_STURM(c2)
+      TE_STURM(c3)
+#undef TE_STURM
+      // rescale by a power of two (exact): at most a factor 6^4 of growth and
+      // pivmin^4 of decay between two rescalings
       const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(pa), fabs(pb)));
       pa = __builtin_amdgcn_ldexp(pa, -ex);
       pb = __builtin_amdgcn_ldexp(pb, -ex);
       c0 = n0;
       c1 = n1;
+      c2 = n2;
+      c3 = n3;
     }
     // new bracket: the largest point with count <= kk and the smallest with
     // count > kk, by a butterfly over the group (max / min: order-free)
-    double na = (cnt <= kk) ? x : a0;
-    double nb = (cnt > kk) ? x : b0;
+    double na = ((int)cnt <= kk) ? x : a0;
+    double nb = ((int)cnt > kk) ? x : b0;
     for (int o = 1; o < ms; o <<= 1) {
       na = fmax(na, __shfl_xor(na, o, 64));
       nb = fmin(nb, __shfl_xor(nb, o, 64));
@@ -1770,11 +1796,14 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
     for (int pass = 0; pass < 2; ++pass) {
       // forward elimination; bit i of swm: rows i and i + 1 exchanged
       unsigned long long swm = 0ull;
-      const double2 d0 = dsc[0];
-      double c0 = d0.x - lv, c1 = (n > 1) ? d0.y : 0.0;
+      double2 di = dsc[0], dn = dsc[1];
+      double c0 = di.x - lv, c1 = (n > 1) ? di.y : 0.0;
       double carry = Xw[r];
+      double xn = Xw[min(1, n - 1) * M + r];
       for (int i = 0; i < n - 1; ++i) {
-        const double2 di = dsc[i], dn = dsc[i + 1];
+        // operands of the next step, loaded ahead (indices kept in range)
+        const double2 dn2 = dsc[i + 2];
+        const double xnn = Xw[min(i + 2, n - 1) * M + r];
         const double sb = di.y, dg = dn.x - lv;
         const double sp = (i + 2 < n) ? dn.y : 0.0;
         const bool swap = fabs(sb) > fabs(c0);
@@ -1784,28 +1813,39 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
         U0[i * M + r] = rp;
         U1[i * M + r] = swap ? dg : c1;
         swm |= (unsigned long long)swap << i;
-        const double xi = carry, xn = Xw[(i + 1) * M + r];
+        const double xi = carry;
         Xw[i * M + r] = swap ? xn : xi;
         carry = swap ? (xi - f * xn) : (xn - f * xi);
         const double n0 = swap ? (c1 - f * dg) : (dg - f * c1);
         const double n1 = swap ? (-f * sp) : sp;
         c0 = n0;
         c1 = n1;
+        di = dn;
+        dn = dn2;
+        xn = xnn;
       }
       Xw[(n - 1) * M + r] = carry;
       const double rpl = te_rcp((c0 == 0.0) ? ptiny : c0);
-      // back substitution
+      // back substitution (operands of the next row loaded ahead)
       double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+      double u0l = U0[(n - 1) * M + r], u1l = U1[(n - 1) * M + r], el = dsc[n].y;
+      double xl = Xw[(n - 1) * M + r];
       for (int i = n - 1; i >= 0; --i) {
-        const double u0l = U0[i * M + r], u1l = U1[i * M + r], el = dsc[i + 1].y;
+        const int ip = max(i - 1, 0);
+        const double u0n = U0[ip * M + r], u1n = U1[ip * M + r], en = dsc[ip + 1].y;
+        const double xnx = Xw[ip * M + r];
         const double u0 = (i == n - 1) ? rpl : u0l;
         const double u1 = (i + 1 < n) ? u1l : 0.0;
         const double u2 = (i + 2 < n && ((swm >> i) & 1ull)) ? el : 0.0;
-        const double xi = (Xw[i * M + r] - u1 * x1 - u2 * x2) * u0;
+        const double xi = (xl - u1 * x1 - u2 * x2) * u0;
         Xw[i * M + r] = xi;
         nrm = fma(xi, xi, nrm);
         x2 = x1;
         x1 = xi;
+        u0l = u0n;
+        u1l = u1n;
+        el = en;
+        xl = xnx;
       }
       const double inv = 1.0 / sqrt(nrm);
       if (pass == 0) {
@@ -1883,6 +1923,6 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
 }
 
 void launch_dense_topeig(hipStream_t s, const double* G, int n, int d, double* V, double* lam,
-                         int* flags) {
-  hipLaunchKernelGGL(dense_topeig_kernel, dim3(1), dim3(256), 0, s, G, n, d, V, lam, flags);
+                         int* flags, const int* stop) {
+  hipLaunchKernelGGL(dense_topeig_kernel, dim3(1), dim3(256), 0, s, G, n, d, V, lam, flags, stop);
 }

@@ -102,7 +102,8 @@ void launch_deim_gather(hipStream_t s, const cplx* U, int N, int n, const cplx* 
                         const double* w, int d, const int* active, cplx* gF,
                         const int* gate = nullptr);
 void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, const int* sub,
-                     int psub, int Nx, const double* factor, const double* phi, double* Y);
+                     int psub, int Nx, const double* factor, const double* phi, double* Y,
+                     const int* stop = nullptr);
 // DEIM basis Psi = sum_s Y_s M_s with per-block column sums (psi_blocks(N)
 // blocks, colpart[block][c]); fused greedy step k (per-block winners into
 // bval, bidx from the previous pass pval, pidx); last index and weights.
@@ -157,14 +158,16 @@ void launch_dense_shrink(hipStream_t s, const cplx* Z, int n, int p, cplx* V, cp
                          double* sig2);
 
 void launch_deim_basis_coeffs(hipStream_t s, const double* V, const double* lam, int P, int d,
-                              double* M, int* flags);
+                              double* M, int* flags, const int* stop = nullptr);
 void launch_dense_symeig(hipStream_t s, const cplx* G, int n, double* V, double* lam, int* flags);
 void launch_deim_k(hipStream_t s, const cplx* gF, const cplx* C12, const cplx* Z, int n, int p,
                    cplx* k);
 void launch_dense_indicator(hipStream_t s, const double* colsq, const cplx* g, int n, int p,
                             double* eps);
 void launch_dense_topeig(hipStream_t s, const double* G, int n, int d, double* V, double* lam,
-                         int* flags);
+                         int* flags, const int* stop = nullptr);
+// error-word bookkeeping at the end of a step with the DEIM chain
+void launch_fold_status(hipStream_t s, int* status);
 void launch_gram_block_real(hipStream_t s, const double* Ynew, const double* const* slots,
                             int nslots, int psub, int N, int r0, int nkb_cap, double* part,
-                            double* S);
+                            double* S, const int* stop = nullptr);

@@ -925,7 +925,9 @@ __global__ void __launch_bounds__(256) snapshot_kernel(const cplx* __restrict__ 
                                                        const int* __restrict__ sub, int psub,
                                                        int Nx, const double* __restrict__ factor,
                                                        const double* __restrict__ phi,
-                                                       double* __restrict__ Y) {
+                                                       double* __restrict__ Y,
+                                                       const int* __restrict__ stop) {
+  if (stop && *stop) return;
   extern __shared__ double smem[];
   cplx* Zs = reinterpret_cast<cplx*>(smem);                 // [psub][NC]
   double* fs = reinterpret_cast<double*>(Zs + psub * NC);    // [psub]
@@ -973,7 +975,9 @@ __global__ void __launch_bounds__(256) snapshot_kernel(const cplx* __restrict__ 
 // reduce_gram_block_kernel.
 __global__ void __launch_bounds__(256) gemm_real_tn_kernel(RealList A, int ka, int a, RealList B,
                                                            int kbcols, int b, int N, int rk, int TR,
-                                                           double* __restrict__ part) {
+                                                           double* __restrict__ part,
+                                                           const int* __restrict__ stop) {
+  if (stop && *stop) return;
   extern __shared__ double smr[];   // staging [a + b][TR], later tile sums [16][GEMM_RED_LD]
   __shared__ const double* colp[128];
   const int tid = threadIdx.x;
@@ -1261,7 +1265,9 @@ void launch_deim_gather(hipStream_t s, const cplx* U, int N, int n, const cplx* 
 // symmetric P x P matrix S at rows r0.. (and the transpose at columns r0..).
 __global__ void __launch_bounds__(256) reduce_gram_block_kernel(const double* __restrict__ part,
                                                                 int nkb, int a, int b, int P,
-                                                                int r0, double* __restrict__ S) {
+                                                                int r0, double* __restrict__ S,
+                                                                const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const int lane = threadIdx.x & 63;
   const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int nout = a * b;
@@ -1278,7 +1284,7 @@ __global__ void __launch_bounds__(256) reduce_gram_block_kernel(const double* __
 
 void launch_gram_block_real(hipStream_t s, const double* Ynew, const double* const* slots,
                             int nslots, int psub, int N, int r0, int nkb_cap, double* part,
-                            double* S) {
+                            double* S, const int* stop) {
   RealList A{}, B{};
   A.ptr[0] = Ynew;
   A.count = 1;
@@ -1298,13 +1304,14 @@ void launch_gram_block_real(hipStream_t s, const double* Ynew, const double* con
   if (sh < (size_t)16 * GEMM_RED_LD * sizeof(double)) sh = (size_t)16 * GEMM_RED_LD * sizeof(double);
   ALLOW_BIG_LDS(gemm_real_tn_kernel);
   hipLaunchKernelGGL(gemm_real_tn_kernel, dim3(nkb), dim3(256), sh, s, A, psub, a, B, psub, b, N, rk,
-                     TR, part);
+                     TR, part, stop);
   hipLaunchKernelGGL(reduce_gram_block_kernel, dim3((a * b + 3) / 4), dim3(256), 0, s, part, nkb, a,
-                     b, b, r0, S);
+                     b, b, r0, S, stop);
 }
 
 void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, const int* sub,
-                     int psub, int Nx, const double* factor, const double* phi, double* Y) {
+                     int psub, int Nx, const double* factor, const double* phi, double* Y,
+                     const int* stop) {
   const int nc = (n <= 16) ? fused_nc(n) : 32;
   const size_t base = (size_t)psub * nc * sizeof(cplx) + (size_t)psub * sizeof(double);
   const size_t phb = (size_t)psub * Nx * sizeof(double);
@@ -1314,7 +1321,7 @@ void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, 
 #define SN(NCV, PV)                                                                          \
   ALLOW_BIG_LDS((snapshot_kernel<NCV, PV>));                                               \
   hipLaunchKernelGGL((snapshot_kernel<NCV, PV>), grid, dim3(256), sh, s, U, N, n, Z, sub, psub, \
-                     Nx, factor, phi, Y)
+                     Nx, factor, phi, Y, stop)
   if (ph_lds) {
     switch (nc) {
       case 4: SN(4, true); break;
