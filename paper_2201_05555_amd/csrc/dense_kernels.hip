@@ -1426,31 +1426,59 @@ __device__ __forceinline__ void te_wave_sum2(double& u, double& v) {
   v = te_lane(v, 63);
 }
 
+// Butterfly partners inside aligned groups of up to 16 lanes by DPP: lane
+// i ^ 1 and i ^ 2 (quad permutations), then the mirror images inside halves
+// of 8 and rows of 16, which pair every lane with one in the other half.
+// Combining with a commutative operation leaves the same bits in every lane
+// of the group.
+template <int LEVEL>
+__device__ __forceinline__ double te_bfly(double v) {
+  if (LEVEL == 0) return te_dpp<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
+  if (LEVEL == 1) return te_dpp<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
+  if (LEVEL == 2) return te_dpp<0x141, 0xf>(v);   // row_half_mirror
+  return te_dpp<0x140, 0xf>(v);                   // row_mirror
+}
+
 // sum over aligned groups of L lanes (L a power of two, 4 <= L <= 64),
-// returned in every lane of the group: an inclusive scan inside the group
-// leaves the total in its last lane, which is then read by the group
+// returned in every lane of the group (the same bits in all of them)
 template <int L>
 __device__ __forceinline__ double te_grp_sum(double v) {
-  const int sub = threadIdx.x & (L - 1);
-  double t;
-  t = te_dpp<0x111, 0xf>(v);
-  v += (sub >= 1) ? t : 0.0;
-  t = te_dpp<0x112, 0xf>(v);
-  v += (sub >= 2) ? t : 0.0;
+  v += te_bfly<0>(v);
+  v += te_bfly<1>(v);
+  if (L >= 8) v += te_bfly<2>(v);
+  if (L >= 16) v += te_bfly<3>(v);
+  if (L >= 32) v += __shfl_xor(v, 16, 64);
+  if (L >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// max and min over aligned groups of L lanes (L a power of two <= 64)
+template <int L>
+__device__ __forceinline__ void te_grp_maxmin(double& mx, double& mn) {
+  if (L >= 2) {
+    mx = fmax(mx, te_bfly<0>(mx));
+    mn = fmin(mn, te_bfly<0>(mn));
+  }
+  if (L >= 4) {
+    mx = fmax(mx, te_bfly<1>(mx));
+    mn = fmin(mn, te_bfly<1>(mn));
+  }
   if (L >= 8) {
-    t = te_dpp<0x114, 0xf>(v);
-    v += (sub >= 4) ? t : 0.0;
+    mx = fmax(mx, te_bfly<2>(mx));
+    mn = fmin(mn, te_bfly<2>(mn));
   }
   if (L >= 16) {
-    t = te_dpp<0x118, 0xf>(v);
-    v += (sub >= 8) ? t : 0.0;
+    mx = fmax(mx, te_bfly<3>(mx));
+    mn = fmin(mn, te_bfly<3>(mn));
   }
-  if (L >= 32) v += te_dpp<0x142, 0xa>(v);
+  if (L >= 32) {
+    mx = fmax(mx, __shfl_xor(mx, 16, 64));
+    mn = fmin(mn, __shfl_xor(mn, 16, 64));
+  }
   if (L >= 64) {
-    v += te_dpp<0x143, 0xc>(v);
-    return te_lane(v, 63);
+    mx = fmax(mx, __shfl_xor(mx, 32, 64));
+    mn = fmin(mn, __shfl_xor(mn, 32, 64));
   }
-  return __shfl(v, (int)(threadIdx.x & 63) | (L - 1), 64);
 }
 
 // Back-transform x <- H_0 H_1 ... H_{n-3} x of the d vectors in Xv
@@ -1459,34 +1487,52 @@ __device__ __forceinline__ double te_grp_sum(double v) {
 // vector c, lane s of the group its entries s, s + L, ...
 template <int L>
 __device__ void te_back_gram(const double* __restrict__ H, const double* __restrict__ tau,
-                             double* __restrict__ Xv, double* __restrict__ Rc, int n, int d) {
+                             double* __restrict__ Xv, double* __restrict__ Rc,
+                             const double* __restrict__ znrm, int n, int d) {
   constexpr int R = TE_M / L;
   const int c = threadIdx.x / L, sub = threadIdx.x & (L - 1);
   const bool act = c < d;
+  const int cc = act ? c : 0;
+  // unit vectors (the scale of each is irrelevant to the orthonormalisation
+  // that follows, but keeps the Gram entries in range)
+  const double inv = 1.0 / sqrt(znrm[cc] + znrm[TE_M + cc]);
   double x[R];
 #pragma unroll
   for (int t = 0; t < R; ++t) {
     const int i = sub + L * t;
-    const double v = Xv[(act ? c : 0) * TE_LX + i];
-    x[t] = (act && i < n) ? v : 0.0;
+    const double v = Xv[cc * TE_LX + i];
+    x[t] = (act && i < n) ? v * inv : 0.0;
+  }
+  // reflector k and its scalar, loaded one step ahead
+  double h[R];
+  double tk = 0.0;
+  if (n >= 3) {
+    tk = tau[n - 3];
+#pragma unroll
+    for (int t = 0; t < R; ++t) h[t] = H[(n - 3) * TE_M + sub + L * t];
   }
   for (int k = n - 3; k >= 0; --k) {
-    const double tk = tau[k];
-    if (tk == 0.0) continue;
-    const double* hk = H + k * TE_M + sub;
-    double h[R];
-    double s0 = 0.0, s1 = 0.0;
+    const int kn = max(k - 1, 0);
+    const double tkn = tau[kn];
+    double hn[R];
 #pragma unroll
-    for (int t = 0; t < R; ++t) {
-      h[t] = hk[L * t];
-      if (t & 1)
-        s1 = fma(h[t], x[t], s1);
-      else
-        s0 = fma(h[t], x[t], s0);
+    for (int t = 0; t < R; ++t) hn[t] = H[kn * TE_M + sub + L * t];
+    if (tk != 0.0) {
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        if (t & 1)
+          s1 = fma(h[t], x[t], s1);
+        else
+          s0 = fma(h[t], x[t], s0);
+      }
+      const double sc = tk * te_grp_sum<L>(s0 + s1);
+#pragma unroll
+      for (int t = 0; t < R; ++t) x[t] = fma(-sc, h[t], x[t]);
     }
-    const double s = tk * te_grp_sum<L>(s0 + s1);
+    tk = tkn;
 #pragma unroll
-    for (int t = 0; t < R; ++t) x[t] = fma(-s, h[t], x[t]);
+    for (int t = 0; t < R; ++t) h[t] = hn[t];
   }
   __syncthreads();   // every group has read its input
 #pragma unroll
@@ -1538,6 +1584,8 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
   unsigned long long tsv[6];
   tsv[0] = wall_clock64();
 #define TS(k) tsv[k] = wall_clock64()
+  unsigned long long tiv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#define TIV(k) tiv[k] = wall_clock64()
   long long seg[5] = {0, 0, 0, 0, 0};
   long long tprev = clock64();
 #define SEG(i)                  \
@@ -1548,6 +1596,7 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
   }
 #else
 #define TS(k)
+#define TIV(k)
 #define SEG(i)
 #endif
   // ---- tridiagonalisation ----
@@ -1718,10 +1767,11 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
   const int kk = n - 1 - (gact ? grp : 0);       // eigenvalue kk in increasing order
   __syncthreads();
   double a0 = lo * isc, b0 = hi * isc;
+  const double frac = (double)(sub + 1) / (double)(ms + 1);
   for (int it = 0; it < 200; ++it) {
     const bool more = gact && (b0 - a0 > 2.2e-16);
     if (!__syncthreads_or(more)) break;
-    const double x = a0 + (b0 - a0) * (double)(sub + 1) / (double)(ms + 1);
+    const double x = fma(b0 - a0, frac, a0);
     // count of negative ratios P_{i+1} / P_i of the leading minors of
     // T / sc - x I (the negative pivots of its LDL^T factorisation)
     double pa = 1.0, pb = 0.0;   // P_i, P_{i-1}
@@ -1756,9 +1806,14 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
     // count > kk, by a butterfly over the group (max / min: order-free)
     double na = ((int)cnt <= kk) ? x : a0;
     double nb = ((int)cnt > kk) ? x : b0;
-    for (int o = 1; o < ms; o <<= 1) {
-      na = fmax(na, __shfl_xor(na, o, 64));
-      nb = fmin(nb, __shfl_xor(nb, o, 64));
+    switch (ms) {
+      case 64: te_grp_maxmin<64>(na, nb); break;
+      case 32: te_grp_maxmin<32>(na, nb); break;
+      case 16: te_grp_maxmin<16>(na, nb); break;
+      case 8: te_grp_maxmin<8>(na, nb); break;
+      case 4: te_grp_maxmin<4>(na, nb); break;
+      case 2: te_grp_maxmin<2>(na, nb); break;
+      default: break;
     }
     if (more) {
       if (!(na > a0) && !(nb < b0)) {
@@ -1772,89 +1827,93 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
   if (gact && sub == 0) lamg[grp] = 0.5 * (a0 + b0) * sc;
   __syncthreads();
   TS(2);
-  // ---- inverse iteration: lane c < d of wavefront 0 owns eigenvector c ----
+  // ---- eigenvectors of T by twisted factorizations of T/sc - lambda I ----
+  // For lane c < d (eigenvalue lambda_c): wavefront 0 forms the top-down
+  // LDL^T pivots delta_i, wavefront 1 at the same time the bottom-up pivots
+  // rho_i and multipliers u_i = e_i / rho_{i+1}; the twist index k minimises
+  // |gamma_i|, gamma_i = delta_i + rho_i - (d_i - lambda); then z_k = 1,
+  // z_i = -(e_i / delta_i) z_{i+1} above k (wavefront 0) and
+  // z_{i+1} = -u_i z_i below k (wavefront 1).  Pivots are kept at least
+  // ptiny in modulus (a perturbation of T / sc of that size).
   const double ptiny = 2.2e-16;
-  double* U0 = W;                // reciprocal pivots
-  double* U1 = W + M * M;        // first superdiagonal of U
-  double* Xw = W + 2 * M * M;    // right-hand side, then solution: Xw[i * M + c]
-  double* Xv = W;                // vectors, Xv[c * TE_LX + i] (after the solves)
-  double* Rc = W + M * TE_LX;    // Gram matrix, then Cholesky factor
-  // (d_i, e_i) of T / sc
-  __shared__ double2 dsc[M + 1];
-  if (tid <= M)
+  double* Dlt = W;                  // delta_i: Dlt[i * M + c]
+  double* Uup = W + M * M;          // u_i
+  double* Rho = W + 2 * M * M;      // rho_i
+  double* Xv = W + 2 * M * M - M;   // vectors, Xv[c * TE_LX + i] (after the pivots; the
+                                    // rows it covers of Uup (i = 63) and Rho are unused then)
+  double* Rc = W;                   // Gram matrix, then Cholesky factor
+  __shared__ double2 dsc[M + 4];    // (d_i, e_i) of T / sc
+  __shared__ double znrm[2 * M];    // squared norms of the two halves of each z
+  if (tid < M + 4)
     dsc[tid] = (tid < n) ? make_double2(dd[tid] * isc, ee[tid] * isc) : make_double2(0.0, 0.0);
-  if (w == 0) {
-    for (int i = 0; i < n; ++i) {
-      // a fixed start vector with no symmetry: 1 + frac(0.618 i) / 2
-      const double hh = 0.6180339887498949 * (double)i;
-      Xw[i * M + r] = 1.0 + 0.5 * (hh - floor(hh));
+  __syncthreads();
+  const double lv = lamg[min(r, max(d - 1, 0))] * isc;
+  auto guard = [&](double v) { return copysign(fmax(fabs(v), ptiny), v); };
+  if (w == 0 && d > 0) {
+    double dl = guard(dsc[0].x - lv);
+    Dlt[r] = dl;
+    double2 dA = dsc[1], dB = dsc[2];
+    for (int i = 0; i + 1 < n; ++i) {
+      const double2 dn = dA;
+      const double2 dC = dsc[i + 3];
+      dA = dB;
+      dB = dC;
+      const double e = dsc[i].y;
+      const double l = e * te_rcp(dl);
+      dl = guard(fma(-l, e, dn.x - lv));
+      Dlt[(i + 1) * M + r] = dl;
+    }
+  } else if (w == 1 && d > 0) {
+    double rh = guard(dsc[n - 1].x - lv);
+    Rho[(n - 1) * M + r] = rh;
+    for (int i = n - 2; i >= 0; --i) {
+      const double2 di = dsc[i];
+      const double u = di.y * te_rcp(rh);
+      Uup[i * M + r] = u;
+      rh = guard(fma(-u, di.y, di.x - lv));
+      Rho[i * M + r] = rh;
     }
   }
   __syncthreads();
-  if (w == 0 && d > 0) {
-    const double lv = lamg[min(r, d - 1)] * isc;
-    for (int pass = 0; pass < 2; ++pass) {
-      // forward elimination; bit i of swm: rows i and i + 1 exchanged
-      unsigned long long swm = 0ull;
-      double2 di = dsc[0], dn = dsc[1];
-      double c0 = di.x - lv, c1 = (n > 1) ? di.y : 0.0;
-      double carry = Xw[r];
-      double xn = Xw[min(1, n - 1) * M + r];
-      for (int i = 0; i < n - 1; ++i) {
-        // operands of the next step, loaded ahead (indices kept in range)
-        const double2 dn2 = dsc[i + 2];
-        const double xnn = Xw[min(i + 2, n - 1) * M + r];
-        const double sb = di.y, dg = dn.x - lv;
-        const double sp = (i + 2 < n) ? dn.y : 0.0;
-        const bool swap = fabs(sb) > fabs(c0);
-        const double piv = swap ? sb : ((c0 == 0.0) ? ptiny : c0);
-        const double rp = te_rcp(piv);
-        const double f = (swap ? c0 : sb) * rp;
-        U0[i * M + r] = rp;
-        U1[i * M + r] = swap ? dg : c1;
-        swm |= (unsigned long long)swap << i;
-        const double xi = carry;
-        Xw[i * M + r] = swap ? xn : xi;
-        carry = swap ? (xi - f * xn) : (xn - f * xi);
-        const double n0 = swap ? (c1 - f * dg) : (dg - f * c1);
-        const double n1 = swap ? (-f * sp) : sp;
-        c0 = n0;
-        c1 = n1;
-        di = dn;
-        dn = dn2;
-        xn = xnn;
-      }
-      Xw[(n - 1) * M + r] = carry;
-      const double rpl = te_rcp((c0 == 0.0) ? ptiny : c0);
-      // back substitution (operands of the next row loaded ahead)
-      double x1 = 0.0, x2 = 0.0, nrm = 0.0;
-      double u0l = U0[(n - 1) * M + r], u1l = U1[(n - 1) * M + r], el = dsc[n].y;
-      double xl = Xw[(n - 1) * M + r];
-      for (int i = n - 1; i >= 0; --i) {
-        const int ip = max(i - 1, 0);
-        const double u0n = U0[ip * M + r], u1n = U1[ip * M + r], en = dsc[ip + 1].y;
-        const double xnx = Xw[ip * M + r];
-        const double u0 = (i == n - 1) ? rpl : u0l;
-        const double u1 = (i + 1 < n) ? u1l : 0.0;
-        const double u2 = (i + 2 < n && ((swm >> i) & 1ull)) ? el : 0.0;
-        const double xi = (xl - u1 * x1 - u2 * x2) * u0;
-        Xw[i * M + r] = xi;
-        nrm = fma(xi, xi, nrm);
-        x2 = x1;
-        x1 = xi;
-        u0l = u0n;
-        u1l = u1n;
-        el = en;
-        xl = xnx;
-      }
-      const double inv = 1.0 / sqrt(nrm);
-      if (pass == 0) {
-        for (int i = 0; i < n; ++i) Xw[i * M + r] *= inv;
-      } else {
-        // publish vector r (the factors are no longer needed)
-        for (int i = 0; i < n; ++i) Xv[r * TE_LX + i] = Xw[i * M + r] * inv;
+  // twist index (both wavefronts, the same in each lane)
+  int k = 0;
+  if (w < 2 && d > 0) {
+    double best = INFINITY;
+    for (int i = 0; i < n; ++i) {
+      const double g = fabs(Dlt[i * M + r] + Rho[i * M + r] - (dsc[i].x - lv));
+      if (g < best) {
+        best = g;
+        k = i;
       }
     }
+  }
+  __syncthreads();   // (the vectors overwrite the rho_i)
+  if (w < 2 && d > 0) {
+    double z = 1.0, nz = 0.0;
+    if (w == 0) {
+      // z_k and the entries above it
+      Xv[r * TE_LX + k] = 1.0;
+      nz = 1.0;
+      for (int i = n - 2; i >= 0; --i) {
+        const double l = dsc[i].y * te_rcp(Dlt[i * M + r]);
+        if (i < k) {
+          z = -l * z;
+          Xv[r * TE_LX + i] = z;
+          nz = fma(z, z, nz);
+        }
+      }
+    } else {
+      // the entries below z_k
+      for (int i = 0; i + 1 < n; ++i) {
+        const double u = Uup[i * M + r];
+        if (i >= k) {
+          z = -u * z;
+          Xv[r * TE_LX + i + 1] = z;
+          nz = fma(z, z, nz);
+        }
+      }
+    }
+    znrm[w * M + r] = nz;
   }
   __syncthreads();
   TS(3);
@@ -1863,11 +1922,11 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
     int L = 64;
     while (L > 4 && L * d > 256) L >>= 1;
     switch (L) {
-      case 64: te_back_gram<64>(H, tau, Xv, Rc, n, d); break;
-      case 32: te_back_gram<32>(H, tau, Xv, Rc, n, d); break;
-      case 16: te_back_gram<16>(H, tau, Xv, Rc, n, d); break;
-      case 8: te_back_gram<8>(H, tau, Xv, Rc, n, d); break;
-      default: te_back_gram<4>(H, tau, Xv, Rc, n, d); break;
+      case 64: te_back_gram<64>(H, tau, Xv, Rc, znrm, n, d); break;
+      case 32: te_back_gram<32>(H, tau, Xv, Rc, znrm, n, d); break;
+      case 16: te_back_gram<16>(H, tau, Xv, Rc, znrm, n, d); break;
+      case 8: te_back_gram<8>(H, tau, Xv, Rc, znrm, n, d); break;
+      default: te_back_gram<4>(H, tau, Xv, Rc, znrm, n, d); break;
     }
   }
   __syncthreads();
@@ -1917,8 +1976,11 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
     for (int k = 0; k < 6; ++k) flags[8 + k] = (int)(tsv[k] - tsv[0]);
   if ((tid & 63) == 0 && flags)
     for (int k = 0; k < 5; ++k) flags[16 + 8 * w + k] = (int)seg[k];
+  if (tid == 0 && flags)
+    for (int k = 1; k < 7; ++k) flags[48 + k] = (int)(tiv[k] - tiv[0]);
 #endif
 #undef TS
+#undef TIV
 #undef SEG
 }
 
