@@ -384,6 +384,48 @@ def test_rom_rank_auto_indicator():
         assert info["two_n"] == two_n == min(8 + 2 * (s + 1), 12)
 
 
+def test_rom_deim_rank_auto_parity():
+    """DEIM with rank adaptation after every step (threshold 0: one pair per
+    step up to the cap), the path on which the next step's DEIM operator is
+    built ahead of its step and built again when the rank changes: ranks,
+    DEIM switch-over, iteration counts and indicators as in the oracle, R
+    within the conditioning-aware bound of the same adaptive run."""
+    binding, torch = _b()
+    kw, two_n, two_n_max, steps = dict(N=20000, p=24, Nx=128), 8, 14, 7
+    w, e = _ens("twostream_deim", **kw)
+    _say("rom deim rank auto", kw, two_n, two_n_max, steps)
+    cfg, st = _oracle_state(w, e, two_n, fp_tol=1e-10, projection="deim", deim_window=3)
+    cfg.two_n_max, cfg.rank_tol_up = two_n_max, 0.0
+    # sensitivity of the adaptive run to a 1e-15 relative change of Z
+    rng = np.random.default_rng(0)
+    outs = []
+    for pert in (0.0, 1e-15):
+        s2 = rom.RomState(U=st.U.copy(), Z=st.Z * (1 + pert * rng.normal(size=st.Z.shape)),
+                          L=st.L)
+        c2 = rom.RomConfig(**cfg.__dict__)   # (the rank policy updates its config)
+        for _ in range(steps):
+            assert rom.prk_step(s2, c2) == rom.OK
+            rom.adapt_rank(s2, c2, 0)
+        outs.append(s2.U @ s2.Z)
+    sR = _rel(outs[1], outs[0])
+    r = _gpu_rom(binding, w, e, two_n, two_n_max=two_n_max, fp_tol=1e-10, projection="deim",
+                 deim_window=3, rank_auto=True, rank_tol_up=0.0)
+    _set_from_oracle(r, st, torch)
+    for s in range(steps):
+        info = r.step(1)
+        assert rom.prk_step(st, cfg) == rom.OK
+        status, two_n_o, eps = rom.adapt_rank(st, cfg, 0)
+        assert info["two_n"] == two_n_o == min(two_n + 2 * (s + 1), two_n_max), (s, info)
+        assert info["deim_active"] == (1 if s >= 3 else 0), (s, info)
+        assert info["iters"] == st.last_iters, (s, info, st.last_iters)
+        assert abs(info["rank_indicator"] - eps) < 1e-6 * max(eps, 1e-3), (s, info, eps)
+    X, V = r.reconstruct()
+    Xo, Vo = rom.reconstruct(st)
+    bound = max(1e-9, _bound(sR))
+    assert _rel(_np(X).T, Xo) < bound, (sR,)
+    assert _rel(_np(V).T, Vo) < bound, (sR,)
+
+
 @pytest.mark.parametrize("kw,two_n,two_n_max,steps", [
     (dict(N=20000, p=24, Nx=128), 8, 8, 6),
     (dict(N=30000, p=64, Nx=128), 10, 60, 6),     # the two-stream workload's DEIM shape
