@@ -105,3 +105,26 @@ inline void allow_big_lds(K kern) {
 
 #define SYMROM_MAX_NC 32    // complex reduced columns held in registers (2n <= 64)
 #define SYMROM_MAX_NX 1024  // grid nodes handled by the Poisson kernel
+
+// One 64-bit DPP move (two 32-bit moves; zero where the source lane is out
+// of range or its row is masked off).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Butterfly partners inside aligned groups of up to 16 lanes: lane i ^ 1
+// and i ^ 2 (quad permutations), then the mirror images inside halves of 8
+// and rows of 16, which pair every lane with one in the other half.
+// Combining with a commutative operation leaves the same bits in every lane
+// of the group.
+template <int LEVEL>
+__device__ __forceinline__ double bfly64(double v) {
+  if (LEVEL == 0) return dpp64<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
+  if (LEVEL == 1) return dpp64<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
+  if (LEVEL == 2) return dpp64<0x141, 0xf>(v);   // row_half_mirror
+  return dpp64<0x140, 0xf>(v);                   // row_mirror
+}

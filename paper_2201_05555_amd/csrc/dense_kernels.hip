@@ -1376,14 +1376,9 @@ __device__ __forceinline__ double te_lane(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// one 32-bit DPP move (zero where the source lane is out of range or the
-// row is masked off)
 template <int CTRL, int ROWS>
 __device__ __forceinline__ double te_dpp(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, true);
-  return __hiloint2double(hi, lo);
+  return dpp64<CTRL, ROWS>(v);
 }
 
 // orders LDS accesses of one wavefront around an exchange between its lanes
@@ -1426,17 +1421,9 @@ __device__ __forceinline__ void te_wave_sum2(double& u, double& v) {
   v = te_lane(v, 63);
 }
 
-// Butterfly partners inside aligned groups of up to 16 lanes by DPP: lane
-// i ^ 1 and i ^ 2 (quad permutations), then the mirror images inside halves
-// of 8 and rows of 16, which pair every lane with one in the other half.
-// Combining with a commutative operation leaves the same bits in every lane
-// of the group.
 template <int LEVEL>
 __device__ __forceinline__ double te_bfly(double v) {
-  if (LEVEL == 0) return te_dpp<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
-  if (LEVEL == 1) return te_dpp<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
-  if (LEVEL == 2) return te_dpp<0x141, 0xf>(v);   // row_half_mirror
-  return te_dpp<0x140, 0xf>(v);                   // row_mirror
+  return bfly64<LEVEL>(v);
 }
 
 // sum over aligned groups of L lanes (L a power of two, 4 <= L <= 64),

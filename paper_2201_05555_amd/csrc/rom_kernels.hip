@@ -850,68 +850,170 @@ __global__ void __launch_bounds__(256) deim_weights_kernel(
   }
 }
 
-// Psi (N x d) = sum_s Y_s M[s*kin:(s+1)*kin, :] (the DEIM basis Y V diag(lam)^{-1/2},
-// M = P x d column-major, ld ldM), plus per-block column sums of Psi into
-// colpart[blockIdx][c] (fixed order: wavefront butterflies, then the four
-// wavefronts in order).  Grid-stride over rows; loads in batches of four.
-template <int MC>
-__global__ void __launch_bounds__(256) psi_colsum_kernel(RealList L, int kin, int N,
-                                                         const double* __restrict__ M, int ldM,
-                                                         int d, double* __restrict__ out,
-                                                         double* __restrict__ colpart) {
-  extern __shared__ double Mr[];   // [P][MC], zero beyond d; then [4][MC] wavefront sums
+// ---------------------------------------------------------------------------
+// FP64 matrix-core tiles (v_mfma_f64_16x16x4f64): a wavefront multiplies a
+// 16 x 4 tile A by a 4 x 16 tile B into a 16 x 16 accumulator D.  Operand
+// layout: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k; result: lane
+// l holds D[4 v + l / 16][l % 16] in item v.
+// ---------------------------------------------------------------------------
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ mf_d4 mf_step(double a, double b, mf_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// DEIM basis Psi = Y M (N x d) from the snapshot slots (Y: N x P, column
+// blocks of kin columns per slot) and M (P x d, ld ldM), computed as
+// Psi^T = M^T Y^T on the matrix cores: per 16-row tile and 16 columns of
+// Psi, 4-row slices of M^T (A, kept in registers) times 4 x 16 slices of Y^T
+// (B: 16 consecutive rows of one column per 16 lanes).  Column sums of Psi
+// per block into colpart[blockIdx][c] (fixed order: butterflies over the 16
+// rows of a tile, tiles in order per lane, then the four wavefronts).
+template <int NCB>
+__global__ void __launch_bounds__(256) psi_mfma_kernel(RealList L, int kin, int N,
+                                                       const double* __restrict__ M, int ldM,
+                                                       int d, double* __restrict__ out,
+                                                       double* __restrict__ colpart) {
+  __shared__ double wsum[4][64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int P = L.count * kin;
-  for (int t = threadIdx.x; t < P * MC; t += blockDim.x) {
-    const int r = t / MC, c = t % MC;
-    Mr[t] = (c < d) ? M[(size_t)c * ldM + r] : 0.0;
+  const int nks = (P + 3) / 4;
+  const int li = lane & 15, lk = lane >> 4;
+  // A operands: a[cb][ks] = M[4 ks + lk][16 cb + li] (zero outside)
+  double a[NCB][16];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      const int k = 4 * ks + lk, c = 16 * cb + li;
+      a[cb][ks] = (k < P && c < d) ? M[(size_t)c * ldM + k] : 0.0;
+    }
+  // column pointers of Y for this lane's rows of B (k = 4 ks + lk)
+  const double* yc[16];
+#pragma unroll
+  for (int ks = 0; ks < 16; ++ks) {
+    const int k = min(4 * ks + lk, P - 1);
+    yc[ks] = L.ptr[k / kin] + (size_t)(k % kin) * N;
   }
+  double cs[NCB][4];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) cs[cb][v] = 0.0;
+  const int ntile = (N + 15) / 16;
+  for (int t = blockIdx.x * 4 + w; t < ntile; t += gridDim.x * 4) {
+    const int row = 16 * t + li;
+    const int rowc = min(row, N - 1);
+    double b[16];
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) b[ks] = yc[ks][rowc];
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) b[ks] = (row < N && 4 * ks + lk < P) ? b[ks] : 0.0;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      mf_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks)
+        if (ks < nks) acc = mf_step(a[cb][ks], b[ks], acc);
+      // lane holds Psi[row 16 t + li][column 16 cb + 4 v + lk]
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = 16 * cb + 4 * v + lk;
+        if (row < N && c < d) out[(size_t)c * N + row] = acc[v];
+        cs[cb][v] += acc[v];   // zero for rows beyond N
+      }
+    }
+  }
+  // sums over the 16 rows of a tile (lanes with the same lk), then waves
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double x = cs[cb][v];
+      x += bfly64<0>(x);
+      x += bfly64<1>(x);
+      x += bfly64<2>(x);
+      x += bfly64<3>(x);
+      if (li == 0) {
+        const int c = 16 * cb + 4 * v + lk;
+        if (c < 64) wsum[w][c] = x;
+      }
+    }
   __syncthreads();
-  double csum[MC];
+  if (tid < d) {
+    const double s = ((wsum[0][tid] + wsum[1][tid]) + wsum[2][tid]) + wsum[3][tid];
+    colpart[(size_t)blockIdx.x * d + tid] = s;
+  }
+}
+
+// Block of the snapshot Gram matrix, S = Ynew^T Yall (a <= 64 rows, b <= 64
+// columns) over the rows [kb rk, (kb+1) rk), 16 rows of S at a time: per 16
+// rows of Y, four 4-row slices of Ynew^T (A) and Yall (B, one 16-column
+// block per accumulator); the four wavefronts' sums are added in order and
+// written as this block's partial part[kb][ib * a + ia].
+__global__ void __launch_bounds__(256) gram_mfma_kernel(RealList A, int ka, int a, RealList B,
+                                                        int kbcols, int b, int N, int rk,
+                                                        double* __restrict__ part,
+                                                        const int* __restrict__ stop) {
+  if (stop && *stop) return;
+  __shared__ double red[4][16 * 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const double* pb[4];
+  bool vb[4];
 #pragma unroll
-  for (int o = 0; o < MC; ++o) csum[o] = 0.0;
-  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < N; l += gridDim.x * blockDim.x) {
-    double acc[MC];
+  for (int cb = 0; cb < 4; ++cb) {
+    const int jb = min(16 * cb + li, b - 1);
+    pb[cb] = B.ptr[jb / kbcols] + (size_t)(jb % kbcols) * N;
+    vb[cb] = 16 * cb + li < b;
+  }
+  const int ncb = (b + 15) / 16;
+  const int r0 = blockIdx.x * rk, r1 = min(N, r0 + rk);
+  const int nout = a * b;
+  for (int i0 = 0; i0 < a; i0 += 16) {
+    const int ia = min(i0 + li, a - 1);
+    const double* pa = A.ptr[ia / ka] + (size_t)(ia % ka) * N;
+    const bool va = i0 + li < a;
+    mf_d4 acc[4];
 #pragma unroll
-    for (int o = 0; o < MC; ++o) acc[o] = 0.0;
-    for (int s = 0; s < L.count; ++s) {
-      const double* ys = L.ptr[s] + l;
-      int k = 0;
-      for (; k + 4 <= kin; k += 4) {
-        double y[4];
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = mf_d4{0.0, 0.0, 0.0, 0.0};
+    for (int base = r0 + 16 * w; base < r1; base += 64) {
+      // rows base + 4 s + lk, s = 0..3
+      double av[4], bv[4][4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) y[u] = ys[(size_t)(k + u) * N];
+      for (int s = 0; s < 4; ++s) {
+        const int row = base + 4 * s + lk;
+        const int rowc = min(row, N - 1);
+        const bool ok = row < r1;
+        const double x = pa[rowc];
+        av[s] = (ok && va) ? x : 0.0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const double* mrow = Mr + (s * kin + k + u) * MC;
-#pragma unroll
-          for (int o = 0; o < MC; ++o) acc[o] = fma(y[u], mrow[o], acc[o]);
+        for (int cb = 0; cb < 4; ++cb) {
+          const double y = pb[cb][rowc];
+          bv[cb][s] = (ok && vb[cb]) ? y : 0.0;
         }
       }
-      for (; k < kin; ++k) {
-        const double y = ys[(size_t)k * N];
-        const double* mrow = Mr + (s * kin + k) * MC;
 #pragma unroll
-        for (int o = 0; o < MC; ++o) acc[o] = fma(y, mrow[o], acc[o]);
-      }
-    }
+      for (int cb = 0; cb < 4; ++cb)
+        if (cb < ncb)
 #pragma unroll
-    for (int o = 0; o < MC; ++o) {
-      if (o < d) out[(size_t)o * N + l] = acc[o];
-      csum[o] += acc[o];
+          for (int s = 0; s < 4; ++s) acc[cb] = mf_step(av[s], bv[cb][s], acc[cb]);
     }
+    // lane holds S[i0 + 4 v + lk][16 cb + li]
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[w][(4 * v + lk) * 64 + 16 * cb + li] = acc[cb][v];
+    __syncthreads();
+    const int na = min(16, a - i0);
+    for (int o = tid; o < na * b; o += 256) {
+      const int i = o % na, j = o / na;
+      const double sm = ((red[0][i * 64 + j] + red[1][i * 64 + j]) + red[2][i * 64 + j]) +
+                        red[3][i * 64 + j];
+      part[(size_t)blockIdx.x * nout + (size_t)j * a + i0 + i] = sm;
+    }
+    __syncthreads();
   }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int o = 0; o < MC; ++o)
-    for (int q = 32; q > 0; q >>= 1) csum[o] += __shfl_xor(csum[o], q, 64);
-  __syncthreads();
-  double* ws = Mr;
-  if (lane == 0)
-#pragma unroll
-    for (int o = 0; o < MC; ++o) ws[w * MC + o] = csum[o];
-  __syncthreads();
-  for (int o = threadIdx.x; o < d; o += blockDim.x)
-    colpart[(size_t)blockIdx.x * d + o] = ((ws[o] + ws[MC + o]) + ws[2 * MC + o]) + ws[3 * MC + o];
 }
 
 // DEIM snapshot Lambda^0(X_r^i) Phi^i at every particle (Sec. 4.3, eq. Ydeim)
@@ -968,91 +1070,6 @@ __global__ void __launch_bounds__(256) snapshot_kernel(const cplx* __restrict__ 
   }
 }
 
-// Real product C = A^T B (A: N x a, B = [B_0 ...] N x b, column-major,
-// a, b <= 64), split over row blocks: row chunks staged through LDS with
-// coalesced loads, 4 x 4 register tiles, tile sums in a padded entry-major
-// LDS layout, block partials part[kb][ib * a + ia] summed by
-// reduce_gram_block_kernel.
-__global__ void __launch_bounds__(256) gemm_real_tn_kernel(RealList A, int ka, int a, RealList B,
-                                                           int kbcols, int b, int N, int rk, int TR,
-                                                           double* __restrict__ part,
-                                                           const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  extern __shared__ double smr[];   // staging [a + b][TR], later tile sums [16][GEMM_RED_LD]
-  __shared__ const double* colp[128];
-  const int tid = threadIdx.x;
-  if (tid < a + b)
-    colp[tid] = (tid < a) ? A.ptr[tid / ka] + (size_t)(tid % ka) * N
-                          : B.ptr[(tid - a) / kbcols] + (size_t)((tid - a) % kbcols) * N;
-  const int kb = blockIdx.x;
-  const int r0 = kb * rk;
-  const int r1 = min(N, r0 + rk);
-  const int nta = (a + 3) / 4, ntb = (b + 3) / 4, nt = nta * ntb;
-  const int R = max(1, 256 / nt);
-  const int tile = tid / R, rg = tid % R;
-  const bool owner = tile < nt;
-  const int ta0 = (tile % nta) * 4, tb0 = (tile / nta) * 4;
-  const int nst = a + b;
-  double* sA = smr;
-  double* sB = smr + (size_t)a * TR;
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int c0 = r0; c0 < r1; c0 += TR) {
-    const int tn = min(TR, r1 - c0);
-    __syncthreads();
-    const int tot = nst * TR;
-    for (int t0 = 0; t0 < tot; t0 += 16 * 256) {
-      double v[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int t = t0 + u * 256 + tid;
-        v[u] = 0.0;
-        if (t < tot) {
-          const int col = t / TR, row = t % TR;
-          if (row < tn) v[u] = colp[col][c0 + row];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int t = t0 + u * 256 + tid;
-        if (t < tot) smr[t] = v[u];
-      }
-    }
-    __syncthreads();
-    if (owner) {
-      for (int row = rg; row < tn; row += R) {
-        double av[4], bv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = (ta0 + i < a) ? sA[(ta0 + i) * TR + row] : 0.0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = (tb0 + j < b) ? sB[(tb0 + j) * TR + row] : 0.0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
-      }
-    }
-  }
-  __syncthreads();
-  double* red = smr;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) red[(i * 4 + j) * GEMM_RED_LD + tid] = acc[i][j];
-  __syncthreads();
-  const int nout = a * b;
-  for (int o = tid; o < nt * 16; o += blockDim.x) {
-    const int tl = o / 16, q = o % 16;
-    double s2 = 0.0;
-#pragma unroll 8
-    for (int g = 0; g < R; ++g) s2 += red[q * GEMM_RED_LD + tl * R + g];
-    const int ia = (tl % nta) * 4 + q / 4, ib = (tl / nta) * 4 + q % 4;
-    if (ia < a && ib < b) part[(size_t)kb * nout + (size_t)ib * a + ia] = s2;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // host launchers
@@ -1298,13 +1315,8 @@ void launch_gram_block_real(hipStream_t s, const double* Ynew, const double* con
   if (nkb < 1) nkb = 1;
   const int rk = (N + nkb - 1) / nkb;
   nkb = (N + rk - 1) / rk;
-  int TR = 256;
-  while (TR > 32 && (a + b) * TR > 8192) TR >>= 1;
-  size_t sh = (size_t)(a + b) * TR * sizeof(double);
-  if (sh < (size_t)16 * GEMM_RED_LD * sizeof(double)) sh = (size_t)16 * GEMM_RED_LD * sizeof(double);
-  ALLOW_BIG_LDS(gemm_real_tn_kernel);
-  hipLaunchKernelGGL(gemm_real_tn_kernel, dim3(nkb), dim3(256), sh, s, A, psub, a, B, psub, b, N, rk,
-                     TR, part, stop);
+  hipLaunchKernelGGL(gram_mfma_kernel, dim3(nkb), dim3(256), 0, s, A, psub, a, B, psub, b, N, rk,
+                     part, stop);
   hipLaunchKernelGGL(reduce_gram_block_kernel, dim3((a * b + 3) / 4), dim3(256), 0, s, part, nkb, a,
                      b, b, r0, S, stop);
 }
@@ -1354,22 +1366,13 @@ void launch_psi_colsum(hipStream_t s, const double* const* in, int nin, int kin,
   RealList L{};
   for (int q = 0; q < nin; ++q) L.ptr[q] = in[q];
   L.count = nin;
-  const int P = nin * kin;
-  const int mc = (d <= 8) ? 8 : (d <= 16) ? 16 : (d <= 32) ? 32 : 64;
-  size_t sh = (size_t)P * mc * sizeof(double);
-  if (sh < (size_t)4 * mc * sizeof(double)) sh = (size_t)4 * mc * sizeof(double);
   dim3 grid(psi_blocks(N));
-#define PC(MCV)                                                                                  \
-  ALLOW_BIG_LDS(psi_colsum_kernel<MCV>);                                                       \
-  hipLaunchKernelGGL(psi_colsum_kernel<MCV>, grid, dim3(256), sh, s, L, kin, N, M, ldM, d, out, \
-                     colpart)
-  switch (mc) {
-    case 8: PC(8); break;
-    case 16: PC(16); break;
-    case 32: PC(32); break;
-    default: PC(64); break;
-  }
-#undef PC
+  if (d <= 16)
+    hipLaunchKernelGGL(psi_mfma_kernel<1>, grid, dim3(256), 0, s, L, kin, N, M, ldM, d, out, colpart);
+  else if (d <= 32)
+    hipLaunchKernelGGL(psi_mfma_kernel<2>, grid, dim3(256), 0, s, L, kin, N, M, ldM, d, out, colpart);
+  else
+    hipLaunchKernelGGL(psi_mfma_kernel<4>, grid, dim3(256), 0, s, L, kin, N, M, ldM, d, out, colpart);
 }
 
 void launch_deim_greedy(hipStream_t s, const double* Psi, int N, int k, int* idx,
