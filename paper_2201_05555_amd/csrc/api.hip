@@ -658,16 +658,12 @@ RowTerms rt(const cplx* in0, const cplx* M0, int k0, const cplx* in1 = nullptr,
   return T;
 }
 
-// g = U^* G~ with the full gradient of every column at (U, Z): deposit,
-// Poisson, then either the fused gather-projection (G~ never stored) or, for
-// ranks beyond the fused kernels, the gather into r.G and a split-K product.
-// With want_colsq, |G~[:, c]|^2 goes to r.colsq.
-void full_gradient(symrom_rom& r, const cplx* U, const cplx* Z, const int* active,
-                   bool do_deposit, bool want_colsq = false, const int* gate = nullptr) {
+// The field of every column at (U, Z): deposit, then Poisson.
+void full_gradient_field(symrom_rom& r, const cplx* U, const cplx* Z, const int* active,
+                         const int* gate = nullptr) {
   hipStream_t s = r.s;
   const int n = r.n;
-  const double qm = r.cfg.q / r.cfg.m;
-  if (do_deposit) {
+  {
     {
       const double pact = (active ? (double)r.n_active : (double)r.p);
       const int ntiles = (r.p + r.gdep.pt - 1) / r.gdep.pt;
@@ -680,6 +676,19 @@ void full_gradient(symrom_rom& r, const cplx* U, const cplx* Z, const int* activ
     launch_poisson(s, r.b.part, r.gdep.nrb, r.p, r.Nx, r.b.qw, r.b.h, r.b.mw, active, r.b.rho,
                    r.b.phi, r.b.e, r.b.energy, gate);
   }
+}
+
+// g = U^* G~ with the full gradient of every column at (U, Z): the field
+// first when do_deposit (else the one in the buffers), then either the
+// fused gather-projection (G~ never stored) or, for ranks beyond the fused
+// kernels, the gather into r.G and a split-K product.  With want_colsq,
+// |G~[:, c]|^2 goes to r.colsq.
+void full_gradient(symrom_rom& r, const cplx* U, const cplx* Z, const int* active,
+                   bool do_deposit, bool want_colsq = false, const int* gate = nullptr) {
+  hipStream_t s = r.s;
+  const int n = r.n;
+  const double qm = r.cfg.q / r.cfg.m;
+  if (do_deposit) full_gradient_field(r, U, Z, active, gate);
   const double pact = (active ? (double)r.n_active : (double)r.p);
   if (fused_gradient_ok(n)) {
     // per (particle, parameter): 4n flops for x and v, 4n for the projection,
@@ -994,13 +1003,17 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   // so that one readback serves both; a failed step exchanges them back.
   std::swap(r.U0, r.Uh);
   std::swap(r.Z0, r.Z1);
-  if (decide_rank) {
-    full_gradient(r, r.U0, r.Z0, nullptr, true, true);
-    launch_dense_indicator(s, r.colsq, r.gproj, n, p, r.eps_dev);
-  }
+  // (the step's error words are final here)
   if (use_deim) launch_fold_status(s, r.status);
   const bool ahead = use_deim && decide_rank;
-  if (ahead) HIPCHK(hipEventRecord(r.ev_fork, s));
+  if (decide_rank) {
+    // the field at the new state, then (beside the DEIM chain ahead, which
+    // needs only the field) its projection and the indicator
+    full_gradient_field(r, r.U0, r.Z0, nullptr);
+    if (ahead) HIPCHK(hipEventRecord(r.ev_fork, s));
+    full_gradient(r, r.U0, r.Z0, nullptr, false, true);
+    launch_dense_indicator(s, r.colsq, r.gproj, n, p, r.eps_dev);
+  }
   // the status copy is started before the chain ahead is enqueued, and
   // waited for after
   HIPCHK(hipMemcpyAsync(r.hstat, r.status, 12 * sizeof(int), hipMemcpyDeviceToHost, s));

@@ -128,3 +128,28 @@ __device__ __forceinline__ double bfly64(double v) {
   if (LEVEL == 2) return dpp64<0x141, 0xf>(v);   // row_half_mirror
   return dpp64<0x140, 0xf>(v);                   // row_mirror
 }
+
+// the same butterfly for 32-bit integers
+template <int LEVEL>
+__device__ __forceinline__ int bfly32(int v) {
+  constexpr int CTRL = (LEVEL == 0) ? 0xB1 : (LEVEL == 1) ? 0x4E : (LEVEL == 2) ? 0x141 : 0x140;
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, true);
+}
+
+// value of v in lane `lane` (uniform), as a scalar
+__device__ __forceinline__ double rdlane64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over the 64 lanes of a wavefront, the same bits in every lane: row
+// butterflies, then the four row sums added in a fixed order
+__device__ __forceinline__ double wave_sum64(double v) {
+  v += bfly64<0>(v);
+  v += bfly64<1>(v);
+  v += bfly64<2>(v);
+  v += bfly64<3>(v);
+  return (rdlane64(v, 0) + rdlane64(v, 16)) + (rdlane64(v, 32) + rdlane64(v, 48));
+}

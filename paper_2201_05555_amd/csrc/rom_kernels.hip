@@ -574,28 +574,42 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
 // DEIM basis, indices and weights (Sec. 4.3), N-wide passes.
 // ---------------------------------------------------------------------------
 
+// (value, index) pairs: the larger value wins, the smaller index on ties
+__device__ __forceinline__ void dg_take(double& best, int& bi, double ov, int oi) {
+  if (ov > best || (ov == best && oi < bi)) {
+    best = ov;
+    bi = oi;
+  }
+}
+
+// winner over the 64 lanes of a wavefront, the same in every lane: row
+// butterflies, then the four row winners in a fixed order
+__device__ __forceinline__ void dg_wave_argmax(double& best, int& bi) {
+  dg_take(best, bi, bfly64<0>(best), bfly32<0>(bi));
+  dg_take(best, bi, bfly64<1>(best), bfly32<1>(bi));
+  dg_take(best, bi, bfly64<2>(best), bfly32<2>(bi));
+  dg_take(best, bi, bfly64<3>(best), bfly32<3>(bi));
+  double rv[4];
+  int ri[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    rv[q] = rdlane64(best, 16 * q);
+    ri[q] = __builtin_amdgcn_readlane(bi, 16 * q);
+  }
+  best = rv[0];
+  bi = ri[0];
+#pragma unroll
+  for (int q = 1; q < 4; ++q) dg_take(best, bi, rv[q], ri[q]);
+}
+
 // winner of per-block (value, index) results: largest value, smallest index
 // on ties; computed by the first wavefront, returned in its lanes
 __device__ int dg_winner(const double* __restrict__ val, const int* __restrict__ idx, int nb) {
   const int lane = threadIdx.x & 63;
   double best = -1.0;
   int bi = 0x7fffffff;
-  for (int b = lane; b < nb; b += 64) {
-    const double v = val[b];
-    const int vi = idx[b];
-    if (v > best || (v == best && vi < bi)) {
-      best = v;
-      bi = vi;
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(best, o, 64);
-    const int oi = __shfl_xor(bi, o, 64);
-    if (ov > best || (ov == best && oi < bi)) {
-      best = ov;
-      bi = oi;
-    }
-  }
+  for (int b = lane; b < nb; b += 64) dg_take(best, bi, val[b], idx[b]);
+  dg_wave_argmax(best, bi);
   return bi;
 }
 
@@ -615,10 +629,7 @@ __device__ int dg_winner(const double* __restrict__ val, const int* __restrict__
 // index) of the largest |r_k| over its rows (smallest index on ties) to bval,
 // bidx.  k = 0 takes r_0 = psi_0.  Inverses are kept as 64 x 64 row-major.
 #define DG_KR 16   // leading columns of Psi prefetched for a thread's first two rows
-__device__ __forceinline__ double dg_wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+__device__ __forceinline__ double dg_wave_sum(double v) { return wave_sum64(v); }
 
 // Bordering step shared by the greedy passes and the weights: reads
 // Bprev (m x m, m = k - 1), uprev (m), the rows idx[0..m-1] and l = lwin;
@@ -765,14 +776,7 @@ __global__ void __launch_bounds__(256) deim_greedy_kernel(
     if (q <= k) r0 = fma(Psi[(size_t)q * N + l], cf[q], r0);
     take(fabs(r0 + r1), l);
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(best, o, 64);
-    const int oi = __shfl_xor(bi, o, 64);
-    if (ov > best || (ov == best && oi < bi)) {
-      best = ov;
-      bi = oi;
-    }
-  }
+  dg_wave_argmax(best, bi);
   if (lane == 0) {
     sv[w] = best;
     si[w] = bi;
