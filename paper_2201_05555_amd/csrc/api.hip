@@ -665,10 +665,11 @@ void full_gradient_field(symrom_rom& r, const cplx* U, const cplx* Z, const int*
   const int n = r.n;
   {
     {
+      // bytes: U and Z once each (the parameter tiles reread U from the
+      // caches), the partial histograms written
       const double pact = (active ? (double)r.n_active : (double)r.p);
-      const int ntiles = (r.p + r.gdep.pt - 1) / r.gdep.pt;
       Timer t(FAM_DEPOSIT, s, 4.0 * n * (double)r.N * pact,
-              16.0 * n * (double)r.N * ntiles + 8.0 * (double)r.gdep.nrb * pact * r.Nx);
+              16.0 * n * ((double)r.N + r.p) + 8.0 * (double)r.gdep.nrb * pact * r.Nx);
       launch_deposit_rom(s, U, r.N, n, Z, r.p, r.Nx, r.gdep, r.b.factor, active, r.b.part,
                          gate);
     }
@@ -943,9 +944,8 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
       if (deim) {
         const double pact = (double)r.n_active;
         {
-          const int ntiles = (r.p + r.gdep.pt - 1) / r.gdep.pt;
           Timer t(FAM_DEPOSIT, s, 4.0 * n * (double)N * pact,
-                  16.0 * n * (double)N * ntiles + 8.0 * (double)r.gdep.nrb * pact * r.Nx);
+                  16.0 * n * ((double)N + p) + 8.0 * (double)r.gdep.nrb * pact * r.Nx);
           launch_deposit_rom(s, r.Uh, N, n, r.Zev, p, r.Nx, r.gdep, r.b.factor, r.active,
                              r.b.part, gate);
         }
