@@ -30,6 +30,13 @@ SINGLE_KERNEL = {
 }
 PEAK_FP64 = 78.6e12      # flop/s, MI355X FP64 vector (= FP64 matrix) peak
 
+# HBM bytes per launch of the deposit kernel, measured with two counter
+# passes (FETCH_SIZE, WRITE_SIZE) calibrated on a plain device copy; valid
+# only for the kernel source it was taken on
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles",
+                               "deposit_rom_kernel_twostream_deim_N1e5_p64_hbm_traffic.md")
+TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2201_05555_amd", "csrc", "pic_kernels.hip")
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -61,6 +68,24 @@ def roofline_of(ms, flops, nbytes, launches):
     return {"bound": "alu", "achieved": ach, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
             "frac": ach / (PEAK_FP64 / 1e12), "traffic": None,
             "avg_launch_us": 1e3 * ms / max(launches, 1), "launches": launches}
+
+
+def measured_traffic():
+    """Counter-measured HBM bytes per deposit launch, or None when the
+    profile is missing or the kernel source has changed since it was taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        sha = hashlib.sha256(open(TRAFFIC_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    val = src = None
+    for line in text.splitlines():
+        if line.startswith("traffic-bytes-per-launch:"):
+            val = float(line.split(":")[1])
+        elif line.startswith("source-sha256"):
+            src = line.split(":")[-1].strip()
+    return val if (val is not None and src == sha) else None
 
 
 def cpu_baseline(w, ens, seconds):
@@ -192,6 +217,11 @@ def main():
     roof = roofline_of(d["ms"], d["flops"], d["bytes"], d["launches"])
     if roof is not None:
         roof["kernel"] = SINGLE_KERNEL[dom]
+        if dom == "deposit":
+            t = measured_traffic()
+            if t is not None:
+                roof["traffic"] = t
+                roof["algorithmic_bytes_per_launch"] = d["bytes"] / max(d["launches"], 1)
         roof["ms_per_step"] = d["ms"] / a.steps
     fom_roof = roofline_of(ms_push, fl_push, by_push, n_push)
 
