@@ -1332,11 +1332,11 @@ void launch_dense_indicator(hipStream_t s, const double* colsq, const cplx* g, i
 //    the three-term recurrence of the leading principal minors of T - x I
 //    (no division; power-of-two rescaling every two terms): 256 / d lanes
 //    per eigenvalue.
-//  * Eigenvector j by inverse iteration (banded Gaussian elimination with
-//    partial pivoting on T - lambda_j I, two passes) in lane j of the first
-//    wavefront; back-transform through the stored reflectors and the Gram
-//    matrix of the vectors by groups of lanes, one group per vector; Cholesky
-//    QR to orthonormalise in order.
+//  * Eigenvector j of T from a twisted factorization of T - lambda_j I (the
+//    top-down and bottom-up pivots on two wavefronts at once, lane j each;
+//    the twist at the smallest |gamma|); back-transform through the stored
+//    reflectors and the Gram matrix of the vectors by groups of lanes, one
+//    group per vector; Cholesky QR to orthonormalise in order.
 // Output: lam (d, decreasing), V (n x d, column-major); bit 32 of flags[0]
 // is set if the vectors are rank deficient.
 // ---------------------------------------------------------------------------

@@ -46,69 +46,80 @@ __global__ void __launch_bounds__(512) deposit_x_kernel(const double* __restrict
 // ---------------------------------------------------------------------------
 // Reduced-model deposit: positions are reconstructed on the fly,
 // x_{l,i} = Re( sum_k U~[l,k] Z~[k,i] ), and never written to memory.
-// One thread per particle row holds its n complex basis entries in
-// registers; the coefficient tile is broadcast from LDS.  Columns whose
-// `active` flag is 0 are skipped (frozen fixed-point columns).
+// A thread holds the n complex basis entries of DEP_ROWS particle rows in
+// registers (loaded together, at clamped indices and masked, so that no
+// load sits behind a branch); the parameter loop runs outside the rows, so
+// one set of coefficient loads (uniform: scalar loads) serves every row of
+// the thread and the LDS queue holds nothing but the histogram atomics.
+// Parameters whose `active` flag is 0 are skipped (frozen fixed-point
+// columns).  Small column counts run 16 wavefronts per block: one block per
+// CU is the usual launch, and the LDS atomics need that many in flight.
 // ---------------------------------------------------------------------------
 template <int NC>
-__global__ void __launch_bounds__(512) deposit_rom_kernel(
+constexpr int deposit_rom_threads() {
+  return (NC <= 8) ? 1024 : 512;
+}
+template <int NC>
+constexpr int deposit_rom_rows() {
+  return (NC <= 16) ? 2 : 1;
+}
+
+template <int NC>
+__global__ void __launch_bounds__(deposit_rom_threads<NC>()) deposit_rom_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx, int pt,
     int rpb, const double* __restrict__ factor, const int* __restrict__ active,
     double* __restrict__ part, const int* __restrict__ gate) {
   if (gate && gate[0] == 0) return;
-  // parameters in flight per thread (independent chains), within registers
-  constexpr int ILP = (NC <= 8) ? 4 : (NC <= 16) ? 2 : 1;
-  extern __shared__ double smem[];
-  double* hist = smem;                                  // pt * Nx
-  cplx* Zs = reinterpret_cast<cplx*>(smem + pt * Nx);   // pt * NC
-  double* fs = reinterpret_cast<double*>(Zs + pt * NC);  // pt factors
-  int* act = reinterpret_cast<int*>(fs + pt);            // pt flags
+  constexpr int R = deposit_rom_rows<NC>();
+  extern __shared__ double hist[];  // pt * Nx
   const int rb = blockIdx.x;
   const int p0 = blockIdx.y * pt;
   const int np = min(pt, p - p0);
   for (int t = threadIdx.x; t < np * Nx; t += blockDim.x) hist[t] = 0.0;
-  for (int t = threadIdx.x; t < np * NC; t += blockDim.x) {
-    int i = t / NC, k = t % NC;
-    Zs[t] = (k < n) ? Z[(size_t)(p0 + i) * n + k] : mk(0.0, 0.0);
-  }
-  for (int i = threadIdx.x; i < np; i += blockDim.x) {
-    fs[i] = factor[p0 + i];
-    act[i] = active ? active[p0 + i] : 1;
-  }
   __syncthreads();
   const int r0 = rb * rpb;
   const int r1 = min(N, r0 + rpb);
-  for (int l = r0 + threadIdx.x; l < r1; l += blockDim.x) {
-    cplx u[NC];
+  const int bs = blockDim.x;
+  for (int lb = r0; lb < r1; lb += R * bs) {
+    cplx u[R][NC];
+    bool ok[R];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) u[k] = (k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
-    // ILP parameters at a time: their position sums, cell lookups and
-    // histogram updates are independent and interleave
-    for (int i0 = 0; i0 < np; i0 += ILP) {
-      double x0[ILP], x1[ILP];
+    for (int r = 0; r < R; ++r) {
+      const int l = lb + r * bs + (int)threadIdx.x;
+      ok[r] = l < r1;
+      const int lc = min(l, r1 - 1);
 #pragma unroll
-      for (int q = 0; q < ILP; ++q) {
-        x0[q] = 0.0;
-        x1[q] = 0.0;
+      for (int k = 0; k < NC; ++k) {
+        const cplx v = U[(size_t)min(k, n - 1) * N + lc];
+        const double m = (k < n) ? 1.0 : 0.0;  // columns k >= n are zero
+        u[r][k] = mk(v.re * m, v.im * m);
       }
+    }
+    for (int i = 0; i < np; ++i) {
+      if (active && !active[p0 + i]) continue;
+      cplx z[NC];
 #pragma unroll
-      for (int q = 0; q < ILP; ++q) {
-        const cplx* zi = Zs + min(i0 + q, np - 1) * NC;
+      for (int k = 0; k < NC; ++k) {
+        const cplx a = Z[(size_t)(p0 + i) * n + min(k, n - 1)];
+        z[k] = (k < n) ? a : mk(0.0, 0.0);
+      }
+      const double f = factor[p0 + i];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        // two partial sums (even and odd columns), as in every kernel that
+        // locates particles, so that the cells agree bit for bit
+        double x0 = 0.0, x1 = 0.0;
 #pragma unroll
         for (int k = 0; k < NC; k += 2) {
-          x0[q] = fma(u[k].re, zi[k].re, x0[q]);
-          x0[q] = fma(-u[k].im, zi[k].im, x0[q]);
-          x1[q] = fma(u[k + 1].re, zi[k + 1].re, x1[q]);
-          x1[q] = fma(-u[k + 1].im, zi[k + 1].im, x1[q]);
+          x0 = fma(u[r][k].re, z[k].re, x0);
+          x0 = fma(-u[r][k].im, z[k].im, x0);
+          x1 = fma(u[r][k + 1].re, z[k + 1].re, x1);
+          x1 = fma(-u[r][k + 1].im, z[k + 1].im, x1);
         }
-      }
-#pragma unroll
-      for (int q = 0; q < ILP; ++q) {
-        const int i = i0 + q;
         int j;
         double th;
-        cell_of(x0[q] + x1[q], fs[min(i, np - 1)], Nx, j, th);
-        if (i < np && act[i]) {
+        cell_of(x0 + x1, f, Nx, j, th);
+        if (ok[r]) {
           const int j1 = (j + 1 == Nx) ? 0 : j + 1;
           lds_add(hist + i * Nx + j, 1.0 - th);
           lds_add(hist + i * Nx + j1, th);
@@ -118,8 +129,8 @@ __global__ void __launch_bounds__(512) deposit_rom_kernel(
   }
   __syncthreads();
   for (int t = threadIdx.x; t < np * Nx; t += blockDim.x) {
-    int i = t / Nx;
-    if (!act[i]) continue;
+    const int i = t / Nx;
+    if (active && !active[p0 + i]) continue;
     part[((size_t)rb * p + p0) * Nx + t] = hist[t];
   }
 }
@@ -135,129 +146,136 @@ __global__ void __launch_bounds__(512) deposit_rom_kernel(
 // from Phi_{j+1} = Phi_j + h e_j and the zero-mean gauge.  This is the exact
 // pseudo-inverse solution, in O(Nx).  Energy E_i = Phi^T rho / (2 m w_i).
 // ---------------------------------------------------------------------------
-__device__ inline double block_exclusive_scan(double v, double* buf) {
-  // Hillis-Steele inclusive scan over blockDim.x thread values, then shift
-  const int t = threadIdx.x;
-  buf[t] = v;
-  __syncthreads();
-  for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-    double add = (t >= o) ? buf[t - o] : 0.0;
-    __syncthreads();
-    buf[t] += add;
-    __syncthreads();
-  }
-  double incl = buf[t];
-  __syncthreads();
-  return incl - v;
+// exclusive prefix sum over the 64 lanes of a wavefront: Hillis-Steele
+// inside rows of 16 by row shifts, the row totals carried by the row
+// broadcasts of lanes 15 and 31, then the inclusive sums moved up one lane
+__device__ __forceinline__ double wave_exclusive_scan(double v) {
+  v += dpp64<0x111, 0xf>(v);  // row_shr:1
+  v += dpp64<0x112, 0xf>(v);  // row_shr:2
+  v += dpp64<0x114, 0xf>(v);  // row_shr:4
+  v += dpp64<0x118, 0xf>(v);  // row_shr:8
+  v += dpp64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const double up = __shfl_up(v, 1, 64);
+  return ((threadIdx.x & 63) == 0) ? 0.0 : up;
 }
 
-__global__ void __launch_bounds__(256) poisson_kernel(
+constexpr int POISSON_THREADS = 512;
+constexpr int POISSON_PER_LANE = SYMROM_MAX_NX / 64;  // nodes per lane in the solve
+
+__global__ void __launch_bounds__(POISSON_THREADS) poisson_kernel(
     const double* __restrict__ part, int nrb, int p, int Nx, const double* __restrict__ qw,
     const double* __restrict__ h, const double* __restrict__ mw, const int* __restrict__ active,
     double* __restrict__ rho_out, double* __restrict__ phi_out, double* __restrict__ e_out,
     double* __restrict__ energy_out, const int* __restrict__ gate) {
   if (gate && gate[0] == 0) return;
-  __shared__ double buf[256];
-  __shared__ double red[8];
+  __shared__ double buf[POISSON_THREADS];
   __shared__ double rho_s[SYMROM_MAX_NX];
-  __shared__ double e_s[SYMROM_MAX_NX];
   const int i = blockIdx.x;
   if (active && !active[i]) return;
-  const int per = (Nx + blockDim.x - 1) / blockDim.x;  // nodes per thread (contiguous)
-  const int j0 = threadIdx.x * per;
   const double hi = h[i];
   const double qwi = qw[i];
   // 1. sums of the unit weights over the nrb row-block partials
-  //    part[(k * p + i) * Nx + j]: G threads per node take every G-th block,
-  //    two chains each, combined in a fixed order
-  {
-    const int G = (Nx <= 64) ? 4 : (Nx <= 128) ? 2 : 1;
-    for (int t = threadIdx.x; t < G * Nx; t += blockDim.x) {
-      const int j = t % Nx, g = t / Nx;
-      // eight partials in flight per thread, summed in block order
-      double acc8[8];
+  //    part[(k * p + i) * Nx + j]: G = blockDim / Nx threads per node take
+  //    every G-th block with all their loads in flight, then the G sums of a
+  //    node are added in group order
+  const int G = max(1, (int)blockDim.x / Nx);
+  for (int t = threadIdx.x; t < G * Nx; t += blockDim.x) {
+    const int j = t % Nx, g = t / Nx;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = g; k < nrb; k += 16 * G) {
+      // loads at clamped indices (no branches), masked when added
+      double v[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc8[u] = 0.0;
-      int k = g;
-      for (; k + 7 * G < nrb; k += 8 * G) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc8[u] += part[((size_t)(k + u * G) * p + i) * Nx + j];
+      for (int u = 0; u < 16; ++u) {
+        const int kc = min(k + u * G, nrb - 1);
+        v[u] = part[((size_t)kc * p + i) * Nx + j];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int kq = k + u * G;
-        if (kq < nrb) acc8[u] += part[((size_t)kq * p + i) * Nx + j];
-      }
-      const double s01 = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) +
-                         ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
-      if (G == 1)
-        rho_s[j] = qwi * s01 + hi;
-      else
-        buf[g * Nx + j] = s01;
+      for (int u = 0; u < 16; ++u) acc[u & 3] += (k + u * G < nrb) ? v[u] : 0.0;
     }
-    __syncthreads();
-    if (G > 1) {
-      for (int j = threadIdx.x; j < Nx; j += blockDim.x) {
+    const double sg = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    if (G == 1)
+      rho_s[j] = qwi * sg + hi;
+    else
+      buf[t] = sg;
+  }
+  __syncthreads();
+  // the solve is one wavefront, nodes j0 .. j0 + per - 1 in lane `lane`
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  const int per = (Nx + 63) / 64;
+  const int j0 = lane * per;
+  double rho[POISSON_PER_LANE];
+  double loc = 0.0;
+#pragma unroll
+  for (int q = 0; q < POISSON_PER_LANE; ++q) {
+    const int j = j0 + q;
+    rho[q] = 0.0;
+    if (q < per && j < Nx) {
+      if (G > 1) {
         double t2 = buf[j];
         for (int g = 1; g < G; ++g) t2 += buf[g * Nx + j];
-        rho_s[j] = qwi * t2 + hi;
+        rho[q] = qwi * t2 + hi;
+      } else {
+        rho[q] = rho_s[j];
       }
-      __syncthreads();
     }
+    loc += rho[q];
   }
-  // 2. zero-mean charge and its prefix sums
-  double loc = 0.0;
-  for (int q = 0; q < per; ++q)
-    if (j0 + q < Nx) loc += rho_s[j0 + q];
-  const double mean_rho = block_sum(loc, red) / Nx;
+  // 2. zero-mean charge, S_j = its inclusive prefix sums, e_j = mean(S) - S_j
+  const double mean_rho = wave_sum64(loc) / Nx;
   double tot = 0.0;
-  for (int q = 0; q < per; ++q)
-    if (j0 + q < Nx) tot += rho_s[j0 + q] - mean_rho;
-  double run = block_exclusive_scan(tot, buf);
+#pragma unroll
+  for (int q = 0; q < POISSON_PER_LANE; ++q)
+    if (q < per && j0 + q < Nx) tot += rho[q] - mean_rho;
+  double run = wave_exclusive_scan(tot);
+  double S[POISSON_PER_LANE];
   double ssum = 0.0;
-  for (int q = 0; q < per; ++q) {
-    int j = j0 + q;
-    if (j < Nx) {
-      run += rho_s[j] - mean_rho;
-      e_s[j] = run;  // S_j for now
+#pragma unroll
+  for (int q = 0; q < POISSON_PER_LANE; ++q) {
+    S[q] = 0.0;
+    if (q < per && j0 + q < Nx) {
+      run += rho[q] - mean_rho;
+      S[q] = run;
       ssum += run;
     }
   }
-  const double mean_S = block_sum(ssum, red) / Nx;
+  const double mean_S = wave_sum64(ssum) / Nx;
   double etot = 0.0;
-  for (int q = 0; q < per; ++q) {
-    int j = j0 + q;
-    if (j < Nx) {
-      e_s[j] = mean_S - e_s[j];
-      etot += e_s[j];
-    }
+#pragma unroll
+  for (int q = 0; q < POISSON_PER_LANE; ++q) {
+    S[q] = mean_S - S[q];  // e_j
+    if (q < per && j0 + q < Nx) etot += S[q];
   }
   // 3. potential: Phi_j = h * sum_{k<j} e_k, then the zero-mean gauge
-  double prun = block_exclusive_scan(etot, buf);
-  double phi_loc[8];
+  double prun = wave_exclusive_scan(etot);
+  double phi[POISSON_PER_LANE];
   double psum = 0.0;
-  for (int q = 0; q < per; ++q) {
-    int j = j0 + q;
-    if (j < Nx) {
-      phi_loc[q] = hi * prun;
-      prun += e_s[j];
-      psum += phi_loc[q];
+#pragma unroll
+  for (int q = 0; q < POISSON_PER_LANE; ++q) {
+    phi[q] = 0.0;
+    if (q < per && j0 + q < Nx) {
+      phi[q] = hi * prun;
+      prun += S[q];
+      psum += phi[q];
     }
   }
-  const double mean_phi = block_sum(psum, red) / Nx;
+  const double mean_phi = wave_sum64(psum) / Nx;
   double en = 0.0;
-  for (int q = 0; q < per; ++q) {
-    int j = j0 + q;
-    if (j < Nx) {
-      double ph = phi_loc[q] - mean_phi;
-      en += ph * rho_s[j];
+#pragma unroll
+  for (int q = 0; q < POISSON_PER_LANE; ++q) {
+    const int j = j0 + q;
+    if (q < per && j < Nx) {
+      const double ph = phi[q] - mean_phi;
+      en += ph * rho[q];
       if (phi_out) phi_out[(size_t)i * Nx + j] = ph;
-      if (rho_out) rho_out[(size_t)i * Nx + j] = rho_s[j];
-      if (e_out) e_out[(size_t)i * Nx + j] = e_s[j];
+      if (rho_out) rho_out[(size_t)i * Nx + j] = rho[q];
+      if (e_out) e_out[(size_t)i * Nx + j] = S[q];
     }
   }
-  const double E = block_sum(en, red);
-  if (threadIdx.x == 0 && energy_out) energy_out[i] = E / (2.0 * mw[i]);
+  const double E = wave_sum64(en);
+  if (lane == 0 && energy_out) energy_out[i] = E / (2.0 * mw[i]);
 }
 
 
@@ -393,12 +411,11 @@ void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* 
                         const int* gate) {
   dim3 grid(g.nrb, (p + g.pt - 1) / g.pt);
   int nc = (n <= 16) ? nc_even(n) : 32;
-  size_t sh = (size_t)g.pt * Nx * sizeof(double) + (size_t)g.pt * nc * sizeof(cplx) +
-              (size_t)g.pt * (sizeof(double) + sizeof(int));
+  size_t sh = (size_t)g.pt * Nx * sizeof(double);
 #define DEP(NCV)                                                                              \
   ALLOW_BIG_LDS(deposit_rom_kernel<NCV>);                                                    \
-  hipLaunchKernelGGL(deposit_rom_kernel<NCV>, grid, dim3(512), sh, s, U, N, n, Z, p, Nx, g.pt, \
-                     g.rpb, factor, active, part, gate)
+  hipLaunchKernelGGL(deposit_rom_kernel<NCV>, grid, dim3(deposit_rom_threads<NCV>()), sh, s, U, \
+                     N, n, Z, p, Nx, g.pt, g.rpb, factor, active, part, gate)
   switch (nc) {
     case 4: DEP(4); break;
     case 6: DEP(6); break;
@@ -414,7 +431,8 @@ void launch_poisson(hipStream_t s, const double* part, int nrb, int p, int Nx, c
                     const double* h, const double* mw, const int* active, double* rho,
                     double* phi, double* e, double* energy, const int* gate) {
   // one block per parameter sums its row-block partials and solves
-  hipLaunchKernelGGL(poisson_kernel, dim3(p), dim3(256), 0, s, part, nrb, p, Nx, qw, h, mw, active,
+  hipLaunchKernelGGL(poisson_kernel, dim3(p), dim3(POISSON_THREADS), 0, s, part, nrb, p, Nx, qw, h,
+                     mw, active,
                      rho, phi, e, energy, gate);
 }
 
