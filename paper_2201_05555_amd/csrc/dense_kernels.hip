@@ -298,24 +298,29 @@ __device__ void bk_jacobi(cplx* A, cplx* V, double* lam, int m, cplx* rot /*3*m/
 // nothing would be dropped and S~^+ = S~^{-1} is formed from the Cholesky
 // factor; otherwise the Jacobi eigendecomposition is used.
 // sigma2 receives the eigenvalues (decreasing) when the eigen path runs, else
-// is left untouched.  Requires n <= 32.
+// is left untouched.  Requires n <= 32.  Z is copied to LDS first (one
+// coalesced pass), so that no loop waits on global loads.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(DTPB) dense_spinv_kernel(const cplx* __restrict__ Z, int n, int p,
                                                            double rtol, cplx* __restrict__ Q,
                                                            double* __restrict__ sigma2,
                                                            int* __restrict__ flags) {
-  __shared__ cplx S[32 * 32];
-  __shared__ cplx R[32 * 32];
-  __shared__ cplx Ri[32 * 32];
+  extern __shared__ cplx sm[];
+  cplx* Zs = sm;          // n x p
+  cplx* S = Zs + n * p;   // n x n
+  cplx* R = S + n * n;
+  cplx* Ri = R + n * n;
   __shared__ cplx rot[3 * 17 + 3];
   __shared__ int pr[40];
   __shared__ double lam[32];
   __shared__ double trs;
+  for (int t = threadIdx.x; t < n * p; t += blockDim.x) Zs[t] = Z[t];
+  __syncthreads();
   // S~ = Z~ Z~^*
   for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
     int a = t % n, b = t / n;
     cplx s = mk(0.0, 0.0);
-    for (int i = 0; i < p; ++i) cfma(s, Z[(size_t)i * n + a], cconj(Z[(size_t)i * n + b]));
+    for (int i = 0; i < p; ++i) cfma(s, Zs[i * n + a], cconj(Zs[i * n + b]));
     S[t] = s;
   }
   __syncthreads();
@@ -353,7 +358,7 @@ __global__ void __launch_bounds__(DTPB) dense_spinv_kernel(const cplx* __restric
   for (int t = threadIdx.x; t < p * n; t += blockDim.x) {
     int i = t % p, b = t / p;
     cplx s = mk(0.0, 0.0);
-    for (int a = 0; a < n; ++a) cfma(s, cconj(Z[(size_t)i * n + a]), R[b * n + a]);
+    for (int a = 0; a < n; ++a) cfma(s, cconj(Zs[i * n + a]), R[b * n + a]);
     Q[(size_t)b * p + i] = s;
   }
 }
@@ -361,18 +366,27 @@ __global__ void __launch_bounds__(DTPB) dense_spinv_kernel(const cplx* __restric
 // After the full-gradient projection g~ = U~^* G~ (n x p): k1 = -i g~ and the
 // row-combination matrices of xi = (dt/2) X~ with X~ = -i (P~ - U~ T),
 // T = g~ Q (n x n):  xi = P~ (-i dt/2 I) + U~ (i dt/2 T).
+// g and Q are copied to LDS first (one coalesced pass).
 __global__ void __launch_bounds__(DTPB) dense_xfinish_kernel(const cplx* __restrict__ g,
                                                              const cplx* __restrict__ Q, int n,
                                                              int p, double dt, cplx* __restrict__ k1,
                                                              cplx* __restrict__ MP,
                                                              cplx* __restrict__ MU) {
-  if (k1)
-    for (int t = threadIdx.x; t < n * p; t += blockDim.x) k1[t] = mk(g[t].im, -g[t].re);
+  extern __shared__ cplx sm[];
+  cplx* gs = sm;          // n x p
+  cplx* Qs = gs + n * p;  // p x n
+  for (int t = threadIdx.x; t < n * p; t += blockDim.x) {
+    const cplx gv = g[t];
+    gs[t] = gv;
+    Qs[t] = Q[t];
+    if (k1) k1[t] = mk(gv.im, -gv.re);
+  }
+  __syncthreads();
   const double h = 0.5 * dt;
   for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
     int a = t % n, b = t / n;
     cplx s = mk(0.0, 0.0);
-    for (int i = 0; i < p; ++i) cfma(s, g[(size_t)i * n + a], Q[(size_t)b * p + i]);
+    for (int i = 0; i < p; ++i) cfma(s, gs[i * n + a], Qs[b * p + i]);
     MU[t] = mk(-h * s.im, h * s.re);  // i h T
     MP[t] = (a == b) ? mk(0.0, -h) : mk(0.0, 0.0);
   }
@@ -562,10 +576,14 @@ __global__ void __launch_bounds__(DTPB) dense_chol_kernel(const cplx* __restrict
                                                           cplx* __restrict__ Rinv,
                                                           cplx* __restrict__ Z, int p,
                                                           int* __restrict__ flags) {
-  __shared__ cplx G[32 * 32];
-  __shared__ cplx R[32 * 32];
-  __shared__ cplx Ri[32 * 32];
+  extern __shared__ cplx sm[];
+  cplx* G = sm;          // n x n
+  cplx* R = G + n * n;
+  cplx* Ri = R + n * n;
+  cplx* Zs = Ri + n * n;  // n x p (when Z is given)
   for (int t = threadIdx.x; t < n * n; t += blockDim.x) G[t] = Gram[t];
+  if (Z)
+    for (int t = threadIdx.x; t < n * p; t += blockDim.x) Zs[t] = Z[t];
   __syncthreads();
   if (bk_chol(G, R, n, 0.0)) {
     if (threadIdx.x == 0 && flags) flags[0] |= 2;
@@ -574,15 +592,12 @@ __global__ void __launch_bounds__(DTPB) dense_chol_kernel(const cplx* __restrict
   bk_triu_inv(R, Ri, n);
   for (int t = threadIdx.x; t < n * n; t += blockDim.x) Rinv[t] = Ri[t];
   if (Z) {
-    // Z <- R Z, column by column (each thread owns columns)
-    for (int i = threadIdx.x; i < p; i += blockDim.x) {
-      cplx zc[32];
-      for (int a = 0; a < n; ++a) zc[a] = Z[(size_t)i * n + a];
-      for (int a = 0; a < n; ++a) {
-        cplx s = mk(0.0, 0.0);
-        for (int b = a; b < n; ++b) cfma(s, R[b * n + a], zc[b]);
-        Z[(size_t)i * n + a] = s;
-      }
+    // Z <- R Z, one entry per thread (R upper triangular)
+    for (int t = threadIdx.x; t < n * p; t += blockDim.x) {
+      const int a = t % n, i = t / n;
+      cplx s = mk(0.0, 0.0);
+      for (int b = a; b < n; ++b) cfma(s, R[b * n + a], Zs[i * n + b]);
+      Z[t] = s;
     }
   }
 }
@@ -602,36 +617,53 @@ __global__ void __launch_bounds__(DTPB) dense_fp_update_kernel(
     double tol, int fixed, int linear_part, int* __restrict__ counters) {
   // nothing left to iterate: a speculative launch after convergence
   if (counters[0] == 0) return;
+  // LDS: C12 (2 n x n), Zeval and the new k (n x p each), then the squared
+  // moduli of the update and of the new k per entry (n x p doubles each)
+  extern __shared__ cplx sm[];
+  cplx* Cs = sm;
+  cplx* zes = Cs + 2 * n * n;
+  cplx* kns = zes + n * p;
+  double* dq = reinterpret_cast<double*>(kns + n * p);
+  double* kq = dq + n * p;
   __shared__ int nact, nstall;
   if (threadIdx.x == 0) {
     nact = 0;
     nstall = 0;
   }
+  if (linear_part)
+    for (int t = threadIdx.x; t < 2 * n * n; t += blockDim.x) Cs[t] = C12[t];
+  for (int t = threadIdx.x; t < n * p; t += blockDim.x) zes[t] = Zeval[t];
   __syncthreads();
+  // one thread per entry (a, i) of an active column
+  for (int t = threadIdx.x; t < n * p; t += blockDim.x) {
+    const int a = t % n, i = t / n;
+    if (!active[i]) continue;
+    const cplx* ze = zes + i * n;
+    cplx g = gF[t];
+    if (linear_part) {
+      cplx s = mk(0.0, 0.0);
+      for (int b = 0; b < n; ++b) {
+        cfma(s, Cs[b * n + a], ze[b]);
+        cfma(s, cscale(cconj(Cs[n * n + b * n + a]), -1.0), cconj(ze[b]));
+      }
+      g = cadd(g, cscale(s, 0.5));
+    }
+    const cplx knew = mk(g.im, -g.re);  // -i g
+    const cplx d = csub(knew, k[t]);
+    dq[t] = cabs2(d);
+    kq[t] = cabs2(knew);
+    kns[t] = knew;
+    k[t] = knew;
+    ZG[t] = ze[a];
+  }
+  __syncthreads();
+  // per column: the relative update (moduli summed in entry order)
   for (int i = threadIdx.x; i < p; i += blockDim.x) {
     if (!active[i]) continue;
     double dn = 0.0, kn = 0.0;
-    const cplx* ze = Zeval + (size_t)i * n;
-    cplx kn_col[32];
     for (int a = 0; a < n; ++a) {
-      cplx g = gF[(size_t)i * n + a];
-      if (linear_part) {
-        cplx s = mk(0.0, 0.0);
-        for (int b = 0; b < n; ++b) {
-          cfma(s, C12[b * n + a], ze[b]);
-          cfma(s, cscale(cconj(C12[n * n + b * n + a]), -1.0), cconj(ze[b]));
-        }
-        g = cadd(g, cscale(s, 0.5));
-      }
-      cplx knew = mk(g.im, -g.re);  // -i g
-      cplx d = csub(knew, k[(size_t)i * n + a]);
-      dn += cabs2(d);
-      kn += cabs2(knew);
-      kn_col[a] = knew;
-    }
-    for (int a = 0; a < n; ++a) {
-      k[(size_t)i * n + a] = kn_col[a];
-      ZG[(size_t)i * n + a] = ze[a];
+      dn += dq[i * n + a];
+      kn += kq[i * n + a];
     }
     bool done = false;
     if (!fixed) {
@@ -647,8 +679,8 @@ __global__ void __launch_bounds__(DTPB) dense_fp_update_kernel(
     } else {
       atomicAdd(&nact, 1);
       for (int a = 0; a < n; ++a) {
-        cplx z0 = Z0[(size_t)i * n + a];
-        cplx kk = kn_col[a];
+        const cplx z0 = Z0[(size_t)i * n + a];
+        const cplx kk = kns[i * n + a];
         Zeval[(size_t)i * n + a] = mk(z0.re + 0.5 * dt * kk.re, z0.im + 0.5 * dt * kk.im);
       }
     }
@@ -778,12 +810,17 @@ static inline unsigned nblk(size_t n) { return (unsigned)((n + 255) / 256); }
 
 void launch_dense_spinv(hipStream_t s, const cplx* Z, int n, int p, double rtol, cplx* Q,
                         double* sigma2, int* flags) {
-  hipLaunchKernelGGL(dense_spinv_kernel, dim3(1), dim3(DTPB), 0, s, Z, n, p, rtol, Q, sigma2,
+  const size_t sh = (size_t)(n * p + 3 * n * n) * sizeof(cplx);
+  ALLOW_BIG_LDS(dense_spinv_kernel);
+  hipLaunchKernelGGL(dense_spinv_kernel, dim3(1), dim3(DTPB), sh, s, Z, n, p, rtol, Q, sigma2,
                      flags);
 }
 void launch_dense_xfinish(hipStream_t s, const cplx* g, const cplx* Q, int n, int p, double dt,
                           cplx* k1, cplx* MP, cplx* MU) {
-  hipLaunchKernelGGL(dense_xfinish_kernel, dim3(1), dim3(DTPB), 0, s, g, Q, n, p, dt, k1, MP, MU);
+  const size_t sh = (size_t)(2 * n * p) * sizeof(cplx);
+  ALLOW_BIG_LDS(dense_xfinish_kernel);
+  hipLaunchKernelGGL(dense_xfinish_kernel, dim3(1), dim3(DTPB), sh, s, g, Q, n, p, dt, k1, MP,
+                     MU);
 }
 void launch_dense_cayley(hipStream_t s, const cplx* Gram, int n, cplx* A_out, cplx* MU,
                          cplx* MX, int* flags) {
@@ -807,13 +844,17 @@ void launch_dense_tangent2(hipStream_t s, const cplx* Gram3, const cplx* C0x, in
 }
 void launch_dense_chol(hipStream_t s, const cplx* Gram, int n, cplx* Rinv, cplx* Z, int p,
                        int* flags) {
-  hipLaunchKernelGGL(dense_chol_kernel, dim3(1), dim3(DTPB), 0, s, Gram, n, Rinv, Z, p, flags);
+  const size_t sh = (size_t)(3 * n * n + (Z ? n * p : 0)) * sizeof(cplx);
+  ALLOW_BIG_LDS(dense_chol_kernel);
+  hipLaunchKernelGGL(dense_chol_kernel, dim3(1), dim3(DTPB), sh, s, Gram, n, Rinv, Z, p, flags);
 }
 void launch_dense_fp_update(hipStream_t s, const cplx* gF, const cplx* C12, int n, int p,
                             const cplx* Z0, cplx* Zeval, cplx* ZG, cplx* k, double* prev,
                             int* active, double dt, double tol, int fixed, int linear_part,
                             int* counters) {
-  hipLaunchKernelGGL(dense_fp_update_kernel, dim3(1), dim3(DTPB), 0, s, gF, C12, n, p, Z0, Zeval,
+  const size_t sh = (size_t)(2 * n * n + 2 * n * p) * sizeof(cplx) + 2 * (size_t)n * p * sizeof(double);
+  ALLOW_BIG_LDS(dense_fp_update_kernel);
+  hipLaunchKernelGGL(dense_fp_update_kernel, dim3(1), dim3(DTPB), sh, s, gF, C12, n, p, Z0, Zeval,
                      ZG, k, prev, active, dt, tol, fixed, linear_part, counters);
 }
 void launch_dense_finish_z(hipStream_t s, const cplx* Z0, const cplx* k, int n, int p, double dt,
