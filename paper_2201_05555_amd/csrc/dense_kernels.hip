@@ -808,12 +808,17 @@ __global__ void z_to_real_kernel(const cplx* Zc, int n, int p, double* Z) {
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(size_t n) { return (unsigned)((n + 255) / 256); }
 
+// Kernels whose work is a chain of small steps separated by block barriers
+// run as one wavefront for small ranks (its barriers cost next to nothing);
+// larger ranks use four wavefronts.
+static int dense_chain_threads(int n) { return (n <= 8) ? 64 : DTPB; }
+
 void launch_dense_spinv(hipStream_t s, const cplx* Z, int n, int p, double rtol, cplx* Q,
                         double* sigma2, int* flags) {
   const size_t sh = (size_t)(n * p + 3 * n * n) * sizeof(cplx);
   ALLOW_BIG_LDS(dense_spinv_kernel);
-  hipLaunchKernelGGL(dense_spinv_kernel, dim3(1), dim3(DTPB), sh, s, Z, n, p, rtol, Q, sigma2,
-                     flags);
+  hipLaunchKernelGGL(dense_spinv_kernel, dim3(1), dim3(dense_chain_threads(n)), sh, s, Z, n, p,
+                     rtol, Q, sigma2, flags);
 }
 void launch_dense_xfinish(hipStream_t s, const cplx* g, const cplx* Q, int n, int p, double dt,
                           cplx* k1, cplx* MP, cplx* MU) {
@@ -826,27 +831,28 @@ void launch_dense_cayley(hipStream_t s, const cplx* Gram, int n, cplx* A_out, cp
                          cplx* MX, int* flags) {
   size_t sh = (size_t)(10 * n * n) * sizeof(cplx);
   ALLOW_BIG_LDS(dense_cayley_kernel);
-  hipLaunchKernelGGL(dense_cayley_kernel, dim3(1), dim3(DTPB), sh, s, Gram, n, A_out, MU, MX,
-                     flags);
+  hipLaunchKernelGGL(dense_cayley_kernel, dim3(1), dim3(dense_chain_threads(n)), sh, s, Gram, n,
+                     A_out, MU, MX, flags);
 }
 void launch_dense_tangent1(hipStream_t s, const cplx* A, const cplx* Gram2, int n, cplx* M1,
                            cplx* M2, cplx* M3, cplx* C0x_out, int* flags) {
   size_t sh = (size_t)7 * n * n * sizeof(cplx);
   ALLOW_BIG_LDS(dense_tangent1_kernel);
-  hipLaunchKernelGGL(dense_tangent1_kernel, dim3(1), dim3(DTPB), sh, s, A, Gram2, n, M1, M2, M3,
-                     C0x_out, flags);
+  hipLaunchKernelGGL(dense_tangent1_kernel, dim3(1), dim3(dense_chain_threads(n)), sh, s, A, Gram2,
+                     n, M1, M2, M3, C0x_out, flags);
 }
 void launch_dense_tangent2(hipStream_t s, const cplx* Gram3, const cplx* C0x, int n, double dt,
                            cplx* M1, cplx* M2, int* flags) {
   size_t sh = (size_t)3 * n * n * sizeof(cplx);
-  hipLaunchKernelGGL(dense_tangent2_kernel, dim3(1), dim3(DTPB), sh, s, Gram3, C0x, n, dt, M1, M2,
-                     flags);
+  hipLaunchKernelGGL(dense_tangent2_kernel, dim3(1), dim3(dense_chain_threads(n)), sh, s, Gram3,
+                     C0x, n, dt, M1, M2, flags);
 }
 void launch_dense_chol(hipStream_t s, const cplx* Gram, int n, cplx* Rinv, cplx* Z, int p,
                        int* flags) {
   const size_t sh = (size_t)(3 * n * n + (Z ? n * p : 0)) * sizeof(cplx);
   ALLOW_BIG_LDS(dense_chol_kernel);
-  hipLaunchKernelGGL(dense_chol_kernel, dim3(1), dim3(DTPB), sh, s, Gram, n, Rinv, Z, p, flags);
+  hipLaunchKernelGGL(dense_chol_kernel, dim3(1), dim3(dense_chain_threads(n)), sh, s, Gram, n,
+                     Rinv, Z, p, flags);
 }
 void launch_dense_fp_update(hipStream_t s, const cplx* gF, const cplx* C12, int n, int p,
                             const cplx* Z0, cplx* Zeval, cplx* ZG, cplx* k, double* prev,

@@ -228,10 +228,17 @@ __global__ void __launch_bounds__(256) reduce_partials_kernel(const cplx* __rest
   const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (o >= nout) return;
   double re = 0.0, im = 0.0;
-  for (int k = lane; k < nkb; k += 64) {
-    const cplx v = part[(size_t)k * nout + o];
-    re += v.re;
-    im += v.im;
+  // eight partials of a lane in flight at once (clamped loads, masked adds)
+  for (int k0 = lane; k0 < nkb; k0 += 8 * 64) {
+    cplx v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)min(k0 + 64 * u, nkb - 1) * nout + o];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = k0 + 64 * u < nkb;
+      re += in ? v[u].re : 0.0;
+      im += in ? v[u].im : 0.0;
+    }
   }
   for (int s = 32; s > 0; s >>= 1) {
     re += __shfl_xor(re, s, 64);
@@ -437,10 +444,17 @@ __global__ void __launch_bounds__(256) reduce_partials2_kernel(const cplx* __res
   const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (o >= nout) return;
   double re = 0.0, im = 0.0;
-  for (int k = lane; k < nkb; k += 64) {
-    const cplx v = part[(size_t)k * rec + o];
-    re += v.re;
-    im += v.im;
+  // eight partials of a lane in flight at once (clamped loads, masked adds)
+  for (int k0 = lane; k0 < nkb; k0 += 8 * 64) {
+    cplx v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)min(k0 + 64 * u, nkb - 1) * rec + o];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = k0 + 64 * u < nkb;
+      re += in ? v[u].re : 0.0;
+      im += in ? v[u].im : 0.0;
+    }
   }
   for (int s = 32; s > 0; s >>= 1) {
     re += __shfl_xor(re, s, 64);
@@ -1294,7 +1308,14 @@ __global__ void __launch_bounds__(256) reduce_gram_block_kernel(const double* __
   const int nout = a * b;
   if (o >= nout) return;
   double s = 0.0;
-  for (int k = lane; k < nkb; k += 64) s += part[(size_t)k * nout + o];
+  // eight partials of a lane in flight at once (clamped loads, masked adds)
+  for (int k0 = lane; k0 < nkb; k0 += 8 * 64) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)min(k0 + 64 * u, nkb - 1) * nout + o];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += (k0 + 64 * u < nkb) ? v[u] : 0.0;
+  }
   for (int w = 32; w > 0; w >>= 1) s += __shfl_xor(s, w, 64);
   if (lane == 0) {
     const int ia = o % a, ib = o / a;
