@@ -411,8 +411,34 @@ __global__ void __launch_bounds__(512) gather_project_kernel(
       csq = fma(v, v, csq);
     }
   }
-  // the eight wavefronts in order, through LDS (the field rows are free now)
+  // the eight wavefronts summed in wave order through LDS (the field rows
+  // are free now): all partials stored at once when they fit in the space
+  // of the field table (NC <= 8), else accumulated one wavefront at a time
   __syncthreads();
+  cplx* pb = part + (size_t)blockIdx.x * rec;
+  if (NC <= 8) {
+    cplx* red = reinterpret_cast<cplx*>(smem);                  // [8][NC][64]
+    double* rcs = smem + 2 * 8 * NC * 64;                        // [8][64]
+#pragma unroll
+    for (int k = 0; k < NC; ++k) red[(w * NC + k) * 64 + lane] = acc[k];
+    rcs[w * 64 + lane] = csq;
+    __syncthreads();
+    for (int t = tid; t < ntc * n; t += 512) {
+      const int q = t / n, k = t % n;
+      cplx sw = red[k * 64 + q];
+#pragma unroll
+      for (int ww = 1; ww < 8; ++ww) sw = cadd(sw, red[(ww * NC + k) * 64 + q]);
+      pb[(size_t)(c0 + q) * n + k] = sw;
+    }
+    if (want_colsq)
+      for (int t = tid; t < ntc; t += 512) {
+        double sw = rcs[t];
+#pragma unroll
+        for (int ww = 1; ww < 8; ++ww) sw += rcs[ww * 64 + t];
+        pb[(size_t)n * p + c0 + t] = mk(sw, 0.0);
+      }
+    return;
+  }
   cplx* red = reinterpret_cast<cplx*>(smem);                  // [NC][64]
   double* rcs = smem + 2 * NC * 64;                            // [64]
   for (int ww = 0; ww < 8; ++ww) {
@@ -423,7 +449,6 @@ __global__ void __launch_bounds__(512) gather_project_kernel(
     }
     __syncthreads();
   }
-  cplx* pb = part + (size_t)blockIdx.x * rec;
   for (int t = tid; t < ntc * n; t += 512) {
     const int q = t / n, k = t % n;
     pb[(size_t)(c0 + q) * n + k] = red[k * 64 + q];
@@ -1103,10 +1128,11 @@ void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cpl
   const int nc = fused_nc(n);
   const int ntile = (p + 63) / 64;
   const int rec = n * p + p;
-  // about 256 rows per block (32 per wavefront), at most 1024 blocks,
-  // partials within part_cap
-  int nb = (N + 255) / 256;
-  if (nb > 1024) nb = 1024;
+  // two blocks per CU (512 on 256 CUs, all resident at once: the loop is
+  // bound by FP64 VALU work, so every CU gets the same share), at least 64
+  // rows per block, partials within part_cap
+  int nb = (N + 63) / 64;
+  if (nb > 512) nb = 512;
   const int cap = (int)(part_cap / (size_t)rec);
   if (nb > cap) nb = cap;
   if (nb < 1) nb = 1;
@@ -1115,8 +1141,10 @@ void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cpl
   const int tw = (p < 64) ? p : 64;
   const size_t et_bytes = (size_t)tw * Nx * sizeof(double);
   const bool et_lds = et_bytes <= 72 * 1024;
-  // the wavefront sums reuse the table's space: NC x 64 complex + 64 doubles
-  const size_t red_bytes = (size_t)nc * 64 * sizeof(cplx) + 64 * sizeof(double);
+  // the wavefront sums reuse the table's space: 8 x NC x 64 complex + 8 x 64
+  // doubles for NC <= 8, else NC x 64 complex + 64 doubles
+  const size_t red_bytes = (nc <= 8) ? (size_t)8 * nc * 64 * sizeof(cplx) + 8 * 64 * sizeof(double)
+                                     : (size_t)nc * 64 * sizeof(cplx) + 64 * sizeof(double);
   const size_t sh = (et_lds && et_bytes > red_bytes) ? et_bytes : red_bytes;
   dim3 grid(nb, ntile);
 #define GPK(NCV, ETV)                                                                          \
