@@ -950,11 +950,12 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
                              r.b.part, gate);
         }
         {
+          // the Poisson solve and the DEIM gather of the sampled rows, per parameter
           Timer t(FAM_POISSON, s);
-          launch_poisson(s, r.b.part, r.gdep.nrb, p, r.Nx, r.b.qw, r.b.h, r.b.mw, r.active,
-                         r.b.rho, r.b.phi, r.b.e, r.b.energy, gate);
+          launch_poisson_deim(s, r.b.part, r.gdep.nrb, p, r.Nx, r.b.qw, r.b.h, r.b.mw, r.active,
+                              r.b.rho, r.b.phi, r.b.e, r.b.energy, gate, r.Uh, N, n, r.Zev,
+                              r.b.factor, r.cfg.q / r.cfg.m, r.didx, r.dw, r.d_cur, r.gF);
         }
-        deim_k(r, r.Uh, r.Zev, r.active, nullptr, nullptr, gate);
       } else {
         full_gradient(r, r.Uh, r.Zev, r.active, true, false, gate);
       }

@@ -62,6 +62,13 @@ void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* 
 void launch_poisson(hipStream_t s, const double* part, int nrb, int p, int Nx, const double* qw,
                     const double* h, const double* mw, const int* active, double* rho,
                     double* phi, double* e, double* energy, const int* gate = nullptr);
+// the Poisson solve followed, per parameter, by the DEIM gather of the
+// sampled rows (gF, n x p) with the field just solved
+void launch_poisson_deim(hipStream_t s, const double* part, int nrb, int p, int Nx,
+                         const double* qw, const double* h, const double* mw, const int* active,
+                         double* rho, double* phi, double* e, double* energy, const int* gate,
+                         const cplx* U, int N, int n, const cplx* Z, const double* factor,
+                         double qm, const int* idx, const double* w, int d, cplx* gF);
 void launch_fom_push(hipStream_t s, double* X, double* V, int N, int p, int Nx, const PicGeom& g,
                      const double* factor, const double* e, double qm, double ck, double cd,
                      double* part);

@@ -163,16 +163,40 @@ __device__ __forceinline__ double wave_exclusive_scan(double v) {
 constexpr int POISSON_THREADS = 512;
 constexpr int POISSON_PER_LANE = SYMROM_MAX_NX / 64;  // nodes per lane in the solve
 
+// Optional DEIM gather (eq. grHDD with the exact potential), when dg.idx is
+// set: with the field e_i just solved, g_F[k,i] = sum_r conj(U~[I_r,k]) w_r
+// (q/m) e_i[j(x_{I_r,i})] over the d sampled rows, with the arithmetic of
+// deim_gather_kernel operation by operation (the same bits).  The rows of U~
+// at the sampled indices are loaded at the start, behind the partial sums.
+struct DeimGatherArgs {
+  const cplx* U;
+  int N, n;
+  const cplx* Z;
+  const double* factor;
+  double qm;
+  const int* idx;
+  const double* w;
+  int d;
+  cplx* gF;
+};
+
 __global__ void __launch_bounds__(POISSON_THREADS) poisson_kernel(
     const double* __restrict__ part, int nrb, int p, int Nx, const double* __restrict__ qw,
     const double* __restrict__ h, const double* __restrict__ mw, const int* __restrict__ active,
     double* __restrict__ rho_out, double* __restrict__ phi_out, double* __restrict__ e_out,
-    double* __restrict__ energy_out, const int* __restrict__ gate) {
+    double* __restrict__ energy_out, const int* __restrict__ gate, DeimGatherArgs dg) {
   if (gate && gate[0] == 0) return;
   __shared__ double buf[POISSON_THREADS];
-  __shared__ double rho_s[SYMROM_MAX_NX];
+  __shared__ double rho_s[SYMROM_MAX_NX];   // the charge, later the field (DEIM gather)
+  __shared__ cplx Ud[64 * SYMROM_MAX_NC];   // U~[I_r, k] at Ud[r * n + k]
+  __shared__ double Fw[64];
   const int i = blockIdx.x;
   if (active && !active[i]) return;
+  const bool deim = dg.idx != nullptr;
+  if (deim && threadIdx.x < dg.d) {
+    const int l = dg.idx[threadIdx.x];
+    for (int k = 0; k < dg.n; ++k) Ud[threadIdx.x * dg.n + k] = dg.U[(size_t)k * dg.N + l];
+  }
   const double hi = h[i];
   const double qwi = qw[i];
   // 1. sums of the unit weights over the nrb row-block partials
@@ -276,6 +300,41 @@ __global__ void __launch_bounds__(POISSON_THREADS) poisson_kernel(
   }
   const double E = wave_sum64(en);
   if (lane == 0 && energy_out) energy_out[i] = E / (2.0 * mw[i]);
+  if (!deim) return;
+  // the field into LDS (the charge is in registers now), then the gather;
+  // LDS accesses of this one wavefront take effect in program order
+#pragma unroll
+  for (int q = 0; q < POISSON_PER_LANE; ++q)
+    if (q < per && j0 + q < Nx) rho_s[j0 + q] = S[q];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int n = dg.n;
+  const cplx* zi = dg.Z + (size_t)i * n;
+  if (lane < dg.d) {
+    double x = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const cplx u = Ud[lane * n + k];
+      x = fma(u.re, zi[k].re, x);
+      x = fma(-u.im, zi[k].im, x);
+    }
+    int j;
+    double th;
+    cell_of(x, dg.factor[i], Nx, j, th);
+    Fw[lane] = dg.w[lane] * dg.qm * rho_s[j];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int k = lane; k < n; k += 64) {
+    cplx sk = mk(0.0, 0.0);
+    for (int r = 0; r < dg.d; ++r) {
+      const cplx u = Ud[r * n + k];
+      sk.re = fma(u.re, Fw[r], sk.re);
+      sk.im = fma(-u.im, Fw[r], sk.im);
+    }
+    dg.gF[(size_t)i * n + k] = sk;
+  }
 }
 
 
@@ -431,9 +490,19 @@ void launch_poisson(hipStream_t s, const double* part, int nrb, int p, int Nx, c
                     const double* h, const double* mw, const int* active, double* rho,
                     double* phi, double* e, double* energy, const int* gate) {
   // one block per parameter sums its row-block partials and solves
+  DeimGatherArgs dg{};
   hipLaunchKernelGGL(poisson_kernel, dim3(p), dim3(POISSON_THREADS), 0, s, part, nrb, p, Nx, qw, h,
-                     mw, active,
-                     rho, phi, e, energy, gate);
+                     mw, active, rho, phi, e, energy, gate, dg);
+}
+
+void launch_poisson_deim(hipStream_t s, const double* part, int nrb, int p, int Nx,
+                         const double* qw, const double* h, const double* mw, const int* active,
+                         double* rho, double* phi, double* e, double* energy, const int* gate,
+                         const cplx* U, int N, int n, const cplx* Z, const double* factor,
+                         double qm, const int* idx, const double* w, int d, cplx* gF) {
+  DeimGatherArgs dg{U, N, n, Z, factor, qm, idx, w, d, gF};
+  hipLaunchKernelGGL(poisson_kernel, dim3(p), dim3(POISSON_THREADS), 0, s, part, nrb, p, Nx, qw, h,
+                     mw, active, rho, phi, e, energy, gate, dg);
 }
 
 void launch_fom_push(hipStream_t s, double* X, double* V, int N, int p, int Nx, const PicGeom& g,
