@@ -950,20 +950,20 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
                              r.b.part, gate);
         }
         {
-          // the Poisson solve and the DEIM gather of the sampled rows, per parameter
+          // per parameter: the Poisson solve, the DEIM gather of the sampled
+          // rows and the fixed-point update of the column
           Timer t(FAM_POISSON, s);
           launch_poisson_deim(s, r.b.part, r.gdep.nrb, p, r.Nx, r.b.qw, r.b.h, r.b.mw, r.active,
                               r.b.rho, r.b.phi, r.b.e, r.b.energy, gate, r.Uh, N, n, r.Zev,
-                              r.b.factor, r.cfg.q / r.cfg.m, r.didx, r.dw, r.d_cur, r.gF);
+                              r.b.factor, r.cfg.q / r.cfg.m, r.didx, r.dw, r.d_cur, r.gF, r.C12,
+                              r.Z0, r.ZG, r.k, r.prev, dt, r.cfg.fp_tol, fixed > 0 ? 1 : 0,
+                              launched + 1, r.counters);
         }
       } else {
         full_gradient(r, r.Uh, r.Zev, r.active, true, false, gate);
-      }
-      {
         Timer t(FAM_DENSE, s);
-        launch_dense_fp_update(s, deim ? r.gF : r.gproj, r.C12, n, p, r.Z0, r.Zev, r.ZG, r.k,
-                               r.prev, r.active, dt, r.cfg.fp_tol, fixed > 0 ? 1 : 0,
-                               deim ? 1 : 0, r.counters);
+        launch_dense_fp_update(s, r.gproj, r.C12, n, p, r.Z0, r.Zev, r.ZG, r.k, r.prev, r.active,
+                               dt, r.cfg.fp_tol, fixed > 0 ? 1 : 0, 0, r.counters);
       }
     }
     LAUNCHCHK();

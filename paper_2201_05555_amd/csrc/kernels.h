@@ -63,12 +63,16 @@ void launch_poisson(hipStream_t s, const double* part, int nrb, int p, int Nx, c
                     const double* h, const double* mw, const int* active, double* rho,
                     double* phi, double* e, double* energy, const int* gate = nullptr);
 // the Poisson solve followed, per parameter, by the DEIM gather of the
-// sampled rows (gF, n x p) with the field just solved
+// sampled rows (gF, n x p) with the field just solved and, when counters is
+// set, the fixed-point update of that column (see dense_fp_update_kernel;
+// iter = the launch's ordinal in the solve, from 1)
 void launch_poisson_deim(hipStream_t s, const double* part, int nrb, int p, int Nx,
-                         const double* qw, const double* h, const double* mw, const int* active,
+                         const double* qw, const double* h, const double* mw, int* active,
                          double* rho, double* phi, double* e, double* energy, const int* gate,
-                         const cplx* U, int N, int n, const cplx* Z, const double* factor,
-                         double qm, const int* idx, const double* w, int d, cplx* gF);
+                         const cplx* U, int N, int n, cplx* Z, const double* factor, double qm,
+                         const int* idx, const double* w, int d, cplx* gF, const cplx* C12,
+                         const cplx* Z0, cplx* ZG, cplx* k, double* prev, double dt, double tol,
+                         int fixed, int iter, int* counters);
 void launch_fom_push(hipStream_t s, double* X, double* V, int N, int p, int Nx, const PicGeom& g,
                      const double* factor, const double* e, double qm, double ck, double cd,
                      double* part);

@@ -178,6 +178,20 @@ struct DeimGatherArgs {
   const double* w;
   int d;
   cplx* gF;
+  // optional fixed-point update of column i after the gather (counters set):
+  // the arithmetic of dense_fp_update_kernel with linear_part on; counters[0]
+  // loses one per column that stops, counters[1] gains the stalled ones,
+  // counters[2] becomes the launch ordinal `iter` when a column was updated
+  const cplx* C12;
+  const cplx* Z0;
+  cplx* Zeval;  // = Z, written for the columns that go on
+  cplx* ZG;
+  cplx* k;
+  double* prev;
+  int* active;
+  double dt, tol;
+  int fixed, iter;
+  int* counters;
 };
 
 __global__ void __launch_bounds__(POISSON_THREADS) poisson_kernel(
@@ -326,6 +340,7 @@ __global__ void __launch_bounds__(POISSON_THREADS) poisson_kernel(
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  cplx g = mk(0.0, 0.0);  // g_F[lane, i]
   for (int k = lane; k < n; k += 64) {
     cplx sk = mk(0.0, 0.0);
     for (int r = 0; r < dg.d; ++r) {
@@ -334,6 +349,59 @@ __global__ void __launch_bounds__(POISSON_THREADS) poisson_kernel(
       sk.im = fma(-u.im, Fw[r], sk.im);
     }
     dg.gF[(size_t)i * n + k] = sk;
+    g = sk;
+  }
+  if (!dg.counters) return;
+  // fixed-point update of column i (entries a = lane < n)
+  const cplx* ze = zi;  // Z is the evaluation point of the iteration
+  cplx knew = mk(0.0, 0.0);
+  if (lane < n) {
+    const int a = lane;
+    cplx sl = mk(0.0, 0.0);
+    for (int b = 0; b < n; ++b) {
+      cfma(sl, dg.C12[b * n + a], ze[b]);
+      cfma(sl, cscale(cconj(dg.C12[n * n + b * n + a]), -1.0), cconj(ze[b]));
+    }
+    g = cadd(g, cscale(sl, 0.5));
+    knew = mk(g.im, -g.re);  // -i g
+    const cplx dk = csub(knew, dg.k[(size_t)i * n + a]);
+    buf[a] = cabs2(dk);
+    buf[64 + a] = cabs2(knew);
+    dg.k[(size_t)i * n + a] = knew;
+    dg.ZG[(size_t)i * n + a] = ze[a];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (lane == 0) {
+    double dn = 0.0, kn = 0.0;
+    for (int a = 0; a < n; ++a) {
+      dn += buf[a];
+      kn += buf[64 + a];
+    }
+    bool done = false;
+    if (!dg.fixed) {
+      const double rel = (kn > 0.0) ? sqrt(dn) / sqrt(kn) : sqrt(dn);
+      const bool conv = rel < dg.tol;
+      const bool stall = !conv && rel >= dg.prev[i];
+      dg.prev[i] = rel;
+      done = conv || stall;
+      if (stall) atomicAdd(&dg.counters[1], 1);
+    }
+    if (done) {
+      dg.active[i] = 0;
+      atomicSub(&dg.counters[0], 1);
+    }
+    atomicMax(&dg.counters[2], dg.iter);
+    Fw[0] = done ? 1.0 : 0.0;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (Fw[0] == 0.0 && lane < n) {
+    const cplx z0 = dg.Z0[(size_t)i * n + lane];
+    dg.Zeval[(size_t)i * n + lane] =
+        mk(z0.re + 0.5 * dg.dt * knew.re, z0.im + 0.5 * dg.dt * knew.im);
   }
 }
 
@@ -496,11 +564,14 @@ void launch_poisson(hipStream_t s, const double* part, int nrb, int p, int Nx, c
 }
 
 void launch_poisson_deim(hipStream_t s, const double* part, int nrb, int p, int Nx,
-                         const double* qw, const double* h, const double* mw, const int* active,
+                         const double* qw, const double* h, const double* mw, int* active,
                          double* rho, double* phi, double* e, double* energy, const int* gate,
-                         const cplx* U, int N, int n, const cplx* Z, const double* factor,
-                         double qm, const int* idx, const double* w, int d, cplx* gF) {
-  DeimGatherArgs dg{U, N, n, Z, factor, qm, idx, w, d, gF};
+                         const cplx* U, int N, int n, cplx* Z, const double* factor, double qm,
+                         const int* idx, const double* w, int d, cplx* gF, const cplx* C12,
+                         const cplx* Z0, cplx* ZG, cplx* k, double* prev, double dt, double tol,
+                         int fixed, int iter, int* counters) {
+  DeimGatherArgs dg{U,   N,  n, Z,    factor, qm,  idx, w,     d,    gF,
+                    C12, Z0, Z, ZG,   k,      prev, active, dt, tol, fixed, iter, counters};
   hipLaunchKernelGGL(poisson_kernel, dim3(p), dim3(POISSON_THREADS), 0, s, part, nrb, p, Nx, qw, h,
                      mw, active, rho, phi, e, energy, gate, dg);
 }
