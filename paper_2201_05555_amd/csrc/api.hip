@@ -465,6 +465,10 @@ struct symrom_rom {
   // ev_fork / ev_join order it after the first-stage field and before its use.
   hipStream_t s2;
   hipEvent_t ev_fork, ev_join;
+  // S(Z)^+ of the second-stage basis velocity on the second stream, beside
+  // the gather-projection that precedes it: ev_sp0 orders it after the fixed
+  // point, ev_sp1 its result before the basis-velocity finish
+  hipEvent_t ev_sp0, ev_sp1;
   hipEvent_t ev_read;  // end-of-step status copy done
   // With rank adaptation the first-stage field of the next step is known at
   // the end of a step: the head of the next DEIM update (snapshot, Gram
@@ -526,7 +530,8 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.flags = r.status;
   r.counters = r.status + 4;
   r.eps_dev = reinterpret_cast<double*>(r.status + 8);
-  const size_t m2 = (size_t)4 * nm * nm;
+  // the largest Gram: [U0, xi, U_half, X]^* of the same (4n x 4n)
+  const size_t m2 = (size_t)16 * nm * nm;
   r.Gram = ar.take<cplx>(m2 > (size_t)p * p ? m2 : (size_t)p * p);
   r.Amat = ar.take<cplx>((size_t)nm * nm);
   r.MU = ar.take<cplx>((size_t)nm * nm);
@@ -634,6 +639,18 @@ MatList ml(const cplx* a, int ca, const cplx* b = nullptr, int cb = 0) {
   }
   return L;
 }
+MatList ml(const cplx* a, int ca, const cplx* b, int cb, const cplx* c, int cc, const cplx* d,
+           int cd) {
+  MatList L{};
+  const cplx* pt[4] = {a, b, c, d};
+  const int cl[4] = {ca, cb, cc, cd};
+  for (int q = 0; q < 4; ++q) {
+    L.ptr[q] = pt[q];
+    L.cols[q] = cl[q];
+  }
+  L.count = 4;
+  return L;
+}
 
 RowTerms rt(const cplx* in0, const cplx* M0, int k0, const cplx* in1 = nullptr,
             const cplx* M1 = nullptr, int k1 = 0, const cplx* in2 = nullptr,
@@ -724,11 +741,12 @@ void materialise_gradient(symrom_rom& r, const cplx* U, const cplx* Z) {
 
 // X~ = -i (G~ Q - U T) scaled by `scale`, written to `out`, with G~ in r.G
 // and g in r.gproj; Q = Z^* S(Z)^+ computed first.
+// q_ready: S(Z)^+ Q has been formed already (and ordered before this call)
 void basis_velocity(symrom_rom& r, const cplx* U, const cplx* Z, double scale, cplx* out,
-                    cplx* k1) {
+                    cplx* k1, bool q_ready = false) {
   hipStream_t s = r.s;
   const int n = r.n;
-  {
+  if (!q_ready) {
     Timer t(FAM_DENSE, s);
     launch_dense_spinv(s, Z, n, r.p, r.cfg.pinv_rtol, r.Q, r.sigma2, r.flags);
   }
@@ -981,11 +999,30 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   r.last.deim_active = deim ? 1 : 0;
   if (fixed == 0 && hc[0] > 0) return fail(SYMROM_ENOCONV, "fixed point not converged");
   launch_dense_finish_z(s, r.Z0, r.k, n, p, dt, r.Z1);
-  // basis velocity at (U_half, Z_G) with the field of each column's last evaluation
+  // basis velocity at (U_half, Z_G) with the field of each column's last
+  // evaluation; S(Z_G)^+ on the second stream (idle here) beside the projection
+  const bool side = r.s2 != nullptr;
+  if (side) {
+    HIPCHK(hipEventRecord(r.ev_sp0, s));
+    HIPCHK(hipStreamWaitEvent(r.s2, r.ev_sp0, 0));
+    Timer t(FAM_DENSE, r.s2);
+    launch_dense_spinv(r.s2, r.ZG, n, p, r.cfg.pinv_rtol, r.Q, r.sigma2, r.flags);
+    HIPCHK(hipEventRecord(r.ev_sp1, r.s2));
+  }
   full_gradient(r, r.Uh, r.ZG, nullptr, false);
-  basis_velocity(r, r.Uh, r.ZG, 1.0, r.Xv, nullptr);
+  if (side) HIPCHK(hipStreamWaitEvent(s, r.ev_sp1, 0));
+  basis_velocity(r, r.Uh, r.ZG, 1.0, r.Xv, nullptr, side);
   // tangent velocity Y(xi_half, Z_G)
-  {
+  if (4 * n <= 64) {
+    // one Gram of [U0, xi, U_half, X] and one row combination (the
+    // intermediate Ups is never formed)
+    Timer t(FAM_BASIS, s);
+    launch_gemm_ah_b(s, ml(r.U0, n, r.Xi, n, r.Uh, n, r.Xv, n), 4 * n,
+                     ml(r.U0, n, r.Xi, n, r.Uh, n, r.Xv, n), 4 * n, false, N, r.nkb, r.gemm_part,
+                     r.Gram);
+    launch_dense_tangent(s, r.Gram, n, dt, r.M1, r.M2, r.M3, r.flags);
+    launch_rowgemm(s, rt(r.Xv, r.M1, n, r.Xi, r.M2, n, r.U0, r.M3, n), N, n, r.P);  // xi_1
+  } else {
     Timer t(FAM_BASIS, s);
     launch_gemm_ah_b(s, ml(r.U0, n, r.Xi, n), 2 * n, ml(r.Xv, n, r.Uh, n), 2 * n, false, N,
                      r.nkb, r.gemm_part, r.Gram);
@@ -1226,7 +1263,9 @@ extern "C" symrom_status rom_init(const symrom_config* cfg, const double* L, con
   if (cfg->projection == SYMROM_DEIM &&
       (hipStreamCreateWithFlags(&r->s2, hipStreamNonBlocking) != hipSuccess ||
        hipEventCreateWithFlags(&r->ev_fork, hipEventDisableTiming) != hipSuccess ||
-       hipEventCreateWithFlags(&r->ev_join, hipEventDisableTiming) != hipSuccess)) {
+       hipEventCreateWithFlags(&r->ev_join, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&r->ev_sp0, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&r->ev_sp1, hipEventDisableTiming) != hipSuccess)) {
     rom_destroy(r);
     return fail(SYMROM_EDEVICE, "rom_init: stream or event creation");
   }
@@ -1447,6 +1486,8 @@ extern "C" void rom_destroy(symrom_rom* r) {
   if (!r) return;
   side_wait(r);
   if (r->ev_fork) (void)hipEventDestroy(r->ev_fork);
+  if (r->ev_sp0) (void)hipEventDestroy(r->ev_sp0);
+  if (r->ev_sp1) (void)hipEventDestroy(r->ev_sp1);
   if (r->ev_join) (void)hipEventDestroy(r->ev_join);
   if (r->ev_read) (void)hipEventDestroy(r->ev_read);
   if (r->s2) (void)hipStreamDestroy(r->s2);

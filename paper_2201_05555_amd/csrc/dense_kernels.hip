@@ -570,6 +570,106 @@ __global__ void __launch_bounds__(DTPB) dense_tangent2_kernel(const cplx* __rest
   }
 }
 
+// Tangent velocity in one pass, from G4 = [U0, xi, Ux, X]^* [U0, xi, Ux, X]
+// (4n x 4n; block (I, J) = the I-th list entry ^* the J-th).  The two halves
+// above, with Ups = X M1 + xi M2 + U0 M3 never formed: its Grams follow from
+// G4, D1 = Ux^*X M1 + Ux^*xi M2 + Ux^*U0 M3 and D0 = U0^*X M1 + U0^*xi M2 +
+// U0^*U0 M3, and
+//   xi1 = dt Y = X (dt M1) + xi (dt M2) + U0 (dt M3 - dt C),
+//   C = (Ux^* U0 + I)^{-1} (D1 + D0) + D0^*.
+// Output K1, K2, K3 (n x n) for the row combination.
+__global__ void __launch_bounds__(DTPB) dense_tangent_kernel(const cplx* __restrict__ G4, int n,
+                                                             double dt, cplx* __restrict__ K1,
+                                                             cplx* __restrict__ K2,
+                                                             cplx* __restrict__ K3,
+                                                             int* __restrict__ flags) {
+  extern __shared__ cplx sm[];
+  const int nn = n * n, m4 = 4 * n;
+  cplx* A = sm;            // U0^* xi
+  cplx* B1 = A + nn;       // U0^* X
+  cplx* C0x = B1 + nn;     // U0^* Ux
+  cplx* XX = C0x + nn;     // xi^* X, then W^* X
+  cplx* UxX = XX + nn;     // Ux^* X
+  cplx* Uxxi = UxX + nn;   // Ux^* xi
+  cplx* UxU0 = Uxxi + nn;  // Ux^* U0
+  cplx* G00 = UxU0 + nn;   // U0^* U0
+  cplx* Mi = G00 + nn;     // (C0x + I)^{-1}
+  cplx* M2 = Mi + nn;
+  cplx* M3 = M2 + nn;
+  cplx* D1 = M3 + nn;
+  cplx* D0 = D1 + nn;
+  cplx* T1 = D0 + nn;
+  cplx* T2 = T1 + nn;
+  __shared__ int piv;
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+    const int a = t % n, b = t / n;
+    auto blk = [&](int I, int J) { return G4[(size_t)(J * n + b) * m4 + I * n + a]; };
+    A[t] = blk(0, 1);
+    B1[t] = blk(0, 3);
+    C0x[t] = blk(0, 2);
+    XX[t] = blk(1, 3);
+    UxX[t] = blk(2, 3);
+    Uxxi[t] = blk(2, 1);
+    UxU0[t] = blk(2, 0);
+    G00[t] = blk(0, 0);
+  }
+  __syncthreads();
+  // W^* X = xi^* X - A^* B1 / 2
+  bk_matmul(T1, A, 1, B1, 0, n, n, n);
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) XX[t] = csub(XX[t], cscale(T1[t], 0.5));
+  // Minv = (C0x + I)^{-1}
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+    const int r = t % n, c = t / n;
+    T2[t] = C0x[t];
+    if (r == c) T2[t].re += 1.0;
+    Mi[t] = (r == c) ? mk(1.0, 0.0) : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  if (bk_lu_solve(T2, n, Mi, n, &piv)) {
+    if (threadIdx.x == 0 && flags) flags[0] |= 1;
+    return;
+  }
+  // M2 = -B1 Minv;  M3 = (A B1 / 2 + W^* X) Minv  (M1 = 2 Minv)
+  bk_matmul(T1, B1, 0, Mi, 0, n, n, n);
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) M2[t] = cscale(T1[t], -1.0);
+  bk_matmul(T1, A, 0, B1, 0, n, n, n);
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) T2[t] = cadd(cscale(T1[t], 0.5), XX[t]);
+  __syncthreads();
+  bk_matmul(M3, T2, 0, Mi, 0, n, n, n);
+  // D1 = Ux^*X M1 + Ux^*xi M2 + Ux^*U0 M3;  D0 = U0^*X M1 + U0^*xi M2 + U0^*U0 M3
+  bk_matmul(D1, UxX, 0, Mi, 0, n, n, n);
+  bk_matmul(T1, Uxxi, 0, M2, 0, n, n, n);
+  bk_matmul(T2, UxU0, 0, M3, 0, n, n, n);
+  for (int t = threadIdx.x; t < nn; t += blockDim.x)
+    D1[t] = cadd(cadd(cscale(D1[t], 2.0), T1[t]), T2[t]);
+  __syncthreads();
+  bk_matmul(D0, B1, 0, Mi, 0, n, n, n);
+  bk_matmul(T1, A, 0, M2, 0, n, n, n);
+  bk_matmul(T2, G00, 0, M3, 0, n, n, n);
+  for (int t = threadIdx.x; t < nn; t += blockDim.x)
+    D0[t] = cadd(cadd(cscale(D0[t], 2.0), T1[t]), T2[t]);
+  __syncthreads();
+  // C = (C0x^* + I)^{-1} (D1 + D0) + D0^*  (the system in T2, the right side in T1)
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+    const int r = t % n, c = t / n;
+    T1[t] = cadd(D1[t], D0[t]);
+    T2[t] = cconj(C0x[r * n + c]);
+    if (r == c) T2[t].re += 1.0;
+  }
+  __syncthreads();
+  if (bk_lu_solve(T2, n, T1, n, &piv)) {
+    if (threadIdx.x == 0 && flags) flags[0] |= 1;
+    return;
+  }
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+    const int r = t % n, c = t / n;
+    const cplx C = cadd(T1[t], cconj(D0[r * n + c]));
+    K1[t] = cscale(Mi[t], 2.0 * dt);
+    K2[t] = cscale(M2[t], dt);
+    K3[t] = cscale(csub(M3[t], C), dt);
+  }
+}
+
 // Cholesky QR step: Gram = U~^* U~ = R^* R; Rinv = R^{-1} for U~ <- U~ R^{-1};
 // Z~ <- R Z~ in place (n x p).
 __global__ void __launch_bounds__(DTPB) dense_chol_kernel(const cplx* __restrict__ Gram, int n,
@@ -846,6 +946,13 @@ void launch_dense_tangent2(hipStream_t s, const cplx* Gram3, const cplx* C0x, in
   size_t sh = (size_t)3 * n * n * sizeof(cplx);
   hipLaunchKernelGGL(dense_tangent2_kernel, dim3(1), dim3(dense_chain_threads(n)), sh, s, Gram3,
                      C0x, n, dt, M1, M2, flags);
+}
+void launch_dense_tangent(hipStream_t s, const cplx* G4, int n, double dt, cplx* K1, cplx* K2,
+                          cplx* K3, int* flags) {
+  const size_t sh = (size_t)15 * n * n * sizeof(cplx);
+  ALLOW_BIG_LDS(dense_tangent_kernel);
+  hipLaunchKernelGGL(dense_tangent_kernel, dim3(1), dim3(dense_chain_threads(n)), sh, s, G4, n, dt,
+                     K1, K2, K3, flags);
 }
 void launch_dense_chol(hipStream_t s, const cplx* Gram, int n, cplx* Rinv, cplx* Z, int p,
                        int* flags) {

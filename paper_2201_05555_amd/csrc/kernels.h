@@ -142,6 +142,10 @@ void launch_dense_tangent1(hipStream_t s, const cplx* A, const cplx* Gram2, int 
                            cplx* M2, cplx* M3, cplx* C0x_out, int* flags);
 void launch_dense_tangent2(hipStream_t s, const cplx* Gram3, const cplx* C0x, int n, double dt,
                            cplx* M1, cplx* M2, int* flags);
+// the whole tangent velocity from G4 = [U0, xi, Ux, X]^* [U0, xi, Ux, X] (4n x 4n):
+// xi1 = X K1 + xi K2 + U0 K3 (n x n each)
+void launch_dense_tangent(hipStream_t s, const cplx* G4, int n, double dt, cplx* K1, cplx* K2,
+                          cplx* K3, int* flags);
 void launch_dense_chol(hipStream_t s, const cplx* Gram, int n, cplx* Rinv, cplx* Z, int p,
                        int* flags);
 void launch_dense_fp_update(hipStream_t s, const cplx* gF, const cplx* C12, int n, int p,
