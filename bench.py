@@ -4,7 +4,8 @@ two-stream ensemble N = 100,000 particles, p = 64 parameters, Nx = 128 cells,
 dt = 0.05, reduced rank 2n starting at 10 (cap 60).
 
 Prints ONE JSON line.  `value` is the ROM throughput N * p * steps / time of
-the timed steps (inputs resident in HBM).  `roofline` describes the
+the timed steps (inputs resident in HBM); by default two warm-up steps and 25
+timed steps (steps 3 to 27, the averaging window of the paper's timings).  `roofline` describes the
 dominant kernel family of the ROM step, timed with HIP events on the
 library's stream over the timed region; `cpu_baseline` times the FP64
 oracle on a bounded sample of the same workload on the host cores.
@@ -45,8 +46,8 @@ TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2201_05555_amd", "csrc", "pic_kernels
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=25)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="twostream_deim")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
