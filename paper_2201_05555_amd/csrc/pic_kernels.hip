@@ -430,14 +430,16 @@ __global__ void __launch_bounds__(512) fom_push_kernel(
     const double* __restrict__ factor, const double* __restrict__ e, double qm, double ck,
     double cd, double* __restrict__ part) {
   extern __shared__ double smem[];
-  double* et = smem;            // pt * Nx field table
-  double* hist = smem + pt * Nx;  // pt * Nx
+  double* et = smem;              // pt * Nx field table
+  double* hist = smem + pt * Nx;  // pt * Nx theta sums per cell
+  unsigned* cnt = reinterpret_cast<unsigned*>(smem + 2 * (size_t)pt * Nx);  // counts per cell
   const int rb = blockIdx.x;
   const int p0 = blockIdx.y * pt;
   const int np = min(pt, p - p0);
   for (int t = threadIdx.x; t < np * Nx; t += blockDim.x) {
     et[t] = e[(size_t)p0 * Nx + t];
     hist[t] = 0.0;
+    cnt[t] = 0u;
   }
   __syncthreads();
   const int r0 = rb * rpb;
@@ -448,6 +450,7 @@ __global__ void __launch_bounds__(512) fom_push_kernel(
     double* Vi = V + (size_t)(p0 + i) * N;
     const double* ei = et + i * Nx;
     double* hi = hist + i * Nx;
+    unsigned* ci = cnt + i * Nx;
     for (int l = r0 + threadIdx.x; l < r1; l += blockDim.x) {
       double x = Xi[l];
       double v = Vi[l];
@@ -459,17 +462,20 @@ __global__ void __launch_bounds__(512) fom_push_kernel(
       Vi[l] = v;
       Xi[l] = x;
       if (part) {
+        // count and theta per cell, as in deposit_rom_kernel
         cell_of(x, f, Nx, j, th);
-        int j1 = (j + 1 == Nx) ? 0 : j + 1;
-        lds_add(hi + j, 1.0 - th);
-        lds_add(hi + j1, th);
+        __hip_atomic_fetch_add(ci + j, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        lds_add(hi + j, th);
       }
     }
   }
   if (!part) return;
   __syncthreads();
-  for (int t = threadIdx.x; t < np * Nx; t += blockDim.x)
-    part[((size_t)rb * p + p0) * Nx + t] = hist[t];
+  for (int t = threadIdx.x; t < np * Nx; t += blockDim.x) {
+    const int i = t / Nx, j = t - i * Nx;
+    const int jm = (j == 0) ? Nx - 1 : j - 1;
+    part[((size_t)rb * p + p0) * Nx + t] = ((double)cnt[t] - hist[t]) + hist[i * Nx + jm];
+  }
 }
 
 // V_out = V + c * a(X) without touching the state (full velocities from the
@@ -590,7 +596,7 @@ void launch_fom_push(hipStream_t s, double* X, double* V, int N, int p, int Nx, 
                      const double* factor, const double* e, double qm, double ck, double cd,
                      double* part) {
   dim3 grid(g.nrb, (p + g.pt - 1) / g.pt);
-  size_t sh = 2 * (size_t)g.pt * Nx * sizeof(double);
+  size_t sh = (size_t)g.pt * Nx * (2 * sizeof(double) + sizeof(unsigned));
   ALLOW_BIG_LDS(fom_push_kernel);
   hipLaunchKernelGGL(fom_push_kernel, grid, dim3(512), sh, s, X, V, N, p, Nx, g.pt, g.rpb, factor,
                      e, qm, ck, cd, part);
