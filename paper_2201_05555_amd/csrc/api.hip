@@ -780,6 +780,28 @@ void cayley(symrom_rom& r, const cplx* U0, const cplx* xi, cplx* Uout, cplx* A_o
   launch_rowgemm(s, rt(U0, r.MU, n, xi, r.MX, n), r.N, n, Uout);
 }
 
+// Uout = R_{U0}(xi) followed by two Cholesky-QR passes with Z <- R Z, the
+// first without a pass over the rows: its Gram comes from the retraction's
+// own Gram (U = U0 MU + xi MX gives U^* U = [MU; MX]^* [U0, xi]^* [U0, xi]
+// [MU; MX]), and R^{-1} is folded into MU, MX, so that one row combination
+// forms the once-factored basis.  Needs 4n <= 64 (the Gram of [U0, xi] and
+// the row combination as for cayley).
+void cayley_cholqr2(symrom_rom& r, const cplx* U0, const cplx* xi, cplx* Uout, cplx* A_out,
+                    cplx* Z) {
+  hipStream_t s = r.s;
+  const int n = r.n;
+  Timer t(FAM_BASIS, s);
+  cplx* G1 = r.Gram + (size_t)4 * n * n;
+  launch_gemm_ah_b(s, ml(U0, n, xi, n), 2 * n, ml(U0, n, xi, n), 2 * n, false, r.N, r.nkb,
+                   r.gemm_part, r.Gram);
+  launch_dense_cayley(s, r.Gram, n, A_out, r.MU, r.MX, r.flags, G1);
+  launch_dense_chol(s, G1, n, r.Rinv, Z, r.p, r.flags, r.MU, r.MX);
+  launch_rowgemm(s, rt(U0, r.MU, n, xi, r.MX, n), r.N, n, Uout);
+  launch_gemm_ah_b(s, ml(Uout, n), n, ml(Uout, n), n, false, r.N, r.nkb, r.gemm_part, r.Gram);
+  launch_dense_chol(s, r.Gram, n, r.Rinv, Z, r.p, r.flags);
+  launch_rowgemm(s, rt(Uout, r.Rinv, n), r.N, n, Uout);
+}
+
 // two Cholesky-QR passes on U (N x n) with Z <- R Z
 void cholqr2(symrom_rom& r, cplx* U, cplx* Z) {
   hipStream_t s = r.s;
@@ -998,16 +1020,19 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   r.last.stalled = hc[1];
   r.last.deim_active = deim ? 1 : 0;
   if (fixed == 0 && hc[0] > 0) return fail(SYMROM_ENOCONV, "fixed point not converged");
-  launch_dense_finish_z(s, r.Z0, r.k, n, p, dt, r.Z1);
   // basis velocity at (U_half, Z_G) with the field of each column's last
-  // evaluation; S(Z_G)^+ on the second stream (idle here) beside the projection
+  // evaluation; S(Z_G)^+ and Z1 = Z0 + dt k on the second stream (idle here)
+  // beside the projection
   const bool side = r.s2 != nullptr;
   if (side) {
     HIPCHK(hipEventRecord(r.ev_sp0, s));
     HIPCHK(hipStreamWaitEvent(r.s2, r.ev_sp0, 0));
     Timer t(FAM_DENSE, r.s2);
     launch_dense_spinv(r.s2, r.ZG, n, p, r.cfg.pinv_rtol, r.Q, r.sigma2, r.flags);
+    launch_dense_finish_z(r.s2, r.Z0, r.k, n, p, dt, r.Z1);
     HIPCHK(hipEventRecord(r.ev_sp1, r.s2));
+  } else {
+    launch_dense_finish_z(s, r.Z0, r.k, n, p, dt, r.Z1);
   }
   full_gradient(r, r.Uh, r.ZG, nullptr, false);
   if (side) HIPCHK(hipStreamWaitEvent(s, r.ev_sp1, 0));
@@ -1034,8 +1059,12 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
     launch_rowgemm(s, rt(r.Ups, r.M1, n, r.U0, r.M2, n), N, n, r.P);  // xi_1 = dt Y
   }
   // U1 = R_{U0}(xi_1)  (into Uh, free now)
-  cayley(r, r.U0, r.P, r.Uh, r.M3);
-  if (r.cfg.reorth) cholqr2(r, r.Uh, r.Z1);
+  if (r.cfg.reorth && 4 * n <= 64) {
+    cayley_cholqr2(r, r.U0, r.P, r.Uh, r.M3, r.Z1);
+  } else {
+    cayley(r, r.U0, r.P, r.Uh, r.M3);
+    if (r.cfg.reorth) cholqr2(r, r.Uh, r.Z1);
+  }
   // Commit by exchanging buffers before the flags are known, and with rank
   // adaptation enqueue the indicator's gradient at the new state behind it,
   // so that one readback serves both; a failed step exchanges them back.

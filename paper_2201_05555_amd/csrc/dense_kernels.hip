@@ -398,10 +398,13 @@ __global__ void __launch_bounds__(DTPB) dense_xfinish_kernel(const cplx* __restr
 //   K = (I - Rc^* Lc / 2)^{-1},  [Y1; Y2] = K Rc^* U0,
 //   R_{U0}(xi) = U0 + W Y1 - U0 Y2 = U0 (I - Y2 - A Y1 / 2) + xi Y1.
 // Output MU, MX (n x n) for the row combination, and A.
+// G1 (optional, n x n): the Gram of the result, [MU; MX]^* Gram [MU; MX],
+// for a Cholesky QR of R_{U0}(xi) without a pass over its rows.
 __global__ void __launch_bounds__(DTPB) dense_cayley_kernel(const cplx* __restrict__ Gram, int n,
                                                             cplx* __restrict__ A_out,
                                                             cplx* __restrict__ MU,
                                                             cplx* __restrict__ MX,
+                                                            cplx* __restrict__ G1,
                                                             int* __restrict__ flags) {
   extern __shared__ cplx sm[];
   const int m = 2 * n;
@@ -464,6 +467,8 @@ __global__ void __launch_bounds__(DTPB) dense_cayley_kernel(const cplx* __restri
   }
   __syncthreads();
   bk_matmul(WW, A, 0, Y1, 0, n, n, n);  // A Y1
+  // [MU; MX] (2n x n) kept in LDS past the end of B when G1 is wanted
+  cplx* Wm = B + m * n;
   for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
     int r = t % n, c = t / n;
     cplx v = cscale(B[c * m + n + r], -1.0);
@@ -471,7 +476,20 @@ __global__ void __launch_bounds__(DTPB) dense_cayley_kernel(const cplx* __restri
     if (r == c) v.re += 1.0;
     MU[t] = v;
     if (A_out) A_out[t] = A[t];
+    if (G1) {
+      Wm[c * m + r] = v;
+      Wm[c * m + n + r] = B[c * m + r];
+    }
   }
+  if (!G1) return;
+  // G1 = W^* (Gram W), W = [MU; MX]; the Gram again from memory
+  cplx* Gs = Wm + m * n;  // 2n x 2n
+  cplx* T = Gs + m * m;   // 2n x n
+  for (int t = threadIdx.x; t < m * m; t += blockDim.x) Gs[t] = Gram[t];
+  __syncthreads();
+  bk_matmul(T, Gs, 0, Wm, 0, m, m, n);
+  bk_matmul(Gs, Wm, 1, T, 0, n, m, n);
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) G1[t] = Gs[t];
 }
 
 // Tangent velocity, first half.  Input A = U0^* xi and
@@ -672,9 +690,13 @@ __global__ void __launch_bounds__(DTPB) dense_tangent_kernel(const cplx* __restr
 
 // Cholesky QR step: Gram = U~^* U~ = R^* R; Rinv = R^{-1} for U~ <- U~ R^{-1};
 // Z~ <- R Z~ in place (n x p).
+// MU, MX (optional, n x n each): replaced by MU R^{-1}, MX R^{-1}, so that a
+// row combination U0 MU + xi MX lands on the factored basis directly.
 __global__ void __launch_bounds__(DTPB) dense_chol_kernel(const cplx* __restrict__ Gram, int n,
                                                           cplx* __restrict__ Rinv,
                                                           cplx* __restrict__ Z, int p,
+                                                          cplx* __restrict__ MU,
+                                                          cplx* __restrict__ MX,
                                                           int* __restrict__ flags) {
   extern __shared__ cplx sm[];
   cplx* G = sm;          // n x n
@@ -691,6 +713,19 @@ __global__ void __launch_bounds__(DTPB) dense_chol_kernel(const cplx* __restrict
   }
   bk_triu_inv(R, Ri, n);
   for (int t = threadIdx.x; t < n * n; t += blockDim.x) Rinv[t] = Ri[t];
+  if (MU) {
+    // M <- M R^{-1} for M = MU, MX (two n x n scratch after Zs)
+    cplx* Ms = Zs + (Z ? n * p : 0);
+    cplx* Ts = Ms + n * n;
+    for (int q = 0; q < 2; ++q) {
+      cplx* M = q ? MX : MU;
+      for (int t = threadIdx.x; t < n * n; t += blockDim.x) Ms[t] = M[t];
+      __syncthreads();
+      bk_matmul(Ts, Ms, 0, Ri, 0, n, n, n);
+      for (int t = threadIdx.x; t < n * n; t += blockDim.x) M[t] = Ts[t];
+      __syncthreads();
+    }
+  }
   if (Z) {
     // Z <- R Z, one entry per thread (R upper triangular)
     for (int t = threadIdx.x; t < n * p; t += blockDim.x) {
@@ -928,11 +963,12 @@ void launch_dense_xfinish(hipStream_t s, const cplx* g, const cplx* Q, int n, in
                      MU);
 }
 void launch_dense_cayley(hipStream_t s, const cplx* Gram, int n, cplx* A_out, cplx* MU,
-                         cplx* MX, int* flags) {
-  size_t sh = (size_t)(10 * n * n) * sizeof(cplx);
+                         cplx* MX, int* flags, cplx* G1) {
+  // 10 n^2 for the solve; with G1, W (2 n^2), the Gram (4 n^2) and T (2 n^2)
+  size_t sh = (size_t)((G1 ? 18 : 10) * n * n) * sizeof(cplx);
   ALLOW_BIG_LDS(dense_cayley_kernel);
   hipLaunchKernelGGL(dense_cayley_kernel, dim3(1), dim3(dense_chain_threads(n)), sh, s, Gram, n,
-                     A_out, MU, MX, flags);
+                     A_out, MU, MX, G1, flags);
 }
 void launch_dense_tangent1(hipStream_t s, const cplx* A, const cplx* Gram2, int n, cplx* M1,
                            cplx* M2, cplx* M3, cplx* C0x_out, int* flags) {
@@ -955,11 +991,11 @@ void launch_dense_tangent(hipStream_t s, const cplx* G4, int n, double dt, cplx*
                      K1, K2, K3, flags);
 }
 void launch_dense_chol(hipStream_t s, const cplx* Gram, int n, cplx* Rinv, cplx* Z, int p,
-                       int* flags) {
-  const size_t sh = (size_t)(3 * n * n + (Z ? n * p : 0)) * sizeof(cplx);
+                       int* flags, cplx* MU, cplx* MX) {
+  const size_t sh = (size_t)(3 * n * n + (Z ? n * p : 0) + (MU ? 2 * n * n : 0)) * sizeof(cplx);
   ALLOW_BIG_LDS(dense_chol_kernel);
   hipLaunchKernelGGL(dense_chol_kernel, dim3(1), dim3(dense_chain_threads(n)), sh, s, Gram, n,
-                     Rinv, Z, p, flags);
+                     Rinv, Z, p, MU, MX, flags);
 }
 void launch_dense_fp_update(hipStream_t s, const cplx* gF, const cplx* C12, int n, int p,
                             const cplx* Z0, cplx* Zeval, cplx* ZG, cplx* k, double* prev,
