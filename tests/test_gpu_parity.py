@@ -204,6 +204,9 @@ def _bound(sens):
     ("landau_tiny", dict(N=3001), 10, 6),
     ("twostream_deim", dict(N=20000, p=24, Nx=128), 12, 5),
     ("twostream_deim", dict(N=12345, p=40, Nx=96), 20, 4),
+    # 2n = 36: the paths for n > 16 (gradient through a stored G~, two-Gram
+    # tangent velocity, retraction and re-orthonormalisation apart)
+    ("twostream_deim", dict(N=6000, p=24, Nx=64), 36, 3),
 ])
 def test_rom_step_parity_fixed_iterations(name, kw, two_n, iters):
     """One step from the identical state with an exact iteration count:
@@ -429,6 +432,7 @@ def test_rom_deim_rank_auto_parity():
 @pytest.mark.parametrize("kw,two_n,two_n_max,steps", [
     (dict(N=20000, p=24, Nx=128), 8, 8, 6),
     (dict(N=30000, p=64, Nx=128), 10, 60, 6),     # the two-stream workload's DEIM shape
+    (dict(N=6000, p=24, Nx=64), 36, 36, 5),        # n > 16 with DEIM
 ])
 def test_rom_deim_steps_parity(kw, two_n, two_n_max, steps):
     """DEIM with the exact potential: Galerkin for the first T steps while
