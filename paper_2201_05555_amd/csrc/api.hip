@@ -857,12 +857,10 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z, bool redo = false,
     const double fP = P, fd = d;
     Timer te(FAM_EIG, s, 4.0 * fP * fP * fP / 3.0 + 2.0 * fP * fP * fd + 2.0 * fP * fd * fd,
              8.0 * fP * fP + 8.0 * fP * fd);
+    // eigenpairs and the basis coefficients M = V diag(lambda)^{-1/2} in one launch
     launch_dense_topeig(s, reinterpret_cast<const double*>(r.YG), P, d,
-                        reinterpret_cast<double*>(r.YV), r.ylam, dflags, stop);
+                        reinterpret_cast<double*>(r.YV), r.ylam, dflags, stop, r.Mdeim);
   }
-  Timer t(FAM_DENSE, s);
-  launch_deim_basis_coeffs(s, reinterpret_cast<const double*>(r.YV), r.ylam, P, d, r.Mdeim,
-                           dflags, stop);
 }
 
 // Second half of the DEIM operator (after deim_update, same stream).

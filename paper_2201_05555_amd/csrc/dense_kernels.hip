@@ -1740,6 +1740,7 @@ __device__ void te_back_gram(const double* __restrict__ H, const double* __restr
 __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restrict__ G, int n, int d,
                                                            double* __restrict__ V,
                                                            double* __restrict__ lam,
+                                                           double* __restrict__ Mc,
                                                            int* __restrict__ flags,
                                                            const int* __restrict__ stop) {
   if (stop && *stop) return;
@@ -2143,10 +2144,19 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
       s /= Rc[c * TE_LX + c];
       Xv[c * TE_LX + tid] = s;
       V[(size_t)c * n + tid] = s;
+      if (Mc) {
+        // the DEIM basis coefficients V[:, c] / sqrt(lambda_c)
+        const double l = __builtin_amdgcn_ldexp(lamg[c], gex);
+        Mc[(size_t)c * n + tid] = (l > 0.0) ? s / sqrt(l) : 0.0;
+      }
     }
   }
-  if (tid < d) lam[tid] = __builtin_amdgcn_ldexp(lamg[tid], gex);
-  if (tid == 0 && bad && flags) flags[0] |= 32;
+  if (tid < d) {
+    const double l = __builtin_amdgcn_ldexp(lamg[tid], gex);
+    lam[tid] = l;
+    if (Mc && !(l > 0.0) && flags) atomicOr(&flags[0], 8);
+  }
+  if (tid == 0 && bad && flags) atomicOr(&flags[0], 32);
 #ifdef SYMROM_TOPEIG_TIMING
   TS(5);
   if (tid == 0 && flags)
@@ -2162,6 +2172,7 @@ __global__ void __launch_bounds__(256) dense_topeig_kernel(const double* __restr
 }
 
 void launch_dense_topeig(hipStream_t s, const double* G, int n, int d, double* V, double* lam,
-                         int* flags, const int* stop) {
-  hipLaunchKernelGGL(dense_topeig_kernel, dim3(1), dim3(256), 0, s, G, n, d, V, lam, flags, stop);
+                         int* flags, const int* stop, double* Mc) {
+  hipLaunchKernelGGL(dense_topeig_kernel, dim3(1), dim3(256), 0, s, G, n, d, V, lam, Mc, flags,
+                     stop);
 }

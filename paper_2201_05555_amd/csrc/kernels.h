@@ -182,8 +182,9 @@ void launch_deim_k(hipStream_t s, const cplx* gF, const cplx* C12, const cplx* Z
                    cplx* k);
 void launch_dense_indicator(hipStream_t s, const double* colsq, const cplx* g, int n, int p,
                             double* eps);
+// Mc (optional, n x d): the DEIM basis coefficients V[:, c] / sqrt(lam_c)
 void launch_dense_topeig(hipStream_t s, const double* G, int n, int d, double* V, double* lam,
-                         int* flags, const int* stop = nullptr);
+                         int* flags, const int* stop = nullptr, double* Mc = nullptr);
 // error-word bookkeeping at the end of a step with the DEIM chain
 void launch_fold_status(hipStream_t s, int* status);
 void launch_gram_block_real(hipStream_t s, const double* Ynew, const double* const* slots,
