@@ -1211,25 +1211,6 @@ void launch_dense_shrink(hipStream_t s, const cplx* Z, int n, int p, cplx* V, cp
 // DEIM (Sec. 4.3): basis coefficients, greedy selection and weights
 // ---------------------------------------------------------------------------
 
-// M[:, c] = Re V[:, c] / sqrt(lam_c), c < d: Psi = Y M is the first d left
-// singular vectors of Y from the eigenpairs of Y^T Y (real symmetric, so V
-// is real).
-__global__ void deim_basis_coeffs_kernel(const double* __restrict__ V, const double* __restrict__ lam,
-                                         int P, int d, double* __restrict__ M,
-                                         int* __restrict__ flags, const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= P * d) return;
-  int c = t / P;
-  double l = lam[c];
-  if (!(l > 0.0)) {
-    if (flags) flags[0] |= 8;
-    M[t] = 0.0;
-    return;
-  }
-  M[t] = V[t] / sqrt(l);
-}
-
 // k = -i (gF + (C1 Z - conj(C2) conj(Z)) / 2): the DEIM reduced gradient
 // (eq. grHDD) with its linear part i U~^* V_r, C1 = U~^* U~, C2 = U~^T U~.
 __global__ void deim_k_kernel(const cplx* __restrict__ gF, const cplx* __restrict__ C12,
@@ -1247,11 +1228,6 @@ __global__ void deim_k_kernel(const cplx* __restrict__ gF, const cplx* __restric
   k[t] = mk(g.im, -g.re);
 }
 
-void launch_deim_basis_coeffs(hipStream_t s, const double* V, const double* lam, int P, int d,
-                              double* M, int* flags, const int* stop) {
-  hipLaunchKernelGGL(deim_basis_coeffs_kernel, dim3(nblk((size_t)P * d)), dim3(256), 0, s, V, lam,
-                     P, d, M, flags, stop);
-}
 void launch_deim_k(hipStream_t s, const cplx* gF, const cplx* C12, const cplx* Z, int n, int p,
                    cplx* k) {
   hipLaunchKernelGGL(deim_k_kernel, dim3(nblk((size_t)n * p)), dim3(256), 0, s, gF, C12, Z, n, p,

@@ -175,8 +175,6 @@ void launch_z_resize(hipStream_t s, const cplx* Zin, int nin, cplx* Zout, int no
 void launch_dense_shrink(hipStream_t s, const cplx* Z, int n, int p, cplx* V, cplx* Znew,
                          double* sig2);
 
-void launch_deim_basis_coeffs(hipStream_t s, const double* V, const double* lam, int P, int d,
-                              double* M, int* flags, const int* stop = nullptr);
 void launch_dense_symeig(hipStream_t s, const cplx* G, int n, double* V, double* lam, int* flags);
 void launch_deim_k(hipStream_t s, const cplx* gF, const cplx* C12, const cplx* Z, int n, int p,
                    cplx* k);
