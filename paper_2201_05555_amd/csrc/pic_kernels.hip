@@ -213,13 +213,34 @@ __global__ void __launch_bounds__(POISSON_THREADS) poisson_kernel(
   __shared__ double buf[POISSON_THREADS];
   __shared__ double rho_s[SYMROM_MAX_NX];   // the charge, later the field (DEIM gather)
   __shared__ cplx Ud[64 * SYMROM_MAX_NC];   // U~[I_r, k] at Ud[r * n + k]
+  __shared__ cplx Zc[SYMROM_MAX_NC];        // column i of Z
+  __shared__ cplx Cs[2 * 16 * 16];          // C12 when n <= 16
   __shared__ double Fw[64];
   const int i = blockIdx.x;
   if (active && !active[i]) return;
   const bool deim = dg.idx != nullptr;
-  if (deim && threadIdx.x < dg.d) {
-    const int l = dg.idx[threadIdx.x];
-    for (int k = 0; k < dg.n; ++k) Ud[threadIdx.x * dg.n + k] = dg.U[(size_t)k * dg.N + l];
+  // everything the gather and the update read, loaded now, behind the
+  // partial sums (the lanes that use a value in the tail load it here)
+  const bool cs_lds = deim && dg.counters && dg.n <= 16;
+  cplx kold = mk(0.0, 0.0), z0v = mk(0.0, 0.0);
+  double wl = 0.0, prev_i = 0.0, fac_i = 1.0;
+  if (deim) {
+    const int t = threadIdx.x;
+    fac_i = dg.factor[i];
+    if (t < dg.d) {
+      const int l = dg.idx[t];
+      wl = dg.w[t];
+      for (int k = 0; k < dg.n; ++k) Ud[t * dg.n + k] = dg.U[(size_t)k * dg.N + l];
+    }
+    if (t < dg.n) {
+      Zc[t] = dg.Z[(size_t)i * dg.n + t];
+      if (dg.counters) {
+        kold = dg.k[(size_t)i * dg.n + t];
+        z0v = dg.Z0[(size_t)i * dg.n + t];
+      }
+    }
+    if (t == 0 && dg.counters) prev_i = dg.prev[i];
+    if (cs_lds && t < 2 * dg.n * dg.n) Cs[t] = dg.C12[t];
   }
   const double hi = h[i];
   const double qwi = qw[i];
@@ -334,7 +355,7 @@ __global__ void __launch_bounds__(POISSON_THREADS) poisson_kernel(
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int n = dg.n;
-  const cplx* zi = dg.Z + (size_t)i * n;
+  const cplx* zi = Zc;
   if (lane < dg.d) {
     double x = 0.0;
     for (int k = 0; k < n; ++k) {
@@ -344,8 +365,8 @@ __global__ void __launch_bounds__(POISSON_THREADS) poisson_kernel(
     }
     int j;
     double th;
-    cell_of(x, dg.factor[i], Nx, j, th);
-    Fw[lane] = dg.w[lane] * dg.qm * rho_s[j];
+    cell_of(x, fac_i, Nx, j, th);
+    Fw[lane] = wl * dg.qm * rho_s[j];
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -364,17 +385,18 @@ __global__ void __launch_bounds__(POISSON_THREADS) poisson_kernel(
   if (!dg.counters) return;
   // fixed-point update of column i (entries a = lane < n)
   const cplx* ze = zi;  // Z is the evaluation point of the iteration
+  const cplx* C12 = cs_lds ? Cs : dg.C12;
   cplx knew = mk(0.0, 0.0);
   if (lane < n) {
     const int a = lane;
     cplx sl = mk(0.0, 0.0);
     for (int b = 0; b < n; ++b) {
-      cfma(sl, dg.C12[b * n + a], ze[b]);
-      cfma(sl, cscale(cconj(dg.C12[n * n + b * n + a]), -1.0), cconj(ze[b]));
+      cfma(sl, C12[b * n + a], ze[b]);
+      cfma(sl, cscale(cconj(C12[n * n + b * n + a]), -1.0), cconj(ze[b]));
     }
     g = cadd(g, cscale(sl, 0.5));
     knew = mk(g.im, -g.re);  // -i g
-    const cplx dk = csub(knew, dg.k[(size_t)i * n + a]);
+    const cplx dk = csub(knew, kold);
     buf[a] = cabs2(dk);
     buf[64 + a] = cabs2(knew);
     dg.k[(size_t)i * n + a] = knew;
@@ -393,7 +415,7 @@ __global__ void __launch_bounds__(POISSON_THREADS) poisson_kernel(
     if (!dg.fixed) {
       const double rel = (kn > 0.0) ? sqrt(dn) / sqrt(kn) : sqrt(dn);
       const bool conv = rel < dg.tol;
-      const bool stall = !conv && rel >= dg.prev[i];
+      const bool stall = !conv && rel >= prev_i;
       dg.prev[i] = rel;
       done = conv || stall;
       if (stall) atomicAdd(&dg.counters[1], 1);
@@ -409,7 +431,7 @@ __global__ void __launch_bounds__(POISSON_THREADS) poisson_kernel(
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   if (Fw[0] == 0.0 && lane < n) {
-    const cplx z0 = dg.Z0[(size_t)i * n + lane];
+    const cplx z0 = z0v;
     dg.Zeval[(size_t)i * n + lane] =
         mk(z0.re + 0.5 * dg.dt * knew.re, z0.im + 0.5 * dg.dt * knew.im);
   }
