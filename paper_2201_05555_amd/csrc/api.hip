@@ -677,7 +677,7 @@ RowTerms rt(const cplx* in0, const cplx* M0, int k0, const cplx* in1 = nullptr,
 
 // The field of every column at (U, Z): deposit, then Poisson.
 void full_gradient_field(symrom_rom& r, const cplx* U, const cplx* Z, const int* active,
-                         const int* gate = nullptr) {
+                         const int* gate = nullptr, int* fold = nullptr) {
   hipStream_t s = r.s;
   const int n = r.n;
   {
@@ -688,7 +688,7 @@ void full_gradient_field(symrom_rom& r, const cplx* U, const cplx* Z, const int*
       Timer t(FAM_DEPOSIT, s, 4.0 * n * (double)r.N * pact,
               16.0 * n * ((double)r.N + r.p) + 8.0 * (double)r.gdep.nrb * pact * r.Nx);
       launch_deposit_rom(s, U, r.N, n, Z, r.p, r.Nx, r.gdep, r.b.factor, active, r.b.part,
-                         gate);
+                         gate, fold);
     }
     Timer t(FAM_POISSON, s);
     launch_poisson(s, r.b.part, r.gdep.nrb, r.p, r.Nx, r.b.qw, r.b.h, r.b.mw, active, r.b.rho,
@@ -1069,12 +1069,13 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   std::swap(r.U0, r.Uh);
   std::swap(r.Z0, r.Z1);
   // (the step's error words are final here)
-  if (use_deim) launch_fold_status(s, r.status);
   const bool ahead = use_deim && decide_rank;
+  if (use_deim && !decide_rank) launch_fold_status(s, r.status);
   if (decide_rank) {
-    // the field at the new state, then (beside the DEIM chain ahead, which
-    // needs only the field) its projection and the indicator
-    full_gradient_field(r, r.U0, r.Z0, nullptr);
+    // the field at the new state (its deposit also does the status
+    // bookkeeping with DEIM), then (beside the DEIM chain ahead, which needs
+    // only the field) its projection and the indicator
+    full_gradient_field(r, r.U0, r.Z0, nullptr, nullptr, use_deim ? r.status : nullptr);
     if (ahead) HIPCHK(hipEventRecord(r.ev_fork, s));
     full_gradient(r, r.U0, r.Z0, nullptr, false, true);
     launch_dense_indicator(s, r.colsq, r.gproj, n, p, r.eps_dev);

@@ -56,9 +56,12 @@ void launch_deposit_x(hipStream_t s, const double* X, int N, int p, int Nx, cons
                       const double* factor, double* part);
 // gate (nullable, device): when *gate == 0 the launch does nothing (the
 // fixed point has converged: speculative iterations exit at once)
+// fold (optional): the status words, given the end-of-step bookkeeping by
+// one thread at the start (see fold_status_kernel)
 void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                         const PicGeom& g, const double* factor, const int* active, double* part,
-                        const int* gate = nullptr);
+                        const int* gate = nullptr,
+                        int* fold = nullptr);
 void launch_poisson(hipStream_t s, const double* part, int nrb, int p, int Nx, const double* qw,
                     const double* h, const double* mw, const int* active, double* rho,
                     double* phi, double* e, double* energy, const int* gate = nullptr);

@@ -73,8 +73,18 @@ template <int NC>
 __global__ void __launch_bounds__(deposit_rom_threads<NC>()) deposit_rom_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx, int pt,
     int rpb, const double* __restrict__ factor, const int* __restrict__ active,
-    double* __restrict__ part, const int* __restrict__ gate) {
+    double* __restrict__ part, const int* __restrict__ gate, int* __restrict__ fold) {
   if (gate && gate[0] == 0) return;
+  if (fold && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    // end-of-step bookkeeping of the status words (the step's kernels are
+    // done): the error word of the DEIM chain of the step (3) is folded into
+    // the step's chain word (2) and cleared; the stop word (12) of the chain
+    // enqueued next is set when this step failed
+    const int tail = fold[2] | fold[3];
+    fold[2] = tail;
+    fold[3] = 0;
+    fold[12] = fold[0] | tail;
+  }
   constexpr int R = deposit_rom_rows<NC>();
   extern __shared__ double hist[];                                    // theta sums, pt * Nx
   unsigned* cnt = reinterpret_cast<unsigned*>(hist + (size_t)pt * Nx);  // counts, pt * Nx
@@ -573,14 +583,14 @@ void launch_deposit_x(hipStream_t s, const double* X, int N, int p, int Nx, cons
 
 void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                         const PicGeom& g, const double* factor, const int* active, double* part,
-                        const int* gate) {
+                        const int* gate, int* fold) {
   dim3 grid(g.nrb, (p + g.pt - 1) / g.pt);
   int nc = (n <= 16) ? nc_even(n) : 32;
   size_t sh = (size_t)g.pt * Nx * (sizeof(double) + sizeof(unsigned));
 #define DEP(NCV)                                                                              \
   ALLOW_BIG_LDS(deposit_rom_kernel<NCV>);                                                    \
   hipLaunchKernelGGL(deposit_rom_kernel<NCV>, grid, dim3(deposit_rom_threads<NCV>()), sh, s, U, \
-                     N, n, Z, p, Nx, g.pt, g.rpb, factor, active, part, gate)
+                     N, n, Z, p, Nx, g.pt, g.rpb, factor, active, part, gate, fold)
   switch (nc) {
     case 4: DEP(4); break;
     case 6: DEP(6); break;
