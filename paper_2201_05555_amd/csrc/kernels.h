@@ -35,11 +35,14 @@ struct RowTerms {
   int count;
 };
 
-// register width of the fused kernels: an even count >= n (the position sums
-// split into even and odd k, so every even width gives the same cells)
+// register width of the fused kernels: a count >= n, exact for the small
+// ranks 2n = 10 and 14 (the position sums split into even and odd k, and the
+// columns beyond n are zero, so every width gives the same cells)
 inline int nc_even(int n) {
   if (n <= 4) return 4;
+  if (n == 5) return 5;
   if (n <= 6) return 6;
+  if (n == 7) return 7;
   if (n <= 8) return 8;
   if (n <= 12) return 12;
   return 16;

@@ -132,8 +132,10 @@ __global__ void __launch_bounds__(deposit_rom_threads<NC>()) deposit_rom_kernel(
         for (int k = 0; k < NC; k += 2) {
           x0 = fma(u[r][k].re, z[k].re, x0);
           x0 = fma(-u[r][k].im, z[k].im, x0);
-          x1 = fma(u[r][k + 1].re, z[k + 1].re, x1);
-          x1 = fma(-u[r][k + 1].im, z[k + 1].im, x1);
+          if (k + 1 < NC) {
+            x1 = fma(u[r][k + 1].re, z[k + 1].re, x1);
+            x1 = fma(-u[r][k + 1].im, z[k + 1].im, x1);
+          }
         }
         int j;
         double th;
@@ -593,7 +595,9 @@ void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* 
                      N, n, Z, p, Nx, g.pt, g.rpb, factor, active, part, gate, fold)
   switch (nc) {
     case 4: DEP(4); break;
+    case 5: DEP(5); break;
     case 6: DEP(6); break;
+    case 7: DEP(7); break;
     case 8: DEP(8); break;
     case 12: DEP(12); break;
     case 16: DEP(16); break;

@@ -395,10 +395,12 @@ __global__ void __launch_bounds__(512) gather_project_kernel(
         x0 = fma(-u[k].im, z[k].im, x0);
         v0 = fma(u[k].re, z[k].im, v0);
         v0 = fma(u[k].im, z[k].re, v0);
-        x1 = fma(u[k + 1].re, z[k + 1].re, x1);
-        x1 = fma(-u[k + 1].im, z[k + 1].im, x1);
-        v1 = fma(u[k + 1].re, z[k + 1].im, v1);
-        v1 = fma(u[k + 1].im, z[k + 1].re, v1);
+        if (k + 1 < NC) {
+          x1 = fma(u[k + 1].re, z[k + 1].re, x1);
+          x1 = fma(-u[k + 1].im, z[k + 1].im, x1);
+          v1 = fma(u[k + 1].re, z[k + 1].im, v1);
+          v1 = fma(u[k + 1].im, z[k + 1].re, v1);
+        }
       }
       const double v = v0 + v1;
       int j;
@@ -572,15 +574,18 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
       v1[q] = 0.0;
 #pragma unroll
       for (int k = 0; k < NC; k += 2) {
-        const cplx za = zc[k], zb = zc[k + 1];
+        const cplx za = zc[k];
         x0[q] = fma(u[k].re, za.re, x0[q]);
         x0[q] = fma(-u[k].im, za.im, x0[q]);
         v0[q] = fma(u[k].re, za.im, v0[q]);
         v0[q] = fma(u[k].im, za.re, v0[q]);
-        x1[q] = fma(u[k + 1].re, zb.re, x1[q]);
-        x1[q] = fma(-u[k + 1].im, zb.im, x1[q]);
-        v1[q] = fma(u[k + 1].re, zb.im, v1[q]);
-        v1[q] = fma(u[k + 1].im, zb.re, v1[q]);
+        if (k + 1 < NC) {
+          const cplx zb = zc[k + 1];
+          x1[q] = fma(u[k + 1].re, zb.re, x1[q]);
+          x1[q] = fma(-u[k + 1].im, zb.im, x1[q]);
+          v1[q] = fma(u[k + 1].re, zb.im, v1[q]);
+          v1[q] = fma(u[k + 1].im, zb.re, v1[q]);
+        }
       }
     }
     double F[ILP];
@@ -1101,8 +1106,10 @@ __global__ void __launch_bounds__(256) snapshot_kernel(const cplx* __restrict__ 
     for (int k = 0; k < NC; k += 2) {
       x0 = fma(u[k].re, zc[k].re, x0);
       x0 = fma(-u[k].im, zc[k].im, x0);
-      x1 = fma(u[k + 1].re, zc[k + 1].re, x1);
-      x1 = fma(-u[k + 1].im, zc[k + 1].im, x1);
+      if (k + 1 < NC) {
+        x1 = fma(u[k + 1].re, zc[k + 1].re, x1);
+        x1 = fma(-u[k + 1].im, zc[k + 1].im, x1);
+      }
     }
     int j;
     double th;
@@ -1154,7 +1161,9 @@ void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cpl
   if (et_lds) {
     switch (nc) {
       case 4: GPK(4, true); break;
+      case 5: GPK(5, true); break;
       case 6: GPK(6, true); break;
+      case 7: GPK(7, true); break;
       case 8: GPK(8, true); break;
       case 12: GPK(12, true); break;
       default: GPK(16, true); break;
@@ -1162,7 +1171,9 @@ void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cpl
   } else {
     switch (nc) {
       case 4: GPK(4, false); break;
+      case 5: GPK(5, false); break;
       case 6: GPK(6, false); break;
+      case 7: GPK(7, false); break;
       case 8: GPK(8, false); break;
       case 12: GPK(12, false); break;
       default: GPK(16, false); break;
@@ -1191,7 +1202,9 @@ void launch_gather_xi(hipStream_t s, const cplx* U, int N, int n, const cplx* Z,
   if (et_lds) {
     switch (nc) {
       case 4: GXK(4, true); break;
+      case 5: GXK(5, true); break;
       case 6: GXK(6, true); break;
+      case 7: GXK(7, true); break;
       case 8: GXK(8, true); break;
       case 12: GXK(12, true); break;
       default: GXK(16, true); break;
@@ -1199,7 +1212,9 @@ void launch_gather_xi(hipStream_t s, const cplx* U, int N, int n, const cplx* Z,
   } else {
     switch (nc) {
       case 4: GXK(4, false); break;
+      case 5: GXK(5, false); break;
       case 6: GXK(6, false); break;
+      case 7: GXK(7, false); break;
       case 8: GXK(8, false); break;
       case 12: GXK(12, false); break;
       default: GXK(16, false); break;
@@ -1390,7 +1405,9 @@ void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, 
   if (ph_lds) {
     switch (nc) {
       case 4: SN(4, true); break;
+      case 5: SN(5, true); break;
       case 6: SN(6, true); break;
+      case 7: SN(7, true); break;
       case 8: SN(8, true); break;
       case 12: SN(12, true); break;
       case 16: SN(16, true); break;
@@ -1399,7 +1416,9 @@ void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, 
   } else {
     switch (nc) {
       case 4: SN(4, false); break;
+      case 5: SN(5, false); break;
       case 6: SN(6, false); break;
+      case 7: SN(7, false); break;
       case 8: SN(8, false); break;
       case 12: SN(12, false); break;
       case 16: SN(16, false); break;
