@@ -798,8 +798,7 @@ void cayley_cholqr2(symrom_rom& r, const cplx* U0, const cplx* xi, cplx* Uout, c
   launch_dense_chol(s, G1, n, r.Rinv, Z, r.p, r.flags, r.MU, r.MX);
   launch_rowgemm(s, rt(U0, r.MU, n, xi, r.MX, n), r.N, n, Uout);
   launch_gemm_ah_b(s, ml(Uout, n), n, ml(Uout, n), n, false, r.N, r.nkb, r.gemm_part, r.Gram);
-  launch_dense_chol(s, r.Gram, n, r.Rinv, Z, r.p, r.flags);
-  launch_rowgemm(s, rt(Uout, r.Rinv, n), r.N, n, Uout);
+  launch_cholqr_apply(s, r.Gram, n, Uout, r.N, Z, r.p, r.flags);
 }
 
 // two Cholesky-QR passes on U (N x n) with Z <- R Z
@@ -809,8 +808,7 @@ void cholqr2(symrom_rom& r, cplx* U, cplx* Z) {
   Timer t(FAM_BASIS, s);
   for (int pass = 0; pass < 2; ++pass) {
     launch_gemm_ah_b(s, ml(U, n), n, ml(U, n), n, false, r.N, r.nkb, r.gemm_part, r.Gram);
-    launch_dense_chol(s, r.Gram, n, r.Rinv, Z, r.p, r.flags);
-    launch_rowgemm(s, rt(U, r.Rinv, n), r.N, n, U);
+    launch_cholqr_apply(s, r.Gram, n, U, r.N, Z, r.p, r.flags);
   }
 }
 

@@ -737,6 +737,64 @@ __global__ void __launch_bounds__(DTPB) dense_chol_kernel(const cplx* __restrict
   }
 }
 
+// One Cholesky-QR pass in one launch: every block factors the n x n Gram
+// U~^* U~ = R^* R itself (a few microseconds, beside its loads of U~) and
+// forms R^{-1}, then U~ <- U~ R^{-1} for its rows; block 0 also writes
+// Z~ <- R Z~.  Replaces a Cholesky launch followed by a row combination.
+template <int MC>
+__global__ void __launch_bounds__(256) cholqr_apply_kernel(const cplx* __restrict__ Gram, int n,
+                                                           cplx* __restrict__ U, int N,
+                                                           cplx* __restrict__ Z, int p,
+                                                           int* __restrict__ flags) {
+  __shared__ cplx G[MC * MC], R[MC * MC], Ri[MC * MC];
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lc = min(l, N - 1);
+  // this thread's row of U~, loaded before the factorisation
+  cplx u[MC];
+#pragma unroll
+  for (int k = 0; k < MC; ++k) {
+    const cplx v = U[(size_t)min(k, n - 1) * N + lc];
+    u[k] = (k < n) ? v : mk(0.0, 0.0);
+  }
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) G[t] = Gram[t];
+  __syncthreads();
+  if (bk_chol(G, R, n, 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && flags) atomicOr(&flags[0], 2);
+    return;
+  }
+  bk_triu_inv(R, Ri, n);
+  if (l < N) {
+    // row of U~ R^{-1} (R^{-1} upper triangular)
+#pragma unroll
+    for (int c = 0; c < MC; ++c) {
+      if (c < n) {
+        cplx sc = mk(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k <= c; ++k) cfma(sc, u[k], Ri[c * n + k]);
+        U[(size_t)c * N + l] = sc;
+      }
+    }
+  }
+  if (blockIdx.x == 0 && Z) {
+    // Z <- R Z, one column per thread (the column is read before written)
+    for (int i = threadIdx.x; i < p; i += blockDim.x) {
+      cplx zc[MC];
+#pragma unroll
+      for (int a = 0; a < MC; ++a) zc[a] = (a < n) ? Z[(size_t)i * n + a] : mk(0.0, 0.0);
+#pragma unroll
+      for (int a = 0; a < MC; ++a) {
+        if (a < n) {
+          cplx sz = mk(0.0, 0.0);
+#pragma unroll
+          for (int b = a; b < MC; ++b)
+            if (b < n) cfma(sz, R[b * n + a], zc[b]);
+          Z[(size_t)i * n + a] = sz;
+        }
+      }
+    }
+  }
+}
+
 // Fixed-point control of the implicit midpoint stage (one thread per
 // column).  k_new = -i g (g = gF, plus (C1 Z - conj(C2) conj(Z)) / 2 when the
 // projection covered positions only: i U~^* V_r with V_r = Im(U~ Z~)).
@@ -996,6 +1054,16 @@ void launch_dense_chol(hipStream_t s, const cplx* Gram, int n, cplx* Rinv, cplx*
   ALLOW_BIG_LDS(dense_chol_kernel);
   hipLaunchKernelGGL(dense_chol_kernel, dim3(1), dim3(dense_chain_threads(n)), sh, s, Gram, n,
                      Rinv, Z, p, MU, MX, flags);
+}
+void launch_cholqr_apply(hipStream_t s, const cplx* Gram, int n, cplx* U, int N, cplx* Z, int p,
+                         int* flags) {
+  dim3 grid((N + 255) / 256);
+  if (n <= 8)
+    hipLaunchKernelGGL(cholqr_apply_kernel<8>, grid, dim3(256), 0, s, Gram, n, U, N, Z, p, flags);
+  else if (n <= 16)
+    hipLaunchKernelGGL(cholqr_apply_kernel<16>, grid, dim3(256), 0, s, Gram, n, U, N, Z, p, flags);
+  else
+    hipLaunchKernelGGL(cholqr_apply_kernel<32>, grid, dim3(256), 0, s, Gram, n, U, N, Z, p, flags);
 }
 void launch_dense_fp_update(hipStream_t s, const cplx* gF, const cplx* C12, int n, int p,
                             const cplx* Z0, cplx* Zeval, cplx* ZG, cplx* k, double* prev,

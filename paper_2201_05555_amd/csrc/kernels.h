@@ -154,6 +154,10 @@ void launch_dense_tangent2(hipStream_t s, const cplx* Gram3, const cplx* C0x, in
 // xi1 = X K1 + xi K2 + U0 K3 (n x n each)
 void launch_dense_tangent(hipStream_t s, const cplx* G4, int n, double dt, cplx* K1, cplx* K2,
                           cplx* K3, int* flags);
+// one Cholesky-QR pass: Gram = U~^* U~ = R^* R, U~ <- U~ R^{-1} (N rows), and
+// Z~ <- R Z~ (n x p) when Z is given
+void launch_cholqr_apply(hipStream_t s, const cplx* Gram, int n, cplx* U, int N, cplx* Z, int p,
+                         int* flags);
 // MU, MX (optional): multiplied by R^{-1} in place
 void launch_dense_chol(hipStream_t s, const cplx* Gram, int n, cplx* Rinv, cplx* Z, int p,
                        int* flags, cplx* MU = nullptr, cplx* MX = nullptr);
