@@ -436,7 +436,7 @@ struct symrom_rom {
   int* counters;
   int* flags;
   int* hstat;  // pinned host mirror of the status block
-  cplx *Gram, *Amat, *MU, *MX, *M1, *M2, *M3, *C0x, *Rinv, *MP;
+  cplx *Gram, *Amat, *MU, *MX, *M1, *M2, *M3, *C0x, *MP;
   cplx* gemm_part;
   double* sigma2;
   double* eps_dev;
@@ -540,7 +540,6 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.M2 = ar.take<cplx>((size_t)nm * nm);
   r.M3 = ar.take<cplx>((size_t)nm * nm);
   r.C0x = ar.take<cplx>((size_t)nm * nm);
-  r.Rinv = ar.take<cplx>((size_t)nm * nm);
   r.MP = ar.take<cplx>((size_t)nm * nm);
   // split-K partials: nkb * max(a*b) with a, b <= 64 (b chunked by 64)
   r.gemm_part = ar.take<cplx>((size_t)r.nkb * 64 * 64);
@@ -791,11 +790,9 @@ void cayley_cholqr2(symrom_rom& r, const cplx* U0, const cplx* xi, cplx* Uout, c
   hipStream_t s = r.s;
   const int n = r.n;
   Timer t(FAM_BASIS, s);
-  cplx* G1 = r.Gram + (size_t)4 * n * n;
   launch_gemm_ah_b(s, ml(U0, n, xi, n), 2 * n, ml(U0, n, xi, n), 2 * n, false, r.N, r.nkb,
                    r.gemm_part, r.Gram);
-  launch_dense_cayley(s, r.Gram, n, A_out, r.MU, r.MX, r.flags, G1);
-  launch_dense_chol(s, G1, n, r.Rinv, Z, r.p, r.flags, r.MU, r.MX);
+  launch_dense_cayley(s, r.Gram, n, A_out, r.MU, r.MX, r.flags, true, Z, r.p);
   launch_rowgemm(s, rt(U0, r.MU, n, xi, r.MX, n), r.N, n, Uout);
   launch_gemm_ah_b(s, ml(Uout, n), n, ml(Uout, n), n, false, r.N, r.nkb, r.gemm_part, r.Gram);
   launch_cholqr_apply(s, r.Gram, n, Uout, r.N, Z, r.p, r.flags);

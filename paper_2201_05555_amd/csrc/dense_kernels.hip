@@ -398,13 +398,14 @@ __global__ void __launch_bounds__(DTPB) dense_xfinish_kernel(const cplx* __restr
 //   K = (I - Rc^* Lc / 2)^{-1},  [Y1; Y2] = K Rc^* U0,
 //   R_{U0}(xi) = U0 + W Y1 - U0 Y2 = U0 (I - Y2 - A Y1 / 2) + xi Y1.
 // Output MU, MX (n x n) for the row combination, and A.
-// G1 (optional, n x n): the Gram of the result, [MU; MX]^* Gram [MU; MX],
-// for a Cholesky QR of R_{U0}(xi) without a pass over its rows.
+// chol: also one Cholesky-QR pass of R_{U0}(xi) without a pass over its rows.
+// Its Gram is G1 = [MU; MX]^* Gram [MU; MX] = R^* R; MU, MX are returned
+// multiplied by R^{-1} and Z (n x p, optional) is replaced by R Z.
 __global__ void __launch_bounds__(DTPB) dense_cayley_kernel(const cplx* __restrict__ Gram, int n,
                                                             cplx* __restrict__ A_out,
                                                             cplx* __restrict__ MU,
                                                             cplx* __restrict__ MX,
-                                                            cplx* __restrict__ G1,
+                                                            cplx* __restrict__ Z, int p, int chol,
                                                             int* __restrict__ flags) {
   extern __shared__ cplx sm[];
   const int m = 2 * n;
@@ -419,6 +420,9 @@ __global__ void __launch_bounds__(DTPB) dense_cayley_kernel(const cplx* __restri
   cplx* Gxx = K;               // xi^* xi   (phase 1 only)
   cplx* T1 = K + n * n;        // scratch  (phase 1 only)
   __shared__ int piv;
+  cplx* Zs = sm + 18 * n * n;  // n x p, chol with Z only; loaded now, used last
+  if (chol && Z)
+    for (int t = threadIdx.x; t < n * p; t += blockDim.x) Zs[t] = Z[t];
   for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
     int a = t % n, b = t / n;
     G00[t] = Gram[b * m + a];
@@ -462,34 +466,56 @@ __global__ void __launch_bounds__(DTPB) dense_cayley_kernel(const cplx* __restri
   cplx* Y1 = UW;
   for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
     int r = t % n, c = t / n;
-    MX[t] = B[c * m + r];
+    if (!chol) MX[t] = B[c * m + r];
     Y1[t] = B[c * m + r];
   }
   __syncthreads();
   bk_matmul(WW, A, 0, Y1, 0, n, n, n);  // A Y1
-  // [MU; MX] (2n x n) kept in LDS past the end of B when G1 is wanted
+  // [MU; MX] (2n x n) kept in LDS past the end of B for the Cholesky pass
   cplx* Wm = B + m * n;
   for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
     int r = t % n, c = t / n;
     cplx v = cscale(B[c * m + n + r], -1.0);
     v = csub(v, cscale(WW[t], 0.5));
     if (r == c) v.re += 1.0;
-    MU[t] = v;
     if (A_out) A_out[t] = A[t];
-    if (G1) {
+    if (chol) {
       Wm[c * m + r] = v;
       Wm[c * m + n + r] = B[c * m + r];
+    } else {
+      MU[t] = v;
     }
   }
-  if (!G1) return;
+  if (!chol) return;
   // G1 = W^* (Gram W), W = [MU; MX]; the Gram again from memory
-  cplx* Gs = Wm + m * n;  // 2n x 2n
+  cplx* Gs = Wm + m * n;  // 2n x 2n region: G1, then R and R^{-1} beside it
   cplx* T = Gs + m * m;   // 2n x n
+  cplx* R = Gs + n * n;
+  cplx* Ri = R + n * n;
   for (int t = threadIdx.x; t < m * m; t += blockDim.x) Gs[t] = Gram[t];
   __syncthreads();
   bk_matmul(T, Gs, 0, Wm, 0, m, m, n);
   bk_matmul(Gs, Wm, 1, T, 0, n, m, n);
-  for (int t = threadIdx.x; t < n * n; t += blockDim.x) G1[t] = Gs[t];
+  if (bk_chol(Gs, R, n, 0.0)) {
+    if (threadIdx.x == 0 && flags) atomicOr(&flags[0], 2);
+    return;
+  }
+  bk_triu_inv(R, Ri, n);
+  bk_matmul(T, Wm, 0, Ri, 0, m, n, n);  // [MU; MX] R^{-1}
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    int r = t % n, c = t / n;
+    MU[t] = T[c * m + r];
+    MX[t] = T[c * m + n + r];
+  }
+  if (Z) {
+    // Z <- R Z from the copy in LDS, one entry per thread (R upper triangular)
+    for (int t = threadIdx.x; t < n * p; t += blockDim.x) {
+      const int a = t % n, i = t / n;
+      cplx sz = mk(0.0, 0.0);
+      for (int b = a; b < n; ++b) cfma(sz, R[b * n + a], Zs[i * n + b]);
+      Z[t] = sz;
+    }
+  }
 }
 
 // Tangent velocity, first half.  Input A = U0^* xi and
@@ -685,55 +711,6 @@ __global__ void __launch_bounds__(DTPB) dense_tangent_kernel(const cplx* __restr
     K1[t] = cscale(Mi[t], 2.0 * dt);
     K2[t] = cscale(M2[t], dt);
     K3[t] = cscale(csub(M3[t], C), dt);
-  }
-}
-
-// Cholesky QR step: Gram = U~^* U~ = R^* R; Rinv = R^{-1} for U~ <- U~ R^{-1};
-// Z~ <- R Z~ in place (n x p).
-// MU, MX (optional, n x n each): replaced by MU R^{-1}, MX R^{-1}, so that a
-// row combination U0 MU + xi MX lands on the factored basis directly.
-__global__ void __launch_bounds__(DTPB) dense_chol_kernel(const cplx* __restrict__ Gram, int n,
-                                                          cplx* __restrict__ Rinv,
-                                                          cplx* __restrict__ Z, int p,
-                                                          cplx* __restrict__ MU,
-                                                          cplx* __restrict__ MX,
-                                                          int* __restrict__ flags) {
-  extern __shared__ cplx sm[];
-  cplx* G = sm;          // n x n
-  cplx* R = G + n * n;
-  cplx* Ri = R + n * n;
-  cplx* Zs = Ri + n * n;  // n x p (when Z is given)
-  for (int t = threadIdx.x; t < n * n; t += blockDim.x) G[t] = Gram[t];
-  if (Z)
-    for (int t = threadIdx.x; t < n * p; t += blockDim.x) Zs[t] = Z[t];
-  __syncthreads();
-  if (bk_chol(G, R, n, 0.0)) {
-    if (threadIdx.x == 0 && flags) flags[0] |= 2;
-    return;
-  }
-  bk_triu_inv(R, Ri, n);
-  for (int t = threadIdx.x; t < n * n; t += blockDim.x) Rinv[t] = Ri[t];
-  if (MU) {
-    // M <- M R^{-1} for M = MU, MX (two n x n scratch after Zs)
-    cplx* Ms = Zs + (Z ? n * p : 0);
-    cplx* Ts = Ms + n * n;
-    for (int q = 0; q < 2; ++q) {
-      cplx* M = q ? MX : MU;
-      for (int t = threadIdx.x; t < n * n; t += blockDim.x) Ms[t] = M[t];
-      __syncthreads();
-      bk_matmul(Ts, Ms, 0, Ri, 0, n, n, n);
-      for (int t = threadIdx.x; t < n * n; t += blockDim.x) M[t] = Ts[t];
-      __syncthreads();
-    }
-  }
-  if (Z) {
-    // Z <- R Z, one entry per thread (R upper triangular)
-    for (int t = threadIdx.x; t < n * p; t += blockDim.x) {
-      const int a = t % n, i = t / n;
-      cplx s = mk(0.0, 0.0);
-      for (int b = a; b < n; ++b) cfma(s, R[b * n + a], Zs[i * n + b]);
-      Z[t] = s;
-    }
   }
 }
 
@@ -1021,12 +998,13 @@ void launch_dense_xfinish(hipStream_t s, const cplx* g, const cplx* Q, int n, in
                      MU);
 }
 void launch_dense_cayley(hipStream_t s, const cplx* Gram, int n, cplx* A_out, cplx* MU,
-                         cplx* MX, int* flags, cplx* G1) {
-  // 10 n^2 for the solve; with G1, W (2 n^2), the Gram (4 n^2) and T (2 n^2)
-  size_t sh = (size_t)((G1 ? 18 : 10) * n * n) * sizeof(cplx);
+                         cplx* MX, int* flags, bool chol, cplx* Z, int p) {
+  // 10 n^2 for the solve; with chol, W (2 n^2), the Gram (4 n^2), T (2 n^2)
+  // and Z (n p)
+  size_t sh = (size_t)((chol ? 18 : 10) * n * n + (chol && Z ? n * p : 0)) * sizeof(cplx);
   ALLOW_BIG_LDS(dense_cayley_kernel);
   hipLaunchKernelGGL(dense_cayley_kernel, dim3(1), dim3(dense_chain_threads(n)), sh, s, Gram, n,
-                     A_out, MU, MX, G1, flags);
+                     A_out, MU, MX, Z, p, (int)chol, flags);
 }
 void launch_dense_tangent1(hipStream_t s, const cplx* A, const cplx* Gram2, int n, cplx* M1,
                            cplx* M2, cplx* M3, cplx* C0x_out, int* flags) {
@@ -1047,13 +1025,6 @@ void launch_dense_tangent(hipStream_t s, const cplx* G4, int n, double dt, cplx*
   ALLOW_BIG_LDS(dense_tangent_kernel);
   hipLaunchKernelGGL(dense_tangent_kernel, dim3(1), dim3(dense_chain_threads(n)), sh, s, G4, n, dt,
                      K1, K2, K3, flags);
-}
-void launch_dense_chol(hipStream_t s, const cplx* Gram, int n, cplx* Rinv, cplx* Z, int p,
-                       int* flags, cplx* MU, cplx* MX) {
-  const size_t sh = (size_t)(3 * n * n + (Z ? n * p : 0) + (MU ? 2 * n * n : 0)) * sizeof(cplx);
-  ALLOW_BIG_LDS(dense_chol_kernel);
-  hipLaunchKernelGGL(dense_chol_kernel, dim3(1), dim3(dense_chain_threads(n)), sh, s, Gram, n,
-                     Rinv, Z, p, MU, MX, flags);
 }
 void launch_cholqr_apply(hipStream_t s, const cplx* Gram, int n, cplx* U, int N, cplx* Z, int p,
                          int* flags) {

@@ -142,10 +142,10 @@ void launch_dense_spinv(hipStream_t s, const cplx* Z, int n, int p, double rtol,
                         double* sigma2, int* flags);
 void launch_dense_xfinish(hipStream_t s, const cplx* g, const cplx* Q, int n, int p, double dt,
                           cplx* k1, cplx* MP, cplx* MU);
-// G1 (optional): the n x n Gram of the retraction's result, from the 2n x 2n
-// Gram and the row-combination matrices
+// chol: also one Cholesky-QR pass of the retraction's result from the 2n x 2n
+// Gram alone (R^* R = its Gram): MU, MX returned times R^{-1}, Z <- R Z
 void launch_dense_cayley(hipStream_t s, const cplx* Gram, int n, cplx* A_out, cplx* MU,
-                         cplx* MX, int* flags, cplx* G1 = nullptr);
+                         cplx* MX, int* flags, bool chol = false, cplx* Z = nullptr, int p = 0);
 void launch_dense_tangent1(hipStream_t s, const cplx* A, const cplx* Gram2, int n, cplx* M1,
                            cplx* M2, cplx* M3, cplx* C0x_out, int* flags);
 void launch_dense_tangent2(hipStream_t s, const cplx* Gram3, const cplx* C0x, int n, double dt,
@@ -158,9 +158,6 @@ void launch_dense_tangent(hipStream_t s, const cplx* G4, int n, double dt, cplx*
 // Z~ <- R Z~ (n x p) when Z is given
 void launch_cholqr_apply(hipStream_t s, const cplx* Gram, int n, cplx* U, int N, cplx* Z, int p,
                          int* flags);
-// MU, MX (optional): multiplied by R^{-1} in place
-void launch_dense_chol(hipStream_t s, const cplx* Gram, int n, cplx* Rinv, cplx* Z, int p,
-                       int* flags, cplx* MU = nullptr, cplx* MX = nullptr);
 void launch_dense_fp_update(hipStream_t s, const cplx* gF, const cplx* C12, int n, int p,
                             const cplx* Z0, cplx* Zeval, cplx* ZG, cplx* k, double* prev,
                             int* active, double dt, double tol, int fixed, int linear_part,
