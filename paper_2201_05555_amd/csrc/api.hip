@@ -793,8 +793,12 @@ void cayley_cholqr2(symrom_rom& r, const cplx* U0, const cplx* xi, cplx* Uout, c
   launch_gemm_ah_b(s, ml(U0, n, xi, n), 2 * n, ml(U0, n, xi, n), 2 * n, false, r.N, r.nkb,
                    r.gemm_part, r.Gram);
   launch_dense_cayley(s, r.Gram, n, A_out, r.MU, r.MX, r.flags, true, Z, r.p);
-  launch_rowgemm(s, rt(U0, r.MU, n, xi, r.MX, n), r.N, n, Uout);
-  launch_gemm_ah_b(s, ml(Uout, n), n, ml(Uout, n), n, false, r.N, r.nkb, r.gemm_part, r.Gram);
+  // the once-factored basis and, in the same pass, its Gram for the second
+  if (!launch_rowgemm_gram(s, rt(U0, r.MU, n, xi, r.MX, n), r.N, n, Uout, r.gemm_part,
+                           (size_t)r.nkb * 64 * 64, r.Gram)) {
+    launch_rowgemm(s, rt(U0, r.MU, n, xi, r.MX, n), r.N, n, Uout);
+    launch_gemm_ah_b(s, ml(Uout, n), n, ml(Uout, n), n, false, r.N, r.nkb, r.gemm_part, r.Gram);
+  }
   launch_cholqr_apply(s, r.Gram, n, Uout, r.N, Z, r.p, r.flags);
 }
 

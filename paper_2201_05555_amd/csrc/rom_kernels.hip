@@ -284,6 +284,78 @@ __global__ void __launch_bounds__(256) rowgemm_kernel(RowTerms T, int N, int m, 
     if (o < m) out[(size_t)o * N + l] = acc[o];
 }
 
+// The row combination for m <= 8 output columns that also forms the split-K
+// partials of the Gram of its output, O^* O: the block's rows are kept in LDS
+// and each upper-triangle entry (i <= j) is summed over four 64-row chunks,
+// the chunks then in order; part[block][j m + i] holds the entry and
+// part[block][i m + j] its conjugate (the layout of gemm_ah_b_kernel).
+template <int MC>
+__global__ void __launch_bounds__(256) rowgemm_gram_kernel(RowTerms T, int N, int m,
+                                                           cplx* __restrict__ out,
+                                                           cplx* __restrict__ part) {
+  extern __shared__ cplx Ms[];
+  __shared__ cplx Os[256 * MC];
+  __shared__ cplx red[4][MC * (MC + 1) / 2];
+  int off = 0;
+  for (int s = 0; s < T.count; ++s) {
+    for (int t = threadIdx.x; t < T.k[s] * m; t += blockDim.x) Ms[off + t] = T.M[s][t];
+    off += T.k[s] * m;
+  }
+  __syncthreads();
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  cplx acc[MC];
+#pragma unroll
+  for (int o = 0; o < MC; ++o) acc[o] = mk(0.0, 0.0);
+  if (l < N) {
+    off = 0;
+    for (int s = 0; s < T.count; ++s) {
+      const cplx* in = T.in[s];
+      const int ks = T.k[s];
+      for (int k = 0; k < ks; ++k) {
+        const cplx v = in[(size_t)k * N + l];
+        const cplx* mrow = Ms + off + k;  // M[k][o] at mrow[o * ks]
+#pragma unroll
+        for (int o = 0; o < MC; ++o)
+          if (o < m) cfma(acc[o], v, mrow[o * ks]);
+      }
+      off += ks * m;
+    }
+#pragma unroll
+    for (int o = 0; o < MC; ++o)
+      if (o < m) out[(size_t)o * N + l] = acc[o];
+  }
+  // rows past N stay zero and add nothing
+#pragma unroll
+  for (int o = 0; o < MC; ++o) Os[threadIdx.x * MC + o] = acc[o];
+  __syncthreads();
+  const int npair = m * (m + 1) / 2;
+  const int pr = threadIdx.x & 63, chunk = threadIdx.x >> 6;
+  int pi = 0, pj = 0;
+  if (pr < npair) {
+    // pair index -> (i, j), i <= j, column by column
+    int q = pr;
+    while (q > pj) {
+      q -= pj + 1;
+      ++pj;
+    }
+    pi = q;
+    cplx sacc = mk(0.0, 0.0);
+    for (int rr = 0; rr < 64; ++rr) {
+      const cplx* orow = Os + (chunk * 64 + rr) * MC;
+      cfma(sacc, cconj(orow[pi]), orow[pj]);
+    }
+    red[chunk][pr] = sacc;
+  }
+  __syncthreads();
+  if (chunk == 0 && pr < npair) {
+    cplx g = red[0][pr];
+    for (int c = 1; c < 4; ++c) g = cadd(g, red[c][pr]);
+    cplx* pb = part + (size_t)blockIdx.x * m * m;
+    pb[pj * m + pi] = g;
+    if (pi != pj) pb[pi * m + pj] = cconj(g);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // DEIM gather (eq. grHDD with the exact potential): for the d sampled rows
 // I_r, g_F[k,i] = sum_r conj(U~[I_r,k]) w_r (q/m) e_i[j(x_{I_r,i})].
@@ -1311,6 +1383,22 @@ void launch_gemm_flags(hipStream_t s, const MatList& A, int a, const MatList& B,
 void launch_gemm_ah_b(hipStream_t s, const MatList& A, int a, const MatList& B, int b, bool b_real,
                       int N, int nkb, cplx* part, cplx* C) {
   launch_gemm_flags(s, A, a, B, b, b_real ? GEMM_B_REAL : 0, N, nkb, part, C);
+}
+
+bool launch_rowgemm_gram(hipStream_t s, const RowTerms& T, int N, int m, cplx* out, cplx* part,
+                         size_t part_cap, cplx* Gram) {
+  const int nb = (N + 255) / 256;
+  if (m > 8 || (size_t)nb * m * m > part_cap) return false;
+  size_t sh = 0;
+  for (int q = 0; q < T.count; ++q) sh += (size_t)T.k[q] * m * sizeof(cplx);
+  if (m <= 4)
+    hipLaunchKernelGGL(rowgemm_gram_kernel<4>, dim3(nb), dim3(256), sh, s, T, N, m, out, part);
+  else
+    hipLaunchKernelGGL(rowgemm_gram_kernel<8>, dim3(nb), dim3(256), sh, s, T, N, m, out, part);
+  const int nout = m * m;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((nout + 3) / 4), dim3(256), 0, s, part, nb, nout,
+                     Gram);
+  return true;
 }
 
 void launch_rowgemm(hipStream_t s, const RowTerms& T, int N, int m, cplx* out) {
