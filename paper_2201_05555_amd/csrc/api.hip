@@ -769,12 +769,15 @@ void basis_velocity(symrom_rom& r, const cplx* U, const cplx* Z, double scale, c
 }
 
 // U_out = R_{U0}(xi) (Cayley retraction); A_out receives U0^* xi.
-void cayley(symrom_rom& r, const cplx* U0, const cplx* xi, cplx* Uout, cplx* A_out) {
+// gram_ready: r.Gram already holds [U0, xi]^* [U0, xi].
+void cayley(symrom_rom& r, const cplx* U0, const cplx* xi, cplx* Uout, cplx* A_out,
+            bool gram_ready = false) {
   hipStream_t s = r.s;
   const int n = r.n;
   Timer t(FAM_BASIS, s);
-  launch_gemm_ah_b(s, ml(U0, n, xi, n), 2 * n, ml(U0, n, xi, n), 2 * n, false, r.N, r.nkb,
-                   r.gemm_part, r.Gram);
+  if (!gram_ready)
+    launch_gemm_ah_b(s, ml(U0, n, xi, n), 2 * n, ml(U0, n, xi, n), 2 * n, false, r.N, r.nkb,
+                     r.gemm_part, r.Gram);
   launch_dense_cayley(s, r.Gram, n, A_out, r.MU, r.MX, r.flags);
   launch_rowgemm(s, rt(U0, r.MU, n, xi, r.MX, n), r.N, n, Uout);
 }
@@ -786,12 +789,13 @@ void cayley(symrom_rom& r, const cplx* U0, const cplx* xi, cplx* Uout, cplx* A_o
 // forms the once-factored basis.  Needs 4n <= 64 (the Gram of [U0, xi] and
 // the row combination as for cayley).
 void cayley_cholqr2(symrom_rom& r, const cplx* U0, const cplx* xi, cplx* Uout, cplx* A_out,
-                    cplx* Z) {
+                    cplx* Z, bool gram_ready = false) {
   hipStream_t s = r.s;
   const int n = r.n;
   Timer t(FAM_BASIS, s);
-  launch_gemm_ah_b(s, ml(U0, n, xi, n), 2 * n, ml(U0, n, xi, n), 2 * n, false, r.N, r.nkb,
-                   r.gemm_part, r.Gram);
+  if (!gram_ready)
+    launch_gemm_ah_b(s, ml(U0, n, xi, n), 2 * n, ml(U0, n, xi, n), 2 * n, false, r.N, r.nkb,
+                     r.gemm_part, r.Gram);
   launch_dense_cayley(s, r.Gram, n, A_out, r.MU, r.MX, r.flags, true, Z, r.p);
   // the once-factored basis and, in the same pass, its Gram for the second
   if (!launch_rowgemm_gram(s, rt(U0, r.MU, n, xi, r.MX, n), r.N, n, Uout, r.gemm_part,
@@ -1035,6 +1039,7 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   if (side) HIPCHK(hipStreamWaitEvent(s, r.ev_sp1, 0));
   basis_velocity(r, r.Uh, r.ZG, 1.0, r.Xv, nullptr, side);
   // tangent velocity Y(xi_half, Z_G)
+  bool gram_ready = false;
   if (4 * n <= 64) {
     // one Gram of [U0, xi, U_half, X] and one row combination (the
     // intermediate Ups is never formed)
@@ -1043,7 +1048,11 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
                      ml(r.U0, n, r.Xi, n, r.Uh, n, r.Xv, n), 4 * n, false, N, r.nkb, r.gemm_part,
                      r.Gram);
     launch_dense_tangent(s, r.Gram, n, dt, r.M1, r.M2, r.M3, r.flags);
-    launch_rowgemm(s, rt(r.Xv, r.M1, n, r.Xi, r.M2, n, r.U0, r.M3, n), N, n, r.P);  // xi_1
+    // xi_1, and in the same pass the Gram of [U0, xi_1] for the retraction
+    gram_ready = launch_rowgemm_gram(s, rt(r.Xv, r.M1, n, r.Xi, r.M2, n, r.U0, r.M3, n), N, n,
+                                     r.P, r.gemm_part, (size_t)r.nkb * 64 * 64, r.Gram, r.U0, n);
+    if (!gram_ready)
+      launch_rowgemm(s, rt(r.Xv, r.M1, n, r.Xi, r.M2, n, r.U0, r.M3, n), N, n, r.P);
   } else {
     Timer t(FAM_BASIS, s);
     launch_gemm_ah_b(s, ml(r.U0, n, r.Xi, n), 2 * n, ml(r.Xv, n, r.Uh, n), 2 * n, false, N,
@@ -1057,9 +1066,9 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   }
   // U1 = R_{U0}(xi_1)  (into Uh, free now)
   if (r.cfg.reorth && 4 * n <= 64) {
-    cayley_cholqr2(r, r.U0, r.P, r.Uh, r.M3, r.Z1);
+    cayley_cholqr2(r, r.U0, r.P, r.Uh, r.M3, r.Z1, gram_ready);
   } else {
-    cayley(r, r.U0, r.P, r.Uh, r.M3);
+    cayley(r, r.U0, r.P, r.Uh, r.M3, gram_ready);
     if (r.cfg.reorth) cholqr2(r, r.Uh, r.Z1);
   }
   // Commit by exchanging buffers before the flags are known, and with rank

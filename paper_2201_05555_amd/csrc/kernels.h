@@ -103,10 +103,11 @@ void launch_gemm_ah_b(hipStream_t s, const MatList& A, int a, const MatList& B, 
 void launch_gemm_flags(hipStream_t s, const MatList& A, int a, const MatList& B, int b, int flags,
                        int N, int nkb, cplx* part, cplx* C);
 void launch_rowgemm(hipStream_t s, const RowTerms& T, int N, int m, cplx* out);
-// the row combination and the Gram of its output (m x m) in one pass over the
-// rows; false (nothing launched) when m > 8 or the partials exceed part_cap
+// the row combination and the Gram of [pre, out] ((kp + m) x (kp + m); pre
+// optional, N x kp) in one pass over the rows; false (nothing launched) when
+// m > 8, kp > 8 or the partials exceed part_cap
 bool launch_rowgemm_gram(hipStream_t s, const RowTerms& T, int N, int m, cplx* out, cplx* part,
-                         size_t part_cap, cplx* Gram);
+                         size_t part_cap, cplx* Gram, const cplx* pre = nullptr, int kp = 0);
 // Fused gather + projection / basis velocity (G~ never stored); only for
 // n with fused_gradient_ok(n).  launch_gather_project writes g (n x p) and,
 // when want_colsq, |G~[:, c]|^2 into colsq; part holds part_cap complex.

@@ -285,17 +285,21 @@ __global__ void __launch_bounds__(256) rowgemm_kernel(RowTerms T, int N, int m, 
 }
 
 // The row combination for m <= 8 output columns that also forms the split-K
-// partials of the Gram of its output, O^* O: the block's rows are kept in LDS
-// and each upper-triangle entry (i <= j) is summed over four 64-row chunks,
-// the chunks then in order; part[block][j m + i] holds the entry and
-// part[block][i m + j] its conjugate (the layout of gemm_ah_b_kernel).
-template <int MC>
+// partials of the Gram of [P, O] (P: kp <= 8 optional leading columns read
+// from `pre`, O the output): the block's rows are kept in LDS and each
+// upper-triangle entry (i <= j) is summed over four 64-row chunks, the
+// chunks then in order; part[block][j g + i] holds the entry and
+// part[block][i g + j] its conjugate, g = kp + m (the layout of
+// gemm_ah_b_kernel).
+template <int MC, bool PRE>
 __global__ void __launch_bounds__(256) rowgemm_gram_kernel(RowTerms T, int N, int m,
                                                            cplx* __restrict__ out,
+                                                           const cplx* __restrict__ pre, int kp,
                                                            cplx* __restrict__ part) {
+  constexpr int GW = PRE ? 2 * MC : MC;  // LDS row width
   extern __shared__ cplx Ms[];
-  __shared__ cplx Os[256 * MC];
-  __shared__ cplx red[4][MC * (MC + 1) / 2];
+  __shared__ cplx Os[256 * GW];
+  __shared__ cplx red[4][GW * (GW + 1) / 2];
   int off = 0;
   for (int s = 0; s < T.count; ++s) {
     for (int t = threadIdx.x; t < T.k[s] * m; t += blockDim.x) Ms[off + t] = T.M[s][t];
@@ -303,6 +307,7 @@ __global__ void __launch_bounds__(256) rowgemm_gram_kernel(RowTerms T, int N, in
   }
   __syncthreads();
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int kpp = PRE ? kp : 0;
   cplx acc[MC];
 #pragma unroll
   for (int o = 0; o < MC; ++o) acc[o] = mk(0.0, 0.0);
@@ -325,34 +330,44 @@ __global__ void __launch_bounds__(256) rowgemm_gram_kernel(RowTerms T, int N, in
       if (o < m) out[(size_t)o * N + l] = acc[o];
   }
   // rows past N stay zero and add nothing
+  cplx* orow = Os + threadIdx.x * GW;
+  if (PRE)
+    for (int k = 0; k < kpp; ++k) orow[k] = (l < N) ? pre[(size_t)k * N + l] : mk(0.0, 0.0);
 #pragma unroll
-  for (int o = 0; o < MC; ++o) Os[threadIdx.x * MC + o] = acc[o];
+  for (int o = 0; o < MC; ++o)
+    if (o < m) orow[kpp + o] = acc[o];
   __syncthreads();
-  const int npair = m * (m + 1) / 2;
-  const int pr = threadIdx.x & 63, chunk = threadIdx.x >> 6;
-  int pi = 0, pj = 0;
-  if (pr < npair) {
+  const int g = kpp + m;
+  const int npair = g * (g + 1) / 2;
+  for (int it = threadIdx.x; it < 4 * npair; it += blockDim.x) {
+    const int chunk = it / npair, pr = it - chunk * npair;
     // pair index -> (i, j), i <= j, column by column
-    int q = pr;
+    int q = pr, pj = 0;
     while (q > pj) {
       q -= pj + 1;
       ++pj;
     }
-    pi = q;
+    const int pi = q;
     cplx sacc = mk(0.0, 0.0);
     for (int rr = 0; rr < 64; ++rr) {
-      const cplx* orow = Os + (chunk * 64 + rr) * MC;
-      cfma(sacc, cconj(orow[pi]), orow[pj]);
+      const cplx* row = Os + (chunk * 64 + rr) * GW;
+      cfma(sacc, cconj(row[pi]), row[pj]);
     }
     red[chunk][pr] = sacc;
   }
   __syncthreads();
-  if (chunk == 0 && pr < npair) {
-    cplx g = red[0][pr];
-    for (int c = 1; c < 4; ++c) g = cadd(g, red[c][pr]);
-    cplx* pb = part + (size_t)blockIdx.x * m * m;
-    pb[pj * m + pi] = g;
-    if (pi != pj) pb[pi * m + pj] = cconj(g);
+  for (int pr = threadIdx.x; pr < npair; pr += blockDim.x) {
+    int q = pr, pj = 0;
+    while (q > pj) {
+      q -= pj + 1;
+      ++pj;
+    }
+    const int pi = q;
+    cplx gs = red[0][pr];
+    for (int c = 1; c < 4; ++c) gs = cadd(gs, red[c][pr]);
+    cplx* pb = part + (size_t)blockIdx.x * g * g;
+    pb[pj * g + pi] = gs;
+    if (pi != pj) pb[pi * g + pj] = cconj(gs);
   }
 }
 
@@ -1386,16 +1401,34 @@ void launch_gemm_ah_b(hipStream_t s, const MatList& A, int a, const MatList& B, 
 }
 
 bool launch_rowgemm_gram(hipStream_t s, const RowTerms& T, int N, int m, cplx* out, cplx* part,
-                         size_t part_cap, cplx* Gram) {
+                         size_t part_cap, cplx* Gram, const cplx* pre, int kp) {
   const int nb = (N + 255) / 256;
-  if (m > 8 || (size_t)nb * m * m > part_cap) return false;
+  if (!pre) kp = 0;
+  const int g = kp + m;
+  if (m > 8 || kp > 8 || (size_t)nb * g * g > part_cap) return false;
   size_t sh = 0;
   for (int q = 0; q < T.count; ++q) sh += (size_t)T.k[q] * m * sizeof(cplx);
-  if (m <= 4)
-    hipLaunchKernelGGL(rowgemm_gram_kernel<4>, dim3(nb), dim3(256), sh, s, T, N, m, out, part);
-  else
-    hipLaunchKernelGGL(rowgemm_gram_kernel<8>, dim3(nb), dim3(256), sh, s, T, N, m, out, part);
-  const int nout = m * m;
+  const dim3 grid(nb), blk(256);
+  ALLOW_BIG_LDS((rowgemm_gram_kernel<4, true>));
+  ALLOW_BIG_LDS((rowgemm_gram_kernel<8, true>));
+  ALLOW_BIG_LDS((rowgemm_gram_kernel<4, false>));
+  ALLOW_BIG_LDS((rowgemm_gram_kernel<8, false>));
+  if (pre) {
+    if (m <= 4 && kp <= 4)
+      hipLaunchKernelGGL((rowgemm_gram_kernel<4, true>), grid, blk, sh, s, T, N, m, out, pre, kp,
+                         part);
+    else
+      hipLaunchKernelGGL((rowgemm_gram_kernel<8, true>), grid, blk, sh, s, T, N, m, out, pre, kp,
+                         part);
+  } else {
+    if (m <= 4)
+      hipLaunchKernelGGL((rowgemm_gram_kernel<4, false>), grid, blk, sh, s, T, N, m, out, pre, 0,
+                         part);
+    else
+      hipLaunchKernelGGL((rowgemm_gram_kernel<8, false>), grid, blk, sh, s, T, N, m, out, pre, 0,
+                         part);
+  }
+  const int nout = g * g;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((nout + 3) / 4), dim3(256), 0, s, part, nb, nout,
                      Gram);
   return true;
