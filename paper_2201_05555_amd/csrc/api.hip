@@ -750,16 +750,17 @@ void basis_velocity(symrom_rom& r, const cplx* U, const cplx* Z, double scale, c
     launch_dense_spinv(s, Z, n, r.p, r.cfg.pinv_rtol, r.Q, r.sigma2, r.flags);
   }
   if (fused_gradient_ok(n)) {
-    {
+    if (k1) {
       Timer t(FAM_DENSE, s);
       launch_dense_xfinish(s, r.gproj, r.Q, n, r.p, 2.0 * scale, k1, r.MP, r.MU);
     }
     // per (particle, parameter): 4n flops for x and v, 4n for G~ Q; plus 4n^2
-    // per particle for U MU; bytes: U read, out written
+    // per particle for U MU; bytes: U read, out written.  Without k1 the
+    // kernel forms MU from g~ and Q itself (no separate launch).
     Timer t(FAM_XI, s, 8.0 * n * (double)r.N * r.p + 8.0 * n * n * (double)r.N,
             32.0 * n * (double)r.N);
     launch_gather_xi(s, U, r.N, n, Z, r.p, r.Nx, r.b.factor, r.b.e, r.cfg.q / r.cfg.m, r.Q, r.MU,
-                     scale, out);
+                     scale, out, k1 ? nullptr : r.gproj);
     return;
   }
   Timer t(FAM_BASIS, s);

@@ -116,9 +116,11 @@ void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cpl
                            int Nx, const double* factor, const double* e, double qm,
                            const int* active, bool want_colsq, cplx* part, size_t part_cap,
                            cplx* g, double* colsq, const int* gate = nullptr);
+// g (optional): the projection g~ (n x p); MU is then formed from g and Q
+// inside the launch and the MU argument is not read
 void launch_gather_xi(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                       const double* factor, const double* e, double qm, const cplx* Q,
-                      const cplx* MU, double h, cplx* out);
+                      const cplx* MU, double h, cplx* out, const cplx* g = nullptr);
 void launch_deim_gather(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                         const double* factor, const double* e, double qm, const int* idx,
                         const double* w, int d, const int* active, cplx* gF,

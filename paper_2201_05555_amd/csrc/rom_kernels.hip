@@ -589,13 +589,16 @@ __global__ void __launch_bounds__(256) reduce_partials2_kernel(const cplx* __res
 // the coefficients, -i h Q and (when they fit) the field rows of all
 // parameters sit in LDS; ILP parameters are processed at a time so their
 // independent position / cell / lookup chains interleave.  Q (p x n, ld p)
-// and MU (n x n, ld n) as written by the dense kernels.
+// and MU (n x n, ld n) as written by the dense kernels; with g (n x p, the
+// projection g~) given instead of MU, every block forms MU = i h g~^T Q
+// itself from g and its copy of -i h Q (eight lanes per entry).
 // ---------------------------------------------------------------------------
 template <int NC, bool ET_LDS>
 __global__ void __launch_bounds__(256) gather_xi_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx,
     const double* __restrict__ factor, const double* __restrict__ e, double qm,
-    const cplx* __restrict__ Q, const cplx* __restrict__ MU, double h, cplx* __restrict__ out) {
+    const cplx* __restrict__ Q, const cplx* __restrict__ MU, const cplx* __restrict__ gp,
+    double h, cplx* __restrict__ out) {
   constexpr int ILP = (NC <= 8) ? 4 : 2;
   extern __shared__ double smem[];
   cplx* Zs = reinterpret_cast<cplx*>(smem);  // [p][NC], zero beyond n
@@ -610,9 +613,29 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
     const cplx qv = (k < n) ? Q[(size_t)k * p + c] : mk(0.0, 0.0);
     Qs[t] = mk(h * qv.im, -h * qv.re);
   }
-  for (int t = tid; t < NC * NC; t += 256) {
-    const int j = t / NC, k = t % NC;
-    Ms[t] = (j < n && k < n) ? MU[(size_t)k * n + j] : mk(0.0, 0.0);
+  if (gp) {
+    __syncthreads();  // Qs complete
+    // Ms[j][k] = -sum_c g[c][j] Qs[c][k]; lanes 8e..8e+7 split the sum over c
+    const int e8 = tid >> 3, part8 = tid & 7;
+    for (int e0 = 0; e0 < NC * NC; e0 += 32) {
+      const int t = e0 + e8;
+      const int j = t / NC, k = t % NC;
+      cplx sacc = mk(0.0, 0.0);
+      if (t < NC * NC && j < n && k < n)
+        for (int c = part8; c < p; c += 8) cfma(sacc, gp[(size_t)c * n + j], Qs[c * NC + k]);
+#pragma unroll
+      for (int o = 4; o >= 1; o >>= 1) {
+        sacc.re += __shfl_xor(sacc.re, o, 64);
+        sacc.im += __shfl_xor(sacc.im, o, 64);
+      }
+      if (part8 == 0 && t < NC * NC)
+        Ms[t] = (j < n && k < n) ? mk(-sacc.re, -sacc.im) : mk(0.0, 0.0);
+    }
+  } else {
+    for (int t = tid; t < NC * NC; t += 256) {
+      const int j = t / NC, k = t % NC;
+      Ms[t] = (j < n && k < n) ? MU[(size_t)k * n + j] : mk(0.0, 0.0);
+    }
   }
   for (int t = tid; t < p; t += 256) fs[t] = factor[t];
   if (ET_LDS) {
@@ -1275,7 +1298,7 @@ void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cpl
 
 void launch_gather_xi(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                       const double* factor, const double* e, double qm, const cplx* Q,
-                      const cplx* MU, double h, cplx* out) {
+                      const cplx* MU, double h, cplx* out, const cplx* g) {
   const int nc = fused_nc(n);
   const size_t base = (size_t)(2 * p * nc + nc * nc) * sizeof(cplx) + (size_t)p * sizeof(double);
   const size_t et_bytes = (size_t)p * Nx * sizeof(double);
@@ -1285,7 +1308,7 @@ void launch_gather_xi(hipStream_t s, const cplx* U, int N, int n, const cplx* Z,
 #define GXK(NCV, ETV)                                                                          \
   ALLOW_BIG_LDS((gather_xi_kernel<NCV, ETV>));                                               \
   hipLaunchKernelGGL((gather_xi_kernel<NCV, ETV>), grid, dim3(256), sh, s, U, N, n, Z, p, Nx,  \
-                     factor, e, qm, Q, MU, h, out)
+                     factor, e, qm, Q, MU, g, h, out)
   if (et_lds) {
     switch (nc) {
       case 4: GXK(4, true); break;
