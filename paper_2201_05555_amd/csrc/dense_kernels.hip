@@ -44,7 +44,20 @@ __device__ int bk_lu_solve(cplx* A, int m, cplx* B, int nrhs, int* piv_s) {
     if (threadIdx.x == 0) {
       int best = c;
       double bv = cabs2(A[c * m + c]);
-      for (int r = c + 1; r < m; ++r) {
+      // four independent LDS loads per round, compared in row order
+      int r = c + 1;
+      for (; r + 3 < m; r += 4) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = cabs2(A[c * m + r + u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (v[u] > bv) {
+            bv = v[u];
+            best = r + u;
+          }
+      }
+      for (; r < m; ++r) {
         double v = cabs2(A[c * m + r]);
         if (v > bv) {
           bv = v;
@@ -81,19 +94,27 @@ __device__ int bk_lu_solve(cplx* A, int m, cplx* B, int nrhs, int* piv_s) {
     }
     __syncthreads();
   }
-  // back substitution
-  for (int c = m - 1; c >= 0; --c) {
+  // back substitution, one barrier per column: x_c = B[c] / A[c][c] is
+  // recomputed by every thread that eliminates with it (row c itself is not
+  // written until the end), then all rows are scaled in one pass
+  for (int c = m - 1; c >= 1; --c) {
     const cplx piv = A[c * m + c];
     const double pn = cabs2(piv);
     const cplx pinv = mk(piv.re / pn, -piv.im / pn);
-    for (int j = threadIdx.x; j < nrhs; j += blockDim.x) B[j * m + c] = cmul(B[j * m + c], pinv);
-    __syncthreads();
     for (int t = threadIdx.x; t < c * nrhs; t += blockDim.x) {
       int r = t % c, j = t / c;
-      B[j * m + r] = csub(B[j * m + r], cmul(A[c * m + r], B[j * m + c]));
+      const cplx xc = cmul(B[j * m + c], pinv);
+      B[j * m + r] = csub(B[j * m + r], cmul(A[c * m + r], xc));
     }
     __syncthreads();
   }
+  for (int t = threadIdx.x; t < m * nrhs; t += blockDim.x) {
+    const int c = t % m;
+    const cplx piv = A[c * m + c];
+    const double pn = cabs2(piv);
+    B[t] = cmul(B[t], mk(piv.re / pn, -piv.im / pn));
+  }
+  __syncthreads();
   return 0;
 }
 
@@ -108,6 +129,7 @@ __device__ int bk_chol(const cplx* G, cplx* R, int n, double shift) {
   for (int j = 0; j < n; ++j) {
     if (threadIdx.x == 0) {
       double d = G[j * n + j].re - shift;
+#pragma unroll 4
       for (int k = 0; k < j; ++k) d -= cabs2(R[j * n + k]);
       if (!(d > 0.0)) {
         fail = 1;
