@@ -898,17 +898,6 @@ void deim_update_tail(symrom_rom& r) {
                       r.dw, dflags);
 }
 
-// DEIM gradient at (U, Z) with the field of the last Poisson solve:
-// gF = U~[I]^* ((q/m) e_{j(x_I)} w), then k = -i (gF + linear part).
-void deim_k(symrom_rom& r, const cplx* U, const cplx* Z, const int* active, cplx* kout,
-            const cplx* c12 = nullptr, const int* gate = nullptr) {
-  hipStream_t s = r.s;
-  Timer t(FAM_DENSE, s);
-  launch_deim_gather(s, U, r.N, r.n, Z, r.p, r.Nx, r.b.factor, r.b.e, r.cfg.q / r.cfg.m, r.didx,
-                     r.dw, r.d_cur, active, r.gF, gate);
-  if (kout) launch_deim_k(s, r.gF, c12, Z, r.n, r.p, kout);
-}
-
 // the whole status block into the pinned mirror (one copy, one wait)
 symrom_status read_status(symrom_rom& r) {
   HIPCHK(hipMemcpyAsync(r.hstat, r.status, 12 * sizeof(int), hipMemcpyDeviceToHost, r.s));
@@ -960,9 +949,14 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   cayley(r, r.U0, r.Xi, r.Uh, r.Amat);
   if (deim) linear_grams(r, r.Uh, r.C12);
   if (use_deim) HIPCHK(hipStreamWaitEvent(s, r.ev_join, 0));
-  if (deim) deim_k(r, r.U0, r.Z0, nullptr, r.k, r.C12a);
-  // fixed point for k2 at U_half
-  {
+  // fixed point for k2 at U_half: start values (with DEIM in the launch that
+  // gathers the first stage's gradient)
+  if (deim) {
+    Timer t(FAM_DENSE, s);
+    const DeimStartArgs st{r.C12a, r.k, r.Zev, 0.5 * dt, r.prev, r.active, r.counters};
+    launch_deim_gather(s, r.U0, N, n, r.Z0, p, r.Nx, r.b.factor, r.b.e, r.cfg.q / r.cfg.m, r.didx,
+                       r.dw, r.d_cur, nullptr, r.gF, nullptr, &st);
+  } else {
     Timer t(FAM_DENSE, s);
     launch_fp_init(s, r.prev, r.active, r.counters, p);
     launch_dense_finish_z(s, r.Z0, r.k, n, p, 0.5 * dt, r.Zev);

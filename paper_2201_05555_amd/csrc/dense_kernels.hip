@@ -1272,29 +1272,6 @@ void launch_dense_shrink(hipStream_t s, const cplx* Z, int n, int p, cplx* V, cp
 // DEIM (Sec. 4.3): basis coefficients, greedy selection and weights
 // ---------------------------------------------------------------------------
 
-// k = -i (gF + (C1 Z - conj(C2) conj(Z)) / 2): the DEIM reduced gradient
-// (eq. grHDD) with its linear part i U~^* V_r, C1 = U~^* U~, C2 = U~^T U~.
-__global__ void deim_k_kernel(const cplx* __restrict__ gF, const cplx* __restrict__ C12,
-                              const cplx* __restrict__ Z, int n, int p, cplx* __restrict__ k) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * p) return;
-  int a = t % n, i = t / n;
-  const cplx* z = Z + (size_t)i * n;
-  cplx s = mk(0.0, 0.0);
-  for (int b = 0; b < n; ++b) {
-    cfma(s, C12[b * n + a], z[b]);
-    cfma(s, cscale(cconj(C12[n * n + b * n + a]), -1.0), cconj(z[b]));
-  }
-  cplx g = cadd(gF[t], cscale(s, 0.5));
-  k[t] = mk(g.im, -g.re);
-}
-
-void launch_deim_k(hipStream_t s, const cplx* gF, const cplx* C12, const cplx* Z, int n, int p,
-                   cplx* k) {
-  hipLaunchKernelGGL(deim_k_kernel, dim3(nblk((size_t)n * p)), dim3(256), 0, s, gF, C12, Z, n, p,
-                     k);
-}
-
 // ---------------------------------------------------------------------------
 // Real symmetric eigendecomposition (n <= 64) in one wavefront: Householder
 // reduction to tridiagonal form, accumulation of the reflectors, then the

@@ -121,10 +121,23 @@ void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cpl
 void launch_gather_xi(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                       const double* factor, const double* e, double qm, const cplx* Q,
                       const cplx* MU, double h, cplx* out, const cplx* g = nullptr);
+// With start (and active == nullptr): also the DEIM reduced gradient
+// k = -i (gF + (C1 Z - conj(C2) conj(Z)) / 2) (C12 = [C1, C2]), the first
+// fixed-point iterate Zev = Z + h k, and the fixed-point start (prev = inf,
+// all columns active, counters reset), each block for its own column.
+struct DeimStartArgs {
+  const cplx* C12;
+  cplx* k;
+  cplx* Zev;
+  double h;
+  double* prev;
+  int* active;
+  int* counters;
+};
 void launch_deim_gather(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                         const double* factor, const double* e, double qm, const int* idx,
                         const double* w, int d, const int* active, cplx* gF,
-                        const int* gate = nullptr);
+                        const int* gate = nullptr, const DeimStartArgs* start = nullptr);
 void launch_snapshot(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, const int* sub,
                      int psub, int Nx, const double* factor, const double* phi, double* Y,
                      const int* stop = nullptr);
@@ -190,8 +203,6 @@ void launch_dense_shrink(hipStream_t s, const cplx* Z, int n, int p, cplx* V, cp
                          double* sig2);
 
 void launch_dense_symeig(hipStream_t s, const cplx* G, int n, double* V, double* lam, int* flags);
-void launch_deim_k(hipStream_t s, const cplx* gF, const cplx* C12, const cplx* Z, int n, int p,
-                   cplx* k);
 void launch_dense_indicator(hipStream_t s, const double* colsq, const cplx* g, int n, int p,
                             double* eps);
 // Mc (optional, n x d): the DEIM basis coefficients V[:, c] / sqrt(lam_c)

@@ -380,7 +380,8 @@ __global__ void __launch_bounds__(64) deim_gather_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx,
     const double* __restrict__ factor, const double* __restrict__ e, double qm,
     const int* __restrict__ idx, const double* __restrict__ w, int d,
-    const int* __restrict__ active, cplx* __restrict__ gF, const int* __restrict__ gate) {
+    const int* __restrict__ active, cplx* __restrict__ gF, const int* __restrict__ gate,
+    DeimStartArgs st) {
   if (gate && gate[0] == 0) return;
   __shared__ double Fw[256];
   const int i = blockIdx.x;
@@ -408,6 +409,31 @@ __global__ void __launch_bounds__(64) deim_gather_kernel(
       s.im = fma(-u.im, Fw[r], s.im);
     }
     gF[(size_t)i * n + k] = s;
+    if (st.k) {
+      // k = -i (gF + (C1 Z - conj(C2) conj(Z)) / 2) for this entry (the DEIM
+      // reduced gradient with its linear part i U~^* V_r, C1 = U~^* U~,
+      // C2 = U~^T U~), then the first iterate Z0 + h k (the arithmetic of
+      // dense_finish_z_kernel)
+      cplx sl = mk(0.0, 0.0);
+      for (int b = 0; b < n; ++b) {
+        cfma(sl, st.C12[b * n + k], zi[b]);
+        cfma(sl, cscale(cconj(st.C12[n * n + b * n + k]), -1.0), cconj(zi[b]));
+      }
+      const cplx g = cadd(s, cscale(sl, 0.5));
+      const cplx kk = mk(g.im, -g.re);
+      const size_t t = (size_t)i * n + k;
+      st.k[t] = kk;
+      st.Zev[t] = mk(zi[k].re + st.h * kk.re, zi[k].im + st.h * kk.im);
+    }
+  }
+  if (st.k) {
+    // start of the fixed point (as fp_init_kernel): column i active, no
+    // previous update; block 0 resets the counters
+    if (threadIdx.x == 0) {
+      st.prev[i] = INFINITY;
+      st.active[i] = 1;
+    }
+    if (i == 0 && threadIdx.x < 4) st.counters[threadIdx.x] = (threadIdx.x == 0) ? p : 0;
   }
 }
 
@@ -1476,9 +1502,12 @@ void launch_rowgemm(hipStream_t s, const RowTerms& T, int N, int m, cplx* out) {
 
 void launch_deim_gather(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                         const double* factor, const double* e, double qm, const int* idx,
-                        const double* w, int d, const int* active, cplx* gF, const int* gate) {
+                        const double* w, int d, const int* active, cplx* gF, const int* gate,
+                        const DeimStartArgs* start) {
+  DeimStartArgs st{};
+  if (start) st = *start;
   hipLaunchKernelGGL(deim_gather_kernel, dim3(p), dim3(64), 0, s, U, N, n, Z, p, Nx, factor, e,
-                     qm, idx, w, d, active, gF, gate);
+                     qm, idx, w, d, active, gF, gate, st);
 }
 
 
