@@ -647,8 +647,17 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
       const int t = e0 + e8;
       const int j = t / NC, k = t % NC;
       cplx sacc = mk(0.0, 0.0);
-      if (t < NC * NC && j < n && k < n)
-        for (int c = part8; c < p; c += 8) cfma(sacc, gp[(size_t)c * n + j], Qs[c * NC + k]);
+      if (t < NC * NC && j < n && k < n) {
+        // eight loads of g in flight per round (one round for p <= 64)
+        for (int c0 = part8; c0 < p; c0 += 64) {
+          cplx gv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) gv[u] = gp[(size_t)min(c0 + 8 * u, p - 1) * n + j];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (c0 + 8 * u < p) cfma(sacc, gv[u], Qs[(c0 + 8 * u) * NC + k]);
+        }
+      }
 #pragma unroll
       for (int o = 4; o >= 1; o >>= 1) {
         sacc.re += __shfl_xor(sacc.re, o, 64);
