@@ -432,6 +432,7 @@ def test_rom_deim_rank_auto_parity():
 @pytest.mark.parametrize("kw,two_n,two_n_max,steps", [
     (dict(N=20000, p=24, Nx=128), 8, 8, 6),
     (dict(N=30000, p=64, Nx=128), 10, 60, 6),     # the two-stream workload's DEIM shape
+    (dict(N=7777, p=20, Nx=64), 14, 14, 5),        # odd register width 7, ragged row blocks
     (dict(N=6000, p=24, Nx=64), 36, 36, 5),        # n > 16 with DEIM
 ])
 def test_rom_deim_steps_parity(kw, two_n, two_n_max, steps):
