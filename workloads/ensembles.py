@@ -134,7 +134,8 @@ def _invert_velocity(u, v0, sigma):
         lo[act] = np.where(f < 0, vv, lo[act])
         hi[act] = np.where(f >= 0, vv, hi[act])
         d = _mixture_pdf(vv, aa, bb)
-        with np.errstate(divide="ignore", invalid="ignore"):
+        # a zero or tiny density gives a non-finite step, replaced by bisection
+        with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
             vn = vv - f / d
         bad = ~np.isfinite(vn) | (vn <= lo[act]) | (vn >= hi[act])
         vn = np.where(bad, 0.5 * (lo[act] + hi[act]), vn)
