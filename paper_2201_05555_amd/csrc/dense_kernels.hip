@@ -34,6 +34,14 @@ __device__ void bk_matmul(cplx* C, const cplx* A, int opA, const cplx* B, int op
   __syncthreads();
 }
 
+// Entry (i, j) of A B for column-major n x n A, B, summed in the order of
+// bk_matmul (so a product formed entry by entry has the same bits).
+__device__ inline cplx mm_entry(const cplx* A, const cplx* B, int i, int j, int n) {
+  cplx s = mk(0.0, 0.0);
+  for (int q = 0; q < n; ++q) cfma(s, A[q * n + i], B[j * n + q]);
+  return s;
+}
+
 // Solve A X = B in place (A m x m destroyed, B m x nrhs overwritten by X)
 // by Gaussian elimination with partial pivoting.  Returns 0 on success.
 __device__ int bk_lu_solve(cplx* A, int m, cplx* B, int nrhs, int* piv_s) {
@@ -454,13 +462,19 @@ __global__ void __launch_bounds__(DTPB) dense_cayley_kernel(const cplx* __restri
   __syncthreads();
   // U0^* W = A - G00 A / 2
   bk_matmul(T1, G00, 0, A, 0, n, n, n);
-  for (int t = threadIdx.x; t < n * n; t += blockDim.x) UW[t] = csub(A[t], cscale(T1[t], 0.5));
-  __syncthreads();
-  // W^* W = Gxx - A^* A + A^* G00 A / 4
-  bk_matmul(WW, A, 1, T1, 0, n, n, n);  // A^* (G00 A)
-  bk_matmul(T1, A, 1, A, 0, n, n, n);   // A^* A
-  for (int t = threadIdx.x; t < n * n; t += blockDim.x)
-    WW[t] = cadd(csub(Gxx[t], T1[t]), cscale(WW[t], 0.25));
+  // and, in the same phase, W^* W = Gxx - A^* A + A^* G00 A / 4 (products
+  // entry by entry in the order of bk_matmul)
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int i = t % n, j = t / n;
+    UW[t] = csub(A[t], cscale(T1[t], 0.5));
+    cplx agA = mk(0.0, 0.0), aa = mk(0.0, 0.0);
+    for (int q = 0; q < n; ++q) {
+      const cplx ac = cconj(A[i * n + q]);
+      cfma(agA, ac, T1[j * n + q]);
+      cfma(aa, ac, A[j * n + q]);
+    }
+    WW[t] = cadd(csub(Gxx[t], aa), cscale(agA, 0.25));
+  }
   __syncthreads();
   // K = I - Rc^* Lc / 2,  Rc^* Lc = [[U0^*W, -U0^*U0], [W^*W, -W^*U0]]
   for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
@@ -695,32 +709,30 @@ __global__ void __launch_bounds__(DTPB) dense_tangent_kernel(const cplx* __restr
     if (threadIdx.x == 0 && flags) flags[0] |= 1;
     return;
   }
-  // M2 = -B1 Minv;  M3 = (A B1 / 2 + W^* X) Minv  (M1 = 2 Minv)
-  bk_matmul(T1, B1, 0, Mi, 0, n, n, n);
-  for (int t = threadIdx.x; t < nn; t += blockDim.x) M2[t] = cscale(T1[t], -1.0);
-  bk_matmul(T1, A, 0, B1, 0, n, n, n);
-  for (int t = threadIdx.x; t < nn; t += blockDim.x) T2[t] = cadd(cscale(T1[t], 0.5), XX[t]);
+  // M2 = -B1 Minv;  M3 = (A B1 / 2 + W^* X) Minv  (M1 = 2 Minv); products
+  // formed entry by entry, independent ones in the same phase
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+    const int i = t % n, j = t / n;
+    M2[t] = cscale(mm_entry(B1, Mi, i, j, n), -1.0);
+    T2[t] = cadd(cscale(mm_entry(A, B1, i, j, n), 0.5), XX[t]);
+  }
   __syncthreads();
-  bk_matmul(M3, T2, 0, Mi, 0, n, n, n);
-  // D1 = Ux^*X M1 + Ux^*xi M2 + Ux^*U0 M3;  D0 = U0^*X M1 + U0^*xi M2 + U0^*U0 M3
-  bk_matmul(D1, UxX, 0, Mi, 0, n, n, n);
-  bk_matmul(T1, Uxxi, 0, M2, 0, n, n, n);
-  bk_matmul(T2, UxU0, 0, M3, 0, n, n, n);
-  for (int t = threadIdx.x; t < nn; t += blockDim.x)
-    D1[t] = cadd(cadd(cscale(D1[t], 2.0), T1[t]), T2[t]);
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) M3[t] = mm_entry(T2, Mi, t % n, t / n, n);
   __syncthreads();
-  bk_matmul(D0, B1, 0, Mi, 0, n, n, n);
-  bk_matmul(T1, A, 0, M2, 0, n, n, n);
-  bk_matmul(T2, G00, 0, M3, 0, n, n, n);
-  for (int t = threadIdx.x; t < nn; t += blockDim.x)
-    D0[t] = cadd(cadd(cscale(D0[t], 2.0), T1[t]), T2[t]);
-  __syncthreads();
-  // C = (C0x^* + I)^{-1} (D1 + D0) + D0^*  (the system in T2, the right side in T1)
+  // D1 = Ux^*X M1 + Ux^*xi M2 + Ux^*U0 M3;  D0 = U0^*X M1 + U0^*xi M2 + U0^*U0 M3;
+  // then C = (C0x^* + I)^{-1} (D1 + D0) + D0^*  (the system in T2, the right
+  // side in T1)
   for (int t = threadIdx.x; t < nn; t += blockDim.x) {
     const int r = t % n, c = t / n;
-    T1[t] = cadd(D1[t], D0[t]);
-    T2[t] = cconj(C0x[r * n + c]);
-    if (r == c) T2[t].re += 1.0;
+    const cplx d1 = cadd(cadd(cscale(mm_entry(UxX, Mi, r, c, n), 2.0), mm_entry(Uxxi, M2, r, c, n)),
+                         mm_entry(UxU0, M3, r, c, n));
+    const cplx d0 = cadd(cadd(cscale(mm_entry(B1, Mi, r, c, n), 2.0), mm_entry(A, M2, r, c, n)),
+                         mm_entry(G00, M3, r, c, n));
+    D0[t] = d0;
+    T1[t] = cadd(d1, d0);
+    cplx tv = cconj(C0x[r * n + c]);
+    if (r == c) tv.re += 1.0;
+    T2[t] = tv;
   }
   __syncthreads();
   if (bk_lu_solve(T2, n, T1, n, &piv)) {
