@@ -33,8 +33,14 @@ PINS = {
     "rom.reorthonormalise": "R = UZ unchanged; U^T U = I",
     "rom.rank_grow": "R bitwise unchanged (zero coefficient rows)",
     "rom.rank_shrink": "removed energy equals dropped singular values",
-    "rom.rank_indicator": "parity unpinned (policy of this build; the paper defers rank adaptation)",
-    "deim.greedy": "brute force on tiny inputs; interpolation property P^T Psi (P^T Psi)^-1 = I",
+    "rom.rank_indicator": "identity ||(I - U U^T) J G||^2 = ||G||^2 - ||g||^2",
+    "rom.rank_policy": "parity unpinned (grow/shrink thresholds are a reading; the paper defers "
+                       "rank adaptation)",
+    "rom.fixed_point_stagnation": "parity unpinned (a reading); the floor is pinned by a planted "
+                                  "2-cycle that must end in ENOCONV",
+    "deim.greedy": "brute force on tiny inputs for every k: each index maximises the "
+                   "interpolation volume |det Psi[I, :k]|; a hand-worked 4 x 3 example",
+    "deim.weights": "hand-worked 4 x 3 example; interpolation of the constant 1",
     "deim.gradient": "d = N reduces exactly to the Galerkin gradient",
     "deim.accuracy_with_exact_potential": "parity unpinned (no printed values)",
 }

@@ -1,4 +1,4 @@
-"""Oracle: DEIM hyper-reduction of the particle-to-grid term (paper Sec. 4.3).
+"""Oracle: DEIM hyper-reduction of the particle-to-grid term (paper Sec. 4.2.2).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
@@ -11,7 +11,7 @@ since m_p^{-1} M_q = (q/m) 1 and nabla Lambda^0 Phi is the cell field e.
 Snapshots: the last T+1 time levels of N_i for a parameter subset of size
 p*, the matrix Y = [Y_1 ... Y_p*] of eq. (Ydeim) (N x p*(T+1)); Psi = its
 first d left singular vectors; the indices follow the greedy DEIM selection
-(Sec. 4.3: at step k, the index of the largest interpolation residual of
+(Sec. 4.2.2: at step k, the index of the largest interpolation residual of
 psi_k on the previous vectors).  reading: the subset is evenly spaced in the
 parameter index, i_k = floor(k p / p*), with p* = min(p, max(8,
 ceil(two_n_max / (T+1)))) so that p*(T+1) >= d for every rank reached.

@@ -91,6 +91,7 @@ class RomConfig:
     m: float = 1.0
     fp_tol: float = 1e-9          # relative update threshold (Sec. 6.1)
     fp_max_iters: int = 100
+    fp_stall_tol: float = 1e-3    # stagnation accepted only below this update
     pinv_rtol: float = 1e-12
     projection: str = "galerkin"  # or "deim"
     deim_window: int = 3          # T: the window holds T + 1 snapshots
@@ -113,6 +114,7 @@ class RomState:
     window: list = dc_field(default_factory=list)   # DEIM snapshots (N x p each)
     last_iters: int = 0
     last_stalled: int = 0
+    last_stall_rel: float = 0.0   # largest relative update accepted by the stagnation rule
     last_status: int = OK
     deim_indices: Optional[np.ndarray] = None
 
@@ -311,7 +313,8 @@ def prk_step(st, cfg, fixed_iters=None):
     5. k^2 = Y(xi_half, Z_G), Z_G the point of the last gradient of each
        column (reading);  U1 = R_{U0}(dt k^2).
     6. re-orthonormalise (this build's addition).
-    Returns the status (OK or ENOCONV); on ENOCONV the state is unchanged.
+    Returns the status (OK or ENOCONV); on ENOCONV the state (U, Z and the
+    DEIM snapshot window) is unchanged.
     """
     from . import deim as deim_mod
     J = J_small(cfg.two_n)
@@ -321,6 +324,8 @@ def prk_step(st, cfg, fixed_iters=None):
 
     gr0 = gradient(U0, Z0, st.L, cfg.Nx, cfg.q, cfg.m)
     deim_op = None
+    window0 = list(st.window)
+    indices0 = st.deim_indices
     if cfg.projection == "deim":
         deim_op = deim_mod.update_window(st, cfg, U0, gr0)
     g1 = gr0.g if deim_op is None else deim_mod.deim_gradient(U0, Z0, gr0, deim_op, cfg)
@@ -336,6 +341,7 @@ def prk_step(st, cfg, fixed_iters=None):
     prev = np.full(p, np.inf)
     iters = 0
     stalled = 0
+    stall_rel = 0.0
     limit = fixed_iters if fixed_iters is not None else cfg.fp_max_iters
     while active.any() and iters < limit:
         iters += 1
@@ -353,9 +359,13 @@ def prk_step(st, cfg, fixed_iters=None):
             # reading: the gathered force is piecewise constant in a particle's
             # own position, so a particle whose midpoint sits on a node can
             # put the map into a 2-cycle; a column whose relative update stops
-            # decreasing is accepted at its current iterate
-            stall = ~conv & (rel >= prev[cols])
+            # decreasing is accepted at its current iterate, provided that
+            # update is already small (below fp_stall_tol); above it the
+            # column keeps iterating and the step fails at fp_max_iters
+            stall = ~conv & (rel >= prev[cols]) & (rel < cfg.fp_stall_tol)
             stalled += int(np.sum(stall))
+            if stall.any():
+                stall_rel = max(stall_rel, float(rel[stall].max()))
             done = conv | stall
             prev[cols] = rel
         else:
@@ -364,7 +374,11 @@ def prk_step(st, cfg, fixed_iters=None):
         active[cols[done]] = False
     st.last_iters = iters
     st.last_stalled = stalled
+    st.last_stall_rel = stall_rel
     if fixed_iters is None and active.any():
+        # the state, the DEIM snapshot window included, stays as it was
+        st.window = window0
+        st.deim_indices = indices0
         st.last_status = ENOCONV
         return ENOCONV
 
@@ -438,11 +452,22 @@ def rank_shrink(st, new_two_n):
     return s[n:]
 
 
+def shrink_target(st, cfg):
+    """Rank kept by the shrink rule (reading R-4): the pairs whose singular
+    value of Z~ is at least rank_tol_down times the largest (at least one)."""
+    s = np.linalg.svd(to_complex_coeff(st.Z), compute_uv=False)
+    if s.size == 0 or s[0] <= 0.0:
+        return st.U.shape[1]
+    keep = max(1, int(np.sum(s >= cfg.rank_tol_down * s[0])))
+    return 2 * min(keep, st.U.shape[1] // 2)
+
+
 def adapt_rank(st, cfg, target_two_n=0):
-    """Force the rank to ``target_two_n`` (even), or apply the indicator
-    policy when target is 0: grow one pair if eps_perp > rank_tol_up and the
-    cap allows (shrinking is only done on request).  Returns (status, new 2n,
-    eps_perp or None)."""
+    """Force the rank to ``target_two_n`` (even), or apply the policy when
+    target is 0 (reading R-4): grow one pair if eps_perp > rank_tol_up and the
+    cap allows; otherwise drop the pairs whose singular value of Z~ falls
+    below rank_tol_down times the largest.  Returns (status, new 2n, eps_perp
+    or None)."""
     r = st.U.shape[1]
     if target_two_n:
         if target_two_n % 2 or target_two_n <= 0:
@@ -458,6 +483,10 @@ def adapt_rank(st, cfg, target_two_n=0):
     eps, gr = rank_indicator(st, cfg)
     if eps > cfg.rank_tol_up and r < cfg.two_n_max:
         rank_grow(st, cfg, 1, gr)
+    else:
+        keep = shrink_target(st, cfg)
+        if keep < r:
+            rank_shrink(st, keep)
     cfg.two_n = st.U.shape[1]
     return OK, cfg.two_n, eps
 

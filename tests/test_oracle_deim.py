@@ -90,3 +90,70 @@ def test_snapshot_parameter_subset():
         assert sub[0] == 0 and len(set(sub.tolist())) == len(sub)
         assert len(sub) == min(p, max(8, -(-cap // (T + 1))))
         assert np.all(np.diff(sub) > 0) and sub[-1] < p
+
+
+def _greedy_by_determinants(Psi):
+    """An independent characterisation of the greedy choice (Sec. 4.2.2):
+    with the first k-1 indices fixed, the k-th maximises over j the volume
+    |det Psi[I_{k-1} + (j), :k]|.  By the Schur complement that determinant is
+    det(P^T Psi_{k-1}) times the interpolation residual r_k(j), so maximising
+    one maximises the other; no solve of the greedy's linear system is used.
+    Returns the indices and the ratio of the runner-up to the winner at each
+    step (to keep away from near ties)."""
+    N, d = Psi.shape
+    idx, margins = [], []
+    for k in range(d):
+        vols = np.array([abs(np.linalg.det(Psi[idx + [j], :k + 1])) if j not in idx else -1.0
+                         for j in range(N)])
+        order = np.argsort(-vols, kind="stable")
+        idx.append(int(order[0]))
+        margins.append(vols[order[1]] / vols[order[0]])
+    return np.array(idx), np.array(margins)
+
+
+def test_greedy_matches_determinant_maximisation():
+    """Brute force on tiny inputs for every k >= 1: the oracle's greedy
+    indices equal the successive maximisers of the interpolation volume.  A
+    greedy that took argmax |psi_k| instead of the residual's argmax (or
+    skipped the solve) fails here: the seeds below include cases where the
+    two rules disagree, which the test checks it has seen."""
+    rng = np.random.default_rng(7)
+    disagree = 0
+    cases = 0
+    while cases < 40:
+        N = int(rng.integers(6, 13))
+        d = int(rng.integers(2, 6))
+        Psi, _ = np.linalg.qr(rng.normal(size=(N, d)))
+        ref, margin = _greedy_by_determinants(Psi)
+        if margin.max() > 1 - 1e-6:
+            continue          # a near tie: any rule may pick either index
+        cases += 1
+        got = deim.greedy_indices(Psi)
+        assert np.array_equal(got, ref), (got, ref)
+        naive = [int(np.argmax(np.where(np.isin(np.arange(N), ref[:k]), -1.0,
+                                        np.abs(Psi[:, k])))) for k in range(d)]
+        disagree += int(naive != ref.tolist())
+    assert disagree >= 10, disagree
+
+
+def test_greedy_hand_worked_example():
+    """A 4 x 3 basis worked by hand (Sec. 4.2.2 greedy):
+      psi_1 = (1, 3, 2, 0):       l_1 = 1 (|3| largest).
+      psi_2 = (1.5, 9, 7, 2.5):   c = psi_2[1] / psi_1[1] = 3,
+                                  r_2 = psi_2 - 3 psi_1 = (-1.5, 0, 1, 2.5), l_2 = 3
+                                  (not 2, the largest unselected entry of psi_2).
+      psi_3 = (4, 3, 1, 5):       [[3, 9], [0, 2.5]] c = (3, 5) gives c = (-5, 2),
+                                  r_3 = psi_3 + 5 psi_1 - 2 psi_2 = (6, 0, -3, 0), l_3 = 0.
+    The weights w = (P^T Psi)^{-T} Psi^T 1 solve the transposed system for
+    Psi^T 1 = (6, 20, 13)."""
+    Psi = np.array([[1.0, 1.5, 4.0], [3.0, 9.0, 3.0], [2.0, 7.0, 1.0], [0.0, 2.5, 5.0]])
+    assert deim.greedy_indices(Psi).tolist() == [1, 3, 0]
+    # P^T Psi rows (1, 3, 0): [[3, 9, 3], [0, 2.5, 5], [1, 1.5, 4]]; by hand,
+    # (P^T Psi)^T w = (6, 20, 13):  3 w1 + w3 = 6,  9 w1 + 2.5 w2 + 1.5 w3 = 20,
+    # 3 w1 + 5 w2 + 4 w3 = 13  ->  18 w1 = 33, so w = (11/6, 1.1, 0.5)
+    w = deim.weights(Psi, np.array([1, 3, 0]))
+    np.testing.assert_allclose(w, [11.0 / 6.0, 1.1, 0.5], rtol=1e-14)
+    A = Psi[[1, 3, 0], :]
+    # the DEIM interpolant of the constant 1 reproduces 1 on the selected rows
+    proj = Psi @ np.linalg.solve(A, np.ones(3))
+    assert np.allclose(proj[[1, 3, 0]], 1.0, atol=1e-13)

@@ -320,3 +320,70 @@ def test_enoconv_leaves_state_unchanged():
     cfg.fp_tol = 0.0
     assert rom.prk_step(st, cfg) == rom.ENOCONV
     assert np.array_equal(st.U, U0) and np.array_equal(st.Z, Z0)
+
+
+def test_enoconv_with_deim_keeps_the_snapshot_window():
+    """A failed DEIM step leaves the snapshot window as it was, so a retry
+    gives the same step as a run that never failed."""
+    N = 500
+    w = workload("twostream_deim", N=N, p=12, Nx=32)
+    ens = make_ensemble(w)
+    cfg = rom.RomConfig(N=N, p=12, Nx=32, two_n=6, dt=0.05, projection="deim",
+                        deim_window=2, fp_tol=1e-11)
+    st = rom.init_state(ens["X0"], ens["V0"], ens["L"], cfg)
+    ref = rom.init_state(ens["X0"], ens["V0"], ens["L"], cfg)
+    for _ in range(4):
+        assert rom.prk_step(st, cfg) == rom.OK
+        assert rom.prk_step(ref, cfg) == rom.OK
+    win = [y.copy() for y in st.window]
+    bad = rom.RomConfig(**{**cfg.__dict__, "fp_max_iters": 1, "fp_tol": 0.0})
+    assert rom.prk_step(st, bad) == rom.ENOCONV
+    assert len(st.window) == len(win) and all(np.array_equal(a, b) for a, b in zip(st.window, win))
+    assert rom.prk_step(st, cfg) == rom.OK
+    assert rom.prk_step(ref, cfg) == rom.OK
+    assert np.array_equal(st.U, ref.U) and np.array_equal(st.Z, ref.Z)
+
+
+def test_stagnation_accepted_only_below_its_floor(monkeypatch):
+    """The stagnation rule (a reading: a column whose relative update stops
+    decreasing is accepted) applies only once that update is below
+    fp_stall_tol.  A gradient that 2-cycles with a large amplitude is a stall
+    far above the floor: the step must fail with ENOCONV, and is accepted
+    only if the floor is lifted."""
+    st, cfg, _ = _tiny_landau(two_n=6, N=400)
+    real = rom.reduced_gradient
+    calls = {"n": 0}
+
+    def cycling(sub, c, U, Z, op=None):
+        g, gr = real(sub, c, U, Z, op)
+        calls["n"] += 1
+        return g * (1.0 + 0.1 * (calls["n"] % 2)), gr
+
+    monkeypatch.setattr(rom, "reduced_gradient", cycling)
+    cfg.fp_max_iters = 30
+    s1 = rom.RomState(U=st.U.copy(), Z=st.Z.copy(), L=st.L)
+    assert rom.prk_step(s1, cfg) == rom.ENOCONV
+    cfg2 = rom.RomConfig(**{**cfg.__dict__, "fp_stall_tol": np.inf})
+    s2 = rom.RomState(U=st.U.copy(), Z=st.Z.copy(), L=st.L)
+    assert rom.prk_step(s2, cfg2) == rom.OK and s2.last_stalled > 0
+
+
+def test_automatic_shrink_drops_negligible_pairs():
+    """Reading R-4: with no growth (indicator below its threshold), the pairs
+    whose singular value of Z~ is below rank_tol_down times the largest are
+    dropped, and R changes by exactly the dropped singular values."""
+    st, cfg, _ = _tiny_landau(two_n=8, N=900)
+    Zt = rom.to_complex_coeff(st.Z)
+    Q, s, Wh = np.linalg.svd(Zt, full_matrices=False)
+    s_new = s.copy()
+    s_new[-1] = 1e-11 * s[0]           # one pair far below the threshold 1e-8
+    st.Z = rom.from_complex_coeff((Q * s_new) @ Wh)
+    R1 = st.U @ st.Z
+    cfg.two_n_max, cfg.rank_tol_up, cfg.rank_tol_down = 12, 2.0, 1e-8
+    status, two_n, eps = rom.adapt_rank(st, cfg, 0)
+    assert status == rom.OK and two_n == 6 and eps < 1.0
+    np.testing.assert_allclose(np.linalg.norm(st.U @ st.Z - R1), s_new[-1], rtol=1e-3)
+    assert _orth_err(st.U) < 1e-12
+    # nothing below the threshold: the rank stays
+    status, two_n, _ = rom.adapt_rank(st, cfg, 0)
+    assert two_n == 6
