@@ -57,7 +57,7 @@ enum { SYMROM_GALERKIN = 0, SYMROM_DEIM = 1 };
 
 typedef struct {
   int32_t N;             /* particles                                        */
-  int32_t p;             /* parameters of the ensemble (reduced model: <= 64) */
+  int32_t p;             /* parameters of the ensemble                       */
   int32_t Nx;            /* grid cells (= nodes) of the periodic P1 mesh     */
   int32_t two_n;         /* reduced dimension 2n (even)                      */
   int32_t two_n_max;     /* capacity for rank growth (even, >= two_n, <= 60) */
@@ -72,7 +72,21 @@ typedef struct {
   int32_t reorth;        /* 1: FP64 re-orthonormalisation after each step    */
   int32_t rank_auto;     /* 1: apply the rank indicator after each step      */
   double rank_tol_up;    /* grow one pair when eps_perp exceeds this         */
+  double fp_stall_tol;   /* a column whose relative update stops decreasing  */
+                         /* is accepted only below this update (else it     */
+                         /* iterates on; ENOCONV at fp_max_iters); 0: 1e-3  */
+  double rank_tol_down;  /* automatic shrink: drop the pairs whose singular  */
+                         /* value of Z~ is below this times the largest     */
+  int32_t deim_rows;     /* d, DEIM sample rows; 0: d = 2n (capped by the    */
+                         /* snapshot count p*(T+1))                          */
+  int32_t precision;     /* SYMROM_FP64 (the only arithmetic built)          */
+  int32_t deterministic; /* 1: theta sums of the deposit in 64-bit fixed     */
+                         /* point (exact for |x N_x / L| >= 1), so the charge */
+                         /* and everything after it is bitwise reproducible  */
+  int32_t reserved;
 } symrom_config;
+
+enum { SYMROM_FP64 = 0 };
 
 typedef struct {
   int32_t iters;          /* fixed-point iterations of the last step          */
@@ -82,6 +96,10 @@ typedef struct {
   double rank_indicator;  /* eps_perp of the last evaluation, -1 if none      */
   int32_t iters_total;    /* fixed-point iterations summed over the call      */
   int32_t deim_steps;     /* steps of the call that used the DEIM gradient    */
+  double stall_rel;       /* largest relative update accepted by the          */
+                          /* stagnation rule in the last step (0 if none)     */
+  int32_t stalled_total;  /* stagnation acceptances summed over the call      */
+  int32_t shrunk;         /* pairs dropped by the automatic shrink, last step */
 } symrom_step_info;
 
 typedef struct symrom_rom symrom_rom;
@@ -115,19 +133,33 @@ symrom_status rom_init(const symrom_config* cfg, const double* L, const double* 
  * Runge-Kutta scheme (Sec. 5): implicit midpoint for Z solved by per-column
  * fixed point (relative update < fp_tol, Sec. 6.1), explicit midpoint for U
  * on the tangent space through the Cayley retraction, with the Galerkin or
- * DEIM (Sec. 4.3, eq. grHDD with the exact potential) gradient.  info (host,
- * nullable) describes the last step.  On ENOCONV the state is the one before
- * the failing step. */
+ * DEIM (Sec. 4.2.2, eq. grHDD with the exact potential) gradient.  A column
+ * whose relative update stops decreasing is accepted while that update is
+ * below fp_stall_tol (a node-crossing 2-cycle of the piecewise-constant
+ * gathered force); the largest update so accepted is info->stall_rel.  With
+ * rank_auto the rank is updated after every step (see rom_adapt_rank, target
+ * 0).  info (host, nullable) describes the last step.  On ENOCONV the state
+ * (U, Z and the DEIM snapshot window) is the one before the failing step. */
 symrom_status rom_step(symrom_rom* h, int32_t nsteps, symrom_step_info* info);
+
+/* Replace the fixed-point controls of the following steps (fp_tol,
+ * fp_max_iters, fp_fixed_iters as in symrom_config).  Host-only. */
+symrom_status rom_set_fixed_point(symrom_rom* h, double fp_tol, int32_t fp_max_iters,
+                                  int32_t fp_fixed_iters);
 
 /* Change the rank.  target_two_n > current: append (target - current)/2
  * symplectic pairs, the leading left singular vectors of
- * (I - U~U~^*)(-i G~) at the current state, with zero coefficient rows
- * (R = U Z unchanged).  target < current: rotate to the singular vectors of
- * Z~ and drop the trailing pairs.  target 0: grow one pair if the indicator
- * eps_perp = ||(I - U U^T) J G|| / ||G|| exceeds rank_tol_up.  (The paper
- * defers rank adaptation to future work, Sec. 6.4.)  new_two_n: host, nullable.
- * Errors: ERANKCAP beyond two_n_max, EINVAL for odd targets. */
+ * (I - U~U~^*)(-i G~) at the current state (orthonormalised against the
+ * basis and among themselves), with zero coefficient rows (R = U Z
+ * unchanged).  target < current: rotate to the singular vectors of Z~ and
+ * drop the trailing pairs.  target 0: grow one pair if the indicator
+ * eps_perp = ||(I - U U^T) J G|| / ||G|| exceeds rank_tol_up and the cap
+ * allows; otherwise drop the pairs whose singular value of Z~ is below
+ * rank_tol_down times the largest (at least one pair stays).  (The paper
+ * defers rank adaptation to future work, Sec. 6.4.)  new_two_n: host,
+ * nullable.  Errors: ERANKCAP beyond two_n_max, EINVAL for odd targets,
+ * ESINGULAR when the new directions cannot be formed (the state is then
+ * unchanged). */
 symrom_status rom_adapt_rank(symrom_rom* h, int32_t target_two_n, int32_t* new_two_n);
 
 /* Copy the state out: U_X (N x 2n, ld N) and Z (2n x p, ld 2n), device;
@@ -142,6 +174,28 @@ symrom_status rom_set_state(symrom_rom* h, int32_t two_n, const double* UX, cons
 
 /* R = U Z: positions X_r = U_X Z and velocities V_r = U_V Z (device, N x p). */
 symrom_status rom_reconstruct(symrom_rom* h, double* X, double* V);
+
+/* R = U Z on a subset of particle rows (Sec. 3.2, eq. UZred): rows (device
+ * int32 [nrows]) lists the rows; X, V (device, nrows x p, column-major,
+ * ld nrows; each nullable) receive X_r and V_r of those rows.  A row index
+ * outside [0, N) gives NaN in its output row.  Synchronises the stream. */
+symrom_status rom_reconstruct_rows(symrom_rom* h, const int32_t* rows, int32_t nrows, double* X,
+                                   double* V);
+
+/* The particle-to-cell map of the reduced model (Sec. 2.1, node index of
+ * x = Re(U~ Z~) with the position arithmetic of the fused deposit, gather and
+ * projection kernels): cells (device int32, N x p) and, nullable, the scaled
+ * positions s = x N_x / L (device, N x p) whose floor gives the cell.  Z
+ * (device, 2n x p, nullable) replaces the handle's coefficients for this call
+ * only.  Synchronises the stream. */
+symrom_status rom_cells(symrom_rom* h, const double* Z, int32_t* cells, double* s);
+
+/* The DEIM operator of the last DEIM step (Sec. 4.2.2; with rank_auto it is
+ * the one already built for the next step): the d sample indices in greedy
+ * order (device int32, capacity >= d) and the weights w = (P^T Psi)^{-T}
+ * Psi^T 1 of eq. grHDD (device, capacity >= d); d (host, nullable).
+ * Errors: ESTATE when no DEIM operator has been built yet. */
+symrom_status rom_deim_operator(symrom_rom* h, int32_t* idx, double* w, int32_t* d);
 
 /* Per-parameter electric energy E(X_r^i) (eq. HamEEfull) and Hamiltonian
  * H = 1/2 |V_r^i|^2 + E (device [p] each). */
@@ -185,6 +239,19 @@ void fom_destroy(symrom_fom* h);
 /* ------------------------------------------------------------------------
  * Stateless particle-to-grid pieces (Sec. 2.1), for tests and tools
  * ------------------------------------------------------------------------ */
+
+/* Workspace bytes for deim_select; 0 unless 1 <= d <= 64 and d <= N. */
+size_t deim_select_workspace_bytes(int32_t N, int32_t d);
+
+/* Greedy DEIM selection (Sec. 4.2.2) on a given orthonormal basis Psi
+ * (device, N x d, column-major): idx[0] = argmax |psi_1|, then for k >= 2
+ * the index of the largest |r_k|, r_k = psi_k - Psi_{k-1} (P^T Psi_{k-1})^{-1}
+ * P^T psi_k (ties to the smaller index); and the weights
+ * w = (P^T Psi)^{-T} Psi^T 1 of eq. grHDD.  idx (device int32 [d]), w (device
+ * [d]).  The kernels are those of the reduced step.  Errors: EINVAL, ENOMEM,
+ * ESINGULAR when a residual vanishes everywhere (rank-deficient basis). */
+symrom_status deim_select(int32_t N, int32_t d, const double* Psi, int32_t* idx, double* w,
+                          void* ws, size_t ws_bytes, void* stream);
 
 /* Workspace bytes for pic_fields. */
 size_t pic_workspace_bytes(int32_t N, int32_t p, int32_t Nx);

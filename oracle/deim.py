@@ -95,7 +95,8 @@ def update_window(st, cfg, U0, gr0):
         st.deim_indices = None
         return None
     Y = np.concatenate(st.window, axis=1)
-    op = build_operator(Y, cfg.two_n)
+    d = cfg.deim_rows if cfg.deim_rows > 0 else cfg.two_n
+    op = build_operator(Y, min(d, Y.shape[1]))
     st.deim_indices = op.idx
     return op
 

@@ -95,6 +95,7 @@ class RomConfig:
     pinv_rtol: float = 1e-12
     projection: str = "galerkin"  # or "deim"
     deim_window: int = 3          # T: the window holds T + 1 snapshots
+    deim_rows: int = 0            # d, DEIM sample rows; 0: d = 2n
     reorth: bool = True
     rank_auto: bool = False
     rank_tol_up: float = 1e-2

@@ -37,7 +37,10 @@ class Config(ctypes.Structure):
         ("fp_tol", ctypes.c_double), ("fp_max_iters", ctypes.c_int32),
         ("fp_fixed_iters", ctypes.c_int32), ("pinv_rtol", ctypes.c_double),
         ("reorth", ctypes.c_int32), ("rank_auto", ctypes.c_int32),
-        ("rank_tol_up", ctypes.c_double),
+        ("rank_tol_up", ctypes.c_double), ("fp_stall_tol", ctypes.c_double),
+        ("rank_tol_down", ctypes.c_double), ("deim_rows", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("deterministic", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -46,6 +49,8 @@ class StepInfo(ctypes.Structure):
         ("iters", ctypes.c_int32), ("stalled", ctypes.c_int32), ("two_n", ctypes.c_int32),
         ("deim_active", ctypes.c_int32), ("rank_indicator", ctypes.c_double),
         ("iters_total", ctypes.c_int32), ("deim_steps", ctypes.c_int32),
+        ("stall_rel", ctypes.c_double), ("stalled_total", ctypes.c_int32),
+        ("shrunk", ctypes.c_int32),
     ]
 
 
@@ -56,10 +61,18 @@ _SIGS = {
                                   ctypes.POINTER(_VP)]),
     "rom_step": (ctypes.c_int32, [_VP, ctypes.c_int32, ctypes.POINTER(StepInfo)]),
     "rom_adapt_rank": (ctypes.c_int32, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "rom_set_fixed_point": (ctypes.c_int32, [_VP, ctypes.c_double, ctypes.c_int32,
+                                             ctypes.c_int32]),
     "rom_get_state": (ctypes.c_int32, [_VP, _VP, _VP, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int64)]),
     "rom_set_state": (ctypes.c_int32, [_VP, ctypes.c_int32, _VP, _VP, ctypes.c_int64]),
     "rom_reconstruct": (ctypes.c_int32, [_VP, _VP, _VP]),
+    "rom_reconstruct_rows": (ctypes.c_int32, [_VP, _VP, ctypes.c_int32, _VP, _VP]),
+    "rom_cells": (ctypes.c_int32, [_VP, _VP, _VP, _VP]),
+    "rom_deim_operator": (ctypes.c_int32, [_VP, _VP, _VP, ctypes.POINTER(ctypes.c_int32)]),
+    "deim_select_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "deim_select": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP, _VP,
+                                     ctypes.c_size_t, _VP]),
     "rom_diagnostics": (ctypes.c_int32, [_VP, _VP, _VP]),
     "rom_gradient": (ctypes.c_int32, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "rom_destroy": (None, [_VP]),
@@ -153,12 +166,22 @@ def kernel_work(family):
 
 def make_config(N, p, Nx, two_n, two_n_max=None, dt=0.05, q=-1.0, m=1.0, projection="galerkin",
                 deim_window=3, fp_tol=1e-9, fp_max_iters=100, fp_fixed_iters=0, pinv_rtol=1e-12,
-                reorth=True, rank_auto=False, rank_tol_up=1e-2):
+                reorth=True, rank_auto=False, rank_tol_up=1e-2, fp_stall_tol=1e-3,
+                rank_tol_down=1e-8, deim_rows=0, deterministic=False):
     return Config(N=N, p=p, Nx=Nx, two_n=two_n, two_n_max=two_n_max or two_n, dt=dt, q=q, m=m,
                   projection=DEIM if projection == "deim" else GALERKIN,
                   deim_window=deim_window, fp_tol=fp_tol, fp_max_iters=fp_max_iters,
                   fp_fixed_iters=fp_fixed_iters, pinv_rtol=pinv_rtol, reorth=int(reorth),
-                  rank_auto=int(rank_auto), rank_tol_up=rank_tol_up)
+                  rank_auto=int(rank_auto), rank_tol_up=rank_tol_up, fp_stall_tol=fp_stall_tol,
+                  rank_tol_down=rank_tol_down, deim_rows=deim_rows, precision=0,
+                  deterministic=int(deterministic), reserved=0)
+
+
+def _info_dict(info):
+    return dict(iters=info.iters, stalled=info.stalled, two_n=info.two_n,
+                deim_active=info.deim_active, rank_indicator=info.rank_indicator,
+                iters_total=info.iters_total, deim_steps=info.deim_steps,
+                stall_rel=info.stall_rel, stalled_total=info.stalled_total, shrunk=info.shrunk)
 
 
 def _dev(x, device="cuda"):
@@ -206,14 +229,15 @@ class Rom:
     def step(self, nsteps=1):
         info = StepInfo()
         _check(lib().rom_step(self.h, nsteps, ctypes.byref(info)))
-        return dict(iters=info.iters, stalled=info.stalled, two_n=info.two_n,
-                    deim_active=info.deim_active, rank_indicator=info.rank_indicator,
-                    iters_total=info.iters_total, deim_steps=info.deim_steps)
+        return _info_dict(info)
 
     def step_status(self, nsteps=1):
         info = StepInfo()
         st = lib().rom_step(self.h, nsteps, ctypes.byref(info))
-        return st, dict(iters=info.iters, stalled=info.stalled)
+        return st, _info_dict(info)
+
+    def set_fixed_point(self, fp_tol, fp_max_iters=100, fp_fixed_iters=0):
+        _check(lib().rom_set_fixed_point(self.h, fp_tol, fp_max_iters, fp_fixed_iters))
 
     def adapt_rank(self, target=0):
         out = ctypes.c_int32()
@@ -238,6 +262,31 @@ class Rom:
         V = torch.empty_like(X)
         _check(lib().rom_reconstruct(self.h, _ptr(X), _ptr(V)))
         return X, V
+
+    def reconstruct_rows(self, rows):
+        """X_r, V_r of the listed particle rows: tensors (p, len(rows))."""
+        rows = torch.as_tensor(np.asarray(rows, dtype=np.int32)).cuda()
+        nr = rows.numel()
+        X = torch.empty((self.cfg.p, nr), dtype=torch.float64, device="cuda")
+        V = torch.empty_like(X)
+        _check(lib().rom_reconstruct_rows(self.h, _ptr(rows), nr, _ptr(X), _ptr(V)))
+        return X, V
+
+    def cells(self, Z=None):
+        """Cells (p, N) int32 and scaled positions s (p, N) of the fused kernels."""
+        cells = torch.empty((self.cfg.p, self.cfg.N), dtype=torch.int32, device="cuda")
+        sv = torch.empty((self.cfg.p, self.cfg.N), dtype=torch.float64, device="cuda")
+        Zp = _ptr(Z.contiguous()) if Z is not None else None
+        _check(lib().rom_cells(self.h, Zp, _ptr(cells), _ptr(sv)))
+        return cells, sv
+
+    def deim_operator(self):
+        """(indices int32 (d,), weights (d,)) of the last DEIM step."""
+        idx = torch.empty(64, dtype=torch.int32, device="cuda")
+        w = torch.empty(64, dtype=torch.float64, device="cuda")
+        d = ctypes.c_int32()
+        _check(lib().rom_deim_operator(self.h, _ptr(idx), _ptr(w), ctypes.byref(d)))
+        return idx[: d.value], w[: d.value]
 
     def diagnostics(self):
         E = torch.empty(self.cfg.p, dtype=torch.float64, device="cuda")
@@ -313,3 +362,19 @@ def pic_fields(X, L, Nx, q=-1.0, stream=None):
     _check(lib().pic_fields(N, p, Nx, Lp, q, _ptr(X), _ptr(cells), _ptr(rho), _ptr(Phi), _ptr(e),
                             _ptr(ws), nbytes, _stream(stream)))
     return cells, rho, Phi, e
+
+
+def deim_select(Psi, stream=None):
+    """Greedy DEIM indices and weights of a basis Psi (numpy N x d, or a
+    device tensor (d, N)): (idx int32 (d,), w (d,)) device tensors."""
+    P = _dev(Psi)
+    d, N = P.shape
+    nbytes = lib().deim_select_workspace_bytes(N, d)
+    if nbytes == 0:
+        raise SymromError(EINVAL, "invalid sizes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    idx = torch.empty(d, dtype=torch.int32, device="cuda")
+    w = torch.empty(d, dtype=torch.float64, device="cuda")
+    _check(lib().deim_select(N, d, _ptr(P), _ptr(idx), _ptr(w), _ptr(ws), nbytes,
+                             _stream(stream)))
+    return idx, w

@@ -180,6 +180,10 @@ PicGeom pic_geom(int N, int p, int Nx, size_t lds_per_table_budget, int min_bloc
   int max_nrb = (N + 255) / 256;
   if (nrb > max_nrb) nrb = max_nrb;
   if (nrb < 1) nrb = 1;
+  // fewer than 2^24 rows per block (the deterministic deposit's integer
+  // theta sums stay below 2^64)
+  const int min_nrb = (int)((N + (1 << 24) - 2) / ((1 << 24) - 1));
+  if (nrb < min_nrb) nrb = min_nrb;
   g.rpb = (N + nrb - 1) / nrb;
   g.nrb = (N + g.rpb - 1) / g.rpb;
   return g;
@@ -447,7 +451,7 @@ struct symrom_rom {
   int fp_hint;   // iterations the last fixed point took (speculative batch size)
   bool stage1_cached;  // G, g and the fields in the buffers belong to (U0, Z0)
   double* colsq;       // per-parameter |G~|^2
-  // DEIM (Sec. 4.3): snapshot ring of T+1 slots (N x psub each) and operator
+  // DEIM (Sec. 4.2.2): snapshot ring of T+1 slots (N x psub each) and operator
   int psub, nslots, win_count, d_cur;
   bool deim_on;
   int* sub;
@@ -478,6 +482,7 @@ struct symrom_rom {
   // means it is built again for the same slot).
   bool head_pending;
   int head_n;
+  double* zsig;  // singular values of Z~ (automatic shrink)
   symrom_step_info last;
 };
 
@@ -552,7 +557,7 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.nslots = r.cfg.deim_window + 1;
   r.psub = deim_psub(r.cfg);
   const int P = r.psub * r.nslots;
-  const int dmax = 2 * nm;
+  const int dmax = std::max(2 * nm, r.cfg.deim_rows);
   r.nbg = 256;
   r.nbc = 64;
   r.sub = ar.take<int>(r.psub);
@@ -573,6 +578,7 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.C12 = ar.take<cplx>((size_t)2 * nm * nm);
   r.C12a = ar.take<cplx>((size_t)2 * nm * nm);
   r.gF = ar.take<cplx>((size_t)nm * p);
+  r.zsig = ar.take<double>(nm);
   r.dpart = ar.take<double>(r.cfg.projection == SYMROM_DEIM ? (size_t)r.nkb * 64 * 64 * 2 : 0);
 }
 
@@ -607,6 +613,22 @@ bool valid_rom_config(const symrom_config* c, std::string& why) {
   }
   if (c->projection != SYMROM_GALERKIN && c->projection != SYMROM_DEIM) {
     why = "projection";
+    return false;
+  }
+  if (!(c->fp_stall_tol >= 0.0) || !(c->rank_tol_down >= 0.0) || !(c->rank_tol_down < 1.0)) {
+    why = "fp_stall_tol >= 0 and 0 <= rank_tol_down < 1";
+    return false;
+  }
+  if (c->deim_rows < 0 || c->deim_rows > 64) {
+    why = "deim_rows must be in 0..64 (0: d = 2n)";
+    return false;
+  }
+  if (c->precision != SYMROM_FP64) {
+    why = "precision: only SYMROM_FP64 arithmetic is built";
+    return false;
+  }
+  if (c->deterministic != 0 && c->deterministic != 1) {
+    why = "deterministic must be 0 or 1";
     return false;
   }
   if (c->p > 64) {
@@ -687,7 +709,7 @@ void full_gradient_field(symrom_rom& r, const cplx* U, const cplx* Z, const int*
       Timer t(FAM_DEPOSIT, s, 4.0 * n * (double)r.N * pact,
               16.0 * n * ((double)r.N + r.p) + 8.0 * (double)r.gdep.nrb * pact * r.Nx);
       launch_deposit_rom(s, U, r.N, n, Z, r.p, r.Nx, r.gdep, r.b.factor, active, r.b.part,
-                         gate, fold);
+                         gate, fold, r.cfg.deterministic);
     }
     Timer t(FAM_POISSON, s);
     launch_poisson(s, r.b.part, r.gdep.nrb, r.p, r.Nx, r.b.qw, r.b.h, r.b.mw, active, r.b.rho,
@@ -855,7 +877,8 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z, bool redo = false,
   }
   r.deim_on = r.win_count >= r.nslots;
   if (!r.deim_on) return;
-  const int d = (2 * n < P) ? 2 * n : P;
+  const int dreq = r.cfg.deim_rows > 0 ? r.cfg.deim_rows : 2 * n;
+  const int d = (dreq < P) ? dreq : P;
   r.d_cur = d;
   {
     const double fP = P, fd = d;
@@ -913,6 +936,16 @@ symrom_status read_flags(symrom_rom& r, int* host) {
 }
 
 symrom_status rom_grow_apply(symrom_rom& r, int k);
+symrom_status rom_shrink(symrom_rom& r, int n_new);
+symrom_status shrink_exact(symrom_rom& r);
+
+// Certificate of the automatic shrink for the current Z0 into status word 13
+// (0: nothing can be dropped, 1: the singular values must be computed).
+void launch_shrink_cert(symrom_rom& r) {
+  const double tol = r.cfg.rank_tol_down;
+  const double c = std::max(2.0 * tol * tol, 1e-13);
+  launch_dense_rank_cert(r.s, r.Z0, r.n, r.p, c, r.status + 13);
+}
 
 // One step of the reduced model; with decide_rank, the rank indicator at the
 // new state and a growth by one pair when it exceeds the threshold.
@@ -983,7 +1016,7 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
           Timer t(FAM_DEPOSIT, s, 4.0 * n * (double)N * pact,
                   16.0 * n * ((double)N + p) + 8.0 * (double)r.gdep.nrb * pact * r.Nx);
           launch_deposit_rom(s, r.Uh, N, n, r.Zev, p, r.Nx, r.gdep, r.b.factor, r.active,
-                             r.b.part, gate);
+                             r.b.part, gate, nullptr, r.cfg.deterministic);
         }
         {
           // per parameter: the Poisson solve, the DEIM gather of the sampled
@@ -992,18 +1025,20 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
           launch_poisson_deim(s, r.b.part, r.gdep.nrb, p, r.Nx, r.b.qw, r.b.h, r.b.mw, r.active,
                               r.b.rho, r.b.phi, r.b.e, r.b.energy, gate, r.Uh, N, n, r.Zev,
                               r.b.factor, r.cfg.q / r.cfg.m, r.didx, r.dw, r.d_cur, r.gF, r.C12,
-                              r.Z0, r.ZG, r.k, r.prev, dt, r.cfg.fp_tol, fixed > 0 ? 1 : 0,
-                              launched + 1, r.counters);
+                              r.Z0, r.ZG, r.k, r.prev, dt, r.cfg.fp_tol, r.cfg.fp_stall_tol,
+                              fixed > 0 ? 1 : 0, launched + 1, r.counters);
         }
       } else {
         full_gradient(r, r.Uh, r.Zev, r.active, true, false, gate);
         Timer t(FAM_DENSE, s);
         launch_dense_fp_update(s, r.gproj, r.C12, n, p, r.Z0, r.Zev, r.ZG, r.k, r.prev, r.active,
-                               dt, r.cfg.fp_tol, fixed > 0 ? 1 : 0, 0, r.counters);
+                               dt, r.cfg.fp_tol, r.cfg.fp_stall_tol, fixed > 0 ? 1 : 0, 0,
+                               r.counters);
       }
     }
     LAUNCHCHK();
-    HIPCHK(hipMemcpyAsync(r.hstat + 4, r.counters, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    // counters [0..2] and the largest stall-accepted update (words 6..7)
+    HIPCHK(hipMemcpyAsync(r.hstat + 4, r.counters, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (int q = 0; q < 3; ++q) hc[q] = r.hstat[4 + q];
     r.n_active = hc[0];
@@ -1014,8 +1049,20 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   if (fixed == 0) r.fp_hint = iters;
   r.last.iters = iters;
   r.last.stalled = hc[1];
+  std::memcpy(&r.last.stall_rel, r.hstat + 10, sizeof(double));
   r.last.deim_active = deim ? 1 : 0;
-  if (fixed == 0 && hc[0] > 0) return fail(SYMROM_ENOCONV, "fixed point not converged");
+  r.last.shrunk = 0;
+  if (fixed == 0 && hc[0] > 0) {
+    // the state, the DEIM snapshot window included, stays as it was: the
+    // snapshot of this step (counted in win_count whether it was taken now
+    // or ahead of the step, and written into the slot of the oldest one,
+    // which the next attempt at this step drops again) is taken back
+    if (use_deim) {
+      r.win_count--;
+      r.deim_on = r.win_count >= r.nslots;
+    }
+    return fail(SYMROM_ENOCONV, "fixed point not converged");
+  }
   // basis velocity at (U_half, Z_G) with the field of each column's last
   // evaluation; S(Z_G)^+ and Z1 = Z0 + dt k on the second stream (idle here)
   // beside the projection
@@ -1082,10 +1129,11 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
     if (ahead) HIPCHK(hipEventRecord(r.ev_fork, s));
     full_gradient(r, r.U0, r.Z0, nullptr, false, true);
     launch_dense_indicator(s, r.colsq, r.gproj, n, p, r.eps_dev);
+    if (r.cfg.rank_tol_down > 0.0) launch_shrink_cert(r);
   }
   // the status copy is started before the chain ahead is enqueued, and
   // waited for after
-  HIPCHK(hipMemcpyAsync(r.hstat, r.status, 12 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(r.hstat, r.status, 14 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipEventRecord(r.ev_read, s));
   if (ahead) {
     // the next step's DEIM chain, beside the readback; its head does
@@ -1121,6 +1169,8 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   if (!(eps > r.cfg.rank_tol_up) || 2 * (n + 1) > r.cfg.two_n_max) {
     // the gradient just computed is the next step's first-stage gradient
     r.stage1_cached = true;
+    // no growth: the automatic shrink, when the certificate does not rule it out
+    if (r.cfg.rank_tol_down > 0.0 && r.hstat[13] != 0) return shrink_exact(r);
     return SYMROM_OK;
   }
   // the growth rewrites Z0 in its new layout: the head must be done with it
@@ -1200,6 +1250,7 @@ extern "C" symrom_status rom_init(const symrom_config* cfg, const double* L, con
   if (!ws || ws_bytes < need) return fail(SYMROM_ENOMEM, "rom_init: workspace too small");
   symrom_rom* r = new symrom_rom{};
   r->cfg = *cfg;
+  if (r->cfg.fp_stall_tol == 0.0) r->cfg.fp_stall_tol = 1e-3;
   r->N = cfg->N;
   r->p = cfg->p;
   r->Nx = cfg->Nx;
@@ -1320,16 +1371,20 @@ void side_wait(symrom_rom* r) {
 extern "C" symrom_status rom_step(symrom_rom* r, int32_t nsteps, symrom_step_info* info) {
   if (!r || nsteps < 0) return fail(SYMROM_EINVAL, "rom_step: bad arguments");
   if (!r->ready) return fail(SYMROM_ESTATE, "rom_step: handle not initialised");
-  int64_t iters_total = 0, deim_steps = 0;
+  int64_t iters_total = 0, deim_steps = 0, stalled_total = 0;
   r->last.iters_total = 0;
   r->last.deim_steps = 0;
+  r->last.stalled_total = 0;
   for (int it = 0; it < nsteps; ++it) {
     symrom_status st = rom_step_one(*r, r->cfg.rank_auto != 0);
     iters_total += r->last.iters;
     deim_steps += r->last.deim_active;
+    stalled_total += r->last.stalled;
     r->last.iters_total = (int32_t)iters_total;
     r->last.deim_steps = (int32_t)deim_steps;
+    r->last.stalled_total = (int32_t)stalled_total;
     if (st != SYMROM_OK) {
+      r->last.two_n = 2 * r->n;
       if (info) *info = r->last;
       return st;
     }
@@ -1361,11 +1416,47 @@ symrom_status rom_grow(symrom_rom& r, int k, bool decide) {
     if (!(eps > r.cfg.rank_tol_up) || 2 * (n + 1) > r.cfg.two_n_max) {
       // the gradient just computed is the next step's first-stage gradient
       r.stage1_cached = true;
+      if (r.cfg.rank_tol_down > 0.0) {
+        launch_shrink_cert(r);
+        LAUNCHCHK();
+        int word = 0;
+        HIPCHK(hipMemcpyAsync(&word, r.status + 13, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (word != 0) return shrink_exact(r);
+      }
       return SYMROM_OK;
     }
     k = 1;
   }
   return rom_grow_apply(r, k);
+}
+
+// The automatic shrink after the certificate failed: the singular values of
+// Z~ (one-sided Jacobi), then a rotation to the singular vectors of Z~ and
+// the drop of the pairs below rank_tol_down times the largest (at least one
+// pair is kept).
+symrom_status shrink_exact(symrom_rom& r) {
+  hipStream_t s = r.s;
+  const int n = r.n, p = r.p;
+  cplx* work = (p >= n) ? r.Gp : r.Xv;
+  launch_dense_zsvals(s, r.Z0, n, p, work, r.zsig);
+  LAUNCHCHK();
+  std::vector<double> sg(n);
+  HIPCHK(hipMemcpyAsync(sg.data(), r.zsig, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (!(sg[0] > 0.0)) return SYMROM_OK;
+  int keep = 0;
+  for (int a = 0; a < n; ++a)
+    if (sg[a] >= r.cfg.rank_tol_down * sg[0]) ++keep;
+  if (keep < 1) keep = 1;
+  if (keep >= n) return SYMROM_OK;
+  // the DEIM head built ahead reads U0 and Z0; the next step builds it again
+  if (r.head_pending && r.s2) HIPCHK(hipStreamSynchronize(r.s2));
+  symrom_status st = rom_shrink(r, keep);
+  r.stage1_cached = false;
+  r.head_n = -1;
+  r.last.shrunk = n - keep;
+  return st;
 }
 
 // Growth by k pairs with the full gradient at (U0, Z0) (field and g) in the
@@ -1382,16 +1473,33 @@ symrom_status rom_grow_apply(symrom_rom& r, int k) {
   if (k > p) return fail(SYMROM_EINVAL, "cannot grow by more pairs than parameters");
   launch_dense_herm_eig(s, r.Gp, p, r.Vp, r.lam, r.flags);
   launch_dense_grow_prep(s, r.Vp, r.lam, r.gproj, n, p, k, r.Q, r.MP, r.flags);
-  launch_rowgemm(s, rt(r.G, r.Q, p, r.U0, r.MP, n), N, k, r.U0 + (size_t)n * N);
+  // the new columns go beyond the current basis (the state is not touched
+  // until the flags are known)
+  cplx* Y = r.U0 + (size_t)n * N;
+  launch_rowgemm(s, rt(r.G, r.Q, p, r.U0, r.MP, n), N, k, Y);
+  // Y came through the eigenvectors of a p x p Gram, so it is orthogonal to
+  // U~ and orthonormal only to about eps cond^2: project U~ out of it and
+  // orthonormalise it by Cholesky QR, twice (R = U Z is unaffected: the new
+  // coefficient rows are zero)
+  for (int pass = 0; pass < 2; ++pass) {
+    launch_gemm_ah_b(s, ml(r.U0, n), n, ml(Y, k), k, false, N, r.nkb, r.gemm_part, r.M1);
+    launch_proj_mats(s, r.M1, n, k, r.M2, r.M3);
+    launch_rowgemm(s, rt(Y, r.M2, k, r.U0, r.M3, n), N, k, r.Xv);
+    launch_copy_cplx(s, Y, r.Xv, (size_t)N * k);
+    launch_gemm_ah_b(s, ml(Y, k), k, ml(Y, k), k, false, N, r.nkb, r.gemm_part, r.Gram);
+    launch_cholqr_apply(s, r.Gram, k, Y, N, nullptr, p, r.flags);
+  }
   launch_colphase(s, r.U0, N, n, k);
-  launch_z_resize(s, r.Z0, n, r.Z1, n + k, p);
-  launch_copy_cplx(s, r.Z0, r.Z1, (size_t)(n + k) * p);
   LAUNCHCHK();
   int fl[2];
   symrom_status st = read_flags(r, fl);
   if (st != SYMROM_OK) return st;
   if (fl[0]) return fail(SYMROM_ESINGULAR, "rank growth: indicator matrix has too small rank");
+  launch_z_resize(s, r.Z0, n, r.Z1, n + k, p);
+  std::swap(r.Z0, r.Z1);
+  LAUNCHCHK();
   r.n = n + k;
+  r.head_n = -1;
   return SYMROM_OK;
 }
 
@@ -1418,12 +1526,18 @@ extern "C" symrom_status rom_adapt_rank(symrom_rom* r, int32_t target_two_n, int
     return fail(SYMROM_EINVAL, "rom_adapt_rank: target must be even and non-negative");
   if (target_two_n > r->cfg.two_n_max) return fail(SYMROM_ERANKCAP, "rom_adapt_rank: above cap");
   symrom_status st = SYMROM_OK;
+  r->last.shrunk = 0;
+  const int n_before = r->n;
   if (target_two_n == 0)
     st = rom_grow(*r, 0, true);
   else if (target_two_n > 2 * r->n)
     st = rom_grow(*r, (target_two_n - 2 * r->n) / 2, false);
   else if (target_two_n < 2 * r->n)
     st = rom_shrink(*r, target_two_n / 2);
+  // a DEIM head built ahead of the next step snapshots the state it saw:
+  // after any change of U or Z it is rebuilt (same slot) by the next step
+  if (target_two_n != 0 && target_two_n != 2 * n_before) r->head_n = -1;
+  if (r->n != n_before) r->head_n = -1;
   if (new_two_n) *new_two_n = 2 * r->n;
   return st;
 }
@@ -1472,6 +1586,119 @@ extern "C" symrom_status rom_reconstruct(symrom_rom* r, double* X, double* V) {
   return SYMROM_OK;
 }
 
+extern "C" symrom_status rom_set_fixed_point(symrom_rom* r, double fp_tol, int32_t fp_max_iters,
+                                             int32_t fp_fixed_iters) {
+  if (!r || !(fp_tol >= 0.0) || fp_max_iters < 1 || fp_fixed_iters < 0)
+    return fail(SYMROM_EINVAL, "rom_set_fixed_point: bad arguments");
+  r->cfg.fp_tol = fp_tol;
+  r->cfg.fp_max_iters = fp_max_iters;
+  r->cfg.fp_fixed_iters = fp_fixed_iters;
+  return SYMROM_OK;
+}
+
+extern "C" symrom_status rom_reconstruct_rows(symrom_rom* r, const int32_t* rows, int32_t nrows,
+                                              double* X, double* V) {
+  side_wait(r);
+  if (!r || !rows || nrows < 0) return fail(SYMROM_EINVAL, "rom_reconstruct_rows: bad arguments");
+  launch_reconstruct(r->s, r->U0, r->N, r->n, r->Z0, r->p, X, V, rows, nrows);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(r->s));
+  return SYMROM_OK;
+}
+
+extern "C" symrom_status rom_cells(symrom_rom* r, const double* Z, int32_t* cells, double* s) {
+  side_wait(r);
+  if (!r || !cells) return fail(SYMROM_EINVAL, "rom_cells: null argument");
+  hipStream_t st = r->s;
+  const cplx* Zc = r->Z0;
+  if (Z) {
+    r->stage1_cached = false;
+    launch_z_from_real(st, Z, r->n, r->p, r->Zev);
+    Zc = r->Zev;
+  }
+  launch_rom_cells(st, r->U0, r->N, r->n, Zc, r->p, r->Nx, r->b.factor, cells, s);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(st));
+  return SYMROM_OK;
+}
+
+extern "C" symrom_status rom_deim_operator(symrom_rom* r, int32_t* idx, double* w, int32_t* d) {
+  side_wait(r);
+  if (!r || !idx || !w) return fail(SYMROM_EINVAL, "rom_deim_operator: null argument");
+  if (r->cfg.projection != SYMROM_DEIM || !r->deim_on)
+    return fail(SYMROM_ESTATE, "rom_deim_operator: no DEIM operator has been built");
+  hipStream_t s = r->s;
+  HIPCHK(hipMemcpyAsync(idx, r->didx, r->d_cur * sizeof(int), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(w, r->dw, r->d_cur * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (d) *d = r->d_cur;
+  return SYMROM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stateless DEIM selection on a given basis (the kernels of the step)
+// ---------------------------------------------------------------------------
+namespace {
+struct SelBufs {
+  double *psi, *colpart, *eye, *bval, *dB, *dcv;
+  int *bidx, *flags;
+};
+SelBufs carve_sel(Arena& ar, int N, int d) {
+  SelBufs b;
+  b.psi = ar.take<double>((size_t)N * d);
+  b.colpart = ar.take<double>((size_t)psi_blocks(N) * d);
+  b.eye = ar.take<double>((size_t)d * d);
+  b.bval = ar.take<double>(2 * 256);
+  b.dB = ar.take<double>(2 * 64 * 64);
+  b.dcv = ar.take<double>(2 * 64);
+  b.bidx = ar.take<int>(2 * 256);
+  b.flags = ar.take<int>(4);
+  return b;
+}
+}  // namespace
+
+extern "C" size_t deim_select_workspace_bytes(int32_t N, int32_t d) {
+  if (N < 1 || d < 1 || d > 64 || d > N) return 0;
+  Arena ar(nullptr);
+  carve_sel(ar, N, d);
+  return ar.off + 256;
+}
+
+extern "C" symrom_status deim_select(int32_t N, int32_t d, const double* Psi, int32_t* idx,
+                                     double* w, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || d < 1 || d > 64 || d > N || !Psi || !idx || !w)
+    return fail(SYMROM_EINVAL, "deim_select: bad arguments");
+  if (!ws || ws_bytes < deim_select_workspace_bytes(N, d))
+    return fail(SYMROM_ENOMEM, "deim_select: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  Arena ar(ws);
+  SelBufs b = carve_sel(ar, N, d);
+  std::vector<double> eye((size_t)d * d, 0.0);
+  for (int c = 0; c < d; ++c) eye[(size_t)c * d + c] = 1.0;
+  HIPCHK(hipMemcpyAsync(b.eye, eye.data(), eye.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(b.flags, 0, 4 * sizeof(int), s));
+  // Psi I: a copy of the basis and its per-block column sums, as the step
+  // forms them from the snapshots
+  const double* in[1] = {Psi};
+  launch_psi_colsum(s, in, 1, d, N, b.eye, d, d, b.psi, b.colpart);
+  const int nbg = 256;
+  for (int k = 0; k < d; ++k) {
+    const int cur = k & 1, prev = cur ^ 1;
+    launch_deim_greedy(s, b.psi, N, k, idx, b.bval + prev * nbg, b.bidx + prev * nbg, nbg, nbg,
+                       b.bval + cur * nbg, b.bidx + cur * nbg, b.dB + prev * 4096,
+                       b.dcv + prev * 64, b.dB + cur * 4096, b.dcv + cur * 64, b.flags);
+  }
+  const int last = (d - 1) & 1;
+  launch_deim_weights(s, b.psi, N, d, idx, b.bval + last * nbg, b.bidx + last * nbg, nbg,
+                      b.dB + last * 4096, b.dcv + last * 64, b.colpart, psi_blocks(N), w, b.flags);
+  LAUNCHCHK();
+  int fl = 0;
+  HIPCHK(hipMemcpyAsync(&fl, b.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (fl) return fail(SYMROM_ESINGULAR, "deim_select: the basis has no finite residual left");
+  return SYMROM_OK;
+}
+
 extern "C" symrom_status rom_gradient(symrom_rom* r, const double* Z, double* g, double* rho,
                                       double* Phi, double* e) {
   side_wait(r);
@@ -1497,7 +1724,8 @@ extern "C" symrom_status rom_diagnostics(symrom_rom* r, double* E, double* H) {
   r->stage1_cached = false;
   hipStream_t s = r->s;
   const int N = r->N, p = r->p, n = r->n;
-  launch_deposit_rom(s, r->U0, N, n, r->Z0, p, r->Nx, r->gdep, r->b.factor, nullptr, r->b.part);
+  launch_deposit_rom(s, r->U0, N, n, r->Z0, p, r->Nx, r->gdep, r->b.factor, nullptr, r->b.part,
+                     nullptr, nullptr, r->cfg.deterministic);
   launch_poisson(s, r->b.part, r->gdep.nrb, p, r->Nx, r->b.qw, r->b.h, r->b.mw, nullptr, r->b.rho,
                  r->b.phi, r->b.e, r->b.energy);
   if (E) HIPCHK(hipMemcpyAsync(E, r->b.energy, p * 8, hipMemcpyDeviceToDevice, s));

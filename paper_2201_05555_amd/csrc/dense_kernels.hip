@@ -810,15 +810,18 @@ __global__ void __launch_bounds__(256) cholqr_apply_kernel(const cplx* __restric
 // column).  k_new = -i g (g = gF, plus (C1 Z - conj(C2) conj(Z)) / 2 when the
 // projection covered positions only: i U~^* V_r with V_r = Im(U~ Z~)).
 // For an active column:  rel = |k_new - k| / |k_new|;  converged if
-// rel < tol, stalled if not converged and rel >= the previous rel (a
-// particle on a node puts the map into a 2-cycle); k <- k_new; ZG <- Zeval;
-// if still active, Zeval <- Z0 + dt/2 k.  counters[0] = active columns left,
-// counters[1] += stalled.  fixed != 0 disables the test.
+// rel < tol, stalled if not converged, rel >= the previous rel (a particle
+// on a node puts the map into a 2-cycle) and rel < stall_tol (a stall above
+// that floor keeps iterating); k <- k_new; ZG <- Zeval; if still active,
+// Zeval <- Z0 + dt/2 k.  counters[0] = active columns left, counters[1] +=
+// stalled, the double at counters + 6 = the largest rel accepted by a stall
+// (atomic maximum of the bit patterns, which order like the values for
+// rel >= 0).  fixed != 0 disables the test.
 __global__ void __launch_bounds__(DTPB) dense_fp_update_kernel(
     const cplx* __restrict__ gF, const cplx* __restrict__ C12, int n, int p,
     const cplx* __restrict__ Z0, cplx* __restrict__ Zeval, cplx* __restrict__ ZG,
     cplx* __restrict__ k, double* __restrict__ prev, int* __restrict__ active, double dt,
-    double tol, int fixed, int linear_part, int* __restrict__ counters) {
+    double tol, double stall_tol, int fixed, int linear_part, int* __restrict__ counters) {
   // nothing left to iterate: a speculative launch after convergence
   if (counters[0] == 0) return;
   // LDS: C12 (2 n x n), Zeval and the new k (n x p each), then the squared
@@ -873,10 +876,14 @@ __global__ void __launch_bounds__(DTPB) dense_fp_update_kernel(
     if (!fixed) {
       const double rel = (kn > 0.0) ? sqrt(dn) / sqrt(kn) : sqrt(dn);
       const bool conv = rel < tol;
-      const bool stall = !conv && rel >= prev[i];
+      const bool stall = !conv && rel >= prev[i] && rel < stall_tol;
       prev[i] = rel;
       done = conv || stall;
-      if (stall) atomicAdd(&nstall, 1);
+      if (stall) {
+        atomicAdd(&nstall, 1);
+        atomicMax(reinterpret_cast<unsigned long long*>(counters + 6),
+                  (unsigned long long)__double_as_longlong(rel));
+      }
     }
     if (done) {
       active[i] = 0;
@@ -905,8 +912,10 @@ __global__ void fp_init_kernel(double* prev, int* active, int* counters, int p) 
     active[t] = 1;
   }
   // [0] columns still active (all, before the first iteration), [1] stalled
-  // columns, [2] iterations that updated at least one column
+  // columns, [2] iterations that updated at least one column, [6..7] the
+  // largest update accepted by a stall (a double)
   if (t < 4) counters[t] = (t == 0) ? p : 0;
+  if (t == 6 || t == 7) counters[t] = 0;
 }
 
 // End of a step with the DEIM chain: the error word of the chain in flight
@@ -1072,12 +1081,12 @@ void launch_cholqr_apply(hipStream_t s, const cplx* Gram, int n, cplx* U, int N,
 }
 void launch_dense_fp_update(hipStream_t s, const cplx* gF, const cplx* C12, int n, int p,
                             const cplx* Z0, cplx* Zeval, cplx* ZG, cplx* k, double* prev,
-                            int* active, double dt, double tol, int fixed, int linear_part,
-                            int* counters) {
+                            int* active, double dt, double tol, double stall_tol, int fixed,
+                            int linear_part, int* counters) {
   const size_t sh = (size_t)(2 * n * n + 2 * n * p) * sizeof(cplx) + 2 * (size_t)n * p * sizeof(double);
   ALLOW_BIG_LDS(dense_fp_update_kernel);
   hipLaunchKernelGGL(dense_fp_update_kernel, dim3(1), dim3(DTPB), sh, s, gF, C12, n, p, Z0, Zeval,
-                     ZG, k, prev, active, dt, tol, fixed, linear_part, counters);
+                     ZG, k, prev, active, dt, tol, stall_tol, fixed, linear_part, counters);
 }
 void launch_dense_finish_z(hipStream_t s, const cplx* Z0, const cplx* k, int n, int p, double dt,
                            cplx* Z1) {
@@ -1281,7 +1290,7 @@ void launch_dense_shrink(hipStream_t s, const cplx* Z, int n, int p, cplx* V, cp
 }
 
 // ---------------------------------------------------------------------------
-// DEIM (Sec. 4.3): basis coefficients, greedy selection and weights
+// DEIM (Sec. 4.2.2): basis coefficients, greedy selection and weights
 // ---------------------------------------------------------------------------
 
 // ---------------------------------------------------------------------------
@@ -1534,6 +1543,150 @@ __global__ void __launch_bounds__(DTPB) dense_indicator_kernel(const double* __r
 void launch_dense_indicator(hipStream_t s, const double* colsq, const cplx* g, int n, int p,
                             double* eps) {
   hipLaunchKernelGGL(dense_indicator_kernel, dim3(1), dim3(DTPB), 0, s, colsq, g, n, p, eps);
+}
+
+// ---------------------------------------------------------------------------
+// Automatic shrink (rank adaptation): the pairs whose singular value of Z~
+// falls below rank_tol_down times the largest are dropped.
+//
+// Certificate: S~ = Z~ Z~^* (n x n); if S~ - c trace(S~) I admits a Cholesky
+// factor then lambda_min(S~) > c trace(S~) >= c lambda_max (up to the
+// factorisation's backward error, about n eps trace, far below c >= 1e-13),
+// so sigma_min / sigma_max > sqrt(c) and, with c >= tol^2, nothing is
+// dropped.  *word = 0 when certified, 1 otherwise (the singular values are
+// then computed accurately by dense_zsvals_kernel).  Requires n <= 32.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(DTPB) dense_rank_cert_kernel(const cplx* __restrict__ Z, int n,
+                                                               int p, double c,
+                                                               int* __restrict__ word) {
+  __shared__ cplx S[32 * 32];
+  __shared__ cplx R[32 * 32];
+  __shared__ double trs;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int a = t % n, b = t / n;
+    cplx acc = mk(0.0, 0.0);
+    for (int i = 0; i < p; ++i) cfma(acc, Z[(size_t)i * n + a], cconj(Z[(size_t)i * n + b]));
+    S[t] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tr = 0.0;
+    for (int a = 0; a < n; ++a) tr += S[a * n + a].re;
+    trs = tr;
+  }
+  __syncthreads();
+  const int bad = (trs > 0.0) ? bk_chol(S, R, n, c * trs) : 1;
+  if (threadIdx.x == 0) *word = bad ? 1 : 0;
+}
+
+// Singular values of Z~ (n x p) by one-sided Jacobi on its rows (high
+// relative accuracy; no Gram is formed): pairs of rows are rotated until
+// every pair is orthogonal to 1e-15 of the product of their norms; the
+// singular values are then the row norms.  The rows are copied to `work`
+// (n x p, row-major) first.  Pairs of a round are disjoint (round-robin
+// order); each of up to 16 pairs is taken by a group of 16 lanes.
+// sig (n, decreasing).  Requires n <= 32.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(DTPB) dense_zsvals_kernel(const cplx* __restrict__ Z, int n,
+                                                            int p, cplx* __restrict__ work,
+                                                            double* __restrict__ sig) {
+  __shared__ int nrot;
+  __shared__ double nv[32];
+  for (int t = threadIdx.x; t < n * p; t += blockDim.x) {
+    const int a = t % n, i = t / n;
+    work[(size_t)a * p + i] = Z[t];
+  }
+  __syncthreads();
+  const int mm = n + (n & 1);
+  const int half = mm / 2;
+  const int grp = threadIdx.x >> 4, gl = threadIdx.x & 15;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (threadIdx.x == 0) nrot = 0;
+    __syncthreads();
+    for (int round = 0; round < mm - 1; ++round) {
+      if (grp < half) {
+        int a, b;
+        if (grp == 0) {
+          a = mm - 1;
+          b = round;
+        } else {
+          a = (round + grp) % (mm - 1);
+          b = (round - grp + (mm - 1)) % (mm - 1);
+        }
+        const int r0 = a < b ? a : b, r1 = a < b ? b : a;
+        if (r1 < n) {
+          cplx* x = work + (size_t)r0 * p;
+          cplx* y = work + (size_t)r1 * p;
+          double al = 0.0, be = 0.0;
+          cplx ga = mk(0.0, 0.0);  // sum x conj(y)
+          for (int i = gl; i < p; i += 16) {
+            al += cabs2(x[i]);
+            be += cabs2(y[i]);
+            cfmac(ga, y[i], x[i]);
+          }
+          for (int o = 8; o > 0; o >>= 1) {
+            al += __shfl_xor(al, o, 16);
+            be += __shfl_xor(be, o, 16);
+            ga.re += __shfl_xor(ga.re, o, 16);
+            ga.im += __shfl_xor(ga.im, o, 16);
+          }
+          const double gab = sqrt(cabs2(ga));
+          if (gab > 1e-300 && gab > 1e-15 * sqrt(al * be)) {
+            if (gl == 0) atomicAdd(&nrot, 1);
+            const double zeta = (be - al) / (2.0 * gab);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+            const cplx e = mk(ga.re / gab, ga.im / gab);  // gamma / |gamma|
+            for (int i = gl; i < p; i += 16) {
+              const cplx xv = x[i], ye = cmul(y[i], e);
+              x[i] = csub(cscale(xv, cs), cscale(ye, sn));
+              y[i] = cadd(cscale(xv, sn), cscale(ye, cs));
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (nrot == 0) break;
+    __syncthreads();
+  }
+  for (int a = threadIdx.x >> 6; a < n; a += blockDim.x >> 6) {
+    double acc = 0.0;
+    for (int i = threadIdx.x & 63; i < p; i += 64) acc += cabs2(work[(size_t)a * p + i]);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) nv[a] = sqrt(acc);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int a = 0; a < n; ++a) {
+      int b = a;
+      for (int c = a + 1; c < n; ++c)
+        if (nv[c] > nv[b]) b = c;
+      const double t = nv[a];
+      nv[a] = nv[b];
+      nv[b] = t;
+      sig[a] = nv[a];
+    }
+  }
+}
+
+// Row-combination matrices that project the k columns Y out of the basis:
+// Y - U~ C with C = U~^* Y (n x k):  Ik = I (k x k), Cn = -C.
+__global__ void proj_mats_kernel(const cplx* __restrict__ C, int n, int k, cplx* __restrict__ Ik,
+                                 cplx* __restrict__ Cn) {
+  for (int t = threadIdx.x; t < k * k; t += blockDim.x)
+    Ik[t] = (t % k == t / k) ? mk(1.0, 0.0) : mk(0.0, 0.0);
+  for (int t = threadIdx.x; t < n * k; t += blockDim.x) Cn[t] = cscale(C[t], -1.0);
+}
+
+void launch_dense_rank_cert(hipStream_t s, const cplx* Z, int n, int p, double c, int* word) {
+  hipLaunchKernelGGL(dense_rank_cert_kernel, dim3(1), dim3(DTPB), 0, s, Z, n, p, c, word);
+}
+void launch_dense_zsvals(hipStream_t s, const cplx* Z, int n, int p, cplx* work, double* sig) {
+  hipLaunchKernelGGL(dense_zsvals_kernel, dim3(1), dim3(DTPB), 0, s, Z, n, p, work, sig);
+}
+void launch_proj_mats(hipStream_t s, const cplx* C, int n, int k, cplx* Ik, cplx* Cn) {
+  hipLaunchKernelGGL(proj_mats_kernel, dim3(1), dim3(256), 0, s, C, n, k, Ik, Cn);
 }
 
 // ---------------------------------------------------------------------------

@@ -64,7 +64,7 @@ void launch_deposit_x(hipStream_t s, const double* X, int N, int p, int Nx, cons
 void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                         const PicGeom& g, const double* factor, const int* active, double* part,
                         const int* gate = nullptr,
-                        int* fold = nullptr);
+                        int* fold = nullptr, int det = 0);
 void launch_poisson(hipStream_t s, const double* part, int nrb, int p, int Nx, const double* qw,
                     const double* h, const double* mw, const int* active, double* rho,
                     double* phi, double* e, double* energy, const int* gate = nullptr);
@@ -78,7 +78,7 @@ void launch_poisson_deim(hipStream_t s, const double* part, int nrb, int p, int 
                          const cplx* U, int N, int n, cplx* Z, const double* factor, double qm,
                          const int* idx, const double* w, int d, cplx* gF, const cplx* C12,
                          const cplx* Z0, cplx* ZG, cplx* k, double* prev, double dt, double tol,
-                         int fixed, int iter, int* counters);
+                         double stall_tol, int fixed, int iter, int* counters);
 void launch_fom_push(hipStream_t s, double* X, double* V, int N, int p, int Nx, const PicGeom& g,
                      const double* factor, const double* e, double qm, double ck, double cd,
                      double* part);
@@ -96,7 +96,12 @@ void launch_gather_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z
                        const PicGeom& g, const double* factor, const double* e, double qm,
                        const int* active, bool full, void* out);
 void launch_reconstruct(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p,
-                        double* X, double* V);
+                        double* X, double* V, const int* rows = nullptr, int nrows = 0);
+// cells j and scaled positions s = x N_x / L of every (particle, parameter)
+// with the position arithmetic of the reduced deposit (cells: N x p int32;
+// s: N x p, nullable)
+void launch_rom_cells(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
+                      const double* factor, int* cells, double* sv);
 void launch_gemm_ah_b(hipStream_t s, const MatList& A, int a, const MatList& B, int b, bool b_real,
                       int N, int nkb, cplx* part, cplx* C);
 // C = op(A) B with flags (GEMM_*): real A / B inputs, A^T instead of A^*
@@ -180,8 +185,8 @@ void launch_cholqr_apply(hipStream_t s, const cplx* Gram, int n, cplx* U, int N,
                          int* flags);
 void launch_dense_fp_update(hipStream_t s, const cplx* gF, const cplx* C12, int n, int p,
                             const cplx* Z0, cplx* Zeval, cplx* ZG, cplx* k, double* prev,
-                            int* active, double dt, double tol, int fixed, int linear_part,
-                            int* counters);
+                            int* active, double dt, double tol, double stall_tol, int fixed,
+                            int linear_part, int* counters);
 void launch_dense_finish_z(hipStream_t s, const cplx* Z0, const cplx* k, int n, int p, double dt,
                            cplx* Z1);
 void launch_fp_init(hipStream_t s, double* prev, int* active, int* counters, int p);
@@ -205,6 +210,13 @@ void launch_dense_shrink(hipStream_t s, const cplx* Z, int n, int p, cplx* V, cp
 void launch_dense_symeig(hipStream_t s, const cplx* G, int n, double* V, double* lam, int* flags);
 void launch_dense_indicator(hipStream_t s, const double* colsq, const cplx* g, int n, int p,
                             double* eps);
+// automatic shrink: *word = 0 when sigma_min(Z~) / sigma_max(Z~) > sqrt(c)
+// is certified by a shifted Cholesky factor of Z~ Z~^*, else 1
+void launch_dense_rank_cert(hipStream_t s, const cplx* Z, int n, int p, double c, int* word);
+// singular values of Z~ (n x p) by one-sided Jacobi (work: n x p complex)
+void launch_dense_zsvals(hipStream_t s, const cplx* Z, int n, int p, cplx* work, double* sig);
+// Ik = I (k x k) and Cn = -C (n x k)
+void launch_proj_mats(hipStream_t s, const cplx* C, int n, int k, cplx* Ik, cplx* Cn);
 // Mc (optional, n x d): the DEIM basis coefficients V[:, c] / sqrt(lam_c)
 void launch_dense_topeig(hipStream_t s, const double* G, int n, int d, double* V, double* lam,
                          int* flags, const int* stop = nullptr, double* Mc = nullptr);

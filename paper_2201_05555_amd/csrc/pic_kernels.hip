@@ -73,7 +73,7 @@ template <int NC>
 __global__ void __launch_bounds__(deposit_rom_threads<NC>()) deposit_rom_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx, int pt,
     int rpb, const double* __restrict__ factor, const int* __restrict__ active,
-    double* __restrict__ part, const int* __restrict__ gate, int* __restrict__ fold) {
+    double* __restrict__ part, const int* __restrict__ gate, int* __restrict__ fold, int det) {
   if (gate && gate[0] == 0) return;
   if (fold && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
     // end-of-step bookkeeping of the status words (the step's kernels are
@@ -143,12 +143,26 @@ __global__ void __launch_bounds__(deposit_rom_threads<NC>()) deposit_rom_kernel(
         if (ok[r]) {
           __hip_atomic_fetch_add(cnt + i * Nx + j, 1u, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_WORKGROUP);
-          lds_add(hist + i * Nx + j, th);
+          if (det)
+            __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(hist) + i * Nx + j,
+                                   __double2ull_rn(th * 0x1p40), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+          else
+            lds_add(hist + i * Nx + j, th);
         }
       }
     }
   }
   __syncthreads();
+  if (det) {
+    // each integer sum becomes a double in place (one rounding each)
+    const unsigned long long* ih = reinterpret_cast<const unsigned long long*>(hist);
+    for (int t = threadIdx.x; t < np * Nx; t += blockDim.x) {
+      const double v = __ull2double_rn(ih[t]) * 0x1p-40;
+      hist[t] = v;
+    }
+    __syncthreads();
+  }
   for (int t = threadIdx.x; t < np * Nx; t += blockDim.x) {
     const int i = t / Nx, j = t - i * Nx;
     if (active && !active[p0 + i]) continue;
@@ -211,7 +225,7 @@ struct DeimGatherArgs {
   cplx* k;
   double* prev;
   int* active;
-  double dt, tol;
+  double dt, tol, stall_tol;
   int fixed, iter;
   int* counters;
 };
@@ -427,10 +441,14 @@ __global__ void __launch_bounds__(POISSON_THREADS) poisson_kernel(
     if (!dg.fixed) {
       const double rel = (kn > 0.0) ? sqrt(dn) / sqrt(kn) : sqrt(dn);
       const bool conv = rel < dg.tol;
-      const bool stall = !conv && rel >= prev_i;
+      const bool stall = !conv && rel >= prev_i && rel < dg.stall_tol;
       dg.prev[i] = rel;
       done = conv || stall;
-      if (stall) atomicAdd(&dg.counters[1], 1);
+      if (stall) {
+        atomicAdd(&dg.counters[1], 1);
+        atomicMax(reinterpret_cast<unsigned long long*>(dg.counters + 6),
+                  (unsigned long long)__double_as_longlong(rel));
+      }
     }
     if (done) {
       dg.active[i] = 0;
@@ -541,6 +559,72 @@ __global__ void cells_kernel(const double* __restrict__ X, int N, int p, int Nx,
   cells[t] = j;
 }
 
+// Cell index and scaled position s = x N_x / L of every (particle,
+// parameter) of the reduced model, with the position arithmetic of
+// deposit_rom_kernel operation by operation (masked register row of U~,
+// even and odd columns summed apart, then added): the cells the fused
+// kernels use, for checking them against an independent reconstruction.
+template <int NC>
+__global__ void __launch_bounds__(256) rom_cells_kernel(const cplx* __restrict__ U, int N, int n,
+                                                        const cplx* __restrict__ Z, int p, int Nx,
+                                                        const double* __restrict__ factor,
+                                                        int* __restrict__ cells,
+                                                        double* __restrict__ sv) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= N) return;
+  cplx u[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const cplx v = U[(size_t)min(k, n - 1) * N + l];
+    const double m = (k < n) ? 1.0 : 0.0;
+    u[k] = mk(v.re * m, v.im * m);
+  }
+  for (int i = 0; i < p; ++i) {
+    cplx z[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const cplx a = Z[(size_t)i * n + min(k, n - 1)];
+      z[k] = (k < n) ? a : mk(0.0, 0.0);
+    }
+    double x0 = 0.0, x1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NC; k += 2) {
+      x0 = fma(u[k].re, z[k].re, x0);
+      x0 = fma(-u[k].im, z[k].im, x0);
+      if (k + 1 < NC) {
+        x1 = fma(u[k + 1].re, z[k + 1].re, x1);
+        x1 = fma(-u[k + 1].im, z[k + 1].im, x1);
+      }
+    }
+    const double x = x0 + x1;
+    int j;
+    double th;
+    cell_of(x, factor[i], Nx, j, th);
+    cells[(size_t)i * N + l] = j;
+    if (sv) sv[(size_t)i * N + l] = x * factor[i];
+  }
+}
+
+void launch_rom_cells(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
+                      const double* factor, int* cells, double* sv) {
+  const int nc = (n <= 16) ? nc_even(n) : 32;
+  dim3 grid((N + 255) / 256);
+#define RCL(NCV)                                                                              \
+  hipLaunchKernelGGL(rom_cells_kernel<NCV>, grid, dim3(256), 0, s, U, N, n, Z, p, Nx, factor, \
+                     cells, sv)
+  switch (nc) {
+    case 4: RCL(4); break;
+    case 5: RCL(5); break;
+    case 6: RCL(6); break;
+    case 7: RCL(7); break;
+    case 8: RCL(8); break;
+    case 12: RCL(12); break;
+    case 16: RCL(16); break;
+    default: RCL(32); break;
+  }
+#undef RCL
+}
+
 // Per-parameter sum of squares of the columns of an N x p matrix, times s:
 // grid (p, chunks) partial sums, combined in order by the second kernel.
 #define CSQ_CHUNKS 32
@@ -585,14 +669,14 @@ void launch_deposit_x(hipStream_t s, const double* X, int N, int p, int Nx, cons
 
 void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                         const PicGeom& g, const double* factor, const int* active, double* part,
-                        const int* gate, int* fold) {
+                        const int* gate, int* fold, int det) {
   dim3 grid(g.nrb, (p + g.pt - 1) / g.pt);
   int nc = (n <= 16) ? nc_even(n) : 32;
   size_t sh = (size_t)g.pt * Nx * (sizeof(double) + sizeof(unsigned));
 #define DEP(NCV)                                                                              \
   ALLOW_BIG_LDS(deposit_rom_kernel<NCV>);                                                    \
   hipLaunchKernelGGL(deposit_rom_kernel<NCV>, grid, dim3(deposit_rom_threads<NCV>()), sh, s, U, \
-                     N, n, Z, p, Nx, g.pt, g.rpb, factor, active, part, gate, fold)
+                     N, n, Z, p, Nx, g.pt, g.rpb, factor, active, part, gate, fold, det)
   switch (nc) {
     case 4: DEP(4); break;
     case 5: DEP(5); break;
@@ -621,9 +705,9 @@ void launch_poisson_deim(hipStream_t s, const double* part, int nrb, int p, int 
                          const cplx* U, int N, int n, cplx* Z, const double* factor, double qm,
                          const int* idx, const double* w, int d, cplx* gF, const cplx* C12,
                          const cplx* Z0, cplx* ZG, cplx* k, double* prev, double dt, double tol,
-                         int fixed, int iter, int* counters) {
-  DeimGatherArgs dg{U,   N,  n, Z,    factor, qm,  idx, w,     d,    gF,
-                    C12, Z0, Z, ZG,   k,      prev, active, dt, tol, fixed, iter, counters};
+                         double stall_tol, int fixed, int iter, int* counters) {
+  DeimGatherArgs dg{U,   N,  n,    Z,      factor, qm,  idx,       w,     d,    gF,      C12,
+                    Z0,  Z,  ZG,   k,      prev,   active, dt, tol, stall_tol, fixed, iter, counters};
   hipLaunchKernelGGL(poisson_kernel, dim3(p), dim3(POISSON_THREADS), 0, s, part, nrb, p, Nx, qw, h,
                      mw, active, rho, phi, e, energy, gate, dg);
 }

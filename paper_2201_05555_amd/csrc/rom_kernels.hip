@@ -66,24 +66,31 @@ __global__ void __launch_bounds__(512) gather_rom_kernel(
   }
 }
 
-// Reconstruct X = Re(U~ Z~), V = Im(U~ Z~) (N x p each).
+// Reconstruct X = Re(U~ Z~), V = Im(U~ Z~) (nout x p each): every row
+// (rows == nullptr, nout = N) or the rows listed in rows[0 .. nout) (a row
+// index outside [0, N) gives NaN in its output row).
 template <int NC>
 __global__ void __launch_bounds__(256) reconstruct_kernel(const cplx* __restrict__ U, int N, int n,
                                                           const cplx* __restrict__ Z, int p,
                                                           double* __restrict__ X,
-                                                          double* __restrict__ V) {
+                                                          double* __restrict__ V,
+                                                          const int* __restrict__ rows, int nout) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= N) return;
+  if (l >= nout) return;
+  const int src = rows ? rows[l] : l;
+  const bool in = src >= 0 && src < N;
+  const int sc = in ? src : 0;
   cplx u[NC];
 #pragma unroll
-  for (int k = 0; k < NC; ++k) u[k] = (k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
+  for (int k = 0; k < NC; ++k) u[k] = (k < n) ? U[(size_t)k * N + sc] : mk(0.0, 0.0);
   for (int i = 0; i < p; ++i) {
     cplx acc = mk(0.0, 0.0);
 #pragma unroll
     for (int k = 0; k < NC; ++k)
       if (k < n) cfma(acc, u[k], Z[(size_t)i * n + k]);
-    if (X) X[(size_t)i * N + l] = acc.re;
-    if (V) V[(size_t)i * N + l] = acc.im;
+    if (!in) acc = mk(NAN, NAN);
+    if (X) X[(size_t)i * nout + l] = acc.re;
+    if (V) V[(size_t)i * nout + l] = acc.im;
   }
 }
 
@@ -434,6 +441,7 @@ __global__ void __launch_bounds__(64) deim_gather_kernel(
       st.active[i] = 1;
     }
     if (i == 0 && threadIdx.x < 4) st.counters[threadIdx.x] = (threadIdx.x == 0) ? p : 0;
+    if (i == 0 && (threadIdx.x == 6 || threadIdx.x == 7)) st.counters[threadIdx.x] = 0;
   }
 }
 
@@ -760,7 +768,7 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// DEIM basis, indices and weights (Sec. 4.3), N-wide passes.
+// DEIM basis, indices and weights (Sec. 4.2.2), N-wide passes.
 // ---------------------------------------------------------------------------
 
 // (value, index) pairs: the larger value wins, the smaller index on ties
@@ -802,7 +810,7 @@ __device__ int dg_winner(const double* __restrict__ val, const int* __restrict__
   return bi;
 }
 
-// Greedy DEIM step k (the selection rule of Sec. 4.3): l_k = argmax |r_k|,
+// Greedy DEIM step k (the selection rule of Sec. 4.2.2): l_k = argmax |r_k|,
 // r_k = psi_k - Psi_{k-1} c_k, M_k c_k = P^T psi_k with M_k = P^T Psi_{k-1}
 // (k x k; rows l_0 .. l_{k-1}).  Instead of a fresh solve per step, the
 // inverse of M_k is carried from pass to pass by bordering: with
@@ -1209,7 +1217,7 @@ __global__ void __launch_bounds__(256) gram_mfma_kernel(RealList A, int ka, int 
   }
 }
 
-// DEIM snapshot Lambda^0(X_r^i) Phi^i at every particle (Sec. 4.3, eq. Ydeim)
+// DEIM snapshot Lambda^0(X_r^i) Phi^i at every particle (Sec. 4.2.2, eq. Ydeim)
 // for the parameters sub[0..psub): (1 - theta) Phi_j + theta Phi_{j+1}, written
 // as column c of Y (N x psub).  The subset's coefficients (zero-padded to NC),
 // factors and, when they fit (PH_LDS), potentials sit in LDS; positions use the
@@ -1397,15 +1405,20 @@ void launch_gather_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z
 }
 
 void launch_reconstruct(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p,
-                        double* X, double* V) {
+                        double* X, double* V, const int* rows, int nrows) {
+  const int nout = rows ? nrows : N;
+  if (nout <= 0) return;
   int nc = nc_bucket(n);
-  dim3 grid((N + 255) / 256);
+  dim3 grid((nout + 255) / 256);
+#define RC(NCV) \
+  hipLaunchKernelGGL(reconstruct_kernel<NCV>, grid, dim3(256), 0, s, U, N, n, Z, p, X, V, rows, nout)
   switch (nc) {
-    case 4: hipLaunchKernelGGL(reconstruct_kernel<4>, grid, dim3(256), 0, s, U, N, n, Z, p, X, V); break;
-    case 8: hipLaunchKernelGGL(reconstruct_kernel<8>, grid, dim3(256), 0, s, U, N, n, Z, p, X, V); break;
-    case 16: hipLaunchKernelGGL(reconstruct_kernel<16>, grid, dim3(256), 0, s, U, N, n, Z, p, X, V); break;
-    default: hipLaunchKernelGGL(reconstruct_kernel<32>, grid, dim3(256), 0, s, U, N, n, Z, p, X, V); break;
+    case 4: RC(4); break;
+    case 8: RC(8); break;
+    case 16: RC(16); break;
+    default: RC(32); break;
   }
+#undef RC
 }
 
 void launch_gemm_flags(hipStream_t s, const MatList& A, int a, const MatList& B, int b, int flags,

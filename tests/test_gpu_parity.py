@@ -200,6 +200,14 @@ def _bound(sens):
     return max(RTOL, 50.0 * sens)
 
 
+def _within(err, sens, what, floor=RTOL):
+    """Assert err < max(floor, 50 sens) and print the margin."""
+    bound = max(floor, _bound(sens))
+    print(f"  {what}: err {err:.2e}  oracle sensitivity {sens:.2e}  bound {bound:.2e}",
+          flush=True)
+    assert err < bound, (what, err, sens, bound)
+
+
 @pytest.mark.parametrize("name,kw,two_n,iters", [
     ("landau_tiny", dict(N=3001), 10, 6),
     ("twostream_deim", dict(N=20000, p=24, Nx=128), 12, 5),
@@ -226,10 +234,10 @@ def test_rom_step_parity_fixed_iterations(name, kw, two_n, iters):
     N = w["N"]
     assert step == 1
     Xo, Vo = rom.reconstruct(st)
-    assert _rel(_np(UX).T, st.U[:N]) < _bound(sU), (sU,)
-    assert _rel(_np(Z).T, st.Z) < _bound(sZ), (sZ,)
-    assert _rel(_np(X).T, Xo) < _bound(sR), (sR,)
-    assert _rel(_np(V).T, Vo) < _bound(sR), (sR,)
+    _within(_rel(_np(UX).T, st.U[:N]), sU, "U_X")
+    _within(_rel(_np(Z).T, st.Z), sZ, "Z")
+    _within(_rel(_np(X).T, Xo), sR, "X_r")
+    _within(_rel(_np(V).T, Vo), sR, "V_r")
 
 
 def test_rom_step_parity_well_conditioned_strict():
@@ -272,8 +280,8 @@ def test_rom_steps_parity_adaptive(name, kw, two_n, steps):
         assert info["iters"] == st.last_iters, (s, info, st.last_iters)
     X, V = r.reconstruct()
     Xo, Vo = rom.reconstruct(st)
-    assert _rel(_np(X).T, Xo) < _bound(sR), sR
-    assert _rel(_np(V).T, Vo) < _bound(sR), sR
+    _within(_rel(_np(X).T, Xo), sR, "X_r")
+    _within(_rel(_np(V).T, Vo), sR, "V_r")
     E, H = r.diagnostics()
     Eo, Ho = rom.diagnostics(st, cfg)
     assert _rel(_np(E), Eo) < max(1e-8, _bound(sR) * 1e3)
@@ -299,8 +307,8 @@ def test_rom_full_size_workload_parity():
         assert info["iters"] == st.last_iters, (s, info, st.last_iters)
     X, V = r.reconstruct()
     Xo, Vo = rom.reconstruct(st)
-    assert _rel(_np(X).T, Xo) < _bound(sR), sR
-    assert _rel(_np(V).T, Vo) < _bound(sR), sR
+    _within(_rel(_np(X).T, Xo), sR, "X_r")
+    _within(_rel(_np(V).T, Vo), sR, "V_r")
 
 
 def test_rom_enoconv_keeps_state():
@@ -345,9 +353,12 @@ def test_rom_rank_grow_parity():
     tol = max(1e-9, 1e-14 * (sv[0] / sv[1]) ** 2)
     assert _rel(UXn, st.U[:N]) < tol, (tol, sv[:2])
     assert _rel(_np(Z).T, st.Z) < 1e-12
-    # still orthonormal to the accuracy of the Gram route
+    # orthonormal to rounding: the new pairs are projected out of the basis
+    # and orthonormalised by Cholesky QR twice
     Utg = UXn[:, :6] - 1j * UXn[:, 6:]
-    assert np.abs(Utg.conj().T @ Utg - np.eye(6)).max() < 1e-9
+    orth = np.abs(Utg.conj().T @ Utg - np.eye(6)).max()
+    print(f"  orthonormality after growth {orth:.2e}", flush=True)
+    assert orth < 1e-12
 
 
 def test_rom_rank_shrink_parity():
@@ -424,9 +435,8 @@ def test_rom_deim_rank_auto_parity():
         assert abs(info["rank_indicator"] - eps) < 1e-6 * max(eps, 1e-3), (s, info, eps)
     X, V = r.reconstruct()
     Xo, Vo = rom.reconstruct(st)
-    bound = max(1e-9, _bound(sR))
-    assert _rel(_np(X).T, Xo) < bound, (sR,)
-    assert _rel(_np(V).T, Vo) < bound, (sR,)
+    _within(_rel(_np(X).T, Xo), sR, "X_r")
+    _within(_rel(_np(V).T, Vo), sR, "V_r")
 
 
 @pytest.mark.parametrize("kw,two_n,two_n_max,steps", [
@@ -460,6 +470,9 @@ def test_rom_deim_steps_parity(kw, two_n, two_n_max, steps):
         assert info["iters"] == st.last_iters, (s, info, st.last_iters)
     X, V = r.reconstruct()
     Xo, Vo = rom.reconstruct(st)
-    bound = max(1e-9, _bound(sR))
-    assert _rel(_np(X).T, Xo) < bound, (sR,)
-    assert _rel(_np(V).T, Vo) < bound, (sR,)
+    # floor 1e-9: the library takes the DEIM basis from the eigenpairs of the
+    # snapshot Gram Y^T Y (accurate to eps sigma_1^2 / gap^2 for trailing
+    # vectors), the oracle from an SVD of Y; the perturbation of Z above does
+    # not see that difference
+    _within(_rel(_np(X).T, Xo), sR, "X_r", floor=1e-9)
+    _within(_rel(_np(V).T, Vo), sR, "V_r", floor=1e-9)
