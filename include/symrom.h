@@ -263,6 +263,22 @@ symrom_status pic_fields(int32_t N, int32_t p, int32_t Nx, const double* L, doub
                          const double* X, int32_t* cells, double* rho, double* Phi, double* e,
                          void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): pic_fields without a workspace
+ * and without any allocation.  L is a DEVICE array [p] here (no host memory
+ * is touched); X, cells, rho, Phi, e as in pic_fields.  The deposit
+ * partials, the per-parameter constants and the energies live in a
+ * file-scope device array of SYMROM_NOALLOC_SCRATCH_BYTES per GPU, held
+ * until the process ends; every word a call reads is written by that call
+ * first.  Calls that overlap on one GPU share that array and race: issue
+ * them one after another.  Errors: EINVAL for bad sizes and when p * Nx is
+ * too large for the array (about 5e5 grid values); use pic_fields then.
+ * Synchronises the stream. */
+#define SYMROM_NOALLOC_SCRATCH_BYTES (8u << 20)
+symrom_status pic_fields_noalloc(int32_t N, int32_t p, int32_t Nx, const double* L, double q,
+                                 const double* X, int32_t* cells, double* rho, double* Phi,
+                                 double* e, void* stream);
+
 /* ------------------------------------------------------------------------ */
 const char* symrom_status_string(symrom_status s);
 const char* symrom_last_error(void);

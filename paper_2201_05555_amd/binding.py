@@ -88,6 +88,8 @@ _SIGS = {
     "pic_fields": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
                                     ctypes.c_double, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t,
                                     _VP]),
+    "pic_fields_noalloc": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
+                                            ctypes.c_double, _VP, _VP, _VP, _VP, _VP, _VP]),
     "symrom_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "symrom_last_error": (ctypes.c_char_p, []),
     "symrom_set_timing": (None, [ctypes.c_int32]),
@@ -378,3 +380,18 @@ def deim_select(Psi, stream=None):
     _check(lib().deim_select(N, d, _ptr(P), _ptr(idx), _ptr(w), _ptr(ws), nbytes,
                              _stream(stream)))
     return idx, w
+
+
+def pic_fields_noalloc(X, L, Nx, q=-1.0, stream=None):
+    """pic_fields through the allocation-free entry point (L on the device):
+    cells (p, N) int32 and rho, Phi, e (p, Nx)."""
+    X = _dev(X)
+    p, N = X.shape
+    Ld = torch.as_tensor(np.asarray(L, dtype=np.float64)).cuda()
+    cells = torch.empty((p, N), dtype=torch.int32, device="cuda")
+    rho = torch.empty((p, Nx), dtype=torch.float64, device="cuda")
+    Phi = torch.empty_like(rho)
+    e = torch.empty_like(rho)
+    _check(lib().pic_fields_noalloc(N, p, Nx, _ptr(Ld), q, _ptr(X), _ptr(cells), _ptr(rho),
+                                    _ptr(Phi), _ptr(e), _stream(stream)))
+    return cells, rho, Phi, e

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -269,6 +270,97 @@ extern "C" symrom_status pic_fields(int32_t N, int32_t p, int32_t Nx, const doub
     launch_poisson(s, b.part, g.nrb, p, Nx, b.qw, b.h, b.mw, nullptr, rho ? rho : b.rho,
                    Phi ? Phi : b.phi, e ? e : b.e, b.energy);
   }
+  if (cells) launch_cells(s, X, N, p, Nx, b.factor, cells);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  return SYMROM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stateless particle-to-grid without allocation: the deposit partials, the
+// per-parameter constants and the energies live in `scratch`, a file-scope
+// device array of SYMROM_NOALLOC_SCRATCH_BYTES that each GPU holds until the
+// process ends.  Its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and only that address is
+// passed to kernels.  Calls that overlap on one GPU share the array and race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[SYMROM_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// device address of this device's scratch array (nullptr on failure)
+symrom_status scratch_address(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SYMROM_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(SYMROM_EDEVICE, "scratch array has no device address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SYMROM_OK;
+}
+
+// per-parameter constants from the device array L (as per_param_consts)
+__global__ void pic_consts_kernel(const double* __restrict__ L, int N, int p, int Nx, double q,
+                                  double* __restrict__ factor, double* __restrict__ qw,
+                                  double* __restrict__ h, double* __restrict__ mw) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p) return;
+  const double Li = L[i];
+  factor[i] = (double)Nx / Li;
+  const double w = Li / (double)N;
+  qw[i] = q * w;
+  h[i] = Li / (double)Nx;
+  mw[i] = w;
+}
+
+// the row-block geometry of pic_fields, with fewer row blocks when the
+// partials would not fit the scratch array; false when even one does not
+bool noalloc_geom(int N, int p, int Nx, PicGeom& g) {
+  g = pic_geom(N, p, Nx, kDepTableBudget, 512);
+  const int ntiles = (p + g.pt - 1) / g.pt;
+  (void)ntiles;
+  for (;;) {
+    Arena ar(nullptr);
+    carve_pic(ar, N, p, Nx, g);
+    if (ar.off + 256 <= SYMROM_NOALLOC_SCRATCH_BYTES) return true;
+    if (g.nrb == 1) return false;
+    const int nrb = std::max(1, g.nrb / 2);
+    g.rpb = (N + nrb - 1) / nrb;
+    g.nrb = (N + g.rpb - 1) / g.rpb;
+  }
+}
+}  // namespace
+
+extern "C" symrom_status pic_fields_noalloc(int32_t N, int32_t p, int32_t Nx, const double* L,
+                                            double q, const double* X, int32_t* cells,
+                                            double* rho, double* Phi, double* e, void* stream) {
+  if (!valid_sizes(N, p, Nx) || !L || !X)
+    return fail(SYMROM_EINVAL, "pic_fields_noalloc: bad arguments");
+  PicGeom g;
+  if (!noalloc_geom(N, p, Nx, g))
+    return fail(SYMROM_EINVAL, "pic_fields_noalloc: p * Nx too large for the " +
+                                   std::to_string(SYMROM_NOALLOC_SCRATCH_BYTES >> 20) +
+                                   " MiB scratch array (use pic_fields with a workspace)");
+  void* base = nullptr;
+  symrom_status st = scratch_address(&base);
+  if (st != SYMROM_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Arena ar(base);
+  PicBufs b = carve_pic(ar, N, p, Nx, g);
+  // every scratch word read below is written first by this call
+  hipLaunchKernelGGL(pic_consts_kernel, dim3((p + 255) / 256), dim3(256), 0, s, L, N, p, Nx, q,
+                     b.factor, b.qw, b.h, b.mw);
+  launch_deposit_x(s, X, N, p, Nx, g, b.factor, b.part);
+  launch_poisson(s, b.part, g.nrb, p, Nx, b.qw, b.h, b.mw, nullptr, rho ? rho : b.rho,
+                 Phi ? Phi : b.phi, e ? e : b.e, b.energy);
   if (cells) launch_cells(s, X, N, p, Nx, b.factor, cells);
   LAUNCHCHK();
   HIPCHK(hipStreamSynchronize(s));
