@@ -73,8 +73,9 @@ typedef struct {
   int32_t rank_auto;     /* 1: apply the rank indicator after each step      */
   double rank_tol_up;    /* grow one pair when eps_perp exceeds this         */
   double fp_stall_tol;   /* a column whose relative update stops decreasing  */
-                         /* is accepted only below this update (else it     */
-                         /* iterates on; ENOCONV at fp_max_iters); 0: 1e-3  */
+                         /* is accepted only when the smaller of its last   */
+                         /* two updates is below this (else it iterates on; */
+                         /* ENOCONV at fp_max_iters); 0: 1e-3               */
   double rank_tol_down;  /* automatic shrink: drop the pairs whose singular  */
                          /* value of Z~ is below this times the largest     */
   int32_t deim_rows;     /* d, DEIM sample rows; 0: d = 2n (capped by the    */
@@ -134,9 +135,11 @@ symrom_status rom_init(const symrom_config* cfg, const double* L, const double* 
  * fixed point (relative update < fp_tol, Sec. 6.1), explicit midpoint for U
  * on the tangent space through the Cayley retraction, with the Galerkin or
  * DEIM (Sec. 4.2.2, eq. grHDD with the exact potential) gradient.  A column
- * whose relative update stops decreasing is accepted while that update is
- * below fp_stall_tol (a node-crossing 2-cycle of the piecewise-constant
- * gathered force); the largest update so accepted is info->stall_rel.  With
+ * whose relative update stops decreasing is accepted when the smaller of its
+ * last two updates is below fp_stall_tol (a node crossing of the
+ * piecewise-constant gathered force makes the iterates cycle between jumps
+ * and contraction steps); the largest update so accepted is
+ * info->stall_rel.  With
  * rank_auto the rank is updated after every step (see rom_adapt_rank, target
  * 0).  info (host, nullable) describes the last step.  On ENOCONV the state
  * (U, Z and the DEIM snapshot window) is the one before the failing step. */

@@ -358,12 +358,15 @@ def prk_step(st, cfg, fixed_iters=None):
             rel = _col_norms(kn - k[:, cols]) / np.where(nk > 0, nk, 1.0)
             conv = rel < cfg.fp_tol
             # reading: the gathered force is piecewise constant in a particle's
-            # own position, so a particle whose midpoint sits on a node can
-            # put the map into a 2-cycle; a column whose relative update stops
-            # decreasing is accepted at its current iterate, provided that
-            # update is already small (below fp_stall_tol); above it the
+            # own position (the cell field of Sec. 2.1), so a particle whose
+            # midpoint sits at a node can put the map into a cycle: the
+            # iterates alternate between contraction steps with the particle
+            # in one cell and jumps when it changes cell.  A column whose
+            # relative update stops decreasing is accepted at its current
+            # iterate, provided the smaller of its last two updates is below
+            # fp_stall_tol (the cycle has a contracted phase); otherwise the
             # column keeps iterating and the step fails at fp_max_iters
-            stall = ~conv & (rel >= prev[cols]) & (rel < cfg.fp_stall_tol)
+            stall = ~conv & (rel >= prev[cols]) & (np.minimum(rel, prev[cols]) < cfg.fp_stall_tol)
             stalled += int(np.sum(stall))
             if stall.any():
                 stall_rel = max(stall_rel, float(rel[stall].max()))

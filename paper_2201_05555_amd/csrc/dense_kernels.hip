@@ -811,8 +811,9 @@ __global__ void __launch_bounds__(256) cholqr_apply_kernel(const cplx* __restric
 // projection covered positions only: i U~^* V_r with V_r = Im(U~ Z~)).
 // For an active column:  rel = |k_new - k| / |k_new|;  converged if
 // rel < tol, stalled if not converged, rel >= the previous rel (a particle
-// on a node puts the map into a 2-cycle) and rel < stall_tol (a stall above
-// that floor keeps iterating); k <- k_new; ZG <- Zeval; if still active,
+// at a node puts the map into a cycle of jumps and contraction steps) and
+// the smaller of the two below stall_tol (a cycle without a contracted phase
+// below that floor keeps iterating); k <- k_new; ZG <- Zeval; if still active,
 // Zeval <- Z0 + dt/2 k.  counters[0] = active columns left, counters[1] +=
 // stalled, the double at counters + 6 = the largest rel accepted by a stall
 // (atomic maximum of the bit patterns, which order like the values for
@@ -876,7 +877,7 @@ __global__ void __launch_bounds__(DTPB) dense_fp_update_kernel(
     if (!fixed) {
       const double rel = (kn > 0.0) ? sqrt(dn) / sqrt(kn) : sqrt(dn);
       const bool conv = rel < tol;
-      const bool stall = !conv && rel >= prev[i] && rel < stall_tol;
+      const bool stall = !conv && rel >= prev[i] && fmin(rel, prev[i]) < stall_tol;
       prev[i] = rel;
       done = conv || stall;
       if (stall) {

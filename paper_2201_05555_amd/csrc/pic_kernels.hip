@@ -441,7 +441,7 @@ __global__ void __launch_bounds__(POISSON_THREADS) poisson_kernel(
     if (!dg.fixed) {
       const double rel = (kn > 0.0) ? sqrt(dn) / sqrt(kn) : sqrt(dn);
       const bool conv = rel < dg.tol;
-      const bool stall = !conv && rel >= prev_i && rel < dg.stall_tol;
+      const bool stall = !conv && rel >= prev_i && fmin(rel, prev_i) < dg.stall_tol;
       dg.prev[i] = rel;
       done = conv || stall;
       if (stall) {

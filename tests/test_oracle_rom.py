@@ -387,3 +387,34 @@ def test_automatic_shrink_drops_negligible_pairs():
     # nothing below the threshold: the rank stays
     status, two_n, _ = rom.adapt_rank(st, cfg, 0)
     assert two_n == 6
+
+
+def test_stagnation_accepts_a_cycle_with_a_contracted_phase(monkeypatch):
+    """The cycle a node crossing makes (Sec. 2.1: the gathered force is
+    piecewise constant in the particle position): the particle changes cell
+    every second evaluation, so the updates alternate between a jump of
+    about 1e-2 and a contraction step far below it.  The stagnation rule
+    measures the cycle by its smaller update: the column is accepted (the
+    accepted update, the jump, is reported), whereas a rule on the current
+    update alone never fires and the step would fail."""
+    st, cfg, _ = _tiny_landau(two_n=6, N=400)
+    real = rom.reduced_gradient
+    calls = {"n": 0}
+
+    def flipping(sub, c, U, Z, op=None):
+        g, gr = real(sub, c, U, Z, op)
+        calls["n"] += 1
+        jump = 1.0 + 1e-2 * ((calls["n"] // 2) % 2)   # cell A, A, B, B, A, A, ...
+        return g * jump, gr
+
+    monkeypatch.setattr(rom, "reduced_gradient", flipping)
+    cfg.fp_max_iters = 40
+    s1 = rom.RomState(U=st.U.copy(), Z=st.Z.copy(), L=st.L)
+    assert rom.prk_step(s1, cfg) == rom.OK
+    assert s1.last_stalled > 0 and 1e-3 < s1.last_stall_rel < 5e-2
+    # the floor still matters: with it at 1e-12 no contracted phase is small
+    # enough and the step fails
+    calls["n"] = 0
+    cfg2 = rom.RomConfig(**{**cfg.__dict__, "fp_stall_tol": 1e-12})
+    s2 = rom.RomState(U=st.U.copy(), Z=st.Z.copy(), L=st.L)
+    assert rom.prk_step(s2, cfg2) == rom.ENOCONV
