@@ -1,18 +1,24 @@
 """Benchmark: particle-parameter steps per second of the reduced model (ROM)
-and of the full-order PIC model (FOM) on one MI355X, on the synthetic
-two-stream ensemble N = 100,000 particles, p = 64 parameters, Nx = 128 cells,
-dt = 0.05, reduced rank 2n starting at 10 (cap 60).
+and of the full-order PIC model (FOM) on one MI355X, on a synthetic
+two-stream ensemble (default: N = 100,000 particles, p = 64 parameters,
+Nx = 128 cells, dt = 0.05, reduced rank 2n from 10 with cap 60, DEIM).
 
 Prints ONE JSON line.  `value` is the ROM throughput N * p * steps / time of
 the timed steps (inputs resident in HBM); by default two warm-up steps and 25
-timed steps (steps 3 to 27, the averaging window of the paper's timings).  `roofline` describes the
-dominant kernel family of the ROM step, timed with HIP events on the
-library's stream over the timed region; `cpu_baseline` times the FP64
-oracle on a bounded sample of the same workload on the host cores.
+timed steps (steps 3 to 27, the averaging window of the paper's timings).
+
+Beside it: the same metric for the FOM on the same ensemble and their ratio
+at matched error (relative position / velocity errors of eq. relative_errors
+and the largest relative electric-energy error of the ROM against the FOM,
+over the same steps from t = 0, with the complex-SVD target error of
+eq. relative_errors_complex_SVD); per-step latency percentiles; `roofline`
+for the dominant kernel on the caller's stream from the algorithmic work of
+its operation (HIP events on the library's stream); `critical_path` for the
+DEIM chain on the second stream; `cpu_baseline` times the FP64 oracle on a
+bounded sample of the same workload, on one host core and on all of them.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -21,19 +27,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12        # B/s, MI355X HBM3E
+PEAK_FP64 = 78.6e12      # flop/s, MI355X FP64 vector (= FP64 matrix) peak
 
-# timing families that hold one kernel each, and that kernel; the first
-# three run on the caller's stream (the step's critical path), the last on
-# the second stream beside the basis-velocity kernels
+# timing families that hold one kernel each on the caller's stream
 SINGLE_KERNEL = {
     "deposit": "deposit_rom_kernel (reconstruct + cell + LDS histogram)",
     "gather": "gather_project_kernel (reconstruct + field gather + g = U^* G)",
     "gather_xi": "gather_xi_kernel (reconstruct + field gather + xi = -i h G Q + U M)",
 }
-SIDE_KERNEL = {
-    "deim_eig": "dense_topeig_kernel (top-d eigenpairs of the DEIM snapshot Gram)",
-}
-PEAK_FP64 = 78.6e12      # flop/s, MI355X FP64 vector (= FP64 matrix) peak
 
 # HBM bytes per launch of the deposit kernel, measured with two counter
 # passes (FETCH_SIZE, WRITE_SIZE) calibrated on a plain device copy; valid
@@ -50,29 +51,33 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="twostream_deim")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-matched", action="store_true", help="skip the matched-error pass")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     return ap.parse_args()
 
 
 def roofline_of(ms, flops, nbytes, launches):
-    """Binding roofline of a kernel family from its algorithmic work and its
-    measured time: the resource with the larger lower bound on time."""
+    """Binding roofline of a kernel family from the algorithmic work of its
+    operation and its measured time: the resource with the larger lower
+    bound on time (FP64 ALU against 78.6 TFLOP/s, or HBM against 8 TB/s)."""
     t = ms * 1e-3
     if t <= 0:
         return None
     t_alu = flops / PEAK_FP64
     t_hbm = nbytes / PEAK_HBM
+    base = {"avg_launch_us": 1e3 * ms / max(launches, 1), "launches": launches,
+            "algorithmic_flops_per_launch": flops / max(launches, 1),
+            "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
+            "frac_hbm": (nbytes / t) / PEAK_HBM, "frac_alu": (flops / t) / PEAK_FP64}
     if t_hbm >= t_alu:
         ach = nbytes / t / 1e9
         return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": ach / (PEAK_HBM / 1e9), "traffic": None,
-                "avg_launch_us": 1e3 * ms / max(launches, 1), "launches": launches}
+                "frac": ach / (PEAK_HBM / 1e9), "traffic": None, **base}
     ach = flops / t / 1e12
     return {"bound": "alu", "achieved": ach, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-            "frac": ach / (PEAK_FP64 / 1e12), "traffic": None,
-            "avg_launch_us": 1e3 * ms / max(launches, 1), "launches": launches}
+            "frac": ach / (PEAK_FP64 / 1e12), "traffic": None, **base}
 
 
 def measured_traffic():
@@ -93,16 +98,12 @@ def measured_traffic():
     return val if (val is not None and src == sha) else None
 
 
-def cpu_baseline(w, ens, seconds):
-    """The oracle's reduced step on a sample of the workload: the first
-    p_sub parameters, the same N, rank and time step."""
+def _oracle_rate(w, ens, seconds, threads):
+    """The oracle's reduced step (+ rank policy) on its first p_sub
+    parameters, same N, rank and time step, with `threads` BLAS threads."""
     import numpy as np
     from oracle import rom
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    from threadpoolctl import threadpool_limits
     p_sub = min(8, w["p"])
     X0 = np.asfortranarray(ens["X0"][:, :p_sub])
     V0 = np.asfortranarray(ens["V0"][:, :p_sub])
@@ -111,22 +112,75 @@ def cpu_baseline(w, ens, seconds):
                         projection=w.get("projection", "galerkin"),
                         deim_window=w.get("deim_window", 3),
                         rank_auto=w["two_n_max"] > w["two_n"], rank_tol_up=1e-2)
-    st = rom.init_state(X0, V0, ens["L"][:p_sub], cfg)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        rom.prk_step(st, cfg)
-        if cfg.rank_auto:
-            rom.adapt_rank(st, cfg, 0)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el > seconds or steps >= 50:
-            break
-    val = w["N"] * p_sub * steps / el
-    return {"value": val, "unit": "particle-param-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"oracle prk_step (+ rank policy), first {p_sub} of {w['p']} parameters, "
-                      f"N={w['N']}, 2n={w['two_n']}->{st.U.shape[1]}, {cfg.projection}, "
-                      f"{steps} steps in {el:.1f} s"}
+    with threadpool_limits(limits=threads):
+        st = rom.init_state(X0, V0, ens["L"][:p_sub], cfg)
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            rom.prk_step(st, cfg)
+            if cfg.rank_auto:
+                rom.adapt_rank(st, cfg, 0)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el > seconds or steps >= 50:
+                break
+    return w["N"] * p_sub * steps / el, steps, el, p_sub, st.U.shape[1]
+
+
+def cpu_baseline(w, ens, seconds):
+    """The oracle (not tuned) on the host: one core, then every core."""
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    v1, s1, e1, p_sub, r1 = _oracle_rate(w, ens, seconds, 1)
+    va, sa, ea, _, ra = _oracle_rate(w, ens, seconds, ncpu)
+    return {"value": va, "unit": "particle-param-steps/s", "cores": ncpu, "kind": "oracle",
+            "single_core_value": v1,
+            "sample": f"oracle prk_step (+ rank policy) on the first {p_sub} of {w['p']} "
+                      f"parameters, N={w['N']}, 2n={w['two_n']}->{ra}, "
+                      f"{w.get('projection', 'galerkin')}: {sa} steps in {ea:.1f} s on {ncpu} "
+                      f"threads, {s1} steps in {e1:.1f} s on 1 thread; the ROM's work per "
+                      f"step is about linear in p, so the rate is per particle-parameter"}
+
+
+def matched_error(binding, torch, w, ens, X0, V0, cfg, steps):
+    """ROM and FOM over the same steps from t = 0 on the same ensemble:
+    eq. relative_errors at the last step, the complex-SVD target error of
+    eq. relative_errors_complex_SVD (the truncated complex SVD of the FOM
+    state at that step, at the ROM's final rank), and the largest relative
+    electric-energy error max_{t, i} |E_rom - E_fom| / max_t E_fom."""
+    import numpy as np
+    N, p, Nx = w["N"], w["p"], w["Nx"]
+    rom_h = binding.Rom(cfg, ens["L"], X0, V0)
+    fom_h = binding.Fom(N, p, Nx, w["dt"], ens["L"], X0, V0)
+    E_r, E_f = [], []
+    for _ in range(steps):
+        rom_h.step(1)
+        fom_h.step(1)
+        E_r.append(rom_h.diagnostics()[0].cpu().numpy())
+        E_f.append(fom_h.diagnostics()[0].cpu().numpy())
+    E_r, E_f = np.array(E_r), np.array(E_f)
+    e_rel_E = float(np.max(np.abs(E_r - E_f) / np.maximum(np.max(np.abs(E_f), axis=0), 1e-300)))
+    Xr, Vr = rom_h.reconstruct()
+    Xf, Vf = fom_h.get_state()
+    ex = float(torch.linalg.norm(Xf - Xr) / torch.linalg.norm(Xf))
+    ev = float(torch.linalg.norm(Vf - Vr) / torch.linalg.norm(Vf))
+    two_n = rom_h.two_n
+    rom_h.close()
+    del Xr, Vr
+    # target: the truncated complex SVD of the FOM state (rom_init computes it)
+    tcfg = binding.make_config(N, p, Nx, two_n, dt=w["dt"])
+    t_h = binding.Rom(tcfg, ens["L"], Xf, Vf)
+    Xt, Vt = t_h.reconstruct()
+    tx = float(torch.linalg.norm(Xf - Xt) / torch.linalg.norm(Xf))
+    tv = float(torch.linalg.norm(Vf - Vt) / torch.linalg.norm(Vf))
+    t_h.close()
+    fom_h.close()
+    return {"steps_from_t0": steps, "eps_rel_X": ex, "eps_rel_V": ev,
+            "target_eps_rel_X": tx, "target_eps_rel_V": tv, "rank_2n": two_n,
+            "max_rel_energy_error": e_rel_E,
+            "definition": "eq. relative_errors (Frobenius over all particles and parameters) "
+                          "at the last step; target = truncated complex SVD of the FOM state; "
+                          "energy error max over steps and parameters of |E_rom - E_fom| / "
+                          "max_t E_fom"}
 
 
 def main():
@@ -158,33 +212,42 @@ def main():
 
     # ---------------- reduced model ----------------
     proj = w.get("projection", "galerkin")
+    rank_auto = w["two_n_max"] > w["two_n"]
     cfg = binding.make_config(N, p, Nx, w["two_n"], two_n_max=w["two_n_max"], dt=w["dt"],
                               projection=proj, deim_window=w.get("deim_window", 3), fp_tol=1e-9,
-                              rank_auto=w["two_n_max"] > w["two_n"], rank_tol_up=1e-2)
+                              rank_auto=rank_auto, rank_tol_up=1e-2, rank_tol_down=1e-8)
     rom_h = binding.Rom(cfg, ens["L"], X0, V0)
     for _ in range(a.warmup):
         rom_h.step(1)
     torch.cuda.synchronize()
-    # timed region: no per-kernel events (each event record leaves a gap in
-    # the stream), so `value` is the plain throughput
-    # (one call for the K steps, as a caller stepping the ensemble would)
+    # timed region: one call for the K steps (as a caller stepping the
+    # ensemble would), no per-kernel events in the stream
     two_n_start = rom_h.two_n
     t0 = time.perf_counter()
     info = rom_h.step(a.steps)
     torch.cuda.synchronize()
     t_rom = time.perf_counter() - t0
-    iters_timed = info["iters_total"]
-    deim_steps = info["deim_steps"]
     two_n_end = rom_h.two_n
-    # second timed region of the same length: HIP events on the library's
-    # stream around every kernel family, for the roofline figures
+    # per-step latency: K further steps, each its own call (the call returns
+    # with the step's status read back)
+    lat, stall_rel, stalled = [], 0.0, 0
+    for _ in range(a.steps):
+        t1 = time.perf_counter()
+        inf = rom_h.step(1)
+        lat.append(time.perf_counter() - t1)
+        stall_rel = max(stall_rel, inf["stall_rel"])
+        stalled += inf["stalled"]
+    # third pass of the same length: HIP events on the library's streams
+    # around every kernel family, for the roofline figures
     binding.set_timing(True)
     for fam in binding.FAMILIES:
         binding.kernel_ms(fam)
         binding.kernel_work(fam)
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        rom_h.step(1)
+        inf = rom_h.step(1)
+        stall_rel = max(stall_rel, inf["stall_rel"])
+        stalled += inf["stalled"]
     torch.cuda.synchronize()
     t_rom_ev = time.perf_counter() - t0
     fams = {}
@@ -214,34 +277,37 @@ def main():
     pp = N * p
     rom_rate = pp * a.steps / t_rom
     fom_rate = pp * a.steps / t_fom
-    # dominant kernel of the ROM step: the single-kernel family on the
-    # caller's stream with the largest device time over the instrumented
-    # steps (the "basis" and "dense" families are groups of different small
-    # kernels; the DEIM eigensolver runs beside them on the second stream and
-    # is reported separately)
+    # dominant kernel of the ROM step on the caller's stream: the
+    # single-kernel family with the largest device time over the
+    # instrumented steps
     dom = max(SINGLE_KERNEL, key=lambda f: fams[f]["ms"])
     d = fams[dom]
     roof = roofline_of(d["ms"], d["flops"], d["bytes"], d["launches"])
     if roof is not None:
         roof["kernel"] = SINGLE_KERNEL[dom]
+        roof["ms_per_step"] = d["ms"] / a.steps
         if dom == "deposit":
             t = measured_traffic()
             if t is not None:
                 roof["traffic"] = t
-                roof["algorithmic_bytes_per_launch"] = d["bytes"] / max(d["launches"], 1)
-        roof["ms_per_step"] = d["ms"] / a.steps
+                roof["traffic_over_algorithmic"] = t / roof["algorithmic_bytes_per_launch"]
     fom_roof = roofline_of(ms_push, fl_push, by_push, n_push)
-    side = {}
-    for f, name in SIDE_KERNEL.items():
-        r = roofline_of(fams[f]["ms"], fams[f]["flops"], fams[f]["bytes"], fams[f]["launches"])
-        if r is not None:
-            r["kernel"] = name
-            r["ms_per_step"] = fams[f]["ms"] / a.steps
-            r["stream"] = "second (beside the basis-velocity kernels)"
-            side[f] = r
-
+    # the DEIM chain on the second stream (snapshot, Gram block, top-d
+    # eigenpairs, Psi, greedy, weights): device time per step
+    crit = None
+    if fams["deim_eig"]["launches"]:
+        e = fams["deim_eig"]
+        eig = roofline_of(e["ms"], e["flops"], e["bytes"], e["launches"])
+        crit = {"stream": "second (beside the basis velocity and Cayley map of the step)",
+                "deim_chain_ms_per_step": (e["ms"] + fams["deim_chain"]["ms"]) / a.steps,
+                "eigensolver_ms_per_step": e["ms"] / a.steps,
+                "eigensolver": dict(eig or {}, kernel="dense_topeig_kernel (top-d eigenpairs "
+                                                      "of the P x P snapshot Gram, one workgroup)"),
+                "rest_of_chain_ms_per_step": fams["deim_chain"]["ms"] / a.steps}
+    lat_ms = np.array(lat) * 1e3
     out = {
-        "metric": "particle-param steps/s, reduced model (ROM) on 1 GPU; FOM and ratio beside",
+        "metric": "particle-param steps/s, reduced model (ROM) on 1 GPU; FOM and ratio at "
+                  "matched error beside",
         "value": rom_rate,
         "unit": "particle-param-steps/s",
         "n_gpus": 1,
@@ -256,17 +322,27 @@ def main():
         "config": {"workload": a.workload, "N": N, "p": p, "Nx": Nx, "dt": w["dt"],
                    "two_n_start": two_n_start, "two_n_end": two_n_end,
                    "two_n_max": w["two_n_max"], "projection": proj,
-                   "rank_auto": bool(cfg.rank_auto), "rank_tol_up": 1e-2,
-                   "deim_steps": deim_steps, "fp_tol": 1e-9,
-                   "mean_fp_iters": iters_timed / a.steps},
+                   "rank_auto": bool(rank_auto), "rank_tol_up": 1e-2, "rank_tol_down": 1e-8,
+                   "deim_steps": info["deim_steps"], "fp_tol": 1e-9,
+                   "mean_fp_iters": info["iters_total"] / a.steps},
+        "fixed_point": {"stalled_columns": info["stalled_total"] + stalled,
+                        "max_stall_accepted_update": stall_rel,
+                        "fp_stall_tol": 1e-3, "note": "over the timed, latency and event passes"},
+        "step_latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
+                            "p99": float(np.percentile(lat_ms, 99)),
+                            "max": float(lat_ms.max())},
         "fom": {"value": fom_rate, "unit": "particle-param-steps/s",
                 "ms_per_step": 1e3 * t_fom / a.steps, "roofline": fom_roof},
         "rom_over_fom": rom_rate / fom_rate,
         "roofline": roof,
-        "roofline_side_stream": side,
+        "critical_path": crit,
         "kernel_families_ms_per_step": {f: fams[f]["ms"] / a.steps for f in fams},
         "ms_per_step_with_events": 1e3 * t_rom_ev / a.steps,
     }
+    if not a.no_matched:
+        out["matched_error"] = matched_error(binding, torch, w, ens, X0, V0, cfg,
+                                             a.warmup + a.steps)
+        out["matched_error"]["rom_over_fom_at_this_error"] = rom_rate / fom_rate
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, ens, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -293,18 +293,21 @@ const char* symrom_last_error(void);
  * gather-projection (g = U~^* G~), 2 = Poisson (histogram sum and solve),
  * 3 = FOM push, 4 = basis (tall-skinny Grams and row combines), 5 = dense
  * (small matrices, DEIM greedy), 6 = DEIM eigenpairs (top d of the snapshot
- * Gram), 7 = fused gather-basis-velocity (xi = -i h G~ Q + U~ M).  Counts
- * launches in *launches (host, nullable). */
+ * Gram), 7 = fused gather-basis-velocity (xi = -i h G~ Q + U~ M), 8 = the
+ * rest of the DEIM chain on the second stream (snapshot, snapshot Gram block,
+ * basis Psi, greedy passes, weights).  Counts launches in *launches (host,
+ * nullable). */
 void symrom_set_timing(int32_t on);
 double symrom_kernel_ms(int32_t family, int64_t* launches);
 
 /* Algorithmic work of the timed launches of a family since the last call:
  * flops and HBM bytes as counted by the operation definitions (not by
  * hardware counters).  Reconstruct-and-deposit: 4n flops per
- * particle-parameter (x = Re(U~ Z~), n complex products), bytes = U~ read
- * once per parameter tile plus the partial histograms.  Gather-projection:
- * (8n + 4) flops per particle-parameter, bytes = U~ read once per tile of 64
- * parameters.  Gather-basis-velocity: 8n flops per particle-parameter plus
+ * particle-parameter (x = Re(U~ Z~), n complex products), bytes = U~ and Z~
+ * read once plus the charge written (8 Nx per active parameter; the
+ * per-row-block partial histograms are traffic of this design, not of the
+ * operation).  Gather-projection: (8n + 4) flops per particle-parameter,
+ * bytes = U~ and Z~ read and g written once.  Gather-basis-velocity: 8n flops per particle-parameter plus
  * 8n^2 per particle, bytes = U~ read and xi written.  DEIM eigenpairs:
  * 4P^3/3 + 2P^2 d + 2P d^2 flops for the tridiagonal reduction,
  * back-transform and orthonormalisation of a P x P Gram, no HBM bytes

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libsymrom.so")
 OK, EINVAL, ENOMEM, ESINGULAR, ENOCONV, EDEVICE, ESTATE, ERANKCAP = 0, -1, -2, -3, -4, -5, -6, -7
 GALERKIN, DEIM = 0, 1
 FAMILIES = {"deposit": 0, "gather": 1, "poisson": 2, "fom_push": 3, "basis": 4, "dense": 5,
-            "deim_eig": 6, "gather_xi": 7}
+            "deim_eig": 6, "gather_xi": 7, "deim_chain": 8}
 
 
 class SymromError(RuntimeError):

@@ -65,10 +65,10 @@ struct TimedLaunch {
 bool g_timing = false;
 std::vector<TimedLaunch> g_pending;
 std::vector<hipEvent_t> g_event_pool;
-double g_ms[8] = {0};
-int64_t g_launches[8] = {0};
-double g_flops[8] = {0};
-double g_bytes[8] = {0};
+double g_ms[9] = {0};
+int64_t g_launches[9] = {0};
+double g_flops[9] = {0};
+double g_bytes[9] = {0};
 
 hipEvent_t take_event() {
   if (!g_event_pool.empty()) {
@@ -126,7 +126,9 @@ enum {
   FAM_BASIS = 4,
   FAM_DENSE = 5,
   FAM_EIG = 6,
-  FAM_XI = 7
+  FAM_XI = 7,
+  FAM_CHAIN = 8,
+  NFAM = 9
 };
 
 extern "C" void symrom_set_timing(int32_t on) {
@@ -136,7 +138,7 @@ extern "C" void symrom_set_timing(int32_t on) {
 
 extern "C" double symrom_kernel_ms(int32_t family, int64_t* launches) {
   drain_timing();
-  if (family < 0 || family >= 8) return 0.0;
+  if (family < 0 || family >= NFAM) return 0.0;
   double v = g_ms[family];
   if (launches) *launches = g_launches[family];
   g_ms[family] = 0.0;
@@ -145,7 +147,7 @@ extern "C" double symrom_kernel_ms(int32_t family, int64_t* launches) {
 }
 
 extern "C" void symrom_kernel_work(int32_t family, double* flops, double* bytes) {
-  if (family < 0 || family >= 8) return;
+  if (family < 0 || family >= NFAM) return;
   if (flops) *flops = g_flops[family];
   if (bytes) *bytes = g_bytes[family];
   g_flops[family] = 0.0;
@@ -795,11 +797,13 @@ void full_gradient_field(symrom_rom& r, const cplx* U, const cplx* Z, const int*
   const int n = r.n;
   {
     {
-      // bytes: U and Z once each (the parameter tiles reread U from the
-      // caches), the partial histograms written
+      // algorithmic work: 4n flops per (particle, parameter) for x; bytes:
+      // U~ and Z~ read once, the charge of the active parameters written
+      // (the per-row-block partial histograms are this design's traffic,
+      // not the operation's)
       const double pact = (active ? (double)r.n_active : (double)r.p);
       Timer t(FAM_DEPOSIT, s, 4.0 * n * (double)r.N * pact,
-              16.0 * n * ((double)r.N + r.p) + 8.0 * (double)r.gdep.nrb * pact * r.Nx);
+              16.0 * n * ((double)r.N + r.p) + 8.0 * pact * r.Nx);
       launch_deposit_rom(s, U, r.N, n, Z, r.p, r.Nx, r.gdep, r.b.factor, active, r.b.part,
                          gate, fold, r.cfg.deterministic);
     }
@@ -823,10 +827,10 @@ void full_gradient(symrom_rom& r, const cplx* U, const cplx* Z, const int* activ
   const double pact = (active ? (double)r.n_active : (double)r.p);
   if (fused_gradient_ok(n)) {
     // per (particle, parameter): 4n flops for x and v, 4n for the projection,
-    // 4 for |G~|^2; bytes: the basis once per parameter tile, the partials
-    const int ntiles = (r.p + 31) / 32;
+    // 4 for |G~|^2; bytes: the basis and the coefficients read once, g written
+    // (the field table, O(p Nx), is negligible)
     Timer t(FAM_GATHER, s, (8.0 * n + 4.0) * (double)r.N * pact,
-            16.0 * n * (double)r.N * ntiles);
+            16.0 * n * ((double)r.N + 2.0 * r.p));
     launch_gather_project(s, U, r.N, n, Z, r.p, r.Nx, r.b.factor, r.b.e, qm, active, want_colsq,
                           r.gemm_part, (size_t)r.nkb * 64 * 64, r.gproj, r.colsq, gate);
     return;
@@ -955,7 +959,10 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z, bool redo = false,
   // head built ahead of its step)
   const int slot = (redo ? r.win_count - 1 : r.win_count) % r.nslots;
   double* Ys = r.Ywin + (size_t)slot * r.psub * N;
-  launch_snapshot(s, U, N, n, Z, r.sub, r.psub, r.Nx, r.b.factor, r.b.phi, Ys, stop);
+  {
+    Timer t(FAM_CHAIN, s);
+    launch_snapshot(s, U, N, n, Z, r.sub, r.psub, r.Nx, r.b.factor, r.b.phi, Ys, stop);
+  }
   if (!redo) r.win_count++;
   const int P = r.psub * r.nslots;
   std::vector<const double*> slots(r.nslots);
@@ -963,7 +970,7 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z, bool redo = false,
   {
     // the Gram Y^T Y (real, P x P) is kept across steps: only the row and
     // column block of the overwritten slot changes
-    Timer t(FAM_DENSE, s);
+    Timer t(FAM_CHAIN, s);
     launch_gram_block_real(s, Ys, slots.data(), r.nslots, r.psub, N, slot * r.psub,
                            r.nkb * 64 * 64 * 2, r.dpart, reinterpret_cast<double*>(r.YG), stop);
   }
@@ -991,7 +998,7 @@ void deim_update_tail(symrom_rom& r) {
   std::vector<const double*> slots(r.nslots);
   for (int q = 0; q < r.nslots; ++q) slots[q] = r.Ywin + (size_t)q * r.psub * N;
   const int P = r.psub * r.nslots;
-  Timer t(FAM_DENSE, s);
+  Timer t(FAM_CHAIN, s);
   // Psi and its column sums.  No sign convention is applied to the columns:
   // flipping the sign of column k negates c_k and the residual exactly, so
   // the greedy indices and the weights are the same bit for bit.
@@ -1106,7 +1113,7 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
         const double pact = (double)r.n_active;
         {
           Timer t(FAM_DEPOSIT, s, 4.0 * n * (double)N * pact,
-                  16.0 * n * ((double)N + p) + 8.0 * (double)r.gdep.nrb * pact * r.Nx);
+                  16.0 * n * ((double)N + p) + 8.0 * pact * r.Nx);
           launch_deposit_rom(s, r.Uh, N, n, r.Zev, p, r.Nx, r.gdep, r.b.factor, r.active,
                              r.b.part, gate, nullptr, r.cfg.deterministic);
         }

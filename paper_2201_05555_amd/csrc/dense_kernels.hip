@@ -1563,11 +1563,25 @@ __global__ void __launch_bounds__(DTPB) dense_rank_cert_kernel(const cplx* __res
   __shared__ cplx S[32 * 32];
   __shared__ cplx R[32 * 32];
   __shared__ double trs;
-  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+  extern __shared__ cplx zs[];  // Z~ (n x p) when it fits, see the launcher
+  const bool lds = n * p <= 4096;
+  if (lds) {
+    for (int t = threadIdx.x; t < n * p; t += blockDim.x) zs[t] = Z[t];
+    __syncthreads();
+  }
+  const cplx* Zr = lds ? zs : Z;
+  // entry (a, b) of Z~ Z~^* by a group of 8 lanes (parameters strided),
+  // summed by a fixed butterfly
+  const int g = threadIdx.x >> 3, gl = threadIdx.x & 7;
+  for (int t = g; t < n * n; t += blockDim.x >> 3) {
     const int a = t % n, b = t / n;
     cplx acc = mk(0.0, 0.0);
-    for (int i = 0; i < p; ++i) cfma(acc, Z[(size_t)i * n + a], cconj(Z[(size_t)i * n + b]));
-    S[t] = acc;
+    for (int i = gl; i < p; i += 8) cfma(acc, Zr[(size_t)i * n + a], cconj(Zr[(size_t)i * n + b]));
+    for (int o = 4; o > 0; o >>= 1) {
+      acc.re += __shfl_xor(acc.re, o, 8);
+      acc.im += __shfl_xor(acc.im, o, 8);
+    }
+    if (gl == 0) S[t] = acc;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1681,7 +1695,9 @@ __global__ void proj_mats_kernel(const cplx* __restrict__ C, int n, int k, cplx*
 }
 
 void launch_dense_rank_cert(hipStream_t s, const cplx* Z, int n, int p, double c, int* word) {
-  hipLaunchKernelGGL(dense_rank_cert_kernel, dim3(1), dim3(DTPB), 0, s, Z, n, p, c, word);
+  const size_t sh = (n * p <= 4096) ? (size_t)n * p * sizeof(cplx) : 0;
+  ALLOW_BIG_LDS(dense_rank_cert_kernel);
+  hipLaunchKernelGGL(dense_rank_cert_kernel, dim3(1), dim3(DTPB), sh, s, Z, n, p, c, word);
 }
 void launch_dense_zsvals(hipStream_t s, const cplx* Z, int n, int p, cplx* work, double* sig) {
   hipLaunchKernelGGL(dense_zsvals_kernel, dim3(1), dim3(DTPB), 0, s, Z, n, p, work, sig);
