@@ -130,6 +130,19 @@ symrom_status rom_init(const symrom_config* cfg, const double* L, const double* 
                        const double* V0, void* ws, size_t ws_bytes, void* stream,
                        symrom_rom** out);
 
+/* rom_init with the initial ensemble loaded on the device (Sec. 6.1: the
+ * perturbed Maxwellian f0 = f_v(v) (1 + alpha cos kx) on [0, 2 pi / k) x
+ * [-10, 10], sampled by inverse CDF with uniforms shared by every
+ * parameter; see symrom_load_family), so that no N x p host array is ever
+ * formed.  family: 0 Landau (f_v = N(0, sigma)), 1 two-stream
+ * (f_v = (N(-v0, sigma) + N(v0, sigma)) / 2).  eta: host, p x 4 row-major
+ * (alpha, k, v0, sigma) per parameter; L_i = 2 pi / k_i.  ux, uv: device [N]
+ * uniforms in (0, 1).  Other arguments and errors as rom_init (EINVAL also
+ * for k <= 0, sigma <= 0 or non-finite eta). */
+symrom_status rom_init_family(const symrom_config* cfg, int32_t family, const double* eta,
+                              const double* ux, const double* uv, void* ws, size_t ws_bytes,
+                              void* stream, symrom_rom** out);
+
 /* Advance the whole ensemble by nsteps steps of the order-2 partitioned
  * Runge-Kutta scheme (Sec. 5): implicit midpoint for Z solved by per-column
  * fixed point (relative update < fp_tol, Sec. 6.1), explicit midpoint for U
@@ -226,6 +239,13 @@ symrom_status fom_init(int32_t N, int32_t p, int32_t Nx, double dt, double q, do
                        const double* L, const double* X0, const double* V0, void* ws,
                        size_t ws_bytes, void* stream, symrom_fom** out);
 
+/* fom_init with the initial ensemble loaded on the device: family, eta
+ * (host, p x 4), ux, uv (device [N]) as in rom_init_family. */
+symrom_status fom_init_family(int32_t N, int32_t p, int32_t Nx, double dt, double q, double m,
+                              int32_t family, const double* eta, const double* ux,
+                              const double* uv, void* ws, size_t ws_bytes, void* stream,
+                              symrom_fom** out);
+
 /* nsteps Stormer-Verlet steps for every parameter:
  * X+ = X + dt (V + dt/2 a(X)),  V+ = V + dt/2 (a(X) + a(X+)),
  * a = -(q/m) e_{j(X)} the acceleration of eq. VPHamEqn. */
@@ -242,6 +262,18 @@ void fom_destroy(symrom_fom* h);
 /* ------------------------------------------------------------------------
  * Stateless particle-to-grid pieces (Sec. 2.1), for tests and tools
  * ------------------------------------------------------------------------ */
+
+/* Initial particle states of an ensemble (Sec. 6.1 loading): for particle l
+ * and parameter i, x = F_x^{-1}(ux[l]) with F_x(x) = (x + (alpha_i / k_i)
+ * sin k_i x) / L_i by Newton kept in [0, L_i], and v = F_v^{-1}(lo + uv[l]
+ * (hi - lo)), lo, hi = F_v(-10), F_v(10), for the Gaussian (family 0) or the
+ * two-beam mixture (family 1) of spread sigma_i (and drift v0_i), by the
+ * inverse normal CDF (family 0) or bracketed Newton (family 1).  eta:
+ * DEVICE, p x 4 row-major (alpha, k, v0, sigma); ux, uv: device [N]; X, V:
+ * device N x p (column-major; each nullable).  Synchronises the stream. */
+symrom_status symrom_load_family(int32_t family, int32_t N, int32_t p, const double* eta,
+                                 const double* ux, const double* uv, double* X, double* V,
+                                 void* stream);
 
 /* Workspace bytes for deim_select; 0 unless 1 <= d <= 64 and d <= N. */
 size_t deim_select_workspace_bytes(int32_t N, int32_t d);

@@ -59,6 +59,14 @@ _SIGS = {
     "rom_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Config)]),
     "rom_init": (ctypes.c_int32, [ctypes.POINTER(Config), _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP,
                                   ctypes.POINTER(_VP)]),
+    "rom_init_family": (ctypes.c_int32, [ctypes.POINTER(Config), ctypes.c_int32, _VP, _VP, _VP,
+                                         _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    "fom_init_family": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int32, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP,
+                                         ctypes.POINTER(_VP)]),
+    "symrom_load_family": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
+                                            _VP, _VP, _VP, _VP, _VP]),
     "rom_step": (ctypes.c_int32, [_VP, ctypes.c_int32, ctypes.POINTER(StepInfo)]),
     "rom_adapt_rank": (ctypes.c_int32, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "rom_set_fixed_point": (ctypes.c_int32, [_VP, ctypes.c_double, ctypes.c_int32,
@@ -186,6 +194,26 @@ def _info_dict(info):
                 stall_rel=info.stall_rel, stalled_total=info.stalled_total, shrunk=info.shrunk)
 
 
+def _dev1(x):
+    """1-D host or device array -> contiguous FP64 device tensor."""
+    if isinstance(x, torch.Tensor):
+        return x.to(dtype=torch.float64, device="cuda").contiguous()
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.float64))).cuda()
+
+
+def load_family(family, params, ux, uv, stream=None):
+    """Initial states X, V (p, N) device tensors of an ensemble, loaded on the
+    device (symrom_load_family)."""
+    eta = torch.from_numpy(eta_array(params)).cuda()
+    uxd, uvd = _dev1(ux), _dev1(uv)
+    N, p = uxd.numel(), eta.shape[0]
+    X = torch.empty((p, N), dtype=torch.float64, device="cuda")
+    V = torch.empty_like(X)
+    _check(lib().symrom_load_family(FAMILY[family], N, p, _ptr(eta), _ptr(uxd), _ptr(uvd),
+                                    _ptr(X), _ptr(V), _stream(stream)))
+    return X, V
+
+
 def _dev(x, device="cuda"):
     """(N, p) numpy -> (p, N) contiguous device tensor (column-major N x p)."""
     if isinstance(x, torch.Tensor):
@@ -193,22 +221,42 @@ def _dev(x, device="cuda"):
     return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.float64).T)).to(device)
 
 
-class Rom:
-    """Reduced-model handle (rom_* entry points)."""
+FAMILY = {"landau": 0, "twostream": 1}
 
-    def __init__(self, cfg, L, X0, V0, stream=None):
+
+def eta_array(params):
+    """p x 4 host array (alpha, k, v0, sigma) from a parameter dict."""
+    return np.ascontiguousarray(np.stack([params["alpha"], params["k"], params["v0"],
+                                          params["sigma"]], axis=1), dtype=np.float64)
+
+
+class Rom:
+    """Reduced-model handle (rom_* entry points).  With X0 = None the initial
+    ensemble is loaded on the device (rom_init_family): pass family, params
+    (dict of alpha, k, v0, sigma arrays) and the shared uniforms ux, uv."""
+
+    def __init__(self, cfg, L, X0, V0, stream=None, family=None, params=None, ux=None, uv=None):
         self.cfg = cfg
-        self.L = np.asarray(L, dtype=np.float64).copy()
         self.stream = stream
         nbytes = lib().rom_workspace_bytes(ctypes.byref(cfg))
         if nbytes == 0:
             raise SymromError(EINVAL, "invalid configuration")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        X0, V0 = _dev(X0), _dev(V0)
-        Lh, Lp = _host_doubles(self.L)
         h = ctypes.c_void_p()
-        _check(lib().rom_init(ctypes.byref(cfg), Lp, _ptr(X0), _ptr(V0), _ptr(self.ws),
-                              nbytes, _stream(stream), ctypes.byref(h)))
+        if X0 is None:
+            eta = eta_array(params)
+            self.L = 2.0 * np.pi / np.asarray(params["k"], dtype=np.float64)
+            uxd, uvd = _dev1(ux), _dev1(uv)
+            _check(lib().rom_init_family(ctypes.byref(cfg), FAMILY[family],
+                                         eta.ctypes.data_as(ctypes.c_void_p), _ptr(uxd),
+                                         _ptr(uvd), _ptr(self.ws), nbytes, _stream(stream),
+                                         ctypes.byref(h)))
+        else:
+            self.L = np.asarray(L, dtype=np.float64).copy()
+            X0, V0 = _dev(X0), _dev(V0)
+            Lh, Lp = _host_doubles(self.L)
+            _check(lib().rom_init(ctypes.byref(cfg), Lp, _ptr(X0), _ptr(V0), _ptr(self.ws),
+                                  nbytes, _stream(stream), ctypes.byref(h)))
         self.h = h
 
     def close(self):
@@ -310,17 +358,26 @@ class Rom:
 class Fom:
     """Full-order PIC handle (fom_* entry points)."""
 
-    def __init__(self, N, p, Nx, dt, L, X0, V0, q=-1.0, m=1.0, stream=None):
+    def __init__(self, N, p, Nx, dt, L, X0, V0, q=-1.0, m=1.0, stream=None, family=None,
+                 params=None, ux=None, uv=None):
         self.N, self.p, self.Nx = N, p, Nx
         nbytes = lib().fom_workspace_bytes(N, p, Nx)
         if nbytes == 0:
             raise SymromError(EINVAL, "invalid sizes")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        X0, V0 = _dev(X0), _dev(V0)
-        Lh, Lp = _host_doubles(L)
         h = ctypes.c_void_p()
-        _check(lib().fom_init(N, p, Nx, dt, q, m, Lp, _ptr(X0), _ptr(V0), _ptr(self.ws), nbytes,
-                              _stream(stream), ctypes.byref(h)))
+        if X0 is None:
+            eta = eta_array(params)
+            uxd, uvd = _dev1(ux), _dev1(uv)
+            _check(lib().fom_init_family(N, p, Nx, dt, q, m, FAMILY[family],
+                                         eta.ctypes.data_as(ctypes.c_void_p), _ptr(uxd),
+                                         _ptr(uvd), _ptr(self.ws), nbytes, _stream(stream),
+                                         ctypes.byref(h)))
+        else:
+            X0, V0 = _dev(X0), _dev(V0)
+            Lh, Lp = _host_doubles(L)
+            _check(lib().fom_init(N, p, Nx, dt, q, m, Lp, _ptr(X0), _ptr(V0), _ptr(self.ws),
+                                  nbytes, _stream(stream), ctypes.byref(h)))
         self.h = h
 
     def close(self):

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -404,10 +405,12 @@ extern "C" size_t fom_workspace_bytes(int32_t N, int32_t p, int32_t Nx) {
   return ar.off + 256;
 }
 
-extern "C" symrom_status fom_init(int32_t N, int32_t p, int32_t Nx, double dt, double q, double m,
-                                  const double* L, const double* X0, const double* V0, void* ws,
-                                  size_t ws_bytes, void* stream, symrom_fom** out) {
-  if (!valid_sizes(N, p, Nx) || !L || !X0 || !V0 || !out || !(m != 0.0))
+namespace {
+// fill(f): writes the initial X, V into f.X, f.V on f.s
+symrom_status fom_init_impl(int32_t N, int32_t p, int32_t Nx, double dt, double q, double m,
+                            const double* L, const std::function<bool(symrom_fom&)>& fill,
+                            void* ws, size_t ws_bytes, void* stream, symrom_fom** out) {
+  if (!valid_sizes(N, p, Nx) || !L || !out || !(m != 0.0))
     return fail(SYMROM_EINVAL, "fom_init: bad arguments");
   for (int i = 0; i < p; ++i)
     if (!(L[i] > 0.0) || !std::isfinite(L[i])) return fail(SYMROM_EINVAL, "fom_init: bad L");
@@ -435,8 +438,7 @@ extern "C" symrom_status fom_init(int32_t N, int32_t p, int32_t Nx, double dt, d
       hipMemcpyAsync(f->b.qw, qw.data(), p * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(f->b.h, h.data(), p * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(f->b.mw, mw.data(), p * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(f->X, X0, (size_t)N * p * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(f->V, V0, (size_t)N * p * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      !fill(*f))
     return cleanup(fail(SYMROM_EDEVICE, "fom_init: copy failed"));
   PicGeom gd = f->g;
   launch_deposit_x(s, f->X, N, p, Nx, gd, f->b.factor, f->b.part);
@@ -449,6 +451,55 @@ extern "C" symrom_status fom_init(int32_t N, int32_t p, int32_t Nx, double dt, d
     return cleanup(fail(SYMROM_EDEVICE, "fom_init: launch"));
   *out = f;
   return SYMROM_OK;
+}
+
+}  // namespace
+
+extern "C" symrom_status fom_init(int32_t N, int32_t p, int32_t Nx, double dt, double q, double m,
+                                  const double* L, const double* X0, const double* V0, void* ws,
+                                  size_t ws_bytes, void* stream, symrom_fom** out) {
+  if (!X0 || !V0) return fail(SYMROM_EINVAL, "fom_init: null state");
+  auto fill = [&](symrom_fom& f) {
+    return hipMemcpyAsync(f.X, X0, (size_t)N * p * 8, hipMemcpyDeviceToDevice, f.s) ==
+               hipSuccess &&
+           hipMemcpyAsync(f.V, V0, (size_t)N * p * 8, hipMemcpyDeviceToDevice, f.s) == hipSuccess;
+  };
+  return fom_init_impl(N, p, Nx, dt, q, m, L, fill, ws, ws_bytes, stream, out);
+}
+
+// L_i = 2 pi / k_i from eta (host, p x 4: alpha, k, v0, sigma); false when
+// a wave number or a spread is not positive or a value is not finite
+namespace {
+bool eta_lengths(int p, const double* eta, std::vector<double>& L) {
+  L.resize(p);
+  for (int i = 0; i < p; ++i) {
+    for (int c = 0; c < 4; ++c)
+      if (!std::isfinite(eta[4 * i + c])) return false;
+    if (!(eta[4 * i + 1] > 0.0) || !(eta[4 * i + 3] > 0.0)) return false;
+    L[i] = 2.0 * M_PI / eta[4 * i + 1];
+  }
+  return true;
+}
+}  // namespace
+
+extern "C" symrom_status fom_init_family(int32_t N, int32_t p, int32_t Nx, double dt, double q,
+                                         double m, int32_t family, const double* eta,
+                                         const double* ux, const double* uv, void* ws,
+                                         size_t ws_bytes, void* stream, symrom_fom** out) {
+  std::vector<double> L;
+  if (!eta || !ux || !uv || (family != 0 && family != 1) || !valid_sizes(N, p, Nx) ||
+      !eta_lengths(p, eta, L))
+    return fail(SYMROM_EINVAL, "fom_init_family: bad arguments");
+  // eta is staged in the deposit-partials buffer (at least 32 p doubles),
+  // which the first deposit overwrites only after the load has read it
+  auto fill = [&](symrom_fom& f) {
+    if (hipMemcpyAsync(f.b.part, eta, (size_t)4 * p * sizeof(double), hipMemcpyHostToDevice,
+                       f.s) != hipSuccess)
+      return false;
+    launch_load_family(f.s, family, N, p, f.b.part, ux, uv, f.X, f.V, nullptr);
+    return hipGetLastError() == hipSuccess;
+  };
+  return fom_init_impl(N, p, Nx, dt, q, m, L.data(), fill, ws, ws_bytes, stream, out);
 }
 
 extern "C" symrom_status fom_step(symrom_fom* f, int32_t nsteps) {
@@ -577,6 +628,9 @@ struct symrom_rom {
   bool head_pending;
   int head_n;
   double* zsig;  // singular values of Z~ (automatic shrink)
+  cplx* Ysub;    // Rayleigh-Ritz eigenvectors of the subspace iteration (64 x 64)
+  cplx* Wsub;    // its p x 64 block of vectors (p > 64)
+  double* lamsub;
   symrom_step_info last;
 };
 
@@ -673,6 +727,9 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.C12a = ar.take<cplx>((size_t)2 * nm * nm);
   r.gF = ar.take<cplx>((size_t)nm * p);
   r.zsig = ar.take<double>(nm);
+  r.Ysub = ar.take<cplx>(64 * 64);
+  r.Wsub = ar.take<cplx>(p > 64 ? (size_t)p * 64 : 0);
+  r.lamsub = ar.take<double>(64);
   r.dpart = ar.take<double>(r.cfg.projection == SYMROM_DEIM ? (size_t)r.nkb * 64 * 64 * 2 : 0);
 }
 
@@ -725,8 +782,8 @@ bool valid_rom_config(const symrom_config* c, std::string& why) {
     why = "deterministic must be 0 or 1";
     return false;
   }
-  if (c->p > 64) {
-    why = "p above 64 is not supported by the initialisation";
+  if (c->p > 4096) {
+    why = "p above 4096 is not supported";
     return false;
   }
   if (c->projection == SYMROM_DEIM) {
@@ -1132,7 +1189,7 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
         Timer t(FAM_DENSE, s);
         launch_dense_fp_update(s, r.gproj, r.C12, n, p, r.Z0, r.Zev, r.ZG, r.k, r.prev, r.active,
                                dt, r.cfg.fp_tol, r.cfg.fp_stall_tol, fixed > 0 ? 1 : 0, 0,
-                               r.counters);
+                               launched + 1, r.counters);
       }
     }
     LAUNCHCHK();
@@ -1337,12 +1394,84 @@ __global__ void unit_minus_proj_kernel(cplx* U, int N, int c, int j) {
 }
 }  // namespace
 
-extern "C" symrom_status rom_init(const symrom_config* cfg, const double* L, const double* X0,
-                                  const double* V0, void* ws, size_t ws_bytes, void* stream,
-                                  symrom_rom** out) {
+namespace {
+// Gram G = A^* A (p x p, ld p) of an N x p matrix with p > 64: the blocks of
+// 64 columns on and above the diagonal by the split-K product, each placed
+// with its conjugate transpose.
+void gram_big(symrom_rom& r, const cplx* A, int p, cplx* G) {
+  hipStream_t s = r.s;
+  const size_t N = (size_t)r.N;
+  for (int a0 = 0; a0 < p; a0 += 64) {
+    const int ac = std::min(64, p - a0);
+    for (int b0 = a0; b0 < p; b0 += 64) {
+      const int bc = std::min(64, p - b0);
+      launch_gemm_ah_b(s, ml(A + a0 * N, ac), ac, ml(A + b0 * N, bc), bc, false, r.N, r.nkb,
+                       r.gemm_part, r.Gram);
+      launch_scatter_block(s, r.Gram, ac, bc, G, p, a0, b0);
+    }
+  }
+}
+
+// The k leading eigenpairs of a Hermitian p x p matrix A (p > 64, k <= 48)
+// by subspace iteration with Rayleigh-Ritz on m = min(k + 16, 64) vectors:
+// W = orth(A V); H = W^* A W (m x m); V = W Y with H = Y diag(lam) Y^*
+// (decreasing).  The leading k Ritz values settle first; the iteration then
+// runs on until the subspace angle, which shrinks by rho = lam_m / lam_k per
+// iteration, is below 1e-15 of its value at that point times 1e-8 (about
+// the square root of the Ritz-value tolerance).  V: p x m (ld p), W: p x m
+// scratch; lam (m, device) and the count m.  At most 400 iterations.
+symrom_status topeig_subspace(symrom_rom& r, const cplx* A, int p, int k, cplx* V, cplx* W,
+                              double* lam, int* m_out) {
+  hipStream_t s = r.s;
+  const int m = std::min(64, std::min(p, k + 16));
+  std::vector<cplx> v0((size_t)p * m);
+  uint64_t x = 0x9e3779b97f4a7c15ull;
+  for (auto& v : v0) {
+    x = x * 6364136223846793005ull + 1442695040888963407ull;
+    const double a = (double)(x >> 11) * 0x1p-53 - 0.5;
+    x = x * 6364136223846793005ull + 1442695040888963407ull;
+    const double b = (double)(x >> 11) * 0x1p-53 - 0.5;
+    v = mk(a, b);
+  }
+  HIPCHK(hipMemcpyAsync(V, v0.data(), v0.size() * sizeof(cplx), hipMemcpyHostToDevice, s));
+  launch_cgs2(s, V, p, m);
+  std::vector<double> prev(m, 0.0), cur(m);
+  int extra = -1;  // iterations still to run once the Ritz values settled
+  for (int it = 0; it < 400; ++it) {
+    launch_herm_mm(s, A, V, p, m, W);
+    launch_cgs2(s, W, p, m);
+    launch_herm_mm(s, A, W, p, m, V);
+    launch_gemm_ah_b(s, ml(W, m), m, ml(V, m), m, false, p, r.nkb, r.gemm_part, r.Gram);
+    launch_dense_herm_eig(s, r.Gram, m, r.Ysub, lam, r.flags);
+    launch_rowgemm(s, rt(W, r.Ysub, m), p, m, V);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(cur.data(), lam, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (extra > 0) {
+      if (--extra == 0) break;
+    } else if (it >= 2) {
+      double dmax = 0.0;
+      for (int j = 0; j < k; ++j) dmax = std::max(dmax, std::fabs(cur[j] - prev[j]));
+      if (dmax <= 1e-14 * std::fabs(cur[0])) {
+        const double rho = (cur[k - 1] > 0.0) ? std::fabs(cur[m - 1]) / cur[k - 1] : 1.0;
+        extra = (rho < 1e-3) ? 3 : std::min(300, 3 + (int)std::ceil(std::log(1e-8) / std::log(rho)));
+      }
+    }
+    prev = cur;
+  }
+  *m_out = m;
+  return SYMROM_OK;
+}
+}  // namespace
+
+namespace {
+// fill(r): writes C0 = X0 + i V0 into r.G on r.s
+symrom_status rom_init_impl(const symrom_config* cfg, const double* L,
+                            const std::function<bool(symrom_rom&)>& fill, void* ws,
+                            size_t ws_bytes, void* stream, symrom_rom** out) {
   std::string why;
   if (!valid_rom_config(cfg, why)) return fail(SYMROM_EINVAL, "rom_init: " + why);
-  if (!L || !X0 || !V0 || !out) return fail(SYMROM_EINVAL, "rom_init: null pointer");
+  if (!L || !out) return fail(SYMROM_EINVAL, "rom_init: null pointer");
   for (int i = 0; i < cfg->p; ++i)
     if (!(L[i] > 0.0) || !std::isfinite(L[i])) return fail(SYMROM_EINVAL, "rom_init: bad L");
   size_t need = rom_workspace_bytes(cfg);
@@ -1370,18 +1499,33 @@ extern "C" symrom_status rom_init(const symrom_config* cfg, const double* L, con
     delete r;
     return fail(SYMROM_EDEVICE, "rom_init: memset");
   }
-  // C0 = X0 + i V0 in the gather buffer; Gram C0^* C0 (p x p) and its eigen
-  launch_make_complex(s, X0, V0, (size_t)N * p, r->G);
-  launch_gemm_ah_b(s, ml(r->G, p), p, ml(r->G, p), p, false, N, r->nkb, r->gemm_part, r->Gp);
-  launch_dense_herm_eig(s, r->Gp, p, r->Vp, r->lam, r->flags);
-  std::vector<double> lam(p);
-  if (hipMemcpyAsync(lam.data(), r->lam, p * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+  // C0 = X0 + i V0 in the gather buffer; Gram C0^* C0 (p x p) and its
+  // leading eigenpairs: all of them by Jacobi for p <= 64, the leading ones
+  // by subspace iteration beyond
+  if (!fill(*r)) {
+    delete r;
+    return fail(SYMROM_EDEVICE, "rom_init: initial state");
+  }
+  int nl = p;
+  if (p <= 64) {
+    launch_gemm_ah_b(s, ml(r->G, p), p, ml(r->G, p), p, false, N, r->nkb, r->gemm_part, r->Gp);
+    launch_dense_herm_eig(s, r->Gp, p, r->Vp, r->lam, r->flags);
+  } else {
+    gram_big(*r, r->G, p, r->Gp);
+    symrom_status st2 = topeig_subspace(*r, r->Gp, p, n, r->Vp, r->Wsub, r->lam, &nl);
+    if (st2 != SYMROM_OK) {
+      delete r;
+      return st2;
+    }
+  }
+  std::vector<double> lam(nl);
+  if (hipMemcpyAsync(lam.data(), r->lam, nl * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
     delete r;
     return fail(SYMROM_EDEVICE, "rom_init: eigen readback");
   }
   int rk = 0;
-  while (rk < n && rk < p && lam[rk] > 1e-26 * lam[0] && lam[rk] > 0.0) ++rk;
+  while (rk < n && rk < nl && lam[rk] > 1e-26 * lam[0] && lam[rk] > 0.0) ++rk;
   // U[:, :rk] = C0 V_rk diag(lam)^{-1/2}
   hipLaunchKernelGGL(scale_cols_kernel, dim3((p * rk + 255) / 256 + 1), dim3(256), 0, s, r->Vp,
                      r->lam, p, rk, r->Q);
@@ -1454,6 +1598,50 @@ extern "C" symrom_status rom_init(const symrom_config* cfg, const double* L, con
   r->stage1_cached = false;
   r->step = 0;
   *out = r;
+  return SYMROM_OK;
+}
+}  // namespace
+
+extern "C" symrom_status rom_init(const symrom_config* cfg, const double* L, const double* X0,
+                                  const double* V0, void* ws, size_t ws_bytes, void* stream,
+                                  symrom_rom** out) {
+  if (!X0 || !V0) return fail(SYMROM_EINVAL, "rom_init: null state");
+  auto fill = [&](symrom_rom& r) {
+    launch_make_complex(r.s, X0, V0, (size_t)r.N * r.p, r.G);
+    return hipGetLastError() == hipSuccess;
+  };
+  return rom_init_impl(cfg, L, fill, ws, ws_bytes, stream, out);
+}
+
+extern "C" symrom_status rom_init_family(const symrom_config* cfg, int32_t family,
+                                         const double* eta, const double* ux, const double* uv,
+                                         void* ws, size_t ws_bytes, void* stream,
+                                         symrom_rom** out) {
+  std::vector<double> L;
+  if (!cfg || !eta || !ux || !uv || (family != 0 && family != 1) || cfg->p <= 0 ||
+      !eta_lengths(cfg->p, eta, L))
+    return fail(SYMROM_EINVAL, "rom_init_family: bad arguments");
+  const int p = cfg->p;
+  // eta is staged in the deposit-partials buffer (at least 32 p doubles),
+  // which nothing uses before the first step
+  auto fill = [&](symrom_rom& r) {
+    if (hipMemcpyAsync(r.b.part, eta, (size_t)4 * p * sizeof(double), hipMemcpyHostToDevice,
+                       r.s) != hipSuccess)
+      return false;
+    launch_load_family(r.s, family, r.N, p, r.b.part, ux, uv, nullptr, nullptr, r.G);
+    return hipGetLastError() == hipSuccess;
+  };
+  return rom_init_impl(cfg, L.data(), fill, ws, ws_bytes, stream, out);
+}
+
+extern "C" symrom_status symrom_load_family(int32_t family, int32_t N, int32_t p,
+                                            const double* eta, const double* ux, const double* uv,
+                                            double* X, double* V, void* stream) {
+  if (N <= 0 || p <= 0 || !eta || !ux || !uv || (family != 0 && family != 1))
+    return fail(SYMROM_EINVAL, "symrom_load_family: bad arguments");
+  launch_load_family((hipStream_t)stream, family, N, p, eta, ux, uv, X, V, nullptr);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
   return SYMROM_OK;
 }
 
@@ -1564,13 +1752,22 @@ symrom_status rom_grow_apply(symrom_rom& r, int k) {
   hipStream_t s = r.s;
   const int n = r.n, p = r.p, N = r.N;
   r.stage1_cached = false;
-  if (fused_gradient_ok(n)) materialise_gradient(r, r.U0, r.Z0);
-  launch_gemm_ah_b(s, ml(r.G, p), p, ml(r.G, p), p, false, N, r.nkb, r.gemm_part, r.Gp);
-  launch_dense_hh(s, r.Gp, r.gproj, n, p, nullptr);
-  LAUNCHCHK();
   if (n + k > r.nmax) return fail(SYMROM_ERANKCAP, "rank growth beyond two_n_max");
   if (k > p) return fail(SYMROM_EINVAL, "cannot grow by more pairs than parameters");
-  launch_dense_herm_eig(s, r.Gp, p, r.Vp, r.lam, r.flags);
+  if (fused_gradient_ok(n)) materialise_gradient(r, r.U0, r.Z0);
+  if (p <= 64)
+    launch_gemm_ah_b(s, ml(r.G, p), p, ml(r.G, p), p, false, N, r.nkb, r.gemm_part, r.Gp);
+  else
+    gram_big(r, r.G, p, r.Gp);
+  launch_dense_hh(s, r.Gp, r.gproj, n, p, nullptr);
+  LAUNCHCHK();
+  if (p <= 64) {
+    launch_dense_herm_eig(s, r.Gp, p, r.Vp, r.lam, r.flags);
+  } else {
+    int ml_ = 0;
+    symrom_status st2 = topeig_subspace(r, r.Gp, p, k, r.Vp, r.Wsub, r.lam, &ml_);
+    if (st2 != SYMROM_OK) return st2;
+  }
   launch_dense_grow_prep(s, r.Vp, r.lam, r.gproj, n, p, k, r.Q, r.MP, r.flags);
   // the new columns go beyond the current basis (the state is not touched
   // until the flags are known)

@@ -12,6 +12,9 @@
 #include "kernels.h"
 
 #define DTPB 256
+// complex entries of an n x p coefficient block staged in LDS by the dense
+// kernels (64 KB); larger blocks are read in place
+#define DENSE_Z_LDS 4096
 
 // ---------------------------------------------------------------------------
 // block-cooperative helpers (all threads of the block call them)
@@ -336,16 +339,20 @@ __global__ void __launch_bounds__(DTPB) dense_spinv_kernel(const cplx* __restric
                                                            double* __restrict__ sigma2,
                                                            int* __restrict__ flags) {
   extern __shared__ cplx sm[];
-  cplx* Zs = sm;          // n x p
-  cplx* S = Zs + n * p;   // n x n
+  // Z (n x p) is staged in LDS when it fits (zlds), else read in place
+  const bool zlds = n * p <= DENSE_Z_LDS;
+  const cplx* Zs = zlds ? sm : Z;
+  cplx* S = zlds ? sm + n * p : sm;   // n x n
   cplx* R = S + n * n;
   cplx* Ri = R + n * n;
   __shared__ cplx rot[3 * 17 + 3];
   __shared__ int pr[40];
   __shared__ double lam[32];
   __shared__ double trs;
-  for (int t = threadIdx.x; t < n * p; t += blockDim.x) Zs[t] = Z[t];
-  __syncthreads();
+  if (zlds) {
+    for (int t = threadIdx.x; t < n * p; t += blockDim.x) sm[t] = Z[t];
+    __syncthreads();
+  }
   // S~ = Z~ Z~^*
   for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
     int a = t % n, b = t / n;
@@ -403,12 +410,16 @@ __global__ void __launch_bounds__(DTPB) dense_xfinish_kernel(const cplx* __restr
                                                              cplx* __restrict__ MP,
                                                              cplx* __restrict__ MU) {
   extern __shared__ cplx sm[];
-  cplx* gs = sm;          // n x p
-  cplx* Qs = gs + n * p;  // p x n
+  // g (n x p) and Q (p x n) staged in LDS when they fit, else read in place
+  const bool lds = n * p <= DENSE_Z_LDS;
+  const cplx* gs = lds ? sm : g;
+  const cplx* Qs = lds ? sm + n * p : Q;
   for (int t = threadIdx.x; t < n * p; t += blockDim.x) {
     const cplx gv = g[t];
-    gs[t] = gv;
-    Qs[t] = Q[t];
+    if (lds) {
+      sm[t] = gv;
+      sm[n * p + t] = Q[t];
+    }
     if (k1) k1[t] = mk(gv.im, -gv.re);
   }
   __syncthreads();
@@ -451,7 +462,8 @@ __global__ void __launch_bounds__(DTPB) dense_cayley_kernel(const cplx* __restri
   cplx* T1 = K + n * n;        // scratch  (phase 1 only)
   __shared__ int piv;
   cplx* Zs = sm + 18 * n * n;  // n x p, chol with Z only; loaded now, used last
-  if (chol && Z)
+  const bool zlds = n * p <= DENSE_Z_LDS;
+  if (chol && Z && zlds)
     for (int t = threadIdx.x; t < n * p; t += blockDim.x) Zs[t] = Z[t];
   for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
     int a = t % n, b = t / n;
@@ -543,13 +555,24 @@ __global__ void __launch_bounds__(DTPB) dense_cayley_kernel(const cplx* __restri
     MU[t] = T[c * m + r];
     MX[t] = T[c * m + n + r];
   }
-  if (Z) {
+  if (Z && zlds) {
     // Z <- R Z from the copy in LDS, one entry per thread (R upper triangular)
     for (int t = threadIdx.x; t < n * p; t += blockDim.x) {
       const int a = t % n, i = t / n;
       cplx sz = mk(0.0, 0.0);
       for (int b = a; b < n; ++b) cfma(sz, R[b * n + a], Zs[i * n + b]);
       Z[t] = sz;
+    }
+  } else if (Z) {
+    // the same products column by column in place (a column is read before
+    // it is written; R is upper triangular, so entry a needs rows b >= a)
+    for (int i = threadIdx.x; i < p; i += blockDim.x) {
+      cplx* zc = Z + (size_t)i * n;
+      for (int a = 0; a < n; ++a) {
+        cplx sz = mk(0.0, 0.0);
+        for (int b = a; b < n; ++b) cfma(sz, R[b * n + a], zc[b]);
+        zc[a] = sz;
+      }
     }
   }
 }
@@ -806,102 +829,89 @@ __global__ void __launch_bounds__(256) cholqr_apply_kernel(const cplx* __restric
   }
 }
 
-// Fixed-point control of the implicit midpoint stage (one thread per
-// column).  k_new = -i g (g = gF, plus (C1 Z - conj(C2) conj(Z)) / 2 when the
-// projection covered positions only: i U~^* V_r with V_r = Im(U~ Z~)).
-// For an active column:  rel = |k_new - k| / |k_new|;  converged if
-// rel < tol, stalled if not converged, rel >= the previous rel (a particle
-// at a node puts the map into a cycle of jumps and contraction steps) and
-// the smaller of the two below stall_tol (a cycle without a contracted phase
-// below that floor keeps iterating); k <- k_new; ZG <- Zeval; if still active,
-// Zeval <- Z0 + dt/2 k.  counters[0] = active columns left, counters[1] +=
-// stalled, the double at counters + 6 = the largest rel accepted by a stall
-// (atomic maximum of the bit patterns, which order like the values for
-// rel >= 0).  fixed != 0 disables the test.
-__global__ void __launch_bounds__(DTPB) dense_fp_update_kernel(
+// Fixed-point control of the implicit midpoint stage, one block per column
+// i (a wavefront; lane a takes entry a).  k_new = -i g (g = gF, plus
+// (C1 Z - conj(C2) conj(Z)) / 2 when the projection covered positions only:
+// i U~^* V_r with V_r = Im(U~ Z~)).  For an active column:
+// rel = |k_new - k| / |k_new| (squared moduli summed in entry order);
+// converged if rel < tol, stalled if not converged, rel >= the previous rel
+// (a particle at a node puts the map into a cycle of jumps and contraction
+// steps) and the smaller of the two below stall_tol (a cycle without a
+// contracted phase below that floor keeps iterating); k <- k_new;
+// ZG <- Zeval; if still active, Zeval <- Z0 + dt/2 k.  counters[0] loses one
+// per column that stops (it counts the active columns), counters[1] gains
+// the stalled ones, counters[2] becomes the launch ordinal `iter`, and the
+// double at counters + 6 is the largest rel accepted by a stall (atomic
+// maximum of the bit patterns, which order like the values for rel >= 0).
+// fixed != 0 disables the test.
+__global__ void __launch_bounds__(64) dense_fp_update_kernel(
     const cplx* __restrict__ gF, const cplx* __restrict__ C12, int n, int p,
     const cplx* __restrict__ Z0, cplx* __restrict__ Zeval, cplx* __restrict__ ZG,
     cplx* __restrict__ k, double* __restrict__ prev, int* __restrict__ active, double dt,
-    double tol, double stall_tol, int fixed, int linear_part, int* __restrict__ counters) {
-  // nothing left to iterate: a speculative launch after convergence
+    double tol, double stall_tol, int fixed, int linear_part, int iter,
+    int* __restrict__ counters) {
+  // nothing left to iterate: a speculative launch after convergence (a
+  // column still active keeps counters[0] >= 1 until its block has run)
   if (counters[0] == 0) return;
-  // LDS: C12 (2 n x n), Zeval and the new k (n x p each), then the squared
-  // moduli of the update and of the new k per entry (n x p doubles each)
-  extern __shared__ cplx sm[];
-  cplx* Cs = sm;
-  cplx* zes = Cs + 2 * n * n;
-  cplx* kns = zes + n * p;
-  double* dq = reinterpret_cast<double*>(kns + n * p);
-  double* kq = dq + n * p;
-  __shared__ int nact, nstall;
-  if (threadIdx.x == 0) {
-    nact = 0;
-    nstall = 0;
-  }
-  if (linear_part)
-    for (int t = threadIdx.x; t < 2 * n * n; t += blockDim.x) Cs[t] = C12[t];
-  for (int t = threadIdx.x; t < n * p; t += blockDim.x) zes[t] = Zeval[t];
+  const int i = blockIdx.x;
+  if (!active[i]) return;
+  __shared__ cplx ze[32];
+  __shared__ double dq[32], kq[32];
+  __shared__ int go_on;
+  const int a = threadIdx.x;
+  if (a < n) ze[a] = Zeval[(size_t)i * n + a];
   __syncthreads();
-  // one thread per entry (a, i) of an active column
-  for (int t = threadIdx.x; t < n * p; t += blockDim.x) {
-    const int a = t % n, i = t / n;
-    if (!active[i]) continue;
-    const cplx* ze = zes + i * n;
+  cplx knew = mk(0.0, 0.0);
+  if (a < n) {
+    const size_t t = (size_t)i * n + a;
     cplx g = gF[t];
     if (linear_part) {
-      cplx s = mk(0.0, 0.0);
+      cplx sl = mk(0.0, 0.0);
       for (int b = 0; b < n; ++b) {
-        cfma(s, Cs[b * n + a], ze[b]);
-        cfma(s, cscale(cconj(Cs[n * n + b * n + a]), -1.0), cconj(ze[b]));
+        cfma(sl, C12[b * n + a], ze[b]);
+        cfma(sl, cscale(cconj(C12[n * n + b * n + a]), -1.0), cconj(ze[b]));
       }
-      g = cadd(g, cscale(s, 0.5));
+      g = cadd(g, cscale(sl, 0.5));
     }
-    const cplx knew = mk(g.im, -g.re);  // -i g
+    knew = mk(g.im, -g.re);  // -i g
     const cplx d = csub(knew, k[t]);
-    dq[t] = cabs2(d);
-    kq[t] = cabs2(knew);
-    kns[t] = knew;
+    dq[a] = cabs2(d);
+    kq[a] = cabs2(knew);
     k[t] = knew;
     ZG[t] = ze[a];
   }
   __syncthreads();
-  // per column: the relative update (moduli summed in entry order)
-  for (int i = threadIdx.x; i < p; i += blockDim.x) {
-    if (!active[i]) continue;
+  if (a == 0) {
     double dn = 0.0, kn = 0.0;
-    for (int a = 0; a < n; ++a) {
-      dn += dq[i * n + a];
-      kn += kq[i * n + a];
+    for (int b = 0; b < n; ++b) {
+      dn += dq[b];
+      kn += kq[b];
     }
     bool done = false;
     if (!fixed) {
       const double rel = (kn > 0.0) ? sqrt(dn) / sqrt(kn) : sqrt(dn);
+      const double pv = prev[i];
       const bool conv = rel < tol;
-      const bool stall = !conv && rel >= prev[i] && fmin(rel, prev[i]) < stall_tol;
+      const bool stall = !conv && rel >= pv && fmin(rel, pv) < stall_tol;
       prev[i] = rel;
       done = conv || stall;
       if (stall) {
-        atomicAdd(&nstall, 1);
+        atomicAdd(&counters[1], 1);
         atomicMax(reinterpret_cast<unsigned long long*>(counters + 6),
                   (unsigned long long)__double_as_longlong(rel));
       }
     }
     if (done) {
       active[i] = 0;
-    } else {
-      atomicAdd(&nact, 1);
-      for (int a = 0; a < n; ++a) {
-        const cplx z0 = Z0[(size_t)i * n + a];
-        const cplx kk = kns[i * n + a];
-        Zeval[(size_t)i * n + a] = mk(z0.re + 0.5 * dt * kk.re, z0.im + 0.5 * dt * kk.im);
-      }
+      atomicSub(&counters[0], 1);
     }
+    atomicMax(&counters[2], iter);
+    go_on = done ? 0 : 1;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    counters[0] = nact;
-    counters[1] += nstall;
-    counters[2] += 1;
+  if (go_on && a < n) {
+    const cplx z0 = Z0[(size_t)i * n + a];
+    Zeval[(size_t)i * n + a] = mk(z0.re + 0.5 * dt * knew.re, z0.im + 0.5 * dt * knew.im);
   }
 }
 
@@ -1029,14 +1039,14 @@ static int dense_chain_threads(int n) { return (n <= 8) ? 64 : DTPB; }
 
 void launch_dense_spinv(hipStream_t s, const cplx* Z, int n, int p, double rtol, cplx* Q,
                         double* sigma2, int* flags) {
-  const size_t sh = (size_t)(n * p + 3 * n * n) * sizeof(cplx);
+  const size_t sh = (size_t)((n * p <= DENSE_Z_LDS ? n * p : 0) + 3 * n * n) * sizeof(cplx);
   ALLOW_BIG_LDS(dense_spinv_kernel);
   hipLaunchKernelGGL(dense_spinv_kernel, dim3(1), dim3(dense_chain_threads(n)), sh, s, Z, n, p,
                      rtol, Q, sigma2, flags);
 }
 void launch_dense_xfinish(hipStream_t s, const cplx* g, const cplx* Q, int n, int p, double dt,
                           cplx* k1, cplx* MP, cplx* MU) {
-  const size_t sh = (size_t)(2 * n * p) * sizeof(cplx);
+  const size_t sh = (n * p <= DENSE_Z_LDS) ? (size_t)(2 * n * p) * sizeof(cplx) : 0;
   ALLOW_BIG_LDS(dense_xfinish_kernel);
   hipLaunchKernelGGL(dense_xfinish_kernel, dim3(1), dim3(DTPB), sh, s, g, Q, n, p, dt, k1, MP,
                      MU);
@@ -1045,7 +1055,8 @@ void launch_dense_cayley(hipStream_t s, const cplx* Gram, int n, cplx* A_out, cp
                          cplx* MX, int* flags, bool chol, cplx* Z, int p) {
   // 10 n^2 for the solve; with chol, W (2 n^2), the Gram (4 n^2), T (2 n^2)
   // and Z (n p)
-  size_t sh = (size_t)((chol ? 18 : 10) * n * n + (chol && Z ? n * p : 0)) * sizeof(cplx);
+  size_t sh = (size_t)((chol ? 18 : 10) * n * n + (chol && Z && n * p <= DENSE_Z_LDS ? n * p : 0)) *
+              sizeof(cplx);
   ALLOW_BIG_LDS(dense_cayley_kernel);
   hipLaunchKernelGGL(dense_cayley_kernel, dim3(1), dim3(dense_chain_threads(n)), sh, s, Gram, n,
                      A_out, MU, MX, Z, p, (int)chol, flags);
@@ -1083,11 +1094,9 @@ void launch_cholqr_apply(hipStream_t s, const cplx* Gram, int n, cplx* U, int N,
 void launch_dense_fp_update(hipStream_t s, const cplx* gF, const cplx* C12, int n, int p,
                             const cplx* Z0, cplx* Zeval, cplx* ZG, cplx* k, double* prev,
                             int* active, double dt, double tol, double stall_tol, int fixed,
-                            int linear_part, int* counters) {
-  const size_t sh = (size_t)(2 * n * n + 2 * n * p) * sizeof(cplx) + 2 * (size_t)n * p * sizeof(double);
-  ALLOW_BIG_LDS(dense_fp_update_kernel);
-  hipLaunchKernelGGL(dense_fp_update_kernel, dim3(1), dim3(DTPB), sh, s, gF, C12, n, p, Z0, Zeval,
-                     ZG, k, prev, active, dt, tol, stall_tol, fixed, linear_part, counters);
+                            int linear_part, int iter, int* counters) {
+  hipLaunchKernelGGL(dense_fp_update_kernel, dim3(p), dim3(64), 0, s, gF, C12, n, p, Z0, Zeval,
+                     ZG, k, prev, active, dt, tol, stall_tol, fixed, linear_part, iter, counters);
 }
 void launch_dense_finish_z(hipStream_t s, const cplx* Z0, const cplx* k, int n, int p, double dt,
                            cplx* Z1) {

@@ -27,12 +27,14 @@ struct RealList {
 // gemm flags
 enum { GEMM_B_REAL = 1, GEMM_A_REAL = 2, GEMM_NO_CONJ_A = 4, GEMM_SAME = 8 };  // SAME: internal
 
-// Terms of a row-wise combination out = sum_s in_s M_s.
+// Terms of a row-wise combination out = sum_s in_s M_s (in_s: N x k_s,
+// M_s: k_s x m column-major with leading dimension ld[s], k_s when 0).
 struct RowTerms {
   const cplx* in[4];
   const cplx* M[4];
   int k[4];
   int count;
+  int ld[4];
 };
 
 // register width of the fused kernels: a count >= n, exact for the small
@@ -186,7 +188,7 @@ void launch_cholqr_apply(hipStream_t s, const cplx* Gram, int n, cplx* U, int N,
 void launch_dense_fp_update(hipStream_t s, const cplx* gF, const cplx* C12, int n, int p,
                             const cplx* Z0, cplx* Zeval, cplx* ZG, cplx* k, double* prev,
                             int* active, double dt, double tol, double stall_tol, int fixed,
-                            int linear_part, int* counters);
+                            int linear_part, int iter, int* counters);
 void launch_dense_finish_z(hipStream_t s, const cplx* Z0, const cplx* k, int n, int p, double dt,
                            cplx* Z1);
 void launch_fp_init(hipStream_t s, double* prev, int* active, int* counters, int p);
@@ -225,3 +227,17 @@ void launch_fold_status(hipStream_t s, int* status);
 void launch_gram_block_real(hipStream_t s, const double* Ynew, const double* const* slots,
                             int nslots, int psub, int N, int r0, int nkb_cap, double* part,
                             double* S, const int* stop = nullptr);
+
+// ensemble_kernels.hip (large ensembles)
+// G[a0.., b0..] = blk (ac x bc) and its conjugate transpose at [b0.., a0..]
+void launch_scatter_block(hipStream_t s, const cplx* blk, int ac, int bc, cplx* G, int p, int a0,
+                          int b0);
+// W = A V (A p x p, V p x m, ld p)
+void launch_herm_mm(hipStream_t s, const cplx* A, const cplx* V, int p, int m, cplx* W);
+// orthonormalise the m <= 64 columns of W (p x m, ld p) in place
+void launch_cgs2(hipStream_t s, cplx* W, int p, int m);
+// initial ensemble of a family (0 Landau, 1 two-stream) from eta (device,
+// p x 4: alpha, k, v0, sigma) and shared uniforms ux, uv (device [N]):
+// X, V (N x p, nullable) and/or C = X + i V (nullable)
+void launch_load_family(hipStream_t s, int family, int N, int p, const double* eta,
+                        const double* ux, const double* uv, double* X, double* V, cplx* C);

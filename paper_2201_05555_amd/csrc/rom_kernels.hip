@@ -260,19 +260,23 @@ __global__ void __launch_bounds__(256) reduce_partials_kernel(const cplx* __rest
 // One thread per row; safe in place (out may alias an input).
 // ---------------------------------------------------------------------------
 template <int MC>
-__global__ void __launch_bounds__(256) rowgemm_kernel(RowTerms T, int N, int m, cplx* out) {
+__global__ void __launch_bounds__(256) rowgemm_kernel(RowTerms T, int N, int m, cplx* out,
+                                                      int accum) {
   extern __shared__ cplx Ms[];
   int off = 0;
   for (int s = 0; s < T.count; ++s) {
-    for (int t = threadIdx.x; t < T.k[s] * m; t += blockDim.x) Ms[off + t] = T.M[s][t];
-    off += T.k[s] * m;
+    // M_s is k_s x m with leading dimension ld_s (k_s when ld_s is 0)
+    const int ks = T.k[s], ld = T.ld[s] ? T.ld[s] : ks;
+    for (int t = threadIdx.x; t < ks * m; t += blockDim.x)
+      Ms[off + t] = T.M[s][(size_t)(t / ks) * ld + t % ks];
+    off += ks * m;
   }
   __syncthreads();
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= N) return;
   cplx acc[MC];
 #pragma unroll
-  for (int o = 0; o < MC; ++o) acc[o] = mk(0.0, 0.0);
+  for (int o = 0; o < MC; ++o) acc[o] = (accum && o < m) ? out[(size_t)o * N + l] : mk(0.0, 0.0);
   off = 0;
   for (int s = 0; s < T.count; ++s) {
     const cplx* in = T.in[s];
@@ -632,38 +636,36 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx,
     const double* __restrict__ factor, const double* __restrict__ e, double qm,
     const cplx* __restrict__ Q, const cplx* __restrict__ MU, const cplx* __restrict__ gp,
-    double h, cplx* __restrict__ out) {
+    double h, cplx* __restrict__ out, int pc) {
   constexpr int ILP = (NC <= 8) ? 4 : 2;
   extern __shared__ double smem[];
-  cplx* Zs = reinterpret_cast<cplx*>(smem);  // [p][NC], zero beyond n
-  cplx* Qs = Zs + (size_t)p * NC;            // [p][NC]: -i h Q[c][k], zero beyond n
-  cplx* Ms = Qs + (size_t)p * NC;            // [NC][NC]: MU[j][k] at Ms[j * NC + k]
-  double* fs = reinterpret_cast<double*>(Ms + NC * NC);  // [p]
-  double* et = fs + p;                       // [p][Nx] (ET_LDS)
+  // parameters are staged pc at a time (all of them when p <= pc)
+  cplx* Zs = reinterpret_cast<cplx*>(smem);  // [pc][NC], zero beyond n
+  cplx* Qs = Zs + (size_t)pc * NC;           // [pc][NC]: -i h Q[c][k], zero beyond n
+  cplx* Ms = Qs + (size_t)pc * NC;           // [NC][NC]: MU[j][k] at Ms[j * NC + k]
+  double* fs = reinterpret_cast<double*>(Ms + NC * NC);  // [pc]
+  double* et = fs + pc;                      // [pc][Nx] (ET_LDS)
   const int tid = threadIdx.x;
-  for (int t = tid; t < p * NC; t += 256) {
-    const int c = t / NC, k = t % NC;
-    Zs[t] = (k < n) ? Z[(size_t)c * n + k] : mk(0.0, 0.0);
-    const cplx qv = (k < n) ? Q[(size_t)k * p + c] : mk(0.0, 0.0);
-    Qs[t] = mk(h * qv.im, -h * qv.re);
-  }
   if (gp) {
-    __syncthreads();  // Qs complete
-    // Ms[j][k] = -sum_c g[c][j] Qs[c][k]; lanes 8e..8e+7 split the sum over c
+    // Ms[j][k] = -sum_c g[c][j] (-i h Q[c][k]); lanes 8e..8e+7 split the sum
+    // over c (eight loads of g and Q in flight per round)
     const int e8 = tid >> 3, part8 = tid & 7;
     for (int e0 = 0; e0 < NC * NC; e0 += 32) {
       const int t = e0 + e8;
       const int j = t / NC, k = t % NC;
       cplx sacc = mk(0.0, 0.0);
       if (t < NC * NC && j < n && k < n) {
-        // eight loads of g in flight per round (one round for p <= 64)
         for (int c0 = part8; c0 < p; c0 += 64) {
-          cplx gv[8];
+          cplx gv[8], qv[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) gv[u] = gp[(size_t)min(c0 + 8 * u, p - 1) * n + j];
+          for (int u = 0; u < 8; ++u) {
+            const int c = min(c0 + 8 * u, p - 1);
+            gv[u] = gp[(size_t)c * n + j];
+            qv[u] = Q[(size_t)k * p + c];
+          }
 #pragma unroll
           for (int u = 0; u < 8; ++u)
-            if (c0 + 8 * u < p) cfma(sacc, gv[u], Qs[(c0 + 8 * u) * NC + k]);
+            if (c0 + 8 * u < p) cfma(sacc, gv[u], mk(h * qv[u].im, -h * qv[u].re));
         }
       }
 #pragma unroll
@@ -678,23 +680,6 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
     for (int t = tid; t < NC * NC; t += 256) {
       const int j = t / NC, k = t % NC;
       Ms[t] = (j < n && k < n) ? MU[(size_t)k * n + j] : mk(0.0, 0.0);
-    }
-  }
-  for (int t = tid; t < p; t += 256) fs[t] = factor[t];
-  if (ET_LDS) {
-    const int tot = p * Nx;
-    for (int t0 = 0; t0 < tot; t0 += 8 * 256) {
-      double v[8];
-#pragma unroll
-      for (int u8 = 0; u8 < 8; ++u8) {
-        const int t = t0 + u8 * 256 + tid;
-        v[u8] = (t < tot) ? e[t] : 0.0;
-      }
-#pragma unroll
-      for (int u8 = 0; u8 < 8; ++u8) {
-        const int t = t0 + u8 * 256 + tid;
-        if (t < tot) et[t] = qm * v[u8];
-      }
     }
   }
   const int l = blockIdx.x * 256 + tid;
@@ -716,47 +701,76 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
     __builtin_amdgcn_sched_barrier(0);
   }
   // then G~ (-i h Q), ILP parameters at a time, accumulated in parameter order
-  for (int c0 = 0; c0 < p; c0 += ILP) {
-    double x0[ILP], x1[ILP], v0[ILP], v1[ILP];
+  for (int cb = 0; cb < p; cb += pc) {
+    const int np = min(pc, p - cb);
+    if (cb > 0) __syncthreads();  // the previous chunk is done with the tables
+    for (int t = tid; t < np * NC; t += 256) {
+      const int c = t / NC, k = t % NC;
+      Zs[t] = (k < n) ? Z[(size_t)(cb + c) * n + k] : mk(0.0, 0.0);
+      const cplx qv = (k < n) ? Q[(size_t)k * p + cb + c] : mk(0.0, 0.0);
+      Qs[t] = mk(h * qv.im, -h * qv.re);
+    }
+    for (int t = tid; t < np; t += 256) fs[t] = factor[cb + t];
+    if (ET_LDS) {
+      const int tot = np * Nx;
+      const double* ec = e + (size_t)cb * Nx;
+      for (int t0 = 0; t0 < tot; t0 += 8 * 256) {
+        double v[8];
 #pragma unroll
-    for (int q = 0; q < ILP; ++q) {
-      const cplx* zc = Zs + min(c0 + q, p - 1) * NC;
-      x0[q] = 0.0;
-      x1[q] = 0.0;
-      v0[q] = 0.0;
-      v1[q] = 0.0;
+        for (int u8 = 0; u8 < 8; ++u8) {
+          const int t = t0 + u8 * 256 + tid;
+          v[u8] = (t < tot) ? ec[t] : 0.0;
+        }
 #pragma unroll
-      for (int k = 0; k < NC; k += 2) {
-        const cplx za = zc[k];
-        x0[q] = fma(u[k].re, za.re, x0[q]);
-        x0[q] = fma(-u[k].im, za.im, x0[q]);
-        v0[q] = fma(u[k].re, za.im, v0[q]);
-        v0[q] = fma(u[k].im, za.re, v0[q]);
-        if (k + 1 < NC) {
-          const cplx zb = zc[k + 1];
-          x1[q] = fma(u[k + 1].re, zb.re, x1[q]);
-          x1[q] = fma(-u[k + 1].im, zb.im, x1[q]);
-          v1[q] = fma(u[k + 1].re, zb.im, v1[q]);
-          v1[q] = fma(u[k + 1].im, zb.re, v1[q]);
+        for (int u8 = 0; u8 < 8; ++u8) {
+          const int t = t0 + u8 * 256 + tid;
+          if (t < tot) et[t] = qm * v[u8];
         }
       }
     }
-    double F[ILP];
+    __syncthreads();
+    for (int c0 = 0; c0 < np; c0 += ILP) {
+      double x0[ILP], x1[ILP], v0[ILP], v1[ILP];
 #pragma unroll
-    for (int q = 0; q < ILP; ++q) {
-      const int c = min(c0 + q, p - 1);
-      int j;
-      double th;
-      cell_of(x0[q] + x1[q], fs[c], Nx, j, th);
-      F[q] = ET_LDS ? et[c * Nx + j] : qm * e[(size_t)c * Nx + j];
-    }
+      for (int q = 0; q < ILP; ++q) {
+        const cplx* zc = Zs + min(c0 + q, np - 1) * NC;
+        x0[q] = 0.0;
+        x1[q] = 0.0;
+        v0[q] = 0.0;
+        v1[q] = 0.0;
 #pragma unroll
-    for (int q = 0; q < ILP; ++q) {
-      if (c0 + q < p) {
-        const cplx gv = mk(F[q], v0[q] + v1[q]);
-        const cplx* qc = Qs + (c0 + q) * NC;
+        for (int k = 0; k < NC; k += 2) {
+          const cplx za = zc[k];
+          x0[q] = fma(u[k].re, za.re, x0[q]);
+          x0[q] = fma(-u[k].im, za.im, x0[q]);
+          v0[q] = fma(u[k].re, za.im, v0[q]);
+          v0[q] = fma(u[k].im, za.re, v0[q]);
+          if (k + 1 < NC) {
+            const cplx zb = zc[k + 1];
+            x1[q] = fma(u[k + 1].re, zb.re, x1[q]);
+            x1[q] = fma(-u[k + 1].im, zb.im, x1[q]);
+            v1[q] = fma(u[k + 1].re, zb.im, v1[q]);
+            v1[q] = fma(u[k + 1].im, zb.re, v1[q]);
+          }
+        }
+      }
+      double F[ILP];
 #pragma unroll
-        for (int k = 0; k < NC; ++k) cfma(acc[k], gv, qc[k]);
+      for (int q = 0; q < ILP; ++q) {
+        const int c = min(c0 + q, np - 1);
+        int j;
+        double th;
+        cell_of(x0[q] + x1[q], fs[c], Nx, j, th);
+        F[q] = ET_LDS ? et[c * Nx + j] : qm * e[(size_t)(cb + c) * Nx + j];
+      }
+#pragma unroll
+      for (int q = 0; q < ILP; ++q) {
+        if (c0 + q < np) {
+          const cplx gv = mk(F[q], v0[q] + v1[q]);
+          const cplx* qc = Qs + (c0 + q) * NC;
+#pragma unroll
+          for (int k = 0; k < NC; ++k) cfma(acc[k], gv, qc[k]);
+        }
       }
     }
   }
@@ -1343,15 +1357,27 @@ void launch_gather_xi(hipStream_t s, const cplx* U, int N, int n, const cplx* Z,
                       const double* factor, const double* e, double qm, const cplx* Q,
                       const cplx* MU, double h, cplx* out, const cplx* g) {
   const int nc = fused_nc(n);
-  const size_t base = (size_t)(2 * p * nc + nc * nc) * sizeof(cplx) + (size_t)p * sizeof(double);
-  const size_t et_bytes = (size_t)p * Nx * sizeof(double);
-  const bool et_lds = base + et_bytes <= 76 * 1024;
-  const size_t sh = base + (et_lds ? et_bytes : 0);
+  // LDS of a chunk of pc parameters: coefficients, -i h Q, factors (+ field rows)
+  auto base = [&](int pc) {
+    return (size_t)(2 * pc * nc + nc * nc) * sizeof(cplx) + (size_t)pc * sizeof(double);
+  };
+  const size_t budget = 76 * 1024;
+  int pc = p;
+  bool et_lds = base(p) + (size_t)p * Nx * sizeof(double) <= budget;
+  if (!et_lds && base(p) > budget) {
+    // more parameters than the tables hold: chunks of pc, field rows in LDS
+    // when a chunk of at least 64 parameters still fits with them
+    pc = 64;
+    et_lds = base(pc) + (size_t)pc * Nx * sizeof(double) <= budget;
+    if (!et_lds)
+      while (2 * pc <= p && base(2 * pc) <= budget) pc *= 2;
+  }
+  const size_t sh = base(pc) + (et_lds ? (size_t)pc * Nx * sizeof(double) : 0);
   dim3 grid((N + 255) / 256);
 #define GXK(NCV, ETV)                                                                          \
   ALLOW_BIG_LDS((gather_xi_kernel<NCV, ETV>));                                               \
   hipLaunchKernelGGL((gather_xi_kernel<NCV, ETV>), grid, dim3(256), sh, s, U, N, n, Z, p, Nx,  \
-                     factor, e, qm, Q, MU, g, h, out)
+                     factor, e, qm, Q, MU, g, h, out, pc)
   if (et_lds) {
     switch (nc) {
       case 4: GXK(4, true); break;
@@ -1505,7 +1531,7 @@ bool launch_rowgemm_gram(hipStream_t s, const RowTerms& T, int N, int m, cplx* o
   return true;
 }
 
-void launch_rowgemm(hipStream_t s, const RowTerms& T, int N, int m, cplx* out) {
+static void rowgemm_launch(hipStream_t s, const RowTerms& T, int N, int m, cplx* out, int accum) {
   size_t sh = 0;
   for (int q = 0; q < T.count; ++q) sh += (size_t)T.k[q] * m * sizeof(cplx);
   dim3 grid((N + 255) / 256);
@@ -1515,10 +1541,42 @@ void launch_rowgemm(hipStream_t s, const RowTerms& T, int N, int m, cplx* out) {
   ALLOW_BIG_LDS(rowgemm_kernel<16>);
   ALLOW_BIG_LDS(rowgemm_kernel<32>);
   switch (mc) {
-    case 4: hipLaunchKernelGGL(rowgemm_kernel<4>, grid, dim3(256), sh, s, T, N, m, out); break;
-    case 8: hipLaunchKernelGGL(rowgemm_kernel<8>, grid, dim3(256), sh, s, T, N, m, out); break;
-    case 16: hipLaunchKernelGGL(rowgemm_kernel<16>, grid, dim3(256), sh, s, T, N, m, out); break;
-    default: hipLaunchKernelGGL(rowgemm_kernel<32>, grid, dim3(256), sh, s, T, N, m, out); break;
+    case 4: hipLaunchKernelGGL(rowgemm_kernel<4>, grid, dim3(256), sh, s, T, N, m, out, accum); break;
+    case 8: hipLaunchKernelGGL(rowgemm_kernel<8>, grid, dim3(256), sh, s, T, N, m, out, accum); break;
+    case 16: hipLaunchKernelGGL(rowgemm_kernel<16>, grid, dim3(256), sh, s, T, N, m, out, accum); break;
+    default: hipLaunchKernelGGL(rowgemm_kernel<32>, grid, dim3(256), sh, s, T, N, m, out, accum); break;
+  }
+}
+
+// The M matrices of all terms are staged in LDS.  When they do not fit
+// (a wide first input, as G~ Q over many parameters), the terms are taken
+// one at a time and a wide term in slices of its columns, each launch
+// adding to the output (a slice of M_q is a row range, read in place with
+// its leading dimension).
+void launch_rowgemm(hipStream_t s, const RowTerms& T, int N, int m, cplx* out) {
+  const size_t lds_cap = 144 * 1024;
+  size_t sh = 0;
+  for (int q = 0; q < T.count; ++q) sh += (size_t)T.k[q] * m * sizeof(cplx);
+  if (sh <= lds_cap) {
+    rowgemm_launch(s, T, N, m, out, 0);
+    return;
+  }
+  const int kmax = (int)(lds_cap / ((size_t)m * sizeof(cplx)));
+  int accum = 0;
+  for (int q = 0; q < T.count; ++q) {
+    for (int k0 = 0; k0 < T.k[q]; k0 += kmax) {
+      const int kc = std::min(kmax, T.k[q] - k0);
+      RowTerms U{};
+      U.count = 1;
+      U.in[0] = T.in[q] + (size_t)k0 * N;
+      U.k[0] = kc;
+      U.M[0] = T.M[q];
+      // rows k0 .. k0 + kc of M_q, read in place with its leading dimension
+      U.M[0] = T.M[q] + k0;
+      U.ld[0] = T.ld[q] ? T.ld[q] : T.k[q];
+      rowgemm_launch(s, U, N, m, out, accum);
+      accum = 1;
+    }
   }
 }
 
