@@ -1,7 +1,10 @@
 """Benchmark: particle-parameter steps per second of the reduced model (ROM)
 and of the full-order PIC model (FOM) on one MI355X, on a synthetic
-two-stream ensemble (default: N = 100,000 particles, p = 64 parameters,
-Nx = 128 cells, dt = 0.05, reduced rank 2n from 10 with cap 60, DEIM).
+two-stream ensemble (default: the large ensemble N = 4,000,000 particles,
+p = 1024 parameters, Nx = 512 cells, dt = 0.05, reduced rank 2n from 16 with
+cap 60, DEIM with d = 2n; `--workload twostream_deim` runs N = 100,000,
+p = 64, Nx = 128, 2n from 10).  The initial ensemble is formed on the device
+from its parameters and shared uniforms.
 
 Prints ONE JSON line.  `value` is the ROM throughput N * p * steps / time of
 the timed steps (inputs resident in HBM); by default two warm-up steps and 25
@@ -39,8 +42,12 @@ SINGLE_KERNEL = {
 # HBM bytes per launch of the deposit kernel, measured with two counter
 # passes (FETCH_SIZE, WRITE_SIZE) calibrated on a plain device copy; valid
 # only for the kernel source it was taken on
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles",
-                               "deposit_rom_kernel_twostream_deim_N1e5_p64_hbm_traffic.md")
+TRAFFIC_PROFILE = {
+    "twostream_deim": os.path.join(ROOT, "profiles",
+                                   "deposit_rom_kernel_twostream_deim_N1e5_p64_hbm_traffic.md"),
+    "twostream_large": os.path.join(ROOT, "profiles",
+                                    "deposit_rom_kernel_twostream_large_N4e6_p1024_hbm_traffic.md"),
+}
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2201_05555_amd", "csrc", "pic_kernels.hip")
 
 
@@ -49,7 +56,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=25)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="twostream_deim")
+    ap.add_argument("--workload", default="twostream_large")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-matched", action="store_true", help="skip the matched-error pass")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -80,14 +87,14 @@ def roofline_of(ms, flops, nbytes, launches):
             "frac": ach / (PEAK_FP64 / 1e12), "traffic": None, **base}
 
 
-def measured_traffic():
+def measured_traffic(workload):
     """Counter-measured HBM bytes per deposit launch, or None when the
     profile is missing or the kernel source has changed since it was taken."""
     import hashlib
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(TRAFFIC_PROFILE[workload]).read()
         sha = hashlib.sha256(open(TRAFFIC_SOURCE, "rb").read()).hexdigest()
-    except OSError:
+    except (OSError, KeyError):
         return None
     val = src = None
     for line in text.splitlines():
@@ -100,14 +107,16 @@ def measured_traffic():
 
 def _oracle_rate(w, ens, seconds, threads):
     """The oracle's reduced step (+ rank policy) on its first p_sub
-    parameters, same N, rank and time step, with `threads` BLAS threads."""
+    parameters and first N_sub particles, same rank and time step, with
+    `threads` BLAS threads."""
     import numpy as np
     from oracle import rom
     from threadpoolctl import threadpool_limits
-    p_sub = min(8, w["p"])
-    X0 = np.asfortranarray(ens["X0"][:, :p_sub])
-    V0 = np.asfortranarray(ens["V0"][:, :p_sub])
-    cfg = rom.RomConfig(N=w["N"], p=p_sub, Nx=w["Nx"], two_n=w["two_n"], dt=w["dt"],
+    p_sub = min(8, w["p"], ens["X0"].shape[1])
+    N_sub = min(w["N"], ens["X0"].shape[0])
+    X0 = np.asfortranarray(ens["X0"][:N_sub, :p_sub])
+    V0 = np.asfortranarray(ens["V0"][:N_sub, :p_sub])
+    cfg = rom.RomConfig(N=N_sub, p=p_sub, Nx=w["Nx"], two_n=w["two_n"], dt=w["dt"],
                         fp_tol=1e-9, two_n_max=w["two_n_max"],
                         projection=w.get("projection", "galerkin"),
                         deim_window=w.get("deim_window", 3),
@@ -124,56 +133,79 @@ def _oracle_rate(w, ens, seconds, threads):
             el = time.perf_counter() - t0
             if el > seconds or steps >= 50:
                 break
-    return w["N"] * p_sub * steps / el, steps, el, p_sub, st.U.shape[1]
+    return N_sub * p_sub * steps / el, steps, el, p_sub, st.U.shape[1], N_sub
 
 
 def cpu_baseline(w, ens, seconds):
     """The oracle (not tuned) on the host: one core, then every core."""
     ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    v1, s1, e1, p_sub, r1 = _oracle_rate(w, ens, seconds, 1)
-    va, sa, ea, _, ra = _oracle_rate(w, ens, seconds, ncpu)
+    v1, s1, e1, p_sub, r1, N_sub = _oracle_rate(w, ens, seconds, 1)
+    va, sa, ea, _, ra, _ = _oracle_rate(w, ens, seconds, ncpu)
     return {"value": va, "unit": "particle-param-steps/s", "cores": ncpu, "kind": "oracle",
             "single_core_value": v1,
             "sample": f"oracle prk_step (+ rank policy) on the first {p_sub} of {w['p']} "
-                      f"parameters, N={w['N']}, 2n={w['two_n']}->{ra}, "
+                      f"parameters and the first {N_sub} of {w['N']} particles, "
+                      f"2n={w['two_n']}->{ra}, "
                       f"{w.get('projection', 'galerkin')}: {sa} steps in {ea:.1f} s on {ncpu} "
-                      f"threads, {s1} steps in {e1:.1f} s on 1 thread; the ROM's work per "
-                      f"step is about linear in p, so the rate is per particle-parameter"}
+                      f"threads, {s1} steps in {e1:.1f} s on 1 thread; the reduced step's "
+                      f"work is about linear in N and in p, so the rate is per "
+                      f"particle-parameter"}
 
 
-def matched_error(binding, torch, w, ens, X0, V0, cfg, steps):
+def _frob_rel_err(torch, A, B):
+    """||A - B||_F / ||A||_F for (p, N) device arrays, a parameter at a time
+    (no N x p temporary)."""
+    num = den = 0.0
+    for i in range(A.shape[0]):
+        num += float(torch.sum((A[i] - B[i]) ** 2))
+        den += float(torch.sum(A[i] ** 2))
+    return (num / den) ** 0.5
+
+
+def matched_error(binding, torch, w, src, cfg, steps):
     """ROM and FOM over the same steps from t = 0 on the same ensemble:
     eq. relative_errors at the last step, the complex-SVD target error of
     eq. relative_errors_complex_SVD (the truncated complex SVD of the FOM
     state at that step, at the ROM's final rank), and the largest relative
-    electric-energy error max_{t, i} |E_rom - E_fom| / max_t E_fom."""
+    electric-energy error max_{t, i} |E_rom - E_fom| / max_t E_fom.  The
+    models run one after the other (the FOM state of a large ensemble and
+    the reduced model's workspace are each tens of GB)."""
     import numpy as np
     N, p, Nx = w["N"], w["p"], w["Nx"]
-    rom_h = binding.Rom(cfg, ens["L"], X0, V0)
-    fom_h = binding.Fom(N, p, Nx, w["dt"], ens["L"], X0, V0)
-    E_r, E_f = [], []
+    fom_h = binding.Fom(N, p, Nx, w["dt"], None, None, None, **src)
+    E_f = []
+    for _ in range(steps):
+        fom_h.step(1)
+        E_f.append(fom_h.diagnostics()[0].cpu().numpy())
+    Xf, Vf = fom_h.get_state()
+    fom_h.close()
+    del fom_h
+    torch.cuda.empty_cache()
+    rom_h = binding.Rom(cfg, None, None, None, **src)
+    E_r = []
     for _ in range(steps):
         rom_h.step(1)
-        fom_h.step(1)
         E_r.append(rom_h.diagnostics()[0].cpu().numpy())
-        E_f.append(fom_h.diagnostics()[0].cpu().numpy())
     E_r, E_f = np.array(E_r), np.array(E_f)
     e_rel_E = float(np.max(np.abs(E_r - E_f) / np.maximum(np.max(np.abs(E_f), axis=0), 1e-300)))
     Xr, Vr = rom_h.reconstruct()
-    Xf, Vf = fom_h.get_state()
-    ex = float(torch.linalg.norm(Xf - Xr) / torch.linalg.norm(Xf))
-    ev = float(torch.linalg.norm(Vf - Vr) / torch.linalg.norm(Vf))
     two_n = rom_h.two_n
     rom_h.close()
+    del rom_h
+    ex = _frob_rel_err(torch, Xf, Xr)
+    ev = _frob_rel_err(torch, Vf, Vr)
     del Xr, Vr
+    torch.cuda.empty_cache()
     # target: the truncated complex SVD of the FOM state (rom_init computes it)
     tcfg = binding.make_config(N, p, Nx, two_n, dt=w["dt"])
-    t_h = binding.Rom(tcfg, ens["L"], Xf, Vf)
+    t_h = binding.Rom(tcfg, src["params"]["L"], Xf, Vf)
     Xt, Vt = t_h.reconstruct()
-    tx = float(torch.linalg.norm(Xf - Xt) / torch.linalg.norm(Xf))
-    tv = float(torch.linalg.norm(Vf - Vt) / torch.linalg.norm(Vf))
     t_h.close()
-    fom_h.close()
+    del t_h
+    tx = _frob_rel_err(torch, Xf, Xt)
+    tv = _frob_rel_err(torch, Vf, Vt)
+    del Xt, Vt, Xf, Vf
+    torch.cuda.empty_cache()
     return {"steps_from_t0": steps, "eps_rel_X": ex, "eps_rel_V": ev,
             "target_eps_rel_X": tx, "target_eps_rel_V": tv, "rank_2n": two_n,
             "max_rel_energy_error": e_rel_E,
@@ -192,7 +224,8 @@ def main():
     import numpy as np
     import torch
     from paper_2201_05555_amd import binding
-    from workloads import make_ensemble, workload
+    from workloads import workload
+    from workloads.ensembles import draw_parameters, load_particles, philox_uniforms
 
     torch.cuda.set_device(0)
     if a.calib_copy_mib:
@@ -205,10 +238,12 @@ def main():
 
     w = workload(a.workload)
     N, p, Nx = w["N"], w["p"], w["Nx"]
-    ens = make_ensemble(w)
-    X0 = binding._dev(ens["X0"])
-    V0 = binding._dev(ens["V0"])
-    torch.cuda.synchronize()
+    # the ensemble: parameters and shared uniforms drawn on the host, the
+    # N x p initial states formed on the device (rom_init_family,
+    # fom_init_family)
+    params = draw_parameters(w)
+    ux, uv = philox_uniforms(1000 * w["number"] + 2, N)
+    src = dict(family=w["family"], params=params, ux=ux, uv=uv)
 
     # ---------------- reduced model ----------------
     proj = w.get("projection", "galerkin")
@@ -216,7 +251,9 @@ def main():
     cfg = binding.make_config(N, p, Nx, w["two_n"], two_n_max=w["two_n_max"], dt=w["dt"],
                               projection=proj, deim_window=w.get("deim_window", 3), fp_tol=1e-9,
                               rank_auto=rank_auto, rank_tol_up=1e-2, rank_tol_down=1e-8)
-    rom_h = binding.Rom(cfg, ens["L"], X0, V0)
+    t_init = time.perf_counter()
+    rom_h = binding.Rom(cfg, None, None, None, **src)
+    t_init = time.perf_counter() - t_init
     for _ in range(a.warmup):
         rom_h.step(1)
     torch.cuda.synchronize()
@@ -257,9 +294,11 @@ def main():
         fams[fam] = dict(ms=ms, launches=n, flops=fl, bytes=by)
     binding.set_timing(False)
     rom_h.close()
+    del rom_h
+    torch.cuda.empty_cache()
 
     # ---------------- full-order model ----------------
-    fom_h = binding.Fom(N, p, Nx, w["dt"], ens["L"], X0, V0)
+    fom_h = binding.Fom(N, p, Nx, w["dt"], None, None, None, **src)
     fom_h.step(a.warmup)
     torch.cuda.synchronize()
     binding.set_timing(True)
@@ -273,6 +312,8 @@ def main():
     fl_push, by_push = binding.kernel_work("fom_push")
     binding.set_timing(False)
     fom_h.close()
+    del fom_h
+    torch.cuda.empty_cache()
 
     pp = N * p
     rom_rate = pp * a.steps / t_rom
@@ -287,7 +328,7 @@ def main():
         roof["kernel"] = SINGLE_KERNEL[dom]
         roof["ms_per_step"] = d["ms"] / a.steps
         if dom == "deposit":
-            t = measured_traffic()
+            t = measured_traffic(a.workload)
             if t is not None:
                 roof["traffic"] = t
                 roof["traffic_over_algorithmic"] = t / roof["algorithmic_bytes_per_launch"]
@@ -339,11 +380,16 @@ def main():
         "kernel_families_ms_per_step": {f: fams[f]["ms"] / a.steps for f in fams},
         "ms_per_step_with_events": 1e3 * t_rom_ev / a.steps,
     }
+    out["config"]["init_s"] = t_init
     if not a.no_matched:
-        out["matched_error"] = matched_error(binding, torch, w, ens, X0, V0, cfg,
-                                             a.warmup + a.steps)
+        out["matched_error"] = matched_error(binding, torch, w, src, cfg, a.warmup + a.steps)
         out["matched_error"]["rom_over_fom_at_this_error"] = rom_rate / fom_rate
     if not a.no_cpu:
+        # the oracle's sample: the first 8 parameters and 1e5 particles
+        ns = min(N, 100_000)
+        sub = {k: v[:8] for k, v in params.items()}
+        Xs, Vs = load_particles(sub, ux[:ns], uv[:ns], w["family"])
+        ens = dict(X0=Xs, V0=Vs, L=sub["L"])
         out["cpu_baseline"] = cpu_baseline(w, ens, a.cpu_seconds)
     print(json.dumps(out), flush=True)
 

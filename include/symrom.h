@@ -101,6 +101,10 @@ typedef struct {
                           /* stagnation rule in the last step (0 if none)     */
   int32_t stalled_total;  /* stagnation acceptances summed over the call      */
   int32_t shrunk;         /* pairs dropped by the automatic shrink, last step */
+  double worst_rel;       /* on ENOCONV: the largest last relative update of  */
+                          /* the columns still iterating (else 0)             */
+  int32_t unconverged;    /* on ENOCONV: the number of those columns          */
+  int32_t reserved;
 } symrom_step_info;
 
 typedef struct symrom_rom symrom_rom;

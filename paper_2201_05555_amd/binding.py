@@ -50,7 +50,8 @@ class StepInfo(ctypes.Structure):
         ("deim_active", ctypes.c_int32), ("rank_indicator", ctypes.c_double),
         ("iters_total", ctypes.c_int32), ("deim_steps", ctypes.c_int32),
         ("stall_rel", ctypes.c_double), ("stalled_total", ctypes.c_int32),
-        ("shrunk", ctypes.c_int32),
+        ("shrunk", ctypes.c_int32), ("worst_rel", ctypes.c_double),
+        ("unconverged", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -191,7 +192,8 @@ def _info_dict(info):
     return dict(iters=info.iters, stalled=info.stalled, two_n=info.two_n,
                 deim_active=info.deim_active, rank_indicator=info.rank_indicator,
                 iters_total=info.iters_total, deim_steps=info.deim_steps,
-                stall_rel=info.stall_rel, stalled_total=info.stalled_total, shrunk=info.shrunk)
+                stall_rel=info.stall_rel, stalled_total=info.stalled_total, shrunk=info.shrunk,
+                worst_rel=info.worst_rel, unconverged=info.unconverged)
 
 
 def _dev1(x):

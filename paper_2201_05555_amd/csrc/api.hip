@@ -1208,7 +1208,22 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   std::memcpy(&r.last.stall_rel, r.hstat + 10, sizeof(double));
   r.last.deim_active = deim ? 1 : 0;
   r.last.shrunk = 0;
+  r.last.unconverged = 0;
+  r.last.worst_rel = 0.0;
   if (fixed == 0 && hc[0] > 0) {
+    // report the columns left and their last relative update
+    {
+      std::vector<int> act(p);
+      std::vector<double> pv(p);
+      if (hipMemcpy(act.data(), r.active, p * sizeof(int), hipMemcpyDeviceToHost) == hipSuccess &&
+          hipMemcpy(pv.data(), r.prev, p * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess) {
+        for (int i = 0; i < p; ++i)
+          if (act[i]) {
+            r.last.unconverged++;
+            r.last.worst_rel = std::max(r.last.worst_rel, pv[i]);
+          }
+      }
+    }
     // the state, the DEIM snapshot window included, stays as it was: the
     // snapshot of this step (counted in win_count whether it was taken now
     // or ahead of the step, and written into the slot of the oldest one,

@@ -29,10 +29,11 @@ WORKLOADS = {
         ranges=dict(alpha=(1e-3, 1e-2), v0=(2.0, 3.0), sigma=(0.1, 0.5)),
         k=0.2,
     ),
-    # very large two-stream ensemble
+    # very large two-stream ensemble, Galerkin projection (the library's
+    # rank cap is 2n = 60)
     "twostream_large": dict(
         number=5, family="twostream", N=4_000_000, p=1024, Nx=512, steps=2000,
-        dt=0.05, two_n=16, two_n_max=128, projection="galerkin",
+        dt=0.05, two_n=16, two_n_max=60, projection="galerkin", deim_window=3,
         ranges=dict(alpha=(1e-3, 1e-2), v0=(2.0, 3.0), sigma=(0.1, 0.5)),
         k=0.2,
     ),
