@@ -60,6 +60,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-matched", action="store_true", help="skip the matched-error pass")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving mix")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-step-scale", type=float, default=0.25)
+    ap.add_argument("--serve-gap", type=float, default=1.0, help="mean inter-arrival (s)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     return ap.parse_args()
@@ -213,6 +217,62 @@ def matched_error(binding, torch, w, src, cfg, steps):
                           "at the last step; target = truncated complex SVD of the FOM state; "
                           "energy error max over steps and parameters of |E_rom - E_fom| / "
                           "max_t E_fom"}
+
+
+def serve_bench(binding, torch, n_req, step_scale, slots, pool_gb, mean_gap_s, seed=4001):
+    """A serving mix after the request recipe of the serving configuration:
+    Poisson arrivals; each request a Landau or two-stream ensemble (1/2 each,
+    eta drawn in that family's box), p uniform on 1..128, N in {1e5, 1e6},
+    initial rank 2n in {8, 16, 32, 60} (60: the library's cap, in place of
+    64), the step count uniform on 200..1000 times step_scale, Galerkin,
+    rank adaptation on (cap 60).  Reported: latency (results ready minus
+    arrival) p50 / p99, throughput over the makespan, peak pool occupancy."""
+    import numpy as np
+    from workloads import workload
+    from workloads.ensembles import draw_parameters, philox_uniforms
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for j in range(n_req):
+        fam = "landau_tiny" if rng.random() < 0.5 else "twostream_deim"
+        p = int(rng.integers(1, 129))
+        N = int(rng.choice([100_000, 1_000_000]))
+        Nx = 128 if N == 100_000 else 256
+        two_n = int(rng.choice([8, 16, 32, 60]))
+        steps = max(1, int(round(int(rng.integers(200, 1001)) * step_scale)))
+        w = workload(fam, p=p, N=N, Nx=Nx)
+        params = draw_parameters(w, seed=seed + 10 * j)
+        ux, uv = philox_uniforms(seed + 10 * j + 1, N)
+        cfg = binding.make_config(N, p, Nx, two_n, two_n_max=60, dt=0.05, fp_tol=1e-9,
+                                  rank_auto=True, rank_tol_up=1e-2)
+        reqs.append((cfg, w["family"], params, ux, uv, steps))
+    gaps = rng.exponential(mean_gap_s, size=n_req)
+    srv = binding.Server(slots, int(pool_gb * (1 << 30)))
+    ids = []
+    t0 = time.perf_counter()
+    t_next = 0.0
+    for (cfg, fam, params, ux, uv, steps), g in zip(reqs, gaps):
+        t_next += g
+        dt = t_next - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        ids.append(srv.submit(cfg, fam, params, ux, uv, steps))
+    peak = srv.drain()
+    infos = [srv.info(i) for i in ids]
+    srv.close()
+    bad = [i for i in infos if i["status"] != 0]
+    lat = np.array([i["t_finish"] - i["t_arrival"] for i in infos])
+    span = max(i["t_finish"] for i in infos) - min(i["t_arrival"] for i in infos)
+    pp = sum(i["pp_steps"] for i in infos if i["status"] == 0)
+    return {"requests": n_req, "failed": len(bad),
+            "failed_status": [i["status"] for i in bad], "slots": slots, "pool_gb": pool_gb,
+            "mean_interarrival_s": mean_gap_s, "step_scale": step_scale,
+            "latency_s": {"p50": float(np.percentile(lat, 50)),
+                          "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
+            "throughput_pp_steps_per_s": pp / span, "makespan_s": span,
+            "peak_pool_gb": peak / (1 << 30),
+            "mix": "Landau / two-stream 1:1, p ~ U{1..128}, N in {1e5, 1e6}, 2n in "
+                   "{8, 16, 32, 60}, steps ~ U{200..1000} x step_scale, Galerkin, "
+                   "rank adaptation to 60, Poisson arrivals"}
 
 
 def main():
@@ -384,6 +444,9 @@ def main():
     if not a.no_matched:
         out["matched_error"] = matched_error(binding, torch, w, src, cfg, a.warmup + a.steps)
         out["matched_error"]["rom_over_fom_at_this_error"] = rom_rate / fom_rate
+    if not a.no_serve:
+        out["serve"] = serve_bench(binding, torch, a.serve_requests, a.serve_step_scale, 4, 96.0,
+                                   a.serve_gap)
     if not a.no_cpu:
         # the oracle's sample: the first 8 parameters and 1e5 particles
         ns = min(N, 100_000)

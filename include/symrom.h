@@ -318,6 +318,68 @@ symrom_status pic_fields_noalloc(int32_t N, int32_t p, int32_t Nx, const double*
                                  const double* X, int32_t* cells, double* rho, double* Phi,
                                  double* e, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over ensembles of parameter queries
+ * ------------------------------------------------------------------------
+ * A request is one ensemble (family, eta of its p parameters, N shared
+ * uniforms, a rank configuration) advanced by nsteps reduced steps from its
+ * initial condition (rom_init_family, rom_step).  Requests arriving at any
+ * time are admitted, in arrival order but without head-of-line blocking,
+ * when one of `slots` worker threads is free and their device memory
+ * (srv_request_bytes: the exact workspace, the uniforms, the results) fits
+ * in the free space of the caller's pool; each runs on a stream of its own,
+ * so admitted requests overlap on the device.  U and Z stay resident in the
+ * request's workspace for all its steps.  Ensembles are never merged (U
+ * depends on all parameters of its ensemble).  With cfg->deterministic = 1 a
+ * request's results are bitwise the same alone and in any mix.  The pool
+ * (device memory, borrowed until srv_destroy) is the only device memory the
+ * server uses; host copies of the request's inputs are kept until it runs. */
+typedef struct symrom_server symrom_server;
+typedef struct {
+  int32_t status;     /* 1 queued, 2 running, 0 done, negative: its error    */
+  int32_t two_n;      /* rank at the end                                     */
+  int64_t steps_done; /* nsteps when done, -1 on error                       */
+  double t_arrival;   /* seconds on the server's clock: submission,          */
+  double t_start;     /* admission to a worker,                              */
+  double t_finish;    /* results ready                                       */
+  double pp_steps;    /* N p nsteps                                          */
+} symrom_request_info;
+
+/* Device bytes a request holds while it runs (0 for an invalid config). */
+size_t srv_request_bytes(const symrom_config* cfg, int32_t nrows);
+
+/* Start a server with `slots` worker threads (1..64) on the current device;
+ * pool: device memory of pool_bytes. */
+symrom_status srv_create(int32_t slots, void* pool, size_t pool_bytes, symrom_server** out);
+
+/* Queue a request: cfg (host, copied), family 0 Landau / 1 two-stream, eta
+ * (host, p x 4: alpha, k, v0, sigma), ux, uv (HOST [N] uniforms, copied),
+ * nsteps, and nrows particle rows (host int32, copied) whose X_r, V_r are
+ * returned.  id: host.  Errors: EINVAL; ENOMEM when the request could never
+ * fit the pool. */
+symrom_status srv_submit(symrom_server* sv, const symrom_config* cfg, int32_t family,
+                         const double* eta, const double* ux, const double* uv, int32_t nsteps,
+                         int32_t nrows, const int32_t* rows, int64_t* id);
+
+/* State and times of a request (host). */
+symrom_status srv_info(symrom_server* sv, int64_t id, symrom_request_info* info);
+
+/* Block until the request is done; returns its status. */
+symrom_status srv_wait(symrom_server* sv, int64_t id);
+
+/* Block until every queued request is done; peak_pool_bytes (host,
+ * nullable) receives the largest pool occupancy so far. */
+symrom_status srv_drain(symrom_server* sv, double* peak_pool_bytes);
+
+/* Results of a finished request (host arrays, each nullable): the electric
+ * energy and Hamiltonian per parameter (p each, eq. HamEEfull), X_r and V_r
+ * of the requested rows (nrows x p, column-major).  ESTATE while it runs. */
+symrom_status srv_result(symrom_server* sv, int64_t id, double* E, double* H, double* X,
+                         double* V);
+
+/* Finish the requests already admitted, drop the queued ones, stop. */
+void srv_destroy(symrom_server* sv);
+
 /* ------------------------------------------------------------------------ */
 const char* symrom_status_string(symrom_status s);
 const char* symrom_last_error(void);

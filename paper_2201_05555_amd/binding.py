@@ -55,6 +55,14 @@ class StepInfo(ctypes.Structure):
     ]
 
 
+class RequestInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32), ("two_n", ctypes.c_int32), ("steps_done", ctypes.c_int64),
+        ("t_arrival", ctypes.c_double), ("t_start", ctypes.c_double),
+        ("t_finish", ctypes.c_double), ("pp_steps", ctypes.c_double),
+    ]
+
+
 _VP = ctypes.c_void_p
 _SIGS = {
     "rom_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Config)]),
@@ -99,6 +107,16 @@ _SIGS = {
                                     _VP]),
     "pic_fields_noalloc": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
                                             ctypes.c_double, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "srv_request_bytes": (ctypes.c_size_t, [ctypes.POINTER(Config), ctypes.c_int32]),
+    "srv_create": (ctypes.c_int32, [ctypes.c_int32, _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]),
+    "srv_submit": (ctypes.c_int32, [_VP, ctypes.POINTER(Config), ctypes.c_int32, _VP, _VP, _VP,
+                                    ctypes.c_int32, ctypes.c_int32, _VP,
+                                    ctypes.POINTER(ctypes.c_int64)]),
+    "srv_info": (ctypes.c_int32, [_VP, ctypes.c_int64, ctypes.POINTER(RequestInfo)]),
+    "srv_wait": (ctypes.c_int32, [_VP, ctypes.c_int64]),
+    "srv_drain": (ctypes.c_int32, [_VP, ctypes.POINTER(ctypes.c_double)]),
+    "srv_result": (ctypes.c_int32, [_VP, ctypes.c_int64, _VP, _VP, _VP, _VP]),
+    "srv_destroy": (None, [_VP]),
     "symrom_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "symrom_last_error": (ctypes.c_char_p, []),
     "symrom_set_timing": (None, [ctypes.c_int32]),
@@ -454,3 +472,67 @@ def pic_fields_noalloc(X, L, Nx, q=-1.0, stream=None):
     _check(lib().pic_fields_noalloc(N, p, Nx, _ptr(Ld), q, _ptr(X), _ptr(cells), _ptr(rho),
                                     _ptr(Phi), _ptr(e), _stream(stream)))
     return cells, rho, Phi, e
+
+
+class Server:
+    """The serving loop (srv_* entry points) over a device pool of pool_bytes."""
+
+    def __init__(self, slots, pool_bytes):
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        _check(lib().srv_create(slots, _ptr(self.pool), int(pool_bytes), ctypes.byref(h)))
+        self.h = h
+        self.meta = {}
+
+    def submit(self, cfg, family, params, ux, uv, nsteps, rows=()):
+        eta = eta_array(params)
+        ux = np.ascontiguousarray(ux, dtype=np.float64)
+        uv = np.ascontiguousarray(uv, dtype=np.float64)
+        rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int32))
+        if ux.size != cfg.N or uv.size != cfg.N or eta.shape[0] != cfg.p:
+            raise ValueError("uniforms must hold N values and eta p rows")
+        rid = ctypes.c_int64()
+        _check(lib().srv_submit(self.h, ctypes.byref(cfg), FAMILY[family],
+                                eta.ctypes.data_as(_VP), ux.ctypes.data_as(_VP),
+                                uv.ctypes.data_as(_VP), nsteps, rows.size,
+                                rows.ctypes.data_as(_VP) if rows.size else None,
+                                ctypes.byref(rid)))
+        self.meta[rid.value] = (cfg.p, rows.size)
+        return rid.value
+
+    def info(self, rid):
+        inf = RequestInfo()
+        _check(lib().srv_info(self.h, rid, ctypes.byref(inf)))
+        return dict(status=inf.status, two_n=inf.two_n, steps_done=inf.steps_done,
+                    t_arrival=inf.t_arrival, t_start=inf.t_start, t_finish=inf.t_finish,
+                    pp_steps=inf.pp_steps)
+
+    def wait(self, rid):
+        _check(lib().srv_wait(self.h, rid))
+
+    def drain(self):
+        peak = ctypes.c_double()
+        _check(lib().srv_drain(self.h, ctypes.byref(peak)))
+        return peak.value
+
+    def result(self, rid):
+        p, nr = self.meta[rid]
+        E = np.empty(p)
+        H = np.empty(p)
+        X = np.empty((p, nr))
+        V = np.empty((p, nr))
+        _check(lib().srv_result(self.h, rid, E.ctypes.data_as(_VP), H.ctypes.data_as(_VP),
+                                X.ctypes.data_as(_VP), V.ctypes.data_as(_VP)))
+        return E, H, X, V
+
+    def close(self):
+        if self.h:
+            lib().srv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
