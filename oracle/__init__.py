@@ -41,6 +41,9 @@ PINS = {
     "deim.greedy": "brute force on tiny inputs for every k: each index maximises the "
                    "interpolation volume |det Psi[I, :k]|; a hand-worked 4 x 3 example",
     "deim.weights": "hand-worked 4 x 3 example; interpolation of the constant 1",
+    "deim.greedy_with_kept": "brute force on tiny inputs: kept positions keep their index, free "
+                             "ones maximise the interpolation volume; nothing kept = the greedy",
+    "deim.update_positions": "hand-worked rotations (10, 60, 30, 80 degrees and a sign flip)",
     "deim.gradient": "d = N reduces exactly to the Galerkin gradient",
     "deim.accuracy_with_exact_potential": "parity unpinned (no printed values)",
 }

@@ -12,7 +12,10 @@ Snapshots: the last T+1 time levels of N_i for a parameter subset of size
 p*, the matrix Y = [Y_1 ... Y_p*] of eq. (Ydeim) (N x p*(T+1)); Psi = its
 first d left singular vectors; the indices follow the greedy DEIM selection
 (Sec. 4.2.2: at step k, the index of the largest interpolation residual of
-psi_k on the previous vectors).  reading: the subset is evenly spaced in the
+psi_k on the previous vectors; with the adaptive update of eq.
+indices_adaptive_DEIM only the positions of the most rotated basis vectors
+are chosen again between full selections).  reading: the subset is evenly
+spaced in the
 parameter index, i_k = floor(k p / p*), with p* = min(p, max(8,
 ceil(two_n_max / (T+1)))) so that p*(T+1) >= d for every rank reached.
 """
@@ -70,6 +73,39 @@ def greedy_indices(Psi):
     return np.array(idx, dtype=np.int64)
 
 
+def greedy_with_kept(Psi, kept):
+    """Greedy DEIM selection in which position k keeps the index kept[k] when
+    that is given and not chosen already (the adaptive update of Sec. 4.2.2,
+    eq. indices_adaptive_DEIM: the indices not in I* are inherited); every
+    other position takes the index of the largest interpolation residual of
+    psi_k on the indices chosen before it, ties to the smallest index."""
+    d = Psi.shape[1]
+    idx = []
+    for k in range(d):
+        if kept[k] is not None and int(kept[k]) not in idx:
+            idx.append(int(kept[k]))
+            continue
+        if k == 0:
+            r = Psi[:, 0]
+        else:
+            c = np.linalg.solve(Psi[idx, :k], Psi[idx, k])
+            r = Psi[:, k] - Psi[:, :k] @ c
+        idx.append(int(np.argmax(np.abs(r))))
+    return np.array(idx, dtype=np.int64)
+
+
+def update_positions(Psi_new, Psi_old, n_up):
+    """The n_up positions I* of eq. indices_adaptive_DEIM whose basis vectors
+    rotated most from the previous DEIM basis.  reading: the printed argmax of
+    sum psi_k^new . psi_k^old would pick the least rotated vectors, while the
+    text asks for the most rotated ones; the smallest |psi_k^new . psi_k^old|
+    are taken (the modulus removes the sign freedom of singular vectors),
+    ties to the smaller position."""
+    rot = np.abs(np.sum(Psi_new * Psi_old, axis=0))
+    order = np.argsort(rot, kind="stable")
+    return set(int(k) for k in order[:n_up])
+
+
 def weights(Psi, idx):
     """w = (P^T Psi)^{-T} Psi^T 1 (the M_q-dependent factor of eq. grHDD)."""
     PtPsi = Psi[idx, :]
@@ -96,8 +132,24 @@ def update_window(st, cfg, U0, gr0):
         return None
     Y = np.concatenate(st.window, axis=1)
     d = cfg.deim_rows if cfg.deim_rows > 0 else cfg.two_n
-    op = build_operator(Y, min(d, Y.shape[1]))
+    d = min(d, Y.shape[1])
+    Psi, _ = deim_basis(Y, d)
+    # every deim_update_every-th operator (and the first, and after a change
+    # of d) by the full greedy; in between only deim_update_rows positions
+    # are chosen again (eq. indices_adaptive_DEIM)
+    k_full = max(1, cfg.deim_update_every)
+    full = (k_full == 1 or st.deim_builds % k_full == 0 or st.deim_psi is None
+            or st.deim_psi.shape[1] != d)
+    if full:
+        idx = greedy_indices(Psi)
+    else:
+        upd = update_positions(Psi, st.deim_psi, cfg.deim_update_rows)
+        kept = [None if k in upd else st.deim_indices[k] for k in range(d)]
+        idx = greedy_with_kept(Psi, kept)
+    op = DeimOp(idx=idx, w=weights(Psi, idx), Psi=Psi)
     st.deim_indices = op.idx
+    st.deim_psi = Psi
+    st.deim_builds += 1
     return op
 
 

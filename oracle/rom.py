@@ -96,6 +96,8 @@ class RomConfig:
     projection: str = "galerkin"  # or "deim"
     deim_window: int = 3          # T: the window holds T + 1 snapshots
     deim_rows: int = 0            # d, DEIM sample rows; 0: d = 2n
+    deim_update_every: int = 1    # k_DEIM: full greedy every k-th DEIM operator
+    deim_update_rows: int = 0     # n_DEIM: positions chosen again in between
     reorth: bool = True
     rank_auto: bool = False
     rank_tol_up: float = 1e-2
@@ -118,6 +120,8 @@ class RomState:
     last_stall_rel: float = 0.0   # largest relative update accepted by the stagnation rule
     last_status: int = OK
     deim_indices: Optional[np.ndarray] = None
+    deim_psi: Optional[np.ndarray] = None   # DEIM basis of the last operator
+    deim_builds: int = 0                    # DEIM operators built so far
 
 
 # ----------------------------------------------------------------------------
@@ -326,7 +330,7 @@ def prk_step(st, cfg, fixed_iters=None):
     gr0 = gradient(U0, Z0, st.L, cfg.Nx, cfg.q, cfg.m)
     deim_op = None
     window0 = list(st.window)
-    indices0 = st.deim_indices
+    indices0, psi0, builds0 = st.deim_indices, st.deim_psi, st.deim_builds
     if cfg.projection == "deim":
         deim_op = deim_mod.update_window(st, cfg, U0, gr0)
     g1 = gr0.g if deim_op is None else deim_mod.deim_gradient(U0, Z0, gr0, deim_op, cfg)
@@ -382,7 +386,7 @@ def prk_step(st, cfg, fixed_iters=None):
     if fixed_iters is None and active.any():
         # the state, the DEIM snapshot window included, stays as it was
         st.window = window0
-        st.deim_indices = indices0
+        st.deim_indices, st.deim_psi, st.deim_builds = indices0, psi0, builds0
         st.last_status = ENOCONV
         return ENOCONV
 

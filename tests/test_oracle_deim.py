@@ -157,3 +157,89 @@ def test_greedy_hand_worked_example():
     # the DEIM interpolant of the constant 1 reproduces 1 on the selected rows
     proj = Psi @ np.linalg.solve(A, np.ones(3))
     assert np.allclose(proj[[1, 3, 0]], 1.0, atol=1e-13)
+
+
+def test_greedy_with_kept_reduces_to_the_greedy():
+    """Nothing kept: the adaptive selection is the full greedy."""
+    rng = np.random.default_rng(11)
+    for _ in range(10):
+        Psi, _ = np.linalg.qr(rng.normal(size=(40, 7)))
+        assert np.array_equal(deim.greedy_with_kept(Psi, [None] * 7), deim.greedy_indices(Psi))
+
+
+def test_greedy_with_kept_maximises_the_volume_at_free_positions():
+    """Brute force (Sec. 4.2.2, eq. indices_adaptive_DEIM): kept positions keep
+    their index; each free position takes the maximiser over j of
+    |det Psi[I_{k-1} + (j), :k]| given the indices before it (the Schur
+    complement identity of the greedy pin above), and a kept index already
+    chosen is chosen again."""
+    rng = np.random.default_rng(12)
+    cases = 0
+    while cases < 30:
+        N = int(rng.integers(8, 14))
+        d = int(rng.integers(3, 6))
+        Psi, _ = np.linalg.qr(rng.normal(size=(N, d)))
+        kept = [int(rng.integers(0, N)) if rng.random() < 0.5 else None for _ in range(d)]
+        got = deim.greedy_with_kept(Psi, kept)
+        ok = True
+        for k in range(d):
+            prev = got[:k].tolist()
+            if kept[k] is not None and kept[k] not in prev:
+                assert got[k] == kept[k]
+                continue
+            vols = np.array([abs(np.linalg.det(Psi[prev + [j], :k + 1])) if j not in prev else -1.0
+                             for j in range(N)])
+            order = np.argsort(-vols, kind="stable")
+            if vols[order[1]] > (1 - 1e-6) * vols[order[0]]:
+                ok = False      # a near tie: either index is right
+                break
+            assert got[k] == order[0], (k, got, order[:3])
+        cases += int(ok)
+    # a kept index equal to an earlier choice is chosen again
+    Psi, _ = np.linalg.qr(rng.normal(size=(12, 3)))
+    first = deim.greedy_indices(Psi)[0]
+    got = deim.greedy_with_kept(Psi, [None, int(first), None])
+    assert len(set(got.tolist())) == 3
+
+
+def test_update_positions_hand_example():
+    """Columns rotated by 10, 60, 30 and 80 degrees (and one sign flip): the
+    two most rotated are positions 1 and 3; the flipped column counts as not
+    rotated."""
+    ang = np.radians([10.0, 60.0, 30.0, 80.0, 0.0])
+    old = np.zeros((10, 5))
+    new = np.zeros((10, 5))
+    for k, a in enumerate(ang):
+        old[2 * k, k] = 1.0
+        new[2 * k, k] = np.cos(a)
+        new[2 * k + 1, k] = np.sin(a)
+    new[:, 4] *= -1.0
+    assert deim.update_positions(new, old, 2) == {1, 3}
+    assert deim.update_positions(new, old, 0) == set()
+
+
+def test_adaptive_deim_schedule():
+    """k_DEIM = 3, n_DEIM = 2: operators 0 and 3 by the full greedy; in
+    between, every position outside the two most rotated inherits its index
+    (unless that index was already taken)."""
+    N = 600
+    w = workload("twostream_deim", N=N, p=12, Nx=32)
+    ens = make_ensemble(w)
+    cfg = rom.RomConfig(N=N, p=12, Nx=32, two_n=6, dt=0.05, projection="deim",
+                        deim_window=2, fp_tol=1e-10, deim_update_every=3, deim_update_rows=2)
+    st = rom.init_state(ens["X0"], ens["V0"], ens["L"], cfg)
+    prev_idx = prev_psi = None
+    for s in range(7):
+        assert rom.prk_step(st, cfg) == rom.OK
+        if st.deim_indices is None:
+            continue
+        b = st.deim_builds - 1
+        if b % 3 == 0:
+            assert np.array_equal(st.deim_indices, deim.greedy_indices(st.deim_psi))
+        else:
+            upd = deim.update_positions(st.deim_psi, prev_psi, 2)
+            for k in range(6):
+                if k not in upd and prev_idx[k] not in st.deim_indices[:k].tolist():
+                    assert st.deim_indices[k] == prev_idx[k]
+        prev_idx, prev_psi = st.deim_indices.copy(), st.deim_psi.copy()
+    assert st.deim_builds >= 4
