@@ -81,9 +81,14 @@ typedef struct {
   int32_t deim_rows;     /* d, DEIM sample rows; 0: d = 2n (capped by the    */
                          /* snapshot count p*(T+1))                          */
   int32_t precision;     /* SYMROM_FP64 (the only arithmetic built)          */
-  int32_t deterministic; /* 1: theta sums of the deposit in 64-bit fixed     */
-                         /* point (exact for |x N_x / L| >= 1), so the charge */
-                         /* and everything after it is bitwise reproducible  */
+  int32_t deterministic; /* 1: theta sums of the reduced deposit as 64-bit   */
+                         /* integers in units of 2^-40, so the charge and    */
+                         /* everything after it is bitwise reproducible      */
+  int32_t deim_update_every; /* k_DEIM: the DEIM indices by the full greedy */
+                         /* every k-th operator (0 or 1: every step)         */
+  int32_t deim_update_rows;  /* n_DEIM: positions chosen again in between    */
+                         /* (those of the most rotated basis vectors, eq.    */
+                         /* indices_adaptive_DEIM); the others are inherited */
   int32_t reserved;
 } symrom_config;
 

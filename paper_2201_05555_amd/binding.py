@@ -40,6 +40,7 @@ class Config(ctypes.Structure):
         ("rank_tol_up", ctypes.c_double), ("fp_stall_tol", ctypes.c_double),
         ("rank_tol_down", ctypes.c_double), ("deim_rows", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("deterministic", ctypes.c_int32),
+        ("deim_update_every", ctypes.c_int32), ("deim_update_rows", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
     ]
 
@@ -196,14 +197,16 @@ def kernel_work(family):
 def make_config(N, p, Nx, two_n, two_n_max=None, dt=0.05, q=-1.0, m=1.0, projection="galerkin",
                 deim_window=3, fp_tol=1e-9, fp_max_iters=100, fp_fixed_iters=0, pinv_rtol=1e-12,
                 reorth=True, rank_auto=False, rank_tol_up=1e-2, fp_stall_tol=1e-3,
-                rank_tol_down=1e-8, deim_rows=0, deterministic=False):
+                rank_tol_down=1e-8, deim_rows=0, deterministic=False, deim_update_every=1,
+                deim_update_rows=0):
     return Config(N=N, p=p, Nx=Nx, two_n=two_n, two_n_max=two_n_max or two_n, dt=dt, q=q, m=m,
                   projection=DEIM if projection == "deim" else GALERKIN,
                   deim_window=deim_window, fp_tol=fp_tol, fp_max_iters=fp_max_iters,
                   fp_fixed_iters=fp_fixed_iters, pinv_rtol=pinv_rtol, reorth=int(reorth),
                   rank_auto=int(rank_auto), rank_tol_up=rank_tol_up, fp_stall_tol=fp_stall_tol,
                   rank_tol_down=rank_tol_down, deim_rows=deim_rows, precision=0,
-                  deterministic=int(deterministic), reserved=0)
+                  deterministic=int(deterministic), deim_update_every=deim_update_every,
+                  deim_update_rows=deim_update_rows, reserved=0)
 
 
 def _info_dict(info):

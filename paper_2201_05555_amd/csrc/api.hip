@@ -628,6 +628,13 @@ struct symrom_rom {
   bool head_pending;
   int head_n;
   double* zsig;  // singular values of Z~ (automatic shrink)
+  // adaptive DEIM (Sec. 4.2.2): double-buffered basis and indices, the d of
+  // the operator in each buffer, the inherited indices, rotation partials
+  double* Psib[2];
+  int* didxb[2];
+  int dbuf[2];
+  int* forced;
+  double* rotpart;
   cplx* Ysub;    // Rayleigh-Ritz eigenvectors of the subspace iteration (64 x 64)
   cplx* Wsub;    // its p x 64 block of vectors (p > 64)
   double* lamsub;
@@ -710,8 +717,16 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.nbc = 64;
   r.sub = ar.take<int>(r.psub);
   r.Ywin = ar.take<double>(r.cfg.projection == SYMROM_DEIM ? (size_t)P * N : 0);
-  r.Psi = ar.take<double>(r.cfg.projection == SYMROM_DEIM ? (size_t)dmax * N : 0);
-  r.didx = ar.take<int>(dmax);
+  // the DEIM basis and indices of two consecutive operators (the adaptive
+  // update reads the previous ones): operator b uses buffer b % 2
+  for (int q = 0; q < 2; ++q) {
+    r.Psib[q] = ar.take<double>(r.cfg.projection == SYMROM_DEIM ? (size_t)dmax * N : 0);
+    r.didxb[q] = ar.take<int>(dmax);
+  }
+  r.Psi = r.Psib[0];
+  r.didx = r.didxb[0];
+  r.forced = ar.take<int>(dmax);
+  r.rotpart = ar.take<double>((size_t)psi_blocks(r.N) * dmax);
   r.dw = ar.take<double>(dmax);
   r.dc = ar.take<double>(dmax);
   r.bval = ar.take<double>(2 * (size_t)r.nbg);
@@ -776,6 +791,10 @@ bool valid_rom_config(const symrom_config* c, std::string& why) {
   }
   if (c->precision != SYMROM_FP64) {
     why = "precision: only SYMROM_FP64 arithmetic is built";
+    return false;
+  }
+  if (c->deim_update_every < 0 || c->deim_update_rows < 0) {
+    why = "deim_update_every and deim_update_rows must be >= 0";
     return false;
   }
   if (c->deterministic != 0 && c->deterministic != 1) {
@@ -1056,10 +1075,27 @@ void deim_update_tail(symrom_rom& r) {
   for (int q = 0; q < r.nslots; ++q) slots[q] = r.Ywin + (size_t)q * r.psub * N;
   const int P = r.psub * r.nslots;
   Timer t(FAM_CHAIN, s);
+  // operator b = win_count - nslots (0 for the first DEIM step; a rebuild of
+  // the same step keeps b, a failed step takes it back) goes to buffer b % 2
+  const int b = r.win_count - r.nslots;
+  const int cur = b & 1, old = cur ^ 1;
+  r.Psi = r.Psib[cur];
+  r.didx = r.didxb[cur];
+  const int kfull = std::max(1, r.cfg.deim_update_every);
+  const bool full = kfull == 1 || b % kfull == 0 || r.dbuf[old] != d || r.cfg.deim_update_rows >= d;
+  r.dbuf[cur] = d;
   // Psi and its column sums.  No sign convention is applied to the columns:
   // flipping the sign of column k negates c_k and the residual exactly, so
   // the greedy indices and the weights are the same bit for bit.
   launch_psi_colsum(s, slots.data(), r.nslots, r.psub, N, r.Mdeim, P, d, r.Psi, r.colpart);
+  // between full selections only the positions of the most rotated basis
+  // vectors are chosen again; the others inherit the previous indices
+  const int* forced = nullptr;
+  if (!full) {
+    launch_deim_forced(s, r.Psi, r.Psib[old], N, d, std::max(0, r.cfg.deim_update_rows),
+                       r.didxb[old], r.rotpart, r.forced, nullptr);
+    forced = r.forced;
+  }
   // greedy selection, one launch per index; block results ping-pong between
   // the two halves of bval / bidx
   // the inverse of P^T Psi and the coefficients ping-pong as well (pass k
@@ -1069,12 +1105,12 @@ void deim_update_tail(symrom_rom& r) {
     launch_deim_greedy(s, r.Psi, N, k, r.didx, r.bval + prev * r.nbg, r.bidx + prev * r.nbg,
                        r.nbg, r.nbg, r.bval + cur * r.nbg, r.bidx + cur * r.nbg,
                        r.dB + prev * 4096, r.dcv + prev * 64, r.dB + cur * 4096,
-                       r.dcv + cur * 64, dflags);
+                       r.dcv + cur * 64, dflags, forced);
   }
   const int last = (d - 1) & 1;
   launch_deim_weights(s, r.Psi, N, d, r.didx, r.bval + last * r.nbg, r.bidx + last * r.nbg,
                       r.nbg, r.dB + last * 4096, r.dcv + last * 64, r.colpart, psi_blocks(N),
-                      r.dw, dflags);
+                      r.dw, dflags, forced);
 }
 
 // the whole status block into the pinned mirror (one copy, one wait)

@@ -157,11 +157,16 @@ void launch_psi_colsum(hipStream_t s, const double* const* in, int nin, int kin,
 void launch_deim_greedy(hipStream_t s, const double* Psi, int N, int k, int* idx,
                         const double* pval, const int* pidx, int nprev, int nblk, double* bval,
                         int* bidx, const double* Bprev, const double* uprev, double* Bnext,
-                        double* cnext, int* flags);
+                        double* cnext, int* flags, const int* forced = nullptr);
 void launch_deim_weights(hipStream_t s, const double* Psi, int N, int d, int* idx,
                          const double* pval, const int* pidx, int nprev, const double* Bprev,
                          const double* uprev, const double* colpart, int ncp, double* w,
-                         int* flags);
+                         int* flags, const int* forced = nullptr);
+// adaptive DEIM update: forced[k] = idx_old[k] for the positions kept, -1
+// for the n_up positions whose basis vectors rotated most (part: psi_blocks(N)
+// x d doubles of scratch)
+void launch_deim_forced(hipStream_t s, const double* Pn, const double* Po, int N, int d, int n_up,
+                        const int* idx_old, double* part, int* forced, const int* stop);
 
 // dense_kernels.hip  (single-workgroup FP64 kernels on small matrices)
 struct DenseCtl;  // device-resident control block, see dense_kernels.hip

@@ -824,6 +824,24 @@ __device__ int dg_winner(const double* __restrict__ val, const int* __restrict__
   return bi;
 }
 
+// The index of position pos: the winner of the previous pass, or, with the
+// adaptive update (Sec. 4.2.2, eq. indices_adaptive_DEIM), the inherited
+// index forced[pos] when it is set and not chosen at an earlier position.
+__device__ int dg_choose(const double* __restrict__ pval, const int* __restrict__ pidx, int nprev,
+                         const int* __restrict__ forced, const int* __restrict__ idx, int pos,
+                         int N) {
+  int win = dg_winner(pval, pidx, nprev);
+  if (forced) {
+    const int f = forced[pos];
+    if (f >= 0 && f < N) {
+      bool dup = false;
+      for (int q = 0; q < pos; ++q) dup |= (idx[q] == f);
+      if (!dup) win = f;
+    }
+  }
+  return win;
+}
+
 // Greedy DEIM step k (the selection rule of Sec. 4.2.2): l_k = argmax |r_k|,
 // r_k = psi_k - Psi_{k-1} c_k, M_k c_k = P^T psi_k with M_k = P^T Psi_{k-1}
 // (k x k; rows l_0 .. l_{k-1}).  Instead of a fresh solve per step, the
@@ -878,7 +896,7 @@ __global__ void __launch_bounds__(256) deim_greedy_kernel(
     const double* __restrict__ pval, const int* __restrict__ pidx, int nprev,
     double* __restrict__ bval, int* __restrict__ bidx, const double* __restrict__ Bprev,
     const double* __restrict__ uprev, double* __restrict__ Bnext, double* __restrict__ cnext,
-    int* __restrict__ flags) {
+    int* __restrict__ flags, const int* __restrict__ forced) {
   __shared__ double Bs[64 * 65];
   __shared__ double us[64], ys[64], bs[64], cs[64], vs[64], cf[64];
   __shared__ double sh_s;
@@ -910,7 +928,7 @@ __global__ void __launch_bounds__(256) deim_greedy_kernel(
       bs[tid] = 0.0;
     }
     if (w == 0) {
-      int win = dg_winner(pval, pidx, nprev);
+      int win = dg_choose(pval, pidx, nprev, forced, idx, k - 1, N);
       if (win < 0 || win >= N) {
         // no finite residual anywhere: report, and keep the row in range
         if (lane == 0 && blockIdx.x == 0 && flags) flags[0] |= 16;
@@ -1015,7 +1033,7 @@ __global__ void __launch_bounds__(256) deim_weights_kernel(
     const double* __restrict__ pval, const int* __restrict__ pidx, int nprev,
     const double* __restrict__ Bprev, const double* __restrict__ uprev,
     const double* __restrict__ colpart, int ncp, double* __restrict__ wout,
-    int* __restrict__ flags) {
+    int* __restrict__ flags, const int* __restrict__ forced) {
   __shared__ double Bs[64 * 65];
   __shared__ double us[64], ys[64], bs[64], cs[64], vs[64], sg[64];
   __shared__ double sh_s;
@@ -1033,7 +1051,7 @@ __global__ void __launch_bounds__(256) deim_weights_kernel(
     sg[tid] = 0.0;
   }
   if (w == 0) {
-    int win = dg_winner(pval, pidx, nprev);
+    int win = dg_choose(pval, pidx, nprev, forced, idx, d - 1, N);
     if (win < 0 || win >= N) {
       if (lane == 0 && flags) flags[0] |= 16;
       win = 0;
@@ -1703,15 +1721,68 @@ void launch_psi_colsum(hipStream_t s, const double* const* in, int nin, int kin,
 void launch_deim_greedy(hipStream_t s, const double* Psi, int N, int k, int* idx,
                         const double* pval, const int* pidx, int nprev, int nblk, double* bval,
                         int* bidx, const double* Bprev, const double* uprev, double* Bnext,
-                        double* cnext, int* flags) {
+                        double* cnext, int* flags, const int* forced) {
   hipLaunchKernelGGL(deim_greedy_kernel, dim3(nblk), dim3(256), 0, s, Psi, N, k, idx, pval, pidx,
-                     nprev, bval, bidx, Bprev, uprev, Bnext, cnext, flags);
+                     nprev, bval, bidx, Bprev, uprev, Bnext, cnext, flags, forced);
 }
 
 void launch_deim_weights(hipStream_t s, const double* Psi, int N, int d, int* idx,
                          const double* pval, const int* pidx, int nprev, const double* Bprev,
                          const double* uprev, const double* colpart, int ncp, double* w,
-                         int* flags) {
+                         int* flags, const int* forced) {
   hipLaunchKernelGGL(deim_weights_kernel, dim3(1), dim3(256), 0, s, Psi, N, d, idx, pval, pidx,
-                     nprev, Bprev, uprev, colpart, ncp, w, flags);
+                     nprev, Bprev, uprev, colpart, ncp, w, flags, forced);
+}
+
+// Rotation of the DEIM basis between two operators: per block, the partial
+// dot products psi_k^new . psi_k^old over its rows (d columns), summed in a
+// fixed order by deim_forced_kernel.
+__global__ void __launch_bounds__(256) psi_rot_kernel(const double* __restrict__ Pn,
+                                                      const double* __restrict__ Po, int N, int d,
+                                                      double* __restrict__ part) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  __shared__ double ws4[4][64];
+  for (int k = 0; k < d; ++k) {
+    double a = 0.0;
+    for (int l = blockIdx.x * 256 + tid; l < N; l += gridDim.x * 256)
+      a = fma(Pn[(size_t)k * N + l], Po[(size_t)k * N + l], a);
+    a = dg_wave_sum(a);
+    if (lane == 0) ws4[w][k & 63] = a;
+    __syncthreads();
+    if (tid == 0) part[(size_t)blockIdx.x * d + k] = ((ws4[0][k & 63] + ws4[1][k & 63]) +
+                                                      ws4[2][k & 63]) + ws4[3][k & 63];
+    __syncthreads();
+  }
+}
+
+// The adaptive update's inherited indices: |psi_k^new . psi_k^old| (block
+// partials summed in order); the n_up smallest (ties to the smaller
+// position) are chosen again (forced = -1), the other positions inherit
+// their previous index (forced = idx_old[k]).
+__global__ void deim_forced_kernel(const double* __restrict__ part, int nb, int d, int n_up,
+                                   const int* __restrict__ idx_old, int* __restrict__ forced,
+                                   const int* __restrict__ stop) {
+  if (stop && *stop) return;
+  __shared__ double rot[64];
+  const int k = threadIdx.x;
+  if (k < d) {
+    double a = 0.0;
+    for (int b = 0; b < nb; ++b) a += part[(size_t)b * d + k];
+    rot[k] = fabs(a);
+  }
+  __syncthreads();
+  if (k < d) {
+    // rank of position k in increasing rotation measure (stable)
+    int rank = 0;
+    for (int q = 0; q < d; ++q) rank += (rot[q] < rot[k]) || (rot[q] == rot[k] && q < k);
+    forced[k] = (rank < n_up) ? -1 : idx_old[k];
+  }
+}
+
+void launch_deim_forced(hipStream_t s, const double* Pn, const double* Po, int N, int d, int n_up,
+                        const int* idx_old, double* part, int* forced, const int* stop) {
+  const int nb = psi_blocks(N);
+  hipLaunchKernelGGL(psi_rot_kernel, dim3(nb), dim3(256), 0, s, Pn, Po, N, d, part);
+  hipLaunchKernelGGL(deim_forced_kernel, dim3(1), dim3(64), 0, s, part, nb, d, n_up, idx_old,
+                     forced, stop);
 }

@@ -348,3 +348,60 @@ def test_reconstruct_rows():
     ok = (rows >= 0) & (rows < 5000)
     assert torch.equal(Xs[:, ok], X[:, rows[ok]]) and torch.equal(Vs[:, ok], V[:, rows[ok]])
     assert torch.isnan(Xs[:, ~ok]).all() and torch.isnan(Vs[:, ~ok]).all()
+
+
+@pytest.mark.parametrize("kw,two_n,k_full,n_up,steps", [
+    # 9 steps: at the tenth, a 1e-15 perturbation of Z flips the cell of a
+    # sampled particle in the oracle and its sensitivity jumps from 8e-8 to
+    # 5e-6, which would make the bound meaningless
+    (dict(N=20000, p=24, Nx=128), 10, 3, 4, 9),
+    (dict(N=30000, p=64, Nx=128), 12, 2, 5, 8),
+])
+def test_adaptive_deim_parity(kw, two_n, k_full, n_up, steps):
+    """Adaptive DEIM index updates (Sec. 4.2.2, eq. indices_adaptive_DEIM):
+    every k_full-th operator by the full greedy, in between n_up positions of
+    the most rotated basis vectors chosen again.  Same iteration counts and
+    indices as the oracle (where its greedy margin allows), R within the DEIM
+    bound."""
+    binding, torch = _b()
+    w, e = _ens("twostream_deim", **kw)
+    _say("adaptive deim", kw, two_n, k_full, n_up, steps)
+    cfg = rom.RomConfig(N=w["N"], p=w["p"], Nx=w["Nx"], two_n=two_n, dt=w["dt"], fp_tol=1e-10,
+                        projection="deim", deim_window=3, deim_update_every=k_full,
+                        deim_update_rows=n_up)
+    st = rom.init_state(e["X0"], e["V0"], e["L"], cfg)
+    gcfg = binding.make_config(w["N"], w["p"], w["Nx"], two_n, dt=w["dt"], fp_tol=1e-10,
+                               projection="deim", deim_window=3, deim_update_every=k_full,
+                               deim_update_rows=n_up)
+    # the oracle's own sensitivity over the same steps, of X_r and of V_r
+    # apart: Z perturbed by 1e-15
+    rng = np.random.default_rng(0)
+    outs = []
+    for pert in (0.0, 1e-15):
+        s2 = rom.RomState(U=st.U.copy(), Z=st.Z * (1 + pert * rng.normal(size=st.Z.shape)),
+                          L=st.L)
+        for _ in range(steps):
+            assert rom.prk_step(s2, cfg) == rom.OK
+        outs.append(rom.reconstruct(s2))
+    sx, sv = _rel(outs[1][0], outs[0][0]), _rel(outs[1][1], outs[0][1])
+    r = binding.Rom(gcfg, e["L"], e["X0"], e["V0"])
+    _set_from_oracle(r, st, torch)
+    same = 0
+    for s in range(steps):
+        info = r.step(1)
+        assert rom.prk_step(st, cfg) == rom.OK
+        assert info["iters"] == st.last_iters, (s, info, st.last_iters)
+        if st.deim_indices is None:
+            continue
+        gi = _np(r.deim_operator()[0]).astype(np.int64)
+        eq = np.array_equal(gi, st.deim_indices)
+        print(f"  step {s}: operator {st.deim_builds - 1}, indices equal {eq}", flush=True)
+        same += int(eq)
+    assert same >= 3
+    X, V = r.reconstruct()
+    Xo, Vo = rom.reconstruct(st)
+    ex, ev = _rel(_np(X).T, Xo), _rel(_np(V).T, Vo)
+    bx, bv = max(1e-9, 50.0 * sx), max(1e-9, 50.0 * sv)
+    print(f"  X_r rel err {ex:.2e} (sensitivity {sx:.2e}, bound {bx:.2e}); V_r rel err "
+          f"{ev:.2e} (sensitivity {sv:.2e}, bound {bv:.2e})", flush=True)
+    assert ex < bx and ev < bv
