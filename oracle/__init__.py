@@ -15,7 +15,7 @@ solves, bincount) as steps.  Every function cites the passage it follows.
 Parity status of each piece is listed in ``PINS`` below; a piece whose result
 no closed form, invariant or brute-force check fixes says "parity unpinned".
 """
-from . import pic, rom, deim  # noqa: F401
+from . import pic, rom, deim, dmd  # noqa: F401
 
 PINS = {
     "pic.cell_index": "brute force on tiny inputs; node ties",
@@ -46,4 +46,17 @@ PINS = {
     "deim.update_positions": "hand-worked rotations (10, 60, 30, 80 degrees and a sign flip)",
     "deim.gradient": "d = N reduces exactly to the Galerkin gradient",
     "deim.accuracy_with_exact_potential": "parity unpinned (no printed values)",
+    "dmd.select_subset": "brute force of every greedy pick (eq. pSampl); gauge invariance",
+    "dmd.dmd / dmd.predict": "exactly linear data: eigenvalues (a damped rotation and real "
+                             "ones) and the prediction at 0, dt/2, dt, 2 dt against the closed-form "
+                             "principal powers; relative truncation; untruncated DMD reproduces "
+                             "the last potential",
+    "dmd.rbf_interpolate": "scipy RBFInterpolator (gaussian, no polynomial); interpolation at "
+                           "the nodes; width and scaling by hand",
+    "dmd.build_operator": "subset coordinates = Theta^+ Phi; others = the scipy interpolant",
+    "rom.dmd_deim_gradient": "central finite difference of the DMD-DEIM Hamiltonian through the "
+                             "brute-force Lambda^0",
+    "rom.prk_step (dmd_deim)": "the first T steps equal the plain reduced model bit for bit; "
+                               "ENOCONV restores both windows",
+    "dmd.accuracy": "parity unpinned (the paper prints no values for it)",
 }

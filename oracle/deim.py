@@ -130,6 +130,11 @@ def update_window(st, cfg, U0, gr0):
     if len(st.window) < T + 1:
         st.deim_indices = None
         return None
+    return build_from_window(st, cfg)
+
+
+def build_from_window(st, cfg):
+    """The DEIM operator of the current snapshot window (T+1 levels)."""
     Y = np.concatenate(st.window, axis=1)
     d = cfg.deim_rows if cfg.deim_rows > 0 else cfg.two_n
     d = min(d, Y.shape[1])

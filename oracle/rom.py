@@ -93,11 +93,13 @@ class RomConfig:
     fp_max_iters: int = 100
     fp_stall_tol: float = 1e-3    # stagnation accepted only below this update
     pinv_rtol: float = 1e-12
-    projection: str = "galerkin"  # or "deim"
+    projection: str = "galerkin"  # "deim" (exact potential) or "dmd_deim" (Alg. 2)
     deim_window: int = 3          # T: the window holds T + 1 snapshots
     deim_rows: int = 0            # d, DEIM sample rows; 0: d = 2n
     deim_update_every: int = 1    # k_DEIM: full greedy every k-th DEIM operator
     deim_update_rows: int = 0     # n_DEIM: positions chosen again in between
+    p_star: int = 0               # dmd_deim: subset size p* (0: p), eq. pSampl
+    dmd_tol: float = 1e-5         # dmd_deim: relative singular value cut (Sec. 6.1)
     reorth: bool = True
     rank_auto: bool = False
     rank_tol_up: float = 1e-2
@@ -122,6 +124,10 @@ class RomState:
     deim_indices: Optional[np.ndarray] = None
     deim_psi: Optional[np.ndarray] = None   # DEIM basis of the last operator
     deim_builds: int = 0                    # DEIM operators built so far
+    eta: Optional[np.ndarray] = None        # dim x p parameters (dmd_deim)
+    subset: Optional[np.ndarray] = None     # S_{p*}, fixed at t = 0 (dmd_deim)
+    phi_window: list = dc_field(default_factory=list)   # subset potentials (N_x x p*)
+    last_dmd_rank: int = 0
 
 
 # ----------------------------------------------------------------------------
@@ -155,9 +161,15 @@ def init_csvd(X0, V0, two_n):
     return from_complex_basis(Ut), from_complex_coeff(Zt)
 
 
-def init_state(X0, V0, L, cfg):
+def init_state(X0, V0, L, cfg, eta=None):
     U, Z = init_csvd(X0, V0, cfg.two_n)
-    return RomState(U=U, Z=Z, L=np.asarray(L, dtype=np.float64).copy())
+    st = RomState(U=U, Z=Z, L=np.asarray(L, dtype=np.float64).copy())
+    if cfg.projection == "dmd_deim":
+        from . import dmd
+        p = Z.shape[1]
+        st.eta = None if eta is None else np.atleast_2d(np.asarray(eta, dtype=np.float64))
+        st.subset = dmd.select_subset(Z, cfg.p_star if cfg.p_star > 0 else p)
+    return st
 
 
 # ----------------------------------------------------------------------------
@@ -322,6 +334,13 @@ def prk_step(st, cfg, fixed_iters=None):
     DEIM snapshot window) is unchanged.
     """
     from . import deim as deim_mod
+    if cfg.projection == "dmd_deim":
+        return _prk_step_dmd(st, cfg, fixed_iters)
+    return _prk_step_core(st, cfg, fixed_iters)
+
+
+def _prk_step_core(st, cfg, fixed_iters):
+    from . import deim as deim_mod
     J = J_small(cfg.two_n)
     U0, Z0 = st.U, st.Z
     dt = cfg.dt
@@ -340,50 +359,25 @@ def prk_step(st, cfg, fixed_iters=None):
     xi_half = 0.5 * dt * kh1
     U_half = cayley(U0, xi_half)
 
-    k = k1.copy()
-    ZG = Z0.copy()
-    active = np.ones(p, dtype=bool)
-    prev = np.full(p, np.inf)
-    iters = 0
-    stalled = 0
-    stall_rel = 0.0
-    limit = fixed_iters if fixed_iters is not None else cfg.fp_max_iters
-    while active.any() and iters < limit:
-        iters += 1
-        cols = np.nonzero(active)[0]
-        Ze = Z0[:, cols] + 0.5 * dt * k[:, cols]
+    def g_of(cols, Ze):
         sub = RomState(U=U_half, Z=Ze, L=st.L[cols])
         op = None if deim_op is None else deim_mod.restrict(deim_op, cols)
-        g, _ = reduced_gradient(sub, cfg, U_half, Ze, op)
-        kn = J @ g
-        ZG[:, cols] = Ze
-        if fixed_iters is None:
-            nk = _col_norms(kn)
-            rel = _col_norms(kn - k[:, cols]) / np.where(nk > 0, nk, 1.0)
-            conv = rel < cfg.fp_tol
-            # reading: the gathered force is piecewise constant in a particle's
-            # own position (the cell field of Sec. 2.1), so a particle whose
-            # midpoint sits at a node can put the map into a cycle: the
-            # iterates alternate between contraction steps with the particle
-            # in one cell and jumps when it changes cell.  A column whose
-            # relative update stops decreasing is accepted at its current
-            # iterate, provided the smaller of its last two updates is below
-            # fp_stall_tol (the cycle has a contracted phase); otherwise the
-            # column keeps iterating and the step fails at fp_max_iters
-            stall = ~conv & (rel >= prev[cols]) & (np.minimum(rel, prev[cols]) < cfg.fp_stall_tol)
-            stalled += int(np.sum(stall))
-            if stall.any():
-                stall_rel = max(stall_rel, float(rel[stall].max()))
-            done = conv | stall
-            prev[cols] = rel
-        else:
-            done = np.zeros(cols.size, dtype=bool)
-        k[:, cols] = kn
-        active[cols[done]] = False
+        return reduced_gradient(sub, cfg, U_half, Ze, op)[0]
+
+    # reading (stagnation rule, in ``_fixed_point``): the gathered force is
+    # piecewise constant in a particle's own position (the cell field of
+    # Sec. 2.1), so a particle whose midpoint sits at a node can put the map
+    # into a cycle: the iterates alternate between contraction steps with the
+    # particle in one cell and jumps when it changes cell.  A column whose
+    # relative update stops decreasing is accepted at its current iterate,
+    # provided the smaller of its last two updates is below fp_stall_tol (the
+    # cycle has a contracted phase); otherwise the column keeps iterating and
+    # the step fails at fp_max_iters
+    k, ZG, iters, stalled, stall_rel, ok = _fixed_point(Z0, k1, dt, cfg, fixed_iters, g_of)
     st.last_iters = iters
     st.last_stalled = stalled
     st.last_stall_rel = stall_rel
-    if fixed_iters is None and active.any():
+    if not ok:
         # the state, the DEIM snapshot window included, stays as it was
         st.window = window0
         st.deim_indices, st.deim_psi, st.deim_builds = indices0, psi0, builds0
@@ -400,6 +394,134 @@ def prk_step(st, cfg, fixed_iters=None):
     st.step += 1
     st.last_status = OK
     return OK
+
+
+def _fixed_point(Z0, k1, dt, cfg, fixed_iters, g_of):
+    """k = J g(Z0 + dt/2 k) per column from k = k1 with the convergence and
+    stagnation rules of ``prk_step``; g_of(cols, Ze) evaluates the gradient
+    of the active columns.  Returns (k, ZG, iters, stalled, stall_rel, ok)."""
+    J = J_small(Z0.shape[0])
+    p = Z0.shape[1]
+    k = k1.copy()
+    ZG = Z0.copy()
+    active = np.ones(p, dtype=bool)
+    prev = np.full(p, np.inf)
+    iters = stalled = 0
+    stall_rel = 0.0
+    limit = fixed_iters if fixed_iters is not None else cfg.fp_max_iters
+    while active.any() and iters < limit:
+        iters += 1
+        cols = np.nonzero(active)[0]
+        Ze = Z0[:, cols] + 0.5 * dt * k[:, cols]
+        kn = J @ g_of(cols, Ze)
+        ZG[:, cols] = Ze
+        if fixed_iters is None:
+            nk = _col_norms(kn)
+            rel = _col_norms(kn - k[:, cols]) / np.where(nk > 0, nk, 1.0)
+            conv = rel < cfg.fp_tol
+            stall = ~conv & (rel >= prev[cols]) & (np.minimum(rel, prev[cols]) < cfg.fp_stall_tol)
+            stalled += int(np.sum(stall))
+            if stall.any():
+                stall_rel = max(stall_rel, float(rel[stall].max()))
+            done = conv | stall
+            prev[cols] = rel
+        else:
+            done = np.zeros(cols.size, dtype=bool)
+        k[:, cols] = kn
+        active[cols[done]] = False
+    ok = fixed_iters is not None or not active.any()
+    return k, ZG, iters, stalled, stall_rel, ok
+
+
+def dmd_deim_gradient(U, Z, e, L, op, cfg):
+    """eq. grHDD: g^DD = U_V^T V_r + (q/m) U_X[I,:]^T (w * e_{j(X_r[I])}), with
+    e the cell field of the DMD potential Phi_DMD(t) (the gradient of the
+    Lambda^0(X_r) Phi_DMD term at the DEIM particles).  Only the d sampled
+    rows of X_r are formed."""
+    N = U.shape[0] // 2
+    XI = U[:N][op.idx, :] @ Z
+    j, _ = pic.cell_index(XI, L, cfg.Nx)
+    FI = (cfg.q / cfg.m) * e[j, np.arange(Z.shape[1])[None, :]]
+    return U[N:].T @ (U[N:] @ Z) + U[:N][op.idx, :].T @ (FI * op.w[:, None])
+
+
+def _prk_step_dmd(st, cfg, fixed_iters):
+    """One step of Alg. 2.  At the start of every step the exact potential of
+    the subset parameters S (Sec. 4.1) is computed with the basis velocity of
+    the subset; it enters the DMD window (eq. DMD_potential_Y_time) and the
+    DEIM snapshots Lambda^0(X_r) Phi (eq. Ydeim).  While the windows hold
+    fewer than T+1 levels the step is the plain reduced step (Alg. 2, first
+    T steps).  Afterwards:
+      k^1 = X(U0, Z0[S]) with the exact subset gradient G^{p*} (eq. UZredhyp);
+      k1  = J g^DD(U0, Z0, t_{tau-1});  U_half = R_{U0}(dt/2 k^1);
+      k2  = J g^DD(U_half, Z0 + dt/2 k2, t_{tau-1} + dt/2) by fixed point;
+      Z1  = Z0 + dt k2;
+      k^2 = Y(dt/2 k^1, Z_G[S]) with G^{p*} at (U_half, Z_G[S]);  U1 = R_{U0}(dt k^2).
+    On ENOCONV the state and both windows are unchanged."""
+    from . import deim as deim_mod
+    from . import dmd
+    S = st.subset
+    T = cfg.deim_window
+    U0, Z0, L = st.U, st.Z, st.L
+    dt = cfg.dt
+    saved = (list(st.window), list(st.phi_window), st.deim_indices, st.deim_psi,
+             st.deim_builds)
+
+    grS = gradient(U0, Z0[:, S], L[S], cfg.Nx, cfg.q, cfg.m)
+    st.phi_window.append(grS.Phi.copy())
+    st.window.append(deim_mod.snapshot(grS.Xr, grS.Phi, L[S]))
+    if len(st.window) > T + 1:
+        st.window.pop(0)
+        st.phi_window.pop(0)
+    if len(st.window) < T + 1:
+        st.deim_indices = None
+        status = _prk_step_core(st, replace_projection(cfg, "galerkin"), fixed_iters)
+        if status != OK:
+            st.window, st.phi_window = saved[0], saved[1]
+        return status
+
+    op = deim_mod.build_from_window(st, cfg)
+    if st.eta is None:
+        raise ValueError("dmd_deim needs the parameters eta for the interpolation")
+    dop = dmd.build_operator(st.phi_window, S, st.eta, dt, cfg.dmd_tol)
+    st.last_dmd_rank = dop.r
+    from . import pic as pic_mod
+    e0 = pic_mod.field(dmd.predict(dop, 0.0), L)
+    eh = pic_mod.field(dmd.predict(dop, 0.5 * dt), L)
+
+    J = J_small(cfg.two_n)
+    k1 = J @ dmd_deim_gradient(U0, Z0, e0, L, op, cfg)
+    kh1 = basis_velocity(U0, Z0[:, S], grS.G, cfg.pinv_rtol)
+    xi_half = 0.5 * dt * kh1
+    U_half = cayley(U0, xi_half)
+
+    def g_of(cols, Ze):
+        return dmd_deim_gradient(U_half, Ze, eh[:, cols], L[cols], op, cfg)
+
+    k, ZG, iters, stalled, stall_rel, ok = _fixed_point(Z0, k1, dt, cfg, fixed_iters, g_of)
+    st.last_iters, st.last_stalled, st.last_stall_rel = iters, stalled, stall_rel
+    if not ok:
+        st.window, st.phi_window = saved[0], saved[1]
+        st.deim_indices, st.deim_psi, st.deim_builds = saved[2], saved[3], saved[4]
+        st.last_status = ENOCONV
+        return ENOCONV
+
+    Z1 = Z0 + dt * k
+    grG = gradient(U_half, ZG[:, S], L[S], cfg.Nx, cfg.q, cfg.m)
+    kh2 = tangent_velocity(U0, xi_half, ZG[:, S], grG.G, cfg.pinv_rtol, Ux=U_half)
+    U1 = cayley(U0, dt * kh2)
+    if cfg.reorth:
+        U1, Z1 = reorthonormalise(U1, Z1)
+    st.U, st.Z = U1, Z1
+    st.step += 1
+    st.last_status = OK
+    return OK
+
+
+def replace_projection(cfg, projection):
+    c = RomConfig(**cfg.__dict__)
+    c.projection = projection
+    return c
 
 
 def run(st, cfg, steps):

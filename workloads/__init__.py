@@ -11,6 +11,7 @@ from .ensembles import (
     draw_parameters,
     load_particles,
     make_ensemble,
+    parameter_matrix,
 )
 
 __all__ = [
@@ -21,4 +22,5 @@ __all__ = [
     "draw_parameters",
     "load_particles",
     "make_ensemble",
+    "parameter_matrix",
 ]

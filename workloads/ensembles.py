@@ -78,6 +78,12 @@ def draw_parameters(w, seed=None):
     return dict(alpha=alpha, k=k, v0=v0, sigma=sigma, L=2.0 * math.pi / k)
 
 
+def parameter_matrix(params):
+    """eta as a 4 x p matrix (rows alpha, k, v0, sigma): the parameter
+    coordinates of every ensemble member, constant rows included."""
+    return np.stack([params["alpha"], params["k"], params["v0"], params["sigma"]]).astype(np.float64)
+
+
 def _invert_position(u, alpha, k):
     """x in [0, L) with (x + (alpha/k) sin kx)/L = u; all arrays broadcast."""
     L = 2.0 * np.pi / k
@@ -165,7 +171,7 @@ def load_particles(params, ux, uv, family):
 def make_ensemble(w, loading="philox", param_seed=None, particle_seed=None):
     """Parameters and initial particle states for workload ``w``.
 
-    Returns dict(params=..., L=(p,), X0=(N, p), V0=(N, p)).
+    Returns dict(params=..., L=(p,), X0=(N, p), V0=(N, p), eta=(4, p)).
     """
     params = draw_parameters(w, param_seed)
     if loading == "hammersley":
@@ -175,4 +181,4 @@ def make_ensemble(w, loading="philox", param_seed=None, particle_seed=None):
             particle_seed = 1000 * w["number"] + 2
         ux, uv = philox_uniforms(particle_seed, w["N"])
     X0, V0 = load_particles(params, ux, uv, w["family"])
-    return dict(params=params, L=params["L"].copy(), X0=X0, V0=V0)
+    return dict(params=params, L=params["L"].copy(), X0=X0, V0=V0, eta=parameter_matrix(params))
