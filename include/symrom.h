@@ -53,7 +53,7 @@ enum {
   SYMROM_ERANKCAP = -7    /* rank growth beyond two_n_max requested          */
 };
 
-enum { SYMROM_GALERKIN = 0, SYMROM_DEIM = 1 };
+enum { SYMROM_GALERKIN = 0, SYMROM_DEIM = 1, SYMROM_DMD_DEIM = 2 };
 
 typedef struct {
   int32_t N;             /* particles                                        */
@@ -63,7 +63,10 @@ typedef struct {
   int32_t two_n_max;     /* capacity for rank growth (even, >= two_n, <= 60) */
   double dt;             /* time step                                        */
   double q, m;           /* charge and mass (-1 and 1 in the paper)          */
-  int32_t projection;    /* SYMROM_GALERKIN or SYMROM_DEIM                   */
+  int32_t projection;    /* SYMROM_GALERKIN, SYMROM_DEIM (exact potential) or */
+                         /* SYMROM_DMD_DEIM (Alg. 2: DMD of the potential,  */
+                         /* DEIM of Lambda^0 Phi_DMD, basis evolved on the  */
+                         /* parameter subset of eq. pSampl)                 */
   int32_t deim_window;   /* T: DEIM snapshots of the last T+1 time levels    */
   double fp_tol;         /* fixed point: relative update threshold           */
   int32_t fp_max_iters;  /* fixed point: iteration cap (ENOCONV beyond)      */
@@ -89,7 +92,11 @@ typedef struct {
   int32_t deim_update_rows;  /* n_DEIM: positions chosen again in between    */
                          /* (those of the most rotated basis vectors, eq.    */
                          /* indices_adaptive_DEIM); the others are inherited */
+  int32_t p_star;        /* SYMROM_DMD_DEIM: size p* of the parameter subset */
+                         /* (Sec. 4.1; 0: p); p*(T+1) <= 64, p* T <= 48      */
   int32_t reserved;
+  double dmd_tol;        /* SYMROM_DMD_DEIM: relative singular value cut of  */
+                         /* Alg. 1, step 1 (0: 1e-5, the value of Sec. 6.1)  */
 } symrom_config;
 
 enum { SYMROM_FP64 = 0 };
@@ -163,8 +170,18 @@ symrom_status rom_init_family(const symrom_config* cfg, int32_t family, const do
  * and contraction steps); the largest update so accepted is
  * info->stall_rel.  With
  * rank_auto the rank is updated after every step (see rom_adapt_rank, target
- * 0).  info (host, nullable) describes the last step.  On ENOCONV the state
- * (U, Z and the DEIM snapshot window) is the one before the failing step. */
+ * 0).  With SYMROM_DMD_DEIM (Alg. 2) the first T steps are the plain
+ * reduced step, recording the snapshot and the potential of the subset S of
+ * eq. pSampl at the start of each; from then on the basis evolves with the
+ * exact gradient of S only (eq. UZredhyp), the coefficients of every
+ * parameter with the DMD-DEIM gradient of eq. grHDD: the potential predicted
+ * by the DMD of the last T+1 subset potentials (Alg. 1, eq.
+ * DMD_approx_potential_subset, coordinates interpolated over the parameters
+ * outside S), evaluated at the d DEIM particles (Sec. 4.2.2), at t_{tau-1}
+ * for the start value and t_{tau-1} + dt/2 for the implicit midpoint stage.
+ * info (host, nullable) describes the last step.  On ENOCONV the state
+ * (U, Z and the snapshot and potential windows) is the one before the
+ * failing step. */
 symrom_status rom_step(symrom_rom* h, int32_t nsteps, symrom_step_info* info);
 
 /* Replace the fixed-point controls of the following steps (fp_tol,
@@ -221,6 +238,27 @@ symrom_status rom_cells(symrom_rom* h, const double* Z, int32_t* cells, double* 
  * Psi^T 1 of eq. grHDD (device, capacity >= d); d (host, nullable).
  * Errors: ESTATE when no DEIM operator has been built yet. */
 symrom_status rom_deim_operator(symrom_rom* h, int32_t* idx, double* w, int32_t* d);
+
+/* SYMROM_DMD_DEIM: the ensemble's parameters for the Gaussian radial basis
+ * interpolation of the DMD coordinates over the parameters outside the
+ * subset (Sec. 4.2.1): eta (host, p x dim row-major, dim <= 8; e.g. alpha,
+ * k, v0, sigma).  Each coordinate is scaled to [0, 1] by its range over the
+ * ensemble; the kernel width is the median distance between subset nodes.
+ * rom_init_family sets them itself (dim 4); rom_init handles need this call
+ * before their first DMD-DEIM step (else that step fails with ESTATE).
+ * Errors: EINVAL (not a DMD-DEIM handle, dim, non-finite eta), ESINGULAR
+ * (interpolation matrix not positive definite: coincident subset nodes). */
+symrom_status rom_set_parameters(symrom_rom* h, const double* eta, int32_t dim);
+
+/* SYMROM_DMD_DEIM: the subset S of eq. pSampl (host int32, capacity >= p*,
+ * nullable) and p* (host, nullable); of the last DMD-DEIM step the DMD rank
+ * r (host, nullable), the eigenvalues of A_tol (Alg. 1; host, 2 r doubles
+ * re/im interleaved, nullable) and the predicted field tables e = (Phi_DMD
+ * (x_{j+1}) - Phi_DMD(x_j)) / h of every parameter at t_{tau-1} (e0) and at
+ * t_{tau-1} + dt/2 (eh) (device, p x Nx row-major, nullable).  Errors:
+ * ESTATE (not a DMD-DEIM handle). */
+symrom_status rom_dmd_state(symrom_rom* h, int32_t* S, int32_t* pstar, int32_t* rank, double* lam,
+                            double* e0, double* eh);
 
 /* Per-parameter electric energy E(X_r^i) (eq. HamEEfull) and Hamiltonian
  * H = 1/2 |V_r^i|^2 + E (device [p] each). */

@@ -128,6 +128,8 @@ class RomState:
     subset: Optional[np.ndarray] = None     # S_{p*}, fixed at t = 0 (dmd_deim)
     phi_window: list = dc_field(default_factory=list)   # subset potentials (N_x x p*)
     last_dmd_rank: int = 0
+    last_dmd: object = None                 # DMD operator of the last DMD-DEIM step
+    last_dmd_tables: object = None          # its field tables (e at t_{tau-1}, at + dt/2)
 
 
 # ----------------------------------------------------------------------------
@@ -488,6 +490,7 @@ def _prk_step_dmd(st, cfg, fixed_iters):
     from . import pic as pic_mod
     e0 = pic_mod.field(dmd.predict(dop, 0.0), L)
     eh = pic_mod.field(dmd.predict(dop, 0.5 * dt), L)
+    st.last_dmd, st.last_dmd_tables = dop, (e0, eh)
 
     J = J_small(cfg.two_n)
     k1 = J @ dmd_deim_gradient(U0, Z0, e0, L, op, cfg)

@@ -7,7 +7,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libsymrom.so")
 SOURCES = ["pic_kernels.hip", "rom_kernels.hip", "dense_kernels.hip", "ensemble_kernels.hip",
-           "api.hip", "server.cpp"]
+           "dmd_kernels.hip", "api.hip", "server.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

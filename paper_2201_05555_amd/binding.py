@@ -17,9 +17,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libsymrom.so")
 
 OK, EINVAL, ENOMEM, ESINGULAR, ENOCONV, EDEVICE, ESTATE, ERANKCAP = 0, -1, -2, -3, -4, -5, -6, -7
-GALERKIN, DEIM = 0, 1
+GALERKIN, DEIM, DMD_DEIM = 0, 1, 2
+PROJECTIONS = {"galerkin": GALERKIN, "deim": DEIM, "dmd_deim": DMD_DEIM}
 FAMILIES = {"deposit": 0, "gather": 1, "poisson": 2, "fom_push": 3, "basis": 4, "dense": 5,
-            "deim_eig": 6, "gather_xi": 7, "deim_chain": 8}
+            "deim_eig": 6, "gather_xi": 7, "deim_chain": 8, "dmd_chain": 9, "dmd_fixed_point": 10}
 
 
 class SymromError(RuntimeError):
@@ -41,7 +42,7 @@ class Config(ctypes.Structure):
         ("rank_tol_down", ctypes.c_double), ("deim_rows", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("deterministic", ctypes.c_int32),
         ("deim_update_every", ctypes.c_int32), ("deim_update_rows", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("p_star", ctypes.c_int32), ("reserved", ctypes.c_int32), ("dmd_tol", ctypes.c_double),
     ]
 
 
@@ -88,6 +89,9 @@ _SIGS = {
     "rom_reconstruct_rows": (ctypes.c_int32, [_VP, _VP, ctypes.c_int32, _VP, _VP]),
     "rom_cells": (ctypes.c_int32, [_VP, _VP, _VP, _VP]),
     "rom_deim_operator": (ctypes.c_int32, [_VP, _VP, _VP, ctypes.POINTER(ctypes.c_int32)]),
+    "rom_set_parameters": (ctypes.c_int32, [_VP, _VP, ctypes.c_int32]),
+    "rom_dmd_state": (ctypes.c_int32, [_VP, _VP, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32), _VP, _VP, _VP]),
     "deim_select_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "deim_select": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP, _VP,
                                      ctypes.c_size_t, _VP]),
@@ -198,15 +202,16 @@ def make_config(N, p, Nx, two_n, two_n_max=None, dt=0.05, q=-1.0, m=1.0, project
                 deim_window=3, fp_tol=1e-9, fp_max_iters=100, fp_fixed_iters=0, pinv_rtol=1e-12,
                 reorth=True, rank_auto=False, rank_tol_up=1e-2, fp_stall_tol=1e-3,
                 rank_tol_down=1e-8, deim_rows=0, deterministic=False, deim_update_every=1,
-                deim_update_rows=0):
+                deim_update_rows=0, p_star=0, dmd_tol=1e-5):
     return Config(N=N, p=p, Nx=Nx, two_n=two_n, two_n_max=two_n_max or two_n, dt=dt, q=q, m=m,
-                  projection=DEIM if projection == "deim" else GALERKIN,
+                  projection=PROJECTIONS[projection],
                   deim_window=deim_window, fp_tol=fp_tol, fp_max_iters=fp_max_iters,
                   fp_fixed_iters=fp_fixed_iters, pinv_rtol=pinv_rtol, reorth=int(reorth),
                   rank_auto=int(rank_auto), rank_tol_up=rank_tol_up, fp_stall_tol=fp_stall_tol,
                   rank_tol_down=rank_tol_down, deim_rows=deim_rows, precision=0,
                   deterministic=int(deterministic), deim_update_every=deim_update_every,
-                  deim_update_rows=deim_update_rows, reserved=0)
+                  deim_update_rows=deim_update_rows, p_star=p_star, reserved=0,
+                  dmd_tol=dmd_tol)
 
 
 def _info_dict(info):
@@ -360,6 +365,28 @@ class Rom:
         d = ctypes.c_int32()
         _check(lib().rom_deim_operator(self.h, _ptr(idx), _ptr(w), ctypes.byref(d)))
         return idx[: d.value], w[: d.value]
+
+    def set_parameters(self, eta):
+        """Parameters of the ensemble (dim x p host array, e.g. rows alpha, k,
+        v0, sigma) for the radial basis interpolation of DMD-DEIM."""
+        eta = np.ascontiguousarray(np.asarray(eta, dtype=np.float64).T)
+        _check(lib().rom_set_parameters(self.h, eta.ctypes.data_as(ctypes.c_void_p),
+                                        eta.shape[1]))
+
+    def dmd_state(self):
+        """(subset S (numpy int), DMD rank r, eigenvalues (numpy complex, r),
+        field tables e0, eh (p, Nx) device tensors) of the last DMD-DEIM step."""
+        S = np.zeros(64, dtype=np.int32)
+        ps = ctypes.c_int32()
+        rk = ctypes.c_int32()
+        lam = np.zeros(2 * 64, dtype=np.float64)
+        e0 = torch.empty((self.cfg.p, self.cfg.Nx), dtype=torch.float64, device="cuda")
+        eh = torch.empty_like(e0)
+        _check(lib().rom_dmd_state(self.h, S.ctypes.data_as(ctypes.c_void_p), ctypes.byref(ps),
+                                   ctypes.byref(rk), lam.ctypes.data_as(ctypes.c_void_p),
+                                   _ptr(e0), _ptr(eh)))
+        r = rk.value
+        return (S[: ps.value].astype(np.int64), r, lam[0:2 * r:2] + 1j * lam[1:2 * r:2], e0, eh)
 
     def diagnostics(self):
         E = torch.empty(self.cfg.p, dtype=torch.float64, device="cuda")

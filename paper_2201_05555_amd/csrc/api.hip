@@ -66,10 +66,10 @@ struct TimedLaunch {
 bool g_timing = false;
 std::vector<TimedLaunch> g_pending;
 std::vector<hipEvent_t> g_event_pool;
-double g_ms[9] = {0};
-int64_t g_launches[9] = {0};
-double g_flops[9] = {0};
-double g_bytes[9] = {0};
+double g_ms[16] = {0};
+int64_t g_launches[16] = {0};
+double g_flops[16] = {0};
+double g_bytes[16] = {0};
 
 hipEvent_t take_event() {
   if (!g_event_pool.empty()) {
@@ -129,7 +129,9 @@ enum {
   FAM_EIG = 6,
   FAM_XI = 7,
   FAM_CHAIN = 8,
-  NFAM = 9
+  FAM_DMD = 9,     // DMD of the subset potentials and the predicted field tables
+  FAM_DMDFP = 10,  // the fused fixed point with the DMD-DEIM gradient
+  NFAM = 11
 };
 
 extern "C" void symrom_set_timing(int32_t on) {
@@ -635,6 +637,25 @@ struct symrom_rom {
   int dbuf[2];
   int* forced;
   double* rotpart;
+  // DMD-DEIM (Alg. 2).  The subset S of eq. pSampl sits in `sub` (psub = p*
+  // entries, chosen at initialisation); sub_id is the identity of the
+  // compact subset.  bs, gdep_s, ggat_s: the per-parameter buffers and
+  // launch shapes of the p* compact columns Zs, used for the exact gradient
+  // of the basis evolution.  phiw: the window levels of the subset
+  // potentials (nslots blocks of p* x Nx, in the slots of the snapshot ring).
+  int* sub_id;
+  PicBufs bs;
+  PicGeom gdep_s, ggat_s;
+  cplx* Zs;
+  double* phiw;
+  DmdChainArgs dmd;
+  double *e0, *eh;     // predicted field tables (p x Nx)
+  double* beta;        // radial basis weights (p x p*)
+  int* member;
+  double* dmin;
+  double* eta;         // parameters (p x eta_dim)
+  int eta_dim;
+  bool beta_ready;
   cplx* Ysub;    // Rayleigh-Ritz eigenvectors of the subspace iteration (64 x 64)
   cplx* Wsub;    // its p x 64 block of vectors (p > 64)
   double* lamsub;
@@ -646,6 +667,8 @@ namespace {
 // i_k = floor(k p / p*), p* = min(p, max(8, ceil(two_n_max / (T+1)))) so that
 // the snapshot matrix (N x p*(T+1)) has at least d = 2n <= two_n_max columns.
 int deim_psub(const symrom_config& c) {
+  // DMD-DEIM: the subset of eq. pSampl, p* columns (all of them when 0)
+  if (c.projection == SYMROM_DMD_DEIM) return (c.p_star > 0 && c.p_star < c.p) ? c.p_star : c.p;
   const int T1 = c.deim_window + 1;
   int ps = (c.two_n_max + T1 - 1) / T1;
   if (ps < 8) ps = 8;
@@ -716,11 +739,12 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.nbg = 256;
   r.nbc = 64;
   r.sub = ar.take<int>(r.psub);
-  r.Ywin = ar.take<double>(r.cfg.projection == SYMROM_DEIM ? (size_t)P * N : 0);
+  const bool dei = r.cfg.projection != SYMROM_GALERKIN;
+  r.Ywin = ar.take<double>(dei ? (size_t)P * N : 0);
   // the DEIM basis and indices of two consecutive operators (the adaptive
   // update reads the previous ones): operator b uses buffer b % 2
   for (int q = 0; q < 2; ++q) {
-    r.Psib[q] = ar.take<double>(r.cfg.projection == SYMROM_DEIM ? (size_t)dmax * N : 0);
+    r.Psib[q] = ar.take<double>(dei ? (size_t)dmax * N : 0);
     r.didxb[q] = ar.take<int>(dmax);
   }
   r.Psi = r.Psib[0];
@@ -730,8 +754,8 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.dw = ar.take<double>(dmax);
   r.dc = ar.take<double>(dmax);
   r.bval = ar.take<double>(2 * (size_t)r.nbg);
-  r.dB = ar.take<double>(r.cfg.projection == SYMROM_DEIM ? 2 * 64 * 64 : 0);
-  r.dcv = ar.take<double>(r.cfg.projection == SYMROM_DEIM ? 2 * 64 : 0);
+  r.dB = ar.take<double>(dei ? 2 * 64 * 64 : 0);
+  r.dcv = ar.take<double>(dei ? 2 * 64 : 0);
   r.bidx = ar.take<int>(2 * (size_t)r.nbg);
   r.colpart = ar.take<double>((size_t)psi_blocks(r.N) * dmax);
   r.Mdeim = ar.take<double>((size_t)P * dmax);
@@ -745,7 +769,41 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.Ysub = ar.take<cplx>(64 * 64);
   r.Wsub = ar.take<cplx>(p > 64 ? (size_t)p * 64 : 0);
   r.lamsub = ar.take<double>(64);
-  r.dpart = ar.take<double>(r.cfg.projection == SYMROM_DEIM ? (size_t)r.nkb * 64 * 64 * 2 : 0);
+  r.dpart = ar.take<double>(dei ? (size_t)r.nkb * 64 * 64 * 2 : 0);
+  // DMD-DEIM
+  const bool dm = r.cfg.projection == SYMROM_DMD_DEIM;
+  const int ps = r.psub, T = r.cfg.deim_window, Pd = ps * T;
+  r.sub_id = ar.take<int>(ps);
+  r.gdep_s = pic_geom(N, ps, Nx, 16 * 1024, 256);
+  r.ggat_s = pic_geom(N, ps, Nx, 64 * 1024, 256);
+  r.bs = carve_pic(ar, dm ? N : 1, dm ? ps : 1, Nx,
+                   r.gdep_s.nrb >= r.ggat_s.nrb ? r.gdep_s : r.ggat_s);
+  r.Zs = ar.take<cplx>(dm ? (size_t)nm * ps : 0);
+  r.phiw = ar.take<double>(dm ? (size_t)r.nslots * ps * Nx : 0);
+  DmdChainArgs& c = r.dmd;
+  c = DmdChainArgs{};
+  const size_t nxp = dm ? (size_t)Nx * Pd : 0, pp = dm ? (size_t)Pd * Pd : 0;
+  c.Y = ar.take<double>(nxp);
+  c.Yp = ar.take<double>(nxp);
+  c.W = ar.take<double>(nxp);
+  c.sig = ar.take<double>(dm ? Pd : 0);
+  c.V = ar.take<double>(pp);
+  c.rdev = ar.take<int>(dm ? 4 : 0);
+  c.B = ar.take<double>(nxp);
+  c.U = ar.take<double>(nxp);
+  c.A = ar.take<double>(pp);
+  c.M = ar.take<double>(pp);
+  c.lam = ar.take<cplx>(dm ? Pd : 0);
+  c.Wb = ar.take<double>(nxp);
+  c.Wf = ar.take<double>(dm ? (size_t)Nx * ps : 0);
+  c.C = ar.take<double>(dm ? (size_t)Pd * ps : 0);
+  c.BM = ar.take<double>(nxp);
+  r.e0 = ar.take<double>(dm ? (size_t)p * Nx : 0);
+  r.eh = ar.take<double>(dm ? (size_t)p * Nx : 0);
+  r.beta = ar.take<double>(dm ? (size_t)p * ps : 0);
+  r.member = ar.take<int>(dm ? p : 0);
+  r.dmin = ar.take<double>(dm ? p : 0);
+  r.eta = ar.take<double>(dm ? (size_t)8 * p : 0);
 }
 
 bool valid_rom_config(const symrom_config* c, std::string& why) {
@@ -777,7 +835,8 @@ bool valid_rom_config(const symrom_config* c, std::string& why) {
     why = "fixed-point limits";
     return false;
   }
-  if (c->projection != SYMROM_GALERKIN && c->projection != SYMROM_DEIM) {
+  if (c->projection != SYMROM_GALERKIN && c->projection != SYMROM_DEIM &&
+      c->projection != SYMROM_DMD_DEIM) {
     why = "projection";
     return false;
   }
@@ -804,6 +863,29 @@ bool valid_rom_config(const symrom_config* c, std::string& why) {
   if (c->p > 4096) {
     why = "p above 4096 is not supported";
     return false;
+  }
+  if (c->projection == SYMROM_DMD_DEIM) {
+    const int ps = deim_psub(*c), T = c->deim_window;
+    if (T < 1 || T > 7) {
+      why = "DMD-DEIM needs deim_window (T) in 1..7";
+      return false;
+    }
+    if (c->p_star < 0 || ps * (T + 1) > 64 || ps * T > 48) {
+      why = "DMD-DEIM needs p* (T+1) <= 64 and p* T <= 48";
+      return false;
+    }
+    if (c->rank_auto) {
+      why = "automatic rank adaptation is not built for DMD-DEIM";
+      return false;
+    }
+    if (!(c->dmd_tol >= 0.0) || !(c->dmd_tol < 1.0)) {
+      why = "dmd_tol must be in [0, 1)";
+      return false;
+    }
+    if (c->two_n_max > 60) {
+      why = "two_n_max above 60";
+      return false;
+    }
   }
   if (c->projection == SYMROM_DEIM) {
     if (c->deim_window < 0 || c->deim_window > 7) {
@@ -1038,6 +1120,10 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z, bool redo = false,
   {
     Timer t(FAM_CHAIN, s);
     launch_snapshot(s, U, N, n, Z, r.sub, r.psub, r.Nx, r.b.factor, r.b.phi, Ys, stop);
+    // DMD-DEIM: the subset potentials of this level into the same slot of
+    // the potential window (eq. DMD_potential_Y_time)
+    if (r.cfg.projection == SYMROM_DMD_DEIM)
+      launch_grid_rows(s, r.b.phi, r.sub, r.psub, r.Nx, r.phiw + (size_t)slot * r.psub * r.Nx);
   }
   if (!redo) r.win_count++;
   const int P = r.psub * r.nslots;
@@ -1139,6 +1225,47 @@ void launch_shrink_cert(symrom_rom& r) {
   launch_dense_rank_cert(r.s, r.Z0, r.n, r.p, c, r.status + 13);
 }
 
+// The end of a step: the tangent velocity Y(xi_half, Z_G) from the basis
+// velocity in Xv (Sec. 5), xi_1 = dt Y, and U1 = R_{U0}(xi_1) into Uh with
+// the re-orthonormalisation applied to Z1.
+void tangent_retract(symrom_rom& r) {
+  hipStream_t s = r.s;
+  const int n = r.n, N = r.N;
+  const double dt = r.cfg.dt;
+  bool gram_ready = false;
+  if (4 * n <= 64) {
+    // one Gram of [U0, xi, U_half, X] and one row combination (the
+    // intermediate Ups is never formed)
+    Timer t(FAM_BASIS, s);
+    launch_gemm_ah_b(s, ml(r.U0, n, r.Xi, n, r.Uh, n, r.Xv, n), 4 * n,
+                     ml(r.U0, n, r.Xi, n, r.Uh, n, r.Xv, n), 4 * n, false, N, r.nkb, r.gemm_part,
+                     r.Gram);
+    launch_dense_tangent(s, r.Gram, n, dt, r.M1, r.M2, r.M3, r.flags);
+    // xi_1, and in the same pass the Gram of [U0, xi_1] for the retraction
+    gram_ready = launch_rowgemm_gram(s, rt(r.Xv, r.M1, n, r.Xi, r.M2, n, r.U0, r.M3, n), N, n,
+                                     r.P, r.gemm_part, (size_t)r.nkb * 64 * 64, r.Gram, r.U0, n);
+    if (!gram_ready)
+      launch_rowgemm(s, rt(r.Xv, r.M1, n, r.Xi, r.M2, n, r.U0, r.M3, n), N, n, r.P);
+  } else {
+    Timer t(FAM_BASIS, s);
+    launch_gemm_ah_b(s, ml(r.U0, n, r.Xi, n), 2 * n, ml(r.Xv, n, r.Uh, n), 2 * n, false, N,
+                     r.nkb, r.gemm_part, r.Gram);
+    launch_dense_tangent1(s, r.Amat, r.Gram, n, r.M1, r.M2, r.M3, r.C0x, r.flags);
+    launch_rowgemm(s, rt(r.Xv, r.M1, n, r.Xi, r.M2, n, r.U0, r.M3, n), N, n, r.Ups);
+    launch_gemm_ah_b(s, ml(r.Uh, n, r.U0, n), 2 * n, ml(r.Ups, n), n, false, N, r.nkb,
+                     r.gemm_part, r.Gram);
+    launch_dense_tangent2(s, r.Gram, r.C0x, n, dt, r.M1, r.M2, r.flags);
+    launch_rowgemm(s, rt(r.Ups, r.M1, n, r.U0, r.M2, n), N, n, r.P);  // xi_1 = dt Y
+  }
+  // U1 = R_{U0}(xi_1)  (into Uh, free now)
+  if (r.cfg.reorth && 4 * n <= 64) {
+    cayley_cholqr2(r, r.U0, r.P, r.Uh, r.M3, r.Z1, gram_ready);
+  } else {
+    cayley(r, r.U0, r.P, r.Uh, r.M3, gram_ready);
+    if (r.cfg.reorth) cholqr2(r, r.Uh, r.Z1);
+  }
+}
+
 // One step of the reduced model; with decide_rank, the rank indicator at the
 // new state and a growth by one pair when it exceeds the threshold.
 symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
@@ -1148,12 +1275,15 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   // (word 3 belongs to a head that may be running on the second stream)
   HIPCHK(hipMemsetAsync(r.flags, 0, 3 * sizeof(int), s));
   const bool use_deim = r.cfg.projection == SYMROM_DEIM;
+  // DMD-DEIM before its windows are full (Alg. 2, first T steps): the plain
+  // reduced step, recording the snapshot and the subset potentials
+  const bool record = r.cfg.projection == SYMROM_DMD_DEIM;
   // stage 1 at (U0, Z0): full gradient, k1 = J g, basis velocity -> xi_half
   if (!r.stage1_cached) full_gradient(r, r.U0, r.Z0, nullptr, true);
   r.stage1_cached = false;
   // the DEIM chain is already enqueued when it was built ahead for this rank
   const bool chain_ready = use_deim && r.head_pending && r.head_n == n;
-  if (use_deim && !chain_ready) {
+  if ((use_deim && !chain_ready) || record) {
     // the DEIM chain needs the first-stage field; it runs beside the basis
     // velocity, the Gram matrices of the linear part and the Cayley map
     HIPCHK(hipEventRecord(r.ev_fork, s));
@@ -1165,7 +1295,7 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   // (the eigensolver keeps one CU busy for a while: enqueue part of the main
   // work before the rest of the chain, so that both streams have work)
   basis_velocity(r, r.U0, r.Z0, 0.5 * dt, r.Xi, deim ? nullptr : r.k);
-  if (use_deim && !chain_ready) {
+  if ((use_deim && !chain_ready) || record) {
     deim_update_tail(r);
     HIPCHK(hipEventRecord(r.ev_join, r.s2));
   }
@@ -1173,7 +1303,7 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   // U_half = R_{U0}(xi_half)
   cayley(r, r.U0, r.Xi, r.Uh, r.Amat);
   if (deim) linear_grams(r, r.Uh, r.C12);
-  if (use_deim) HIPCHK(hipStreamWaitEvent(s, r.ev_join, 0));
+  if (use_deim || record) HIPCHK(hipStreamWaitEvent(s, r.ev_join, 0));
   // fixed point for k2 at U_half: start values (with DEIM in the launch that
   // gathers the first stage's gradient)
   if (deim) {
@@ -1264,7 +1394,7 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
     // snapshot of this step (counted in win_count whether it was taken now
     // or ahead of the step, and written into the slot of the oldest one,
     // which the next attempt at this step drops again) is taken back
-    if (use_deim) {
+    if (use_deim || record) {
       r.win_count--;
       r.deim_on = r.win_count >= r.nslots;
     }
@@ -1287,39 +1417,7 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   full_gradient(r, r.Uh, r.ZG, nullptr, false);
   if (side) HIPCHK(hipStreamWaitEvent(s, r.ev_sp1, 0));
   basis_velocity(r, r.Uh, r.ZG, 1.0, r.Xv, nullptr, side);
-  // tangent velocity Y(xi_half, Z_G)
-  bool gram_ready = false;
-  if (4 * n <= 64) {
-    // one Gram of [U0, xi, U_half, X] and one row combination (the
-    // intermediate Ups is never formed)
-    Timer t(FAM_BASIS, s);
-    launch_gemm_ah_b(s, ml(r.U0, n, r.Xi, n, r.Uh, n, r.Xv, n), 4 * n,
-                     ml(r.U0, n, r.Xi, n, r.Uh, n, r.Xv, n), 4 * n, false, N, r.nkb, r.gemm_part,
-                     r.Gram);
-    launch_dense_tangent(s, r.Gram, n, dt, r.M1, r.M2, r.M3, r.flags);
-    // xi_1, and in the same pass the Gram of [U0, xi_1] for the retraction
-    gram_ready = launch_rowgemm_gram(s, rt(r.Xv, r.M1, n, r.Xi, r.M2, n, r.U0, r.M3, n), N, n,
-                                     r.P, r.gemm_part, (size_t)r.nkb * 64 * 64, r.Gram, r.U0, n);
-    if (!gram_ready)
-      launch_rowgemm(s, rt(r.Xv, r.M1, n, r.Xi, r.M2, n, r.U0, r.M3, n), N, n, r.P);
-  } else {
-    Timer t(FAM_BASIS, s);
-    launch_gemm_ah_b(s, ml(r.U0, n, r.Xi, n), 2 * n, ml(r.Xv, n, r.Uh, n), 2 * n, false, N,
-                     r.nkb, r.gemm_part, r.Gram);
-    launch_dense_tangent1(s, r.Amat, r.Gram, n, r.M1, r.M2, r.M3, r.C0x, r.flags);
-    launch_rowgemm(s, rt(r.Xv, r.M1, n, r.Xi, r.M2, n, r.U0, r.M3, n), N, n, r.Ups);
-    launch_gemm_ah_b(s, ml(r.Uh, n, r.U0, n), 2 * n, ml(r.Ups, n), n, false, N, r.nkb,
-                     r.gemm_part, r.Gram);
-    launch_dense_tangent2(s, r.Gram, r.C0x, n, dt, r.M1, r.M2, r.flags);
-    launch_rowgemm(s, rt(r.Ups, r.M1, n, r.U0, r.M2, n), N, n, r.P);  // xi_1 = dt Y
-  }
-  // U1 = R_{U0}(xi_1)  (into Uh, free now)
-  if (r.cfg.reorth && 4 * n <= 64) {
-    cayley_cholqr2(r, r.U0, r.P, r.Uh, r.M3, r.Z1, gram_ready);
-  } else {
-    cayley(r, r.U0, r.P, r.Uh, r.M3, gram_ready);
-    if (r.cfg.reorth) cholqr2(r, r.Uh, r.Z1);
-  }
+  tangent_retract(r);
   // Commit by exchanging buffers before the flags are known, and with rank
   // adaptation enqueue the indicator's gradient at the new state behind it,
   // so that one readback serves both; a failed step exchanges them back.
@@ -1327,7 +1425,7 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   std::swap(r.Z0, r.Z1);
   // (the step's error words are final here)
   const bool ahead = use_deim && decide_rank;
-  if (use_deim && !decide_rank) launch_fold_status(s, r.status);
+  if ((use_deim || record) && !decide_rank) launch_fold_status(s, r.status);
   if (decide_rank) {
     // the field at the new state (its deposit also does the status
     // bookkeeping with DEIM), then (beside the DEIM chain ahead, which needs
@@ -1368,6 +1466,7 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
       r.win_count--;
       r.deim_on = r.win_count >= r.nslots;
     }
+    if (record) r.win_count--;  // the recorded level is taken back
     return fail(SYMROM_ESINGULAR, "singular small matrix in the basis update");
   }
   r.step++;
@@ -1384,6 +1483,166 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   if (r.head_pending) HIPCHK(hipStreamSynchronize(r.s2));
   HIPCHK(hipMemsetAsync(r.flags, 0, 2 * sizeof(int), s));
   return rom_grow_apply(r, 1);
+}
+
+// The handle's per-parameter buffers and sizes made those of the compact
+// subset S (Sec. 4.1) for the exact gradient of the basis evolution; the
+// whole ensemble is restored at the end of the scope.
+struct SubsetView {
+  symrom_rom& r;
+  int p;
+  PicBufs b;
+  PicGeom gdep, ggat;
+  int* sub;
+  explicit SubsetView(symrom_rom& rr)
+      : r(rr), p(rr.p), b(rr.b), gdep(rr.gdep), ggat(rr.ggat), sub(rr.sub) {
+    r.p = r.psub;
+    r.b = r.bs;
+    r.gdep = r.gdep_s;
+    r.ggat = r.ggat_s;
+    r.sub = r.sub_id;
+    r.n_active = r.psub;
+  }
+  ~SubsetView() {
+    r.p = p;
+    r.b = b;
+    r.gdep = gdep;
+    r.ggat = ggat;
+    r.sub = sub;
+    r.n_active = p;
+  }
+};
+
+// One step of Alg. 2 once the windows hold T+1 levels (Sec. 4.3, eq.
+// UZredhyp; the scheme of Sec. 5):
+//   stage 1: the exact gradient of the subset at (U0, Z0[S]) gives the
+//     snapshot and potential level of this step and k^1 = X(U0, Z0[S]);
+//     U_half = R_{U0}(dt/2 k^1);
+//   second stream: DEIM operator (snapshot Gram, Psi, indices, weights) and
+//     DMD of the potential window, then the predicted field tables of every
+//     parameter at t_{tau-1} and t_{tau-1} + dt/2;
+//   the fixed point of every column with the DMD-DEIM gradient (one launch,
+//     no deposit over the particles);
+//   stage 2: the exact gradient of the subset at (U_half, Z_G[S]), the basis
+//     velocity, the tangent velocity and the retraction with the
+//     re-orthonormalisation of U1 and Z1 = Z0 + dt k.
+// One readback per step: the error words and the fixed-point counters.
+symrom_status rom_step_dmd(symrom_rom& r) {
+  hipStream_t s = r.s;
+  const int n = r.n, p = r.p, N = r.N, ps = r.psub;
+  const double dt = r.cfg.dt;
+  if (!r.beta_ready)
+    return fail(SYMROM_ESTATE, "rom_step: DMD-DEIM needs the parameters (rom_set_parameters)");
+  HIPCHK(hipMemsetAsync(r.flags, 0, 3 * sizeof(int), s));
+  // counters: columns left, stalled, iterations, stall maximum
+  HIPCHK(hipMemsetAsync(r.counters, 0, 8 * sizeof(int), s));
+  launch_gather_zcols(s, r.Z0, n, r.sub, ps, r.Zs);
+  {
+    SubsetView v(r);
+    full_gradient(r, r.U0, r.Zs, nullptr, true);
+    HIPCHK(hipEventRecord(r.ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(r.s2, r.ev_fork, 0));
+    deim_update(r, r.U0, r.Zs);
+    basis_velocity(r, r.U0, r.Zs, 0.5 * dt, r.Xi, nullptr);
+  }
+  deim_update_tail(r);
+  {
+    // the DMD of the window (levels win_count - nslots .. win_count - 1)
+    Timer t(FAM_DMD, r.s2);
+    DmdChainArgs c = r.dmd;
+    c.ring = r.phiw;
+    c.nslots = r.nslots;
+    c.base = r.win_count % r.nslots;
+    c.pstar = ps;
+    c.T = r.cfg.deim_window;
+    c.Nx = r.Nx;
+    c.tol = r.cfg.dmd_tol > 0.0 ? r.cfg.dmd_tol : 1e-5;
+    c.flags = r.flags + 3;
+    launch_dmd_operator(r.s2, c);
+    launch_dmd_tables(r.s2, c, p, r.beta, r.b.h, r.e0, r.eh);
+  }
+  HIPCHK(hipEventRecord(r.ev_join, r.s2));
+  linear_grams(r, r.U0, r.C12a);
+  cayley(r, r.U0, r.Xi, r.Uh, r.Amat);
+  linear_grams(r, r.Uh, r.C12);
+  HIPCHK(hipStreamWaitEvent(s, r.ev_join, 0));
+  {
+    const int fixed = r.cfg.fp_fixed_iters;
+    Timer t(FAM_DMDFP, s);
+    DmdFpArgs a{};
+    a.U0 = r.U0;
+    a.Uh = r.Uh;
+    a.N = N;
+    a.n = n;
+    a.idx = r.didx;
+    a.w = r.dw;
+    a.d = r.d_cur;
+    a.Z0 = r.Z0;
+    a.factor = r.b.factor;
+    a.e0 = r.e0;
+    a.eh = r.eh;
+    a.Nx = r.Nx;
+    a.qm = r.cfg.q / r.cfg.m;
+    a.C12a = r.C12a;
+    a.C12 = r.C12;
+    a.dt = dt;
+    a.tol = r.cfg.fp_tol;
+    a.stall_tol = r.cfg.fp_stall_tol;
+    a.max_iters = r.cfg.fp_max_iters;
+    a.fixed = fixed > 0 ? fixed : 0;
+    a.k = r.k;
+    a.ZG = r.ZG;
+    a.prev = r.prev;
+    a.active = r.active;
+    a.counters = r.counters;
+    launch_dmd_fp(s, a, p);
+  }
+  {
+    Timer t(FAM_DENSE, s);
+    launch_dense_finish_z(s, r.Z0, r.k, n, p, dt, r.Z1);
+  }
+  // stage 2: the subset's exact gradient at (U_half, Z_G[S]) and its basis velocity
+  launch_gather_zcols(s, r.ZG, n, r.sub, ps, r.Zs);
+  {
+    SubsetView v(r);
+    full_gradient(r, r.Uh, r.Zs, nullptr, true);
+    basis_velocity(r, r.Uh, r.Zs, 1.0, r.Xv, nullptr);
+  }
+  tangent_retract(r);
+  std::swap(r.U0, r.Uh);
+  std::swap(r.Z0, r.Z1);
+  launch_fold_status(s, r.status);
+  HIPCHK(hipMemcpyAsync(r.hstat, r.status, 14 * sizeof(int), hipMemcpyDeviceToHost, s));
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  const int fl0 = r.hstat[0] | r.hstat[2];
+  r.last.iters = r.hstat[6];
+  r.last.stalled = r.hstat[5];
+  std::memcpy(&r.last.stall_rel, r.hstat + 10, sizeof(double));
+  r.last.deim_active = 1;
+  r.last.shrunk = 0;
+  r.last.unconverged = 0;
+  r.last.worst_rel = 0.0;
+  if (r.hstat[4] > 0 || fl0) {
+    std::swap(r.U0, r.Uh);
+    std::swap(r.Z0, r.Z1);
+    r.win_count--;
+    r.deim_on = r.win_count >= r.nslots;
+    if (fl0) return fail(SYMROM_ESINGULAR, "singular small matrix in the DMD-DEIM step");
+    std::vector<int> act(p);
+    std::vector<double> pv(p);
+    if (hipMemcpy(act.data(), r.active, p * sizeof(int), hipMemcpyDeviceToHost) == hipSuccess &&
+        hipMemcpy(pv.data(), r.prev, p * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess) {
+      for (int i = 0; i < p; ++i)
+        if (act[i]) {
+          r.last.unconverged++;
+          r.last.worst_rel = std::max(r.last.worst_rel, pv[i]);
+        }
+    }
+    return fail(SYMROM_ENOCONV, "fixed point not converged");
+  }
+  r.step++;
+  return SYMROM_OK;
 }
 }  // namespace
 
@@ -1517,14 +1776,22 @@ symrom_status topeig_subspace(symrom_rom& r, const cplx* A, int p, int k, cplx* 
 
 namespace {
 // fill(r): writes C0 = X0 + i V0 into r.G on r.s
+symrom_status set_parameters(symrom_rom& r, const double* eta, int dim);
+
 symrom_status rom_init_impl(const symrom_config* cfg, const double* L,
-                            const std::function<bool(symrom_rom&)>& fill, void* ws,
-                            size_t ws_bytes, void* stream, symrom_rom** out) {
+                            const std::function<bool(symrom_rom&)>& fill, const double* eta4,
+                            void* ws, size_t ws_bytes, void* stream, symrom_rom** out) {
   std::string why;
   if (!valid_rom_config(cfg, why)) return fail(SYMROM_EINVAL, "rom_init: " + why);
   if (!L || !out) return fail(SYMROM_EINVAL, "rom_init: null pointer");
   for (int i = 0; i < cfg->p; ++i)
     if (!(L[i] > 0.0) || !std::isfinite(L[i])) return fail(SYMROM_EINVAL, "rom_init: bad L");
+  // the DMD of the potential treats the potentials of all parameters as
+  // vectors on one grid (Sec. 4.2.1: the potential depends on the parameter
+  // only through the state)
+  if (cfg->projection == SYMROM_DMD_DEIM)
+    for (int i = 1; i < cfg->p; ++i)
+      if (L[i] != L[0]) return fail(SYMROM_EINVAL, "rom_init: DMD-DEIM needs one domain length");
   size_t need = rom_workspace_bytes(cfg);
   if (!ws || ws_bytes < need) return fail(SYMROM_ENOMEM, "rom_init: workspace too small");
   symrom_rom* r = new symrom_rom{};
@@ -1636,7 +1903,7 @@ symrom_status rom_init_impl(const symrom_config* cfg, const double* L,
     rom_destroy(r);
     return fail(SYMROM_EDEVICE, "rom_init: event creation");
   }
-  if (cfg->projection == SYMROM_DEIM &&
+  if (cfg->projection != SYMROM_GALERKIN &&
       (hipStreamCreateWithFlags(&r->s2, hipStreamNonBlocking) != hipSuccess ||
        hipEventCreateWithFlags(&r->ev_fork, hipEventDisableTiming) != hipSuccess ||
        hipEventCreateWithFlags(&r->ev_join, hipEventDisableTiming) != hipSuccess ||
@@ -1645,10 +1912,66 @@ symrom_status rom_init_impl(const symrom_config* cfg, const double* L,
     rom_destroy(r);
     return fail(SYMROM_EDEVICE, "rom_init: stream or event creation");
   }
+  if (cfg->projection == SYMROM_DMD_DEIM) {
+    // the parameter subset of eq. pSampl from Z^0, fixed from now on, and
+    // the per-parameter constants of its compact columns
+    const int ps = r->psub;
+    launch_subset_select(s, r->Z0, n, p, ps, r->dmin, r->sub);
+    std::vector<int> S(ps), id(ps);
+    for (int k = 0; k < ps; ++k) id[k] = k;
+    std::vector<double> Ls(ps), factor, qw, h, mw;
+    bool okc = hipMemcpyAsync(S.data(), r->sub, ps * sizeof(int), hipMemcpyDeviceToHost, s) ==
+                   hipSuccess &&
+               hipMemcpyAsync(r->sub_id, id.data(), ps * sizeof(int), hipMemcpyHostToDevice, s) ==
+                   hipSuccess &&
+               hipStreamSynchronize(s) == hipSuccess;
+    if (okc) {
+      for (int k = 0; k < ps; ++k) Ls[k] = L[S[k]];
+      per_param_consts(Ls.data(), N, ps, r->Nx, cfg->q, cfg->m, factor, qw, h, mw);
+      okc = hipMemcpyAsync(r->bs.factor, factor.data(), ps * 8, hipMemcpyHostToDevice, s) ==
+                hipSuccess &&
+            hipMemcpyAsync(r->bs.qw, qw.data(), ps * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+            hipMemcpyAsync(r->bs.h, h.data(), ps * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+            hipMemcpyAsync(r->bs.mw, mw.data(), ps * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+            hipStreamSynchronize(s) == hipSuccess;
+    }
+    if (!okc) {
+      rom_destroy(r);
+      return fail(SYMROM_EDEVICE, "rom_init: parameter subset");
+    }
+    r->beta_ready = false;
+    if (eta4) {
+      r->ready = true;
+      const symrom_status st2 = set_parameters(*r, eta4, 4);
+      if (st2 != SYMROM_OK) {
+        rom_destroy(r);
+        return st2;
+      }
+    }
+  }
   r->ready = true;
   r->stage1_cached = false;
   r->step = 0;
   *out = r;
+  return SYMROM_OK;
+}
+
+// eta (host, dim per parameter) into the handle and the radial basis
+// weights of the subset nodes (Sec. 4.2.1)
+symrom_status set_parameters(symrom_rom& r, const double* eta, int dim) {
+  hipStream_t s = r.s;
+  for (int q = 0; q < r.p * dim; ++q)
+    if (!std::isfinite(eta[q])) return fail(SYMROM_EINVAL, "rom_set_parameters: non-finite eta");
+  HIPCHK(hipMemsetAsync(r.flags, 0, sizeof(int), s));
+  HIPCHK(hipMemcpyAsync(r.eta, eta, (size_t)r.p * dim * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_rbf_weights(s, r.eta, dim, r.p, r.sub, r.psub, r.member, r.beta, r.flags);
+  LAUNCHCHK();
+  int fl = 0;
+  HIPCHK(hipMemcpyAsync(&fl, r.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (fl & 64) return fail(SYMROM_ESINGULAR, "rom_set_parameters: interpolation matrix not positive definite");
+  r.eta_dim = dim;
+  r.beta_ready = true;
   return SYMROM_OK;
 }
 }  // namespace
@@ -1661,7 +1984,7 @@ extern "C" symrom_status rom_init(const symrom_config* cfg, const double* L, con
     launch_make_complex(r.s, X0, V0, (size_t)r.N * r.p, r.G);
     return hipGetLastError() == hipSuccess;
   };
-  return rom_init_impl(cfg, L, fill, ws, ws_bytes, stream, out);
+  return rom_init_impl(cfg, L, fill, nullptr, ws, ws_bytes, stream, out);
 }
 
 extern "C" symrom_status rom_init_family(const symrom_config* cfg, int32_t family,
@@ -1682,7 +2005,7 @@ extern "C" symrom_status rom_init_family(const symrom_config* cfg, int32_t famil
     launch_load_family(r.s, family, r.N, p, r.b.part, ux, uv, nullptr, nullptr, r.G);
     return hipGetLastError() == hipSuccess;
   };
-  return rom_init_impl(cfg, L.data(), fill, ws, ws_bytes, stream, out);
+  return rom_init_impl(cfg, L.data(), fill, eta, ws, ws_bytes, stream, out);
 }
 
 extern "C" symrom_status symrom_load_family(int32_t family, int32_t N, int32_t p,
@@ -1714,7 +2037,9 @@ extern "C" symrom_status rom_step(symrom_rom* r, int32_t nsteps, symrom_step_inf
   r->last.deim_steps = 0;
   r->last.stalled_total = 0;
   for (int it = 0; it < nsteps; ++it) {
-    symrom_status st = rom_step_one(*r, r->cfg.rank_auto != 0);
+    // DMD-DEIM (Alg. 2): the plain step until the windows hold T+1 levels
+    const bool dmd = r->cfg.projection == SYMROM_DMD_DEIM && r->win_count + 1 >= r->nslots;
+    symrom_status st = dmd ? rom_step_dmd(*r) : rom_step_one(*r, r->cfg.rank_auto != 0);
     iters_total += r->last.iters;
     deim_steps += r->last.deim_active;
     stalled_total += r->last.stalled;
@@ -1972,7 +2297,7 @@ extern "C" symrom_status rom_cells(symrom_rom* r, const double* Z, int32_t* cell
 extern "C" symrom_status rom_deim_operator(symrom_rom* r, int32_t* idx, double* w, int32_t* d) {
   side_wait(r);
   if (!r || !idx || !w) return fail(SYMROM_EINVAL, "rom_deim_operator: null argument");
-  if (r->cfg.projection != SYMROM_DEIM || !r->deim_on)
+  if (r->cfg.projection == SYMROM_GALERKIN || !r->deim_on)
     return fail(SYMROM_ESTATE, "rom_deim_operator: no DEIM operator has been built");
   hipStream_t s = r->s;
   HIPCHK(hipMemcpyAsync(idx, r->didx, r->d_cur * sizeof(int), hipMemcpyDeviceToDevice, s));
@@ -1985,6 +2310,37 @@ extern "C" symrom_status rom_deim_operator(symrom_rom* r, int32_t* idx, double* 
 // ---------------------------------------------------------------------------
 // stateless DEIM selection on a given basis (the kernels of the step)
 // ---------------------------------------------------------------------------
+extern "C" symrom_status rom_set_parameters(symrom_rom* r, const double* eta, int32_t dim) {
+  if (!r || !eta || dim < 1 || dim > 8) return fail(SYMROM_EINVAL, "rom_set_parameters: bad arguments");
+  if (!r->ready) return fail(SYMROM_ESTATE, "rom_set_parameters: handle not initialised");
+  if (r->cfg.projection != SYMROM_DMD_DEIM)
+    return fail(SYMROM_EINVAL, "rom_set_parameters: only DMD-DEIM uses the parameters");
+  side_wait(r);
+  return set_parameters(*r, eta, dim);
+}
+
+extern "C" symrom_status rom_dmd_state(symrom_rom* r, int32_t* S, int32_t* pstar, int32_t* rank,
+                                       double* lam, double* e0, double* eh) {
+  if (!r) return fail(SYMROM_EINVAL, "rom_dmd_state: null handle");
+  if (!r->ready || r->cfg.projection != SYMROM_DMD_DEIM)
+    return fail(SYMROM_ESTATE, "rom_dmd_state: not a DMD-DEIM handle");
+  side_wait(r);
+  hipStream_t s = r->s;
+  if (pstar) *pstar = r->psub;
+  if (S) HIPCHK(hipMemcpyAsync(S, r->sub, r->psub * sizeof(int), hipMemcpyDeviceToHost, s));
+  int rk = 0;
+  HIPCHK(hipMemcpyAsync(&rk, r->dmd.rdev, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (rank) *rank = rk;
+  if (lam && rk > 0)
+    HIPCHK(hipMemcpyAsync(lam, r->dmd.lam, (size_t)rk * sizeof(cplx), hipMemcpyDeviceToHost, s));
+  const size_t tb = (size_t)r->p * r->Nx * sizeof(double);
+  if (e0) HIPCHK(hipMemcpyAsync(e0, r->e0, tb, hipMemcpyDeviceToDevice, s));
+  if (eh) HIPCHK(hipMemcpyAsync(eh, r->eh, tb, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return SYMROM_OK;
+}
+
 namespace {
 struct SelBufs {
   double *psi, *colpart, *eye, *bval, *dB, *dcv;

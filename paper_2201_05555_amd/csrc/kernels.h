@@ -246,3 +246,62 @@ void launch_cgs2(hipStream_t s, cplx* W, int p, int m);
 // X, V (N x p, nullable) and/or C = X + i V (nullable)
 void launch_load_family(hipStream_t s, int family, int N, int p, const double* eta,
                         const double* ux, const double* uv, double* X, double* V, cplx* C);
+
+// dmd_kernels.hip (DMD-DEIM: Sec. 4.1, Sec. 4.2.1 Alg. 1, eq. grHDD, Alg. 2)
+// subset of eq. pSampl: pstar column indices of Z~ (n x p) into S; dmin: p doubles
+void launch_subset_select(hipStream_t s, const cplx* Z, int n, int p, int pstar, double* dmin,
+                          int* S);
+// radial basis weights beta (p x pstar, row i contiguous) of the subset
+// nodes S for parameters eta (device, dim per parameter); member: p ints
+void launch_rbf_weights(hipStream_t s, const double* eta, int dim, int p, const int* S, int pstar,
+                        int* member, double* beta, int* flags);
+// rows `cols` (or the first k) of a p x Nx grid into a k x Nx block
+void launch_grid_rows(hipStream_t s, const double* src, const int* cols, int k, int Nx,
+                      double* dst);
+// columns S of Z~ (n x p) into a compact n x k block
+void launch_gather_zcols(hipStream_t s, const cplx* Z, int n, const int* S, int k, cplx* out);
+
+// buffers of the DMD of the subset potentials (all device)
+struct DmdChainArgs {
+  const double* ring;  // nslots blocks of pstar x Nx: the window levels
+  int nslots, base;    // level t in slot (base + t) % nslots, t = 0 .. T
+  int pstar, T, Nx;
+  double tol;          // relative singular value cut of Alg. 1
+  double *Y, *Yp, *W;  // Nx x P each (P = pstar T): data, shifted data, QR work
+  double *sig, *V;     // P, P x P: singular values and right vectors (sorted)
+  int* rdev;           // retained rank r
+  double *B, *U, *A;   // Nx x P, Nx x P, P x P (r used)
+  double* M;           // r x r: Re(W Lambda^{1/2} W^{-1})
+  cplx* lam;           // r eigenvalues of A_tol
+  double *Wb, *Wf;     // Nx x P, Nx x pstar: QR work for B^+
+  double* C;           // r x pstar: subset coordinates B^+ Phi_{tau-1}
+  double* BM;          // Nx x P: B M
+  int* flags;
+};
+// window matrices, SVD, A_tol, its eigendecomposition and M, coordinates
+void launch_dmd_operator(hipStream_t s, const DmdChainArgs& c);
+// predicted field tables e0 (t_{tau-1}) and eh (t_{tau-1} + dt/2), p x Nx
+void launch_dmd_tables(hipStream_t s, const DmdChainArgs& c, int p, const double* beta,
+                       const double* h, double* e0, double* eh);
+
+// the fixed point of the coefficients with the DMD-DEIM gradient, whole
+struct DmdFpArgs {
+  const cplx *U0, *Uh;  // bases at t_{tau-1} and at the half step (N x n)
+  int N, n;
+  const int* idx;       // d DEIM rows
+  const double* w;      // d DEIM weights
+  int d;
+  const cplx* Z0;       // n x p
+  const double* factor; // Nx / L per parameter
+  const double *e0, *eh;  // p x Nx field tables
+  int Nx;
+  double qm;
+  const cplx *C12a, *C12;  // [U~^* U~, U~^T U~] at U0 and at U_half
+  double dt, tol, stall_tol;
+  int max_iters, fixed;
+  cplx *k, *ZG;
+  double* prev;
+  int* active;
+  int* counters;        // [0] left, [1] stalled, [2] iterations, [6..7] stall max (zeroed first)
+};
+void launch_dmd_fp(hipStream_t s, const DmdFpArgs& a, int p);

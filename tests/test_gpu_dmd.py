@@ -1,0 +1,182 @@
+"""GPU parity of the DMD-DEIM reduced model (Alg. 2: parameter subset of
+eq. pSampl, DMD of the potential by Alg. 1 with radial basis interpolation
+of its coordinates, DEIM of Lambda^0 Phi_DMD, eq. grHDD) through the C ABI
+against the FP64 oracle on the same seeded inputs: the subset, the DMD rank
+and eigenvalues, the predicted field tables, the DEIM indices, the
+fixed-point iteration counts and the state, each step."""
+import numpy as np
+import pytest
+
+from oracle import rom
+from workloads import make_ensemble, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _b():
+    import torch
+    from paper_2201_05555_amd import binding
+    assert torch.cuda.is_available()
+    return binding, torch
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _set_from_oracle(r, st, torch):
+    N = st.U.shape[0] // 2
+    UX = torch.from_numpy(np.ascontiguousarray(st.U[:N].T)).cuda()
+    Z = torch.from_numpy(np.ascontiguousarray(st.Z.T)).cuda()
+    r.set_state(UX, Z, st.step)
+
+
+def _match(a, b):
+    """Largest distance from an element of either set to the nearest of the
+    other, relative to max |b|."""
+    if a.size == 0 or b.size == 0:
+        return 0.0
+    dist = np.abs(a[:, None] - b[None, :])
+    return max(dist.min(axis=0).max(), dist.min(axis=1).max()) / np.abs(b).max()
+
+
+def _table_sensitivity(st, dt, tol, delta, seed=0):
+    """The oracle's field tables and eigenvalues when the window potentials
+    of its last DMD-DEIM step are perturbed by delta (relative, Gaussian):
+    the small DMD modes (singular values down to tol sigma_1) amplify
+    differences of the data.  Returns the relative changes of e0, eh and of
+    the eigenvalues (rank changes: inf)."""
+    from oracle import dmd, pic
+    rng = np.random.default_rng(seed)
+    lv = [a * (1 + delta * rng.normal(size=a.shape)) for a in st.phi_window]
+    op = dmd.build_operator(lv, st.subset, st.eta, dt, tol)
+    e0o, eho = st.last_dmd_tables
+    e0 = pic.field(dmd.predict(op, 0.0), st.L)
+    eh = pic.field(dmd.predict(op, 0.5 * dt), st.L)
+    lam = _match(op.lam, st.last_dmd.lam) if op.r == st.last_dmd.r else np.inf
+    return _rel(e0, e0o), _rel(eh, eho), lam
+
+
+def _pair(kw, two_n, T, pstar, d):
+    w = workload("twostream_deim", **kw)
+    e = make_ensemble(w)
+    cfg = rom.RomConfig(N=w["N"], p=w["p"], Nx=w["Nx"], two_n=two_n, dt=w["dt"], fp_tol=1e-10,
+                        projection="dmd_deim", deim_window=T, p_star=pstar, deim_rows=d)
+    return w, e, cfg
+
+
+def _gpu(binding, w, e, two_n, T, pstar, d, family=False):
+    gcfg = binding.make_config(w["N"], w["p"], w["Nx"], two_n, dt=w["dt"], fp_tol=1e-10,
+                               projection="dmd_deim", deim_window=T, p_star=pstar, deim_rows=d)
+    r = binding.Rom(gcfg, e["L"], e["X0"], e["V0"])
+    r.set_parameters(e["eta"])
+    return r
+
+
+@pytest.mark.parametrize("kw,two_n,T,pstar,d", [
+    (dict(N=20000, p=24, Nx=64), 8, 3, 6, 16),
+    (dict(N=30000, p=64, Nx=128), 10, 3, 12, 24),
+])
+def test_subset_matches_the_oracle(kw, two_n, T, pstar, d):
+    binding, torch = _b()
+    w, e, cfg = _pair(kw, two_n, T, pstar, d)
+    _say("dmd subset", kw, pstar)
+    st = rom.init_state(e["X0"], e["V0"], e["L"], cfg, eta=e["eta"])
+    r = _gpu(binding, w, e, two_n, T, pstar, d)
+    S, _, _, _, _ = r.dmd_state()
+    print(f"  GPU subset {S.tolist()}, oracle {st.subset.tolist()}", flush=True)
+    assert np.array_equal(S, st.subset)
+
+
+@pytest.mark.parametrize("kw,two_n,T,pstar,d,steps", [
+    (dict(N=20000, p=24, Nx=64), 8, 3, 6, 16, 8),
+    (dict(N=30000, p=64, Nx=128), 10, 3, 12, 24, 7),
+])
+def test_dmd_deim_steps_parity(kw, two_n, T, pstar, d, steps):
+    """From the oracle's state: the plain steps of the first T, then the
+    DMD-DEIM steps with the same DMD rank, DEIM indices and iteration counts;
+    eigenvalues and field tables within 10x the oracle's change when its
+    window potentials are perturbed by the measured difference between the
+    two sides' potentials (at least 1e-13: their exact Poisson solves differ
+    by about that; after plain steps of an ill-conditioned ensemble the
+    states, and with them the potentials, differ by the oracle's own
+    sensitivity); X_r and V_r within 50x the oracle's own sensitivity to a
+    1e-15 perturbation of Z (each apart, floor 1e-9)."""
+    binding, torch = _b()
+    w, e, cfg = _pair(kw, two_n, T, pstar, d)
+    _say("dmd-deim steps", kw, two_n, T, pstar, d, steps)
+    st = rom.init_state(e["X0"], e["V0"], e["L"], cfg, eta=e["eta"])
+    # the oracle's own sensitivity, step by step: a run from Z perturbed by
+    # 1e-15 in lockstep with the reference run (field tables, eigenvalues,
+    # and at the end X_r and V_r, each apart)
+    rng = np.random.default_rng(0)
+    sp = rom.init_state(e["X0"], e["V0"], e["L"], cfg, eta=e["eta"])
+    sp.Z = sp.Z * (1 + 1e-15 * rng.normal(size=sp.Z.shape))
+    r = _gpu(binding, w, e, two_n, T, pstar, d)
+    _set_from_oracle(r, st, torch)
+    dphis = []
+    for s in range(steps):
+        # the potentials at the start of the step, both sides (printed: the
+        # data the DMD of this step is built from)
+        _, _, phig, _ = r.gradient(r.get_state()[1])
+        gro = rom.gradient(st.U, st.Z, st.L, cfg.Nx)
+        dphi = _rel(_np(phig).T[:, st.subset], gro.Phi[:, st.subset])
+        dphis.append(dphi)
+        info = r.step(1)
+        assert rom.prk_step(st, cfg) == rom.OK
+        assert rom.prk_step(sp, cfg) == rom.OK
+        assert info["iters"] == st.last_iters, (s, info, st.last_iters)
+        if st.last_dmd is None or st.deim_indices is None or s < T:
+            continue
+        S, rk, lam, e0, eh = r.dmd_state()
+        e0o, eho = st.last_dmd_tables
+        lo = st.last_dmd.lam
+        idx = _np(r.deim_operator()[0]).astype(np.int64)
+        err0 = _rel(_np(e0).T, e0o)
+        errh = _rel(_np(eh).T, eho)
+        # the probe at the measured difference of the window's potentials
+        delta = max(1e-13, max(dphis[-(T + 1):]))
+        s0, sh, lsen = _table_sensitivity(st, cfg.dt, cfg.dmd_tol, delta)
+        # eigenvalues matched by nearest neighbour both ways (their order is
+        # not part of the result)
+        lerr = _match(lam, lo) if rk == st.last_dmd.r else np.inf
+        print(f"  step {s}: rank {rk}/{st.last_dmd.r}, |lam| err {lerr:.2e} (sens {lsen:.2e}), "
+              f"e0 {err0:.2e} ({s0:.2e}), eh {errh:.2e} ({sh:.2e}), iters {info['iters']}, "
+              f"indices equal {np.array_equal(idx, st.deim_indices)}, subset Phi diff {dphi:.2e}",
+              flush=True)
+        assert rk == st.last_dmd.r
+        assert lerr < max(1e-11, 10 * lsen)
+        assert err0 < max(1e-11, 10 * s0) and errh < max(1e-11, 10 * sh)
+        assert np.array_equal(idx, st.deim_indices)
+    outs = [rom.reconstruct(st), rom.reconstruct(sp)]
+    sx, sv = _rel(outs[1][0], outs[0][0]), _rel(outs[1][1], outs[0][1])
+    X, V = r.reconstruct()
+    Xo, Vo = rom.reconstruct(st)
+    ex, ev = _rel(_np(X).T, Xo), _rel(_np(V).T, Vo)
+    bx, bv = max(1e-9, 50 * sx), max(1e-9, 50 * sv)
+    print(f"  X_r rel err {ex:.2e} (sensitivity {sx:.2e}); V_r {ev:.2e} ({sv:.2e})", flush=True)
+    assert ex < bx and ev < bv
+
+
+def test_dmd_deim_needs_parameters():
+    """A rom_init handle refuses its first DMD-DEIM step until the
+    parameters are given (ESTATE), then runs."""
+    binding, torch = _b()
+    w, e, cfg = _pair(dict(N=6000, p=12, Nx=32), 8, 2, 4, 12)
+    _say("dmd-deim without parameters")
+    gcfg = binding.make_config(w["N"], w["p"], w["Nx"], 8, dt=w["dt"], fp_tol=1e-10,
+                               projection="dmd_deim", deim_window=2, p_star=4, deim_rows=12)
+    r = binding.Rom(gcfg, e["L"], e["X0"], e["V0"])
+    r.step(2)
+    st, _ = r.step_status(1)
+    assert st == binding.ESTATE
+    r.set_parameters(e["eta"])
+    r.step(2)
