@@ -616,6 +616,10 @@ struct symrom_rom {
   // ev_fork / ev_join order it after the first-stage field and before its use.
   hipStream_t s2;
   hipEvent_t ev_fork, ev_join;
+  // DMD-DEIM: the DMD of the potential window on a third stream (default
+  // priority) beside the DEIM chain; both need only the first-stage field
+  hipStream_t s3;
+  hipEvent_t ev_join3;
   // S(Z)^+ of the second-stage basis velocity on the second stream, beside
   // the gather-projection that precedes it: ev_sp0 orders it after the fixed
   // point, ev_sp1 its result before the basis-velocity finish
@@ -1109,7 +1113,7 @@ void linear_grams(symrom_rom& r, const cplx* U, cplx* C12) {
 // of Y (from the eigenpairs of Y^T Y), greedy indices, weights.  Enqueued on
 // the second stream, with its own partials and its own error word flags[2].
 void deim_update(symrom_rom& r, const cplx* U, const cplx* Z, bool redo = false,
-                 const int* stop = nullptr) {
+                 const int* stop = nullptr, bool copy_phi = true) {
   hipStream_t s = r.s2;
   int* dflags = r.flags + 3;
   const int N = r.N, n = r.n;
@@ -1122,7 +1126,7 @@ void deim_update(symrom_rom& r, const cplx* U, const cplx* Z, bool redo = false,
     launch_snapshot(s, U, N, n, Z, r.sub, r.psub, r.Nx, r.b.factor, r.b.phi, Ys, stop);
     // DMD-DEIM: the subset potentials of this level into the same slot of
     // the potential window (eq. DMD_potential_Y_time)
-    if (r.cfg.projection == SYMROM_DMD_DEIM)
+    if (r.cfg.projection == SYMROM_DMD_DEIM && copy_phi)
       launch_grid_rows(s, r.b.phi, r.sub, r.psub, r.Nx, r.phiw + (size_t)slot * r.psub * r.Nx);
   }
   if (!redo) r.win_count++;
@@ -1534,21 +1538,28 @@ symrom_status rom_step_dmd(symrom_rom& r) {
   if (!r.beta_ready)
     return fail(SYMROM_ESTATE, "rom_step: DMD-DEIM needs the parameters (rom_set_parameters)");
   HIPCHK(hipMemsetAsync(r.flags, 0, 3 * sizeof(int), s));
-  // counters: columns left, stalled, iterations, stall maximum
+  // counters: columns left, stalled, iterations, stall maximum; the DMD
+  // chain's error word
   HIPCHK(hipMemsetAsync(r.counters, 0, 8 * sizeof(int), s));
+  HIPCHK(hipMemsetAsync(r.status + 14, 0, sizeof(int), s));
   launch_gather_zcols(s, r.Z0, n, r.sub, ps, r.Zs);
   {
     SubsetView v(r);
     full_gradient(r, r.U0, r.Zs, nullptr, true);
     HIPCHK(hipEventRecord(r.ev_fork, s));
     HIPCHK(hipStreamWaitEvent(r.s2, r.ev_fork, 0));
-    deim_update(r, r.U0, r.Zs);
+    HIPCHK(hipStreamWaitEvent(r.s3, r.ev_fork, 0));
+    deim_update(r, r.U0, r.Zs, false, nullptr, false);
+    // this level's subset potentials into the window, on the DMD stream
+    launch_grid_rows(r.s3, r.b.phi, nullptr, ps, r.Nx,
+                     r.phiw + (size_t)((r.win_count - 1) % r.nslots) * ps * r.Nx);
     basis_velocity(r, r.U0, r.Zs, 0.5 * dt, r.Xi, nullptr);
   }
   deim_update_tail(r);
+  HIPCHK(hipEventRecord(r.ev_join, r.s2));
   {
     // the DMD of the window (levels win_count - nslots .. win_count - 1)
-    Timer t(FAM_DMD, r.s2);
+    Timer t(FAM_DMD, r.s3);
     DmdChainArgs c = r.dmd;
     c.ring = r.phiw;
     c.nslots = r.nslots;
@@ -1557,15 +1568,17 @@ symrom_status rom_step_dmd(symrom_rom& r) {
     c.T = r.cfg.deim_window;
     c.Nx = r.Nx;
     c.tol = r.cfg.dmd_tol > 0.0 ? r.cfg.dmd_tol : 1e-5;
-    c.flags = r.flags + 3;
-    launch_dmd_operator(r.s2, c);
-    launch_dmd_tables(r.s2, c, p, r.beta, r.b.h, r.e0, r.eh);
+    // (its own error word, status word 14)
+    c.flags = r.status + 14;
+    launch_dmd_operator(r.s3, c);
+    launch_dmd_tables(r.s3, c, p, r.beta, r.b.h, r.e0, r.eh);
   }
-  HIPCHK(hipEventRecord(r.ev_join, r.s2));
+  HIPCHK(hipEventRecord(r.ev_join3, r.s3));
   linear_grams(r, r.U0, r.C12a);
   cayley(r, r.U0, r.Xi, r.Uh, r.Amat);
   linear_grams(r, r.Uh, r.C12);
   HIPCHK(hipStreamWaitEvent(s, r.ev_join, 0));
+  HIPCHK(hipStreamWaitEvent(s, r.ev_join3, 0));
   {
     const int fixed = r.cfg.fp_fixed_iters;
     Timer t(FAM_DMDFP, s);
@@ -1612,10 +1625,10 @@ symrom_status rom_step_dmd(symrom_rom& r) {
   std::swap(r.U0, r.Uh);
   std::swap(r.Z0, r.Z1);
   launch_fold_status(s, r.status);
-  HIPCHK(hipMemcpyAsync(r.hstat, r.status, 14 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(r.hstat, r.status, 16 * sizeof(int), hipMemcpyDeviceToHost, s));
   LAUNCHCHK();
   HIPCHK(hipStreamSynchronize(s));
-  const int fl0 = r.hstat[0] | r.hstat[2];
+  const int fl0 = r.hstat[0] | r.hstat[2] | r.hstat[14];
   r.last.iters = r.hstat[6];
   r.last.stalled = r.hstat[5];
   std::memcpy(&r.last.stall_rel, r.hstat + 10, sizeof(double));
@@ -1628,7 +1641,14 @@ symrom_status rom_step_dmd(symrom_rom& r) {
     std::swap(r.Z0, r.Z1);
     r.win_count--;
     r.deim_on = r.win_count >= r.nslots;
-    if (fl0) return fail(SYMROM_ESINGULAR, "singular small matrix in the DMD-DEIM step");
+    if (fl0) {
+      // error bits: 64 interpolation matrix, 128 SVD of the window, 256 QR
+      // iteration of A_tol, 512 B rank deficient, others the basis update
+      char msg[96];
+      std::snprintf(msg, sizeof msg, "singular small matrix in the DMD-DEIM step (error bits 0x%x)",
+                    (unsigned)fl0);
+      return fail(SYMROM_ESINGULAR, msg);
+    }
     std::vector<int> act(p);
     std::vector<double> pv(p);
     if (hipMemcpy(act.data(), r.active, p * sizeof(int), hipMemcpyDeviceToHost) == hipSuccess &&
@@ -1909,6 +1929,12 @@ symrom_status rom_init_impl(const symrom_config* cfg, const double* L,
        hipEventCreateWithFlags(&r->ev_join, hipEventDisableTiming) != hipSuccess ||
        hipEventCreateWithFlags(&r->ev_sp0, hipEventDisableTiming) != hipSuccess ||
        hipEventCreateWithFlags(&r->ev_sp1, hipEventDisableTiming) != hipSuccess)) {
+    rom_destroy(r);
+    return fail(SYMROM_EDEVICE, "rom_init: stream or event creation");
+  }
+  if (cfg->projection == SYMROM_DMD_DEIM &&
+      (hipStreamCreateWithFlags(&r->s3, hipStreamNonBlocking) != hipSuccess ||
+       hipEventCreateWithFlags(&r->ev_join3, hipEventDisableTiming) != hipSuccess)) {
     rom_destroy(r);
     return fail(SYMROM_EDEVICE, "rom_init: stream or event creation");
   }
@@ -2452,6 +2478,11 @@ extern "C" void rom_destroy(symrom_rom* r) {
   if (r->ev_sp1) (void)hipEventDestroy(r->ev_sp1);
   if (r->ev_join) (void)hipEventDestroy(r->ev_join);
   if (r->ev_read) (void)hipEventDestroy(r->ev_read);
+  if (r->ev_join3) (void)hipEventDestroy(r->ev_join3);
+  if (r->s3) {
+    (void)hipStreamSynchronize(r->s3);
+    (void)hipStreamDestroy(r->s3);
+  }
   if (r->s2) (void)hipStreamDestroy(r->s2);
   if (r->hstat) (void)hipHostFree(r->hstat);
   delete r;

@@ -349,10 +349,12 @@ __device__ void householder_qr(double* W, int Nx, int P, double* alpha, double* 
 // ---------------------------------------------------------------------------
 // Alg. 1, step 1: the truncated SVD of Y (N_x x P, P <= 64) by Householder
 // QR (work copy W) and one-sided Jacobi on the columns of R (m x P, m =
-// min(N_x, P), in LDS) with the rotations accumulated in V; no Gram of Y is
-// formed.  The left vectors are the rotated columns of R, which the
-// stopping rule leaves orthogonal to working precision, each over its norm,
-// mapped back by the reflectors: U = Q [R V S^{-1}; 0].  (U = Y V S^{-1}
+// min(N_x, P), in LDS) with the rotations accumulated, or on those of R^T
+// when the window is wider than the grid (fewer, longer columns); no Gram
+// of Y is formed.  With R: V = the rotations, U = Q [R V S^{-1}; 0] from the
+// rotated columns, which the stopping rule leaves orthogonal to working
+// precision.  With R^T (R^T G = V S): V = the rotated columns over their
+// norms, U = Q [G; 0].  (U = Y V S^{-1}
 // would lose orthogonality between the columns of small singular values,
 // by about eps s_1 / s_j, and A_tol = U^T B with it.)  Output sorted by
 // decreasing singular value: sig (P), V (P x P, ld P), the retained count
@@ -370,58 +372,90 @@ __global__ void __launch_bounds__(256) dmd_svd_kernel(double* __restrict__ W, in
   __shared__ double sv[64];
   __shared__ int rot, rkeep;
   extern __shared__ double jsm[];
-  double* Rs = jsm;              // column j at Rs[j * 64] (dynamic: 64 KB with Vs)
-  double* Vs = jsm + 64 * 64;
+  // column j at Rs[j * JS]: the stride of 65 doubles puts element i of the
+  // columns that concurrent pair groups rotate in different LDS banks
+  constexpr int JS = 65;
+  double* Rs = jsm;
+  double* Vs = jsm + 64 * JS;
   const int t = threadIdx.x;
   householder_qr(W, Nx, P, alpha, tau, nullptr, 0, red);
   const int m = min(Nx, P);
+  // Jacobi on the columns of R (m x P) when m = P, on those of R^T (P x m)
+  // when the window is wider than the grid (m < P): C columns of length ell,
+  // the rotations accumulated in G (C x C).  R (upper trapezoidal): R[i][j]
+  // = W[j Nx + i] above the diagonal, alpha[i] on it.
+  const bool wide = m < P;
+  const int C = wide ? m : P, ell = wide ? P : m;
   for (int q = t; q < 64 * 64; q += 256) {
     const int j = q >> 6, i = q & 63;
     double v = 0.0;
-    if (j < P && i < m) v = (i < j) ? W[(size_t)j * Nx + i] : (i == j ? alpha[i] : 0.0);
-    Rs[q] = v;
-    Vs[q] = (i == j && j < P) ? 1.0 : 0.0;
+    if (j < C && i < ell) {
+      const int ri = wide ? j : i, rj = wide ? i : j;  // the entry R[ri][rj]
+      v = (ri < rj) ? W[(size_t)rj * Nx + ri] : (ri == rj ? alpha[ri] : 0.0);
+    }
+    Rs[j * JS + i] = v;
+    Vs[j * JS + i] = (i == j && j < C) ? 1.0 : 0.0;
   }
   __syncthreads();
-  // round-robin pairs (circle method) over P2 = P rounded up to even; a
+  // columns at rounding level (|col|^2 below (1e-15 |R|_F)^2) take part in
+  // no rotation: their mutual rounding noise never settles
+  double fr = 0.0;
+  for (int q = t; q < 64 * 64; q += 256) {
+    const double v = Rs[(q >> 6) * JS + (q & 63)];
+    fr = fma(v, v, fr);
+  }
+  const double tiny = 1e-30 * block_sum(fr, red);
+  // round-robin pairs (circle method) over C2 = C rounded up to even; a
   // pair with the padding column is skipped
-  const int P2 = P + (P & 1);
+  const int C2 = C + (C & 1);
   const int g = t >> 3, sub = t & 7;
   int sweep = 0;
   for (; sweep < 60; ++sweep) {
     if (t == 0) rot = 0;
     __syncthreads();
-    for (int rnd = 0; rnd < P2 - 1; ++rnd) {
-      if (g < P2 / 2) {
-        const int ia = (g == 0) ? 0 : ((g - 1 + rnd) % (P2 - 1)) + 1;
-        const int ib = ((P2 - 2 - g + rnd) % (P2 - 1)) + 1;
-        if (ia < P && ib < P) {
-          const int a = min(ia, ib), b = max(ia, ib);
+    for (int rnd = 0; rnd < C2 - 1; ++rnd) {
+      // (the 8 lanes of a pair group sit in one DPP row half: every lane of
+      // the group takes part in the sums below, also when its pair is idle)
+      int ia = g - 1 + rnd, ib = C2 - 2 - g + rnd;
+      ia = (ia >= C2 - 1) ? ia - (C2 - 1) : ia;
+      ib = (ib >= C2 - 1) ? ib - (C2 - 1) : ib;
+      ia = (g == 0) ? 0 : ia + 1;
+      ib = ib + 1;
+      const bool act = g < C2 / 2 && ia < C && ib < C;
+      {
+        {
+          const int a = act ? min(ia, ib) : 0, b = act ? max(ia, ib) : 0;
           double al = 0.0, be = 0.0, ga = 0.0;
-          for (int i = sub; i < m; i += 8) {
-            const double xa = Rs[a * 64 + i], xb = Rs[b * 64 + i];
-            al = fma(xa, xa, al);
-            be = fma(xb, xb, be);
-            ga = fma(xa, xb, ga);
-          }
-          for (int o = 1; o < 8; o <<= 1) {
-            al += __shfl_xor(al, o, 64);
-            be += __shfl_xor(be, o, 64);
-            ga += __shfl_xor(ga, o, 64);
-          }
-          if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+          if (act)
+            for (int i = sub; i < ell; i += 8) {
+              const double xa = Rs[a * JS + i], xb = Rs[b * JS + i];
+              al = fma(xa, xa, al);
+              be = fma(xb, xb, be);
+              ga = fma(xa, xb, ga);
+            }
+          // sums over the 8 lanes of the group by DPP butterflies
+          al += bfly64<0>(al);
+          be += bfly64<0>(be);
+          ga += bfly64<0>(ga);
+          al += bfly64<1>(al);
+          be += bfly64<1>(be);
+          ga += bfly64<1>(ga);
+          al += bfly64<2>(al);
+          be += bfly64<2>(be);
+          ga += bfly64<2>(ga);
+          if (act && ga != 0.0 && al > tiny && be > tiny && fabs(ga) > 1e-15 * sqrt(al * be)) {
             const double zeta = (be - al) / (2.0 * ga);
             const double tt = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-            for (int i = sub; i < m; i += 8) {
-              const double xa = Rs[a * 64 + i], xb = Rs[b * 64 + i];
-              Rs[a * 64 + i] = c * xa - s * xb;
-              Rs[b * 64 + i] = s * xa + c * xb;
+            for (int i = sub; i < ell; i += 8) {
+              const double xa = Rs[a * JS + i], xb = Rs[b * JS + i];
+              Rs[a * JS + i] = c * xa - s * xb;
+              Rs[b * JS + i] = s * xa + c * xb;
             }
-            for (int i = sub; i < P; i += 8) {
-              const double xa = Vs[a * 64 + i], xb = Vs[b * 64 + i];
-              Vs[a * 64 + i] = c * xa - s * xb;
-              Vs[b * 64 + i] = s * xa + c * xb;
+            for (int i = sub; i < C; i += 8) {
+              const double xa = Vs[a * JS + i], xb = Vs[b * JS + i];
+              Vs[a * JS + i] = c * xa - s * xb;
+              Vs[b * JS + i] = s * xa + c * xb;
             }
             if (sub == 0) rot = 1;
           }
@@ -433,35 +467,42 @@ __global__ void __launch_bounds__(256) dmd_svd_kernel(double* __restrict__ W, in
     __syncthreads();
     if (!any) break;
   }
-  if (t < P) {
+  if (t < C) {
     double s = 0.0;
-    for (int i = 0; i < m; ++i) s = fma(Rs[t * 64 + i], Rs[t * 64 + i], s);
+    for (int i = 0; i < ell; ++i) s = fma(Rs[t * JS + i], Rs[t * JS + i], s);
     sv[t] = sqrt(s);
   }
   __syncthreads();
-  if (t < P) {
+  // right vectors: the rotations (R) or the rotated columns over their norms (R^T)
+  if (t < C) {
     int rank = 0;
-    for (int j = 0; j < P; ++j) rank += (sv[j] > sv[t]) || (sv[j] == sv[t] && j < t);
+    for (int j = 0; j < C; ++j) rank += (sv[j] > sv[t]) || (sv[j] == sv[t] && j < t);
     sig[rank] = sv[t];
-    for (int i = 0; i < P; ++i) Vout[(size_t)rank * P + i] = Vs[t * 64 + i];
+    for (int i = 0; i < P; ++i)
+      Vout[(size_t)rank * P + i] = wide ? (sv[t] > 0.0 ? Rs[t * JS + i] / sv[t] : 0.0)
+                                        : Vs[t * JS + i];
   }
+  for (int k = C + t; k < P; k += 256) sig[k] = 0.0;
   if (t == 0) {
     double smax = 0.0;
-    for (int j = 0; j < P; ++j) smax = fmax(smax, sv[j]);
+    for (int j = 0; j < C; ++j) smax = fmax(smax, sv[j]);
     int r = 0;
-    for (int j = 0; j < P; ++j) r += sv[j] > tol * smax;
+    for (int j = 0; j < C; ++j) r += sv[j] > tol * smax;
     rout[0] = r;
     rkeep = r;
     if ((sweep == 60 || smax == 0.0) && flags) atomicOr(flags, 128);
   }
   __syncthreads();
-  // U: the retained rotated columns over their norms, padded to N_x rows
+  // U: the small left vectors (the rotated columns over their norms for R,
+  // the rotations for R^T), padded to N_x rows
   const int r = rkeep;
-  for (int q = t; q < P * Nx; q += 256) {
+  for (int q = t; q < C * Nx; q += 256) {
     const int j = q / Nx, i = q - j * Nx;
     int rank = 0;
-    for (int jj = 0; jj < P; ++jj) rank += (sv[jj] > sv[j]) || (sv[jj] == sv[j] && jj < j);
-    if (rank < r) Uout[(size_t)rank * Nx + i] = (i < m) ? Rs[j * 64 + i] / sv[j] : 0.0;
+    for (int jj = 0; jj < C; ++jj) rank += (sv[jj] > sv[j]) || (sv[jj] == sv[j] && jj < j);
+    if (rank < r)
+      Uout[(size_t)rank * Nx + i] =
+          (i < m) ? (wide ? Vs[j * JS + i] : Rs[j * JS + i] / sv[j]) : 0.0;
   }
   __threadfence_block();
   __syncthreads();
@@ -1034,7 +1075,7 @@ void launch_dmd_operator(hipStream_t s, const DmdChainArgs& c) {
   // the QR works on a copy of Y (its reflectors stay there)
   (void)hipMemcpyAsync(c.W, c.Y, (size_t)c.Nx * P * sizeof(double), hipMemcpyDeviceToDevice, s);
   ALLOW_BIG_LDS(dmd_svd_kernel);
-  hipLaunchKernelGGL(dmd_svd_kernel, dim3(1), dim3(256), 2 * 64 * 64 * sizeof(double), s, c.W,
+  hipLaunchKernelGGL(dmd_svd_kernel, dim3(1), dim3(256), 2 * 64 * 65 * sizeof(double), s, c.W,
                      c.Nx, P, c.tol, c.sig, c.V, c.rdev, c.U, c.flags);
   hipLaunchKernelGGL(dmd_form_kernel, dim3(1), dim3(256), 0, s, c.Yp, c.Nx, P, c.sig, c.V,
                      c.rdev, c.B, c.U, c.A);

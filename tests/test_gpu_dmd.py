@@ -7,7 +7,7 @@ fixed-point iteration counts and the state, each step."""
 import numpy as np
 import pytest
 
-from oracle import rom
+from oracle import deim, rom
 from workloads import make_ensemble, workload
 
 pytestmark = pytest.mark.gpu
@@ -66,8 +66,10 @@ def _table_sensitivity(st, dt, tol, delta, seed=0):
 
 
 def _pair(kw, two_n, T, pstar, d):
-    w = workload("twostream_deim", **kw)
-    e = make_ensemble(w)
+    kw = dict(kw)
+    name = kw.pop("name", "twostream_deim")
+    w = workload(name, **kw)
+    e = make_ensemble(w, loading=w.get("loading", "philox"))
     cfg = rom.RomConfig(N=w["N"], p=w["p"], Nx=w["Nx"], two_n=two_n, dt=w["dt"], fp_tol=1e-10,
                         projection="dmd_deim", deim_window=T, p_star=pstar, deim_rows=d)
     return w, e, cfg
@@ -99,6 +101,15 @@ def test_subset_matches_the_oracle(kw, two_n, T, pstar, d):
 @pytest.mark.parametrize("kw,two_n,T,pstar,d,steps", [
     (dict(N=20000, p=24, Nx=64), 8, 3, 6, 16, 8),
     (dict(N=30000, p=64, Nx=128), 10, 3, 12, 24, 7),
+    # the Landau damping ensemble of Sec. 6.2 (quiet start, rank 4): the
+    # window is wider than the grid (p* T = 48 > N_x = 32), so the SVD has
+    # exactly zero columns.  d = 16 stays within the numerical rank of the
+    # DEIM snapshot matrix; d = 32 (the paper's value) reaches singular
+    # values near 1e-8 of the largest, whose vectors neither the oracle's SVD
+    # nor the library's snapshot Gram determine beyond rounding: the weights
+    # then agree to about 1e-5 and the state to about 1e-8 (floor 1e-8)
+    (dict(name="landau_ld", N=20000, p=40), 4, 3, 16, 16, 8),
+    (dict(name="landau_ld", N=20000, p=40, floor=1e-8), 4, 3, 16, 32, 8),
 ])
 def test_dmd_deim_steps_parity(kw, two_n, T, pstar, d, steps):
     """From the oracle's state: the plain steps of the first T, then the
@@ -111,6 +122,8 @@ def test_dmd_deim_steps_parity(kw, two_n, T, pstar, d, steps):
     sensitivity); X_r and V_r within 50x the oracle's own sensitivity to a
     1e-15 perturbation of Z (each apart, floor 1e-9)."""
     binding, torch = _b()
+    kw = dict(kw)
+    floor = kw.pop("floor", 1e-9)
     w, e, cfg = _pair(kw, two_n, T, pstar, d)
     _say("dmd-deim steps", kw, two_n, T, pstar, d, steps)
     st = rom.init_state(e["X0"], e["V0"], e["L"], cfg, eta=e["eta"])
@@ -139,7 +152,9 @@ def test_dmd_deim_steps_parity(kw, two_n, T, pstar, d, steps):
         S, rk, lam, e0, eh = r.dmd_state()
         e0o, eho = st.last_dmd_tables
         lo = st.last_dmd.lam
-        idx = _np(r.deim_operator()[0]).astype(np.int64)
+        idxg, wg = r.deim_operator()
+        idx = _np(idxg).astype(np.int64)
+        werr = _rel(_np(wg), deim.weights(st.deim_psi, st.deim_indices))
         err0 = _rel(_np(e0).T, e0o)
         errh = _rel(_np(eh).T, eho)
         # the probe at the measured difference of the window's potentials
@@ -150,7 +165,8 @@ def test_dmd_deim_steps_parity(kw, two_n, T, pstar, d, steps):
         lerr = _match(lam, lo) if rk == st.last_dmd.r else np.inf
         print(f"  step {s}: rank {rk}/{st.last_dmd.r}, |lam| err {lerr:.2e} (sens {lsen:.2e}), "
               f"e0 {err0:.2e} ({s0:.2e}), eh {errh:.2e} ({sh:.2e}), iters {info['iters']}, "
-              f"indices equal {np.array_equal(idx, st.deim_indices)}, subset Phi diff {dphi:.2e}",
+              f"indices equal {np.array_equal(idx, st.deim_indices)}, weights {werr:.2e}, "
+              f"subset Phi diff {dphi:.2e}",
               flush=True)
         assert rk == st.last_dmd.r
         assert lerr < max(1e-11, 10 * lsen)
@@ -161,7 +177,7 @@ def test_dmd_deim_steps_parity(kw, two_n, T, pstar, d, steps):
     X, V = r.reconstruct()
     Xo, Vo = rom.reconstruct(st)
     ex, ev = _rel(_np(X).T, Xo), _rel(_np(V).T, Vo)
-    bx, bv = max(1e-9, 50 * sx), max(1e-9, 50 * sv)
+    bx, bv = max(floor, 50 * sx), max(floor, 50 * sv)
     print(f"  X_r rel err {ex:.2e} (sensitivity {sx:.2e}); V_r {ev:.2e} ({sv:.2e})", flush=True)
     assert ex < bx and ev < bv
 

@@ -12,6 +12,7 @@ from .ensembles import (
     load_particles,
     make_ensemble,
     parameter_matrix,
+    particle_uniforms,
 )
 
 __all__ = [
@@ -23,4 +24,5 @@ __all__ = [
     "load_particles",
     "make_ensemble",
     "parameter_matrix",
+    "particle_uniforms",
 ]

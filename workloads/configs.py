@@ -37,6 +37,16 @@ WORKLOADS = {
         ranges=dict(alpha=(1e-3, 1e-2), v0=(2.0, 3.0), sigma=(0.1, 0.5)),
         k=0.2,
     ),
+    # the weak Landau damping experiment of Sec. 6.2 with DMD-DEIM (Alg. 2):
+    # eta = (alpha, sigma), k fixed (one domain for every parameter), quiet
+    # start, rank 2n = 4, d = 32 DEIM rows with 12 updated per step and a
+    # full greedy every 3 steps, window T = 3, p* = 16 subset parameters
+    "landau_ld": dict(
+        number=6, family="landau", N=50_000, p=300, Nx=32, steps=8000, dt=0.0025,
+        two_n=4, two_n_max=4, projection="dmd_deim", deim_window=3, p_star=16,
+        deim_rows=32, deim_update_every=3, deim_update_rows=12, loading="hammersley",
+        ranges=dict(alpha=(0.03, 0.06), sigma=(0.8, 1.0)), k=0.5,
+    ),
 }
 
 

@@ -168,6 +168,19 @@ def load_particles(params, ux, uv, family):
     return np.asfortranarray(X), np.asfortranarray(V)
 
 
+def particle_uniforms(w, seed=None):
+    """The N shared uniforms of workload w: the Hammersley point set (quiet
+    start, Sec. 6.1) in a seeded random particle order when the workload asks
+    for it, else Philox streams."""
+    if seed is None:
+        seed = 1000 * w["number"] + 2
+    if w.get("loading") == "hammersley":
+        ux, uv = hammersley_uniforms(w["N"])
+        perm = np.random.Generator(np.random.Philox(key=int(seed))).permutation(w["N"])
+        return ux[perm], uv[perm]
+    return philox_uniforms(seed, w["N"])
+
+
 def make_ensemble(w, loading="philox", param_seed=None, particle_seed=None):
     """Parameters and initial particle states for workload ``w``.
 
