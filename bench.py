@@ -19,6 +19,9 @@ for the dominant kernel on the caller's stream from the algorithmic work of
 its operation (HIP events on the library's stream); `critical_path` for the
 DEIM chain on the second stream; `cpu_baseline` times the FP64 oracle on a
 bounded sample of the same workload, on one host core and on all of them.
+`dmd_deim` runs the paper's full method (Alg. 2: DMD of the potential, DEIM,
+parameter subset) on its weak Landau damping ensemble (Sec. 6.2) with the
+same fields, and `serve` a Poisson-arrival mix of requests.
 """
 import argparse
 import json
@@ -64,6 +67,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-step-scale", type=float, default=0.25)
     ap.add_argument("--serve-gap", type=float, default=1.0, help="mean inter-arrival (s)")
+    ap.add_argument("--no-dmd", action="store_true", help="skip the DMD-DEIM leg")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     return ap.parse_args()
@@ -217,6 +221,95 @@ def matched_error(binding, torch, w, src, cfg, steps):
                           "at the last step; target = truncated complex SVD of the FOM state; "
                           "energy error max over steps and parameters of |E_rom - E_fom| / "
                           "max_t E_fom"}
+
+
+def dmd_deim_leg(binding, torch, steps, warmup, p=1024, p_sweep=(300, 1024, 2048)):
+    """The DMD-DEIM reduced model (Alg. 2) on the weak Landau damping
+    ensemble of Sec. 6.2 (eta = (alpha, sigma), k = 0.5, N = 5e4, N_x = 32,
+    dt = 0.0025, quiet start; p* = 16 subset parameters, window T = 3, d = 32
+    DEIM rows, 12 of them chosen again per step with a full greedy every 3rd)
+    at p parameters and rank 2n = 6 (the quiet-start ensemble has complex
+    rank 3 at t = 0, the density perturbation its smallest part; the paper's
+    2n = 4 drops it): throughput of the reduced and full-order steps, their
+    ratio, the matched error over the same steps from t = 0, and the step
+    time over a range of p (the reduced step's cost per parameter does not
+    depend on N)."""
+    import numpy as np
+    from workloads import workload, particle_uniforms
+    from workloads.ensembles import draw_parameters
+
+    def setup(pp):
+        w = workload("landau_ld", p=pp)
+        params = draw_parameters(w)
+        ux, uv = particle_uniforms(w)
+        src = dict(family=w["family"], params=params, ux=ux, uv=uv)
+        cfg = binding.make_config(w["N"], pp, w["Nx"], 6, two_n_max=6, dt=w["dt"],
+                                  projection="dmd_deim", deim_window=w["deim_window"],
+                                  p_star=w["p_star"], deim_rows=w["deim_rows"],
+                                  deim_update_every=w["deim_update_every"],
+                                  deim_update_rows=w["deim_update_rows"], fp_tol=1e-9)
+        return w, src, cfg
+
+    def rates(w, src, cfg, with_events=False):
+        r = binding.Rom(cfg, None, None, None, **src)
+        r.step(warmup + w["deim_window"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = r.step(steps)
+        torch.cuda.synchronize()
+        t_rom = time.perf_counter() - t0
+        rank = r.dmd_state()[1]
+        fams = None
+        if with_events:
+            binding.set_timing(True)
+            for fam in binding.FAMILIES:
+                binding.kernel_ms(fam)
+            r.step(steps)
+            torch.cuda.synchronize()
+            fams = {f: binding.kernel_ms(f)[0] / steps for f in binding.FAMILIES}
+            binding.set_timing(False)
+        r.close()
+        del r
+        torch.cuda.empty_cache()
+        f = binding.Fom(w["N"], cfg.p, w["Nx"], w["dt"], None, None, None, **src)
+        f.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f.step(steps)
+        torch.cuda.synchronize()
+        t_fom = time.perf_counter() - t0
+        f.close()
+        del f
+        torch.cuda.empty_cache()
+        return t_rom, t_fom, info, rank, fams
+
+    w, src, cfg = setup(p)
+    t_rom, t_fom, info, rank, fams = rates(w, src, cfg, with_events=True)
+    pp = w["N"] * p
+    out = {"workload": "landau_ld", "N": w["N"], "p": p, "Nx": w["Nx"], "dt": w["dt"],
+           "two_n": 6, "p_star": w["p_star"], "deim_rows": w["deim_rows"],
+           "deim_window": w["deim_window"], "deim_update_every": w["deim_update_every"],
+           "deim_update_rows": w["deim_update_rows"], "loading": "hammersley (quiet start)",
+           "value": pp * steps / t_rom, "unit": "particle-param-steps/s",
+           "ms_per_step": 1e3 * t_rom / steps, "mean_fp_iters": info["iters_total"] / steps,
+           "stalled_columns": info["stalled_total"], "dmd_rank": rank,
+           "fom": {"value": pp * steps / t_fom, "ms_per_step": 1e3 * t_fom / steps},
+           "rom_over_fom": t_fom / t_rom,
+           "kernel_families_ms_per_step": fams}
+    out["matched_error"] = matched_error(binding, torch, w, src, cfg,
+                                         warmup + w["deim_window"] + steps)
+    sweep = []
+    for pv in p_sweep:
+        if pv == p:
+            sweep.append({"p": pv, "rom_ms": out["ms_per_step"],
+                          "fom_ms": out["fom"]["ms_per_step"], "rom_over_fom": out["rom_over_fom"]})
+            continue
+        w2, src2, cfg2 = setup(pv)
+        tr, tf, _, _, _ = rates(w2, src2, cfg2)
+        sweep.append({"p": pv, "rom_ms": 1e3 * tr / steps, "fom_ms": 1e3 * tf / steps,
+                      "rom_over_fom": tf / tr})
+    out["p_sweep"] = sweep
+    return out
 
 
 def serve_bench(binding, torch, n_req, step_scale, slots, pool_gb, mean_gap_s, seed=4001):
@@ -444,6 +537,8 @@ def main():
     if not a.no_matched:
         out["matched_error"] = matched_error(binding, torch, w, src, cfg, a.warmup + a.steps)
         out["matched_error"]["rom_over_fom_at_this_error"] = rom_rate / fom_rate
+    if not a.no_dmd:
+        out["dmd_deim"] = dmd_deim_leg(binding, torch, a.steps, a.warmup)
     if not a.no_serve:
         out["serve"] = serve_bench(binding, torch, a.serve_requests, a.serve_step_scale, 4, 96.0,
                                    a.serve_gap)

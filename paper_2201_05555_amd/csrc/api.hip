@@ -1862,52 +1862,70 @@ symrom_status rom_init_impl(const symrom_config* cfg, const double* L,
     delete r;
     return fail(SYMROM_EDEVICE, "rom_init: eigen readback");
   }
-  int rk = 0;
-  while (rk < n && rk < nl && lam[rk] > 1e-26 * lam[0] && lam[rk] > 0.0) ++rk;
-  // U[:, :rk] = C0 V_rk diag(lam)^{-1/2}
-  hipLaunchKernelGGL(scale_cols_kernel, dim3((p * rk + 255) / 256 + 1), dim3(256), 0, s, r->Vp,
-                     r->lam, p, rk, r->Q);
-  if (rk > 0) launch_rowgemm(s, rt(r->G, r->Q, p), N, rk, r->U0);
-  // completion by Gram-Schmidt of e_0, e_1, ... (two projections via CholQR2)
-  int j = 0;
-  int have = rk;
-  std::vector<cplx> gram;
-  while (have < n) {
-    if (j >= N) {
-      delete r;
-      return fail(SYMROM_EINVAL, "rom_init: cannot complete the basis");
-    }
-    hipLaunchKernelGGL(unit_minus_proj_kernel, dim3((N + 255) / 256), dim3(256), 0, s, r->U0, N,
-                       have, j);
-    // accept if the projected vector is not negligible
-    launch_gemm_ah_b(s, ml(r->U0 + (size_t)have * N, 1), 1, ml(r->U0 + (size_t)have * N, 1), 1,
-                     false, N, r->nkb, r->gemm_part, r->Gram);
-    cplx nv;
-    if (hipMemcpyAsync(&nv, r->Gram, sizeof(cplx), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-      delete r;
-      return fail(SYMROM_EDEVICE, "rom_init: readback");
-    }
-    ++j;
-    if (std::sqrt(nv.re) > 1e-8) {
-      hipLaunchKernelGGL(scale_col_kernel, dim3((N + 255) / 256), dim3(256), 0, s,
-                         r->U0 + (size_t)have * N, N, 1.0 / std::sqrt(nv.re));
-      ++have;
-    }
-  }
-  // orthonormalise (CholQR2), then Z = U^* C0
-  r->n = n;
-  launch_fill_cplx(s, r->Z0, (size_t)n * p, mk(0.0, 0.0));
-  cholqr2(*r, r->U0, nullptr);
-  launch_gemm_ah_b(s, ml(r->U0, n), n, ml(r->G, p), p, false, N, r->nkb, r->gemm_part, r->Z0);
-  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
-    delete r;
-    return fail(SYMROM_EDEVICE, "rom_init: launch failure");
-  }
+  // The basis: the leading eigenpairs of C0^* C0 (U = C0 V lam^{-1/2}),
+  // completed by Gram-Schmidt of e_0, e_1, ..., then two Cholesky-QR passes
+  // and Z = U^* C0.  Eigenpairs far below the largest are not resolved by
+  // the Gram (their vectors are rounding): when the orthonormalisation fails
+  // with every pair above 1e-26 lam_0, it is redone with the pairs above
+  // 1e-13 lam_0 (vectors accurate to about 1e-3, which the Cholesky-QR
+  // passes repair), the completion taking the rest.
+  const double lam_floor[2] = {1e-26, 1e-13};
   int fl[2] = {0, 0};
-  if (hipMemcpy(fl, r->flags, 2 * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
-    delete r;
-    return fail(SYMROM_EDEVICE, "rom_init: flags readback");
+  int rk_prev = -1;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    int rk = 0;
+    while (rk < n && rk < nl && lam[rk] > lam_floor[attempt] * lam[0] && lam[rk] > 0.0) ++rk;
+    if (rk == rk_prev) break;
+    rk_prev = rk;
+    if (hipMemsetAsync(r->flags, 0, 2 * sizeof(int), s) != hipSuccess) {
+      delete r;
+      return fail(SYMROM_EDEVICE, "rom_init: memset");
+    }
+    // U[:, :rk] = C0 V_rk diag(lam)^{-1/2}
+    hipLaunchKernelGGL(scale_cols_kernel, dim3((p * rk + 255) / 256 + 1), dim3(256), 0, s, r->Vp,
+                       r->lam, p, rk, r->Q);
+    if (rk > 0) launch_rowgemm(s, rt(r->G, r->Q, p), N, rk, r->U0);
+    // completion by Gram-Schmidt of e_0, e_1, ... (two projections via CholQR2)
+    int j = 0;
+    int have = rk;
+    std::vector<cplx> gram;
+    while (have < n) {
+      if (j >= N) {
+        delete r;
+        return fail(SYMROM_EINVAL, "rom_init: cannot complete the basis");
+      }
+      hipLaunchKernelGGL(unit_minus_proj_kernel, dim3((N + 255) / 256), dim3(256), 0, s, r->U0, N,
+                         have, j);
+      // accept if the projected vector is not negligible
+      launch_gemm_ah_b(s, ml(r->U0 + (size_t)have * N, 1), 1, ml(r->U0 + (size_t)have * N, 1), 1,
+                       false, N, r->nkb, r->gemm_part, r->Gram);
+      cplx nv;
+      if (hipMemcpyAsync(&nv, r->Gram, sizeof(cplx), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        delete r;
+        return fail(SYMROM_EDEVICE, "rom_init: readback");
+      }
+      ++j;
+      if (std::sqrt(nv.re) > 1e-8) {
+        hipLaunchKernelGGL(scale_col_kernel, dim3((N + 255) / 256), dim3(256), 0, s,
+                           r->U0 + (size_t)have * N, N, 1.0 / std::sqrt(nv.re));
+        ++have;
+      }
+    }
+    // orthonormalise (CholQR2), then Z = U^* C0
+    r->n = n;
+    launch_fill_cplx(s, r->Z0, (size_t)n * p, mk(0.0, 0.0));
+    cholqr2(*r, r->U0, nullptr);
+    launch_gemm_ah_b(s, ml(r->U0, n), n, ml(r->G, p), p, false, N, r->nkb, r->gemm_part, r->Z0);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+      delete r;
+      return fail(SYMROM_EDEVICE, "rom_init: launch failure");
+    }
+    if (hipMemcpy(fl, r->flags, 2 * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+      delete r;
+      return fail(SYMROM_EDEVICE, "rom_init: flags readback");
+    }
+    if (!fl[0]) break;
   }
   if (fl[0]) {
     delete r;

@@ -208,3 +208,27 @@ def test_large_p_rank_growth():
     assert err < tol
     Utg = UXn[:, :6] - 1j * UXn[:, 6:]
     assert np.abs(Utg.conj().T @ Utg - np.eye(6)).max() < 1e-12
+
+
+def test_init_beyond_the_numerical_rank():
+    """A rank far above the ensemble's numerical rank (Landau, p = 51, whose
+    singular values fall below 1e-13 of the largest after about ten; 2n =
+    60): the eigenpairs of C0^* C0 that the Gram resolves (above 1e-13 of
+    the largest eigenvalue) are kept and Gram-Schmidt completes the basis.
+    The basis is orthonormal and R_0 misses only the dropped tail (2e-8 of
+    |C_0| here; the oracle's SVD keeps it)."""
+    binding, torch = _b()
+    w = workload("landau_tiny", p=51, N=20000, Nx=128)
+    _say("init beyond the numerical rank")
+    e = make_ensemble(w)
+    r = binding.Rom(binding.make_config(w["N"], w["p"], w["Nx"], 60, dt=w["dt"]), e["L"],
+                    e["X0"], e["V0"])
+    X, V = r.reconstruct()
+    C = e["X0"] + 1j * e["V0"]
+    R = _np(X).T + 1j * _np(V).T
+    err = float(np.linalg.norm(R - C) / np.linalg.norm(C))
+    UX = _np(r.get_state()[0]).T
+    Ut = UX[:, :30] - 1j * UX[:, 30:]
+    orth = float(np.abs(Ut.conj().T @ Ut - np.eye(30)).max())
+    print(f"  |R0 - C0| / |C0| = {err:.2e}, orthonormality {orth:.2e}", flush=True)
+    assert err < 1e-7 and orth < 1e-12
