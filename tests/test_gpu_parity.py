@@ -159,6 +159,11 @@ def test_rom_init_parity(name, kw, two_n):
 @pytest.mark.parametrize("name,kw,two_n", [
     ("landau_tiny", dict(N=3001), 10),
     ("twostream_deim", dict(N=20000, p=24, Nx=128), 16),
+    # a grid whose 64-parameter field table does not fit the LDS budget: the
+    # tiled gather-projection (field rows of 32 parameters in LDS), with a
+    # ragged last tile
+    ("twostream_deim", dict(N=20000, p=70, Nx=512), 16),
+    ("twostream_deim", dict(N=9001, p=33, Nx=512), 10),
 ])
 def test_rom_gradient_parity(name, kw, two_n):
     binding, torch = _b()
