@@ -610,6 +610,7 @@ struct symrom_rom {
   int* bidx;
   int nbg, nbc;
   cplx *YG, *YV, *C12, *C12a, *gF;
+  cplx* C12t;  // the Grams of a basis passed to full_gradient without its own
   double* dpart;  // split-K partials of the DEIM Gram (its own: the chain runs beside the main work)
   // The DEIM operator is built on a second stream (default priority) beside
   // the basis velocity and Cayley map of the same step, which do not need it;
@@ -768,6 +769,7 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   r.YV = ar.take<cplx>((size_t)P * P);
   r.C12 = ar.take<cplx>((size_t)2 * nm * nm);
   r.C12a = ar.take<cplx>((size_t)2 * nm * nm);
+  r.C12t = ar.take<cplx>((size_t)2 * nm * nm);
   r.gF = ar.take<cplx>((size_t)nm * p);
   r.zsig = ar.take<double>(nm);
   r.Ysub = ar.take<cplx>(64 * 64);
@@ -975,26 +977,34 @@ void full_gradient_field(symrom_rom& r, const cplx* U, const cplx* Z, const int*
   }
 }
 
+void linear_grams(symrom_rom& r, const cplx* U, cplx* C12);
+
 // g = U^* G~ with the full gradient of every column at (U, Z): the field
 // first when do_deposit (else the one in the buffers), then either the
-// fused gather-projection (G~ never stored) or, for ranks beyond the fused
-// kernels, the gather into r.G and a split-K product.  With want_colsq,
-// |G~[:, c]|^2 goes to r.colsq.
+// fused gather-projection (G~ never stored; the velocity part from the
+// Grams G12 = [U^* U, U^T U] of this U, formed here into r.C12t when not
+// given) or, for ranks beyond the fused kernels, the gather into r.G and a
+// split-K product.  With want_colsq, |G~[:, c]|^2 goes to r.colsq.
 void full_gradient(symrom_rom& r, const cplx* U, const cplx* Z, const int* active,
-                   bool do_deposit, bool want_colsq = false, const int* gate = nullptr) {
+                   bool do_deposit, bool want_colsq = false, const int* gate = nullptr,
+                   const cplx* G12 = nullptr) {
   hipStream_t s = r.s;
   const int n = r.n;
   const double qm = r.cfg.q / r.cfg.m;
   if (do_deposit) full_gradient_field(r, U, Z, active, gate);
   const double pact = (active ? (double)r.n_active : (double)r.p);
   if (fused_gradient_ok(n)) {
-    // per (particle, parameter): 4n flops for x and v, 4n for the projection,
-    // 4 for |G~|^2; bytes: the basis and the coefficients read once, g written
-    // (the field table, O(p Nx), is negligible)
-    Timer t(FAM_GATHER, s, (8.0 * n + 4.0) * (double)r.N * pact,
+    if (!G12) {
+      linear_grams(r, U, r.C12t);
+      G12 = r.C12t;
+    }
+    // per (particle, parameter): 4n flops for x, 4n for the projection of
+    // F, 2 for |F|^2; bytes: the basis and the coefficients read once, g
+    // written (the field table, O(p Nx), is negligible)
+    Timer t(FAM_GATHER, s, (8.0 * n + 2.0) * (double)r.N * pact,
             16.0 * n * ((double)r.N + 2.0 * r.p));
     launch_gather_project(s, U, r.N, n, Z, r.p, r.Nx, r.b.factor, r.b.e, qm, active, want_colsq,
-                          r.gemm_part, (size_t)r.nkb * 64 * 64, r.gproj, r.colsq, gate);
+                          r.gemm_part, (size_t)r.nkb * 64 * 64, r.gproj, r.colsq, G12, gate);
     return;
   }
   {
@@ -1034,10 +1044,10 @@ void basis_velocity(symrom_rom& r, const cplx* U, const cplx* Z, double scale, c
       Timer t(FAM_DENSE, s);
       launch_dense_xfinish(s, r.gproj, r.Q, n, r.p, 2.0 * scale, k1, r.MP, r.MU);
     }
-    // per (particle, parameter): 4n flops for x and v, 4n for G~ Q; plus 4n^2
-    // per particle for U MU; bytes: U read, out written.  Without k1 the
-    // kernel forms MU from g~ and Q itself (no separate launch).
-    Timer t(FAM_XI, s, 8.0 * n * (double)r.N * r.p + 8.0 * n * n * (double)r.N,
+    // per (particle, parameter): 4n flops for x, 4n for F (-i h Q); plus
+    // 16n^2 per particle for U M + conj(U) N; bytes: U read, out written.
+    // Without k1 the kernel forms MU from g~ and Q itself (no separate launch).
+    Timer t(FAM_XI, s, 8.0 * n * (double)r.N * r.p + 16.0 * n * n * (double)r.N,
             32.0 * n * (double)r.N);
     launch_gather_xi(s, U, r.N, n, Z, r.p, r.Nx, r.b.factor, r.b.e, r.cfg.q / r.cfg.m, r.Q, r.MU,
                      scale, out, k1 ? nullptr : r.gproj);
@@ -1282,8 +1292,14 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   // DMD-DEIM before its windows are full (Alg. 2, first T steps): the plain
   // reduced step, recording the snapshot and the subset potentials
   const bool record = r.cfg.projection == SYMROM_DMD_DEIM;
-  // stage 1 at (U0, Z0): full gradient, k1 = J g, basis velocity -> xi_half
-  if (!r.stage1_cached) full_gradient(r, r.U0, r.Z0, nullptr, true);
+  // stage 1 at (U0, Z0): full gradient, k1 = J g, basis velocity -> xi_half.
+  // With the fused gradient the Grams of U0 (its velocity part; also the
+  // DEIM start's) are formed first, or were formed with the cached gradient.
+  const bool fused = fused_gradient_ok(n);
+  if (!r.stage1_cached) {
+    if (fused) linear_grams(r, r.U0, r.C12a);
+    full_gradient(r, r.U0, r.Z0, nullptr, true, false, nullptr, fused ? r.C12a : nullptr);
+  }
   r.stage1_cached = false;
   // the DEIM chain is already enqueued when it was built ahead for this rank
   const bool chain_ready = use_deim && r.head_pending && r.head_n == n;
@@ -1303,10 +1319,10 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
     deim_update_tail(r);
     HIPCHK(hipEventRecord(r.ev_join, r.s2));
   }
-  if (deim) linear_grams(r, r.U0, r.C12a);
+  if (deim && !fused) linear_grams(r, r.U0, r.C12a);
   // U_half = R_{U0}(xi_half)
   cayley(r, r.U0, r.Xi, r.Uh, r.Amat);
-  if (deim) linear_grams(r, r.Uh, r.C12);
+  if (deim || fused) linear_grams(r, r.Uh, r.C12);
   if (use_deim || record) HIPCHK(hipStreamWaitEvent(s, r.ev_join, 0));
   // fixed point for k2 at U_half: start values (with DEIM in the launch that
   // gathers the first stage's gradient)
@@ -1355,7 +1371,7 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
                               fixed > 0 ? 1 : 0, launched + 1, r.counters);
         }
       } else {
-        full_gradient(r, r.Uh, r.Zev, r.active, true, false, gate);
+        full_gradient(r, r.Uh, r.Zev, r.active, true, false, gate, fused ? r.C12 : nullptr);
         Timer t(FAM_DENSE, s);
         launch_dense_fp_update(s, r.gproj, r.C12, n, p, r.Z0, r.Zev, r.ZG, r.k, r.prev, r.active,
                                dt, r.cfg.fp_tol, r.cfg.fp_stall_tol, fixed > 0 ? 1 : 0, 0,
@@ -1418,7 +1434,7 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   } else {
     launch_dense_finish_z(s, r.Z0, r.k, n, p, dt, r.Z1);
   }
-  full_gradient(r, r.Uh, r.ZG, nullptr, false);
+  full_gradient(r, r.Uh, r.ZG, nullptr, false, false, nullptr, fused ? r.C12 : nullptr);
   if (side) HIPCHK(hipStreamWaitEvent(s, r.ev_sp1, 0));
   basis_velocity(r, r.Uh, r.ZG, 1.0, r.Xv, nullptr, side);
   tangent_retract(r);
@@ -1436,7 +1452,9 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
     // only the field) its projection and the indicator
     full_gradient_field(r, r.U0, r.Z0, nullptr, nullptr, use_deim ? r.status : nullptr);
     if (ahead) HIPCHK(hipEventRecord(r.ev_fork, s));
-    full_gradient(r, r.U0, r.Z0, nullptr, false, true);
+    // (the Grams of the new U0 stay in C12a for the next step's first stage)
+    if (fused) linear_grams(r, r.U0, r.C12a);
+    full_gradient(r, r.U0, r.Z0, nullptr, false, true, nullptr, fused ? r.C12a : nullptr);
     launch_dense_indicator(s, r.colsq, r.gproj, n, p, r.eps_dev);
     if (r.cfg.rank_tol_down > 0.0) launch_shrink_cert(r);
   }
@@ -1543,9 +1561,10 @@ symrom_status rom_step_dmd(symrom_rom& r) {
   HIPCHK(hipMemsetAsync(r.counters, 0, 8 * sizeof(int), s));
   HIPCHK(hipMemsetAsync(r.status + 14, 0, sizeof(int), s));
   launch_gather_zcols(s, r.Z0, n, r.sub, ps, r.Zs);
+  linear_grams(r, r.U0, r.C12a);
   {
     SubsetView v(r);
-    full_gradient(r, r.U0, r.Zs, nullptr, true);
+    full_gradient(r, r.U0, r.Zs, nullptr, true, false, nullptr, r.C12a);
     HIPCHK(hipEventRecord(r.ev_fork, s));
     HIPCHK(hipStreamWaitEvent(r.s2, r.ev_fork, 0));
     HIPCHK(hipStreamWaitEvent(r.s3, r.ev_fork, 0));
@@ -1574,7 +1593,6 @@ symrom_status rom_step_dmd(symrom_rom& r) {
     launch_dmd_tables(r.s3, c, p, r.beta, r.b.h, r.e0, r.eh);
   }
   HIPCHK(hipEventRecord(r.ev_join3, r.s3));
-  linear_grams(r, r.U0, r.C12a);
   cayley(r, r.U0, r.Xi, r.Uh, r.Amat);
   linear_grams(r, r.Uh, r.C12);
   HIPCHK(hipStreamWaitEvent(s, r.ev_join, 0));
@@ -1618,7 +1636,7 @@ symrom_status rom_step_dmd(symrom_rom& r) {
   launch_gather_zcols(s, r.ZG, n, r.sub, ps, r.Zs);
   {
     SubsetView v(r);
-    full_gradient(r, r.Uh, r.Zs, nullptr, true);
+    full_gradient(r, r.Uh, r.Zs, nullptr, true, false, nullptr, r.C12);
     basis_velocity(r, r.Uh, r.Zs, 1.0, r.Xv, nullptr);
   }
   tangent_retract(r);
@@ -1964,7 +1982,9 @@ symrom_status rom_init_impl(const symrom_config* cfg, const double* L,
     std::vector<int> S(ps), id(ps);
     for (int k = 0; k < ps; ++k) id[k] = k;
     std::vector<double> Ls(ps), factor, qw, h, mw;
-    bool okc = hipMemcpyAsync(S.data(), r->sub, ps * sizeof(int), hipMemcpyDeviceToHost, s) ==
+    // (no DMD yet: rank 0 until the first DMD-DEIM step)
+    bool okc = hipMemsetAsync(r->dmd.rdev, 0, 4 * sizeof(int), s) == hipSuccess &&
+               hipMemcpyAsync(S.data(), r->sub, ps * sizeof(int), hipMemcpyDeviceToHost, s) ==
                    hipSuccess &&
                hipMemcpyAsync(r->sub_id, id.data(), ps * sizeof(int), hipMemcpyHostToDevice, s) ==
                    hipSuccess &&
@@ -2108,7 +2128,11 @@ symrom_status rom_grow(symrom_rom& r, int k, bool decide) {
   hipStream_t s = r.s;
   const int n = r.n, p = r.p;
   HIPCHK(hipMemsetAsync(r.flags, 0, 2 * sizeof(int), s));
-  full_gradient(r, r.U0, r.Z0, nullptr, true, decide);
+  // (the Grams of U0 into C12a: this gradient may become the next step's
+  // first stage)
+  const bool fused = fused_gradient_ok(n);
+  if (fused) linear_grams(r, r.U0, r.C12a);
+  full_gradient(r, r.U0, r.Z0, nullptr, true, decide, nullptr, fused ? r.C12a : nullptr);
   if (decide) {
     // eps needs only |G|^2 and |g|^2
     launch_dense_indicator(s, r.colsq, r.gproj, n, p, r.eps_dev);
@@ -2375,6 +2399,8 @@ extern "C" symrom_status rom_dmd_state(symrom_rom* r, int32_t* S, int32_t* pstar
   int rk = 0;
   HIPCHK(hipMemcpyAsync(&rk, r->dmd.rdev, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  // (the rank of the last DMD, at most the window width p* T <= 64)
+  if (rk < 0 || rk > 64) return fail(SYMROM_EDEVICE, "rom_dmd_state: corrupt DMD rank");
   if (rank) *rank = rk;
   if (lam && rk > 0)
     HIPCHK(hipMemcpyAsync(lam, r->dmd.lam, (size_t)rk * sizeof(cplx), hipMemcpyDeviceToHost, s));

@@ -301,19 +301,24 @@ __global__ void dmd_window_kernel(const double* __restrict__ ring, int nslots, i
 }
 
 // ---------------------------------------------------------------------------
-// Householder QR of an Nx x P matrix W (column-major, in place), one
+// Householder QR of an Nx x P matrix W (column-major, leading dimension ld,
+// in place), one
 // workgroup of 256: reflector k (k < min(Nx, P)) is stored below the
 // diagonal with its head in W[k, k] replaced by v_0, alpha_k (the diagonal
 // of R) in alpha[k] and 2 / v^T v in tau[k]; R above the diagonal stays in
-// W.  Every further column (and the ncx columns of X, Nx x ncx, when given)
-// is updated by the wavefront that owns it (column j by wave j mod 4).
+// W.  Every further column (and the ncx columns of X, Nx x ncx with the same
+// leading dimension, when given)
+// is updated either by one thread that runs down its rows (ByThread: W in
+// LDS, no cross-lane reduction and independent loads) or by the wavefront
+// that owns it (column j by wave j mod 4, coalesced rows: W in global).
 // ---------------------------------------------------------------------------
-__device__ void householder_qr(double* W, int Nx, int P, double* alpha, double* tau, double* X,
-                               int ncx, double* red) {
+template <bool ByThread>
+__device__ void householder_qr(double* W, int Nx, int ld, int P, double* alpha, double* tau,
+                               double* X, int ncx, double* red) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int mq = min(Nx, P);
   for (int k = 0; k < mq; ++k) {
-    double* wk = W + (size_t)k * Nx;
+    double* wk = W + (size_t)k * ld;
     double s = 0.0;
     for (int i = k + t; i < Nx; i += 256) s += wk[i] * wk[i];
     const double nrm2 = block_sum(s, red);
@@ -332,14 +337,30 @@ __device__ void householder_qr(double* W, int Nx, int P, double* alpha, double* 
     __syncthreads();
     if (tk != 0.0) {
       const int ntot = (P - k - 1) + ncx;
-      for (int c = wv; c < ntot; c += 4) {
-        double* col = (c < P - k - 1) ? W + (size_t)(k + 1 + c) * Nx
-                                      : X + (size_t)(c - (P - k - 1)) * Nx;
-        double d = 0.0;
-        for (int i = k + lane; i < Nx; i += 64) d = fma(wk[i], col[i], d);
-        for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
-        const double f = tk * d;
-        for (int i = k + lane; i < Nx; i += 64) col[i] = fma(-f, wk[i], col[i]);
+      if (ByThread) {
+        for (int c = t; c < ntot; c += 256) {
+          double* col = (c < P - k - 1) ? W + (size_t)(k + 1 + c) * ld
+                                        : X + (size_t)(c - (P - k - 1)) * ld;
+          double d0 = 0.0, d1 = 0.0;
+          int i = k;
+          for (; i + 1 < Nx; i += 2) {
+            d0 = fma(wk[i], col[i], d0);
+            d1 = fma(wk[i + 1], col[i + 1], d1);
+          }
+          if (i < Nx) d0 = fma(wk[i], col[i], d0);
+          const double f = tk * (d0 + d1);
+          for (int i2 = k; i2 < Nx; ++i2) col[i2] = fma(-f, wk[i2], col[i2]);
+        }
+      } else {
+        for (int c = wv; c < ntot; c += 4) {
+          double* col = (c < P - k - 1) ? W + (size_t)(k + 1 + c) * ld
+                                        : X + (size_t)(c - (P - k - 1)) * ld;
+          double d = 0.0;
+          for (int i = k + lane; i < Nx; i += 64) d = fma(wk[i], col[i], d);
+          d = wave_sum64(d);
+          const double f = tk * d;
+          for (int i = k + lane; i < Nx; i += 64) col[i] = fma(-f, wk[i], col[i]);
+        }
       }
     }
     __syncthreads();
@@ -371,6 +392,7 @@ __global__ void __launch_bounds__(256) dmd_svd_kernel(double* __restrict__ W, in
   __shared__ double alpha[64], tau[64];
   __shared__ double sv[64];
   __shared__ int rot, rkeep;
+  __shared__ int perm[64];
   extern __shared__ double jsm[];
   // column j at Rs[j * JS]: the stride of 65 doubles puts element i of the
   // columns that concurrent pair groups rotate in different LDS banks
@@ -378,7 +400,25 @@ __global__ void __launch_bounds__(256) dmd_svd_kernel(double* __restrict__ W, in
   double* Rs = jsm;
   double* Vs = jsm + 64 * JS;
   const int t = threadIdx.x;
-  householder_qr(W, Nx, P, alpha, tau, nullptr, 0, red);
+  // the QR in LDS when the window fits (ldl P <= 8192 doubles, ldl = N_x
+  // rounded up to odd so that the columns that the threads of a wavefront
+  // walk down fall in different banks): every reflection then waits on LDS,
+  // not on global loads
+  const int ldl = Nx | 1;
+  const bool lw = ldl * P <= 8192;
+  const int ldq = lw ? ldl : Nx;
+  double* Wl = jsm + 2 * 64 * JS;
+  if (lw) {
+    for (int q = t; q < Nx * P; q += 256) {
+      const int j = q / Nx, i = q - j * Nx;
+      Wl[j * ldl + i] = W[q];
+    }
+    __syncthreads();
+    householder_qr<true>(Wl, Nx, ldl, P, alpha, tau, nullptr, 0, red);
+  } else {
+    householder_qr<false>(W, Nx, Nx, P, alpha, tau, nullptr, 0, red);
+  }
+  const double* Wq = lw ? Wl : W;
   const int m = min(Nx, P);
   // Jacobi on the columns of R (m x P) when m = P, on those of R^T (P x m)
   // when the window is wider than the grid (m < P): C columns of length ell,
@@ -391,7 +431,7 @@ __global__ void __launch_bounds__(256) dmd_svd_kernel(double* __restrict__ W, in
     double v = 0.0;
     if (j < C && i < ell) {
       const int ri = wide ? j : i, rj = wide ? i : j;  // the entry R[ri][rj]
-      v = (ri < rj) ? W[(size_t)rj * Nx + ri] : (ri == rj ? alpha[ri] : 0.0);
+      v = (ri < rj) ? Wq[(size_t)rj * ldq + ri] : (ri == rj ? alpha[ri] : 0.0);
     }
     Rs[j * JS + i] = v;
     Vs[j * JS + i] = (i == j && j < C) ? 1.0 : 0.0;
@@ -404,7 +444,15 @@ __global__ void __launch_bounds__(256) dmd_svd_kernel(double* __restrict__ W, in
     const double v = Rs[(q >> 6) * JS + (q & 63)];
     fr = fma(v, v, fr);
   }
-  const double tiny = 1e-30 * block_sum(fr, red);
+  const double frob2 = block_sum(fr, red);
+  const double tiny = 1e-30 * frob2;
+  // two columns both below (1e-3 tol)^2 |R|_F^2 are not rotated against each
+  // other: every column above that stays orthogonal to all others, so the
+  // singular triplets above it are those of the converged part, while all
+  // the singular values of the unsettled remainder sit below sqrt(C) 1e-3 tol
+  // |R|_F <= C 1e-3 tol sigma_1, under the truncation tol sigma_1 (its
+  // triplets are dropped anyway)
+  const double cut = fmax(tiny, 1e-6 * tol * tol * frob2);
   // round-robin pairs (circle method) over C2 = C rounded up to even; a
   // pair with the padding column is skipped
   const int C2 = C + (C & 1);
@@ -423,42 +471,52 @@ __global__ void __launch_bounds__(256) dmd_svd_kernel(double* __restrict__ W, in
       ib = ib + 1;
       const bool act = g < C2 / 2 && ia < C && ib < C;
       {
-        {
-          const int a = act ? min(ia, ib) : 0, b = act ? max(ia, ib) : 0;
-          double al = 0.0, be = 0.0, ga = 0.0;
-          if (act)
-            for (int i = sub; i < ell; i += 8) {
-              const double xa = Rs[a * JS + i], xb = Rs[b * JS + i];
-              al = fma(xa, xa, al);
-              be = fma(xb, xb, be);
-              ga = fma(xa, xb, ga);
-            }
-          // sums over the 8 lanes of the group by DPP butterflies
-          al += bfly64<0>(al);
-          be += bfly64<0>(be);
-          ga += bfly64<0>(ga);
-          al += bfly64<1>(al);
-          be += bfly64<1>(be);
-          ga += bfly64<1>(ga);
-          al += bfly64<2>(al);
-          be += bfly64<2>(be);
-          ga += bfly64<2>(ga);
-          if (act && ga != 0.0 && al > tiny && be > tiny && fabs(ga) > 1e-15 * sqrt(al * be)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            const double tt = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-            for (int i = sub; i < ell; i += 8) {
-              const double xa = Rs[a * JS + i], xb = Rs[b * JS + i];
-              Rs[a * JS + i] = c * xa - s * xb;
-              Rs[b * JS + i] = s * xa + c * xb;
-            }
-            for (int i = sub; i < C; i += 8) {
-              const double xa = Vs[a * JS + i], xb = Vs[b * JS + i];
-              Vs[a * JS + i] = c * xa - s * xb;
-              Vs[b * JS + i] = s * xa + c * xb;
-            }
-            if (sub == 0) rot = 1;
+        // the lane's elements of both columns (and of G) in registers: one
+        // batch of loads, the sums, the rotation, one batch of stores
+        // (unpredicated: entries past ell of a column of R and past C of
+        // one of G are zero and stay zero under the rotations, and an idle
+        // group reads column 0 and writes nothing)
+        const int a = act ? min(ia, ib) : 0, b = act ? max(ia, ib) : 0;
+        double xa[8], xb[8], ga_[8], gb_[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = sub + 8 * u;
+          xa[u] = Rs[a * JS + i];
+          xb[u] = Rs[b * JS + i];
+          ga_[u] = Vs[a * JS + i];
+          gb_[u] = Vs[b * JS + i];
+        }
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          al = fma(xa[u], xa[u], al);
+          be = fma(xb[u], xb[u], be);
+          ga = fma(xa[u], xb[u], ga);
+        }
+        // sums over the 8 lanes of the group by DPP butterflies
+        al += bfly64<0>(al);
+        be += bfly64<0>(be);
+        ga += bfly64<0>(ga);
+        al += bfly64<1>(al);
+        be += bfly64<1>(be);
+        ga += bfly64<1>(ga);
+        al += bfly64<2>(al);
+        be += bfly64<2>(be);
+        ga += bfly64<2>(ga);
+        if (act && ga != 0.0 && al > tiny && be > tiny && fmax(al, be) > cut &&
+            fabs(ga) > 1e-15 * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double tt = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int i = sub + 8 * u;
+            Rs[a * JS + i] = c * xa[u] - s * xb[u];
+            Rs[b * JS + i] = s * xa[u] + c * xb[u];
+            Vs[a * JS + i] = c * ga_[u] - s * gb_[u];
+            Vs[b * JS + i] = s * ga_[u] + c * gb_[u];
           }
+          if (sub == 0) rot = 1;
         }
       }
       __syncthreads();
@@ -494,32 +552,72 @@ __global__ void __launch_bounds__(256) dmd_svd_kernel(double* __restrict__ W, in
   }
   __syncthreads();
   // U: the small left vectors (the rotated columns over their norms for R,
-  // the rotations for R^T), padded to N_x rows
+  // the rotations for R^T), padded to N_x rows, then Q = H_0 ... H_{m-1}
+  // applied from the last reflector to the first.  With the reflectors in
+  // LDS the r columns are staged in the half of the Jacobi storage that the
+  // right vectors have been read from (ld ldl), column c of U is run by
+  // thread c, and U is written out at the end; otherwise U is formed in
+  // global memory, column c by wavefront c mod 4.
   const int r = rkeep;
+  if (t < C) {
+    int rank = 0;
+    for (int jj = 0; jj < C; ++jj) rank += (sv[jj] > sv[t]) || (sv[jj] == sv[t] && jj < t);
+    perm[t] = rank;
+  }
+  __syncthreads();
+  const double* src = wide ? Vs : Rs;
+  const bool lu = lw && r * ldl <= 64 * JS;
+  double* Ul = wide ? Rs : Vs;
   for (int q = t; q < C * Nx; q += 256) {
     const int j = q / Nx, i = q - j * Nx;
-    int rank = 0;
-    for (int jj = 0; jj < C; ++jj) rank += (sv[jj] > sv[j]) || (sv[jj] == sv[j] && jj < j);
-    if (rank < r)
-      Uout[(size_t)rank * Nx + i] =
-          (i < m) ? (wide ? Vs[j * JS + i] : Rs[j * JS + i] / sv[j]) : 0.0;
+    const int rank = perm[j];
+    if (rank < r) {
+      const double v = (i < m) ? (wide ? src[j * JS + i] : src[j * JS + i] / sv[j]) : 0.0;
+      if (lu)
+        Ul[rank * ldl + i] = v;
+      else
+        Uout[(size_t)rank * Nx + i] = v;
+    }
   }
   __threadfence_block();
   __syncthreads();
-  // then Q = H_0 ... H_{m-1} applied from the last reflector to the first
-  // (column c by wavefront c mod 4)
-  const int lane = t & 63, wv = t >> 6;
-  for (int c = wv; c < r; c += 4) {
-    double* u = Uout + (size_t)c * Nx;
-    for (int k = m - 1; k >= 0; --k) {
-      const double tk = tau[k];
-      if (tk == 0.0) continue;
-      const double* vk = W + (size_t)k * Nx;
-      double d = 0.0;
-      for (int i = k + lane; i < Nx; i += 64) d = fma(vk[i], u[i], d);
-      for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
-      const double f = tk * d;
-      for (int i = k + lane; i < Nx; i += 64) u[i] = fma(-f, vk[i], u[i]);
+  if (lu) {
+    for (int c = t; c < r; c += 256) {
+      double* u = Ul + c * ldl;
+      for (int k = m - 1; k >= 0; --k) {
+        const double tk = tau[k];
+        if (tk == 0.0) continue;
+        const double* vk = Wl + k * ldl;
+        double d0 = 0.0, d1 = 0.0;
+        int i = k;
+        for (; i + 1 < Nx; i += 2) {
+          d0 = fma(vk[i], u[i], d0);
+          d1 = fma(vk[i + 1], u[i + 1], d1);
+        }
+        if (i < Nx) d0 = fma(vk[i], u[i], d0);
+        const double f = tk * (d0 + d1);
+        for (int i2 = k; i2 < Nx; ++i2) u[i2] = fma(-f, vk[i2], u[i2]);
+      }
+    }
+    __syncthreads();
+    for (int q = t; q < r * Nx; q += 256) {
+      const int c = q / Nx, i = q - c * Nx;
+      Uout[q] = Ul[c * ldl + i];
+    }
+  } else {
+    const int lane = t & 63, wv = t >> 6;
+    for (int c = wv; c < r; c += 4) {
+      double* u = Uout + (size_t)c * Nx;
+      for (int k = m - 1; k >= 0; --k) {
+        const double tk = tau[k];
+        if (tk == 0.0) continue;
+        const double* vk = Wq + (size_t)k * ldq;
+        double d = 0.0;
+        for (int i = k + lane; i < Nx; i += 64) d = fma(vk[i], u[i], d);
+        d = wave_sum64(d);
+        const double f = tk * d;
+        for (int i = k + lane; i < Nx; i += 64) u[i] = fma(-f, vk[i], u[i]);
+      }
     }
   }
 }
@@ -845,7 +943,7 @@ __global__ void __launch_bounds__(256) dmd_coords_kernel(const double* __restric
   for (int q = t; q < Nx * r; q += 256) Wb[q] = B[q];
   __threadfence_block();
   __syncthreads();
-  householder_qr(Wb, Nx, r, alpha, tau, Wf, pstar, red);
+  householder_qr<false>(Wb, Nx, Nx, r, alpha, tau, Wf, pstar, red);
   double amax = 0.0;
   for (int k = 0; k < r; ++k) amax = fmax(amax, fabs(alpha[k]));
   bool bad = false;
@@ -1075,7 +1173,7 @@ void launch_dmd_operator(hipStream_t s, const DmdChainArgs& c) {
   // the QR works on a copy of Y (its reflectors stay there)
   (void)hipMemcpyAsync(c.W, c.Y, (size_t)c.Nx * P * sizeof(double), hipMemcpyDeviceToDevice, s);
   ALLOW_BIG_LDS(dmd_svd_kernel);
-  hipLaunchKernelGGL(dmd_svd_kernel, dim3(1), dim3(256), 2 * 64 * 65 * sizeof(double), s, c.W,
+  hipLaunchKernelGGL(dmd_svd_kernel, dim3(1), dim3(256), (2 * 64 * 65 + 8192) * sizeof(double), s, c.W,
                      c.Nx, P, c.tol, c.sig, c.V, c.rdev, c.U, c.flags);
   hipLaunchKernelGGL(dmd_form_kernel, dim3(1), dim3(256), 0, s, c.Yp, c.Nx, P, c.sig, c.V,
                      c.rdev, c.B, c.U, c.A);

@@ -118,11 +118,12 @@ bool launch_rowgemm_gram(hipStream_t s, const RowTerms& T, int N, int m, cplx* o
 // Fused gather + projection / basis velocity (G~ never stored); only for
 // n with fused_gradient_ok(n).  launch_gather_project writes g (n x p) and,
 // when want_colsq, |G~[:, c]|^2 into colsq; part holds part_cap complex.
+// G12 = [U~^* U~, U~^T U~] of this U (the velocity part comes from them).
 bool fused_gradient_ok(int n);
 void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p,
                            int Nx, const double* factor, const double* e, double qm,
                            const int* active, bool want_colsq, cplx* part, size_t part_cap,
-                           cplx* g, double* colsq, const int* gate = nullptr);
+                           cplx* g, double* colsq, const cplx* G12, const int* gate = nullptr);
 // g (optional): the projection g~ (n x p); MU is then formed from g and Q
 // inside the launch and the MU argument is not read
 void launch_gather_xi(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,

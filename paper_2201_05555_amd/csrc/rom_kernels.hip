@@ -451,15 +451,18 @@ __global__ void __launch_bounds__(64) deim_gather_kernel(
 
 
 // ---------------------------------------------------------------------------
-// Fused gather + projection (eq. grads): g = U~^* G~ (n x p) with
-// G~ = F + i v evaluated on the fly and never stored; F = (q/m) e_c at the
-// particle's cell, v = Im(U~ Z~).  Lanes are the 64 parameters of a tile
+// Fused gather + projection (eq. grads): the field part U~^* F of
+// g = U~^* G~ (n x p), G~ = F + i v, with F = (q/m) e_c at the particle's
+// cell evaluated on the fly and never stored.  The velocity part
+// i U~^* v, v = Im(U~ Z~), is linear in Z~ and is added by the reduction
+// from the small Gram matrices of U~ (it needs no pass over the particles).
+// Lanes are the 64 parameters of a tile
 // (blockIdx.y); each wavefront takes one particle row at a time, so the row
 // of U~ is wavefront-uniform (scalar loads, no LDS traffic) and the
 // projection needs no cross-lane reduction while rows stream.  The field
 // rows of the tile sit in LDS.  The eight wavefronts are summed in a fixed
 // order; block b writes part[b * rec + c * n + k] and, with want_colsq,
-// |G~[:, c]|^2 at part[b * rec + n * p + c].re.  Positions use the operation
+// |F[:, c]|^2 at part[b * rec + n * p + c].re.  Positions use the operation
 // order of the deposit, so both see the same cells.
 // ---------------------------------------------------------------------------
 template <int NC, bool ET_LDS>
@@ -513,29 +516,27 @@ __global__ void __launch_bounds__(512) gather_project_kernel(
       cplx u[NC];
 #pragma unroll
       for (int k = 0; k < NC; ++k) u[k] = (k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
-      double x0 = 0.0, x1 = 0.0, v0 = 0.0, v1 = 0.0;
+      double x0 = 0.0, x1 = 0.0;
 #pragma unroll
       for (int k = 0; k < NC; k += 2) {
         x0 = fma(u[k].re, z[k].re, x0);
         x0 = fma(-u[k].im, z[k].im, x0);
-        v0 = fma(u[k].re, z[k].im, v0);
-        v0 = fma(u[k].im, z[k].re, v0);
         if (k + 1 < NC) {
           x1 = fma(u[k + 1].re, z[k + 1].re, x1);
           x1 = fma(-u[k + 1].im, z[k + 1].im, x1);
-          v1 = fma(u[k + 1].re, z[k + 1].im, v1);
-          v1 = fma(u[k + 1].im, z[k + 1].re, v1);
         }
       }
-      const double v = v0 + v1;
       int j;
       double th;
       cell_of(x0 + x1, fac, Nx, j, th);
       const double F = ET_LDS ? et[lane * Nx + j] : qm * e[(size_t)c * Nx + j];
+      // conj(u) F
 #pragma unroll
-      for (int k = 0; k < NC; ++k) cfmac(acc[k], u[k], mk(F, v));
+      for (int k = 0; k < NC; ++k) {
+        acc[k].re = fma(u[k].re, F, acc[k].re);
+        acc[k].im = fma(-u[k].im, F, acc[k].im);
+      }
       csq = fma(F, F, csq);
-      csq = fma(v, v, csq);
     }
   }
   // the eight wavefronts summed in wave order through LDS (the field rows
@@ -586,11 +587,18 @@ __global__ void __launch_bounds__(512) gather_project_kernel(
 
 // C1[o] = sum_b part[b][o] for o < n1, C2[o - n1] = the real part of that sum
 // for n1 <= o < nout; blocks summed in a fixed order (one wavefront per output).
+// With G12 = [U~^* U~, U~^T U~] (n x n each, column-major) and the
+// coefficients Z (n x p) given, the velocity part of the gradient is added:
+// for o = c n + a < n1, (G1 z - conj(G2 z))_a / 2 with z = Z[:, c] (this is
+// i U~^* Im(U~ z)), and for o = n1 + c, |Im(U~ z)|^2 =
+// (z^* G1 z - Re(z^T G2 z)) / 2.
 __global__ void __launch_bounds__(256) reduce_partials2_kernel(const cplx* __restrict__ part,
                                                                int nkb, int rec, int n1, int nout,
                                                                cplx* __restrict__ C1,
                                                                double* __restrict__ C2,
-                                                               const int* __restrict__ gate) {
+                                                               const int* __restrict__ gate,
+                                                               const cplx* __restrict__ G12,
+                                                               const cplx* __restrict__ Z, int n) {
   if (gate && gate[0] == 0) return;
   const int lane = threadIdx.x & 63;
   const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -608,6 +616,33 @@ __global__ void __launch_bounds__(256) reduce_partials2_kernel(const cplx* __res
       im += in ? v[u].im : 0.0;
     }
   }
+  if (G12) {
+    const cplx* G1 = G12;
+    const cplx* G2 = G12 + (size_t)n * n;
+    if (o < n1) {
+      const int c = o / n, a = o - c * n;
+      const cplx* z = Z + (size_t)c * n;
+      for (int b = lane; b < n; b += 64) {
+        cplx t1 = mk(0.0, 0.0), t2 = mk(0.0, 0.0);
+        cfma(t1, G1[(size_t)b * n + a], z[b]);
+        cfma(t2, G2[(size_t)b * n + a], z[b]);
+        re += 0.5 * (t1.re - t2.re);
+        im += 0.5 * (t1.im + t2.im);
+      }
+    } else {
+      const int c = o - n1;
+      const cplx* z = Z + (size_t)c * n;
+      for (int t = lane; t < n * n; t += 64) {
+        const int b = t / n, a = t - b * n;
+        cplx t1 = mk(0.0, 0.0), t2 = mk(0.0, 0.0);
+        cfma(t1, G1[(size_t)b * n + a], z[b]);  // G1[a][b] z_b
+        cfma(t2, G2[(size_t)b * n + a], z[b]);  // G2[a][b] z_b
+        const cplx za = z[a];
+        // Re(conj(z_a) t1) - Re(z_a t2)
+        re += 0.5 * ((za.re * t1.re + za.im * t1.im) - (za.re * t2.re - za.im * t2.im));
+      }
+    }
+  }
   for (int s = 32; s > 0; s >>= 1) {
     re += __shfl_xor(re, s, 64);
     im += __shfl_xor(im, s, 64);
@@ -623,13 +658,19 @@ __global__ void __launch_bounds__(256) reduce_partials2_kernel(const cplx* __res
 // ---------------------------------------------------------------------------
 // Fused gather + basis velocity: out = G~ (-i h Q) + U~ MU (N x n), the
 // tangent step xi = h X~ of eq. Xdot in complex form (X~ = -i (G~ Q - U~ g~ Q)),
-// with G~ evaluated on the fly (not stored).  One thread per particle row;
-// the coefficients, -i h Q and (when they fit) the field rows of all
-// parameters sit in LDS; ILP parameters are processed at a time so their
-// independent position / cell / lookup chains interleave.  Q (p x n, ld p)
-// and MU (n x n, ld n) as written by the dense kernels; with g (n x p, the
-// projection g~) given instead of MU, every block forms MU = i h g~^T Q
-// itself from g and its copy of -i h Q (eight lanes per entry).
+// with G~ = F + i v.  Only the field part F (-i h Q) is evaluated per
+// particle and parameter (F at the particle's cell, never stored); the
+// velocity part h v Q, v = Im(U~ Z~), equals U~ (-(i h / 2) Z~ Q) +
+// conj(U~) ((i h / 2) conj(Z~) Q), two n x n products per row.  One thread
+// per particle row, the parameters in a loop: their coefficients, Q entries
+// and factors are wavefront-uniform (scalar loads into SGPRs, read by the
+// FP64 instructions directly, no LDS traffic); the field rows sit in LDS
+// when they fit (pc at a time), and ILP parameters are processed at a time
+// so their independent position / cell / lookup chains interleave.  Q (p x
+// n, ld p) and MU (n x n, ld n) as written by the dense kernels; with g (n x
+// p, the projection g~) given instead of MU, every block forms MU = i h g~^T
+// Q itself.  Every block forms the n x n matrices M and N in LDS (eight
+// lanes per entry).
 // ---------------------------------------------------------------------------
 template <int NC, bool ET_LDS>
 __global__ void __launch_bounds__(256) gather_xi_kernel(
@@ -637,81 +678,72 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
     const double* __restrict__ factor, const double* __restrict__ e, double qm,
     const cplx* __restrict__ Q, const cplx* __restrict__ MU, const cplx* __restrict__ gp,
     double h, cplx* __restrict__ out, int pc) {
-  constexpr int ILP = (NC <= 8) ? 4 : 2;
+  // (the coefficients of ILP parameters take 4 ILP NC SGPRs, then their Q
+  // entries as many)
+  constexpr int ILP = 2;
   extern __shared__ double smem[];
-  // parameters are staged pc at a time (all of them when p <= pc)
-  cplx* Zs = reinterpret_cast<cplx*>(smem);  // [pc][NC], zero beyond n
-  cplx* Qs = Zs + (size_t)pc * NC;           // [pc][NC]: -i h Q[c][k], zero beyond n
-  cplx* Ms = Qs + (size_t)pc * NC;           // [NC][NC]: MU[j][k] at Ms[j * NC + k]
-  double* fs = reinterpret_cast<double*>(Ms + NC * NC);  // [pc]
-  double* et = fs + pc;                      // [pc][Nx] (ET_LDS)
+  cplx* Ms = reinterpret_cast<cplx*>(smem);  // [NC][NC]: M[j][k] at Ms[j * NC + k]
+  cplx* Ns = Ms + NC * NC;                   // [NC][NC]: (i h / 2) (conj(Z~) Q)[j][k]
+  double* et = reinterpret_cast<double*>(Ns + NC * NC);  // [pc][Nx] (ET_LDS)
   const int tid = threadIdx.x;
-  if (gp) {
-    // Ms[j][k] = -sum_c g[c][j] (-i h Q[c][k]); lanes 8e..8e+7 split the sum
-    // over c (eight loads of g and Q in flight per round)
+  {
+    // M[j][k] = MU[j][k] - (i h / 2) (Z~ Q)[j][k], MU = i h (g~ Q)[j][k]
+    // formed here when g is given; N[j][k] = (i h / 2) (conj(Z~) Q)[j][k].
+    // Lanes 8e..8e+7 split the sums over c (eight loads in flight per round).
     const int e8 = tid >> 3, part8 = tid & 7;
     for (int e0 = 0; e0 < NC * NC; e0 += 32) {
       const int t = e0 + e8;
       const int j = t / NC, k = t % NC;
-      cplx sacc = mk(0.0, 0.0);
+      cplx sm = mk(0.0, 0.0), sn = mk(0.0, 0.0);
       if (t < NC * NC && j < n && k < n) {
         for (int c0 = part8; c0 < p; c0 += 64) {
-          cplx gv[8], qv[8];
+          cplx gv[8], zv[8], qv[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const int c = min(c0 + 8 * u, p - 1);
-            gv[u] = gp[(size_t)c * n + j];
+            gv[u] = gp ? gp[(size_t)c * n + j] : mk(0.0, 0.0);
+            zv[u] = Z[(size_t)c * n + j];
             qv[u] = Q[(size_t)k * p + c];
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u)
-            if (c0 + 8 * u < p) cfma(sacc, gv[u], mk(h * qv[u].im, -h * qv[u].re));
+            if (c0 + 8 * u < p) {
+              // (-i h q) times (g - z / 2) and times conj(z)
+              const cplx mq = mk(h * qv[u].im, -h * qv[u].re);
+              cfma(sm, mk(gv[u].re - 0.5 * zv[u].re, gv[u].im - 0.5 * zv[u].im), mq);
+              cfmac(sn, zv[u], mq);
+            }
         }
       }
 #pragma unroll
       for (int o = 4; o >= 1; o >>= 1) {
-        sacc.re += __shfl_xor(sacc.re, o, 64);
-        sacc.im += __shfl_xor(sacc.im, o, 64);
+        sm.re += __shfl_xor(sm.re, o, 64);
+        sm.im += __shfl_xor(sm.im, o, 64);
+        sn.re += __shfl_xor(sn.re, o, 64);
+        sn.im += __shfl_xor(sn.im, o, 64);
       }
-      if (part8 == 0 && t < NC * NC)
-        Ms[t] = (j < n && k < n) ? mk(-sacc.re, -sacc.im) : mk(0.0, 0.0);
-    }
-  } else {
-    for (int t = tid; t < NC * NC; t += 256) {
-      const int j = t / NC, k = t % NC;
-      Ms[t] = (j < n && k < n) ? MU[(size_t)k * n + j] : mk(0.0, 0.0);
+      if (part8 == 0 && t < NC * NC) {
+        const bool in = j < n && k < n;
+        const cplx mu = (in && !gp) ? MU[(size_t)k * n + j] : mk(0.0, 0.0);
+        Ms[t] = in ? mk(mu.re - sm.re, mu.im - sm.im) : mk(0.0, 0.0);
+        Ns[t] = in ? mk(-0.5 * sn.re, -0.5 * sn.im) : mk(0.0, 0.0);
+      }
     }
   }
   const int l = blockIdx.x * 256 + tid;
   const bool valid = l < N;
-  cplx u[NC], acc[NC];
+  cplx u[NC], aq[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     u[k] = (valid && k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
-    acc[k] = mk(0.0, 0.0);
+    aq[k] = mk(0.0, 0.0);
   }
   __syncthreads();
-  // the padding (k >= n) is zero in u, Zs, Qs and Ms: those terms add exact
-  // zeros, so the loops run branch-free over NC.  First U~ MU.
-#pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    const cplx* mj = Ms + j * NC;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) cfma(acc[k], u[j], mj[k]);
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  // then G~ (-i h Q), ILP parameters at a time, accumulated in parameter order
+  // aq = F Q over the parameters in order (-i h applied at the end)
   for (int cb = 0; cb < p; cb += pc) {
     const int np = min(pc, p - cb);
-    if (cb > 0) __syncthreads();  // the previous chunk is done with the tables
-    for (int t = tid; t < np * NC; t += 256) {
-      const int c = t / NC, k = t % NC;
-      Zs[t] = (k < n) ? Z[(size_t)(cb + c) * n + k] : mk(0.0, 0.0);
-      const cplx qv = (k < n) ? Q[(size_t)k * p + cb + c] : mk(0.0, 0.0);
-      Qs[t] = mk(h * qv.im, -h * qv.re);
-    }
-    for (int t = tid; t < np; t += 256) fs[t] = factor[cb + t];
     if (ET_LDS) {
+      if (cb > 0) __syncthreads();  // the previous chunk is done with the table
       const int tot = np * Nx;
       const double* ec = e + (size_t)cb * Nx;
       for (int t0 = 0; t0 < tot; t0 += 8 * 256) {
@@ -727,57 +759,64 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
           if (t < tot) et[t] = qm * v[u8];
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
     for (int c0 = 0; c0 < np; c0 += ILP) {
-      double x0[ILP], x1[ILP], v0[ILP], v1[ILP];
-#pragma unroll
-      for (int q = 0; q < ILP; ++q) {
-        const cplx* zc = Zs + min(c0 + q, np - 1) * NC;
-        x0[q] = 0.0;
-        x1[q] = 0.0;
-        v0[q] = 0.0;
-        v1[q] = 0.0;
-#pragma unroll
-        for (int k = 0; k < NC; k += 2) {
-          const cplx za = zc[k];
-          x0[q] = fma(u[k].re, za.re, x0[q]);
-          x0[q] = fma(-u[k].im, za.im, x0[q]);
-          v0[q] = fma(u[k].re, za.im, v0[q]);
-          v0[q] = fma(u[k].im, za.re, v0[q]);
-          if (k + 1 < NC) {
-            const cplx zb = zc[k + 1];
-            x1[q] = fma(u[k + 1].re, zb.re, x1[q]);
-            x1[q] = fma(-u[k + 1].im, zb.im, x1[q]);
-            v1[q] = fma(u[k + 1].re, zb.im, v1[q]);
-            v1[q] = fma(u[k + 1].im, zb.re, v1[q]);
-          }
-        }
-      }
       double F[ILP];
 #pragma unroll
       for (int q = 0; q < ILP; ++q) {
-        const int c = min(c0 + q, np - 1);
+        // (a pair past the end repeats the last parameter and is not added)
+        const int c = cb + min(c0 + q, np - 1);
+        const cplx* zc = Z + (size_t)c * n;
+        double x0 = 0.0, x1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < NC; k += 2) {
+          // (past n the entry read is finite and u is exactly zero)
+          const cplx za = zc[min(k, n - 1)];
+          x0 = fma(u[k].re, za.re, x0);
+          x0 = fma(-u[k].im, za.im, x0);
+          if (k + 1 < NC) {
+            const cplx zb = zc[min(k + 1, n - 1)];
+            x1 = fma(u[k + 1].re, zb.re, x1);
+            x1 = fma(-u[k + 1].im, zb.im, x1);
+          }
+        }
         int j;
         double th;
-        cell_of(x0[q] + x1[q], fs[c], Nx, j, th);
-        F[q] = ET_LDS ? et[c * Nx + j] : qm * e[(size_t)(cb + c) * Nx + j];
+        cell_of(x0 + x1, factor[c], Nx, j, th);
+        F[q] = ET_LDS ? et[(c - cb) * Nx + j] : qm * e[(size_t)c * Nx + j];
       }
+      // (the Q entries are loaded after the coefficients are dead: the
+      // empty asm keeps them from being hoisted above the lookups)
+      asm volatile("" ::: "memory");
 #pragma unroll
       for (int q = 0; q < ILP; ++q) {
         if (c0 + q < np) {
-          const cplx gv = mk(F[q], v0[q] + v1[q]);
-          const cplx* qc = Qs + (c0 + q) * NC;
+          const int c = cb + c0 + q;
 #pragma unroll
-          for (int k = 0; k < NC; ++k) cfma(acc[k], gv, qc[k]);
+          for (int k = 0; k < NC; ++k) {
+            // (aq past n is never written out)
+            const cplx qv = Q[(size_t)min(k, n - 1) * p + c];
+            aq[k].re = fma(F[q], qv.re, aq[k].re);
+            aq[k].im = fma(F[q], qv.im, aq[k].im);
+          }
         }
       }
     }
   }
-  if (valid) {
+  // out[:, k] = -i h aq[k] + (U~ M + conj(U~) N)[:, k], one column at a time
+  // (the padding k >= n is zero in u, Ms and Ns; the empty asm keeps the
+  // LDS reads of a column from being hoisted above the previous one)
 #pragma unroll
-    for (int k = 0; k < NC; ++k)
-      if (k < n) out[(size_t)k * N + l] = acc[k];
+  for (int k = 0; k < NC; ++k) {
+    cplx a = mk(h * aq[k].im, -h * aq[k].re);
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      cfma(a, u[j], Ms[j * NC + k]);
+      cfmac(a, u[j], Ns[j * NC + k]);
+    }
+    if (valid && k < n) out[(size_t)k * N + l] = a;
+    asm volatile("" ::: "memory");
   }
 }
 
@@ -1316,7 +1355,7 @@ static int fused_nc(int n) { return nc_even(n); }
 void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p,
                            int Nx, const double* factor, const double* e, double qm,
                            const int* active, bool want_colsq, cplx* part, size_t part_cap,
-                           cplx* g, double* colsq, const int* gate) {
+                           cplx* g, double* colsq, const cplx* G12, const int* gate) {
   const int nc = fused_nc(n);
   const int ntile = (p + 63) / 64;
   const int rec = n * p + p;
@@ -1367,7 +1406,7 @@ void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cpl
 #undef GPK
   const int nout = want_colsq ? rec : n * p;
   hipLaunchKernelGGL(reduce_partials2_kernel, dim3((nout + 3) / 4), dim3(256), 0, s, part, nb, rec,
-                     n * p, nout, g, colsq, gate);
+                     n * p, nout, g, colsq, gate, G12, Z, n);
 }
 
 
@@ -1375,22 +1414,17 @@ void launch_gather_xi(hipStream_t s, const cplx* U, int N, int n, const cplx* Z,
                       const double* factor, const double* e, double qm, const cplx* Q,
                       const cplx* MU, double h, cplx* out, const cplx* g) {
   const int nc = fused_nc(n);
-  // LDS of a chunk of pc parameters: coefficients, -i h Q, factors (+ field rows)
-  auto base = [&](int pc) {
-    return (size_t)(2 * pc * nc + nc * nc) * sizeof(cplx) + (size_t)pc * sizeof(double);
-  };
+  // LDS: the n x n matrices M and N, and the field rows of all parameters
+  // when they fit, else of chunks of 64 when those fit, else none
+  const size_t base = (size_t)2 * nc * nc * sizeof(cplx);
   const size_t budget = 76 * 1024;
   int pc = p;
-  bool et_lds = base(p) + (size_t)p * Nx * sizeof(double) <= budget;
-  if (!et_lds && base(p) > budget) {
-    // more parameters than the tables hold: chunks of pc, field rows in LDS
-    // when a chunk of at least 64 parameters still fits with them
+  bool et_lds = base + (size_t)p * Nx * sizeof(double) <= budget;
+  if (!et_lds && p > 64 && base + (size_t)64 * Nx * sizeof(double) <= budget) {
     pc = 64;
-    et_lds = base(pc) + (size_t)pc * Nx * sizeof(double) <= budget;
-    if (!et_lds)
-      while (2 * pc <= p && base(2 * pc) <= budget) pc *= 2;
+    et_lds = true;
   }
-  const size_t sh = base(pc) + (et_lds ? (size_t)pc * Nx * sizeof(double) : 0);
+  const size_t sh = base + (et_lds ? (size_t)pc * Nx * sizeof(double) : 0);
   dim3 grid((N + 255) / 256);
 #define GXK(NCV, ETV)                                                                          \
   ALLOW_BIG_LDS((gather_xi_kernel<NCV, ETV>));                                               \
