@@ -38,7 +38,7 @@ PEAK_FP64 = 78.6e12      # flop/s, MI355X FP64 vector (= FP64 matrix) peak
 # timing families that hold one kernel each on the caller's stream
 SINGLE_KERNEL = {
     "deposit": "deposit_rom_kernel (reconstruct + cell + LDS histogram)",
-    "gather": "gather_project_kernel (reconstruct + field gather + g = U^* G)",
+    "gather": "gather_project_mfma_kernel (reconstruct + field gather + g = U^* F on FP64 MFMA)",
     "gather_xi": "gather_xi_kernel (reconstruct + field gather + xi = -i h G Q + U M)",
 }
 

@@ -451,138 +451,208 @@ __global__ void __launch_bounds__(64) deim_gather_kernel(
 
 
 // ---------------------------------------------------------------------------
-// Fused gather + projection (eq. grads): the field part U~^* F of
-// g = U~^* G~ (n x p), G~ = F + i v, with F = (q/m) e_c at the particle's
-// cell evaluated on the fly and never stored.  The velocity part
-// i U~^* v, v = Im(U~ Z~), is linear in Z~ and is added by the reduction
-// from the small Gram matrices of U~ (it needs no pass over the particles).
-// Lanes are the 64 parameters of a tile
-// (blockIdx.y); each wavefront takes one particle row at a time, so the row
-// of U~ is wavefront-uniform (scalar loads, no LDS traffic) and the
-// projection needs no cross-lane reduction while rows stream.  The field
-// rows of the tile sit in LDS.  The eight wavefronts are summed in a fixed
-// order; block b writes part[b * rec + c * n + k] and, with want_colsq,
-// |F[:, c]|^2 at part[b * rec + n * p + c].re.  Positions use the operation
-// order of the deposit, so both see the same cells.
+// Fused gather + projection on the FP64 matrix cores: the field part U~^* F
+// of g (the velocity part is added by the reduction, as for
+// gather_project_kernel), per wavefront 16 particle rows at a time against
+// the 64 parameters of the tile.  Real form with K = 2 NC: a = [Re U~ |
+// -Im U~] (row-major per particle), b = [Re Z~; Im Z~], so that the positions
+// X = a b (16 rows x 16 parameters per accumulator, four accumulators).  In
+// the accumulator layout lane l holds X[4 v + l / 16][l % 16], which is the
+// layout of the B operand of g = a^T F for the 4-row step v: the cell, the
+// field lookup and the masks run on the positions in registers and feed
+// the second product directly.  Results: block b writes part[b * rec + c *
+// n + k] and, with want_colsq, |F[:, c]|^2 at part[b * rec + n * p + c].re;
+// the four wavefronts are summed in a fixed order.
 // ---------------------------------------------------------------------------
-template <int NC, bool ET_LDS>
-__global__ void __launch_bounds__(512) gather_project_kernel(
+typedef double gm_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ gm_d4 gm_step(double a, double b, gm_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int NC, int CBN, bool ET_LDS>
+__global__ void __launch_bounds__(256) gather_project_mfma_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx, int rpb,
     const double* __restrict__ factor, const double* __restrict__ e, double qm,
     const int* __restrict__ active, int rec, int want_colsq, cplx* __restrict__ part,
     const int* __restrict__ gate) {
   if (gate && gate[0] == 0) return;
+  constexpr int KS = (2 * NC + 3) / 4;    // 4-deep steps of the position product
+  constexpr int MT = (2 * NC + 15) / 16;  // 16-row tiles of the projection
+  constexpr int PT = 16 * CBN;            // parameters of the tile
   extern __shared__ double smem[];
-  double* et = smem;  // [64][Nx] (ET_LDS); after the rows, the wavefront sums
+  double* et = smem;  // [PT][Nx] (ET_LDS); after the rows, the wavefront sums
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int c0 = blockIdx.y * 64;
-  const int c = c0 + lane;
-  const int ntc = min(64, p - c0);
-  const bool on = (lane < ntc) && (!active || active[c]);
+  const int li = lane & 15, lk = lane >> 4;
+  // parameter tiles vary fastest over the grid: blocks of the same rows run
+  // together and share the rows of U~ in L2
+  const int c0 = blockIdx.x * PT;
+  const int ntc = min(PT, p - c0);
+  const int rb = blockIdx.y;
   if (ET_LDS) {
-    // the tile's field rows are contiguous: a linear copy, four loads in flight
     const double* es = e + (size_t)c0 * Nx;
     const int tot = ntc * Nx;
-    for (int t0 = 0; t0 < tot; t0 += 4 * 512) {
+    for (int t0 = 0; t0 < tot; t0 += 4 * 256) {
       double v[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int t = t0 + u * 512 + tid;
+        const int t = t0 + u * 256 + tid;
         v[u] = (t < tot) ? es[t] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int t = t0 + u * 512 + tid;
+        const int t = t0 + u * 256 + tid;
         if (t < tot) et[t] = qm * v[u];
       }
     }
   }
-  cplx z[NC], acc[NC];
+  // B operands of the positions (b[q][parameter 16 cb + li] for q = 4 ks +
+  // lk), the factor and the mask of this lane's parameter in each block
+  double bz[CBN][KS], fac[CBN];
+  bool on[CBN];
 #pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    z[k] = (on && k < n) ? Z[(size_t)c * n + k] : mk(0.0, 0.0);
-    acc[k] = mk(0.0, 0.0);
+  for (int cb = 0; cb < CBN; ++cb) {
+    const int cl = 16 * cb + li;
+    const int c = c0 + min(cl, ntc - 1);
+    on[cb] = cl < ntc && (!active || active[c]);
+    fac[cb] = factor[c];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int q = 4 * ks + lk;
+      double v = 0.0;
+      if (q < NC) {
+        if (q < n) v = Z[(size_t)c * n + q].re;
+      } else if (q - NC < n && q - NC < NC) {
+        v = Z[(size_t)c * n + (q - NC)].im;
+      }
+      bz[cb][ks] = on[cb] ? v : 0.0;
+    }
   }
-  const double fac = on ? factor[c] : 1.0;
-  double csq = 0.0;
+  gm_d4 acc[MT][CBN];
+  double csq[CBN];
+#pragma unroll
+  for (int cb = 0; cb < CBN; ++cb) {
+    csq[cb] = 0.0;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt][cb] = gm_d4{0.0, 0.0, 0.0, 0.0};
+  }
   __syncthreads();
-  const int r0 = blockIdx.x * rpb;
+  const int r0 = rb * rpb;
   const int r1 = min(N, r0 + rpb);
-  if (on) {
-    for (int l = r0 + w; l < r1; l += 8) {
-      // the padding (k >= n) is zero in u and z: those terms add exact
-      // zeros, so the loops run branch-free over NC
-      cplx u[NC];
+  // the operands of U~ for a tile of 16 rows: a[row t0 + li][q = 4 ks + lk]
+  // for the positions and a^T[o = 16 mt + li][row t0 + 4 s + lk] for the
+  // projection; those of the next tile are loaded while this one computes
+  // (the rows stream from memory: each tile would otherwise wait for them)
+  // Each operand entry is sgn * (component of U~[col][row]): the column, the
+  // component (re or im) and the sign (+1, -1 for -Im, 0 past n) of a lane
+  // are fixed, so they are set up once (a zero entry reads column 0).
+  const double* pa_[KS];
+  double sa_[KS];
 #pragma unroll
-      for (int k = 0; k < NC; ++k) u[k] = (k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
-      double x0 = 0.0, x1 = 0.0;
-#pragma unroll
-      for (int k = 0; k < NC; k += 2) {
-        x0 = fma(u[k].re, z[k].re, x0);
-        x0 = fma(-u[k].im, z[k].im, x0);
-        if (k + 1 < NC) {
-          x1 = fma(u[k + 1].re, z[k + 1].re, x1);
-          x1 = fma(-u[k + 1].im, z[k + 1].im, x1);
-        }
-      }
-      int j;
-      double th;
-      cell_of(x0 + x1, fac, Nx, j, th);
-      const double F = ET_LDS ? et[lane * Nx + j] : qm * e[(size_t)c * Nx + j];
-      // conj(u) F
-#pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        acc[k].re = fma(u[k].re, F, acc[k].re);
-        acc[k].im = fma(-u[k].im, F, acc[k].im);
-      }
-      csq = fma(F, F, csq);
-    }
+  for (int ks = 0; ks < KS; ++ks) {
+    const int q = 4 * ks + lk;
+    const int col = (q < NC) ? q : q - NC;
+    const bool ok = q < 2 * NC && col < n;
+    pa_[ks] = reinterpret_cast<const double*>(U + (size_t)(ok ? col : 0) * N) + (q < NC ? 0 : 1);
+    sa_[ks] = ok ? (q < NC ? 1.0 : -1.0) : 0.0;
   }
-  // the eight wavefronts summed in wave order through LDS (the field rows
-  // are free now): all partials stored at once when they fit in the space
-  // of the field table (NC <= 8), else accumulated one wavefront at a time
+  const double* pt_[MT];
+  double st_[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int o = 16 * mt + li;
+    const int col = (o < NC) ? o : o - NC;
+    const bool ok = o < 2 * NC && col < n;
+    pt_[mt] = reinterpret_cast<const double*>(U + (size_t)(ok ? col : 0) * N) + (o < NC ? 0 : 1);
+    st_[mt] = ok ? (o < NC ? 1.0 : -1.0) : 0.0;
+  }
+  double a[KS], at[MT][4], an[KS], atn[MT][4];
+  auto load_tile = [&](int tt, double* ra, double (*rat)[4]) {
+    const int row = min(tt + li, r1 - 1);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) ra[ks] = sa_[ks] * pa_[ks][2 * (size_t)row];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int rw = min(tt + 4 * s4 + lk, r1 - 1);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) rat[mt][s4] = st_[mt] * pt_[mt][2 * (size_t)rw];
+    }
+  };
+  load_tile(r0 + 16 * w, a, at);
+  for (int t0 = r0 + 16 * w; t0 < r1; t0 += 64) {
+    load_tile(t0 + 64, an, atn);
+    gm_d4 X[CBN];
+#pragma unroll
+    for (int cb = 0; cb < CBN; ++cb) {
+      X[cb] = gm_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) X[cb] = gm_step(a[ks], bz[cb][ks], X[cb]);
+    }
+    // F at the positions: lane holds row t0 + 4 v + lk, parameter 16 cb + li
+    double F[CBN][4];
+#pragma unroll
+    for (int cb = 0; cb < CBN; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int j;
+        double th;
+        cell_of(X[cb][v], fac[cb], Nx, j, th);
+        const int cl = min(16 * cb + li, ntc - 1);
+        const double f = ET_LDS ? et[cl * Nx + j] : qm * e[(size_t)(c0 + cl) * Nx + j];
+        F[cb][v] = (on[cb] && t0 + 4 * v + lk < r1) ? f : 0.0;
+        csq[cb] = fma(F[cb][v], F[cb][v], csq[cb]);
+      }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int cb = 0; cb < CBN; ++cb)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) acc[mt][cb] = gm_step(at[mt][s4], F[cb][s4], acc[mt][cb]);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) a[ks] = an[ks];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) at[mt][s4] = atn[mt][s4];
+  }
+  // the column sums of |F|^2 over the four row groups of a lane's parameter
+#pragma unroll
+  for (int cb = 0; cb < CBN; ++cb) {
+    csq[cb] += __shfl_xor(csq[cb], 16, 64);
+    csq[cb] += __shfl_xor(csq[cb], 32, 64);
+  }
+  __syncthreads();  // (the field rows are no longer needed)
+  // wavefront sums: red[w][o][parameter], o over the 16 MT real outputs
+  double* red = smem;                         // [4][16 MT][PT]
+  double* rcs = smem + 4 * 16 * MT * PT;       // [4][PT]
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int cb = 0; cb < CBN; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        red[((size_t)w * 16 * MT + 16 * mt + 4 * v + lk) * PT + 16 * cb + li] = acc[mt][cb][v];
+  if (lk == 0)
+#pragma unroll
+    for (int cb = 0; cb < CBN; ++cb) rcs[w * PT + 16 * cb + li] = csq[cb];
   __syncthreads();
-  cplx* pb = part + (size_t)blockIdx.x * rec;
-  if (NC <= 8) {
-    cplx* red = reinterpret_cast<cplx*>(smem);                  // [8][NC][64]
-    double* rcs = smem + 2 * 8 * NC * 64;                        // [8][64]
-#pragma unroll
-    for (int k = 0; k < NC; ++k) red[(w * NC + k) * 64 + lane] = acc[k];
-    rcs[w * 64 + lane] = csq;
-    __syncthreads();
-    for (int t = tid; t < ntc * n; t += 512) {
-      const int q = t / n, k = t % n;
-      cplx sw = red[k * 64 + q];
-#pragma unroll
-      for (int ww = 1; ww < 8; ++ww) sw = cadd(sw, red[(ww * NC + k) * 64 + q]);
-      pb[(size_t)(c0 + q) * n + k] = sw;
-    }
-    if (want_colsq)
-      for (int t = tid; t < ntc; t += 512) {
-        double sw = rcs[t];
-#pragma unroll
-        for (int ww = 1; ww < 8; ++ww) sw += rcs[ww * 64 + t];
-        pb[(size_t)n * p + c0 + t] = mk(sw, 0.0);
-      }
-    return;
-  }
-  cplx* red = reinterpret_cast<cplx*>(smem);                  // [NC][64]
-  double* rcs = smem + 2 * NC * 64;                            // [64]
-  for (int ww = 0; ww < 8; ++ww) {
-    if (w == ww) {
-#pragma unroll
-      for (int k = 0; k < NC; ++k) red[k * 64 + lane] = (ww == 0) ? acc[k] : cadd(red[k * 64 + lane], acc[k]);
-      rcs[lane] = (ww == 0) ? csq : rcs[lane] + csq;
-    }
-    __syncthreads();
-  }
-  for (int t = tid; t < ntc * n; t += 512) {
+  cplx* pb = part + (size_t)rb * rec;
+  for (int t = tid; t < ntc * n; t += 256) {
     const int q = t / n, k = t % n;
-    pb[(size_t)(c0 + q) * n + k] = red[k * 64 + q];
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) {
+      re += red[((size_t)ww * 16 * MT + k) * PT + q];
+      im += red[((size_t)ww * 16 * MT + NC + k) * PT + q];
+    }
+    pb[(size_t)(c0 + q) * n + k] = mk(re, im);
   }
   if (want_colsq)
-    for (int t = tid; t < ntc; t += 512) pb[(size_t)n * p + c0 + t] = mk(rcs[t], 0.0);
+    for (int t = tid; t < ntc; t += 256) {
+      const double sw = ((rcs[t] + rcs[PT + t]) + rcs[2 * PT + t]) + rcs[3 * PT + t];
+      pb[(size_t)n * p + c0 + t] = mk(sw, 0.0);
+    }
 }
 
 // C1[o] = sum_b part[b][o] for o < n1, C2[o - n1] = the real part of that sum
@@ -1357,7 +1427,6 @@ void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cpl
                            const int* active, bool want_colsq, cplx* part, size_t part_cap,
                            cplx* g, double* colsq, const cplx* G12, const int* gate) {
   const int nc = fused_nc(n);
-  const int ntile = (p + 63) / 64;
   const int rec = n * p + p;
   // two blocks per CU (512 on 256 CUs, all resident at once: the loop is
   // bound by FP64 VALU work, so every CU gets the same share), at least 64
@@ -1369,41 +1438,48 @@ void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cpl
   if (nb < 1) nb = 1;
   const int rpb = (N + nb - 1) / nb;
   nb = (N + rpb - 1) / rpb;
-  const int tw = (p < 64) ? p : 64;
-  const size_t et_bytes = (size_t)tw * Nx * sizeof(double);
-  const bool et_lds = et_bytes <= 72 * 1024;
-  // the wavefront sums reuse the table's space: 8 x NC x 64 complex + 8 x 64
-  // doubles for NC <= 8, else NC x 64 complex + 64 doubles
-  const size_t red_bytes = (nc <= 8) ? (size_t)8 * nc * 64 * sizeof(cplx) + 8 * 64 * sizeof(double)
-                                     : (size_t)nc * 64 * sizeof(cplx) + 64 * sizeof(double);
-  const size_t sh = (et_lds && et_bytes > red_bytes) ? et_bytes : red_bytes;
-  dim3 grid(nb, ntile);
-#define GPK(NCV, ETV)                                                                          \
-  ALLOW_BIG_LDS((gather_project_kernel<NCV, ETV>));                                          \
-  hipLaunchKernelGGL((gather_project_kernel<NCV, ETV>), grid, dim3(512), sh, s, U, N, n, Z, p, \
-                     Nx, rpb, factor, e, qm, active, rec, want_colsq ? 1 : 0, part, gate)
-  if (et_lds) {
-    switch (nc) {
-      case 4: GPK(4, true); break;
-      case 5: GPK(5, true); break;
-      case 6: GPK(6, true); break;
-      case 7: GPK(7, true); break;
-      case 8: GPK(8, true); break;
-      case 12: GPK(12, true); break;
-      default: GPK(16, true); break;
-    }
-  } else {
-    switch (nc) {
-      case 4: GPK(4, false); break;
-      case 5: GPK(5, false); break;
-      case 6: GPK(6, false); break;
-      case 7: GPK(7, false); break;
-      case 8: GPK(8, false); break;
-      case 12: GPK(12, false); break;
-      default: GPK(16, false); break;
-    }
+  // parameter tiles of 16 CBN with their field rows in LDS (CBN as large as
+  // the 72 KB budget allows, at most 4); without room for even 16 rows, tiles
+  // of 64 with the table read from global memory
+  const size_t budget = 72 * 1024;
+  int cbn = 4;
+  while (cbn > 1 && (size_t)16 * cbn * Nx * sizeof(double) > budget) cbn /= 2;
+  const bool et_lds = (size_t)16 * cbn * Nx * sizeof(double) <= budget;
+  if (!et_lds) cbn = 4;
+  const int pt = 16 * cbn;
+  const int ntile = (p + pt - 1) / pt;
+  const size_t et_bytes = et_lds ? (size_t)pt * Nx * sizeof(double) : 0;
+  // the wavefront sums reuse the table's space: 4 x 16 MT x PT + 4 x PT doubles
+  const int mt = (2 * nc + 15) / 16;
+  const size_t red_bytes = (size_t)4 * 16 * mt * pt * sizeof(double) + 4 * pt * sizeof(double);
+  const size_t sh = std::max(et_bytes, red_bytes);
+  dim3 grid(ntile, nb);
+#define GPM(NCV, CBV, ETV)                                                                      \
+  ALLOW_BIG_LDS((gather_project_mfma_kernel<NCV, CBV, ETV>));                                 \
+  hipLaunchKernelGGL((gather_project_mfma_kernel<NCV, CBV, ETV>), grid, dim3(256), sh, s, U, N, \
+                     n, Z, p, Nx, rpb, factor, e, qm, active, rec, want_colsq ? 1 : 0, part,    \
+                     gate)
+#define GPM_NC(CBV, ETV)                \
+  switch (nc) {                         \
+    case 4: GPM(4, CBV, ETV); break;    \
+    case 5: GPM(5, CBV, ETV); break;    \
+    case 6: GPM(6, CBV, ETV); break;    \
+    case 7: GPM(7, CBV, ETV); break;    \
+    case 8: GPM(8, CBV, ETV); break;    \
+    case 12: GPM(12, CBV, ETV); break;  \
+    default: GPM(16, CBV, ETV); break;  \
   }
-#undef GPK
+  if (!et_lds) {
+    GPM_NC(4, false)
+  } else if (cbn == 4) {
+    GPM_NC(4, true)
+  } else if (cbn == 2) {
+    GPM_NC(2, true)
+  } else {
+    GPM_NC(1, true)
+  }
+#undef GPM_NC
+#undef GPM
   const int nout = want_colsq ? rec : n * p;
   hipLaunchKernelGGL(reduce_partials2_kernel, dim3((nout + 3) / 4), dim3(256), 0, s, part, nb, rec,
                      n * p, nout, g, colsq, gate, G12, Z, n);
