@@ -692,7 +692,8 @@ int nkb_for(int N) {
 void carve_rom(Arena& ar, symrom_rom& r) {
   const int N = r.N, p = r.p, Nx = r.Nx, nm = r.nmax;
   // one parameter tile of up to 64 KB of LDS per table, ~one block per CU
-  r.gdep = pic_geom(N, p, Nx, 16 * 1024, 256);
+  // (row blocks for deposit tiles of deposit_tile_params(Nx) parameters)
+  r.gdep = pic_geom(N, p, Nx, (size_t)deposit_tile_params(Nx) * Nx * sizeof(double), 256);
   r.ggat = pic_geom(N, p, Nx, 64 * 1024, 256);
   r.nkb = nkb_for(N);
   r.b = carve_pic(ar, N, p, Nx, r.gdep.nrb >= r.ggat.nrb ? r.gdep : r.ggat);
@@ -780,7 +781,7 @@ void carve_rom(Arena& ar, symrom_rom& r) {
   const bool dm = r.cfg.projection == SYMROM_DMD_DEIM;
   const int ps = r.psub, T = r.cfg.deim_window, Pd = ps * T;
   r.sub_id = ar.take<int>(ps);
-  r.gdep_s = pic_geom(N, ps, Nx, 16 * 1024, 256);
+  r.gdep_s = pic_geom(N, ps, Nx, (size_t)deposit_tile_params(Nx) * Nx * sizeof(double), 256);
   r.ggat_s = pic_geom(N, ps, Nx, 64 * 1024, 256);
   r.bs = carve_pic(ar, dm ? N : 1, dm ? ps : 1, Nx,
                    r.gdep_s.nrb >= r.ggat_s.nrb ? r.gdep_s : r.ggat_s);

@@ -60,6 +60,75 @@ __device__ inline void cell_of(double x, double factor, int Nx, int& j, double& 
   j = (int)r;
 }
 
+// ---------------------------------------------------------------------------
+// Particle positions on the FP64 matrix cores (v_mfma_f64_16x16x4f64: a
+// wavefront multiplies a 16 x 4 tile A by a 4 x 16 tile B into a 16 x 16
+// accumulator; A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, and lane
+// l holds D[4 v + l / 16][l % 16] in item v).  In real form with K = 2 NC,
+// X = a b with a = [Re U~ | -Im U~] (one row per particle) and b = [Re Z~;
+// Im Z~], for 16 particle rows against 16 parameters: lane li + 16 lk holds
+// a[row + li][4 ks + lk] and b[4 ks + lk][parameter li] for step ks, and ends
+// with the positions of rows 4 v + lk of its parameter li.  Every kernel
+// that deposits or gathers at these positions forms them with this code,
+// so that a particle lands in the same cell in each.
+// ---------------------------------------------------------------------------
+typedef double mf4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ mf4 mfma_f64_step(double a, double b, mf4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Entries of a: the column, component (re or im) and sign (+1, -1 for
+// -Im, 0 past n or past 2 NC) of entry q are fixed per lane, so they are set
+// up once; a zero entry reads column 0.
+template <int KS>
+struct PosRows {
+  const double* ptr[KS];
+  double sgn[KS];
+  __device__ __forceinline__ void setup(const cplx* __restrict__ U, int N, int n, int NC,
+                                        int lk) {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int q = 4 * ks + lk;
+      const int col = (q < NC) ? q : q - NC;
+      const bool ok = q < 2 * NC && col < n;
+      ptr[ks] = reinterpret_cast<const double*>(U + (size_t)(ok ? col : 0) * N) + (q < NC ? 0 : 1);
+      sgn[ks] = ok ? (q < NC ? 1.0 : -1.0) : 0.0;
+    }
+  }
+  // a[ks] for particle row `row` (this lane's row of the tile)
+  __device__ __forceinline__ void load(int row, double* a) const {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) a[ks] = sgn[ks] * ptr[ks][2 * (size_t)row];
+  }
+};
+
+// Entries of b for parameter c (zero past n, or everywhere when !on)
+template <int KS>
+__device__ __forceinline__ void pos_coefs(const cplx* __restrict__ Z, int n, int NC, int c,
+                                          bool on, int lk, double* bz) {
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int q = 4 * ks + lk;
+    double v = 0.0;
+    if (q < NC) {
+      if (q < n) v = Z[(size_t)c * n + q].re;
+    } else if (q - NC < n && q - NC < NC) {
+      v = Z[(size_t)c * n + (q - NC)].im;
+    }
+    bz[ks] = on ? v : 0.0;
+  }
+}
+
+// X for the tile: the KS steps in order from zero
+template <int KS>
+__device__ __forceinline__ mf4 pos_tile(const double* a, const double* bz) {
+  mf4 X = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) X = mfma_f64_step(a[ks], bz[ks], X);
+  return X;
+}
+
 // LDS FP64 atomic add (hardware ds_add_f64 on gfx950)
 __device__ inline void lds_add(double* addr, double v) {
   __hip_atomic_fetch_add(addr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);

@@ -63,6 +63,8 @@ void launch_deposit_x(hipStream_t s, const double* X, int N, int p, int Nx, cons
 // fixed point has converged: speculative iterations exit at once)
 // fold (optional): the status words, given the end-of-step bookkeeping by
 // one thread at the start (see fold_status_kernel)
+// parameters per block of the reduced deposit on the matrix cores (n <= 16)
+int deposit_tile_params(int Nx);
 void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                         const PicGeom& g, const double* factor, const int* active, double* part,
                         const int* gate = nullptr,

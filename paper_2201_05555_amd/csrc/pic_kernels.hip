@@ -172,6 +172,101 @@ __global__ void __launch_bounds__(deposit_rom_threads<NC>()) deposit_rom_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// The same deposit with the positions formed on the FP64 matrix cores
+// (PosRows / pos_tile, as the gather-projection forms them, so that both see
+// the same cells): a tile of PT <= 16 parameters per block (one B operand;
+// lanes past PT idle), each of the 16 wavefronts taking 16-row tiles in
+// turn; lane li + 16 lk ends with the positions of rows 4 v + lk for
+// parameter li and adds them to the block's count and theta tables.  The
+// operands of the next row tile are loaded while the current one is
+// deposited.
+// ---------------------------------------------------------------------------
+int deposit_tile_params(int Nx) {
+  // count and theta tables of PT parameters within 128 KB of LDS
+  int pt = (int)((size_t)128 * 1024 / ((size_t)Nx * (sizeof(double) + sizeof(unsigned))));
+  return pt < 1 ? 1 : (pt > 16 ? 16 : pt);
+}
+
+template <int NC>
+__global__ void __launch_bounds__(1024) deposit_rom_mfma_kernel(
+    const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx, int PT,
+    int rpb, const double* __restrict__ factor, const int* __restrict__ active,
+    double* __restrict__ part, const int* __restrict__ gate, int* __restrict__ fold, int det) {
+  if (gate && gate[0] == 0) return;
+  if (fold && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    // end-of-step bookkeeping of the status words, as in deposit_rom_kernel
+    const int tail = fold[2] | fold[3];
+    fold[2] = tail;
+    fold[3] = 0;
+    fold[12] = fold[0] | tail;
+  }
+  constexpr int KS = (2 * NC + 3) / 4;
+  extern __shared__ double hist[];                                    // theta sums, PT * Nx
+  unsigned* cnt = reinterpret_cast<unsigned*>(hist + (size_t)PT * Nx);  // counts, PT * Nx
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nw = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int rb = blockIdx.x;
+  const int p0 = blockIdx.y * PT;
+  const int np = min(PT, p - p0);
+  for (int t = tid; t < np * Nx; t += blockDim.x) {
+    hist[t] = 0.0;
+    cnt[t] = 0u;
+  }
+  const int c = p0 + min(li, np - 1);
+  const bool on = li < np && (!active || active[c]);  // (np <= PT <= 16)
+  const double fac = factor[c];
+  double bz[KS];
+  pos_coefs<KS>(Z, n, NC, c, on, lk, bz);
+  PosRows<KS> pr;
+  pr.setup(U, N, n, NC, lk);
+  __syncthreads();
+  const int r0 = rb * rpb;
+  const int r1 = min(N, r0 + rpb);
+  double a[KS], an[KS];
+  pr.load(min(r0 + 16 * w + li, r1 - 1), a);
+  for (int t0 = r0 + 16 * w; t0 < r1; t0 += 16 * nw) {
+    pr.load(min(t0 + 16 * nw + li, r1 - 1), an);
+    const mf4 X = pos_tile<KS>(a, bz);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int j;
+      double th;
+      cell_of(X[v], fac, Nx, j, th);
+      if (on && t0 + 4 * v + lk < r1) {
+        __hip_atomic_fetch_add(cnt + li * Nx + j, 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (det)
+          __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(hist) + li * Nx + j,
+                                 __double2ull_rn(th * 0x1p40), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+          lds_add(hist + li * Nx + j, th);
+      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) a[ks] = an[ks];
+  }
+  __syncthreads();
+  if (det) {
+    // each integer sum becomes a double in place (one rounding each)
+    const unsigned long long* ih = reinterpret_cast<const unsigned long long*>(hist);
+    for (int t = tid; t < np * Nx; t += blockDim.x) {
+      const double v = __ull2double_rn(ih[t]) * 0x1p-40;
+      hist[t] = v;
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < np * Nx; t += blockDim.x) {
+    const int i = t / Nx, j = t - i * Nx;
+    if (active && !active[p0 + i]) continue;
+    const int jm = (j == 0) ? Nx - 1 : j - 1;
+    part[((size_t)rb * p + p0) * Nx + t] = ((double)cnt[t] - hist[t]) + hist[i * Nx + jm];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Poisson solve (eq. PoissonSystem) for one parameter per block.
 //
 // rho_j = q w_i * (sum of the row-block partials) + h_i (P1 load vector of
@@ -670,8 +765,30 @@ void launch_deposit_x(hipStream_t s, const double* X, int N, int p, int Nx, cons
 void launch_deposit_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
                         const PicGeom& g, const double* factor, const int* active, double* part,
                         const int* gate, int* fold, int det) {
-  dim3 grid(g.nrb, (p + g.pt - 1) / g.pt);
   int nc = (n <= 16) ? nc_even(n) : 32;
+  if (n <= 16) {
+    // positions on the matrix cores, tiles of deposit_tile_params(Nx)
+    // parameters (the row blocks of g)
+    const int pte = deposit_tile_params(Nx);
+    dim3 gridm(g.nrb, (p + pte - 1) / pte);
+    const size_t shm = (size_t)pte * Nx * (sizeof(double) + sizeof(unsigned));
+#define DEPM(NCV)                                                                                 \
+  ALLOW_BIG_LDS(deposit_rom_mfma_kernel<NCV>);                                                   \
+  hipLaunchKernelGGL(deposit_rom_mfma_kernel<NCV>, gridm, dim3(1024), shm, s, U, N, n, Z, p, Nx,  \
+                     pte, g.rpb, factor, active, part, gate, fold, det)
+    switch (nc) {
+      case 4: DEPM(4); break;
+      case 5: DEPM(5); break;
+      case 6: DEPM(6); break;
+      case 7: DEPM(7); break;
+      case 8: DEPM(8); break;
+      case 12: DEPM(12); break;
+      default: DEPM(16); break;
+    }
+#undef DEPM
+    return;
+  }
+  dim3 grid(g.nrb, (p + g.pt - 1) / g.pt);
   size_t sh = (size_t)g.pt * Nx * (sizeof(double) + sizeof(unsigned));
 #define DEP(NCV)                                                                              \
   ALLOW_BIG_LDS(deposit_rom_kernel<NCV>);                                                    \

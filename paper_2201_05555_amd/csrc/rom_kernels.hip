@@ -464,12 +464,6 @@ __global__ void __launch_bounds__(64) deim_gather_kernel(
 // n + k] and, with want_colsq, |F[:, c]|^2 at part[b * rec + n * p + c].re;
 // the four wavefronts are summed in a fixed order.
 // ---------------------------------------------------------------------------
-typedef double gm_d4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ gm_d4 gm_step(double a, double b, gm_d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
 template <int NC, int CBN, bool ET_LDS>
 __global__ void __launch_bounds__(256) gather_project_mfma_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx, int rpb,
@@ -517,25 +511,15 @@ __global__ void __launch_bounds__(256) gather_project_mfma_kernel(
     const int c = c0 + min(cl, ntc - 1);
     on[cb] = cl < ntc && (!active || active[c]);
     fac[cb] = factor[c];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int q = 4 * ks + lk;
-      double v = 0.0;
-      if (q < NC) {
-        if (q < n) v = Z[(size_t)c * n + q].re;
-      } else if (q - NC < n && q - NC < NC) {
-        v = Z[(size_t)c * n + (q - NC)].im;
-      }
-      bz[cb][ks] = on[cb] ? v : 0.0;
-    }
+    pos_coefs<KS>(Z, n, NC, c, on[cb], lk, bz[cb]);
   }
-  gm_d4 acc[MT][CBN];
+  mf4 acc[MT][CBN];
   double csq[CBN];
 #pragma unroll
   for (int cb = 0; cb < CBN; ++cb) {
     csq[cb] = 0.0;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) acc[mt][cb] = gm_d4{0.0, 0.0, 0.0, 0.0};
+    for (int mt = 0; mt < MT; ++mt) acc[mt][cb] = mf4{0.0, 0.0, 0.0, 0.0};
   }
   __syncthreads();
   const int r0 = rb * rpb;
@@ -544,19 +528,10 @@ __global__ void __launch_bounds__(256) gather_project_mfma_kernel(
   // for the positions and a^T[o = 16 mt + li][row t0 + 4 s + lk] for the
   // projection; those of the next tile are loaded while this one computes
   // (the rows stream from memory: each tile would otherwise wait for them)
-  // Each operand entry is sgn * (component of U~[col][row]): the column, the
-  // component (re or im) and the sign (+1, -1 for -Im, 0 past n) of a lane
-  // are fixed, so they are set up once (a zero entry reads column 0).
-  const double* pa_[KS];
-  double sa_[KS];
-#pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    const int q = 4 * ks + lk;
-    const int col = (q < NC) ? q : q - NC;
-    const bool ok = q < 2 * NC && col < n;
-    pa_[ks] = reinterpret_cast<const double*>(U + (size_t)(ok ? col : 0) * N) + (q < NC ? 0 : 1);
-    sa_[ks] = ok ? (q < NC ? 1.0 : -1.0) : 0.0;
-  }
+  // (each operand entry is sgn * a component of U~[col][row], with the
+  // column, component and sign fixed per lane: set up once)
+  PosRows<KS> pr;
+  pr.setup(U, N, n, NC, lk);
   const double* pt_[MT];
   double st_[MT];
 #pragma unroll
@@ -569,9 +544,7 @@ __global__ void __launch_bounds__(256) gather_project_mfma_kernel(
   }
   double a[KS], at[MT][4], an[KS], atn[MT][4];
   auto load_tile = [&](int tt, double* ra, double (*rat)[4]) {
-    const int row = min(tt + li, r1 - 1);
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) ra[ks] = sa_[ks] * pa_[ks][2 * (size_t)row];
+    pr.load(min(tt + li, r1 - 1), ra);
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
       const int rw = min(tt + 4 * s4 + lk, r1 - 1);
@@ -582,13 +555,9 @@ __global__ void __launch_bounds__(256) gather_project_mfma_kernel(
   load_tile(r0 + 16 * w, a, at);
   for (int t0 = r0 + 16 * w; t0 < r1; t0 += 64) {
     load_tile(t0 + 64, an, atn);
-    gm_d4 X[CBN];
+    mf4 X[CBN];
 #pragma unroll
-    for (int cb = 0; cb < CBN; ++cb) {
-      X[cb] = gm_d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) X[cb] = gm_step(a[ks], bz[cb][ks], X[cb]);
-    }
+    for (int cb = 0; cb < CBN; ++cb) X[cb] = pos_tile<KS>(a, bz[cb]);
     // F at the positions: lane holds row t0 + 4 v + lk, parameter 16 cb + li
     double F[CBN][4];
 #pragma unroll
@@ -608,7 +577,8 @@ __global__ void __launch_bounds__(256) gather_project_mfma_kernel(
 #pragma unroll
       for (int cb = 0; cb < CBN; ++cb)
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) acc[mt][cb] = gm_step(at[mt][s4], F[cb][s4], acc[mt][cb]);
+        for (int s4 = 0; s4 < 4; ++s4)
+          acc[mt][cb] = mfma_f64_step(at[mt][s4], F[cb][s4], acc[mt][cb]);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) a[ks] = an[ks];
 #pragma unroll
@@ -1192,16 +1162,10 @@ __global__ void __launch_bounds__(256) deim_weights_kernel(
   }
 }
 
-// ---------------------------------------------------------------------------
-// FP64 matrix-core tiles (v_mfma_f64_16x16x4f64): a wavefront multiplies a
-// 16 x 4 tile A by a 4 x 16 tile B into a 16 x 16 accumulator D.  Operand
-// layout: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k; result: lane
-// l holds D[4 v + l / 16][l % 16] in item v.
-// ---------------------------------------------------------------------------
-typedef double mf_d4 __attribute__((ext_vector_type(4)));
-
+// (FP64 matrix-core tiles: the layout is described with mfma_f64_step.)
+typedef mf4 mf_d4;
 __device__ __forceinline__ mf_d4 mf_step(double a, double b, mf_d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  return mfma_f64_step(a, b, c);
 }
 
 // DEIM basis Psi = Y M (N x d) from the snapshot slots (Y: N x P, column
