@@ -37,21 +37,29 @@ PEAK_FP64 = 78.6e12      # flop/s, MI355X FP64 vector (= FP64 matrix) peak
 
 # timing families that hold one kernel each on the caller's stream
 SINGLE_KERNEL = {
-    "deposit": "deposit_rom_kernel (reconstruct + cell + LDS histogram)",
+    "deposit": "deposit_rom_mfma_kernel (reconstruct on FP64 MFMA + cell + LDS histogram)",
     "gather": "gather_project_mfma_kernel (reconstruct + field gather + g = U^* F on FP64 MFMA)",
-    "gather_xi": "gather_xi_kernel (reconstruct + field gather + xi = -i h G Q + U M)",
+    "gather_xi": "gather_xi_mfma_kernel (reconstruct + field gather + xi = -i h F Q + U M + conj(U) N on FP64 MFMA)",
 }
 
-# HBM bytes per launch of the deposit kernel, measured with two counter
+# HBM bytes per launch of the dominant kernel, measured with two counter
 # passes (FETCH_SIZE, WRITE_SIZE) calibrated on a plain device copy; valid
-# only for the kernel source it was taken on
+# only for the kernel sources it was taken on (their SHA-256 in the profile)
+_CSRC = os.path.join(ROOT, "paper_2201_05555_amd", "csrc")
 TRAFFIC_PROFILE = {
-    "twostream_deim": os.path.join(ROOT, "profiles",
-                                   "deposit_rom_kernel_twostream_deim_N1e5_p64_hbm_traffic.md"),
-    "twostream_large": os.path.join(ROOT, "profiles",
-                                    "deposit_rom_kernel_twostream_large_N4e6_p1024_hbm_traffic.md"),
+    ("gather", "twostream_large"): (
+        os.path.join(ROOT, "profiles", "gather_project_mfma_kernel_twostream_large_N4e6_p1024_hbm_traffic.md"),
+        [os.path.join(_CSRC, "rom_kernels.hip"), os.path.join(_CSRC, "common.h")]),
+    ("deposit", "twostream_deim"): (
+        os.path.join(ROOT, "profiles", "deposit_rom_mfma_kernel_twostream_deim_N1e5_p64_hbm_traffic.md"),
+        [os.path.join(_CSRC, "pic_kernels.hip"), os.path.join(_CSRC, "common.h")]),
 }
-TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2201_05555_amd", "csrc", "pic_kernels.hip")
+
+
+def _progress(msg):
+    """One line on stderr as each part of the run ends (the JSON line stays
+    the only output on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
@@ -68,6 +76,8 @@ def parse():
     ap.add_argument("--serve-step-scale", type=float, default=0.25)
     ap.add_argument("--serve-gap", type=float, default=1.0, help="mean inter-arrival (s)")
     ap.add_argument("--no-dmd", action="store_true", help="skip the DMD-DEIM leg")
+    ap.add_argument("--dmd-only", action="store_true",
+                    help="run only the DMD-DEIM leg (at p = 1024, no sweep) and print its line")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     return ap.parse_args()
@@ -95,22 +105,26 @@ def roofline_of(ms, flops, nbytes, launches):
             "frac": ach / (PEAK_FP64 / 1e12), "traffic": None, **base}
 
 
-def measured_traffic(workload):
-    """Counter-measured HBM bytes per deposit launch, or None when the
-    profile is missing or the kernel source has changed since it was taken."""
+def measured_traffic(family, workload):
+    """Counter-measured HBM bytes per launch of a kernel family, or None when
+    the profile is missing or a kernel source has changed since it was taken."""
     import hashlib
     try:
-        text = open(TRAFFIC_PROFILE[workload]).read()
-        sha = hashlib.sha256(open(TRAFFIC_SOURCE, "rb").read()).hexdigest()
+        path, sources = TRAFFIC_PROFILE[(family, workload)]
+        text = open(path).read()
+        shas = {os.path.relpath(f, ROOT): hashlib.sha256(open(f, "rb").read()).hexdigest()
+                for f in sources}
     except (OSError, KeyError):
         return None
-    val = src = None
+    val = None
+    seen = {}
     for line in text.splitlines():
         if line.startswith("traffic-bytes-per-launch:"):
             val = float(line.split(":")[1])
-        elif line.startswith("source-sha256"):
-            src = line.split(":")[-1].strip()
-    return val if (val is not None and src == sha) else None
+        elif line.startswith("source-sha256 ("):
+            name = line[len("source-sha256 ("):line.index(")")]
+            seen[name] = line.split(":")[-1].strip()
+    return val if (val is not None and seen == shas) else None
 
 
 def _oracle_rate(w, ens, seconds, threads):
@@ -308,6 +322,7 @@ def dmd_deim_leg(binding, torch, steps, warmup, p=1024, p_sweep=(300, 1024, 2048
         tr, tf, _, _, _ = rates(w2, src2, cfg2)
         sweep.append({"p": pv, "rom_ms": 1e3 * tr / steps, "fom_ms": 1e3 * tf / steps,
                       "rom_over_fom": tf / tr})
+        _progress(f"DMD-DEIM sweep p = {pv} done")
     out["p_sweep"] = sweep
     return out
 
@@ -381,6 +396,10 @@ def main():
     from workloads.ensembles import draw_parameters, load_particles, philox_uniforms
 
     torch.cuda.set_device(0)
+    if a.dmd_only:
+        print(json.dumps({"dmd_deim": dmd_deim_leg(binding, torch, a.steps, a.warmup,
+                                                   p_sweep=())}), flush=True)
+        return
     if a.calib_copy_mib:
         src = torch.empty(a.calib_copy_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -449,6 +468,7 @@ def main():
     rom_h.close()
     del rom_h
     torch.cuda.empty_cache()
+    _progress(f"reduced model: {1e3 * t_rom / a.steps:.2f} ms per step")
 
     # ---------------- full-order model ----------------
     fom_h = binding.Fom(N, p, Nx, w["dt"], None, None, None, **src)
@@ -467,6 +487,7 @@ def main():
     fom_h.close()
     del fom_h
     torch.cuda.empty_cache()
+    _progress(f"full-order model: {1e3 * t_fom / a.steps:.2f} ms per step")
 
     pp = N * p
     rom_rate = pp * a.steps / t_rom
@@ -480,11 +501,10 @@ def main():
     if roof is not None:
         roof["kernel"] = SINGLE_KERNEL[dom]
         roof["ms_per_step"] = d["ms"] / a.steps
-        if dom == "deposit":
-            t = measured_traffic(a.workload)
-            if t is not None:
-                roof["traffic"] = t
-                roof["traffic_over_algorithmic"] = t / roof["algorithmic_bytes_per_launch"]
+        t = measured_traffic(dom, a.workload)
+        if t is not None:
+            roof["traffic"] = t
+            roof["traffic_over_algorithmic"] = t / roof["algorithmic_bytes_per_launch"]
     fom_roof = roofline_of(ms_push, fl_push, by_push, n_push)
     # the DEIM chain on the second stream (snapshot, Gram block, top-d
     # eigenpairs, Psi, greedy, weights): device time per step
@@ -537,11 +557,14 @@ def main():
     if not a.no_matched:
         out["matched_error"] = matched_error(binding, torch, w, src, cfg, a.warmup + a.steps)
         out["matched_error"]["rom_over_fom_at_this_error"] = rom_rate / fom_rate
+        _progress("matched error done")
     if not a.no_dmd:
         out["dmd_deim"] = dmd_deim_leg(binding, torch, a.steps, a.warmup)
+        _progress("DMD-DEIM leg done")
     if not a.no_serve:
         out["serve"] = serve_bench(binding, torch, a.serve_requests, a.serve_step_scale, 4, 96.0,
                                    a.serve_gap)
+        _progress("serving mix done")
     if not a.no_cpu:
         # the oracle's sample: the first 8 parameters and 1e5 particles
         ns = min(N, 100_000)

@@ -701,35 +701,41 @@ __global__ void __launch_bounds__(256) reduce_partials2_kernel(const cplx* __res
 // with G~ = F + i v.  Only the field part F (-i h Q) is evaluated per
 // particle and parameter (F at the particle's cell, never stored); the
 // velocity part h v Q, v = Im(U~ Z~), equals U~ (-(i h / 2) Z~ Q) +
-// conj(U~) ((i h / 2) conj(Z~) Q), two n x n products per row.  One thread
-// per particle row, the parameters in a loop: their coefficients, Q entries
-// and factors are wavefront-uniform (scalar loads into SGPRs, read by the
-// FP64 instructions directly, no LDS traffic); the field rows sit in LDS
-// when they fit (pc at a time), and ILP parameters are processed at a time
-// so their independent position / cell / lookup chains interleave.  Q (p x
-// n, ld p) and MU (n x n, ld n) as written by the dense kernels; with g (n x
-// p, the projection g~) given instead of MU, every block forms MU = i h g~^T
-// Q itself.  Every block forms the n x n matrices M and N in LDS (eight
-// lanes per entry).
+// conj(U~) ((i h / 2) conj(Z~) Q), two n x n products per row.  Q (p x n,
+// ld p) and MU (n x n, ld n) as written by the dense kernels; with g (n x p,
+// the projection g~) given instead of MU, every block forms MU = i h g~^T Q
+// itself, and every block forms M = MU - (i h / 2) Z~ Q and N = (i h / 2)
+// conj(Z~) Q (eight lanes per entry).  The products run on the FP64 matrix
+// cores.  Each wavefront takes 64 particle rows (four 16-row tiles)
+// and walks the parameters 16 at a time: the positions come from pos_tile
+// (the code of the deposit and the gather-projection, so the cells agree),
+// an LDS transpose gives each lane one row and the 16 parameters (the
+// lookups of a wavefront then fall in one parameter's field row), a second
+// one gives the A operand of aq = F (-i h Q) in real form (outputs o: the
+// real parts of the n columns, then the imaginary parts), accumulated on
+// the matrix cores.  At the end the outputs of a row are gathered through
+// LDS and U~ M + conj(U~) N is added per row.
 // ---------------------------------------------------------------------------
-template <int NC, bool ET_LDS>
-__global__ void __launch_bounds__(256) gather_xi_kernel(
+template <int NC>
+__global__ void __launch_bounds__(256) gather_xi_mfma_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx,
     const double* __restrict__ factor, const double* __restrict__ e, double qm,
     const cplx* __restrict__ Q, const cplx* __restrict__ MU, const cplx* __restrict__ gp,
-    double h, cplx* __restrict__ out, int pc) {
-  // (the coefficients of ILP parameters take 4 ILP NC SGPRs, then their Q
-  // entries as many)
-  constexpr int ILP = 2;
-  extern __shared__ double smem[];
-  cplx* Ms = reinterpret_cast<cplx*>(smem);  // [NC][NC]: M[j][k] at Ms[j * NC + k]
-  cplx* Ns = Ms + NC * NC;                   // [NC][NC]: (i h / 2) (conj(Z~) Q)[j][k]
-  double* et = reinterpret_cast<double*>(Ns + NC * NC);  // [pc][Nx] (ET_LDS)
-  const int tid = threadIdx.x;
+    double h, cplx* __restrict__ out) {
+  constexpr int KS = (2 * NC + 3) / 4;
+  constexpr int MT = (2 * NC + 15) / 16;
+  constexpr int XS = 65;  // row stride of the position tile (parameter-major)
+  constexpr int FS = 17;  // row stride of the field tile (row-major)
+  constexpr int OS = 16 * MT + 1;  // row stride of the output tile (>= FS)
+  __shared__ cplx Ms[NC * NC], Ns[NC * NC];
+  __shared__ double Xs[4][16 * XS];
+  __shared__ double Fs[4][64 * OS];  // the field tile, then the output tile
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
   {
-    // M[j][k] = MU[j][k] - (i h / 2) (Z~ Q)[j][k], MU = i h (g~ Q)[j][k]
-    // formed here when g is given; N[j][k] = (i h / 2) (conj(Z~) Q)[j][k].
-    // Lanes 8e..8e+7 split the sums over c (eight loads in flight per round).
+    // M = MU - (i h / 2) Z~ Q (MU = i h g~ Q formed here when g is given),
+    // N = (i h / 2) conj(Z~) Q; lanes 8e..8e+7 split the sums over c
     const int e8 = tid >> 3, part8 = tid & 7;
     for (int e0 = 0; e0 < NC * NC; e0 += 32) {
       const int t = e0 + e8;
@@ -748,7 +754,6 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
 #pragma unroll
           for (int u = 0; u < 8; ++u)
             if (c0 + 8 * u < p) {
-              // (-i h q) times (g - z / 2) and times conj(z)
               const cplx mq = mk(h * qv[u].im, -h * qv[u].re);
               cfma(sm, mk(gv[u].re - 0.5 * zv[u].re, gv[u].im - 0.5 * zv[u].im), mq);
               cfmac(sn, zv[u], mq);
@@ -770,93 +775,114 @@ __global__ void __launch_bounds__(256) gather_xi_kernel(
       }
     }
   }
-  const int l = blockIdx.x * 256 + tid;
-  const bool valid = l < N;
-  cplx u[NC], aq[NC];
-#pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    u[k] = (valid && k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
-    aq[k] = mk(0.0, 0.0);
-  }
   __syncthreads();
-  // aq = F Q over the parameters in order (-i h applied at the end)
-  for (int cb = 0; cb < p; cb += pc) {
-    const int np = min(pc, p - cb);
-    if (ET_LDS) {
-      if (cb > 0) __syncthreads();  // the previous chunk is done with the table
-      const int tot = np * Nx;
-      const double* ec = e + (size_t)cb * Nx;
-      for (int t0 = 0; t0 < tot; t0 += 8 * 256) {
-        double v[8];
+  const int rbase = (blockIdx.x * 4 + w) * 64;  // this wavefront's 64 rows
+  if (rbase >= N) return;
+  const int rlast = N - 1;
+  PosRows<KS> pr;
+  pr.setup(U, N, n, NC, lk);
+  double a[4][KS];
 #pragma unroll
-        for (int u8 = 0; u8 < 8; ++u8) {
-          const int t = t0 + u8 * 256 + tid;
-          v[u8] = (t < tot) ? ec[t] : 0.0;
-        }
+  for (int rt = 0; rt < 4; ++rt) pr.load(min(rbase + 16 * rt + li, rlast), a[rt]);
+  mf4 acc[4][MT];
 #pragma unroll
-        for (int u8 = 0; u8 < 8; ++u8) {
-          const int t = t0 + u8 * 256 + tid;
-          if (t < tot) et[t] = qm * v[u8];
-        }
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[rt][mt] = mf4{0.0, 0.0, 0.0, 0.0};
+  double* xs = Xs[w];
+  double* fs = Fs[w];
+  for (int c0 = 0; c0 < p; c0 += 16) {
+    const int ntc = min(16, p - c0);
+    // B operands: the coefficients of parameter c0 + li and the entries
+    // qr[c0 + 4 s + lk][o = 16 mt + li] of -i h Q in real form
+    double bz[KS];
+    pos_coefs<KS>(Z, n, NC, c0 + min(li, ntc - 1), li < ntc, lk, bz);
+    double qb[MT][4];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int c = c0 + 4 * s4 + lk;
+      const bool cv = 4 * s4 + lk < ntc;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int o = 16 * mt + li;
+        const int k = (o < NC) ? o : o - NC;
+        const bool ok = cv && o < 2 * NC && k < n;
+        const cplx qv = Q[(size_t)(ok ? k : 0) * p + min(c, p - 1)];
+        // -i h q = (h q.im, -h q.re)
+        qb[mt][s4] = ok ? ((o < NC) ? h * qv.im : -h * qv.re) : 0.0;
       }
-      __syncthreads();
     }
-    for (int c0 = 0; c0 < np; c0 += ILP) {
-      double F[ILP];
+    // positions, parameter-major in LDS: xs[param li][row 16 rt + 4 v + lk]
 #pragma unroll
-      for (int q = 0; q < ILP; ++q) {
-        // (a pair past the end repeats the last parameter and is not added)
-        const int c = cb + min(c0 + q, np - 1);
-        const cplx* zc = Z + (size_t)c * n;
-        double x0 = 0.0, x1 = 0.0;
+    for (int rt = 0; rt < 4; ++rt) {
+      const mf4 X = pos_tile<KS>(a[rt], bz);
 #pragma unroll
-        for (int k = 0; k < NC; k += 2) {
-          // (past n the entry read is finite and u is exactly zero)
-          const cplx za = zc[min(k, n - 1)];
-          x0 = fma(u[k].re, za.re, x0);
-          x0 = fma(-u[k].im, za.im, x0);
-          if (k + 1 < NC) {
-            const cplx zb = zc[min(k + 1, n - 1)];
-            x1 = fma(u[k + 1].re, zb.re, x1);
-            x1 = fma(-u[k + 1].im, zb.im, x1);
-          }
-        }
-        int j;
+      for (int v = 0; v < 4; ++v) xs[li * XS + 16 * rt + 4 * v + lk] = X[v];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // lane = row rbase + lane: its 16 positions, cells and field values
+    // (parameter q uniform across the wavefront: one field row per lookup;
+    // all 16 lookups in flight together)
+    {
+      int jq[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
         double th;
-        cell_of(x0 + x1, factor[c], Nx, j, th);
-        F[q] = ET_LDS ? et[(c - cb) * Nx + j] : qm * e[(size_t)c * Nx + j];
+        cell_of(xs[q * XS + lane], factor[c0 + min(q, ntc - 1)], Nx, jq[q], th);
       }
-      // (the Q entries are loaded after the coefficients are dead: the
-      // empty asm keeps them from being hoisted above the lookups)
-      asm volatile("" ::: "memory");
+      double fq[16];
 #pragma unroll
-      for (int q = 0; q < ILP; ++q) {
-        if (c0 + q < np) {
-          const int c = cb + c0 + q;
+      for (int q = 0; q < 16; ++q) fq[q] = e[(size_t)(c0 + min(q, ntc - 1)) * Nx + jq[q]];
 #pragma unroll
-          for (int k = 0; k < NC; ++k) {
-            // (aq past n is never written out)
-            const cplx qv = Q[(size_t)min(k, n - 1) * p + c];
-            aq[k].re = fma(F[q], qv.re, aq[k].re);
-            aq[k].im = fma(F[q], qv.im, aq[k].im);
-          }
-        }
-      }
+      for (int q = 0; q < 16; ++q) fs[lane * FS + q] = (q < ntc) ? qm * fq[q] : 0.0;
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // aq += F qr: A[row 16 rt + li][parameter 4 s + lk] from the field tile
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const double fa = fs[(16 * rt + li) * FS + 4 * s4 + lk];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[rt][mt] = mfma_f64_step(fa, qb[mt][s4], acc[rt][mt]);
+      }
   }
-  // out[:, k] = -i h aq[k] + (U~ M + conj(U~) N)[:, k], one column at a time
-  // (the padding k >= n is zero in u, Ms and Ns; the empty asm keeps the
-  // LDS reads of a column from being hoisted above the previous one)
+  // the outputs of each row through LDS (the field tile's space): lane holds
+  // aq[row 16 rt + 4 v + lk][o = 16 mt + li]
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  double* os = fs;  // [64][OS]
 #pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    cplx a = mk(h * aq[k].im, -h * aq[k].re);
+  for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      cfma(a, u[j], Ms[j * NC + k]);
-      cfmac(a, u[j], Ns[j * NC + k]);
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) os[(16 * rt + 4 * v + lk) * OS + 16 * mt + li] = acc[rt][mt][v];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int l = rbase + lane;
+  if (l < N) {
+    cplx u[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) u[k] = (k < n) ? U[(size_t)k * N + l] : mk(0.0, 0.0);
+    // out[:, k] = aq[k] + (U~ M + conj(U~) N)[:, k], one column at a time
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      cplx r = mk(os[lane * OS + k], os[lane * OS + NC + k]);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        cfma(r, u[j], Ms[j * NC + k]);
+        cfmac(r, u[j], Ns[j * NC + k]);
+      }
+      if (k < n) out[(size_t)k * N + l] = r;
+      asm volatile("" ::: "memory");
     }
-    if (valid && k < n) out[(size_t)k * N + l] = a;
-    asm volatile("" ::: "memory");
   }
 }
 
@@ -1454,44 +1480,21 @@ void launch_gather_xi(hipStream_t s, const cplx* U, int N, int n, const cplx* Z,
                       const double* factor, const double* e, double qm, const cplx* Q,
                       const cplx* MU, double h, cplx* out, const cplx* g) {
   const int nc = fused_nc(n);
-  // LDS: the n x n matrices M and N, and the field rows of all parameters
-  // when they fit, else of chunks of 64 when those fit, else none
-  const size_t base = (size_t)2 * nc * nc * sizeof(cplx);
-  const size_t budget = 76 * 1024;
-  int pc = p;
-  bool et_lds = base + (size_t)p * Nx * sizeof(double) <= budget;
-  if (!et_lds && p > 64 && base + (size_t)64 * Nx * sizeof(double) <= budget) {
-    pc = 64;
-    et_lds = true;
-  }
-  const size_t sh = base + (et_lds ? (size_t)pc * Nx * sizeof(double) : 0);
+  // 256 rows per block (four wavefronts of 64)
   dim3 grid((N + 255) / 256);
-#define GXK(NCV, ETV)                                                                          \
-  ALLOW_BIG_LDS((gather_xi_kernel<NCV, ETV>));                                               \
-  hipLaunchKernelGGL((gather_xi_kernel<NCV, ETV>), grid, dim3(256), sh, s, U, N, n, Z, p, Nx,  \
-                     factor, e, qm, Q, MU, g, h, out, pc)
-  if (et_lds) {
-    switch (nc) {
-      case 4: GXK(4, true); break;
-      case 5: GXK(5, true); break;
-      case 6: GXK(6, true); break;
-      case 7: GXK(7, true); break;
-      case 8: GXK(8, true); break;
-      case 12: GXK(12, true); break;
-      default: GXK(16, true); break;
-    }
-  } else {
-    switch (nc) {
-      case 4: GXK(4, false); break;
-      case 5: GXK(5, false); break;
-      case 6: GXK(6, false); break;
-      case 7: GXK(7, false); break;
-      case 8: GXK(8, false); break;
-      case 12: GXK(12, false); break;
-      default: GXK(16, false); break;
-    }
+#define GXM(NCV)                                                                               \
+  hipLaunchKernelGGL(gather_xi_mfma_kernel<NCV>, grid, dim3(256), 0, s, U, N, n, Z, p, Nx, factor, \
+                     e, qm, Q, MU, g, h, out)
+  switch (nc) {
+    case 4: GXM(4); break;
+    case 5: GXM(5); break;
+    case 6: GXM(6); break;
+    case 7: GXM(7); break;
+    case 8: GXM(8); break;
+    case 12: GXM(12); break;
+    default: GXM(16); break;
   }
-#undef GXK
+#undef GXM
 }
 
 void launch_gather_rom(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p, int Nx,
