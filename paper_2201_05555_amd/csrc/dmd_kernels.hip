@@ -300,6 +300,41 @@ __global__ void dmd_window_kernel(const double* __restrict__ ring, int nslots, i
   }
 }
 
+// Reflection of one column held in LDS by one thread: col[k:Nx] -=
+// tau (v^T col[k:Nx]) v with v = vk[k:Nx].  Rows in chunks of 8 whose loads
+// are issued together and unpredicated (the region is followed by 8 doubles
+// of slack; rows past Nx are masked by selects, not branches), so the
+// thread waits for LDS once per chunk, not once per row.
+__device__ __forceinline__ void reflect_col_lds(const double* vk, double* col, int k, int Nx,
+                                                double tk) {
+  double d = 0.0;
+  for (int i0 = k; i0 < Nx; i0 += 8) {
+    double wv[8], cv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      wv[u] = vk[i0 + u];
+      cv[u] = col[i0 + u];
+    }
+    // (the rows past Nx hold padding or the next column, possibly never
+    // written: the accumulation itself is selected, so no product of them
+    // reaches d)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) d = (i0 + u < Nx) ? fma(wv[u], cv[u], d) : d;
+  }
+  const double f = tk * d;
+  for (int i0 = k; i0 < Nx; i0 += 8) {
+    double wv[8], cv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      wv[u] = vk[i0 + u];
+      cv[u] = col[i0 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u < Nx) col[i0 + u] = fma(-f, wv[u], cv[u]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Householder QR of an Nx x P matrix W (column-major, leading dimension ld,
 // in place), one
@@ -309,7 +344,8 @@ __global__ void dmd_window_kernel(const double* __restrict__ ring, int nslots, i
 // W.  Every further column (and the ncx columns of X, Nx x ncx with the same
 // leading dimension, when given)
 // is updated either by one thread that runs down its rows (ByThread: W in
-// LDS, no cross-lane reduction and independent loads) or by the wavefront
+// LDS, followed by 8 doubles of slack; no cross-lane reduction, loads in
+// chunks of 8) or by the wavefront
 // that owns it (column j by wave j mod 4, coalesced rows: W in global).
 // ---------------------------------------------------------------------------
 template <bool ByThread>
@@ -338,18 +374,11 @@ __device__ void householder_qr(double* W, int Nx, int ld, int P, double* alpha, 
     if (tk != 0.0) {
       const int ntot = (P - k - 1) + ncx;
       if (ByThread) {
+        // (W in LDS with 8 doubles of slack past its last column)
         for (int c = t; c < ntot; c += 256) {
           double* col = (c < P - k - 1) ? W + (size_t)(k + 1 + c) * ld
                                         : X + (size_t)(c - (P - k - 1)) * ld;
-          double d0 = 0.0, d1 = 0.0;
-          int i = k;
-          for (; i + 1 < Nx; i += 2) {
-            d0 = fma(wk[i], col[i], d0);
-            d1 = fma(wk[i + 1], col[i + 1], d1);
-          }
-          if (i < Nx) d0 = fma(wk[i], col[i], d0);
-          const double f = tk * (d0 + d1);
-          for (int i2 = k; i2 < Nx; ++i2) col[i2] = fma(-f, wk[i2], col[i2]);
+          reflect_col_lds(wk, col, k, Nx, tk);
         }
       } else {
         for (int c = wv; c < ntot; c += 4) {
@@ -405,7 +434,7 @@ __global__ void __launch_bounds__(256) dmd_svd_kernel(double* __restrict__ W, in
   // walk down fall in different banks): every reflection then waits on LDS,
   // not on global loads
   const int ldl = Nx | 1;
-  const bool lw = ldl * P <= 8192;
+  const bool lw = ldl * P + 8 <= 8192;
   const int ldq = lw ? ldl : Nx;
   double* Wl = jsm + 2 * 64 * JS;
   if (lw) {
@@ -446,13 +475,6 @@ __global__ void __launch_bounds__(256) dmd_svd_kernel(double* __restrict__ W, in
   }
   const double frob2 = block_sum(fr, red);
   const double tiny = 1e-30 * frob2;
-  // two columns both below (1e-3 tol)^2 |R|_F^2 are not rotated against each
-  // other: every column above that stays orthogonal to all others, so the
-  // singular triplets above it are those of the converged part, while all
-  // the singular values of the unsettled remainder sit below sqrt(C) 1e-3 tol
-  // |R|_F <= C 1e-3 tol sigma_1, under the truncation tol sigma_1 (its
-  // triplets are dropped anyway)
-  const double cut = fmax(tiny, 1e-6 * tol * tol * frob2);
   // round-robin pairs (circle method) over C2 = C rounded up to even; a
   // pair with the padding column is skipped
   const int C2 = C + (C & 1);
@@ -503,11 +525,13 @@ __global__ void __launch_bounds__(256) dmd_svd_kernel(double* __restrict__ W, in
         al += bfly64<2>(al);
         be += bfly64<2>(be);
         ga += bfly64<2>(ga);
-        if (act && ga != 0.0 && al > tiny && be > tiny && fmax(al, be) > cut &&
-            fabs(ga) > 1e-15 * sqrt(al * be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double tt = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+        if (act && ga != 0.0 && al > tiny && be > tiny && ga * ga > 1e-30 * (al * be)) {
+          // tan of the rotation, the root of smaller modulus of t^2 + 2 zeta t
+          // - 1 = 0 with zeta = (be - al) / (2 ga): t = sign(d) 2ga / (|d| +
+          // hypot(d, 2ga)), d = be - al (t = +-1 when d = 0)
+          const double d = be - al, g2 = 2.0 * ga;
+          const double tt = ((d >= 0.0) ? g2 : -g2) / (fabs(d) + sqrt(fma(d, d, g2 * g2)));
+          const double c = 1.0 / sqrt(fma(tt, tt, 1.0)), s = c * tt;
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const int i = sub + 8 * u;
@@ -566,7 +590,7 @@ __global__ void __launch_bounds__(256) dmd_svd_kernel(double* __restrict__ W, in
   }
   __syncthreads();
   const double* src = wide ? Vs : Rs;
-  const bool lu = lw && r * ldl <= 64 * JS;
+  const bool lu = lw && r * ldl + 8 <= 64 * JS;
   double* Ul = wide ? Rs : Vs;
   for (int q = t; q < C * Nx; q += 256) {
     const int j = q / Nx, i = q - j * Nx;
@@ -582,21 +606,14 @@ __global__ void __launch_bounds__(256) dmd_svd_kernel(double* __restrict__ W, in
   __threadfence_block();
   __syncthreads();
   if (lu) {
+    // (Ul ends at least 8 doubles before the end of its half of the Jacobi
+    // storage or runs into Wl; Wl has 8 doubles of slack)
     for (int c = t; c < r; c += 256) {
       double* u = Ul + c * ldl;
       for (int k = m - 1; k >= 0; --k) {
         const double tk = tau[k];
         if (tk == 0.0) continue;
-        const double* vk = Wl + k * ldl;
-        double d0 = 0.0, d1 = 0.0;
-        int i = k;
-        for (; i + 1 < Nx; i += 2) {
-          d0 = fma(vk[i], u[i], d0);
-          d1 = fma(vk[i + 1], u[i + 1], d1);
-        }
-        if (i < Nx) d0 = fma(vk[i], u[i], d0);
-        const double f = tk * (d0 + d1);
-        for (int i2 = k; i2 < Nx; ++i2) u[i2] = fma(-f, vk[i2], u[i2]);
+        reflect_col_lds(Wl + k * ldl, u, k, Nx, tk);
       }
     }
     __syncthreads();

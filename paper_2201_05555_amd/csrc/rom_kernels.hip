@@ -451,21 +451,24 @@ __global__ void __launch_bounds__(64) deim_gather_kernel(
 
 
 // ---------------------------------------------------------------------------
-// Fused gather + projection on the FP64 matrix cores: the field part U~^* F
-// of g (the velocity part is added by the reduction, as for
-// gather_project_kernel), per wavefront 16 particle rows at a time against
-// the 64 parameters of the tile.  Real form with K = 2 NC: a = [Re U~ |
-// -Im U~] (row-major per particle), b = [Re Z~; Im Z~], so that the positions
-// X = a b (16 rows x 16 parameters per accumulator, four accumulators).  In
-// the accumulator layout lane l holds X[4 v + l / 16][l % 16], which is the
-// layout of the B operand of g = a^T F for the 4-row step v: the cell, the
-// field lookup and the masks run on the positions in registers and feed
-// the second product directly.  Results: block b writes part[b * rec + c *
-// n + k] and, with want_colsq, |F[:, c]|^2 at part[b * rec + n * p + c].re;
-// the four wavefronts are summed in a fixed order.
+// Fused gather + projection (eq. grads) on the FP64 matrix cores: the field
+// part U~^* F of g = U~^* G~, G~ = F + i v, with F = (q/m) e_c at the
+// particle's cell evaluated on the fly and never stored (the velocity part
+// i U~^* v, v = Im(U~ Z~), is linear in Z~ and is added by the reduction
+// from the small Gram matrices of U~).  A block takes a tile of 16 CBN
+// parameters (their field rows in LDS with ET_LDS) and a range of particle
+// rows, each of its WV wavefronts 16 rows at a time.  Real form with K = 2
+// NC: a = [Re U~ | -Im U~] (row-major per particle), b = [Re Z~; Im Z~], so
+// that the positions X = a b (16 rows x 16 parameters per accumulator, CBN
+// accumulators).  In the accumulator layout lane l holds X[4 v + l / 16][l %
+// 16], which is the layout of the B operand of g = a^T F for the 4-row step
+// v: the cell, the field lookup and the masks run on the positions in
+// registers and feed the second product directly.  Results: row block b
+// writes part[b * rec + c * n + k] and, with want_colsq, |F[:, c]|^2 at
+// part[b * rec + n * p + c].re; the wavefronts are summed in a fixed order.
 // ---------------------------------------------------------------------------
-template <int NC, int CBN, bool ET_LDS>
-__global__ void __launch_bounds__(256) gather_project_mfma_kernel(
+template <int NC, int CBN, bool ET_LDS, int WV>
+__global__ void __launch_bounds__(64 * WV) gather_project_mfma_kernel(
     const cplx* __restrict__ U, int N, int n, const cplx* __restrict__ Z, int p, int Nx, int rpb,
     const double* __restrict__ factor, const double* __restrict__ e, double qm,
     const int* __restrict__ active, int rec, int want_colsq, cplx* __restrict__ part,
@@ -487,16 +490,16 @@ __global__ void __launch_bounds__(256) gather_project_mfma_kernel(
   if (ET_LDS) {
     const double* es = e + (size_t)c0 * Nx;
     const int tot = ntc * Nx;
-    for (int t0 = 0; t0 < tot; t0 += 4 * 256) {
+    for (int t0 = 0; t0 < tot; t0 += 4 * 64 * WV) {
       double v[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int t = t0 + u * 256 + tid;
+        const int t = t0 + u * 64 * WV + tid;
         v[u] = (t < tot) ? es[t] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int t = t0 + u * 256 + tid;
+        const int t = t0 + u * 64 * WV + tid;
         if (t < tot) et[t] = qm * v[u];
       }
     }
@@ -553,8 +556,8 @@ __global__ void __launch_bounds__(256) gather_project_mfma_kernel(
     }
   };
   load_tile(r0 + 16 * w, a, at);
-  for (int t0 = r0 + 16 * w; t0 < r1; t0 += 64) {
-    load_tile(t0 + 64, an, atn);
+  for (int t0 = r0 + 16 * w; t0 < r1; t0 += 16 * WV) {
+    load_tile(t0 + 16 * WV, an, atn);
     mf4 X[CBN];
 #pragma unroll
     for (int cb = 0; cb < CBN; ++cb) X[cb] = pos_tile<KS>(a, bz[cb]);
@@ -594,8 +597,8 @@ __global__ void __launch_bounds__(256) gather_project_mfma_kernel(
   }
   __syncthreads();  // (the field rows are no longer needed)
   // wavefront sums: red[w][o][parameter], o over the 16 MT real outputs
-  double* red = smem;                         // [4][16 MT][PT]
-  double* rcs = smem + 4 * 16 * MT * PT;       // [4][PT]
+  double* red = smem;                          // [WV][16 MT][PT]
+  double* rcs = smem + WV * 16 * MT * PT;       // [WV][PT]
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -608,19 +611,21 @@ __global__ void __launch_bounds__(256) gather_project_mfma_kernel(
     for (int cb = 0; cb < CBN; ++cb) rcs[w * PT + 16 * cb + li] = csq[cb];
   __syncthreads();
   cplx* pb = part + (size_t)rb * rec;
-  for (int t = tid; t < ntc * n; t += 256) {
+  for (int t = tid; t < ntc * n; t += 64 * WV) {
     const int q = t / n, k = t % n;
     double re = 0.0, im = 0.0;
 #pragma unroll
-    for (int ww = 0; ww < 4; ++ww) {
+    for (int ww = 0; ww < WV; ++ww) {
       re += red[((size_t)ww * 16 * MT + k) * PT + q];
       im += red[((size_t)ww * 16 * MT + NC + k) * PT + q];
     }
     pb[(size_t)(c0 + q) * n + k] = mk(re, im);
   }
   if (want_colsq)
-    for (int t = tid; t < ntc; t += 256) {
-      const double sw = ((rcs[t] + rcs[PT + t]) + rcs[2 * PT + t]) + rcs[3 * PT + t];
+    for (int t = tid; t < ntc; t += 64 * WV) {
+      double sw = rcs[t];
+#pragma unroll
+      for (int ww = 1; ww < WV; ++ww) sw += rcs[ww * PT + t];
       pb[(size_t)n * p + c0 + t] = mk(sw, 0.0);
     }
 }
@@ -1439,16 +1444,23 @@ void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cpl
   const int pt = 16 * cbn;
   const int ntile = (p + pt - 1) / pt;
   const size_t et_bytes = et_lds ? (size_t)pt * Nx * sizeof(double) : 0;
-  // the wavefront sums reuse the table's space: 4 x 16 MT x PT + 4 x PT doubles
+  // eight wavefronts per block on one field table when the tile is narrow
+  // (more wavefronts per SIMD for the same LDS), else four; the wavefront
+  // sums reuse the table's space: WV x 16 MT x PT + WV x PT doubles
+  const int wv = (cbn <= 2) ? 8 : 4;
   const int mt = (2 * nc + 15) / 16;
-  const size_t red_bytes = (size_t)4 * 16 * mt * pt * sizeof(double) + 4 * pt * sizeof(double);
+  const size_t red_bytes =
+      (size_t)wv * 16 * mt * pt * sizeof(double) + (size_t)wv * pt * sizeof(double);
   const size_t sh = std::max(et_bytes, red_bytes);
   dim3 grid(ntile, nb);
-#define GPM(NCV, CBV, ETV)                                                                      \
-  ALLOW_BIG_LDS((gather_project_mfma_kernel<NCV, CBV, ETV>));                                 \
-  hipLaunchKernelGGL((gather_project_mfma_kernel<NCV, CBV, ETV>), grid, dim3(256), sh, s, U, N, \
-                     n, Z, p, Nx, rpb, factor, e, qm, active, rec, want_colsq ? 1 : 0, part,    \
-                     gate)
+#define GPM(NCV, CBV, ETV)                                                                  \
+  {                                                                                        \
+    constexpr int WVV = (CBV <= 2) ? 8 : 4;                                                \
+    ALLOW_BIG_LDS((gather_project_mfma_kernel<NCV, CBV, ETV, WVV>));                       \
+    hipLaunchKernelGGL((gather_project_mfma_kernel<NCV, CBV, ETV, WVV>), grid, dim3(64 * WVV), \
+                       sh, s, U, N, n, Z, p, Nx, rpb, factor, e, qm, active, rec,           \
+                       want_colsq ? 1 : 0, part, gate);                                     \
+  }
 #define GPM_NC(CBV, ETV)                \
   switch (nc) {                         \
     case 4: GPM(4, CBV, ETV); break;    \
