@@ -159,11 +159,14 @@ def test_rom_init_parity(name, kw, two_n):
 @pytest.mark.parametrize("name,kw,two_n", [
     ("landau_tiny", dict(N=3001), 10),
     ("twostream_deim", dict(N=20000, p=24, Nx=128), 16),
-    # a grid whose 64-parameter field table does not fit the LDS budget: the
-    # tiled gather-projection (field rows of 32 parameters in LDS), with a
-    # ragged last tile
+    # a grid whose 64-parameter field table does not fit the LDS budget:
+    # parameter tiles of 16 with their field rows in LDS, a ragged last tile
     ("twostream_deim", dict(N=20000, p=70, Nx=512), 16),
     ("twostream_deim", dict(N=9001, p=33, Nx=512), 10),
+    # a grid beyond even 16 field rows in LDS: the gather-projection reads
+    # the table from global memory, the deposit takes tiles of 10 parameters
+    # (21 = 10 + 10 + 1)
+    ("twostream_deim", dict(N=5000, p=21, Nx=1024), 12),
 ])
 def test_rom_gradient_parity(name, kw, two_n):
     binding, torch = _b()
@@ -217,6 +220,9 @@ def _within(err, sens, what, floor=RTOL):
     ("landau_tiny", dict(N=3001), 10, 6),
     ("twostream_deim", dict(N=20000, p=24, Nx=128), 12, 5),
     ("twostream_deim", dict(N=12345, p=40, Nx=96), 20, 4),
+    # 2n = 30: the widest compiled column count of the particle kernels (16;
+    # two 16-row tiles of outputs, eight steps of the position product)
+    ("twostream_deim", dict(N=6000, p=20, Nx=64), 30, 3),
     # 2n = 36: the paths for n > 16 (gradient through a stored G~, two-Gram
     # tangent velocity, retraction and re-orthonormalisation apart)
     ("twostream_deim", dict(N=6000, p=24, Nx=64), 36, 3),
