@@ -62,6 +62,19 @@ def _progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _leg(name, fn):
+    """Run an optional part of the benchmark; a failure of the library in it
+    (for example a fixed point that does not converge) is reported in its
+    place instead of ending the run, so the headline line is still printed."""
+    try:
+        out = fn()
+        _progress(f"{name} done")
+        return out
+    except Exception as e:  # reported, not hidden: the leg's entry says what failed
+        _progress(f"{name} failed: {type(e).__name__}: {e}")
+        return {"failed": f"{type(e).__name__}: {e}"}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,11 +331,13 @@ def dmd_deim_leg(binding, torch, steps, warmup, p=1024, p_sweep=(300, 1024, 2048
             sweep.append({"p": pv, "rom_ms": out["ms_per_step"],
                           "fom_ms": out["fom"]["ms_per_step"], "rom_over_fom": out["rom_over_fom"]})
             continue
-        w2, src2, cfg2 = setup(pv)
-        tr, tf, _, _, _ = rates(w2, src2, cfg2)
-        sweep.append({"p": pv, "rom_ms": 1e3 * tr / steps, "fom_ms": 1e3 * tf / steps,
-                      "rom_over_fom": tf / tr})
-        _progress(f"DMD-DEIM sweep p = {pv} done")
+        def point(pv=pv):
+            w2, src2, cfg2 = setup(pv)
+            tr, tf, _, _, _ = rates(w2, src2, cfg2)
+            return {"p": pv, "rom_ms": 1e3 * tr / steps, "fom_ms": 1e3 * tf / steps,
+                    "rom_over_fom": tf / tr}
+        res = _leg(f"DMD-DEIM sweep p = {pv}", point)
+        sweep.append(res if "failed" not in res else dict(res, p=pv))
     out["p_sweep"] = sweep
     return out
 
@@ -555,16 +570,16 @@ def main():
     }
     out["config"]["init_s"] = t_init
     if not a.no_matched:
-        out["matched_error"] = matched_error(binding, torch, w, src, cfg, a.warmup + a.steps)
-        out["matched_error"]["rom_over_fom_at_this_error"] = rom_rate / fom_rate
-        _progress("matched error done")
+        out["matched_error"] = _leg("matched error", lambda: matched_error(
+            binding, torch, w, src, cfg, a.warmup + a.steps))
+        if "failed" not in out["matched_error"]:
+            out["matched_error"]["rom_over_fom_at_this_error"] = rom_rate / fom_rate
     if not a.no_dmd:
-        out["dmd_deim"] = dmd_deim_leg(binding, torch, a.steps, a.warmup)
-        _progress("DMD-DEIM leg done")
+        out["dmd_deim"] = _leg("DMD-DEIM leg", lambda: dmd_deim_leg(binding, torch, a.steps,
+                                                                     a.warmup))
     if not a.no_serve:
-        out["serve"] = serve_bench(binding, torch, a.serve_requests, a.serve_step_scale, 4, 96.0,
-                                   a.serve_gap)
-        _progress("serving mix done")
+        out["serve"] = _leg("serving mix", lambda: serve_bench(
+            binding, torch, a.serve_requests, a.serve_step_scale, 4, 96.0, a.serve_gap))
     if not a.no_cpu:
         # the oracle's sample: the first 8 parameters and 1e5 particles
         ns = min(N, 100_000)
