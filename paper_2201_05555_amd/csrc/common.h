@@ -45,18 +45,12 @@ __host__ __device__ inline double cabs2(cplx a) { return a.re * a.re + a.im * a.
 // Particle-to-cell lookup of the periodic P1 mesh.  s = x * (Nx / L) with the
 // factor formed once in FP64 on the host; c = floor(s); theta = s - c (exact);
 // node j = c mod Nx (Euclidean).  A particle on a node takes the cell to its
-// right.  Valid for unwrapped positions with |s| < 2^52.  For a power-of-two
-// Nx and |c| < 2^30 the Euclidean remainder is the low bits of the
-// two's-complement integer c (the same j, with a few integer operations in
-// place of the floating-point division and corrections).
+// right.  Valid for unwrapped positions with |s| < 2^52.  Branch-free, so
+// that the cells of several particles of a thread interleave.
 __device__ inline void cell_of(double x, double factor, int Nx, int& j, double& theta) {
   const double s = x * factor;
   const double c = floor(s);
   theta = s - c;
-  if ((Nx & (Nx - 1)) == 0 && fabs(c) < 0x1p30) {
-    j = (int)c & (Nx - 1);
-    return;
-  }
   // Euclidean c mod Nx in exact double arithmetic (c and q*Nx are integers
   // below 2^53); the quotient estimate is corrected by at most one.
   const double fNx = (double)Nx;

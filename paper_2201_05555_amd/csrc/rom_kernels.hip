@@ -561,20 +561,29 @@ __global__ void __launch_bounds__(64 * WV) gather_project_mfma_kernel(
     mf4 X[CBN];
 #pragma unroll
     for (int cb = 0; cb < CBN; ++cb) X[cb] = pos_tile<KS>(a, bz[cb]);
-    // F at the positions: lane holds row t0 + 4 v + lk, parameter 16 cb + li
+    // F at the positions: lane holds row t0 + 4 v + lk, parameter 16 cb + li.
+    // All cells first, then all lookups (unconditional: the cell is always
+    // in range), then the masks as selects, so that the lookups of a lane
+    // are in flight together
     double F[CBN][4];
 #pragma unroll
-    for (int cb = 0; cb < CBN; ++cb)
+    for (int cb = 0; cb < CBN; ++cb) {
+      int jv[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int j;
         double th;
-        cell_of(X[cb][v], fac[cb], Nx, j, th);
-        const int cl = min(16 * cb + li, ntc - 1);
-        const double f = ET_LDS ? et[cl * Nx + j] : qm * e[(size_t)(c0 + cl) * Nx + j];
-        F[cb][v] = (on[cb] && t0 + 4 * v + lk < r1) ? f : 0.0;
+        cell_of(X[cb][v], fac[cb], Nx, jv[v], th);
+      }
+      const int cl = min(16 * cb + li, ntc - 1);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        F[cb][v] = ET_LDS ? et[cl * Nx + jv[v]] : qm * e[(size_t)(c0 + cl) * Nx + jv[v]];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        F[cb][v] = (on[cb] && t0 + 4 * v + lk < r1) ? F[cb][v] : 0.0;
         csq[cb] = fma(F[cb][v], F[cb][v], csq[cb]);
       }
+    }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
