@@ -250,6 +250,15 @@ def matched_error(binding, torch, w, src, cfg, steps):
                           "max_t E_fom"}
 
 
+# Stagnation floor of the fixed point in the DMD-DEIM leg: with DEIM the
+# reduced gradient of a column jumps when one of its d sampled particles
+# (each carrying a weight of order N/d) crosses a node, so a column can
+# settle into a cycle at the size of that jump; with the default floor of
+# 1e-3 one column of 1024 occasionally ended a step with ENOCONV.  The leg
+# reports the floor it uses.
+DMD_STALL_TOL = 1e-2
+
+
 def dmd_deim_leg(binding, torch, steps, warmup, p=1024, p_sweep=(300, 1024, 2048)):
     """The DMD-DEIM reduced model (Alg. 2) on the weak Landau damping
     ensemble of Sec. 6.2 (eta = (alpha, sigma), k = 0.5, N = 5e4, N_x = 32,
@@ -274,7 +283,8 @@ def dmd_deim_leg(binding, torch, steps, warmup, p=1024, p_sweep=(300, 1024, 2048
                                   projection="dmd_deim", deim_window=w["deim_window"],
                                   p_star=w["p_star"], deim_rows=w["deim_rows"],
                                   deim_update_every=w["deim_update_every"],
-                                  deim_update_rows=w["deim_update_rows"], fp_tol=1e-9)
+                                  deim_update_rows=w["deim_update_rows"], fp_tol=1e-9,
+                                  fp_stall_tol=DMD_STALL_TOL)
         return w, src, cfg
 
     def rates(w, src, cfg, with_events=False):
@@ -317,6 +327,7 @@ def dmd_deim_leg(binding, torch, steps, warmup, p=1024, p_sweep=(300, 1024, 2048
            "two_n": 6, "p_star": w["p_star"], "deim_rows": w["deim_rows"],
            "deim_window": w["deim_window"], "deim_update_every": w["deim_update_every"],
            "deim_update_rows": w["deim_update_rows"], "loading": "hammersley (quiet start)",
+           "fp_stall_tol": DMD_STALL_TOL,
            "value": pp * steps / t_rom, "unit": "particle-param-steps/s",
            "ms_per_step": 1e3 * t_rom / steps, "mean_fp_iters": info["iters_total"] / steps,
            "stalled_columns": info["stalled_total"], "dmd_rank": rank,
@@ -412,8 +423,8 @@ def main():
 
     torch.cuda.set_device(0)
     if a.dmd_only:
-        print(json.dumps({"dmd_deim": dmd_deim_leg(binding, torch, a.steps, a.warmup,
-                                                   p_sweep=())}), flush=True)
+        print(json.dumps({"dmd_deim": _leg("DMD-DEIM leg", lambda: dmd_deim_leg(
+            binding, torch, a.steps, a.warmup, p_sweep=()))}), flush=True)
         return
     if a.calib_copy_mib:
         src = torch.empty(a.calib_copy_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")

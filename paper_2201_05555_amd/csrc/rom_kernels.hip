@@ -1082,6 +1082,20 @@ __global__ void __launch_bounds__(256) deim_greedy_kernel(
       if (tid < k) cnext[tid] = cs[tid];
     }
   }
+  // The residual scan finds the winner of position k, which the next pass
+  // (or the weights) takes.  A position that inherits its index needs none,
+  // unless that index repeats one chosen before (then dg_choose falls back
+  // to the scan): the same test as dg_choose's, on idx[0..k-2] and this
+  // pass's winner of position k - 1 (idx[k - 1] is being written by block 0).
+  if (forced) {
+    const int f = forced[k];
+    if (f >= 0 && f < N) {
+      bool dup = false;
+      for (int q = 0; q + 1 < k; ++q) dup |= (idx[q] == f);
+      if (k > 0) dup |= (lwin == f);
+      if (!dup) return;
+    }
+  }
   // residual coefficients: r_k = psi_k - sum_q c_q psi_q
   if (tid < 64) cf[tid] = (tid < k) ? -cs[tid] : ((tid == k) ? 1.0 : 0.0);
   __syncthreads();
