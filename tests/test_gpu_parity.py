@@ -322,6 +322,36 @@ def test_rom_full_size_workload_parity():
     _within(_rel(_np(V).T, Vo), sR, "V_r")
 
 
+def test_rom_landau_trajectory_100_steps():
+    """The small Landau workload at its full size (N = 10000, p = 4, N_x = 64,
+    2n = 10, dt = 0.1) over its 100 steps from the oracle's initial state:
+    R = U Z every 10 steps within 50x the oracle's own sensitivity along the
+    same trajectory (its run from Z perturbed by 1e-15), and the first step
+    whose fixed-point iteration count differs, if any, reported."""
+    binding, torch = _b()
+    w, e = _ens("landau_tiny")
+    _say("rom trajectory", w["N"], w["p"], w["Nx"], 100)
+    cfg, st = _oracle_state(w, e, 10, fp_tol=1e-10)
+    rng = np.random.default_rng(0)
+    sp = rom.RomState(U=st.U.copy(), Z=st.Z * (1 + 1e-15 * rng.normal(size=st.Z.shape)),
+                      L=st.L)
+    r = _gpu_rom(binding, w, e, 10, fp_tol=1e-10)
+    _set_from_oracle(r, st, torch)
+    first_mismatch = None
+    for k in range(1, 101):
+        info = r.step(1)
+        assert rom.prk_step(st, cfg) == rom.OK
+        assert rom.prk_step(sp, cfg) == rom.OK
+        if first_mismatch is None and info["iters"] != st.last_iters:
+            first_mismatch = (k, info["iters"], st.last_iters)
+        if k % 10 == 0:
+            X, _ = r.reconstruct()
+            Xo, _ = rom.reconstruct(st)
+            Xp, _ = rom.reconstruct(sp)
+            _within(_rel(_np(X).T, Xo), _rel(Xp, Xo), f"X_r at step {k}")
+    print(f"  first step with a different iteration count: {first_mismatch}", flush=True)
+
+
 def test_rom_enoconv_keeps_state():
     binding, torch = _b()
     w, e = _ens("landau_tiny", N=2000)
