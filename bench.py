@@ -465,7 +465,7 @@ def main():
     two_n_end = rom_h.two_n
     # per-step latency: K further steps, each its own call (the call returns
     # with the step's status read back)
-    lat, stall_rel, stalled = [], 0.0, 0
+    lat, stall_rel, stalled = [], info["stall_rel"], 0
     for _ in range(a.steps):
         t1 = time.perf_counter()
         inf = rom_h.step(1)

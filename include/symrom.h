@@ -110,7 +110,7 @@ typedef struct {
   int32_t iters_total;    /* fixed-point iterations summed over the call      */
   int32_t deim_steps;     /* steps of the call that used the DEIM gradient    */
   double stall_rel;       /* largest relative update accepted by the          */
-                          /* stagnation rule in the last step (0 if none)     */
+                          /* stagnation rule over the call (0 if none)        */
   int32_t stalled_total;  /* stagnation acceptances summed over the call      */
   int32_t shrunk;         /* pairs dropped by the automatic shrink, last step */
   double worst_rel;       /* on ENOCONV: the largest last relative update of  */

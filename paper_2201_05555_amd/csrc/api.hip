@@ -2098,6 +2098,7 @@ extern "C" symrom_status rom_step(symrom_rom* r, int32_t nsteps, symrom_step_inf
   if (!r || nsteps < 0) return fail(SYMROM_EINVAL, "rom_step: bad arguments");
   if (!r->ready) return fail(SYMROM_ESTATE, "rom_step: handle not initialised");
   int64_t iters_total = 0, deim_steps = 0, stalled_total = 0;
+  double stall_max = 0.0;
   r->last.iters_total = 0;
   r->last.deim_steps = 0;
   r->last.stalled_total = 0;
@@ -2108,6 +2109,8 @@ extern "C" symrom_status rom_step(symrom_rom* r, int32_t nsteps, symrom_step_inf
     iters_total += r->last.iters;
     deim_steps += r->last.deim_active;
     stalled_total += r->last.stalled;
+    stall_max = std::max(stall_max, r->last.stall_rel);
+    r->last.stall_rel = stall_max;
     r->last.iters_total = (int32_t)iters_total;
     r->last.deim_steps = (int32_t)deim_steps;
     r->last.stalled_total = (int32_t)stalled_total;
