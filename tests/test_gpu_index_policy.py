@@ -275,6 +275,33 @@ def test_stagnation_counters_match_the_oracle():
         assert info["stall_rel"] < cfg.fp_stall_tol
 
 
+def test_multi_step_call_reports_the_largest_stall_of_the_call():
+    """A call of three steps reports the stall acceptances and iterations
+    summed over its steps and the largest update accepted in any of them:
+    the same as three one-step calls from the same state (deterministic
+    mode, so that the two runs are identical).  With fp_tol = 0 no column
+    converges by the tolerance, so every column ends by the stagnation rule
+    once its updates reach the rounding floor."""
+    binding, torch = _b()
+    w, e = _ens("landau_tiny", N=2000)
+    _say("stall report of a multi-step call")
+    kw = dict(dt=w["dt"], fp_tol=0.0, deterministic=True)
+    ra = binding.Rom(binding.make_config(w["N"], w["p"], w["Nx"], 10, **kw), e["L"], e["X0"],
+                     e["V0"])
+    rb = binding.Rom(binding.make_config(w["N"], w["p"], w["Nx"], 10, **kw), e["L"], e["X0"],
+                     e["V0"])
+    per = [ra.step(1) for _ in range(3)]
+    ib = rb.step(3)
+    rels = " ".join(f"{i['stall_rel']:.2e}" for i in per)
+    print(f"  per step: stalled {[i['stalled'] for i in per]}, stall_rel {rels}; one call: "
+          f"stalled_total {ib['stalled_total']}, stall_rel {ib['stall_rel']:.2e}", flush=True)
+    assert sum(i["stalled"] for i in per) > 0
+    assert ib["stalled_total"] == sum(i["stalled"] for i in per)
+    assert ib["iters_total"] == sum(i["iters"] for i in per)
+    assert ib["stall_rel"] == max(i["stall_rel"] for i in per)
+    assert torch.equal(ra.get_state()[1], rb.get_state()[1])
+
+
 def test_automatic_shrink_matches_the_oracle():
     """rom_adapt_rank(0) with growth ruled out: the pair whose singular value
     of Z~ is 1e-11 of the largest (below rank_tol_down = 1e-8) is dropped,
