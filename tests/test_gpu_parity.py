@@ -480,6 +480,57 @@ def test_rom_deim_rank_auto_parity():
     _within(_rel(_np(V).T, Vo), sR, "V_r")
 
 
+def test_rom_deim_rank_growth_to_the_cap_and_shrink():
+    """A long DEIM run of the two-stream workload with rank adaptation after
+    every step and growth forced (threshold 0): 2n goes from 10 to the cap 60
+    one pair per step, the DEIM operator is rebuilt at each new rank, and at
+    the cap the automatic shrink drops the pairs whose singular value of Z~
+    fell below rank_tol_down.  Ranks and the DEIM switch-over equal the
+    oracle's at every step; fixed-point iteration counts equal it except
+    where a column's last update sits at the tolerance (reported); R after
+    every step within the conditioning-aware bound of the same adaptive run
+    (the oracle's own run from Z perturbed by 1e-15, stepped alongside)."""
+    binding, torch = _b()
+    kw, two_n, two_n_max, steps = dict(N=12000, p=24, Nx=128), 10, 60, 27
+    w, e = _ens("twostream_deim", **kw)
+    _say("rom deim rank growth to the cap", kw, two_n, two_n_max, steps)
+    cfg, st = _oracle_state(w, e, two_n, fp_tol=1e-10, projection="deim", deim_window=3)
+    cfg.two_n_max, cfg.rank_tol_up = two_n_max, 0.0
+    rng = np.random.default_rng(0)
+    s2 = rom.RomState(U=st.U.copy(), Z=st.Z * (1 + 1e-15 * rng.normal(size=st.Z.shape)), L=st.L)
+    c2 = rom.RomConfig(**cfg.__dict__)
+    r = _gpu_rom(binding, w, e, two_n, two_n_max=two_n_max, fp_tol=1e-10, projection="deim",
+                 deim_window=3, rank_auto=True, rank_tol_up=0.0)
+    _set_from_oracle(r, st, torch)
+    ranks, iters_diff, worst = [], [], 0.0
+    for s in range(steps):
+        info = r.step(1)
+        assert rom.prk_step(st, cfg) == rom.OK
+        _, two_n_o, _ = rom.adapt_rank(st, cfg, 0)
+        assert rom.prk_step(s2, c2) == rom.OK
+        rom.adapt_rank(s2, c2, 0)
+        assert info["two_n"] == two_n_o, (s, info, two_n_o)
+        assert info["deim_active"] == (1 if s >= 3 else 0), (s, info)
+        ranks.append(two_n_o)
+        if info["iters"] != st.last_iters:
+            iters_diff.append((s, info["iters"], st.last_iters))
+        Ro = st.U @ st.Z
+        sR = _rel(s2.U @ s2.Z, Ro)
+        X, V = r.reconstruct()
+        Xo, Vo = rom.reconstruct(st)
+        eX, eV = _rel(_np(X).T, Xo), _rel(_np(V).T, Vo)
+        bound = max(1e-9, _bound(sR))
+        worst = max(worst, max(eX, eV) / bound)
+        if s % 3 == 2 or s == steps - 1:
+            print(f"  step {s + 1:2d}: 2n {two_n_o}  err X {eX:.2e} V {eV:.2e}  oracle "
+                  f"sensitivity {sR:.2e}  bound {bound:.2e}", flush=True)
+        assert eX < bound and eV < bound, (s, eX, eV, sR, bound)
+    print(f"  ranks {ranks}; steps with another iteration count: {iters_diff}; largest "
+          f"error / bound {worst:.2f}", flush=True)
+    assert max(ranks) == two_n_max and ranks[-1] < two_n_max   # grown to the cap, then shrunk
+    assert len(iters_diff) <= 2 and all(abs(a - b) == 1 for _, a, b in iters_diff)
+
+
 @pytest.mark.parametrize("kw,two_n,two_n_max,steps", [
     (dict(N=20000, p=24, Nx=128), 8, 8, 6),
     (dict(N=30000, p=64, Nx=128), 10, 60, 6),     # the two-stream workload's DEIM shape
