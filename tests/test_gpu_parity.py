@@ -299,27 +299,46 @@ def test_rom_steps_parity_adaptive(name, kw, two_n, steps):
     assert _rel(_np(H), Ho) < _bound(sR)
 
 
-def test_rom_full_size_workload_parity():
-    """The benchmark's own shapes (N = 100000, p = 64, Nx = 128, 2n = 10, the
-    launch configuration bench.py times): two steps from the oracle's
-    initial state with identical iteration counts, and R = U Z on every row
-    within the conditioning-aware bound."""
+@pytest.mark.parametrize("proj,steps", [("galerkin", 2), ("deim", 5)])
+def test_rom_full_size_workload_parity(proj, steps):
+    """The two-stream workload at its full size (N = 100000, p = 64, Nx = 128,
+    2n = 10, the launch configuration bench.py times for it): steps from the
+    oracle's initial state with identical iteration counts, and R = U Z on
+    every row within the conditioning-aware bound.  With DEIM (T = 3) the
+    last two steps use the DEIM gradient."""
     binding, torch = _b()
     w, e = _ens("twostream_deim")
-    _say("rom full size", w["N"], w["p"], w["Nx"])
-    cfg, st = _oracle_state(w, e, 10, fp_tol=1e-10)
+    _say("rom full size", w["N"], w["p"], w["Nx"], proj, steps)
+    kw = dict(fp_tol=1e-10) if proj == "galerkin" else dict(fp_tol=1e-10, projection="deim",
+                                                            deim_window=3)
+    cfg, st = _oracle_state(w, e, 10, **kw)
     st_s = rom.RomState(U=st.U.copy(), Z=st.Z.copy(), L=st.L)
-    sU, sZ, sR = _oracle_sensitivity(st_s, cfg, 6, steps=2)
-    r = _gpu_rom(binding, w, e, 10, fp_tol=1e-10)
+    if proj == "galerkin":
+        sU, sZ, sR = _oracle_sensitivity(st_s, cfg, 6, steps=steps)
+    else:
+        # the adaptive run itself (the DEIM switch-over needs the window)
+        rng = np.random.default_rng(0)
+        s2 = rom.RomState(U=st.U.copy(), Z=st.Z * (1 + 1e-15 * rng.normal(size=st.Z.shape)),
+                          L=st.L)
+        c2 = rom.RomConfig(**cfg.__dict__)
+        for _ in range(steps):
+            assert rom.prk_step(s2, c2) == rom.OK
+    r = _gpu_rom(binding, w, e, 10, **kw)
     _set_from_oracle(r, st, torch)
-    for s in range(2):
+    for s in range(steps):
         info = r.step(1)
         assert rom.prk_step(st, cfg) == rom.OK
         assert info["iters"] == st.last_iters, (s, info, st.last_iters)
+        assert info["deim_active"] == (1 if proj == "deim" and s >= 3 else 0), (s, info)
+    if proj != "galerkin":
+        sR = _rel(s2.U @ s2.Z, st.U @ st.Z)
     X, V = r.reconstruct()
     Xo, Vo = rom.reconstruct(st)
-    _within(_rel(_np(X).T, Xo), sR, "X_r")
-    _within(_rel(_np(V).T, Vo), sR, "V_r")
+    # DEIM: the floor of the other DEIM tests (basis from the snapshot Gram's
+    # eigenpairs here, from an SVD of the snapshots in the oracle)
+    floor = RTOL if proj == "galerkin" else 1e-9
+    _within(_rel(_np(X).T, Xo), sR, "X_r", floor=floor)
+    _within(_rel(_np(V).T, Vo), sR, "V_r", floor=floor)
 
 
 def test_rom_landau_trajectory_100_steps():
