@@ -45,7 +45,9 @@ __host__ __device__ inline double cabs2(cplx a) { return a.re * a.re + a.im * a.
 // Particle-to-cell lookup of the periodic P1 mesh.  s = x * (Nx / L) with the
 // factor formed once in FP64 on the host; c = floor(s); theta = s - c (exact);
 // node j = c mod Nx (Euclidean).  A particle on a node takes the cell to its
-// right.  Valid for unwrapped positions with |s| < 2^52.  Branch-free, so
+// right.  Exact for unwrapped positions with |s| < 2^52.  Beyond that, and for
+// a non-finite position (a diverged state), the cell is still some j in
+// [0, Nx), so that no lookup or deposit leaves its table.  Branch-free, so
 // that the cells of several particles of a thread interleave.
 __device__ inline void cell_of(double x, double factor, int Nx, int& j, double& theta) {
   const double s = x * factor;
@@ -58,6 +60,8 @@ __device__ inline void cell_of(double x, double factor, int Nx, int& j, double& 
   double r = fma(-q, fNx, c);
   r = (r < 0.0) ? r + fNx : r;
   r = (r >= fNx) ? r - fNx : r;
+  // (no effect in the exact range; fmax takes 0 for a NaN)
+  r = fmin(fmax(r, 0.0), fNx - 1.0);
   j = (int)r;
 }
 

@@ -68,6 +68,29 @@ def test_pic_fields_node_ties():
     assert np.array_equal(_np(cells).T, j.astype(np.int32))
 
 
+def test_pic_fields_positions_out_of_the_exact_range():
+    """Positions of a diverged state (NaN, infinite, or beyond 2^52 cells)
+    still get a cell in [0, Nx): the deposit and every lookup stay inside
+    their tables, and the other parameters' charge and field are untouched."""
+    binding, torch = _b()
+    _say("pic_fields positions out of the exact range")
+    w, e = _ens("landau_tiny", N=1000)
+    L = np.array([e["L"][0]] * 3)
+    X = np.stack([e["X0"][:, 0]] * 3, axis=1)
+    X[:12, 1] = [np.nan, -np.nan, np.inf, -np.inf, 1e300, -1e300, 1.2345e17, -9.87e16,
+                 2.0 ** 60, -(2.0 ** 58), 1e20, -3e19]
+    cells, rho, Phi, ef = binding.pic_fields(X, L, w["Nx"])
+    torch.cuda.synchronize()
+    c = _np(cells)
+    assert c.min() >= 0 and c.max() < w["Nx"]
+    Xo = X[:, [0, 2]]
+    j, _ = pic.cell_index(Xo, L[[0, 2]], w["Nx"])
+    assert np.array_equal(c[[0, 2]].T, j.astype(np.int32))
+    rho_o, Phi_o, e_o = pic.fields_of(Xo, L[[0, 2]], w["Nx"])
+    assert _rel(_np(rho)[[0, 2]].T, rho_o) < 1e-12
+    assert _rel(_np(ef)[[0, 2]].T, e_o) < 1e-10
+
+
 @pytest.mark.parametrize("name,kw,steps", [
     ("landau_tiny", dict(N=4099), 20),
     ("twostream_deim", dict(N=30000, p=12, Nx=128), 10),
