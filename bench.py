@@ -89,6 +89,10 @@ def parse():
     ap.add_argument("--serve-step-scale", type=float, default=0.25)
     ap.add_argument("--serve-gap", type=float, default=1.0, help="mean inter-arrival (s)")
     ap.add_argument("--no-dmd", action="store_true", help="skip the DMD-DEIM leg")
+    ap.add_argument("--no-restart", action="store_true",
+                    help="skip the two-stream restart at t = 30 (Sec. 6.4)")
+    ap.add_argument("--restart-only", action="store_true",
+                    help="run only the two-stream restart leg and print its result")
     ap.add_argument("--dmd-only", action="store_true",
                     help="run only the DMD-DEIM leg (at p = 1024, no sweep) and print its line")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -257,6 +261,13 @@ def matched_error(binding, torch, w, src, cfg, steps):
 # 1e-3 one column of 1024 occasionally ended a step with ENOCONV.  The leg
 # reports the floor it uses.
 DMD_STALL_TOL = 1e-2
+# The floor for the DMD-DEIM runs of the restart leg (ranks 8 to 24 of the
+# two-stream ensemble at t = 30, d = 64 sampled rows): single columns cycle
+# at a few per cent there (with a floor of 1e-2 the 2n = 12 run ended with
+# ENOCONV after about 100 steps; with d = 32 cycles of 10-20 % ended every
+# run from 2n = 12 on within 50-520 steps); the largest update accepted is
+# reported.
+RESTART_DMD_STALL_TOL = 1e-1
 
 
 def dmd_deim_leg(binding, torch, steps, warmup, p=1024, p_sweep=(300, 1024, 2048)):
@@ -409,6 +420,108 @@ def serve_bench(binding, torch, n_req, step_scale, slots, pool_gb, mean_gap_s, s
                    "rank adaptation to 60, Poisson arrivals"}
 
 
+def restart_leg(binding, torch, ranks=(8, 12, 18, 24), steps=2000, every=500):
+    """The restart of Sec. 6.4: the two-stream instability ensemble (eta =
+    (alpha, sigma), N = 1.5e5, p = 300, N_x = 64, dt = 0.0025) is run with the
+    full-order model to t = 30, where a rank 2n <= 8 no longer follows the
+    dynamics; the reduced model is started again there from the truncated
+    complex SVD of the full-order state at each rank 2n in ``ranks``, with
+    the Galerkin projection and with DMD-DEIM (T = 3, p* = 8, d = 64 rows, a
+    full greedy every 3rd step), and run ``steps`` further steps beside the
+    full-order
+    model.  Reported every ``every`` steps: eq. relative_errors of each run
+    and the complex-SVD target error of eq. relative_errors_complex_SVD at
+    that rank; a run that fails reports its status."""
+    from workloads import workload, particle_uniforms
+    from workloads.ensembles import draw_parameters, parameter_matrix
+    w = workload("twostream_tsi")
+    N, p, Nx, dt = w["N"], w["p"], w["Nx"], w["dt"]
+    params = draw_parameters(w)
+    ux, uv = particle_uniforms(w)
+    n0 = int(round(w["restart_t"] / dt))
+    f = binding.Fom(N, p, Nx, dt, None, None, None, family=w["family"], params=params, ux=ux,
+                    uv=uv)
+    f.step(n0)
+    X0, V0 = f.get_state()
+    cps = []
+    for _ in range(steps // every):
+        f.step(every)
+        cps.append(f.get_state())
+    f.close()
+    del f
+    L = params["L"]
+    eta = parameter_matrix(params)
+    times = [w["restart_t"] + every * dt * (c + 1) for c in range(len(cps))]
+    out = {"workload": "twostream_tsi", "N": N, "p": p, "Nx": Nx, "dt": dt,
+           "t_restart": w["restart_t"], "times": times, "ranks": list(ranks),
+           "p_star": w["p_star"], "deim_window": w["deim_window"], "deim_rows": w["deim_rows"],
+           "deim_update_every": w["deim_update_every"],
+           "deim_update_rows": w["deim_update_rows"]}
+
+    def target(tn):
+        ex, ev = [], []
+        for Xc, Vc in [(X0, V0)] + cps:
+            t_h = binding.Rom(binding.make_config(N, p, Nx, tn, dt=dt), L, Xc, Vc)
+            Xt, Vt = t_h.reconstruct()
+            t_h.close()
+            ex.append(_frob_rel_err(torch, Xc, Xt))
+            ev.append(_frob_rel_err(torch, Vc, Vt))
+            del Xt, Vt
+        return {"eps_rel_X": ex, "eps_rel_V": ev, "note": "first entry at t_restart"}
+
+    def run(proj, tn):
+        cfg = binding.make_config(N, p, Nx, tn, two_n_max=tn, dt=dt, projection=proj,
+                                  deim_window=w["deim_window"], p_star=w["p_star"],
+                                  deim_rows=w["deim_rows"],
+                                  deim_update_every=w["deim_update_every"],
+                                  deim_update_rows=w["deim_update_rows"], fp_tol=1e-9,
+                                  fp_stall_tol=RESTART_DMD_STALL_TOL if proj == "dmd_deim"
+                                  else 1e-3)
+        r = binding.Rom(cfg, L, X0, V0)
+        if proj == "dmd_deim":
+            r.set_parameters(eta)
+        ex, ev, t_steps, iters, stalled, srel, fail = [], [], 0.0, 0, 0, 0.0, None
+        try:
+            for Xc, Vc in cps:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, info = r.step_status(every)
+                torch.cuda.synchronize()
+                if st == 0:
+                    t_steps += time.perf_counter() - t0
+                    iters += info["iters_total"]
+                stalled += info["stalled_total"]
+                srel = max(srel, info["stall_rel"])
+                if st != 0:
+                    # the state is the one before the failing step
+                    fail = {"status": binding.lib().symrom_status_string(st).decode(),
+                            "after_steps": r.get_state()[2],
+                            "worst_rel": info["worst_rel"], "unconverged": info["unconverged"]}
+                    break
+                Xm, Vm = r.reconstruct()
+                ex.append(_frob_rel_err(torch, Xc, Xm))
+                ev.append(_frob_rel_err(torch, Vc, Vm))
+                del Xm, Vm
+        finally:
+            r.close()
+        n = max(1, every * len(ex))
+        out = {"eps_rel_X": ex, "eps_rel_V": ev, "ms_per_step": 1e3 * t_steps / n,
+               "mean_fp_iters": iters / n, "stalled_columns": stalled,
+               "max_stall_accepted_update": srel, "fp_stall_tol": cfg.fp_stall_tol}
+        if fail:
+            out["failed_step"] = fail
+        return out
+
+    out["target"] = {str(tn): _leg(f"restart target 2n = {tn}", lambda tn=tn: target(tn))
+                     for tn in ranks}
+    for proj in ("galerkin", "dmd_deim"):
+        out[proj] = {str(tn): _leg(f"restart {proj} 2n = {tn}", lambda tn=tn: run(proj, tn))
+                     for tn in ranks}
+    del X0, V0, cps
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -422,6 +535,10 @@ def main():
     from workloads.ensembles import draw_parameters, load_particles, philox_uniforms
 
     torch.cuda.set_device(0)
+    if a.restart_only:
+        print(json.dumps({"restart": _leg("restart leg", lambda: restart_leg(binding, torch))}),
+              flush=True)
+        return
     if a.dmd_only:
         print(json.dumps({"dmd_deim": _leg("DMD-DEIM leg", lambda: dmd_deim_leg(
             binding, torch, a.steps, a.warmup, p_sweep=()))}), flush=True)
@@ -588,6 +705,8 @@ def main():
     if not a.no_dmd:
         out["dmd_deim"] = _leg("DMD-DEIM leg", lambda: dmd_deim_leg(binding, torch, a.steps,
                                                                      a.warmup))
+    if not a.no_restart:
+        out["restart"] = _leg("restart leg", lambda: restart_leg(binding, torch))
     if not a.no_serve:
         out["serve"] = _leg("serving mix", lambda: serve_bench(
             binding, torch, a.serve_requests, a.serve_step_scale, 4, 96.0, a.serve_gap))

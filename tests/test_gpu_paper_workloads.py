@@ -1,0 +1,74 @@
+"""The paper's workloads as validation of the GPU library (no oracle: the
+reduced model against the full-order model on the device, both checked
+against the oracle elsewhere).
+
+* The restart of Sec. 6.4: the two-stream instability ensemble run to t = 30
+  with the full-order model, where a small rank no longer follows the
+  dynamics, and the reduced model started again there from the truncated
+  complex SVD of the full-order state: the error against the full-order model
+  falls with the rank, and stays within a small factor of the complex-SVD
+  target error (eq. relative_errors_complex_SVD) of the same rank.  The
+  target is the best rank-n approximation of X + iV, so it bounds the
+  combined error of X and V from below (not each part alone).
+"""
+import numpy as np
+import pytest
+
+from workloads import particle_uniforms, workload
+from workloads.ensembles import draw_parameters
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _frob(torch, A, B):
+    return float(torch.linalg.norm(A - B) / torch.linalg.norm(A))
+
+
+def _frob2(torch, A, B, C, D):
+    """|| [A; C] - [B; D] ||_F / || [A; C] ||_F"""
+    num = torch.linalg.norm(A - B) ** 2 + torch.linalg.norm(C - D) ** 2
+    return float(torch.sqrt(num / (torch.linalg.norm(A) ** 2 + torch.linalg.norm(C) ** 2)))
+
+
+def test_restart_at_t30_error_falls_with_the_rank():
+    import torch
+    from paper_2201_05555_amd import binding
+    assert torch.cuda.is_available()
+    w = workload("twostream_tsi", N=30000, p=32)
+    N, p, Nx, dt = w["N"], w["p"], w["Nx"], w["dt"]
+    _say("restart at t = 30", N, p, Nx, dt)
+    params = draw_parameters(w)
+    ux, uv = particle_uniforms(w)
+    f = binding.Fom(N, p, Nx, dt, None, None, None, family=w["family"], params=params, ux=ux,
+                    uv=uv)
+    f.step(int(round(w["restart_t"] / dt)))
+    X0, V0 = f.get_state()
+    steps = 400
+    f.step(steps)
+    Xf, Vf = f.get_state()
+    f.close()
+    ranks, errs, targets = (8, 16, 24), [], []
+    for tn in ranks:
+        r = binding.Rom(binding.make_config(N, p, Nx, tn, dt=dt, fp_tol=1e-9), params["L"], X0,
+                        V0)
+        r.step(steps)
+        X, V = r.reconstruct()
+        r.close()
+        t = binding.Rom(binding.make_config(N, p, Nx, tn, dt=dt), params["L"], Xf, Vf)
+        Xt, Vt = t.reconstruct()
+        t.close()
+        errs.append((_frob(torch, Xf, X), _frob(torch, Vf, V), _frob2(torch, Xf, X, Vf, V)))
+        targets.append((_frob(torch, Xf, Xt), _frob(torch, Vf, Vt),
+                        _frob2(torch, Xf, Xt, Vf, Vt)))
+        print(f"  2n {tn}: eps_rel X {errs[-1][0]:.3e} V {errs[-1][1]:.3e} both "
+              f"{errs[-1][2]:.3e}  target X {targets[-1][0]:.3e} V {targets[-1][1]:.3e} both "
+              f"{targets[-1][2]:.3e}", flush=True)
+    ex, ev, eb = np.array(errs).T
+    assert np.all(np.diff(ex) < 0) and np.all(np.diff(ev) < 0)
+    for (e_x, e_v, e_b), (t_x, t_v, t_b) in zip(errs, targets):
+        assert t_b <= e_b < 2.0 * t_b
+        assert e_x < 2.0 * t_x and e_v < 2.0 * t_v

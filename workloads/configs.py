@@ -47,6 +47,18 @@ WORKLOADS = {
         deim_rows=32, deim_update_every=3, deim_update_rows=12, loading="hammersley",
         ranges=dict(alpha=(0.03, 0.06), sigma=(0.8, 1.0)), k=0.5,
     ),
+    # the two-stream instability experiment of Sec. 6.4: eta = (alpha, sigma),
+    # v0 = 3 and k = 0.2 fixed, N = 1.5e5, N_x = 64, dt = 0.0025; the
+    # reduced model restarted at t = 30 from the full-order state with
+    # larger ranks (DMD-DEIM with T = 3, p* = 8, d = 64, a full greedy every
+    # 3rd step)
+    "twostream_tsi": dict(
+        number=7, family="twostream", N=150_000, p=300, Nx=64, steps=8000, dt=0.0025,
+        two_n=8, two_n_max=24, projection="dmd_deim", deim_window=3, p_star=8,
+        deim_rows=64, deim_update_every=3, deim_update_rows=24, v0=3.0,
+        ranges=dict(alpha=(0.009, 0.011), sigma=(0.98, 1.02)), k=0.2,
+        restart_t=30.0,
+    ),
 }
 
 
