@@ -34,6 +34,9 @@ PINS = {
     "rom.rank_grow": "R bitwise unchanged (zero coefficient rows)",
     "rom.rank_shrink": "removed energy equals dropped singular values",
     "rom.rank_indicator": "identity ||(I - U U^T) J G||^2 = ||G||^2 - ||g||^2",
+    "rom.local_singular_values / numerical_rank": "a matrix built with prescribed singular "
+                                                  "values (random orthogonal factors); rank "
+                                                  "counts by hand",
     "rom.rank_policy": "parity unpinned (grow/shrink thresholds are a reading; the paper defers "
                        "rank adaptation)",
     "rom.fixed_point_stagnation": "parity unpinned (a reading); the floor is pinned by a planted "

@@ -163,6 +163,19 @@ def init_csvd(X0, V0, two_n):
     return from_complex_basis(Ut), from_complex_coeff(Zt)
 
 
+def local_singular_values(S):
+    """Singular values, decreasing, of a local snapshot matrix S^tau = [X^1
+    ... X^p] (or of the velocities) of eq. local_snapshots (Sec. 6.1)."""
+    return np.linalg.svd(np.asarray(S), compute_uv=False)
+
+
+def numerical_rank(sig, tol):
+    """The numerical rank of Sec. 6.1: the number of singular values above
+    tol times the largest."""
+    sig = np.asarray(sig, dtype=np.float64)
+    return int(np.sum(sig > tol * sig[0])) if sig.size else 0
+
+
 def init_state(X0, V0, L, cfg, eta=None):
     U, Z = init_csvd(X0, V0, cfg.two_n)
     st = RomState(U=U, Z=Z, L=np.asarray(L, dtype=np.float64).copy())

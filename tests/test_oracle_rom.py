@@ -418,3 +418,25 @@ def test_stagnation_accepts_a_cycle_with_a_contracted_phase(monkeypatch):
     cfg2 = rom.RomConfig(**{**cfg.__dict__, "fp_stall_tol": 1e-12})
     s2 = rom.RomState(U=st.U.copy(), Z=st.Z.copy(), L=st.L)
     assert rom.prk_step(s2, cfg2) == rom.ENOCONV
+
+
+def test_local_singular_values_and_numerical_rank():
+    """eq. local_snapshots and the numerical rank of Sec. 6.1: a snapshot
+    matrix built from random orthogonal factors and prescribed singular values
+    gives those values back, in decreasing order, and the rank counts the
+    values strictly above tol times the largest (hand-counted)."""
+    rng = np.random.default_rng(7)
+    N, p = 200, 12
+    sig = np.array([3.0, 1.0, 0.5, 2e-3, 1e-3, 5e-4, 1e-5, 5e-6, 1e-8, 0, 0, 0])
+    Uq, _ = np.linalg.qr(rng.normal(size=(N, p)))
+    Vq, _ = np.linalg.qr(rng.normal(size=(p, p)))
+    order = rng.permutation(p)             # columns of the factor in another order
+    S = (Uq * sig[order]) @ Vq.T
+    s = rom.local_singular_values(S)
+    np.testing.assert_allclose(s, sig, rtol=0, atol=1e-14 * sig[0])
+    assert rom.numerical_rank(s, 1e-3) == 3   # above 3e-3: 3, 1, 0.5
+    assert rom.numerical_rank(s, 1e-4) == 6   # above 3e-4: and 2e-3, 1e-3, 5e-4
+    assert rom.numerical_rank(s, 1e-5) == 6   # 1e-5 is below 3e-5
+    assert rom.numerical_rank(s, 1e-6) == 8   # above 3e-6: and 1e-5, 5e-6
+    assert rom.numerical_rank(s, 1.0) == 0    # strictly above the largest: none
+    assert rom.numerical_rank([], 1e-3) == 0
