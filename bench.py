@@ -90,9 +90,10 @@ def parse():
     ap.add_argument("--serve-gap", type=float, default=1.0, help="mean inter-arrival (s)")
     ap.add_argument("--no-dmd", action="store_true", help="skip the DMD-DEIM leg")
     ap.add_argument("--no-restart", action="store_true",
-                    help="skip the two-stream restart at t = 30 (Sec. 6.4)")
+                    help="skip the two-stream restart at t = 30 (Sec. 6.4) and the local-rank "
+                         "study (Sec. 6.1)")
     ap.add_argument("--restart-only", action="store_true",
-                    help="run only the two-stream restart leg and print its result")
+                    help="run only the restart and local-rank legs and print their results")
     ap.add_argument("--dmd-only", action="store_true",
                     help="run only the DMD-DEIM leg (at p = 1024, no sweep) and print its line")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -522,6 +523,51 @@ def restart_leg(binding, torch, ranks=(8, 12, 18, 24), steps=2000, every=500):
     return out
 
 
+def local_rank_leg(binding, torch, p=64, every=400, tols=(1e-3, 1e-4, 1e-5)):
+    """The local-rank study of Sec. 6.1 (eq. local_snapshots) on the
+    full-order solutions of the weak Landau damping (Sec. 6.2) and the
+    two-stream instability (Sec. 6.4) ensembles at p parameters, over the
+    paper's interval (0, 20]: every ``every`` steps the singular values of
+    S_X^tau = [X^1 ... X^p] and of S_V^tau, found by the library's
+    initialisation (rom_init of C0 = X + 0 i, all p values for p <= 64), and
+    the numerical ranks at each tolerance (values above tol * sigma_1).
+    Positions are the unwrapped ones the reduced model represents."""
+    import numpy as np
+    from workloads import workload, particle_uniforms
+    from workloads.ensembles import draw_parameters
+    out = {"p": p, "every_steps": every, "tolerances": list(tols),
+           "definition": "number of singular values of S_X^tau (S_V^tau) above tol * sigma_1"}
+    for name in ("landau_ld", "twostream_tsi"):
+        w = workload(name, p=p)
+        N, Nx, dt = w["N"], w["Nx"], w["dt"]
+        params = draw_parameters(w)
+        ux, uv = particle_uniforms(w)
+        f = binding.Fom(N, p, Nx, dt, None, None, None, family=w["family"], params=params, ux=ux,
+                        uv=uv)
+        nsteps = int(round(20.0 / dt))
+        times, rx, rv = [], [], []
+        for k in range(0, nsteps + 1, every):
+            if k:
+                f.step(every)
+            X, V = f.get_state()
+            ranks = []
+            for S in (X, V):
+                r = binding.Rom(binding.make_config(N, p, Nx, 2, dt=dt), params["L"], S,
+                                torch.zeros_like(S))
+                sg = r.init_singular_values()
+                r.close()
+                ranks.append([int(np.sum(sg > t * sg[0])) for t in tols])
+            del X, V
+            times.append(k * dt)
+            rx.append(ranks[0])
+            rv.append(ranks[1])
+        f.close()
+        del f
+        torch.cuda.empty_cache()
+        out[name] = {"N": N, "Nx": Nx, "dt": dt, "times": times, "rank_X": rx, "rank_V": rv}
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -536,7 +582,9 @@ def main():
 
     torch.cuda.set_device(0)
     if a.restart_only:
-        print(json.dumps({"restart": _leg("restart leg", lambda: restart_leg(binding, torch))}),
+        print(json.dumps({"restart": _leg("restart leg", lambda: restart_leg(binding, torch)),
+                          "local_rank": _leg("local rank leg",
+                                             lambda: local_rank_leg(binding, torch))}),
               flush=True)
         return
     if a.dmd_only:
@@ -707,6 +755,7 @@ def main():
                                                                      a.warmup))
     if not a.no_restart:
         out["restart"] = _leg("restart leg", lambda: restart_leg(binding, torch))
+        out["local_rank"] = _leg("local rank leg", lambda: local_rank_leg(binding, torch))
     if not a.no_serve:
         out["serve"] = _leg("serving mix", lambda: serve_bench(
             binding, torch, a.serve_requests, a.serve_step_scale, 4, 96.0, a.serve_gap))

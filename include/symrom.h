@@ -260,6 +260,17 @@ symrom_status rom_set_parameters(symrom_rom* h, const double* eta, int32_t dim);
 symrom_status rom_dmd_state(symrom_rom* h, int32_t* S, int32_t* pstar, int32_t* rank, double* lam,
                             double* e0, double* eh);
 
+/* Singular values of the initial state C0 = X0 + i V0 (N x p) that
+ * rom_init or rom_init_family decomposed (the complex SVD of the
+ * initialisation, Sec. 6.1), in decreasing order, as the square roots of the
+ * eigenvalues of C0^* C0: all p of them for p <= 64, the n = two_n/2
+ * leading ones beyond.  With V0 = 0 they are the singular values of the
+ * local snapshot matrix S_X = [X^1 ... X^p] of eq. local_snapshots, whose
+ * count above tol * sigma_1 is the numerical rank of Sec. 6.1 (values below
+ * about 1e-7 sigma_1 are not resolved through the Gram).  sig: host, up to
+ * cap values written; *m: the number available.  Errors: EINVAL. */
+symrom_status rom_init_singular_values(symrom_rom* h, double* sig, int32_t cap, int32_t* m);
+
 /* Per-parameter electric energy E(X_r^i) (eq. HamEEfull) and Hamiltonian
  * H = 1/2 |V_r^i|^2 + E (device [p] each). */
 symrom_status rom_diagnostics(symrom_rom* h, double* E, double* H);

@@ -96,6 +96,8 @@ _SIGS = {
     "deim_select": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP, _VP,
                                      ctypes.c_size_t, _VP]),
     "rom_diagnostics": (ctypes.c_int32, [_VP, _VP, _VP]),
+    "rom_init_singular_values": (ctypes.c_int32, [_VP, _VP, ctypes.c_int32,
+                                                  ctypes.POINTER(ctypes.c_int32)]),
     "rom_gradient": (ctypes.c_int32, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "rom_destroy": (None, [_VP]),
     "fom_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32] * 3),
@@ -365,6 +367,16 @@ class Rom:
         d = ctypes.c_int32()
         _check(lib().rom_deim_operator(self.h, _ptr(idx), _ptr(w), ctypes.byref(d)))
         return idx[: d.value], w[: d.value]
+
+    def init_singular_values(self):
+        """Singular values (numpy, decreasing) of the initial state the
+        handle decomposed: all p for p <= 64, the n leading ones beyond."""
+        m = ctypes.c_int32()
+        _check(lib().rom_init_singular_values(self.h, None, 0, ctypes.byref(m)))
+        sig = np.zeros(max(1, m.value), dtype=np.float64)
+        _check(lib().rom_init_singular_values(self.h, sig.ctypes.data_as(ctypes.c_void_p),
+                                              m.value, ctypes.byref(m)))
+        return sig[: m.value]
 
     def set_parameters(self, eta):
         """Parameters of the ensemble (dim x p host array, e.g. rows alpha, k,

@@ -665,6 +665,7 @@ struct symrom_rom {
   cplx* Wsub;    // its p x 64 block of vectors (p > 64)
   double* lamsub;
   symrom_step_info last;
+  std::vector<double> init_sig;  // singular values of C0 found by the initialisation
 };
 
 namespace {
@@ -1881,6 +1882,13 @@ symrom_status rom_init_impl(const symrom_config* cfg, const double* L,
     delete r;
     return fail(SYMROM_EDEVICE, "rom_init: eigen readback");
   }
+  // the singular values of C0 (all p by Jacobi; the n converged leading ones
+  // of the subspace iteration beyond 64)
+  {
+    const int ns = (p <= 64) ? nl : std::min(nl, n);
+    r->init_sig.resize(ns);
+    for (int j = 0; j < ns; ++j) r->init_sig[j] = std::sqrt(std::max(lam[j], 0.0));
+  }
   // The basis: the leading eigenpairs of C0^* C0 (U = C0 V lam^{-1/2}),
   // completed by Gram-Schmidt of e_0, e_1, ..., then two Cholesky-QR passes
   // and Z = U^* C0.  Eigenpairs far below the largest are not resolved by
@@ -2492,6 +2500,16 @@ extern "C" symrom_status rom_gradient(symrom_rom* r, const double* Z, double* g,
   if (e) HIPCHK(hipMemcpyAsync(e, r->b.e, gb, hipMemcpyDeviceToDevice, s));
   LAUNCHCHK();
   HIPCHK(hipStreamSynchronize(s));
+  return SYMROM_OK;
+}
+
+extern "C" symrom_status rom_init_singular_values(symrom_rom* r, double* sig, int32_t cap,
+                                                  int32_t* m) {
+  if (!r || !m || cap < 0 || (cap > 0 && !sig))
+    return fail(SYMROM_EINVAL, "rom_init_singular_values: bad arguments");
+  const int ns = (int)r->init_sig.size();
+  for (int j = 0; j < std::min(ns, (int)cap); ++j) sig[j] = r->init_sig[j];
+  *m = ns;
   return SYMROM_OK;
 }
 

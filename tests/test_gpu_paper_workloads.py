@@ -72,3 +72,42 @@ def test_restart_at_t30_error_falls_with_the_rank():
     for (e_x, e_v, e_b), (t_x, t_v, t_b) in zip(errs, targets):
         assert t_b <= e_b < 2.0 * t_b
         assert e_x < 2.0 * t_x and e_v < 2.0 * t_v
+
+
+@pytest.mark.parametrize("p,two_n", [(16, 10), (80, 60)])
+def test_local_singular_values_match_the_oracle(p, two_n):
+    """The singular values of a local snapshot matrix S_X^tau (eq.
+    local_snapshots) as the library's initialisation finds them (rom_init
+    of C0 = X + 0 i; all of them for p <= 64, the n leading ones of the
+    subspace iteration beyond) against the oracle's SVD of the same matrix,
+    in squares within 1e-12 of the largest, and the numerical ranks of Sec.
+    6.1 at the paper's tolerances equal."""
+    import torch
+    from oracle import rom
+    from paper_2201_05555_amd import binding
+    assert torch.cuda.is_available()
+    w = workload("twostream_tsi", N=20000, p=p)
+    N, Nx, dt = w["N"], w["Nx"], w["dt"]
+    _say("local singular values", N, p, two_n)
+    params = draw_parameters(w)
+    ux, uv = particle_uniforms(w)
+    f = binding.Fom(N, p, Nx, dt, None, None, None, family=w["family"], params=params, ux=ux,
+                    uv=uv)
+    f.step(400)
+    X, V = f.get_state()
+    f.close()
+    for name, S in (("X", X), ("V", V)):
+        r = binding.Rom(binding.make_config(N, p, Nx, two_n, dt=dt), params["L"], S,
+                        torch.zeros_like(S))
+        sg = r.init_singular_values()
+        r.close()
+        so = rom.local_singular_values(S.cpu().numpy().T)
+        m = len(sg)
+        assert m == (p if p <= 64 else two_n // 2)
+        err = np.max(np.abs(sg ** 2 - so[:m] ** 2)) / so[0] ** 2
+        ranks = [(rom.numerical_rank(sg, t), rom.numerical_rank(so, t)) for t in (1e-3, 1e-4, 1e-5)]
+        print(f"  S_{name}: {m} values, max |sg^2 - so^2| / s1^2 = {err:.2e}, ranks at 1e-3, "
+              f"1e-4, 1e-5 (GPU, oracle): {ranks}", flush=True)
+        assert err < 1e-12
+        for a, b in ranks:
+            assert a == b or (a == m and b >= m)
