@@ -37,6 +37,9 @@ PINS = {
     "rom.local_singular_values / numerical_rank": "a matrix built with prescribed singular "
                                                   "values (random orthogonal factors); rank "
                                                   "counts by hand",
+    "rom.hamiltonian_split": "complete basis (2n = 2N): the basis does not move, both basis "
+                             "terms vanish; the end rows equal the Hamiltonians of the states "
+                             "before and after the step",
     "rom.rank_policy": "parity unpinned (grow/shrink thresholds are a reading; the paper defers "
                        "rank adaptation)",
     "rom.fixed_point_stagnation": "parity unpinned (a reading); the floor is pinned by a planted "

@@ -130,6 +130,8 @@ class RomState:
     last_dmd_rank: int = 0
     last_dmd: object = None                 # DMD operator of the last DMD-DEIM step
     last_dmd_tables: object = None          # its field tables (e at t_{tau-1}, at + dt/2)
+    last_U_half: Optional[np.ndarray] = None   # U_{tau-1/2} of the last Galerkin/DEIM step
+    last_Z_new: Optional[np.ndarray] = None    # Z_tau of that step, before re-orthonormalisation
 
 
 # ----------------------------------------------------------------------------
@@ -403,6 +405,7 @@ def _prk_step_core(st, cfg, fixed_iters):
     grG = gradient(U_half, ZG, st.L, cfg.Nx, cfg.q, cfg.m)
     kh2 = tangent_velocity(U0, xi_half, ZG, grG.G, cfg.pinv_rtol, Ux=U_half)
     U1 = cayley(U0, dt * kh2)
+    st.last_U_half, st.last_Z_new = U_half, Z1.copy()
     if cfg.reorth:
         U1, Z1 = reorthonormalise(U1, Z1)
     st.U, st.Z = U1, Z1
@@ -653,6 +656,24 @@ def diagnostics(st, cfg):
     rho, Phi, _ = pic.fields_of(Xr, st.L, cfg.Nx, cfg.q)
     E = pic.electric_energy(Phi, rho, st.L, Xr.shape[0], cfg.m)
     return E, 0.5 * np.sum(Vr * Vr, axis=0) + E
+
+
+def hamiltonian_split(U_prev, Z_prev, U_half, Z_new, U_tau, Z_tau, L, Nx, q=-1.0, m=1.0):
+    """The four Hamiltonians of the splitting eq. error_ham_tot of one step,
+    per parameter: H(U_{tau-1} Z_{tau-1}), H(U_{tau-1/2} Z_{tau-1}),
+    H(U_{tau-1/2} Z_tau), H(U_tau Z_tau) (rows of a 4 x p array).  With them
+    Delta H = |H_3 - H_0| is bounded by |H_3 - H_2| + |H_1 - H_0| (the two
+    basis terms) + |H_2 - H_1| (the coefficient term), each taken as the
+    2-norm over the parameters.  Z_tau is the coefficient matrix of the
+    step before the re-orthonormalisation, which rotates U_tau and Z_tau
+    together and leaves U_tau Z_tau unchanged; (U_tau, Z_tau) is the state
+    after the step."""
+    N = U_prev.shape[0] // 2
+    rows = []
+    for U, Z in ((U_prev, Z_prev), (U_half, Z_prev), (U_half, Z_new), (U_tau, Z_tau)):
+        R = U @ Z
+        rows.append(pic.hamiltonian(R[:N], R[N:], L, Nx, q, m))
+    return np.array(rows)
 
 
 def relative_errors(X, V, Xr, Vr):

@@ -440,3 +440,35 @@ def test_local_singular_values_and_numerical_rank():
     assert rom.numerical_rank(s, 1e-6) == 8   # above 3e-6: and 1e-5, 5e-6
     assert rom.numerical_rank(s, 1.0) == 0    # strictly above the largest: none
     assert rom.numerical_rank([], 1e-3) == 0
+
+
+def test_hamiltonian_split_complete_basis_and_end_rows():
+    """eq. error_ham_tot: with a complete basis (2n = 2N) the basis cannot
+    move, so U_{tau-1/2} = U_{tau-1} = U_tau: the two basis terms vanish and
+    the whole change of the Hamiltonian is the coefficient term.  On a
+    low-rank step the first and last rows are the Hamiltonians of the
+    states before and after the step, and the basis terms are not zero."""
+    rng = np.random.default_rng(11)
+    N, p, Nx = 30, 2, 8
+    L = np.array([6.0, 7.5])
+    X = rng.uniform(0, 1, size=(N, p)) * L[None, :]
+    V = rng.normal(size=(N, p))
+    cfg = rom.RomConfig(N=N, p=p, Nx=Nx, two_n=2 * N, dt=0.05, fp_tol=1e-14, fp_max_iters=400)
+    st = rom.RomState(U=np.eye(2 * N), Z=np.concatenate([X, V], axis=0), L=L)
+    U0, Z0 = st.U.copy(), st.Z.copy()
+    assert rom.prk_step(st, cfg) == rom.OK
+    H = rom.hamiltonian_split(U0, Z0, st.last_U_half, st.last_Z_new, st.U, st.Z, L, Nx)
+    scale = np.abs(H).max()
+    assert np.abs(H[1] - H[0]).max() < 1e-13 * scale
+    assert np.abs(H[3] - H[2]).max() < 1e-13 * scale
+    assert np.abs(H[2] - H[1]).max() > 1e-8 * scale      # the coefficients did move
+    # a reduced step of the small Landau case
+    st, cfg, _ = _tiny_landau(two_n=6, N=400)
+    U0, Z0 = st.U.copy(), st.Z.copy()
+    _, H0 = rom.diagnostics(st, cfg)
+    assert rom.prk_step(st, cfg) == rom.OK
+    _, H1 = rom.diagnostics(st, cfg)
+    H = rom.hamiltonian_split(U0, Z0, st.last_U_half, st.last_Z_new, st.U, st.Z, st.L, cfg.Nx)
+    np.testing.assert_allclose(H[0], H0, rtol=1e-13)
+    np.testing.assert_allclose(H[3], H1, rtol=1e-12)
+    assert np.linalg.norm(H[1] - H[0]) > 0 and np.linalg.norm(H[3] - H[2]) > 0
