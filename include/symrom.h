@@ -260,6 +260,27 @@ symrom_status rom_set_parameters(symrom_rom* h, const double* eta, int32_t dim);
 symrom_status rom_dmd_state(symrom_rom* h, int32_t* S, int32_t* pstar, int32_t* rank, double* lam,
                             double* e0, double* eh);
 
+/* Scratch bytes for rom_step_hamiltonian_split: U_{tau-1/2} (N x n_max
+ * complex) and Z_tau (n_max x p complex), 256-byte aligned. */
+size_t rom_hamiltonian_split_bytes(const symrom_rom* h);
+
+/* One step as rom_step (without rank adaptation) that also returns the four
+ * Hamiltonians of the splitting of the step's Hamiltonian change (Sec. 6.2,
+ * eq. error_ham_tot), per parameter, in H4 (device, 4 x p row-major):
+ * H(U_{tau-1} Z_{tau-1}), H(U_{tau-1/2} Z_{tau-1}), H(U_{tau-1/2} Z_tau),
+ * H(U_tau Z_tau), with H(UZ) = |V_r|^2 / 2 + E(X_r) (eq. HamEEfull).  The
+ * change |H_3 - H_0| is bounded by the two basis terms |H_3 - H_2| and
+ * |H_1 - H_0| and the coefficient term |H_2 - H_1|.  Z_tau is taken before
+ * the re-orthonormalisation (which rotates U_tau and Z_tau together and
+ * leaves U_tau Z_tau unchanged).  scratch: device, at least
+ * rom_hamiltonian_split_bytes(h) bytes, 256-byte aligned, caller-owned.
+ * Errors as rom_step (on failure the state is the one before the step and
+ * H4 is not written); EINVAL for a null pointer or a small or misaligned
+ * scratch; ESTATE for a DMD-DEIM step (its windows full): the splitting is
+ * taken on the Galerkin and exact-potential DEIM steps. */
+symrom_status rom_step_hamiltonian_split(symrom_rom* h, void* scratch, size_t scratch_bytes,
+                                         double* H4, symrom_step_info* info);
+
 /* Singular values of the initial state C0 = X0 + i V0 (N x p) that
  * rom_init or rom_init_family decomposed (the complex SVD of the
  * initialisation, Sec. 6.1), in decreasing order, as the square roots of the

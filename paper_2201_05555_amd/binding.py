@@ -98,6 +98,9 @@ _SIGS = {
     "rom_diagnostics": (ctypes.c_int32, [_VP, _VP, _VP]),
     "rom_init_singular_values": (ctypes.c_int32, [_VP, _VP, ctypes.c_int32,
                                                   ctypes.POINTER(ctypes.c_int32)]),
+    "rom_hamiltonian_split_bytes": (ctypes.c_size_t, [_VP]),
+    "rom_step_hamiltonian_split": (ctypes.c_int32, [_VP, _VP, ctypes.c_size_t, _VP,
+                                                    ctypes.POINTER(StepInfo)]),
     "rom_gradient": (ctypes.c_int32, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "rom_destroy": (None, [_VP]),
     "fom_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32] * 3),
@@ -367,6 +370,19 @@ class Rom:
         d = ctypes.c_int32()
         _check(lib().rom_deim_operator(self.h, _ptr(idx), _ptr(w), ctypes.byref(d)))
         return idx[: d.value], w[: d.value]
+
+    def step_hamiltonian_split(self):
+        """One step with the four Hamiltonians of eq. error_ham_tot: (info,
+        H4 (4, p) device tensor: H(U_{tau-1} Z_{tau-1}), H(U_{tau-1/2}
+        Z_{tau-1}), H(U_{tau-1/2} Z_tau), H(U_tau Z_tau))."""
+        nb = lib().rom_hamiltonian_split_bytes(self.h)
+        scratch = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+        off = (-scratch.data_ptr()) % 256
+        H4 = torch.empty((4, self.cfg.p), dtype=torch.float64, device="cuda")
+        info = StepInfo()
+        _check(lib().rom_step_hamiltonian_split(self.h, ctypes.c_void_p(scratch.data_ptr() + off),
+                                                nb, _ptr(H4), ctypes.byref(info)))
+        return _info_dict(info), H4
 
     def init_singular_values(self):
         """Singular values (numpy, decreasing) of the initial state the

@@ -666,6 +666,10 @@ struct symrom_rom {
   double* lamsub;
   symrom_step_info last;
   std::vector<double> init_sig;  // singular values of C0 found by the initialisation
+  // set during rom_step_hamiltonian_split: U_{tau-1/2} and Z_tau (before the
+  // re-orthonormalisation) are copied here (caller's scratch)
+  cplx* split_U = nullptr;
+  cplx* split_Z = nullptr;
 };
 
 namespace {
@@ -1439,6 +1443,14 @@ symrom_status rom_step_one(symrom_rom& r, bool decide_rank) {
   full_gradient(r, r.Uh, r.ZG, nullptr, false, false, nullptr, fused ? r.C12 : nullptr);
   if (side) HIPCHK(hipStreamWaitEvent(s, r.ev_sp1, 0));
   basis_velocity(r, r.Uh, r.ZG, 1.0, r.Xv, nullptr, side);
+  if (r.split_U) {
+    // the midpoint basis and the new coefficients, before the retraction
+    // overwrites the one and rotates the other
+    HIPCHK(hipMemcpyAsync(r.split_U, r.Uh, (size_t)N * n * sizeof(cplx), hipMemcpyDeviceToDevice,
+                          s));
+    HIPCHK(hipMemcpyAsync(r.split_Z, r.Z1, (size_t)n * p * sizeof(cplx), hipMemcpyDeviceToDevice,
+                          s));
+  }
   tangent_retract(r);
   // Commit by exchanging buffers before the flags are known, and with rank
   // adaptation enqueue the indicator's gradient at the new state behind it,
@@ -2500,6 +2512,70 @@ extern "C" symrom_status rom_gradient(symrom_rom* r, const double* Z, double* g,
   if (e) HIPCHK(hipMemcpyAsync(e, r->b.e, gb, hipMemcpyDeviceToDevice, s));
   LAUNCHCHK();
   HIPCHK(hipStreamSynchronize(s));
+  return SYMROM_OK;
+}
+
+namespace {
+// H(U Z) per parameter (device [p]): the electric energy of the deposit at
+// X_r = Re(U~ Z~) plus |V_r|^2 / 2, V_r = Im(U~ Z~) (the arithmetic of
+// rom_diagnostics, on the handle's field and gather buffers)
+void hamiltonian_of(symrom_rom& r, const cplx* U, const cplx* Z, double* H) {
+  hipStream_t s = r.s;
+  const int N = r.N, p = r.p, n = r.n;
+  launch_deposit_rom(s, U, N, n, Z, p, r.Nx, r.gdep, r.b.factor, nullptr, r.b.part, nullptr,
+                     nullptr, r.cfg.deterministic);
+  launch_poisson(s, r.b.part, r.gdep.nrb, p, r.Nx, r.b.qw, r.b.h, r.b.mw, nullptr, r.b.rho,
+                 r.b.phi, r.b.e, r.b.energy);
+  double* Vr = reinterpret_cast<double*>(r.G);
+  launch_reconstruct(s, U, N, n, Z, p, nullptr, Vr);
+  launch_colsumsq(s, Vr, N, p, 0.5, H, r.b.part);
+  launch_vec_add(s, H, r.b.energy, p);
+}
+
+size_t split_z_offset(const symrom_rom* r) {
+  return ((size_t)r->N * r->nmax * sizeof(cplx) + 255) & ~(size_t)255;
+}
+}  // namespace
+
+extern "C" size_t rom_hamiltonian_split_bytes(const symrom_rom* r) {
+  if (!r) return 0;
+  return split_z_offset(r) + (size_t)r->nmax * r->p * sizeof(cplx);
+}
+
+extern "C" symrom_status rom_step_hamiltonian_split(symrom_rom* r, void* scratch,
+                                                    size_t scratch_bytes, double* H4,
+                                                    symrom_step_info* info) {
+  if (!r || !scratch || !H4) return fail(SYMROM_EINVAL, "rom_step_hamiltonian_split: null pointer");
+  if (!r->ready) return fail(SYMROM_ESTATE, "rom_step_hamiltonian_split: handle not initialised");
+  if (scratch_bytes < rom_hamiltonian_split_bytes(r))
+    return fail(SYMROM_EINVAL, "rom_step_hamiltonian_split: scratch too small");
+  if (reinterpret_cast<uintptr_t>(scratch) % 256 != 0)
+    return fail(SYMROM_EINVAL, "rom_step_hamiltonian_split: scratch not 256-byte aligned");
+  if (r->cfg.projection == SYMROM_DMD_DEIM && r->win_count + 1 >= r->nslots)
+    return fail(SYMROM_ESTATE, "rom_step_hamiltonian_split: DMD-DEIM steps are not split");
+  side_wait(r);
+  const int p = r->p;
+  r->split_U = static_cast<cplx*>(scratch);
+  r->split_Z = reinterpret_cast<cplx*>(static_cast<char*>(scratch) + split_z_offset(r));
+  r->last.iters_total = r->last.deim_steps = r->last.stalled_total = 0;
+  symrom_status st = rom_step_one(*r, false);
+  r->split_U = r->split_Z = nullptr;
+  r->last.iters_total = r->last.iters;
+  r->last.deim_steps = r->last.deim_active;
+  r->last.stalled_total = r->last.stalled;
+  r->last.two_n = 2 * r->n;
+  if (info) *info = r->last;
+  if (st != SYMROM_OK) return st;
+  // after the step U_{tau-1}, Z_{tau-1} are in the exchanged buffers
+  r->stage1_cached = false;
+  hamiltonian_of(*r, r->Uh, r->Z1, H4);
+  hamiltonian_of(*r, (const cplx*)scratch, r->Z1, H4 + p);
+  hamiltonian_of(*r, (const cplx*)scratch,
+                 reinterpret_cast<const cplx*>(static_cast<char*>(scratch) + split_z_offset(r)),
+                 H4 + 2 * p);
+  hamiltonian_of(*r, r->U0, r->Z0, H4 + 3 * p);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(r->s));
   return SYMROM_OK;
 }
 

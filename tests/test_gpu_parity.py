@@ -394,6 +394,48 @@ def test_rom_landau_trajectory_100_steps():
     print(f"  first step with a different iteration count: {first_mismatch}", flush=True)
 
 
+@pytest.mark.parametrize("name,kw,two_n,proj,steps", [
+    ("landau_tiny", dict(N=3001), 10, "galerkin", 2),
+    ("twostream_deim", dict(N=20000, p=24, Nx=128), 10, "deim", 5),   # the last on DEIM
+])
+def test_rom_hamiltonian_split_parity(name, kw, two_n, proj, steps):
+    """rom_step_hamiltonian_split against the oracle's splitting of eq.
+    error_ham_tot after each step: the four Hamiltonians H(U_{tau-1}
+    Z_{tau-1}), H(U_{tau-1/2} Z_{tau-1}), H(U_{tau-1/2} Z_tau), H(U_tau Z_tau)
+    per parameter and the three terms of the bound, relative to the largest
+    |H|; the iteration counts as the oracle's."""
+    binding, torch = _b()
+    w, e = _ens(name, **kw)
+    _say("rom hamiltonian split", name, kw, two_n, proj)
+    ckw = dict(fp_tol=1e-10) if proj == "galerkin" else dict(fp_tol=1e-10, projection="deim",
+                                                             deim_window=3)
+    cfg, st = _oracle_state(w, e, two_n, **ckw)
+    r = _gpu_rom(binding, w, e, two_n, **ckw)
+    _set_from_oracle(r, st, torch)
+    for s in range(steps):
+        U0, Z0 = st.U.copy(), st.Z.copy()
+        info, H4 = r.step_hamiltonian_split()
+        assert rom.prk_step(st, cfg) == rom.OK
+        assert info["iters"] == st.last_iters, (s, info, st.last_iters)
+        Ho = rom.hamiltonian_split(U0, Z0, st.last_U_half, st.last_Z_new, st.U, st.Z, st.L,
+                                   w["Nx"])
+        Hg = _np(H4)
+        scale = np.abs(Ho).max()
+        err = np.abs(Hg - Ho).max() / scale
+        terms_o = [np.linalg.norm(Ho[3] - Ho[0]), np.linalg.norm(Ho[3] - Ho[2]),
+                   np.linalg.norm(Ho[1] - Ho[0]), np.linalg.norm(Ho[2] - Ho[1])]
+        terms_g = [np.linalg.norm(Hg[3] - Hg[0]), np.linalg.norm(Hg[3] - Hg[2]),
+                   np.linalg.norm(Hg[1] - Hg[0]), np.linalg.norm(Hg[2] - Hg[1])]
+        terr = max(abs(a - b) for a, b in zip(terms_g, terms_o)) / scale
+        print(f"  step {s}: H rows err {err:.2e}; terms (dH, basis 1, basis 2, coeff) GPU "
+              f"{[f'{t:.3e}' for t in terms_g]} oracle {[f'{t:.3e}' for t in terms_o]}; "
+              f"term err {terr:.2e}", flush=True)
+        assert err < 1e-9 and terr < 1e-9
+        assert terms_o[0] <= terms_o[1] + terms_o[2] + terms_o[3] + 1e-15 * scale
+    if proj == "deim":
+        assert info["deim_active"] == 1
+
+
 def test_rom_enoconv_keeps_state():
     binding, torch = _b()
     w, e = _ens("landau_tiny", N=2000)
