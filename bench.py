@@ -90,10 +90,11 @@ def parse():
     ap.add_argument("--serve-gap", type=float, default=1.0, help="mean inter-arrival (s)")
     ap.add_argument("--no-dmd", action="store_true", help="skip the DMD-DEIM leg")
     ap.add_argument("--no-restart", action="store_true",
-                    help="skip the two-stream restart at t = 30 (Sec. 6.4) and the local-rank "
-                         "study (Sec. 6.1)")
+                    help="skip the paper-workload legs: the two-stream restart at t = 30 "
+                         "(Sec. 6.4), the local-rank study (Sec. 6.1) and the Hamiltonian "
+                         "splitting (Sec. 6.2)")
     ap.add_argument("--restart-only", action="store_true",
-                    help="run only the restart and local-rank legs and print their results")
+                    help="run only the paper-workload legs and print their results")
     ap.add_argument("--dmd-only", action="store_true",
                     help="run only the DMD-DEIM leg (at p = 1024, no sweep) and print its line")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -568,6 +569,55 @@ def local_rank_leg(binding, torch, p=64, every=400, tols=(1e-3, 1e-4, 1e-5)):
     return out
 
 
+def hamiltonian_split_leg(binding, torch, steps=200, p=300):
+    """The splitting of the step-to-step Hamiltonian change of Sec. 6.2
+    (eq. error_ham_tot) on the weak Landau damping ensemble (eta = (alpha,
+    sigma), k = 0.5, N = 5e4, N_x = 32, dt = 0.0025, quiet start) at p
+    parameters and 2n = 6, with the Galerkin projection and with DEIM of the
+    exact potential (T = 3, d = 32): per step the 2-norms over the
+    parameters of Delta H = |H(U_tau Z_tau) - H(U_{tau-1} Z_{tau-1})|, of the
+    two basis terms and of the coefficient term, through
+    rom_step_hamiltonian_split; reported: their mean and maximum over the
+    steps, and the mean relative Hamiltonian change per step."""
+    import numpy as np
+    from workloads import workload, particle_uniforms
+    from workloads.ensembles import draw_parameters
+    w = workload("landau_ld", p=p)
+    params = draw_parameters(w)
+    ux, uv = particle_uniforms(w)
+    src = dict(family=w["family"], params=params, ux=ux, uv=uv)
+    out = {"workload": "landau_ld", "N": w["N"], "p": p, "Nx": w["Nx"], "dt": w["dt"],
+           "two_n": 6, "steps": steps,
+           "terms": "dH = |H_tau - H_{tau-1}|, basis_new = |H(U_tau Z_tau) - H(U_{tau-1/2} "
+                    "Z_tau)|, basis_old = |H(U_{tau-1/2} Z_{tau-1}) - H(U_{tau-1} Z_{tau-1})|, "
+                    "coeff = |H(U_{tau-1/2} Z_tau) - H(U_{tau-1/2} Z_{tau-1})|, 2-norms over "
+                    "the parameters"}
+    for proj in ("galerkin", "deim"):
+        def run(proj=proj):
+            cfg = binding.make_config(w["N"], p, w["Nx"], 6, dt=w["dt"], projection=proj,
+                                      deim_window=3, deim_rows=32, fp_tol=1e-9,
+                                      fp_stall_tol=DMD_STALL_TOL)
+            r = binding.Rom(cfg, None, None, None, **src)
+            T = []
+            try:
+                for _ in range(steps):
+                    _, H4 = r.step_hamiltonian_split()
+                    H = H4.cpu().numpy()
+                    T.append([np.linalg.norm(H[3] - H[0]), np.linalg.norm(H[3] - H[2]),
+                              np.linalg.norm(H[1] - H[0]), np.linalg.norm(H[2] - H[1]),
+                              np.linalg.norm(H[3] - H[0]) / np.linalg.norm(H[0])])
+            finally:
+                r.close()
+            T = np.array(T)
+            names = ("dH", "basis_new", "basis_old", "coeff")
+            res = {k: {"mean": float(T[:, i].mean()), "max": float(T[:, i].max())}
+                   for i, k in enumerate(names)}
+            res["mean_relative_dH_per_step"] = float(T[:, 4].mean())
+            return res
+        out[proj] = _leg(f"Hamiltonian split {proj}", run)
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -584,7 +634,10 @@ def main():
     if a.restart_only:
         print(json.dumps({"restart": _leg("restart leg", lambda: restart_leg(binding, torch)),
                           "local_rank": _leg("local rank leg",
-                                             lambda: local_rank_leg(binding, torch))}),
+                                             lambda: local_rank_leg(binding, torch)),
+                          "hamiltonian_split": _leg("Hamiltonian split leg",
+                                                    lambda: hamiltonian_split_leg(binding,
+                                                                                  torch))}),
               flush=True)
         return
     if a.dmd_only:
@@ -756,6 +809,8 @@ def main():
     if not a.no_restart:
         out["restart"] = _leg("restart leg", lambda: restart_leg(binding, torch))
         out["local_rank"] = _leg("local rank leg", lambda: local_rank_leg(binding, torch))
+        out["hamiltonian_split"] = _leg("Hamiltonian split leg",
+                                        lambda: hamiltonian_split_leg(binding, torch))
     if not a.no_serve:
         out["serve"] = _leg("serving mix", lambda: serve_bench(
             binding, torch, a.serve_requests, a.serve_step_scale, 4, 96.0, a.serve_gap))
