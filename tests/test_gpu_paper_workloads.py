@@ -1,6 +1,7 @@
-"""The paper's workloads as validation of the GPU library (no oracle: the
-reduced model against the full-order model on the device, both checked
-against the oracle elsewhere).
+"""The paper's workloads as validation of the GPU library: the reduced model
+against the full-order model on the device (both checked against the oracle
+elsewhere), and the singular values behind the local-rank study against the
+oracle.
 
 * The restart of Sec. 6.4: the two-stream instability ensemble run to t = 30
   with the full-order model, where a small rank no longer follows the
@@ -10,6 +11,9 @@ against the oracle elsewhere).
   target error (eq. relative_errors_complex_SVD) of the same rank.  The
   target is the best rank-n approximation of X + iV, so it bounds the
   combined error of X and V from below (not each part alone).
+* The local snapshot matrices of eq. local_snapshots: their singular values
+  as the library's initialisation finds them, and the numerical ranks of
+  Sec. 6.1, against the oracle's SVD.
 """
 import numpy as np
 import pytest
