@@ -573,8 +573,9 @@ def hamiltonian_split_leg(binding, torch, steps=200, p=300):
     """The splitting of the step-to-step Hamiltonian change of Sec. 6.2
     (eq. error_ham_tot) on the weak Landau damping ensemble (eta = (alpha,
     sigma), k = 0.5, N = 5e4, N_x = 32, dt = 0.0025, quiet start) at p
-    parameters and 2n = 6, with the Galerkin projection and with DEIM of the
-    exact potential (T = 3, d = 32): per step the 2-norms over the
+    parameters and 2n = 6, with the Galerkin projection, with DEIM of the
+    exact potential (T = 3, d = 32) and with DMD-DEIM (Alg. 2, as in the
+    DMD-DEIM leg): per step the 2-norms over the
     parameters of Delta H = |H(U_tau Z_tau) - H(U_{tau-1} Z_{tau-1})|, of the
     two basis terms and of the coefficient term, through
     rom_step_hamiltonian_split; reported: their mean and maximum over the
@@ -592,11 +593,14 @@ def hamiltonian_split_leg(binding, torch, steps=200, p=300):
                     "Z_tau)|, basis_old = |H(U_{tau-1/2} Z_{tau-1}) - H(U_{tau-1} Z_{tau-1})|, "
                     "coeff = |H(U_{tau-1/2} Z_tau) - H(U_{tau-1/2} Z_{tau-1})|, 2-norms over "
                     "the parameters"}
-    for proj in ("galerkin", "deim"):
+    for proj in ("galerkin", "deim", "dmd_deim"):
         def run(proj=proj):
+            dmd = proj == "dmd_deim"
             cfg = binding.make_config(w["N"], p, w["Nx"], 6, dt=w["dt"], projection=proj,
                                       deim_window=3, deim_rows=32, fp_tol=1e-9,
-                                      fp_stall_tol=DMD_STALL_TOL)
+                                      fp_stall_tol=DMD_STALL_TOL, p_star=w["p_star"],
+                                      deim_update_every=w["deim_update_every"] if dmd else 1,
+                                      deim_update_rows=w["deim_update_rows"] if dmd else 0)
             r = binding.Rom(cfg, None, None, None, **src)
             T = []
             try:

@@ -274,10 +274,11 @@ size_t rom_hamiltonian_split_bytes(const symrom_rom* h);
  * the re-orthonormalisation (which rotates U_tau and Z_tau together and
  * leaves U_tau Z_tau unchanged).  scratch: device, at least
  * rom_hamiltonian_split_bytes(h) bytes, 256-byte aligned, caller-owned.
+ * Every projection, DMD-DEIM steps included (H is the Hamiltonian of the
+ * full model at the reconstructed state, not the DMD-DEIM approximation).
  * Errors as rom_step (on failure the state is the one before the step and
  * H4 is not written); EINVAL for a null pointer or a small or misaligned
- * scratch; ESTATE for a DMD-DEIM step (its windows full): the splitting is
- * taken on the Galerkin and exact-potential DEIM steps. */
+ * scratch. */
 symrom_status rom_step_hamiltonian_split(symrom_rom* h, void* scratch, size_t scratch_bytes,
                                          double* H4, symrom_step_info* info);
 

@@ -130,7 +130,7 @@ class RomState:
     last_dmd_rank: int = 0
     last_dmd: object = None                 # DMD operator of the last DMD-DEIM step
     last_dmd_tables: object = None          # its field tables (e at t_{tau-1}, at + dt/2)
-    last_U_half: Optional[np.ndarray] = None   # U_{tau-1/2} of the last Galerkin/DEIM step
+    last_U_half: Optional[np.ndarray] = None   # U_{tau-1/2} of the last step
     last_Z_new: Optional[np.ndarray] = None    # Z_tau of that step, before re-orthonormalisation
 
 
@@ -529,6 +529,7 @@ def _prk_step_dmd(st, cfg, fixed_iters):
     grG = gradient(U_half, ZG[:, S], L[S], cfg.Nx, cfg.q, cfg.m)
     kh2 = tangent_velocity(U0, xi_half, ZG[:, S], grG.G, cfg.pinv_rtol, Ux=U_half)
     U1 = cayley(U0, dt * kh2)
+    st.last_U_half, st.last_Z_new = U_half, Z1.copy()
     if cfg.reorth:
         U1, Z1 = reorthonormalise(U1, Z1)
     st.U, st.Z = U1, Z1

@@ -1653,6 +1653,12 @@ symrom_status rom_step_dmd(symrom_rom& r) {
     full_gradient(r, r.Uh, r.Zs, nullptr, true, false, nullptr, r.C12);
     basis_velocity(r, r.Uh, r.Zs, 1.0, r.Xv, nullptr);
   }
+  if (r.split_U) {
+    HIPCHK(hipMemcpyAsync(r.split_U, r.Uh, (size_t)N * n * sizeof(cplx), hipMemcpyDeviceToDevice,
+                          s));
+    HIPCHK(hipMemcpyAsync(r.split_Z, r.Z1, (size_t)n * p * sizeof(cplx), hipMemcpyDeviceToDevice,
+                          s));
+  }
   tangent_retract(r);
   std::swap(r.U0, r.Uh);
   std::swap(r.Z0, r.Z1);
@@ -2551,14 +2557,13 @@ extern "C" symrom_status rom_step_hamiltonian_split(symrom_rom* r, void* scratch
     return fail(SYMROM_EINVAL, "rom_step_hamiltonian_split: scratch too small");
   if (reinterpret_cast<uintptr_t>(scratch) % 256 != 0)
     return fail(SYMROM_EINVAL, "rom_step_hamiltonian_split: scratch not 256-byte aligned");
-  if (r->cfg.projection == SYMROM_DMD_DEIM && r->win_count + 1 >= r->nslots)
-    return fail(SYMROM_ESTATE, "rom_step_hamiltonian_split: DMD-DEIM steps are not split");
   side_wait(r);
+  const bool dmd = r->cfg.projection == SYMROM_DMD_DEIM && r->win_count + 1 >= r->nslots;
   const int p = r->p;
   r->split_U = static_cast<cplx*>(scratch);
   r->split_Z = reinterpret_cast<cplx*>(static_cast<char*>(scratch) + split_z_offset(r));
   r->last.iters_total = r->last.deim_steps = r->last.stalled_total = 0;
-  symrom_status st = rom_step_one(*r, false);
+  symrom_status st = dmd ? rom_step_dmd(*r) : rom_step_one(*r, false);
   r->split_U = r->split_Z = nullptr;
   r->last.iters_total = r->last.iters;
   r->last.deim_steps = r->last.deim_active;

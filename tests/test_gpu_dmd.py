@@ -182,6 +182,40 @@ def test_dmd_deim_steps_parity(kw, two_n, T, pstar, d, steps):
     assert ex < bx and ev < bv
 
 
+def test_dmd_deim_hamiltonian_split_parity():
+    """rom_step_hamiltonian_split on the DMD-DEIM model (Alg. 2, the Landau
+    damping ensemble of Sec. 6.2): after each of the plain steps and the
+    DMD-DEIM steps, the four Hamiltonians of eq. error_ham_tot against the
+    oracle's (the same iteration counts), relative to the largest |H|; and
+    the steps after a split continue as the oracle's (the evaluations leave
+    the state and the windows alone)."""
+    binding, torch = _b()
+    kw, two_n, T, pstar, d, steps = dict(name="landau_ld", N=20000, p=40), 4, 3, 16, 16, 6
+    w, e, cfg = _pair(kw, two_n, T, pstar, d)
+    _say("dmd-deim hamiltonian split", kw, two_n, T, pstar, d, steps)
+    st = rom.init_state(e["X0"], e["V0"], e["L"], cfg, eta=e["eta"])
+    r = _gpu(binding, w, e, two_n, T, pstar, d)
+    _set_from_oracle(r, st, torch)
+    for s in range(steps):
+        U0, Z0 = st.U.copy(), st.Z.copy()
+        info, H4 = r.step_hamiltonian_split()
+        assert rom.prk_step(st, cfg) == rom.OK
+        assert info["iters"] == st.last_iters, (s, info, st.last_iters)
+        Ho = rom.hamiltonian_split(U0, Z0, st.last_U_half, st.last_Z_new, st.U, st.Z, st.L,
+                                   cfg.Nx)
+        Hg = _np(H4)
+        err = np.abs(Hg - Ho).max() / np.abs(Ho).max()
+        terms = [np.linalg.norm(Ho[3] - Ho[0]), np.linalg.norm(Ho[3] - Ho[2]),
+                 np.linalg.norm(Ho[1] - Ho[0]), np.linalg.norm(Ho[2] - Ho[1])]
+        print(f"  step {s} ({'DMD-DEIM' if info['deim_active'] else 'plain'}): H rows err "
+              f"{err:.2e}; dH {terms[0]:.3e}, basis {terms[1]:.3e} {terms[2]:.3e}, "
+              f"coefficients {terms[3]:.3e}", flush=True)
+        # (the DMD-DEIM states agree with the oracle's to about 1e-9, the floor
+        # of the DMD-DEIM step parity above; H follows them)
+        assert err < 5e-9
+    assert info["deim_active"] == 1
+
+
 def test_dmd_deim_needs_parameters():
     """A rom_init handle refuses its first DMD-DEIM step until the
     parameters are given (ESTATE), then runs."""
