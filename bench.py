@@ -625,8 +625,8 @@ def hamiltonian_split_leg(binding, torch, steps=200, p=300):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {a.gpus}); the "
-              "multi-GPU design is described but not built.", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only (asked for {a.gpus}); "
+              "sharding over several GPUs is designed but not built.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

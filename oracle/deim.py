@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
 The nonlinear term N_i = Lambda^0(X_r^i) Phi^i (values of the potential at
 the particles) is interpolated on d particle indices.  With the exact
-potential (no DMD, reading for this build) the DEIM gradient of eq. (grHDD) is
+potential (no DMD; a reading) the DEIM gradient of eq. (grHDD) is
   g_i = U_V^T V_r^i + U_X[I,:]^T ( (q/m) e_i[j(X_r^i[I])] * w ),
   w = (P^T Psi)^{-T} Psi^T 1,
 since m_p^{-1} M_q = (q/m) 1 and nabla Lambda^0 Phi is the cell field e.

@@ -346,7 +346,7 @@ def prk_step(st, cfg, fixed_iters=None):
     4. Z1 = Z0 + dt k2.
     5. k^2 = Y(xi_half, Z_G), Z_G the point of the last gradient of each
        column (reading);  U1 = R_{U0}(dt k^2).
-    6. re-orthonormalise (this build's addition).
+    6. re-orthonormalise (an addition to the paper's scheme).
     Returns the status (OK or ENOCONV); on ENOCONV the state (U, Z and the
     DEIM snapshot window) is unchanged.
     """
@@ -555,7 +555,7 @@ def run(st, cfg, steps):
 
 
 # ----------------------------------------------------------------------------
-# Rank adaptation (this build's policy; the paper defers rank adaptation)
+# Rank adaptation (a policy of its own here; the paper defers rank adaptation)
 # ----------------------------------------------------------------------------
 
 def rank_indicator(st, cfg, gr=None):
