@@ -741,9 +741,11 @@ __global__ void __launch_bounds__(256) gather_xi_mfma_kernel(
   constexpr int XS = 65;  // row stride of the position tile (parameter-major)
   constexpr int FS = 17;  // row stride of the field tile (row-major)
   constexpr int OS = 16 * MT + 1;  // row stride of the output tile (>= FS)
+  // one region per wavefront holds the position tile, then the field tile,
+  // then the output tile (each read whole before the next is written)
+  constexpr int WS = (16 * XS > 64 * OS) ? 16 * XS : 64 * OS;
   __shared__ cplx Ms[NC * NC], Ns[NC * NC];
-  __shared__ double Xs[4][16 * XS];
-  __shared__ double Fs[4][64 * OS];  // the field tile, then the output tile
+  __shared__ double Ws[4][WS];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lk = lane >> 4;
@@ -803,8 +805,8 @@ __global__ void __launch_bounds__(256) gather_xi_mfma_kernel(
   for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) acc[rt][mt] = mf4{0.0, 0.0, 0.0, 0.0};
-  double* xs = Xs[w];
-  double* fs = Fs[w];
+  double* xs = Ws[w];
+  double* fs = Ws[w];
   for (int c0 = 0; c0 < p; c0 += 16) {
     const int ntc = min(16, p - c0);
     // B operands: the coefficients of parameter c0 + li and the entries
@@ -827,6 +829,10 @@ __global__ void __launch_bounds__(256) gather_xi_mfma_kernel(
       }
     }
     // positions, parameter-major in LDS: xs[param li][row 16 rt + 4 v + lk]
+    // (after the last tile's field reads)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt) {
       const mf4 X = pos_tile<KS>(a[rt], bz);
@@ -849,6 +855,10 @@ __global__ void __launch_bounds__(256) gather_xi_mfma_kernel(
       double fq[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) fq[q] = e[(size_t)(c0 + min(q, ntc - 1)) * Nx + jq[q]];
+      // (the positions are read: the field tile takes their place)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
       for (int q = 0; q < 16; ++q) fs[lane * FS + q] = (q < ntc) ? qm * fq[q] : 0.0;
     }
