@@ -260,6 +260,22 @@ symrom_status rom_set_parameters(symrom_rom* h, const double* eta, int32_t dim);
 symrom_status rom_dmd_state(symrom_rom* h, int32_t* S, int32_t* pstar, int32_t* rank, double* lam,
                             double* e0, double* eh);
 
+/* Tile autotuning of the fused gather-projection (the dominant kernel of
+ * the reduced step, eq. grads) for this handle's sizes (N, p, N_x, n): every
+ * launch shape that fits (16, 32 or 64 parameters per tile, their field rows
+ * in LDS or read from global memory, 256 to 1024 row blocks) is timed on the
+ * handle's current state (three launches after one untimed), and the
+ * fastest, when at least 3 % faster than the built-in rule, is kept for
+ * every later launch of these sizes in the process (all handles).  Results
+ * differ between shapes only by the rounding of the row-block partial sums.
+ * Out (host, nullable): the shape kept and the time per launch of it and of
+ * the rule (ms).  Errors: ESTATE for a deterministic handle (it keeps the
+ * built-in shape, so that its results repeat bitwise across processes) or
+ * for a rank beyond the fused kernels (2n > 32); EDEVICE if a timed launch
+ * failed (the rule is kept). */
+symrom_status rom_autotune(symrom_rom* h, int32_t* cbn, int32_t* et_lds, int32_t* nb_max,
+                           double* best_ms, double* rule_ms);
+
 /* Scratch bytes for rom_step_hamiltonian_split: U_{tau-1/2} (N x n_max
  * complex) and Z_tau (n_max x p complex), 256-byte aligned. */
 size_t rom_hamiltonian_split_bytes(const symrom_rom* h);

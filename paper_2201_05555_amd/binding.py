@@ -98,6 +98,8 @@ _SIGS = {
     "rom_diagnostics": (ctypes.c_int32, [_VP, _VP, _VP]),
     "rom_init_singular_values": (ctypes.c_int32, [_VP, _VP, ctypes.c_int32,
                                                   ctypes.POINTER(ctypes.c_int32)]),
+    "rom_autotune": (ctypes.c_int32, [_VP] + [ctypes.POINTER(ctypes.c_int32)] * 3
+                     + [ctypes.POINTER(ctypes.c_double)] * 2),
     "rom_hamiltonian_split_bytes": (ctypes.c_size_t, [_VP]),
     "rom_step_hamiltonian_split": (ctypes.c_int32, [_VP, _VP, ctypes.c_size_t, _VP,
                                                     ctypes.POINTER(StepInfo)]),
@@ -370,6 +372,17 @@ class Rom:
         d = ctypes.c_int32()
         _check(lib().rom_deim_operator(self.h, _ptr(idx), _ptr(w), ctypes.byref(d)))
         return idx[: d.value], w[: d.value]
+
+    def autotune(self):
+        """Time the launch shapes of the fused gather-projection for this
+        handle's sizes and keep the fastest (process-wide): dict of the shape
+        kept and the times per launch (ms) of it and of the built-in rule."""
+        c, e, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        tb, tr = ctypes.c_double(), ctypes.c_double()
+        _check(lib().rom_autotune(self.h, ctypes.byref(c), ctypes.byref(e), ctypes.byref(nb),
+                                  ctypes.byref(tb), ctypes.byref(tr)))
+        return dict(params_per_tile=16 * c.value, table_in_lds=bool(e.value),
+                    row_blocks_max=nb.value, ms=tb.value, rule_ms=tr.value)
 
     def step_hamiltonian_split(self):
         """One step with the four Hamiltonians of eq. error_ham_tot: (info,

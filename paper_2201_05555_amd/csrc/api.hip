@@ -2584,6 +2584,81 @@ extern "C" symrom_status rom_step_hamiltonian_split(symrom_rom* r, void* scratch
   return SYMROM_OK;
 }
 
+extern "C" symrom_status rom_autotune(symrom_rom* r, int32_t* cbn, int32_t* et_lds,
+                                      int32_t* nb_max, double* best_ms, double* rule_ms) {
+  if (!r) return fail(SYMROM_EINVAL, "rom_autotune: null handle");
+  if (!r->ready) return fail(SYMROM_ESTATE, "rom_autotune: handle not initialised");
+  if (r->cfg.deterministic)
+    return fail(SYMROM_ESTATE, "rom_autotune: a deterministic handle keeps the built-in shape");
+  if (!fused_gradient_ok(r->n))
+    return fail(SYMROM_ESTATE, "rom_autotune: no fused gather-projection at this rank");
+  side_wait(r);
+  hipStream_t s = r->s;
+  const int N = r->N, p = r->p, Nx = r->Nx, n = r->n;
+  const size_t cap = (size_t)r->nkb * 64 * 64;
+  const double qm = r->cfg.q / r->cfg.m;
+  // the field and the Grams of the current state (the timed launches then
+  // compute its gradient)
+  r->stage1_cached = false;
+  set_gather_project_shape(N, p, Nx, n, nullptr);
+  const GpShape rule = gather_project_shape(N, p, Nx, n, cap);
+  linear_grams(*r, r->U0, r->C12t);
+  full_gradient_field(*r, r->U0, r->Z0, nullptr);
+  hipEvent_t ea = nullptr, eb = nullptr;
+  HIPCHK(hipEventCreate(&ea));
+  if (hipEventCreate(&eb) != hipSuccess) {
+    (void)hipEventDestroy(ea);
+    return fail(SYMROM_EDEVICE, "rom_autotune: event");
+  }
+  auto launch = [&]() {
+    launch_gather_project(s, r->U0, N, n, r->Z0, p, Nx, r->b.factor, r->b.e, qm, nullptr, true,
+                          r->gemm_part, cap, r->gproj, r->colsq, r->C12t);
+  };
+  // the average of three launches after one untimed one
+  auto time_shape = [&](const GpShape& sh) -> double {
+    set_gather_project_shape(N, p, Nx, n, &sh);
+    launch();
+    float ms = -1.0f;
+    if (hipEventRecord(ea, s) != hipSuccess) return -1.0;
+    for (int k = 0; k < 3; ++k) launch();
+    if (hipEventRecord(eb, s) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
+        hipEventElapsedTime(&ms, ea, eb) != hipSuccess || hipGetLastError() != hipSuccess)
+      return -1.0;
+    return ms / 3.0;
+  };
+  GpShape best = rule;
+  double t_rule = time_shape(rule), t_best = t_rule;
+  bool ok = t_rule > 0.0;
+  for (const GpShape& sh : gather_project_shapes(N, p, Nx, n, cap)) {
+    if (!ok) break;
+    if (sh.cbn == rule.cbn && sh.et_lds == rule.et_lds && sh.nb_max == rule.nb_max) continue;
+    const double t = time_shape(sh);
+    if (t <= 0.0) {
+      ok = false;
+      break;
+    }
+    // another shape only when clearly faster (launch-to-launch noise is a
+    // per cent or two)
+    if (t < 0.97 * t_best) {
+      best = sh;
+      t_best = t;
+    }
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  if (!ok) {
+    set_gather_project_shape(N, p, Nx, n, nullptr);
+    return fail(SYMROM_EDEVICE, "rom_autotune: a timed launch failed");
+  }
+  set_gather_project_shape(N, p, Nx, n, &best);
+  if (cbn) *cbn = best.cbn;
+  if (et_lds) *et_lds = best.et_lds ? 1 : 0;
+  if (nb_max) *nb_max = best.nb_max;
+  if (best_ms) *best_ms = t_best;
+  if (rule_ms) *rule_ms = t_rule;
+  return SYMROM_OK;
+}
+
 extern "C" symrom_status rom_init_singular_values(symrom_rom* r, double* sig, int32_t cap,
                                                   int32_t* m) {
   if (!r || !m || cap < 0 || (cap > 0 && !sig))

@@ -1,6 +1,7 @@
 // Launch interface between the host orchestration and the HIP kernels.
 #pragma once
 
+#include <vector>
 #include "common.h"
 
 // Geometry of the particle-to-grid launches: nrb row blocks of rpb rows,
@@ -122,6 +123,18 @@ bool launch_rowgemm_gram(hipStream_t s, const RowTerms& T, int N, int m, cplx* o
 // when want_colsq, |G~[:, c]|^2 into colsq; part holds part_cap complex.
 // G12 = [U~^* U~, U~^T U~] of this U (the velocity part comes from them).
 bool fused_gradient_ok(int n);
+// Launch shape of the fused gather-projection: 16 cbn parameters per tile,
+// their field rows in LDS (et_lds) or read from global memory, and at most
+// nb_max row blocks.  launch_gather_project takes the shape set for (N, p,
+// Nx, n) by set_gather_project_shape (process-wide), else a built-in rule.
+struct GpShape {
+  int cbn;
+  bool et_lds;
+  int nb_max;
+};
+std::vector<GpShape> gather_project_shapes(int N, int p, int Nx, int n, size_t part_cap);
+void set_gather_project_shape(int N, int p, int Nx, int n, const GpShape* shape);
+GpShape gather_project_shape(int N, int p, int Nx, int n, size_t part_cap);
 void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p,
                            int Nx, const double* factor, const double* e, double qm,
                            const int* active, bool want_colsq, cplx* part, size_t part_cap,

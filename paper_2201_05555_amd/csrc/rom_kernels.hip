@@ -1,6 +1,10 @@
 // Streaming kernels of the reduced model: field gather at reconstructed
 // particles, tall-skinny products with reduction over particles (split over
 // row blocks, reduced in a fixed order), and row-wise small products.
+#include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
 #include "common.h"
 #include "kernels.h"
 
@@ -1450,30 +1454,93 @@ bool fused_gradient_ok(int n) { return n <= 16; }
 
 static int fused_nc(int n) { return nc_even(n); }
 
+namespace {
+// shapes set by set_gather_project_shape, by (N, p, Nx, column count)
+std::mutex gp_shape_mu;
+std::map<std::array<int, 4>, GpShape> gp_shapes;
+
+// LDS the kernel may take beyond its static arrays (the attribute call of
+// ALLOW_BIG_LDS raises the cap to the CU's 160 KB)
+constexpr size_t kGpLdsMax = 150 * 1024;
+
+size_t gp_lds_bytes(const GpShape& sh, int Nx, int nc) {
+  const int pt = 16 * sh.cbn;
+  const int wv = (sh.cbn <= 2) ? 8 : 4;
+  const int mt = (2 * nc + 15) / 16;
+  const size_t et = sh.et_lds ? (size_t)pt * Nx * sizeof(double) : 0;
+  const size_t red = (size_t)wv * 16 * mt * pt * sizeof(double) + (size_t)wv * pt * sizeof(double);
+  return std::max(et, red);
+}
+}  // namespace
+
+// the built-in rule: parameter tiles of 16 CBN with their field rows in LDS
+// (CBN as large as a 72 KB budget allows, at most 4; without room for even
+// 16 rows, tiles of 64 with the table read from global memory), and two
+// blocks per CU (512 row blocks on 256 CUs)
+GpShape gather_project_shape(int N, int p, int Nx, int n, size_t part_cap) {
+  const int nc = fused_nc(n);
+  {
+    std::lock_guard<std::mutex> lk(gp_shape_mu);
+    auto it = gp_shapes.find({N, p, Nx, nc});
+    if (it != gp_shapes.end()) return it->second;
+  }
+  (void)part_cap;
+  const size_t budget = 72 * 1024;
+  GpShape sh{4, true, 512};
+  while (sh.cbn > 1 && (size_t)16 * sh.cbn * Nx * sizeof(double) > budget) sh.cbn /= 2;
+  sh.et_lds = (size_t)16 * sh.cbn * Nx * sizeof(double) <= budget;
+  if (!sh.et_lds) sh.cbn = 4;
+  return sh;
+}
+
+std::vector<GpShape> gather_project_shapes(int N, int p, int Nx, int n, size_t part_cap) {
+  const int nc = fused_nc(n);
+  const int rec = n * p + p;
+  const int cap = (int)(part_cap / (size_t)rec);
+  std::vector<GpShape> out;
+  std::vector<std::array<int, 3>> seen;  // (cbn, et, effective row blocks)
+  for (int cbn : {1, 2, 4})
+    for (bool et : {true, false})
+      for (int nbm : {256, 512, 1024}) {
+        const GpShape sh{cbn, et, nbm};
+        if (gp_lds_bytes(sh, Nx, nc) > kGpLdsMax) continue;
+        if (cbn > 1 && 16 * (cbn / 2) >= p) continue;  // a narrower tile already holds p
+        const int eff = std::max(1, std::min(std::min(nbm, (N + 63) / 64), cap));
+        const std::array<int, 3> k{cbn, et ? 1 : 0, eff};
+        if (std::find(seen.begin(), seen.end(), k) != seen.end()) continue;
+        seen.push_back(k);
+        out.push_back(sh);
+      }
+  return out;
+}
+
+void set_gather_project_shape(int N, int p, int Nx, int n, const GpShape* shape) {
+  std::lock_guard<std::mutex> lk(gp_shape_mu);
+  const std::array<int, 4> key{N, p, Nx, fused_nc(n)};
+  if (shape)
+    gp_shapes[key] = *shape;
+  else
+    gp_shapes.erase(key);
+}
+
 void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cplx* Z, int p,
                            int Nx, const double* factor, const double* e, double qm,
                            const int* active, bool want_colsq, cplx* part, size_t part_cap,
                            cplx* g, double* colsq, const cplx* G12, const int* gate) {
   const int nc = fused_nc(n);
   const int rec = n * p + p;
-  // two blocks per CU (512 on 256 CUs, all resident at once: the loop is
-  // bound by FP64 VALU work, so every CU gets the same share), at least 64
-  // rows per block, partials within part_cap
+  const GpShape shape = gather_project_shape(N, p, Nx, n, part_cap);
+  // at least 64 rows per block, at most nb_max blocks (all resident at once:
+  // every CU gets the same share), partials within part_cap
   int nb = (N + 63) / 64;
-  if (nb > 512) nb = 512;
+  if (nb > shape.nb_max) nb = shape.nb_max;
   const int cap = (int)(part_cap / (size_t)rec);
   if (nb > cap) nb = cap;
   if (nb < 1) nb = 1;
   const int rpb = (N + nb - 1) / nb;
   nb = (N + rpb - 1) / rpb;
-  // parameter tiles of 16 CBN with their field rows in LDS (CBN as large as
-  // the 72 KB budget allows, at most 4); without room for even 16 rows, tiles
-  // of 64 with the table read from global memory
-  const size_t budget = 72 * 1024;
-  int cbn = 4;
-  while (cbn > 1 && (size_t)16 * cbn * Nx * sizeof(double) > budget) cbn /= 2;
-  const bool et_lds = (size_t)16 * cbn * Nx * sizeof(double) <= budget;
-  if (!et_lds) cbn = 4;
+  const int cbn = shape.cbn;
+  const bool et_lds = shape.et_lds;
   const int pt = 16 * cbn;
   const int ntile = (p + pt - 1) / pt;
   const size_t et_bytes = et_lds ? (size_t)pt * Nx * sizeof(double) : 0;
@@ -1504,14 +1571,22 @@ void launch_gather_project(hipStream_t s, const cplx* U, int N, int n, const cpl
     case 12: GPM(12, CBV, ETV); break;  \
     default: GPM(16, CBV, ETV); break;  \
   }
-  if (!et_lds) {
-    GPM_NC(4, false)
-  } else if (cbn == 4) {
-    GPM_NC(4, true)
-  } else if (cbn == 2) {
-    GPM_NC(2, true)
+  if (et_lds) {
+    if (cbn == 4) {
+      GPM_NC(4, true)
+    } else if (cbn == 2) {
+      GPM_NC(2, true)
+    } else {
+      GPM_NC(1, true)
+    }
   } else {
-    GPM_NC(1, true)
+    if (cbn == 4) {
+      GPM_NC(4, false)
+    } else if (cbn == 2) {
+      GPM_NC(2, false)
+    } else {
+      GPM_NC(1, false)
+    }
   }
 #undef GPM_NC
 #undef GPM

@@ -436,6 +436,31 @@ def test_rom_hamiltonian_split_parity(name, kw, two_n, proj, steps):
         assert info["deim_active"] == 1
 
 
+def test_autotune_keeps_gradient_parity():
+    """rom_autotune times the launch shapes of the fused gather-projection and
+    keeps the fastest for these sizes: the gradient stays within 1e-10 of the
+    oracle's with the shape it keeps, and after every shape it timed; a
+    deterministic handle keeps the built-in shape (ESTATE)."""
+    binding, torch = _b()
+    w, e = _ens("twostream_deim", N=20011, p=40, Nx=128)   # sizes no other test uses
+    _say("autotune", w["N"], w["p"], w["Nx"])
+    cfg, st = _oracle_state(w, e, 12, fp_tol=1e-10)
+    r = _gpu_rom(binding, w, e, 12, fp_tol=1e-10)
+    _set_from_oracle(r, st, torch)
+    res = r.autotune()
+    print(f"  kept {res}", flush=True)
+    assert res["ms"] > 0 and res["rule_ms"] > 0 and res["ms"] <= res["rule_ms"]
+    Zt = torch.from_numpy(np.ascontiguousarray(st.Z.T)).cuda()
+    g, rho, Phi, ef = r.gradient(Zt)
+    gr = rom.gradient(st.U, st.Z, st.L, w["Nx"])
+    err = _rel(_np(g).T, gr.g)
+    print(f"  g rel err {err:.2e}", flush=True)
+    assert err < RTOL
+    rd = _gpu_rom(binding, w, e, 12, fp_tol=1e-10, deterministic=True)
+    with pytest.raises(binding.SymromError):
+        rd.autotune()
+
+
 def test_rom_enoconv_keeps_state():
     binding, torch = _b()
     w, e = _ens("landau_tiny", N=2000)
